@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched mapping step on one MI355X.
+
+Workload (the batched mapping step the paper's renderer runs every
+iteration, DROID-Splat Sec. 3.3 and supplementary S1.2): 500k Gaussians with
+SH degree 3, 8 keyframes at 1200x680 (f = 600) on a smooth trajectory,
+forward + summed L1 RGB + L1 depth loss + backward (all Gaussian gradients and
+the pose twists), FP32.  Synthetic scene (seeded, shaped like the paper's
+Replica/TUM maps); targets are renders of the unperturbed means.
+
+Reports forward+backward Mpixels/s of the batched launch, the same work as
+one launch sequence per frame (batched vs per-frame speedup), per-stage GPU
+time from HIP events recorded on the library's stream inside the timed
+region, the roofline position of the dominant kernel, and the FP64 CPU
+oracle timed on a bounded sample (one keyframe) on the host cores.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic cost per evaluated (pixel, entry) pair of the compositing
+# kernels (FP32 operations counted from the method's arithmetic; see the
+# design notes): forward 27 flops + 1 exp, backward 60 flops + 1 exp + 1 rcp.
+FLOPS_PER_PAIR = {"composite_fwd": 27.0, "composite_bwd": 60.0}
+PEAK_FP32_VECTOR_TFLOPS = 157.3  # MI355X fp32 vector (published)
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-per-frame", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--n", type=int, default=500_000)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU; the rasterizer shards over keyframes "
+              "across GPUs only by design (no multi-GPU path is built), so --gpus must be 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2411_17660_amd import scenes
+    from paper_2411_17660_amd.raster import Rasterizer
+
+    tile = tuple(int(v) for v in args.tile.split("x"))
+    t0 = time.time()
+    sc = scenes.scene_c3(n=args.n)
+    log(f"[bench] scene generated in {time.time() - t0:.1f}s: n={sc.n} frames={sc.n_frames}")
+    dev = {k: torch.from_numpy(np.ascontiguousarray(getattr(sc, k), np.float32)).cuda()
+           for k in ("means", "log_scales", "quats", "opacity", "sh", "poses")}
+    gt_means = torch.from_numpy(sc.extra["gt_means"]).cuda()
+    P = sc.n_pixels
+    F = sc.n_frames
+    W, H = sc.cams[0][:2]
+    depth_weight = 1.0
+    rast = Rasterizer(0)
+    # targets: render of the ground-truth means (workload set-up, untimed)
+    t_rgb, t_dep, _ = rast.forward(gt_means, dev["log_scales"], dev["quats"], dev["opacity"],
+                                   dev["sh"], dev["poses"], sc.cams, 3, tile=tile)
+    t_rgb, t_dep = t_rgb.clone(), t_dep.clone()
+    torch.cuda.synchronize()
+
+    def buffers(n_frames_px, nF):
+        K = (sc.sh_degree + 1) ** 2
+        n = sc.n
+        return dict(rgb=torch.empty(3 * n_frames_px, device="cuda"),
+                    depth=torch.empty(n_frames_px, device="cuda"),
+                    alpha=torch.empty(n_frames_px, device="cuda"),
+                    loss=torch.empty(1, device="cuda"), means=torch.empty(n, 3, device="cuda"),
+                    log_scales=torch.empty(n, 3, device="cuda"),
+                    quats=torch.empty(n, 4, device="cuda"), opacity=torch.empty(n, device="cuda"),
+                    sh=torch.empty(n, K, 3, device="cuda"), twist=torch.empty(nF, 6, device="cuda"))
+
+    def step(r, cams, poses, trgb, tdep, bufs, cap, timing=False):
+        r.step_l1(dev["means"], dev["log_scales"], dev["quats"], dev["opacity"], dev["sh"],
+                  poses, cams, 3, trgb, tdep, depth_weight, bufs, tile=tile, key_capacity=cap,
+                  timing=timing)
+
+    # ---------------- batched: one launch sequence for all 8 frames
+    bb = buffers(P, F)
+    step(rast, sc.cams, dev["poses"], t_rgb, t_dep, bb, 0)
+    torch.cuda.synchronize()
+    K = rast.stats()["n_keys"]
+    cap = int(K * 1.05) + 1024  # fixed capacity: no host read inside the step
+    log(f"[bench] K={K} keys per step; capacity {cap}")
+    for _ in range(args.warmup):
+        step(rast, sc.cams, dev["poses"], t_rgb, t_dep, bb, cap)
+    torch.cuda.synchronize()
+    rast.timings()  # drop anything recorded so far
+    log(f"[bench] timed batched steps: {args.steps}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(rast, sc.cams, dev["poses"], t_rgb, t_dep, bb, cap, timing=True)
+    torch.cuda.synchronize()
+    t_batched = (time.perf_counter() - t0) / args.steps
+    rast.check_overflow()
+    stages = rast.timings()
+    loss = bb["loss"].item()
+    log(f"[bench] batched {t_batched * 1e3:.2f} ms/step, loss {loss:.5f}")
+
+    # evaluated (pixel, entry) pairs of one forward (separate counting pass)
+    rast.forward(dev["means"], dev["log_scales"], dev["quats"], dev["opacity"], dev["sh"],
+                 dev["poses"], sc.cams, 3, tile=tile, key_capacity=cap, count_pairs=True)
+    pairs = rast.stats()["n_pairs"]
+    log(f"[bench] evaluated pairs per forward {pairs}")
+
+    # ---------------- per-frame: the same work, one launch sequence per frame
+    t_per_frame = None
+    if not args.no_per_frame:
+        rf = Rasterizer(0)
+        per = []
+        for f in range(F):
+            cams_f = [sc.cams[f]]
+            poses_f = dev["poses"][f:f + 1].contiguous()
+            tr = t_rgb[3 * f * W * H:3 * (f + 1) * W * H]
+            td = t_dep[f * W * H:(f + 1) * W * H]
+            bf = buffers(W * H, 1)
+            step(rf, cams_f, poses_f, tr, td, bf, 0)
+            torch.cuda.synchronize()
+            kf = rf.stats()["n_keys"]
+            per.append((cams_f, poses_f, tr, td, bf, int(kf * 1.05) + 1024))
+        for _ in range(args.warmup):
+            for (c, p, tr, td, bf, kc) in per:
+                step(rf, c, p, tr, td, bf, kc)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            for (c, p, tr, td, bf, kc) in per:
+                step(rf, c, p, tr, td, bf, kc)
+        torch.cuda.synchronize()
+        t_per_frame = (time.perf_counter() - t0) / args.steps
+        rf.check_overflow()
+        log(f"[bench] per-frame {t_per_frame * 1e3:.2f} ms/step")
+
+    mpix = P / 1e6
+    value = mpix / t_batched
+    per_stage = {k: round(v[0] / max(args.steps, 1), 4) for k, v in stages.items() if v[1]}
+    # roofline of the dominant compositing kernel
+    dom = max(("composite_fwd", "composite_bwd"), key=lambda k: stages[k][0])
+    dur_ms = stages[dom][0] / max(stages[dom][1], 1)
+    achieved = pairs * FLOPS_PER_PAIR[dom] / (dur_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3),
+                "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": None,
+                "avg_launch_ms": round(dur_ms, 4), "pairs_per_launch": pairs,
+                "flops_per_pair": FLOPS_PER_PAIR[dom]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(sc, args.cpu_threads)
+
+    out = {
+        "metric": "fwd+bwd Mpixels/s at 500k Gaussians; batched vs per-frame speedup",
+        "value": round(value, 3), "unit": "Mpixels/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(t_batched * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded piecewise-planar scenes shaped like the paper's maps)",
+        "config": {"workload": "c3: 500k Gaussians SH3, 8 keyframes 1200x680 f=600, "
+                               "fwd + L1 rgb + L1 depth + bwd incl. pose twists",
+                   "n_gaussians": sc.n, "frames": F, "resolution": [W, H],
+                   "tile": list(tile), "keys_per_step": int(K)},
+        "per_frame_ms_per_step": None if t_per_frame is None else round(t_per_frame * 1e3, 4),
+        "batched_vs_per_frame_speedup": None if t_per_frame is None else
+        round(t_per_frame / t_batched, 4),
+        "stage_ms_per_step": per_stage,
+        "loss": loss,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(sc, threads):
+    """FP64 oracle, forward + backward of keyframe 0 (all Gaussians, one of
+    the eight frames) on the host cores; upstream gradients of the L1 loss's
+    shape (+-1/(3HW) per channel, +-1/HW per depth pixel)."""
+    import numpy as np
+
+    import oracle
+    nthreads = threads or min(16, os.cpu_count() or 1)
+    sf = sc.subset_frames([0])
+    log(f"[bench] cpu baseline: oracle on keyframe 0 with {nthreads} threads")
+    t0 = time.perf_counter()
+    r = oracle.forward(sf, threads=nthreads)
+    P = r.P
+    rng = np.random.default_rng(0)
+    G = (rng.choice([-1.0, 1.0], 3 * P) / (3 * P), rng.choice([-1.0, 1.0], P) / P, np.zeros(P))
+    r.backward(*G)
+    dt = time.perf_counter() - t0
+    log(f"[bench] cpu baseline {dt:.1f}s")
+    return {"value": round(P / 1e6 / dt, 5), "unit": "Mpixels/s", "cores": nthreads,
+            "kind": "oracle", "seconds": round(dt, 2),
+            "sample": "keyframe 0 of the 8 (1200x680, all 500k Gaussians), fwd+bwd, FP64"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,196 @@
+/*
+ * gsr.h -- C ABI of libgsr.so, a differentiable tile rasterizer for 3D
+ * Gaussian Splatting on AMD Instinct MI355X (gfx950).
+ *
+ * It computes the rendering step of DROID-Splat's mapper (Sec. 3.3
+ * "Differentiable Rendering"): Gaussians with mean P, rotation r, scale s,
+ * density sigma and SH colour are rendered at keyframe poses by front-to-back
+ * alpha compositing, C = sum_i c_i a_i prod_{j<i} (1 - a_j), with
+ * a_i = sigma_i G(R, t, P_i, r_i, s_i) (eqn:rendering), producing an image
+ * and a depth map per keyframe; gradients flow to every Gaussian parameter
+ * and, for pose refinement, to each keyframe pose (Sec. 3.3, last paragraph;
+ * supplementary S1.3).  The mapper renders a batch of keyframes per
+ * iteration (supplementary S1.2): one call renders F frames of any sizes.
+ *
+ * Conventions
+ *  - All tensor arguments are device pointers to contiguous FP32 arrays owned
+ *    by the caller (the Python binding passes PyTorch storage); `cams` and
+ *    `settings` are host structs.  Pointers must be 4-byte aligned.
+ *  - Parameters: means [n,3]; log_scales [n,3] (s = exp); quats [n,4] as
+ *    (w, x, y, z), normalised inside; opacity_logits [n] (sigma = 1/(1+e^-o));
+ *    sh [n, (d+1)^2, 3] real SH coefficients, coefficient-major, colour =
+ *    max(0, sum_k sh_k Y_k(dir) + 1/2), dir the unit vector from the camera
+ *    centre to the mean.
+ *  - poses [F,3,4] world->camera [R | t], OpenCV axes (x right, y down,
+ *    z forward); pixel (i, j) samples the point (i, j) of the pinhole image
+ *    u = fx x/z + cx, v = fy y/z + cy.
+ *  - Outputs are packed over frames in order: rgb holds, per frame, a [3,H,W]
+ *    block; depth and alpha hold a [H,W] block per frame.  depth is the
+ *    alpha-blended view depth sum_i z_i a_i T_i; alpha = 1 - T_final;
+ *    rgb = sum_i c_i a_i T_i + T_final * background.
+ *  - Culling and thresholds: keep a Gaussian in a frame iff z > near, the
+ *    projected 2x2 covariance (+0.3 px^2) is positive definite and its
+ *    3-sigma pixel square [ceil(u-r), floor(u+r)] x [ceil(v-r), floor(v+r)],
+ *    r = 3 sqrt(lambda_max), meets the image.  A Gaussian contributes to a
+ *    pixel only inside its square (so results do not depend on the tile
+ *    shape); a = min(0.99, sigma exp(-q/2)); entries with a < 1/255 are
+ *    skipped; a pixel stops before the entry that would take T below 1e-4.
+ *  - The pose gradient g_twist [F,6] = dL/dxi at xi = 0 for the left
+ *    perturbation T_f <- Exp(xi) T_f, xi = (rho, phi), translation first.
+ *  - Gradient outputs are overwritten, never accumulated.
+ *  - `stream` is a hipStream_t (NULL = default stream).  Calls are
+ *    asynchronous unless stated; one context serves one stream at a time.
+ *
+ * Errors: every call returns a gsr_status; no exception or abort crosses the
+ * ABI.  Arguments are validated on the host before any launch.  A HIP error
+ * returns GSR_ERR_HIP; gsr_last_error() gives the message.  n == 0 or a
+ * frame that nothing reaches is not an error (background, 0, 0).
+ */
+#ifndef GSR_H
+#define GSR_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gsr_status;
+#define GSR_OK 0
+#define GSR_ERR_INVALID_ARGUMENT 1
+#define GSR_ERR_CAPACITY 2      /* more (tile, Gaussian) keys than key_capacity */
+#define GSR_ERR_OUT_OF_MEMORY 3
+#define GSR_ERR_HIP 4
+#define GSR_ERR_STATE 5         /* backward without a matching forward */
+#define GSR_ERR_UNSUPPORTED 6   /* e.g. a tile shape without a kernel */
+
+/* One pinhole camera per frame (host struct). */
+typedef struct {
+  int32_t width, height;
+  float fx, fy, cx, cy;
+  float near_z; /* cull depth, 0.2 in the workloads */
+} gsr_camera;
+
+/* Render settings (host struct). */
+typedef struct {
+  int32_t sh_degree;      /* 0..3 */
+  float background[3];
+  int32_t tile_w, tile_h; /* 16x16, 8x8, 32x8, 16x8 or 32x16 */
+  int32_t lds_batch;      /* entries staged per LDS round; 0 or 64 */
+  int64_t key_capacity;   /* 0: the library sizes the key buffers from the
+                             exact count (one 8-byte device->host read per
+                             forward); > 0: fixed capacity, no host read, and
+                             an overflow is reported by gsr_check_overflow */
+  uint32_t flags;         /* GSR_FLAG_* */
+} gsr_settings;
+
+#define GSR_FLAG_NO_XCD_REMAP 1u /* map workgroup i to tile i (default: each
+                                    XCD gets a contiguous run of tiles) */
+#define GSR_FLAG_TIMING 2u       /* record HIP events around every stage on the
+                                    call's stream; read with gsr_debug_timings */
+#define GSR_FLAG_COUNT_PAIRS 4u  /* count evaluated (pixel, entry) pairs in the
+                                    forward compositing; see gsr_stats.n_pairs */
+
+/* Stages timed under GSR_FLAG_TIMING (index into gsr_debug_timings). */
+#define GSR_STAGE_PREPROCESS 0
+#define GSR_STAGE_DEPTH_SORT 1
+#define GSR_STAGE_OFFSETS 2
+#define GSR_STAGE_KEYGEN 3
+#define GSR_STAGE_TILE_SORT 4
+#define GSR_STAGE_RANGES 5
+#define GSR_STAGE_COMPOSITE_FWD 6
+#define GSR_STAGE_LOSS 7
+#define GSR_STAGE_COMPOSITE_BWD 8
+#define GSR_STAGE_PREPROCESS_BWD 9
+#define GSR_N_STAGES 10
+
+typedef struct gsr_context gsr_context;
+
+/* Creates a context bound to HIP device `device`.  *out receives it. */
+gsr_status gsr_create(gsr_context** out, int32_t device);
+/* Frees the context and its workspace (synchronises the device first). */
+gsr_status gsr_destroy(gsr_context* ctx);
+/* Message of the last failed call on ctx ("" if none).  Owned by ctx. */
+const char* gsr_last_error(const gsr_context* ctx);
+
+/* Forward render of F frames (rows A0-A6 of the method: preprocess, depth
+ * sort, keys, tile sort, ranges, compositing).  Saves what the backward
+ * needs in the context; the caller keeps every input unchanged until the
+ * matching gsr_backward has been enqueued. */
+gsr_status gsr_forward(gsr_context* ctx, const gsr_settings* settings, int64_t n,
+                       const float* means, const float* log_scales, const float* quats,
+                       const float* opacity_logits, const float* sh, int32_t n_frames,
+                       const gsr_camera* cams, const float* poses, float* rgb, float* depth,
+                       float* alpha, void* stream);
+
+/* Backward of the last forward on ctx for upstream gradients g_rgb, g_depth,
+ * g_alpha (packed like the outputs).  Writes g_means [n,3], g_log_scales
+ * [n,3], g_quats [n,4], g_opacity_logits [n], g_sh [n,(d+1)^2,3] (summed
+ * over frames) and g_twist [F,6].  GSR_ERR_STATE if no forward preceded. */
+gsr_status gsr_backward(gsr_context* ctx, const float* g_rgb, const float* g_depth,
+                        const float* g_alpha, float* g_means, float* g_log_scales,
+                        float* g_quats, float* g_opacity_logits, float* g_sh, float* g_twist,
+                        void* stream);
+
+/* L1 loss of the last forward's outputs against targets (packed like them):
+ * *loss = sum_f [ mean |rgb - target_rgb| + depth_weight * mean over
+ * {target_depth > 0} |depth - target_depth| ] (the L1 terms of the paper's
+ * rendering loss), and its gradients g_rgb, g_depth, g_alpha (= 0), ready
+ * for gsr_backward.  `loss` is a device float. */
+gsr_status gsr_loss_l1(gsr_context* ctx, const float* target_rgb, const float* target_depth,
+                       float depth_weight, float* loss, float* g_rgb, float* g_depth,
+                       float* g_alpha, void* stream);
+
+/* One mapping step: gsr_forward, gsr_loss_l1 and gsr_backward in sequence,
+ * with the upstream gradients held in the context. */
+gsr_status gsr_step_l1(gsr_context* ctx, const gsr_settings* settings, int64_t n,
+                       const float* means, const float* log_scales, const float* quats,
+                       const float* opacity_logits, const float* sh, int32_t n_frames,
+                       const gsr_camera* cams, const float* poses, const float* target_rgb,
+                       const float* target_depth, float depth_weight, float* rgb, float* depth,
+                       float* alpha, float* loss, float* g_means, float* g_log_scales,
+                       float* g_quats, float* g_opacity_logits, float* g_sh, float* g_twist,
+                       void* stream);
+
+/* Synchronises `stream` and returns GSR_ERR_CAPACITY if a fixed-capacity
+ * forward since the last check had more keys than key_capacity (its outputs
+ * are then undefined), else GSR_OK.  Clears the flag. */
+gsr_status gsr_check_overflow(gsr_context* ctx, void* stream);
+
+typedef struct {
+  int64_t n_records;    /* n * F */
+  int64_t n_keys;       /* (tile, Gaussian) keys of the last forward */
+  int64_t n_tiles;      /* tiles over all frames */
+  int64_t n_pixels;
+  int64_t key_capacity; /* allocated key slots */
+  uint32_t epoch;       /* backward calls so far */
+  int32_t tile_w, tile_h;
+  int64_t n_pairs;      /* evaluated (pixel, entry) pairs of the last forward
+                           with GSR_FLAG_COUNT_PAIRS, else -1 */
+} gsr_stats;
+
+/* Statistics of the last forward (synchronises `stream`). */
+gsr_status gsr_debug_stats(gsr_context* ctx, gsr_stats* out, void* stream);
+
+/* Per-stage GPU time of every call made with GSR_FLAG_TIMING since the last
+ * read: ms[s] = total milliseconds, calls[s] = number of timed launches of
+ * stage s (arrays of GSR_N_STAGES).  Synchronises on the recorded events and
+ * clears them. */
+gsr_status gsr_debug_timings(gsr_context* ctx, double* ms, int64_t* calls);
+
+/* Copies the last forward's integer artefacts to host arrays (synchronises
+ * `stream`); any pointer may be NULL.  Record r = f*n + g:
+ *   ntiles [n*F]     tiles covered (0 = culled)
+ *   depth_key [n*F]  bits of fp32(z) (0xffffffff = culled)
+ *   square [n*F*2]   x_lo | x_hi << 16, y_lo | y_hi << 16 (kept records)
+ *   tile_keys [K], tile_vals [K]  sorted global tile ids and record ids
+ *   ranges [T*2]     [start, end) of each tile in the sorted keys
+ *   n_last [P]       per pixel, list position after its last blended entry
+ *   t_final [P]      per pixel, final transmittance */
+gsr_status gsr_debug_lists(gsr_context* ctx, uint32_t* ntiles, uint32_t* depth_key,
+                           uint32_t* square, uint32_t* tile_keys, uint32_t* tile_vals,
+                           uint32_t* ranges, int32_t* n_last, float* t_final, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,89 @@
+// gsr_device.h -- device-side layouts and helpers of the MI355X (gfx950)
+// tile rasterizer.  Internal to libgsr.so; the public boundary is
+// include/gsr.h.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gsr {
+
+// Per-pair thresholds of the compositing loop (FP32 compares).
+constexpr float kAlphaMin = 1.0f / 255.0f;  // skip entries with alpha < 1/255
+constexpr float kAlphaMax = 0.99f;          // alpha is clamped to 0.99
+constexpr float kTMin = 1e-4f;              // stop before T drops below 1e-4
+// EWA screen-space low-pass (px^2), Jacobian guard, 3-sigma extent.
+constexpr double kLowpass = 0.3;
+constexpr double kJGuard = 1.3;
+constexpr double kExtent = 3.0;
+// -0.5 * log2(e): alpha = opacity * 2^(q * kNegHalfLog2e)
+constexpr float kNegHalfLog2e = -0.72134752044448170368f;
+
+constexpr int kWave = 64;
+
+// One frame of a batch (A0 batch descriptor).
+struct FrameDesc {
+  int32_t width, height;
+  float fx, fy, cx, cy, near_z;
+  int32_t grid_x, grid_y;
+  int32_t tile_offset;   // first global tile id of the frame
+  int64_t pixel_offset;  // first packed pixel of the frame
+};
+
+// Per (Gaussian, frame) record written by the preprocess and staged through
+// LDS by the compositing kernels: 64 bytes, read with 4 x 16-byte loads.
+//  - (u, v) as FP32 hi/lo pairs so that u - i is exact to FP32 rounding even
+//    at 1900 px;
+//  - the conic in completed-square form q = (a1 dx + a2 dy)^2 + (a3 dy)^2,
+//    a1 = sqrt(A), a2 = B / sqrt(A), a3 = sqrt(C - B^2/A) = 1/sqrt(s_yy):
+//    both terms are non-negative, so anisotropic Gaussians do not cancel;
+//  - the 3-sigma pixel square, 16 bits per bound.
+struct alignas(16) Record {
+  float u_hi, u_lo, v_hi, v_lo;
+  float a1, a2, a3, opacity;
+  float c0, c1, c2, z;
+  uint32_t sqx, sqy;      // lo | hi << 16
+  uint32_t key_offset;    // first key slot of the record (keygen)
+  uint32_t frame;
+};
+static_assert(sizeof(Record) == 64, "record layout");
+
+// Gradient of one (tile, entry) key: du, dv, dA, dB, dC, dopacity, dc0..2, dz
+constexpr int kNG = 10;
+
+__device__ __forceinline__ int frame_of_tile(const FrameDesc* fr, int n_frames, int tile) {
+  int f = 0;
+  while (f + 1 < n_frames && tile >= fr[f + 1].tile_offset) ++f;
+  return f;
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const uint32_t lane = __lane_id();
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Alpha of an entry at one pixel, the single definition used by the forward
+// and backward compositing kernels so that both take identical decisions.
+// dx, dy: Gaussian centre minus pixel.  Explicit fma, no contraction.
+struct AlphaEval {
+  float dx, dy, g, a;  // g = exp(-q/2); a = min(kAlphaMax, opacity * g)
+  bool clamped;
+};
+
+__device__ __forceinline__ float dx_of(float hi, float lo, int px) {
+#pragma clang fp contract(off)
+  return (hi - (float)px) + lo;  // hi - px is exact (Sterbenz / integer grid)
+}
+
+__device__ __forceinline__ float q_of(float a1, float a2, float a3, float dx, float dy) {
+#pragma clang fp contract(off)
+  const float m = __builtin_fmaf(a2, dy, a1 * dx);
+  const float b = a3 * dy;
+  return __builtin_fmaf(m, m, b * b);
+}
+
+__device__ __forceinline__ float gauss_of(float q) {
+#pragma clang fp contract(off)
+  return __builtin_amdgcn_exp2f(q * kNegHalfLog2e);
+}
+
+}  // namespace gsr

@@ -1,0 +1,572 @@
+// preprocess.hip -- per (Gaussian, frame) projection (forward) and its chain
+// rule (backward), FP64 on gfx950.
+//
+// Forward (DROID-Splat Sec. 3.3: parameters P, r, s, sigma, SH; alpha_i =
+// sigma_i * G(R, t, P_i, r_i, s_i) with the EWA projection of the 3DGS
+// rasterizer the paper builds on; Sec. 3.1 pinhole Pi_c):
+//   s = exp(l), R(q/|q|), Sigma = R diag(s^2) R^T, sigma = 1/(1+e^-o);
+//   t = R_f mu + t_f, keep iff t_z > near;
+//   (u, v) = (fx t_x/t_z + cx, fy t_y/t_z + cy);
+//   Sigma' = J R_f Sigma R_f^T J^T + 0.3 I (J with the 1.3x frustum guard);
+//   r = 3 sqrt(lambda_max(Sigma')); square = [ceil(u-r), floor(u+r)] x ...;
+//   colour = max(0, sum_k sh_k Y_k(dir) + 1/2), dir from the camera centre.
+// Every integer decision (cull, square, tile rect, depth key) is taken in
+// FP64 with contraction off, in a fixed operation order, so that it is
+// reproducible on any IEEE-754 double implementation.
+//
+// One thread per Gaussian walks all frames of the batch: the parameters are
+// read from HBM once per step and the world covariance is built once.
+#include "gsr_device.h"
+
+namespace gsr {
+
+struct GaussSetup {
+  double s[3], qn, qh[4], R[9], Sig[9], opacity;
+};
+
+__device__ __forceinline__ void gaussian_setup(const float* __restrict__ log_scales,
+                                               const float* __restrict__ quats,
+                                               const float* __restrict__ opac, int64_t g,
+                                               GaussSetup& G) {
+#pragma clang fp contract(off)
+  for (int a = 0; a < 3; ++a) G.s[a] = exp((double)log_scales[g * 3 + a]);
+  double q[4];
+  for (int a = 0; a < 4; ++a) q[a] = (double)quats[g * 4 + a];
+  G.qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  for (int a = 0; a < 4; ++a) G.qh[a] = q[a] / G.qn;
+  const double w = G.qh[0], x = G.qh[1], y = G.qh[2], z = G.qh[3];
+  G.R[0] = 1.0 - 2.0 * (y * y + z * z);
+  G.R[1] = 2.0 * (x * y - w * z);
+  G.R[2] = 2.0 * (x * z + w * y);
+  G.R[3] = 2.0 * (x * y + w * z);
+  G.R[4] = 1.0 - 2.0 * (x * x + z * z);
+  G.R[5] = 2.0 * (y * z - w * x);
+  G.R[6] = 2.0 * (x * z - w * y);
+  G.R[7] = 2.0 * (y * z + w * x);
+  G.R[8] = 1.0 - 2.0 * (x * x + y * y);
+  double M[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) M[i * 3 + j] = G.R[i * 3 + j] * G.s[j];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < 3; ++k) acc += M[i * 3 + k] * M[j * 3 + k];
+      G.Sig[i * 3 + j] = acc;
+    }
+  G.opacity = 1.0 / (1.0 + exp(-(double)opac[g]));
+}
+
+// Projection of one Gaussian into one frame (FP64).
+struct Proj {
+  bool keep;
+  double t[3], u, v, J[6], Sc[9], cov[3], det;
+  int clamp_x, clamp_y;
+  int32_t x_lo, x_hi, y_lo, y_hi;
+};
+
+__device__ __forceinline__ void load_pose(const float* __restrict__ poses, int f, double W[9],
+                                          double tf[3]) {
+  const float* P = poses + f * 12;
+  W[0] = P[0]; W[1] = P[1]; W[2] = P[2]; tf[0] = P[3];
+  W[3] = P[4]; W[4] = P[5]; W[5] = P[6]; tf[1] = P[7];
+  W[6] = P[8]; W[7] = P[9]; W[8] = P[10]; tf[2] = P[11];
+}
+
+__device__ __forceinline__ void project(const FrameDesc& fr, const double W[9],
+                                        const double tf[3], const double mu[3],
+                                        const GaussSetup& G, Proj& p) {
+#pragma clang fp contract(off)
+  p.keep = false;
+  for (int i = 0; i < 3; ++i)
+    p.t[i] = W[i * 3 + 0] * mu[0] + W[i * 3 + 1] * mu[1] + W[i * 3 + 2] * mu[2] + tf[i];
+  const double tx = p.t[0], ty = p.t[1], tz = p.t[2];
+  if (!(tz > (double)fr.near_z)) return;
+  const double fx = fr.fx, fy = fr.fy, cx = fr.cx, cy = fr.cy;
+  p.u = fx * tx / tz + cx;
+  p.v = fy * ty / tz + cy;
+  const double limx = kJGuard * (double)fr.width / (2.0 * fx);
+  const double limy = kJGuard * (double)fr.height / (2.0 * fy);
+  double rx = tx / tz, ry = ty / tz;
+  p.clamp_x = 0;
+  p.clamp_y = 0;
+  if (rx < -limx) { rx = -limx; p.clamp_x = -1; }
+  if (rx > limx) { rx = limx; p.clamp_x = 1; }
+  if (ry < -limy) { ry = -limy; p.clamp_y = -1; }
+  if (ry > limy) { ry = limy; p.clamp_y = 1; }
+  const double txc = tz * rx, tyc = tz * ry;
+  p.J[0] = fx / tz; p.J[1] = 0.0; p.J[2] = -fx * txc / (tz * tz);
+  p.J[3] = 0.0; p.J[4] = fy / tz; p.J[5] = -fy * tyc / (tz * tz);
+  double T1[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < 3; ++k) acc += W[i * 3 + k] * G.Sig[k * 3 + j];
+      T1[i * 3 + j] = acc;
+    }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < 3; ++k) acc += T1[i * 3 + k] * W[j * 3 + k];
+      p.Sc[i * 3 + j] = acc;
+    }
+  double JS[6];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < 3; ++k) acc += p.J[i * 3 + k] * p.Sc[k * 3 + j];
+      JS[i * 3 + j] = acc;
+    }
+  double S2[4];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < 3; ++k) acc += JS[i * 3 + k] * p.J[j * 3 + k];
+      S2[i * 2 + j] = acc;
+    }
+  p.cov[0] = S2[0] + kLowpass;
+  p.cov[1] = S2[1];
+  p.cov[2] = S2[3] + kLowpass;
+  p.det = p.cov[0] * p.cov[2] - p.cov[1] * p.cov[1];
+  if (!(p.det > 0.0)) return;
+  const double mid = 0.5 * (p.cov[0] + p.cov[2]);
+  const double hd = 0.5 * (p.cov[0] - p.cov[2]);
+  const double lmax = mid + sqrt(hd * hd + p.cov[1] * p.cov[1]);
+  const double r = kExtent * sqrt(lmax);
+  const double xa = ceil(p.u - r), xb = floor(p.u + r);
+  const double ya = ceil(p.v - r), yb = floor(p.v + r);
+  const double Wm1 = (double)(fr.width - 1), Hm1 = (double)(fr.height - 1);
+  if (!(xa <= Wm1 && xb >= 0.0 && xa <= xb)) return;
+  if (!(ya <= Hm1 && yb >= 0.0 && ya <= yb)) return;
+  p.x_lo = (int32_t)(xa > 0.0 ? xa : 0.0);
+  p.x_hi = (int32_t)(xb < Wm1 ? xb : Wm1);
+  p.y_lo = (int32_t)(ya > 0.0 ? ya : 0.0);
+  p.y_hi = (int32_t)(yb < Hm1 ? yb : Hm1);
+  p.keep = true;
+}
+
+// Real spherical harmonics up to degree 3 in the order (l, m = -l..l) with
+// the (-1)^|m| phase; coefficients are the textbook normalisations.
+constexpr double kY0 = 0.28209479177387814;   // 1/(2 sqrt(pi))
+constexpr double kY1 = 0.4886025119029199;    // sqrt(3/(4 pi))
+constexpr double kY2a = 1.0925484305920792;   // sqrt(15/pi)/2
+constexpr double kY2b = 0.31539156525252005;  // sqrt(5/pi)/4
+constexpr double kY2c = 0.5462742152960396;   // sqrt(15/pi)/4
+constexpr double kY3a = 0.5900435899266435;   // sqrt(35/(2 pi))/4
+constexpr double kY3b = 2.890611442640554;    // sqrt(105/pi)/2
+constexpr double kY3c = 0.4570457994644658;   // sqrt(21/(2 pi))/4
+constexpr double kY3d = 0.3731763325901154;   // sqrt(7/pi)/4
+constexpr double kY3e = 1.445305721320277;    // sqrt(105/pi)/4
+
+// Basis values Y[k], k < (DEG+1)^2.
+template <int DEG>
+__device__ __forceinline__ void sh_basis(double x, double y, double z, double* Y) {
+  Y[0] = kY0;
+  if (DEG < 1) return;
+  Y[1] = -kY1 * y; Y[2] = kY1 * z; Y[3] = -kY1 * x;
+  if (DEG < 2) return;
+  const double xx = x * x, yy = y * y, zz = z * z;
+  Y[4] = kY2a * x * y;
+  Y[5] = -kY2a * y * z;
+  Y[6] = kY2b * (2.0 * zz - xx - yy);
+  Y[7] = -kY2a * x * z;
+  Y[8] = kY2c * (xx - yy);
+  if (DEG < 3) return;
+  Y[9] = -kY3a * y * (3.0 * xx - yy);
+  Y[10] = kY3b * x * y * z;
+  Y[11] = -kY3c * y * (4.0 * zz - xx - yy);
+  Y[12] = kY3d * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
+  Y[13] = -kY3c * x * (4.0 * zz - xx - yy);
+  Y[14] = kY3e * z * (xx - yy);
+  Y[15] = -kY3a * x * (xx - 3.0 * yy);
+}
+
+// ddir = sum_k w[k] * grad Y_k(x, y, z), the direction components taken as
+// independent variables (the polynomials above differentiated term by term).
+template <int DEG>
+__device__ __forceinline__ void sh_dir_grad(double x, double y, double z, const double* w,
+                                            double* dd) {
+  dd[0] = dd[1] = dd[2] = 0.0;
+  if (DEG < 1) return;
+  dd[0] += -kY1 * w[3];
+  dd[1] += -kY1 * w[1];
+  dd[2] += kY1 * w[2];
+  if (DEG < 2) return;
+  const double xx = x * x, yy = y * y, zz = z * z;
+  dd[0] += kY2a * y * w[4] - 2.0 * kY2b * x * w[6] - kY2a * z * w[7] + 2.0 * kY2c * x * w[8];
+  dd[1] += kY2a * x * w[4] - kY2a * z * w[5] - 2.0 * kY2b * y * w[6] - 2.0 * kY2c * y * w[8];
+  dd[2] += -kY2a * y * w[5] + 4.0 * kY2b * z * w[6] - kY2a * x * w[7];
+  if (DEG < 3) return;
+  dd[0] += -6.0 * kY3a * x * y * w[9] + kY3b * y * z * w[10] + 2.0 * kY3c * x * y * w[11] -
+           6.0 * kY3d * x * z * w[12] - kY3c * (4.0 * zz - 3.0 * xx - yy) * w[13] +
+           2.0 * kY3e * x * z * w[14] - 3.0 * kY3a * (xx - yy) * w[15];
+  dd[1] += -3.0 * kY3a * (xx - yy) * w[9] + kY3b * x * z * w[10] -
+           kY3c * (4.0 * zz - xx - 3.0 * yy) * w[11] - 6.0 * kY3d * y * z * w[12] +
+           2.0 * kY3c * x * y * w[13] - 2.0 * kY3e * y * z * w[14] + 6.0 * kY3a * x * y * w[15];
+  dd[2] += kY3b * x * y * w[10] - 8.0 * kY3c * y * z * w[11] +
+           kY3d * (6.0 * zz - 3.0 * xx - 3.0 * yy) * w[12] - 8.0 * kY3c * x * z * w[13] +
+           kY3e * (xx - yy) * w[14];
+}
+
+// Camera centre C = -R_f^T t_f and the unit direction from it to mu.
+__device__ __forceinline__ double view_dir(const double W[9], const double tf[3],
+                                           const double mu[3], double dir[3]) {
+#pragma clang fp contract(off)
+  double d[3];
+  for (int i = 0; i < 3; ++i) {
+    const double C = -(W[0 * 3 + i] * tf[0] + W[1 * 3 + i] * tf[1] + W[2 * 3 + i] * tf[2]);
+    d[i] = mu[i] - C;
+  }
+  const double dist = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  for (int i = 0; i < 3; ++i) dir[i] = d[i] / dist;
+  return dist;
+}
+
+// --------------------------------------------------------------------------
+// A1: forward preprocess
+// --------------------------------------------------------------------------
+template <int DEG>
+__global__ void __launch_bounds__(256) preprocess_fwd_kernel(
+    int64_t n, int n_frames, const FrameDesc* __restrict__ frames,
+    const float* __restrict__ poses, const float* __restrict__ means,
+    const float* __restrict__ log_scales, const float* __restrict__ quats,
+    const float* __restrict__ opac, const float* __restrict__ sh, int tile_w,
+    int tile_h, Record* __restrict__ rec, uint32_t* __restrict__ depth_key,
+    uint32_t* __restrict__ rec_id, uint32_t* __restrict__ ntiles) {
+#pragma clang fp contract(off)
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  GaussSetup G;
+  gaussian_setup(log_scales, quats, opac, g, G);
+  const double mu[3] = {means[g * 3 + 0], means[g * 3 + 1], means[g * 3 + 2]};
+  constexpr int nb = (DEG + 1) * (DEG + 1);
+  for (int f = 0; f < n_frames; ++f) {
+    const int64_t r = (int64_t)f * n + g;
+    const FrameDesc fr = frames[f];
+    double W[9], tf[3];
+    load_pose(poses, f, W, tf);
+    Proj p;
+    project(fr, W, tf, mu, G, p);
+    rec_id[r] = (uint32_t)r;
+    if (!p.keep) {
+      depth_key[r] = 0xffffffffu;
+      ntiles[r] = 0;
+      continue;
+    }
+    const int tx0 = p.x_lo / tile_w, tx1 = p.x_hi / tile_w;
+    const int ty0 = p.y_lo / tile_h, ty1 = p.y_hi / tile_h;
+    ntiles[r] = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+    const float zf = (float)p.t[2];
+    depth_key[r] = __float_as_uint(zf);
+    double dir[3];
+    view_dir(W, tf, mu, dir);
+    double Y[16];
+    sh_basis<DEG>(dir[0], dir[1], dir[2], Y);
+    double raw[3] = {0.0, 0.0, 0.0};
+    const float* shg = sh + g * nb * 3;
+    for (int k = 0; k < nb; ++k)
+      for (int c = 0; c < 3; ++c) raw[c] += (double)shg[k * 3 + c] * Y[k];
+    Record o;
+    o.u_hi = (float)p.u;
+    o.u_lo = (float)(p.u - (double)o.u_hi);
+    o.v_hi = (float)p.v;
+    o.v_lo = (float)(p.v - (double)o.v_hi);
+    o.a1 = (float)sqrt(p.cov[2] / p.det);
+    o.a2 = (float)(-p.cov[1] / sqrt(p.cov[2] * p.det));
+    o.a3 = (float)(1.0 / sqrt(p.cov[2]));
+    o.opacity = (float)G.opacity;
+    const double c0 = raw[0] + 0.5, c1 = raw[1] + 0.5, c2 = raw[2] + 0.5;
+    o.c0 = (float)(c0 > 0.0 ? c0 : 0.0);
+    o.c1 = (float)(c1 > 0.0 ? c1 : 0.0);
+    o.c2 = (float)(c2 > 0.0 ? c2 : 0.0);
+    o.z = zf;
+    o.sqx = (uint32_t)p.x_lo | ((uint32_t)p.x_hi << 16);
+    o.sqy = (uint32_t)p.y_lo | ((uint32_t)p.y_hi << 16);
+    o.key_offset = 0;
+    o.frame = (uint32_t)f;
+    rec[r] = o;
+  }
+}
+
+// --------------------------------------------------------------------------
+// A9 + A10: per-record reduction of the key partials and chain rule to the
+// parameters; per (Gaussian, frame) twist partials reduced per wave in FP64.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum_f64(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int DEG>
+__global__ void __launch_bounds__(256) preprocess_bwd_kernel(
+    int64_t n, int n_frames, const FrameDesc* __restrict__ frames,
+    const float* __restrict__ poses, const float* __restrict__ means,
+    const float* __restrict__ log_scales, const float* __restrict__ quats,
+    const float* __restrict__ opac, const float* __restrict__ sh,
+    const Record* __restrict__ rec, const uint32_t* __restrict__ ntiles,
+    const float* __restrict__ partial, const uint32_t* __restrict__ stamp, uint32_t epoch,
+    uint64_t key_capacity, float* __restrict__ g_means, float* __restrict__ g_log_scales,
+    float* __restrict__ g_quats, float* __restrict__ g_opac, float* __restrict__ g_sh,
+    double* __restrict__ twist_partial /* [F][n_waves][6] */) {
+  const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = g0 < n;
+  const int64_t g = active ? g0 : 0;
+  const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  const int64_t wave_id = g0 / kWave;
+  constexpr int nb = (DEG + 1) * (DEG + 1);
+  GaussSetup G;
+  if (active) gaussian_setup(log_scales, quats, opac, g, G);
+  const double mu[3] = {active ? (double)means[g * 3 + 0] : 0.0,
+                        active ? (double)means[g * 3 + 1] : 0.0,
+                        active ? (double)means[g * 3 + 2] : 0.0};
+  const float* shg = sh + g * nb * 3;
+  double dmu[3] = {0, 0, 0}, dSig[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, dsig = 0.0;
+  float dsh[nb * 3];
+  for (int i = 0; i < nb * 3; ++i) dsh[i] = 0.0f;
+  for (int f = 0; f < n_frames; ++f) {
+    double tw[6] = {0, 0, 0, 0, 0, 0};
+    const int64_t r = (int64_t)f * n + g;
+    uint32_t cnt = active ? ntiles[r] : 0u;
+    const uint32_t off = cnt ? rec[r].key_offset : 0u;
+    if (cnt && (uint64_t)off + cnt > key_capacity) cnt = 0;  // overflowed in keygen
+    if (cnt > 0) {
+      // A9: fixed-order sum over the record's key slots written this step
+      double gr[kNG];
+      for (int j = 0; j < kNG; ++j) gr[j] = 0.0;
+      for (uint32_t s = 0; s < cnt; ++s) {
+        if (stamp[off + s] != epoch) continue;
+        const float* pp = partial + (size_t)(off + s) * kNG;
+        for (int j = 0; j < kNG; ++j) gr[j] += (double)pp[j];
+      }
+      const FrameDesc fr = frames[f];
+      double W[9], tf[3];
+      load_pose(poses, f, W, tf);
+      Proj p;
+      project(fr, W, tf, mu, G, p);
+      const double fx = fr.fx, fy = fr.fy;
+      const double tx = p.t[0], ty = p.t[1], tz = p.t[2];
+      const double tz2 = tz * tz, tz3 = tz2 * tz;
+      double dt[3];
+      dt[0] = gr[0] * fx / tz;
+      dt[1] = gr[1] * fy / tz;
+      dt[2] = -gr[0] * fx * tx / tz2 - gr[1] * fy * ty / tz2 + gr[9];
+      dsig += gr[5];
+      // conic -> Sigma': dL/dSigma' = -Q G_Q Q, G_Q = [[dA, dB/2], [dB/2, dC]]
+      const double A = p.cov[2] / p.det, B = -p.cov[1] / p.det, C = p.cov[0] / p.det;
+      const double gA = gr[2], gB = 0.5 * gr[3], gC = gr[4];
+      const double m00 = A * gA + B * gB, m01 = A * gB + B * gC;
+      const double m10 = B * gA + C * gB, m11 = B * gB + C * gC;
+      const double S00 = -(m00 * A + m01 * B), S01 = -(m00 * B + m01 * C);
+      const double S11 = -(m10 * B + m11 * C);
+      const double GS[4] = {S00, S01, S01, S11};
+      // Sigma' = J Sc J^T + lowpass: G_J = 2 GS J Sc, G_Sc = J^T GS J
+      double JSc[6];
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 3; ++j)
+          JSc[i * 3 + j] = p.J[i * 3 + 0] * p.Sc[0 * 3 + j] + p.J[i * 3 + 1] * p.Sc[1 * 3 + j] +
+                           p.J[i * 3 + 2] * p.Sc[2 * 3 + j];
+      double GJ[6];
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 3; ++j)
+          GJ[i * 3 + j] = 2.0 * (GS[i * 2 + 0] * JSc[0 * 3 + j] + GS[i * 2 + 1] * JSc[1 * 3 + j]);
+      double GJt[6];  // GS J (2x3)
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 3; ++j)
+          GJt[i * 3 + j] = GS[i * 2 + 0] * p.J[0 * 3 + j] + GS[i * 2 + 1] * p.J[1 * 3 + j];
+      double GSc[9];
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+          GSc[a * 3 + b] = p.J[0 * 3 + a] * GJt[0 * 3 + b] + p.J[1 * 3 + a] * GJt[1 * 3 + b];
+      // J -> t (the guard clamp freezes t_x/t_z where active)
+      dt[2] += -GJ[0] * fx / tz2 - GJ[4] * fy / tz2;
+      if (p.clamp_x == 0) {
+        dt[0] += -GJ[2] * fx / tz2;
+        dt[2] += GJ[2] * 2.0 * fx * tx / tz3;
+      } else {
+        const double txc = tz * (p.clamp_x * kJGuard * (double)fr.width / (2.0 * fx));
+        dt[2] += GJ[2] * fx * txc / tz3;
+      }
+      if (p.clamp_y == 0) {
+        dt[1] += -GJ[5] * fy / tz2;
+        dt[2] += GJ[5] * 2.0 * fy * ty / tz3;
+      } else {
+        const double tyc = tz * (p.clamp_y * kJGuard * (double)fr.height / (2.0 * fy));
+        dt[2] += GJ[5] * fy * tyc / tz3;
+      }
+      // Sc = W Sigma W^T -> G_Sigma += W^T G_Sc W
+      double T2[9];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+          T2[i * 3 + j] = W[0 * 3 + i] * GSc[0 * 3 + j] + W[1 * 3 + i] * GSc[1 * 3 + j] +
+                          W[2 * 3 + i] * GSc[2 * 3 + j];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+          dSig[i * 3 + j] += T2[i * 3 + 0] * W[0 * 3 + j] + T2[i * 3 + 1] * W[1 * 3 + j] +
+                             T2[i * 3 + 2] * W[2 * 3 + j];
+      // colour: c = max(0, raw), raw = sum_k sh_k Y_k(dir) + 1/2
+      double dir[3];
+      const double dist = view_dir(W, tf, mu, dir);
+      double Y[16];
+      sh_basis<DEG>(dir[0], dir[1], dir[2], Y);
+      double raw[3] = {0.0, 0.0, 0.0};
+      for (int k = 0; k < nb; ++k)
+        for (int c = 0; c < 3; ++c) raw[c] += (double)shg[k * 3 + c] * Y[k];
+      double draw[3];
+      for (int c = 0; c < 3; ++c) draw[c] = raw[c] + 0.5 > 0.0 ? gr[6 + c] : 0.0;
+      double wk[16];
+      for (int k = 0; k < nb; ++k) {
+        double acc = 0.0;
+        for (int c = 0; c < 3; ++c) {
+          dsh[k * 3 + c] += (float)(Y[k] * draw[c]);
+          acc += (double)shg[k * 3 + c] * draw[c];
+        }
+        wk[k] = acc;
+      }
+      double ddir[3];
+      sh_dir_grad<DEG>(dir[0], dir[1], dir[2], wk, ddir);
+      const double pr = dir[0] * ddir[0] + dir[1] * ddir[1] + dir[2] * ddir[2];
+      double dd[3];
+      for (int a = 0; a < 3; ++a) dd[a] = (ddir[a] - dir[a] * pr) / dist;
+      for (int a = 0; a < 3; ++a)
+        dmu[a] += W[0 * 3 + a] * dt[0] + W[1 * 3 + a] * dt[1] + W[2 * 3 + a] * dt[2] + dd[a];
+      // twist (rho, phi), left perturbation at zero:
+      //   dt = rho + phi x t, dSc = [phi]x Sc - Sc [phi]x, dC = -W^T rho
+      for (int a = 0; a < 3; ++a)
+        tw[a] = dt[a] + W[a * 3 + 0] * dd[0] + W[a * 3 + 1] * dd[1] + W[a * 3 + 2] * dd[2];
+      tw[3] = ty * dt[2] - tz * dt[1];
+      tw[4] = tz * dt[0] - tx * dt[2];
+      tw[5] = tx * dt[1] - ty * dt[0];
+      // <G_Sc, [e_k]x Sc - Sc [e_k]x> for k = x, y, z
+      const double* S = p.Sc;
+      const double* Gm = GSc;
+      // [e_x]x = [[0,0,0],[0,0,-1],[0,1,0]]
+      {
+        double E[3][9] = {{0, 0, 0, 0, 0, -1, 0, 1, 0},
+                          {0, 0, 1, 0, 0, 0, -1, 0, 0},
+                          {0, -1, 0, 1, 0, 0, 0, 0, 0}};
+        for (int k = 0; k < 3; ++k) {
+          double acc = 0.0;
+          for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+              double es = 0.0, se = 0.0;
+              for (int l = 0; l < 3; ++l) {
+                es += E[k][i * 3 + l] * S[l * 3 + j];
+                se += S[i * 3 + l] * E[k][l * 3 + j];
+              }
+              acc += Gm[i * 3 + j] * (es - se);
+            }
+          tw[3 + k] += acc;
+        }
+      }
+    }
+    for (int j = 0; j < 6; ++j) {
+      const double s = wave_sum_f64(tw[j]);
+      if ((threadIdx.x & (kWave - 1)) == 0)
+        twist_partial[((int64_t)f * n_waves + wave_id) * 6 + j] = s;
+    }
+  }
+  if (!active) return;
+  // Sigma = M M^T, M = R diag(s)
+  double Gs[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) Gs[i * 3 + j] = 0.5 * (dSig[i * 3 + j] + dSig[j * 3 + i]);
+  double GM[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < 3; ++k) acc += Gs[i * 3 + k] * G.R[k * 3 + j] * G.s[j];
+      GM[i * 3 + j] = 2.0 * acc;
+    }
+  double dR[9], ds[3] = {0, 0, 0};
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      dR[i * 3 + j] = GM[i * 3 + j] * G.s[j];
+      ds[j] += GM[i * 3 + j] * G.R[i * 3 + j];
+    }
+  for (int a = 0; a < 3; ++a) g_log_scales[g * 3 + a] = (float)(ds[a] * G.s[a]);
+  // dR -> unit quaternion (w, x, y, z)
+  const double w = G.qh[0], x = G.qh[1], y = G.qh[2], z = G.qh[3];
+  double dq[4];
+  dq[0] = 2.0 * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+  dq[1] = 2.0 * (y * dR[1] + z * dR[2] + y * dR[3] - 2.0 * x * dR[4] - w * dR[5] + z * dR[6] +
+                 w * dR[7] - 2.0 * x * dR[8]);
+  dq[2] = 2.0 * (-2.0 * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] +
+                 z * dR[7] - 2.0 * y * dR[8]);
+  dq[3] = 2.0 * (-2.0 * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.0 * z * dR[4] +
+                 y * dR[5] + x * dR[6] + y * dR[7]);
+  const double pr = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
+  for (int a = 0; a < 4; ++a) g_quats[g * 4 + a] = (float)((dq[a] - G.qh[a] * pr) / G.qn);
+  for (int a = 0; a < 3; ++a) g_means[g * 3 + a] = (float)dmu[a];
+  g_opac[g] = (float)(dsig * G.opacity * (1.0 - G.opacity));
+  float* gs = g_sh + g * nb * 3;
+  for (int i = 0; i < nb * 3; ++i) gs[i] = dsh[i];
+}
+
+// A11: per-frame sum of the per-wave twist partials (FP64, fixed order).
+__global__ void __launch_bounds__(256) twist_reduce_kernel(const double* __restrict__ part,
+                                                           int64_t n_waves,
+                                                           float* __restrict__ g_twist) {
+  __shared__ double red[256];
+  const int f = blockIdx.x;
+  for (int j = 0; j < 6; ++j) {
+    double s = 0.0;
+    for (int64_t w = threadIdx.x; w < n_waves; w += blockDim.x)
+      s += part[((int64_t)f * n_waves + w) * 6 + j];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) g_twist[f * 6 + j] = (float)red[0];
+    __syncthreads();
+  }
+}
+
+void launch_preprocess_fwd(hipStream_t st, int64_t n, int F, const FrameDesc* frames,
+                           const float* poses, const float* means, const float* log_scales,
+                           const float* quats, const float* opac, const float* sh, int deg,
+                           int tile_w, int tile_h, Record* rec, uint32_t* depth_key,
+                           uint32_t* rec_id, uint32_t* ntiles) {
+  if (n <= 0) return;
+  const dim3 grid((unsigned)((n + 255) / 256));
+#define GSR_PRE_FWD(D)                                                                      \
+  hipLaunchKernelGGL(preprocess_fwd_kernel<D>, grid, dim3(256), 0, st, n, F, frames, poses, \
+                     means, log_scales, quats, opac, sh, tile_w, tile_h, rec, depth_key,    \
+                     rec_id, ntiles)
+  switch (deg) {
+    case 0: GSR_PRE_FWD(0); break;
+    case 1: GSR_PRE_FWD(1); break;
+    case 2: GSR_PRE_FWD(2); break;
+    default: GSR_PRE_FWD(3); break;
+  }
+#undef GSR_PRE_FWD
+}
+
+int64_t preprocess_bwd_waves(int64_t n) { return ((n + 255) / 256) * 4; }
+
+void launch_preprocess_bwd(hipStream_t st, int64_t n, int F, const FrameDesc* frames,
+                           const float* poses, const float* means, const float* log_scales,
+                           const float* quats, const float* opac, const float* sh, int deg,
+                           const Record* rec, const uint32_t* ntiles, const float* partial,
+                           const uint32_t* stamp, uint32_t epoch, uint64_t key_capacity,
+                           float* g_means, float* g_log_scales, float* g_quats, float* g_opac,
+                           float* g_sh, double* twist_partial, float* g_twist) {
+  const dim3 grid((unsigned)((n + 255) / 256));
+#define GSR_PRE_BWD(D)                                                                       \
+  hipLaunchKernelGGL(preprocess_bwd_kernel<D>, grid, dim3(256), 0, st, n, F, frames, poses,  \
+                     means, log_scales, quats, opac, sh, rec, ntiles, partial, stamp, epoch, \
+                     key_capacity, g_means, g_log_scales, g_quats, g_opac, g_sh, twist_partial)
+  if (n > 0) {
+    switch (deg) {
+      case 0: GSR_PRE_BWD(0); break;
+      case 1: GSR_PRE_BWD(1); break;
+      case 2: GSR_PRE_BWD(2); break;
+      default: GSR_PRE_BWD(3); break;
+    }
+  }
+#undef GSR_PRE_BWD
+  hipLaunchKernelGGL(twist_reduce_kernel, dim3(F), dim3(256), 0, st, twist_partial,
+                     n > 0 ? preprocess_bwd_waves(n) : 0, g_twist);
+}
+
+}  // namespace gsr

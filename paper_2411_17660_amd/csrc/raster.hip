@@ -1,0 +1,342 @@
+// raster.hip -- front-to-back compositing (forward) and its reverse-order
+// backward, one wavefront per tile.
+//
+// Forward, per pixel, over its tile's list in (depth, index) order
+// (DROID-Splat eqn:rendering, C = sum_i c_i a_i prod_{j<i}(1 - a_j), with
+// a_i = sigma_i G_i): entries whose 3-sigma square misses the pixel are
+// skipped; a = min(0.99, sigma exp(-q/2)); a < 1/255 is skipped; the pixel
+// stops before an entry that would drop T below 1e-4.  Outputs RGB + T bg,
+// the alpha-blended depth sum z_i a_i T_i and accumulated alpha 1 - T.
+//
+// Layout on CDNA4: a tile of TW x TH pixels is one 64-lane wave; lane l owns
+// column l % TW and PIX = TW*TH/64 pixels in row strips of 64/TW rows, so a
+// whole strip is skipped (wave-uniform branch) when an entry's square misses
+// its rows.  64 records at a time are staged in LDS by the wave itself and
+// read back as broadcasts; per-entry values stay wave-uniform.
+//
+// Backward: the wave walks the tile's processed prefix from the back.  Each
+// lane recomputes alpha bit-identically (same helpers, explicit fma), rebuilds
+// T_i = T_{i+1} / (1 - a_i), accumulates the 10 per-entry gradients over its
+// pixels, and the wave sums them with a butterfly; the result for this
+// (tile, entry) key goes to its own slot (no atomics), stamped with the
+// backward's epoch so the per-record reduction can skip slots of keys that
+// no pixel reached.
+#include "gsr_device.h"
+
+namespace gsr {
+
+__device__ __forceinline__ int tile_of_block(int bid, int n_tiles, bool xcd_remap) {
+  if (!xcd_remap) return bid;
+  // Consecutive workgroups go to the 8 XCDs in turn; give each XCD a
+  // contiguous run of tiles so neighbouring tiles share its L2.
+  const int per = (n_tiles + 7) / 8;
+  return (bid & 7) * per + (bid >> 3);
+}
+
+template <int TW, int TH, bool COUNT>
+__global__ void __launch_bounds__(64) composite_fwd_kernel(
+    int n_tiles, int n_frames, const FrameDesc* __restrict__ frames,
+    const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals,
+    const Record* __restrict__ rec, float bg0, float bg1, float bg2, float* __restrict__ rgb,
+    float* __restrict__ depth, float* __restrict__ alpha, float* __restrict__ t_final,
+    int32_t* __restrict__ n_last, uint32_t* __restrict__ tile_nproc, int xcd_remap,
+    unsigned long long* __restrict__ pair_count) {
+  constexpr int PIX = TW * TH / kWave;
+  constexpr int RPP = kWave / TW;  // rows per strip
+  __shared__ Record sm[kWave];
+  const int tile = tile_of_block(blockIdx.x, n_tiles, xcd_remap != 0);
+  if (tile >= n_tiles) return;
+  const int f = frame_of_tile(frames, n_frames, tile);
+  const FrameDesc fr = frames[f];
+  const int lt = tile - fr.tile_offset;
+  const int x0 = (lt % fr.grid_x) * TW, y0 = (lt / fr.grid_x) * TH;
+  const int lane = threadIdx.x;
+  const int px = x0 + lane % TW;
+  const int ly = lane / TW;
+  const uint2 rg = ranges[tile];
+
+  float T[PIX], C0[PIX], C1[PIX], C2[PIX], D[PIX];
+  int last[PIX];
+  bool done[PIX];
+  uint32_t hits = 0;  // (pixel, entry) pairs whose square test passed (COUNT only)
+#pragma unroll
+  for (int k = 0; k < PIX; ++k) {
+    T[k] = 1.0f; C0[k] = C1[k] = C2[k] = D[k] = 0.0f; last[k] = 0;
+    const int py = y0 + k * RPP + ly;
+    done[k] = !(px < fr.width && py < fr.height);
+  }
+  for (uint32_t b = rg.x; b < rg.y; b += kWave) {
+    bool live = false;
+#pragma unroll
+    for (int k = 0; k < PIX; ++k) live |= !done[k];
+    if (__ballot(live) == 0) break;
+    const uint32_t e = b + lane;
+    if (e < rg.y) sm[lane] = rec[vals[e]];
+    __syncthreads();
+    const int cnt = (int)min((uint32_t)kWave, rg.y - b);
+    for (int j = 0; j < cnt; ++j) {
+      const Record& R = sm[j];
+      const int xlo = R.sqx & 0xffff, xhi = R.sqx >> 16;
+      const int ylo = R.sqy & 0xffff, yhi = R.sqy >> 16;
+      const bool xin = (unsigned)(px - xlo) <= (unsigned)(xhi - xlo);
+      const float dx = dx_of(R.u_hi, R.u_lo, px);
+#pragma unroll
+      for (int k = 0; k < PIX; ++k) {
+        const int row0 = y0 + k * RPP;
+        if (ylo > row0 + RPP - 1 || yhi < row0) continue;  // strip missed (uniform)
+        const int py = row0 + ly;
+        if (done[k] || !xin || (unsigned)(py - ylo) > (unsigned)(yhi - ylo)) continue;
+        if (COUNT) ++hits;
+        const float dy = dx_of(R.v_hi, R.v_lo, py);
+        const float q = q_of(R.a1, R.a2, R.a3, dx, dy);
+        const float g = gauss_of(q);
+        const float a = fminf(kAlphaMax, R.opacity * g);
+        if (a < kAlphaMin) continue;
+        const float Tn = T[k] * (1.0f - a);
+        if (Tn < kTMin) { done[k] = true; continue; }
+        const float w = a * T[k];
+        C0[k] += R.c0 * w;
+        C1[k] += R.c1 * w;
+        C2[k] += R.c2 * w;
+        D[k] += R.z * w;
+        T[k] = Tn;
+        last[k] = (int)(b + j + 1 - rg.x);
+      }
+    }
+    __syncthreads();
+  }
+  int mx = 0;
+  const int64_t plane = (int64_t)fr.width * fr.height;
+#pragma unroll
+  for (int k = 0; k < PIX; ++k) {
+    const int py = y0 + k * RPP + ly;
+    if (px < fr.width && py < fr.height) {
+      const int64_t p = (int64_t)py * fr.width + px;
+      float* img = rgb + 3 * fr.pixel_offset;
+      img[p] = C0[k] + T[k] * bg0;
+      img[plane + p] = C1[k] + T[k] * bg1;
+      img[2 * plane + p] = C2[k] + T[k] * bg2;
+      depth[fr.pixel_offset + p] = D[k];
+      alpha[fr.pixel_offset + p] = 1.0f - T[k];
+      t_final[fr.pixel_offset + p] = T[k];
+      n_last[fr.pixel_offset + p] = last[k];
+      mx = max(mx, last[k]);
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
+  if (lane == 0) tile_nproc[tile] = (uint32_t)mx;
+  if (COUNT) {
+    unsigned long long h = hits;
+    for (int o = 32; o > 0; o >>= 1) h += __shfl_xor(h, o, 64);
+    if (lane == 0) atomicAdd(pair_count, h);
+  }
+}
+
+template <int TW, int TH>
+__global__ void __launch_bounds__(64) composite_bwd_kernel(
+    int n_tiles, int n_frames, const FrameDesc* __restrict__ frames,
+    const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals,
+    const Record* __restrict__ rec, const uint32_t* __restrict__ tile_nproc, float bg0,
+    float bg1, float bg2, const float* __restrict__ g_rgb, const float* __restrict__ g_depth,
+    const float* __restrict__ g_alpha, const float* __restrict__ t_final,
+    const int32_t* __restrict__ n_last, float* __restrict__ partial,
+    uint32_t* __restrict__ stamp, uint32_t epoch, int xcd_remap) {
+  constexpr int PIX = TW * TH / kWave;
+  constexpr int RPP = kWave / TW;
+  __shared__ Record sm[kWave];
+  __shared__ uint32_t slot[kWave];
+  const int tile = tile_of_block(blockIdx.x, n_tiles, xcd_remap != 0);
+  if (tile >= n_tiles) return;
+  const uint32_t nproc = tile_nproc[tile];
+  if (nproc == 0) return;
+  const int f = frame_of_tile(frames, n_frames, tile);
+  const FrameDesc fr = frames[f];
+  const int lt = tile - fr.tile_offset;
+  const int tx = lt % fr.grid_x, ty = lt / fr.grid_x;
+  const int x0 = tx * TW, y0 = ty * TH;
+  const int lane = threadIdx.x;
+  const int px = x0 + lane % TW;
+  const int ly = lane / TW;
+  const uint2 rg = ranges[tile];
+  const int64_t plane = (int64_t)fr.width * fr.height;
+
+  float T[PIX], Tf[PIX], A0[PIX], A1[PIX], A2[PIX], AZ[PIX];
+  float G0[PIX], G1[PIX], G2[PIX], GD[PIX], GA[PIX];
+  int last[PIX];
+#pragma unroll
+  for (int k = 0; k < PIX; ++k) {
+    const int py = y0 + k * RPP + ly;
+    const bool valid = px < fr.width && py < fr.height;
+    const int64_t p = (int64_t)py * fr.width + px;
+    last[k] = valid ? n_last[fr.pixel_offset + p] : 0;
+    Tf[k] = valid ? t_final[fr.pixel_offset + p] : 1.0f;
+    T[k] = Tf[k];
+    A0[k] = Tf[k] * bg0; A1[k] = Tf[k] * bg1; A2[k] = Tf[k] * bg2; AZ[k] = 0.0f;
+    const float* gi = g_rgb + 3 * fr.pixel_offset;
+    G0[k] = valid ? gi[p] : 0.0f;
+    G1[k] = valid ? gi[plane + p] : 0.0f;
+    G2[k] = valid ? gi[2 * plane + p] : 0.0f;
+    GD[k] = valid ? g_depth[fr.pixel_offset + p] : 0.0f;
+    GA[k] = valid ? g_alpha[fr.pixel_offset + p] : 0.0f;
+  }
+  for (int hi = (int)nproc; hi > 0; hi -= kWave) {
+    const int lo = max(0, hi - kWave);
+    if (lo + lane < hi) {
+      const uint32_t r = vals[rg.x + lo + lane];
+      const Record R = rec[r];
+      sm[lane] = R;
+      const int rx0 = (R.sqx & 0xffff) / TW, rx1 = (R.sqx >> 16) / TW;
+      const int ry0 = (R.sqy & 0xffff) / TH;
+      slot[lane] = R.key_offset + (uint32_t)((ty - ry0) * (rx1 - rx0 + 1) + (tx - rx0));
+    }
+    __syncthreads();
+    for (int j = hi - lo - 1; j >= 0; --j) {
+      const int pos = lo + j;
+      const Record& R = sm[j];
+      const int xlo = R.sqx & 0xffff, xhi = R.sqx >> 16;
+      const int ylo = R.sqy & 0xffff, yhi = R.sqy >> 16;
+      const bool xin = (unsigned)(px - xlo) <= (unsigned)(xhi - xlo);
+      const float dx = dx_of(R.u_hi, R.u_lo, px);
+      const float cA = R.a1 * R.a1, cB = R.a1 * R.a2, cC = R.a2 * R.a2 + R.a3 * R.a3;
+      float gu = 0.f, gv = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, gs = 0.f;
+      float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f, gz = 0.f;
+      bool any = false;
+#pragma unroll
+      for (int k = 0; k < PIX; ++k) {
+        const int row0 = y0 + k * RPP;
+        if (ylo > row0 + RPP - 1 || yhi < row0) continue;
+        const int py = row0 + ly;
+        if (pos >= last[k] || !xin || (unsigned)(py - ylo) > (unsigned)(yhi - ylo)) continue;
+        const float dy = dx_of(R.v_hi, R.v_lo, py);
+        const float q = q_of(R.a1, R.a2, R.a3, dx, dy);
+        const float g = gauss_of(q);
+        const float sg = R.opacity * g;
+        const float a = fminf(kAlphaMax, sg);
+        if (a < kAlphaMin) continue;
+        const float om = 1.0f - a;
+        const float inv = 1.0f / om;
+        const float Ti = T[k] * inv;
+        const float w = a * Ti;
+        const float dLda = G0[k] * (R.c0 * Ti - A0[k] * inv) + G1[k] * (R.c1 * Ti - A1[k] * inv) +
+                           G2[k] * (R.c2 * Ti - A2[k] * inv) + GD[k] * (R.z * Ti - AZ[k] * inv) +
+                           GA[k] * (Tf[k] * inv);
+        gc0 += G0[k] * w;
+        gc1 += G1[k] * w;
+        gc2 += G2[k] * w;
+        gz += GD[k] * w;
+        A0[k] += R.c0 * w;
+        A1[k] += R.c1 * w;
+        A2[k] += R.c2 * w;
+        AZ[k] += R.z * w;
+        T[k] = Ti;
+        any = true;
+        if (sg > kAlphaMax) continue;  // clamped: alpha does not move
+        gs += dLda * g;
+        const float dq = -0.5f * a * dLda;
+        gu += dq * 2.0f * (cA * dx + cB * dy);
+        gv += dq * 2.0f * (cB * dx + cC * dy);
+        gA += dq * dx * dx;
+        gB += dq * 2.0f * dx * dy;
+        gC += dq * dy * dy;
+      }
+      if (__ballot(any) == 0) continue;
+      for (int o = 32; o > 0; o >>= 1) {
+        gu += __shfl_xor(gu, o, 64);
+        gv += __shfl_xor(gv, o, 64);
+        gA += __shfl_xor(gA, o, 64);
+        gB += __shfl_xor(gB, o, 64);
+        gC += __shfl_xor(gC, o, 64);
+        gs += __shfl_xor(gs, o, 64);
+        gc0 += __shfl_xor(gc0, o, 64);
+        gc1 += __shfl_xor(gc1, o, 64);
+        gc2 += __shfl_xor(gc2, o, 64);
+        gz += __shfl_xor(gz, o, 64);
+      }
+      const uint32_t sl = slot[j];
+      float v = gu;
+      v = lane == 1 ? gv : v;
+      v = lane == 2 ? gA : v;
+      v = lane == 3 ? gB : v;
+      v = lane == 4 ? gC : v;
+      v = lane == 5 ? gs : v;
+      v = lane == 6 ? gc0 : v;
+      v = lane == 7 ? gc1 : v;
+      v = lane == 8 ? gc2 : v;
+      v = lane == 9 ? gz : v;
+      if (lane < kNG) partial[(size_t)sl * kNG + lane] = v;
+      if (lane == kNG) stamp[sl] = epoch;
+    }
+    __syncthreads();
+  }
+}
+
+template <int TW, int TH>
+static void launch_fwd_t(hipStream_t st, int n_tiles, int F, const FrameDesc* frames,
+                         const uint2* ranges, const uint32_t* vals, const Record* rec,
+                         const float* bg, float* rgb, float* depth, float* alpha,
+                         float* t_final, int32_t* n_last, uint32_t* nproc, bool remap,
+                         unsigned long long* pairs) {
+  const unsigned grid = remap ? (unsigned)(((n_tiles + 7) / 8) * 8) : (unsigned)n_tiles;
+  if (pairs)
+    hipLaunchKernelGGL((composite_fwd_kernel<TW, TH, true>), dim3(grid), dim3(kWave), 0, st,
+                       n_tiles, F, frames, ranges, vals, rec, bg[0], bg[1], bg[2], rgb, depth,
+                       alpha, t_final, n_last, nproc, remap ? 1 : 0, pairs);
+  else
+    hipLaunchKernelGGL((composite_fwd_kernel<TW, TH, false>), dim3(grid), dim3(kWave), 0, st,
+                       n_tiles, F, frames, ranges, vals, rec, bg[0], bg[1], bg[2], rgb, depth,
+                       alpha, t_final, n_last, nproc, remap ? 1 : 0, pairs);
+}
+
+template <int TW, int TH>
+static void launch_bwd_t(hipStream_t st, int n_tiles, int F, const FrameDesc* frames,
+                         const uint2* ranges, const uint32_t* vals, const Record* rec,
+                         const uint32_t* nproc, const float* bg, const float* g_rgb,
+                         const float* g_depth, const float* g_alpha, const float* t_final,
+                         const int32_t* n_last, float* partial, uint32_t* stamp, uint32_t epoch,
+                         bool remap) {
+  const unsigned grid = remap ? (unsigned)(((n_tiles + 7) / 8) * 8) : (unsigned)n_tiles;
+  hipLaunchKernelGGL((composite_bwd_kernel<TW, TH>), dim3(grid), dim3(kWave), 0, st, n_tiles, F,
+                     frames, ranges, vals, rec, nproc, bg[0], bg[1], bg[2], g_rgb, g_depth,
+                     g_alpha, t_final, n_last, partial, stamp, epoch, remap ? 1 : 0);
+}
+
+bool tile_shape_supported(int tw, int th) {
+  return (tw == 16 && th == 16) || (tw == 8 && th == 8) || (tw == 32 && th == 8) ||
+         (tw == 16 && th == 8) || (tw == 32 && th == 16);
+}
+
+void launch_composite_fwd(hipStream_t st, int tw, int th, int n_tiles, int F,
+                          const FrameDesc* frames, const uint2* ranges, const uint32_t* vals,
+                          const Record* rec, const float* bg, float* rgb, float* depth,
+                          float* alpha, float* t_final, int32_t* n_last, uint32_t* nproc,
+                          bool remap, unsigned long long* pairs) {
+  if (n_tiles <= 0) return;
+#define GSR_FWD(W, H) launch_fwd_t<W, H>(st, n_tiles, F, frames, ranges, vals, rec, bg, rgb, \
+                                         depth, alpha, t_final, n_last, nproc, remap, pairs)
+  if (tw == 16 && th == 16) GSR_FWD(16, 16);
+  else if (tw == 8 && th == 8) GSR_FWD(8, 8);
+  else if (tw == 32 && th == 8) GSR_FWD(32, 8);
+  else if (tw == 16 && th == 8) GSR_FWD(16, 8);
+  else if (tw == 32 && th == 16) GSR_FWD(32, 16);
+#undef GSR_FWD
+}
+
+void launch_composite_bwd(hipStream_t st, int tw, int th, int n_tiles, int F,
+                          const FrameDesc* frames, const uint2* ranges, const uint32_t* vals,
+                          const Record* rec, const uint32_t* nproc, const float* bg,
+                          const float* g_rgb, const float* g_depth, const float* g_alpha,
+                          const float* t_final, const int32_t* n_last, float* partial,
+                          uint32_t* stamp, uint32_t epoch, bool remap) {
+  if (n_tiles <= 0) return;
+#define GSR_BWD(W, H)                                                                          \
+  launch_bwd_t<W, H>(st, n_tiles, F, frames, ranges, vals, rec, nproc, bg, g_rgb, g_depth,   \
+                     g_alpha, t_final, n_last, partial, stamp, epoch, remap)
+  if (tw == 16 && th == 16) GSR_BWD(16, 16);
+  else if (tw == 8 && th == 8) GSR_BWD(8, 8);
+  else if (tw == 32 && th == 8) GSR_BWD(32, 8);
+  else if (tw == 16 && th == 8) GSR_BWD(16, 8);
+  else if (tw == 32 && th == 16) GSR_BWD(32, 16);
+#undef GSR_BWD
+}
+
+}  // namespace gsr

@@ -1,0 +1,674 @@
+// runtime.hip -- host side of libgsr.so: context, workspace, validation and
+// the launch sequences behind the C ABI (include/gsr.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/gsr.h"
+#include "gsr_device.h"
+
+namespace gsr {
+// preprocess.hip
+void launch_preprocess_fwd(hipStream_t, int64_t, int, const FrameDesc*, const float*,
+                           const float*, const float*, const float*, const float*, const float*,
+                           int, int, int, Record*, uint32_t*, uint32_t*, uint32_t*);
+int64_t preprocess_bwd_waves(int64_t n);
+void launch_preprocess_bwd(hipStream_t, int64_t, int, const FrameDesc*, const float*,
+                           const float*, const float*, const float*, const float*, const float*,
+                           int, const Record*, const uint32_t*, const float*, const uint32_t*,
+                           uint32_t, uint64_t, float*, float*, float*, float*, float*, double*,
+                           float*);
+// sort.hip
+void launch_fill_u32(hipStream_t, uint32_t*, uint64_t, uint32_t);
+size_t radix_hist_elems(uint64_t n_max);
+size_t scan_block_elems(uint64_t n_max);
+bool launch_radix_sort(hipStream_t, uint32_t*, uint32_t*, uint32_t*, uint32_t*, const uint64_t*,
+                       uint64_t, int, uint32_t*, uint32_t*);
+void launch_offsets_scan(hipStream_t, const uint32_t*, const uint32_t*, uint64_t, uint64_t*,
+                         uint64_t*, uint64_t*);
+void launch_keygen(hipStream_t, uint64_t, const uint32_t*, const uint32_t*, const uint64_t*,
+                   Record*, const FrameDesc*, int, int, uint64_t, uint32_t*, uint32_t*,
+                   uint32_t*);
+void launch_ranges(hipStream_t, const uint32_t*, const uint64_t*, uint64_t, uint64_t, uint2*,
+                   uint64_t);
+// raster.hip
+bool tile_shape_supported(int tw, int th);
+void launch_composite_fwd(hipStream_t, int, int, int, int, const FrameDesc*, const uint2*,
+                          const uint32_t*, const Record*, const float*, float*, float*, float*,
+                          float*, int32_t*, uint32_t*, bool, unsigned long long*);
+void launch_composite_bwd(hipStream_t, int, int, int, int, const FrameDesc*, const uint2*,
+                          const uint32_t*, const Record*, const uint32_t*, const float*,
+                          const float*, const float*, const float*, const float*,
+                          const int32_t*, float*, uint32_t*, uint32_t, bool);
+// loss.hip
+int loss_blocks_x(int64_t max_hw);
+void launch_loss_l1(hipStream_t, int, int, const FrameDesc*, const float*, const float*,
+                    const float*, const float*, float, double*, float*, float*, float*, float*,
+                    float*);
+}  // namespace gsr
+
+using namespace gsr;
+
+namespace {
+
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct Saved {
+  bool valid = false;
+  gsr_settings set{};
+  int64_t n = 0;
+  int F = 0;
+  const float *means = nullptr, *log_scales = nullptr, *quats = nullptr, *opac = nullptr,
+              *sh = nullptr, *poses = nullptr;
+  const float *rgb = nullptr, *depth = nullptr;
+  int64_t T = 0, P = 0, max_hw = 0;
+  uint64_t K = 0;          // exact count (grow mode) or capacity bound (fixed mode)
+  bool k_known = false;
+  bool sorted_in_b = false;   // tile sort result buffer
+  bool recs_in_b = false;     // depth sort result buffer
+};
+
+}  // namespace
+
+struct gsr_context {
+  int device = 0;
+  std::string err;
+  // workspace
+  DBuf rec, dkey_a, dval_a, dkey_b, dval_b, ntiles, offsets, scan_tmp, hist, counters;
+  DBuf keys_a, vals_a, keys_b, vals_b, partial, stamp;
+  DBuf ranges, nproc, t_final, n_last, frames, twist_part, loss_part, loss_scale;
+  DBuf up_rgb, up_depth, up_alpha;  // upstream gradients for gsr_step_l1
+  uint64_t key_cap = 0;             // allocated key slots
+  // pinned host staging
+  FrameDesc* h_frames = nullptr;
+  int h_frames_cap = 0;
+  uint64_t* h_count = nullptr;
+  hipEvent_t frames_ev = nullptr;
+  std::vector<FrameDesc> last_frames;
+  uint32_t epoch = 0;
+  Saved s;
+  // GSR_FLAG_TIMING: event pairs per stage, read by gsr_debug_timings
+  struct Timed { int stage; hipEvent_t a, b; };
+  std::vector<Timed> timed;
+  std::vector<hipEvent_t> ev_pool;
+  int64_t n_pairs = -1;
+};
+
+namespace {
+
+gsr_status fail(gsr_context* c, gsr_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return code;
+}
+
+gsr_status hip_check(gsr_context* c, hipError_t e, const char* what) {
+  if (e == hipSuccess) return GSR_OK;
+  return fail(c, GSR_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define GSR_HIP(expr)                                            \
+  do {                                                           \
+    gsr_status _s = hip_check(ctx, (expr), #expr);               \
+    if (_s != GSR_OK) return _s;                                 \
+  } while (0)
+
+// Grow-only device buffer.  Growing synchronises the stream first so that no
+// queued kernel still uses the old allocation.
+gsr_status ensure(gsr_context* ctx, DBuf& b, size_t bytes, hipStream_t st, bool zero = false) {
+  if (bytes == 0) bytes = 16;
+  if (b.bytes >= bytes) return GSR_OK;
+  const size_t want = bytes + bytes / 4;
+  if (b.p) {
+    GSR_HIP(hipStreamSynchronize(st));
+    GSR_HIP(hipFree(b.p));
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, GSR_ERR_OUT_OF_MEMORY, "hipMalloc of %zu bytes failed", want);
+  }
+  b.p = p;
+  b.bytes = want;
+  if (zero) GSR_HIP(hipMemsetAsync(p, 0, want, st));
+  return GSR_OK;
+}
+
+template <typename T>
+T* P(const DBuf& b) { return static_cast<T*>(b.p); }
+
+// Bits needed for values < v.  The tile sort uses bits_for(T + 1) so that the
+// all-ones sentinel of an overflowed record never aliases a real tile id.
+int bits_for(uint64_t v) {
+  int b = 1;
+  while (b < 32 && (1ull << b) < v) ++b;
+  return b;
+}
+
+gsr_status validate(gsr_context* ctx, const gsr_settings* s, int64_t n, const float* means,
+                    const float* log_scales, const float* quats, const float* opac,
+                    const float* sh, int32_t F, const gsr_camera* cams, const float* poses,
+                    const float* rgb, const float* depth, const float* alpha) {
+  if (!ctx) return GSR_ERR_INVALID_ARGUMENT;
+  if (!s) return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "settings is NULL");
+  if (n < 0) return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "n < 0");
+  if (n >= (int64_t)1 << 31) return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "n >= 2^31");
+  if (F < 1) return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "n_frames < 1");
+  if ((int64_t)F * n >= (int64_t)1 << 32)
+    return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "n * n_frames >= 2^32");
+  if (s->sh_degree < 0 || s->sh_degree > 3)
+    return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "sh_degree %d not in [0,3]", s->sh_degree);
+  if (!tile_shape_supported(s->tile_w, s->tile_h))
+    return fail(ctx, GSR_ERR_UNSUPPORTED, "tile shape %dx%d not supported", s->tile_w,
+                s->tile_h);
+  if (s->lds_batch != 0 && s->lds_batch != kWave)
+    return fail(ctx, GSR_ERR_UNSUPPORTED, "lds_batch %d not supported", s->lds_batch);
+  if (s->key_capacity < 0 || s->key_capacity >= ((int64_t)1 << 32))
+    return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "key_capacity out of range");
+  if (!cams || !poses) return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "cams/poses is NULL");
+  if (!rgb || !depth || !alpha) return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "output is NULL");
+  if (n > 0 && (!means || !log_scales || !quats || !opac || !sh))
+    return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "parameter pointer is NULL");
+  const void* ptrs[] = {means, log_scales, quats, opac, sh, poses, rgb, depth, alpha};
+  for (const void* p : ptrs)
+    if (((uintptr_t)p) & 3u) return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "pointer not 4-aligned");
+  for (int f = 0; f < F; ++f) {
+    const gsr_camera& c = cams[f];
+    if (c.width < 1 || c.height < 1 || c.width > 65535 || c.height > 65535)
+      return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "frame %d: size %dx%d", f, c.width, c.height);
+    if (!(c.fx > 0.0f) || !(c.fy > 0.0f))
+      return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "frame %d: focal length <= 0", f);
+  }
+  return GSR_OK;
+}
+
+// Frame descriptors to the device (re-uploaded only when they change).
+gsr_status upload_frames(gsr_context* ctx, const std::vector<FrameDesc>& fr, hipStream_t st) {
+  const size_t bytes = fr.size() * sizeof(FrameDesc);
+  if (ctx->last_frames.size() == fr.size() &&
+      std::memcmp(ctx->last_frames.data(), fr.data(), bytes) == 0)
+    return GSR_OK;
+  gsr_status rc = ensure(ctx, ctx->frames, bytes, st);
+  if (rc) return rc;
+  if ((int)fr.size() > ctx->h_frames_cap) {
+    if (ctx->h_frames) {
+      GSR_HIP(hipEventSynchronize(ctx->frames_ev));
+      GSR_HIP(hipHostFree(ctx->h_frames));
+    }
+    GSR_HIP(hipHostMalloc((void**)&ctx->h_frames, bytes, hipHostMallocDefault));
+    ctx->h_frames_cap = (int)fr.size();
+  } else {
+    GSR_HIP(hipEventSynchronize(ctx->frames_ev));  // previous copy has read the staging
+  }
+  std::memcpy(ctx->h_frames, fr.data(), bytes);
+  GSR_HIP(hipMemcpyAsync(ctx->frames.p, ctx->h_frames, bytes, hipMemcpyHostToDevice, st));
+  GSR_HIP(hipEventRecord(ctx->frames_ev, st));
+  ctx->last_frames = fr;
+  return GSR_OK;
+}
+
+hipEvent_t take_event(gsr_context* ctx) {
+  if (!ctx->ev_pool.empty()) {
+    hipEvent_t e = ctx->ev_pool.back();
+    ctx->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one stage with events on the call's stream when timing is on.
+struct StageTimer {
+  gsr_context* ctx;
+  hipStream_t st;
+  int stage;
+  hipEvent_t a = nullptr;
+  StageTimer(gsr_context* c, hipStream_t s, bool on, int id) : ctx(c), st(s), stage(id) {
+    if (!on) return;
+    a = take_event(ctx);
+    if (a) (void)hipEventRecord(a, st);
+  }
+  ~StageTimer() {
+    if (!a) return;
+    hipEvent_t b = take_event(ctx);
+    if (!b) return;
+    (void)hipEventRecord(b, st);
+    ctx->timed.push_back({stage, a, b});
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+gsr_status gsr_create(gsr_context** out, int32_t device) {
+  if (!out) return GSR_ERR_INVALID_ARGUMENT;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+    return GSR_ERR_INVALID_ARGUMENT;
+  if (hipSetDevice(device) != hipSuccess) return GSR_ERR_HIP;
+  gsr_context* ctx = new (std::nothrow) gsr_context();
+  if (!ctx) return GSR_ERR_OUT_OF_MEMORY;
+  ctx->device = device;
+  if (hipEventCreateWithFlags(&ctx->frames_ev, hipEventDisableTiming) != hipSuccess ||
+      hipHostMalloc((void**)&ctx->h_count, sizeof(uint64_t) * 4, hipHostMallocDefault) !=
+          hipSuccess) {
+    delete ctx;
+    return GSR_ERR_HIP;
+  }
+  *out = ctx;
+  return GSR_OK;
+}
+
+gsr_status gsr_destroy(gsr_context* ctx) {
+  if (!ctx) return GSR_ERR_INVALID_ARGUMENT;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  DBuf* bufs[] = {&ctx->rec, &ctx->dkey_a, &ctx->dval_a, &ctx->dkey_b, &ctx->dval_b,
+                  &ctx->ntiles, &ctx->offsets, &ctx->scan_tmp, &ctx->hist, &ctx->counters,
+                  &ctx->keys_a, &ctx->vals_a, &ctx->keys_b, &ctx->vals_b, &ctx->partial,
+                  &ctx->stamp, &ctx->ranges, &ctx->nproc, &ctx->t_final, &ctx->n_last,
+                  &ctx->frames, &ctx->twist_part, &ctx->loss_part, &ctx->loss_scale,
+                  &ctx->up_rgb, &ctx->up_depth, &ctx->up_alpha};
+  for (DBuf* b : bufs)
+    if (b->p) (void)hipFree(b->p);
+  if (ctx->h_frames) (void)hipHostFree(ctx->h_frames);
+  if (ctx->h_count) (void)hipHostFree(ctx->h_count);
+  if (ctx->frames_ev) (void)hipEventDestroy(ctx->frames_ev);
+  for (auto& t : ctx->timed) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  delete ctx;
+  return GSR_OK;
+}
+
+const char* gsr_last_error(const gsr_context* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+gsr_status gsr_forward(gsr_context* ctx, const gsr_settings* s, int64_t n, const float* means,
+                       const float* log_scales, const float* quats, const float* opac,
+                       const float* sh, int32_t F, const gsr_camera* cams, const float* poses,
+                       float* rgb, float* depth, float* alpha, void* stream) {
+  gsr_status rc = validate(ctx, s, n, means, log_scales, quats, opac, sh, F, cams, poses, rgb,
+                           depth, alpha);
+  if (rc) return rc;
+  ctx->err.clear();
+  ctx->s.valid = false;
+  hipStream_t st = (hipStream_t)stream;
+  GSR_HIP(hipSetDevice(ctx->device));
+  const int tw = s->tile_w, th = s->tile_h;
+  // A0: frame descriptors
+  std::vector<FrameDesc> fr(F);
+  int64_t T = 0, Px = 0, max_hw = 0;
+  for (int f = 0; f < F; ++f) {
+    const gsr_camera& c = cams[f];
+    FrameDesc& d = fr[f];
+    d.width = c.width; d.height = c.height;
+    d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy; d.near_z = c.near_z;
+    d.grid_x = (c.width + tw - 1) / tw;
+    d.grid_y = (c.height + th - 1) / th;
+    d.tile_offset = (int32_t)T;
+    d.pixel_offset = Px;
+    T += (int64_t)d.grid_x * d.grid_y;
+    Px += (int64_t)c.width * c.height;
+    max_hw = std::max<int64_t>(max_hw, (int64_t)c.width * c.height);
+  }
+  if (T >= ((int64_t)1 << 31)) return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "too many tiles");
+  if ((rc = upload_frames(ctx, fr, st))) return rc;
+  const uint64_t M = (uint64_t)n * F;
+  // workspace sized by M, T, P
+  if ((rc = ensure(ctx, ctx->rec, M * sizeof(Record), st))) return rc;
+  if ((rc = ensure(ctx, ctx->dkey_a, M * 4, st))) return rc;
+  if ((rc = ensure(ctx, ctx->dval_a, M * 4, st))) return rc;
+  if ((rc = ensure(ctx, ctx->dkey_b, M * 4, st))) return rc;
+  if ((rc = ensure(ctx, ctx->dval_b, M * 4, st))) return rc;
+  if ((rc = ensure(ctx, ctx->ntiles, M * 4, st))) return rc;
+  if ((rc = ensure(ctx, ctx->offsets, M * 8, st))) return rc;
+  if ((rc = ensure(ctx, ctx->counters, 64, st, true))) return rc;
+  if ((rc = ensure(ctx, ctx->ranges, (size_t)T * 8, st))) return rc;
+  if ((rc = ensure(ctx, ctx->nproc, (size_t)T * 4, st))) return rc;
+  if ((rc = ensure(ctx, ctx->t_final, (size_t)Px * 4, st))) return rc;
+  if ((rc = ensure(ctx, ctx->n_last, (size_t)Px * 4, st))) return rc;
+  uint64_t* d_count = P<uint64_t>(ctx->counters);               // [0] = K
+  uint32_t* d_overflow = (uint32_t*)(P<uint64_t>(ctx->counters) + 1);
+  const bool timing = (s->flags & GSR_FLAG_TIMING) != 0;
+  // A1 preprocess
+  {
+    StageTimer t(ctx, st, timing, GSR_STAGE_PREPROCESS);
+    launch_preprocess_fwd(st, n, F, P<FrameDesc>(ctx->frames), poses, means, log_scales, quats,
+                          opac, sh, s->sh_degree, tw, th, P<Record>(ctx->rec),
+                          P<uint32_t>(ctx->dkey_a), P<uint32_t>(ctx->dval_a),
+                          P<uint32_t>(ctx->ntiles));
+  }
+  // depth sort of the records (32-bit keys)
+  const uint64_t kcap_guess = std::max<uint64_t>(ctx->key_cap, s->key_capacity);
+  const size_t hist_need = std::max(radix_hist_elems(M), radix_hist_elems(std::max<uint64_t>(kcap_guess, 1)));
+  if ((rc = ensure(ctx, ctx->hist, hist_need * 4, st))) return rc;
+  const size_t scan_need = std::max(scan_block_elems(M), scan_block_elems(hist_need));
+  if ((rc = ensure(ctx, ctx->scan_tmp, scan_need * 8, st))) return rc;
+  bool recs_in_b = false;
+  {
+    StageTimer t(ctx, st, timing, GSR_STAGE_DEPTH_SORT);
+    if (M > 0)
+      recs_in_b = launch_radix_sort(st, P<uint32_t>(ctx->dkey_a), P<uint32_t>(ctx->dval_a),
+                                    P<uint32_t>(ctx->dkey_b), P<uint32_t>(ctx->dval_b), nullptr,
+                                    M, 32, P<uint32_t>(ctx->hist), P<uint32_t>(ctx->scan_tmp));
+  }
+  const uint32_t* perm = P<uint32_t>(recs_in_b ? ctx->dval_b : ctx->dval_a);
+  // A2 offsets over the depth-ordered records, K on the device
+  {
+    StageTimer t(ctx, st, timing, GSR_STAGE_OFFSETS);
+    launch_offsets_scan(st, P<uint32_t>(ctx->ntiles), perm, M, P<uint64_t>(ctx->offsets),
+                        P<uint64_t>(ctx->scan_tmp), d_count);
+  }
+  // key capacity
+  uint64_t K = 0, cap = 0;
+  bool k_known = false;
+  if (s->key_capacity == 0) {
+    GSR_HIP(hipMemcpyAsync(ctx->h_count, d_count, 8, hipMemcpyDeviceToHost, st));
+    GSR_HIP(hipStreamSynchronize(st));
+    K = ctx->h_count[0];
+    if (K >= (1ull << 32) - 1) return fail(ctx, GSR_ERR_CAPACITY, "%llu keys exceed 2^32",
+                                           (unsigned long long)K);
+    cap = K;
+    k_known = true;
+  } else {
+    cap = (uint64_t)s->key_capacity;
+    K = cap;
+  }
+  if (cap > ctx->key_cap || !ctx->keys_a.p) {
+    const uint64_t c2 = std::max<uint64_t>(cap, 1);
+    if ((rc = ensure(ctx, ctx->keys_a, c2 * 4, st))) return rc;
+    if ((rc = ensure(ctx, ctx->vals_a, c2 * 4, st))) return rc;
+    if ((rc = ensure(ctx, ctx->keys_b, c2 * 4, st))) return rc;
+    if ((rc = ensure(ctx, ctx->vals_b, c2 * 4, st))) return rc;
+    if ((rc = ensure(ctx, ctx->partial, c2 * kNG * 4, st))) return rc;
+    if ((rc = ensure(ctx, ctx->stamp, c2 * 4, st, true))) return rc;
+    ctx->key_cap = std::min({ctx->keys_a.bytes / 4, ctx->keys_b.bytes / 4, ctx->vals_a.bytes / 4,
+                             ctx->vals_b.bytes / 4, ctx->partial.bytes / (kNG * 4),
+                             ctx->stamp.bytes / 4});
+    const size_t h2 = radix_hist_elems(ctx->key_cap);
+    if ((rc = ensure(ctx, ctx->hist, h2 * 4, st))) return rc;
+    if ((rc = ensure(ctx, ctx->scan_tmp, std::max(scan_block_elems(M), scan_block_elems(h2)) * 8,
+                     st)))
+      return rc;
+  }
+  const uint64_t use_cap = s->key_capacity ? std::min<uint64_t>(cap, ctx->key_cap) : ctx->key_cap;
+  // A3 keygen
+  {
+    StageTimer t(ctx, st, timing, GSR_STAGE_KEYGEN);
+    launch_keygen(st, M, perm, P<uint32_t>(ctx->ntiles), P<uint64_t>(ctx->offsets),
+                  P<Record>(ctx->rec), P<FrameDesc>(ctx->frames), tw, th, use_cap,
+                  P<uint32_t>(ctx->keys_a), P<uint32_t>(ctx->vals_a), d_overflow);
+  }
+  // A4 stable sort by tile id
+  const uint64_t sort_n = k_known ? K : use_cap;
+  bool keys_in_b = false;
+  {
+    StageTimer t(ctx, st, timing, GSR_STAGE_TILE_SORT);
+    if (sort_n > 0)
+      keys_in_b = launch_radix_sort(st, P<uint32_t>(ctx->keys_a), P<uint32_t>(ctx->vals_a),
+                                    P<uint32_t>(ctx->keys_b), P<uint32_t>(ctx->vals_b),
+                                    k_known ? nullptr : d_count, sort_n,
+                                    bits_for((uint64_t)T + 1), P<uint32_t>(ctx->hist),
+                                    P<uint32_t>(ctx->scan_tmp));
+  }
+  const uint32_t* skeys = P<uint32_t>(keys_in_b ? ctx->keys_b : ctx->keys_a);
+  const uint32_t* svals = P<uint32_t>(keys_in_b ? ctx->vals_b : ctx->vals_a);
+  // A5 ranges
+  {
+    StageTimer t(ctx, st, timing, GSR_STAGE_RANGES);
+    launch_ranges(st, skeys, d_count, sort_n, use_cap, P<uint2>(ctx->ranges), (uint64_t)T);
+  }
+  // A6 compositing
+  const bool remap = !(s->flags & GSR_FLAG_NO_XCD_REMAP);
+  unsigned long long* d_pairs = (unsigned long long*)(P<uint64_t>(ctx->counters) + 2);
+  const bool count = (s->flags & GSR_FLAG_COUNT_PAIRS) != 0;
+  if (count) launch_fill_u32(st, (uint32_t*)d_pairs, 2, 0u);
+  {
+    StageTimer t(ctx, st, timing, GSR_STAGE_COMPOSITE_FWD);
+    launch_composite_fwd(st, tw, th, (int)T, F, P<FrameDesc>(ctx->frames),
+                         P<uint2>(ctx->ranges), svals, P<Record>(ctx->rec), s->background, rgb,
+                         depth, alpha, P<float>(ctx->t_final), P<int32_t>(ctx->n_last),
+                         P<uint32_t>(ctx->nproc), remap, count ? d_pairs : nullptr);
+  }
+  ctx->n_pairs = count ? -2 : -1;  // -2: count pending on the device
+  GSR_HIP(hipGetLastError());
+  Saved& sv = ctx->s;
+  sv.valid = true;
+  sv.set = *s;
+  sv.n = n;
+  sv.F = F;
+  sv.means = means; sv.log_scales = log_scales; sv.quats = quats; sv.opac = opac; sv.sh = sh;
+  sv.poses = poses;
+  sv.rgb = rgb;
+  sv.depth = depth;
+  sv.T = T;
+  sv.P = Px;
+  sv.max_hw = max_hw;
+  sv.K = sort_n;
+  sv.k_known = k_known;
+  sv.sorted_in_b = keys_in_b;
+  sv.recs_in_b = recs_in_b;
+  return GSR_OK;
+}
+
+gsr_status gsr_backward(gsr_context* ctx, const float* g_rgb, const float* g_depth,
+                        const float* g_alpha, float* g_means, float* g_log_scales,
+                        float* g_quats, float* g_opac, float* g_sh, float* g_twist,
+                        void* stream) {
+  if (!ctx) return GSR_ERR_INVALID_ARGUMENT;
+  Saved& sv = ctx->s;
+  if (!sv.valid) return fail(ctx, GSR_ERR_STATE, "backward without a preceding forward");
+  if (!g_rgb || !g_depth || !g_alpha || !g_twist)
+    return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "gradient pointer is NULL");
+  if (sv.n > 0 && (!g_means || !g_log_scales || !g_quats || !g_opac || !g_sh))
+    return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "gradient pointer is NULL");
+  ctx->err.clear();
+  hipStream_t st = (hipStream_t)stream;
+  GSR_HIP(hipSetDevice(ctx->device));
+  const gsr_settings& s = sv.set;
+  gsr_status rc;
+  ++ctx->epoch;
+  if (ctx->epoch == 0) {  // wrapped: restart the stamps
+    GSR_HIP(hipMemsetAsync(ctx->stamp.p, 0, ctx->stamp.bytes, st));
+    ctx->epoch = 1;
+  }
+  const uint32_t* svals = P<uint32_t>(sv.sorted_in_b ? ctx->vals_b : ctx->vals_a);
+  const bool remap = !(s.flags & GSR_FLAG_NO_XCD_REMAP);
+  const bool timing = (s.flags & GSR_FLAG_TIMING) != 0;
+  // A8 reverse compositing -> per-key partials
+  {
+    StageTimer t(ctx, st, timing, GSR_STAGE_COMPOSITE_BWD);
+    launch_composite_bwd(st, s.tile_w, s.tile_h, (int)sv.T, sv.F, P<FrameDesc>(ctx->frames),
+                         P<uint2>(ctx->ranges), svals, P<Record>(ctx->rec),
+                         P<uint32_t>(ctx->nproc), s.background, g_rgb, g_depth, g_alpha,
+                         P<float>(ctx->t_final), P<int32_t>(ctx->n_last),
+                         P<float>(ctx->partial), P<uint32_t>(ctx->stamp), ctx->epoch, remap);
+  }
+  // A9-A11 per-record reduce, chain rule, twist
+  const int64_t waves = sv.n > 0 ? preprocess_bwd_waves(sv.n) : 0;
+  if ((rc = ensure(ctx, ctx->twist_part, (size_t)std::max<int64_t>(waves, 1) * sv.F * 6 * 8, st)))
+    return rc;
+  {
+    StageTimer t(ctx, st, timing, GSR_STAGE_PREPROCESS_BWD);
+    launch_preprocess_bwd(st, sv.n, sv.F, P<FrameDesc>(ctx->frames), sv.poses, sv.means,
+                          sv.log_scales, sv.quats, sv.opac, sv.sh, s.sh_degree,
+                          P<Record>(ctx->rec), P<uint32_t>(ctx->ntiles), P<float>(ctx->partial),
+                          P<uint32_t>(ctx->stamp), ctx->epoch, ctx->key_cap, g_means,
+                          g_log_scales, g_quats, g_opac, g_sh, P<double>(ctx->twist_part),
+                          g_twist);
+  }
+  GSR_HIP(hipGetLastError());
+  return GSR_OK;
+}
+
+gsr_status gsr_loss_l1(gsr_context* ctx, const float* target_rgb, const float* target_depth,
+                       float depth_weight, float* loss, float* g_rgb, float* g_depth,
+                       float* g_alpha, void* stream) {
+  if (!ctx) return GSR_ERR_INVALID_ARGUMENT;
+  Saved& sv = ctx->s;
+  if (!sv.valid) return fail(ctx, GSR_ERR_STATE, "loss without a preceding forward");
+  if (!target_rgb || !target_depth || !loss || !g_rgb || !g_depth || !g_alpha)
+    return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "pointer is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  GSR_HIP(hipSetDevice(ctx->device));
+  const int bx = loss_blocks_x(sv.max_hw);
+  gsr_status rc;
+  if ((rc = ensure(ctx, ctx->loss_part, (size_t)bx * sv.F * 3 * 8, st))) return rc;
+  if ((rc = ensure(ctx, ctx->loss_scale, (size_t)sv.F * 2 * 4, st))) return rc;
+  {
+    StageTimer t(ctx, st, (sv.set.flags & GSR_FLAG_TIMING) != 0, GSR_STAGE_LOSS);
+    launch_loss_l1(st, sv.F, bx, P<FrameDesc>(ctx->frames), sv.rgb, sv.depth, target_rgb,
+                   target_depth, depth_weight, P<double>(ctx->loss_part),
+                   P<float>(ctx->loss_scale), loss, g_rgb, g_depth, g_alpha);
+  }
+  GSR_HIP(hipGetLastError());
+  return GSR_OK;
+}
+
+gsr_status gsr_step_l1(gsr_context* ctx, const gsr_settings* s, int64_t n, const float* means,
+                       const float* log_scales, const float* quats, const float* opac,
+                       const float* sh, int32_t F, const gsr_camera* cams, const float* poses,
+                       const float* target_rgb, const float* target_depth, float depth_weight,
+                       float* rgb, float* depth, float* alpha, float* loss, float* g_means,
+                       float* g_log_scales, float* g_quats, float* g_opac, float* g_sh,
+                       float* g_twist, void* stream) {
+  gsr_status rc = gsr_forward(ctx, s, n, means, log_scales, quats, opac, sh, F, cams, poses,
+                              rgb, depth, alpha, stream);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t npix = (size_t)ctx->s.P;
+  if ((rc = ensure(ctx, ctx->up_rgb, npix * 3 * 4, st))) return rc;
+  if ((rc = ensure(ctx, ctx->up_depth, npix * 4, st))) return rc;
+  if ((rc = ensure(ctx, ctx->up_alpha, npix * 4, st))) return rc;
+  rc = gsr_loss_l1(ctx, target_rgb, target_depth, depth_weight, loss, P<float>(ctx->up_rgb),
+                   P<float>(ctx->up_depth), P<float>(ctx->up_alpha), stream);
+  if (rc) return rc;
+  return gsr_backward(ctx, P<float>(ctx->up_rgb), P<float>(ctx->up_depth),
+                      P<float>(ctx->up_alpha), g_means, g_log_scales, g_quats, g_opac, g_sh,
+                      g_twist, stream);
+}
+
+gsr_status gsr_check_overflow(gsr_context* ctx, void* stream) {
+  if (!ctx) return GSR_ERR_INVALID_ARGUMENT;
+  if (!ctx->counters.p) return GSR_OK;
+  hipStream_t st = (hipStream_t)stream;
+  GSR_HIP(hipSetDevice(ctx->device));
+  GSR_HIP(hipMemcpyAsync(ctx->h_count, ctx->counters.p, 16, hipMemcpyDeviceToHost, st));
+  GSR_HIP(hipStreamSynchronize(st));
+  const uint32_t flag = (uint32_t)(ctx->h_count[1] & 0xffffffffu);
+  if (flag) {
+    launch_fill_u32(st, (uint32_t*)(P<uint64_t>(ctx->counters) + 1), 1, 0u);
+    GSR_HIP(hipStreamSynchronize(st));
+    return fail(ctx, GSR_ERR_CAPACITY, "%llu keys exceeded the fixed key capacity",
+                (unsigned long long)ctx->h_count[0]);
+  }
+  return GSR_OK;
+}
+
+gsr_status gsr_debug_stats(gsr_context* ctx, gsr_stats* out, void* stream) {
+  if (!ctx || !out) return GSR_ERR_INVALID_ARGUMENT;
+  const Saved& sv = ctx->s;
+  if (!sv.valid) return fail(ctx, GSR_ERR_STATE, "no forward");
+  hipStream_t st = (hipStream_t)stream;
+  GSR_HIP(hipSetDevice(ctx->device));
+  GSR_HIP(hipMemcpyAsync(ctx->h_count, ctx->counters.p, 24, hipMemcpyDeviceToHost, st));
+  GSR_HIP(hipStreamSynchronize(st));
+  out->n_pairs = ctx->n_pairs == -2 ? (int64_t)ctx->h_count[2] : -1;
+  out->n_records = sv.n * sv.F;
+  out->n_keys = (int64_t)ctx->h_count[0];
+  out->n_tiles = sv.T;
+  out->n_pixels = sv.P;
+  out->key_capacity = (int64_t)ctx->key_cap;
+  out->epoch = ctx->epoch;
+  out->tile_w = sv.set.tile_w;
+  out->tile_h = sv.set.tile_h;
+  return GSR_OK;
+}
+
+gsr_status gsr_debug_timings(gsr_context* ctx, double* ms, int64_t* calls) {
+  if (!ctx || !ms || !calls) return GSR_ERR_INVALID_ARGUMENT;
+  for (int i = 0; i < GSR_N_STAGES; ++i) {
+    ms[i] = 0.0;
+    calls[i] = 0;
+  }
+  GSR_HIP(hipSetDevice(ctx->device));
+  gsr_status rc = GSR_OK;
+  for (auto& t : ctx->timed) {
+    float e = 0.0f;
+    if (rc == GSR_OK) {
+      hipError_t err = hipEventSynchronize(t.b);
+      if (err == hipSuccess) err = hipEventElapsedTime(&e, t.a, t.b);
+      if (err != hipSuccess) rc = hip_check(ctx, err, "hipEventElapsedTime");
+    }
+    if (t.stage >= 0 && t.stage < GSR_N_STAGES) {
+      ms[t.stage] += e;
+      calls[t.stage] += 1;
+    }
+    ctx->ev_pool.push_back(t.a);
+    ctx->ev_pool.push_back(t.b);
+  }
+  ctx->timed.clear();
+  return rc;
+}
+
+gsr_status gsr_debug_lists(gsr_context* ctx, uint32_t* ntiles, uint32_t* depth_key,
+                           uint32_t* square, uint32_t* tile_keys, uint32_t* tile_vals,
+                           uint32_t* ranges, int32_t* n_last, float* t_final, void* stream) {
+  if (!ctx) return GSR_ERR_INVALID_ARGUMENT;
+  const Saved& sv = ctx->s;
+  if (!sv.valid) return fail(ctx, GSR_ERR_STATE, "no forward");
+  hipStream_t st = (hipStream_t)stream;
+  GSR_HIP(hipSetDevice(ctx->device));
+  GSR_HIP(hipStreamSynchronize(st));
+  const size_t M = (size_t)sv.n * sv.F;
+  uint64_t K = 0;
+  GSR_HIP(hipMemcpy(&K, ctx->counters.p, 8, hipMemcpyDeviceToHost));
+  K = std::min<uint64_t>(K, ctx->key_cap);
+  if (ntiles && M) GSR_HIP(hipMemcpy(ntiles, ctx->ntiles.p, M * 4, hipMemcpyDeviceToHost));
+  if (depth_key && M) {
+    // the depth keys were sorted in place; rebuild the per-record view
+    std::vector<uint32_t> k(M), v(M);
+    const DBuf& kb = sv.recs_in_b ? ctx->dkey_b : ctx->dkey_a;
+    const DBuf& vb = sv.recs_in_b ? ctx->dval_b : ctx->dval_a;
+    GSR_HIP(hipMemcpy(k.data(), kb.p, M * 4, hipMemcpyDeviceToHost));
+    GSR_HIP(hipMemcpy(v.data(), vb.p, M * 4, hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < M; ++i) depth_key[v[i]] = k[i];
+  }
+  if (square && M) {
+    std::vector<Record> r(M);
+    GSR_HIP(hipMemcpy(r.data(), ctx->rec.p, M * sizeof(Record), hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < M; ++i) {
+      square[2 * i] = r[i].sqx;
+      square[2 * i + 1] = r[i].sqy;
+    }
+  }
+  const DBuf& kb = sv.sorted_in_b ? ctx->keys_b : ctx->keys_a;
+  const DBuf& vb = sv.sorted_in_b ? ctx->vals_b : ctx->vals_a;
+  if (tile_keys && K) GSR_HIP(hipMemcpy(tile_keys, kb.p, K * 4, hipMemcpyDeviceToHost));
+  if (tile_vals && K) GSR_HIP(hipMemcpy(tile_vals, vb.p, K * 4, hipMemcpyDeviceToHost));
+  if (ranges && sv.T) GSR_HIP(hipMemcpy(ranges, ctx->ranges.p, sv.T * 8, hipMemcpyDeviceToHost));
+  if (n_last && sv.P) GSR_HIP(hipMemcpy(n_last, ctx->n_last.p, sv.P * 4, hipMemcpyDeviceToHost));
+  if (t_final && sv.P) GSR_HIP(hipMemcpy(t_final, ctx->t_final.p, sv.P * 4, hipMemcpyDeviceToHost));
+  return GSR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,352 @@
+// sort.hip -- key generation and ordering of the (tile, Gaussian) lists.
+//
+// The compositing order of a pixel is its Gaussians by ascending (fp32 view
+// depth, index) (front-to-back compositing, DROID-Splat eqn:rendering; tile
+// lists of the 3DGS rasterizer it builds on).  Instead of one wide sort of
+// (tile | depth) keys, the path sorts twice:
+//   1. the N*F records by depth bits (stable LSD radix, 4 x 8-bit passes over
+//      N*F elements), which puts each frame's Gaussians front to back with
+//      ties broken by index;
+//   2. keygen walks the records in that order and writes one 32-bit tile id
+//      per covered tile; a stable LSD radix pass over only the tile-id bits
+//      (2 passes for up to 65k tiles) then groups the keys by tile while
+//      keeping the depth order inside each tile.
+// This moves about 40 bytes per key instead of 6-7 passes over 12-byte
+// (tile | depth, value) pairs.
+//
+// The radix passes use a hand-written LDS multi-split: each wave ranks its
+// 64 keys per round with 8 ballots (one per digit bit), keeps running digit
+// counts in LDS, and the block combines the 4 waves' counts into stable
+// block offsets; no global atomics.  Scans are reduce-then-scan in 3
+// launches.  All kernels read the element count from device memory so the
+// sequence is capturable.
+#include "gsr_device.h"
+
+namespace gsr {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;  // elements per block
+
+constexpr int kSortThreads = 256;
+constexpr int kSortWaves = kSortThreads / kWave;
+constexpr int kSortRounds = 16;  // 64-key rounds per wave
+constexpr int kSortTile = kSortThreads * kSortRounds;  // keys per block (4096)
+constexpr int kRadixBins = 256;
+
+// ---------------------------------------------------------------------------
+// Block-wide exclusive scan of one value per thread (256 threads).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T* sh, T& total) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int o = 1; o < kScanThreads; o <<= 1) {
+    T add = tid >= o ? sh[tid - o] : (T)0;
+    __syncthreads();
+    sh[tid] += add;
+    __syncthreads();
+  }
+  total = sh[kScanThreads - 1];
+  const T incl = sh[tid];
+  __syncthreads();
+  return incl - v;
+}
+
+// Loaders: element i of the scanned sequence.
+struct LoadCountsPerm {  // ntiles[perm[i]] for the depth-sorted records
+  const uint32_t* ntiles;
+  const uint32_t* perm;
+  __device__ uint64_t operator()(uint64_t i) const { return ntiles[perm[i]]; }
+};
+struct LoadU32 {
+  const uint32_t* a;
+  __device__ uint32_t operator()(uint64_t i) const { return a[i]; }
+};
+
+template <typename T, typename Load>
+__global__ void __launch_bounds__(kScanThreads) scan_reduce_kernel(Load ld, const uint64_t* n_dev,
+                                                                   uint64_t n_host,
+                                                                   T* __restrict__ block_sums) {
+  __shared__ T sh[kScanThreads];
+  const uint64_t n = n_dev ? min(*n_dev, n_host) : n_host;
+  const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+  T s = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    const uint64_t i = base + (uint64_t)k * kScanThreads + threadIdx.x;
+    if (i < n) s += (T)ld(i);
+  }
+  T total;
+  block_exclusive_scan<T>(s, sh, total);
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+// Single block: exclusive scan of the block sums in place; total -> *total.
+template <typename T>
+__global__ void __launch_bounds__(kScanThreads) scan_spine_kernel(T* __restrict__ sums, int nb,
+                                                                  T* __restrict__ total_out) {
+  __shared__ T sh[kScanThreads];
+  T carry = 0;
+  for (int base = 0; base < nb; base += kScanThreads) {
+    const int i = base + threadIdx.x;
+    const T v = i < nb ? sums[i] : (T)0;
+    T tot;
+    const T ex = block_exclusive_scan<T>(v, sh, tot);
+    if (i < nb) sums[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0 && total_out) *total_out = carry;
+}
+
+template <typename T, typename Load>
+__global__ void __launch_bounds__(kScanThreads) scan_down_kernel(Load ld, const uint64_t* n_dev,
+                                                                 uint64_t n_host,
+                                                                 const T* __restrict__ block_base,
+                                                                 T* __restrict__ out) {
+  __shared__ T sh[kScanThreads];
+  const uint64_t n = n_dev ? min(*n_dev, n_host) : n_host;
+  const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
+  T v[kScanItems];
+  T s = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    const uint64_t i = base + k;
+    v[k] = i < n ? (T)ld(i) : (T)0;
+    s += v[k];
+  }
+  T total;
+  T run = block_exclusive_scan<T>(s, sh, total) + block_base[blockIdx.x];
+  for (int k = 0; k < kScanItems; ++k) {
+    const uint64_t i = base + k;
+    if (i < n) out[i] = run;
+    run += v[k];
+  }
+}
+
+// Note: scan_reduce sums a strided set of kScanTile elements and scan_down a
+// thread-contiguous set; both cover exactly the block's kScanTile elements,
+// so the block totals agree.
+
+// ---------------------------------------------------------------------------
+// LSD radix pass, 8-bit digit at `shift`, stable.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(
+    const uint32_t* __restrict__ keys, const uint64_t* n_dev, uint64_t n_host, int shift,
+    uint32_t* __restrict__ hist /* [256][nblocks] */) {
+  __shared__ uint32_t cnt[kRadixBins];
+  const uint64_t n = n_dev ? min(*n_dev, n_host) : n_host;
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+  for (int k = 0; k < kSortRounds; ++k) {
+    const uint64_t i = base + (uint64_t)k * kSortThreads + threadIdx.x;
+    if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 0xffu], 1u);
+  }
+  __syncthreads();
+  hist[(uint64_t)threadIdx.x * gridDim.x + blockIdx.x] = cnt[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
+    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
+    const uint64_t* n_dev, uint64_t n_host, int shift,
+    const uint32_t* __restrict__ offsets /* scanned [256][nblocks] */,
+    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
+  __shared__ uint32_t wcnt[kSortWaves][kRadixBins];
+  const uint64_t n = n_dev ? min(*n_dev, n_host) : n_host;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  for (int i = threadIdx.x; i < kSortWaves * kRadixBins; i += kSortThreads)
+    (&wcnt[0][0])[i] = 0;
+  __syncthreads();
+  const uint64_t wbase = (uint64_t)blockIdx.x * kSortTile + (uint64_t)w * (kWave * kSortRounds);
+  const uint64_t lt = lanemask_lt();
+  uint32_t key[kSortRounds], val[kSortRounds], rank[kSortRounds];
+  for (int k = 0; k < kSortRounds; ++k) {
+    const uint64_t i = wbase + (uint64_t)k * kWave + lane;
+    const bool valid = i < n;
+    key[k] = valid ? keys_in[i] : 0u;
+    val[k] = valid ? vals_in[i] : 0u;
+    const uint32_t d = (key[k] >> shift) & 0xffu;
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bb = __ballot(bit);
+      m &= bit ? bb : ~bb;
+    }
+    // lanes with the same digit form the group m (valid lanes only)
+    const uint32_t before = wcnt[w][d];
+    rank[k] = before + (uint32_t)__popcll(m & lt);
+    const bool leader = valid && (m & lt) == 0;
+    if (leader) wcnt[w][d] = before + (uint32_t)__popcll(m);
+    // wave-local ordering of LDS ops keeps the read above before the write
+  }
+  __syncthreads();
+  // per digit: base of each wave = global block offset + earlier waves
+  {
+    const int d = threadIdx.x;
+    uint32_t run = offsets[(uint64_t)d * gridDim.x + blockIdx.x];
+    for (int ww = 0; ww < kSortWaves; ++ww) {
+      const uint32_t c = wcnt[ww][d];
+      wcnt[ww][d] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  for (int k = 0; k < kSortRounds; ++k) {
+    const uint64_t i = wbase + (uint64_t)k * kWave + lane;
+    if (i < n) {
+      const uint32_t d = (key[k] >> shift) & 0xffu;
+      const uint32_t dst = wcnt[w][d] + rank[k];
+      keys_out[dst] = key[k];
+      vals_out[dst] = val[k];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// keygen: one thread per depth-sorted record
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) keygen_kernel(
+    const uint64_t* __restrict__ m_dev, uint64_t m_host, const uint32_t* __restrict__ perm,
+    const uint32_t* __restrict__ ntiles, const uint64_t* __restrict__ offsets,
+    Record* __restrict__ rec, const FrameDesc* __restrict__ frames, int tile_w, int tile_h,
+    uint64_t capacity, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+    uint32_t* __restrict__ overflow) {
+  const uint64_t m = m_dev ? *m_dev : m_host;
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const uint32_t r = perm[i];
+  const uint32_t cnt = ntiles[r];
+  if (cnt == 0) return;
+  const uint64_t off = offsets[i];
+  Record& o = rec[r];
+  if (off + cnt > capacity) {
+    // Fixed capacity exceeded: flag it, mark the record unreachable and fill
+    // the slots that do exist with a sentinel tile id past every real tile.
+    atomicOr(overflow, 1u);
+    o.key_offset = 0xffffffffu;
+    for (uint64_t k = off; k < capacity; ++k) {
+      keys[k] = 0xffffffffu;
+      vals[k] = 0u;
+    }
+    return;
+  }
+  o.key_offset = (uint32_t)off;
+  const FrameDesc fr = frames[o.frame];
+  const int x_lo = o.sqx & 0xffff, x_hi = o.sqx >> 16;
+  const int y_lo = o.sqy & 0xffff, y_hi = o.sqy >> 16;
+  const int tx0 = x_lo / tile_w, tx1 = x_hi / tile_w;
+  const int ty0 = y_lo / tile_h, ty1 = y_hi / tile_h;
+  uint64_t k = off;
+  for (int ty = ty0; ty <= ty1; ++ty)
+    for (int tx = tx0; tx <= tx1; ++tx) {
+      keys[k] = (uint32_t)(fr.tile_offset + ty * fr.grid_x + tx);
+      vals[k] = r;
+      ++k;
+    }
+}
+
+// [start, end) of every tile's run in the sorted keys (ranges pre-zeroed).
+__global__ void __launch_bounds__(256) ranges_kernel(const uint32_t* __restrict__ keys,
+                                                     const uint64_t* k_dev, uint64_t capacity,
+                                                     uint2* __restrict__ ranges,
+                                                     uint32_t n_tiles) {
+  const uint64_t K = *k_dev < capacity ? *k_dev : capacity;
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= K) return;
+  const uint32_t t = keys[i];
+  if (t >= n_tiles) return;  // sentinel of an overflowed record
+  if (i == 0 || keys[i - 1] != t) ranges[t].x = (uint32_t)i;
+  if (i + 1 == K || keys[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
+}
+
+__global__ void fill_u32_kernel(uint32_t* __restrict__ p, uint64_t n, uint32_t v) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// host-side launch sequences
+// ---------------------------------------------------------------------------
+static inline unsigned blocks_for(uint64_t n, uint64_t per) {
+  return (unsigned)((n + per - 1) / per);
+}
+
+void launch_fill_u32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t v) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n, v);
+}
+
+size_t radix_hist_elems(uint64_t n_max) { return (size_t)kRadixBins * blocks_for(n_max, kSortTile); }
+size_t scan_block_elems(uint64_t n_max) { return blocks_for(n_max, kScanTile) + 1; }
+
+// Stable sort of (keys, vals) by the key bits [0, bits).  The element count
+// is *n_dev (<= n_max).  Result ends in (keys_a, vals_a) if the number of
+// passes is even, else in (keys_b, vals_b); returns true if in b.
+bool launch_radix_sort(hipStream_t st, uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b,
+                       uint32_t* vals_b, const uint64_t* n_dev, uint64_t n_max, int bits,
+                       uint32_t* hist, uint32_t* scan_tmp) {
+  if (n_max == 0) return false;
+  const unsigned nb = blocks_for(n_max, kSortTile);
+  const uint64_t hn = (uint64_t)kRadixBins * nb;
+  const unsigned sb = blocks_for(hn, kScanTile);
+  bool in_b = false;
+  for (int shift = 0; shift < bits; shift += 8) {
+    uint32_t* ki = in_b ? keys_b : keys_a;
+    uint32_t* vi = in_b ? vals_b : vals_a;
+    uint32_t* ko = in_b ? keys_a : keys_b;
+    uint32_t* vo = in_b ? vals_a : vals_b;
+    hipLaunchKernelGGL(radix_hist_kernel, dim3(nb), dim3(kSortThreads), 0, st, ki, n_dev, n_max,
+                       shift, hist);
+    LoadU32 ld{hist};
+    hipLaunchKernelGGL((scan_reduce_kernel<uint32_t, LoadU32>), dim3(sb), dim3(kScanThreads), 0,
+                       st, ld, (const uint64_t*)nullptr, hn, scan_tmp);
+    hipLaunchKernelGGL((scan_spine_kernel<uint32_t>), dim3(1), dim3(kScanThreads), 0, st,
+                       scan_tmp, (int)sb, (uint32_t*)nullptr);
+    hipLaunchKernelGGL((scan_down_kernel<uint32_t, LoadU32>), dim3(sb), dim3(kScanThreads), 0,
+                       st, ld, (const uint64_t*)nullptr, hn, scan_tmp, hist);
+    hipLaunchKernelGGL(radix_scatter_kernel, dim3(nb), dim3(kSortThreads), 0, st, ki, vi, n_dev,
+                       n_max, shift, hist, ko, vo);
+    in_b = !in_b;
+  }
+  return in_b;
+}
+
+// Exclusive scan of ntiles[perm[i]] over the m records into offsets (u64),
+// total into *total.
+void launch_offsets_scan(hipStream_t st, const uint32_t* ntiles, const uint32_t* perm,
+                         uint64_t m, uint64_t* offsets, uint64_t* block_tmp, uint64_t* total) {
+  if (m == 0) {
+    launch_fill_u32(st, (uint32_t*)total, 2, 0u);
+    return;
+  }
+  const unsigned sb = blocks_for(m, kScanTile);
+  LoadCountsPerm ld{ntiles, perm};
+  hipLaunchKernelGGL((scan_reduce_kernel<uint64_t, LoadCountsPerm>), dim3(sb),
+                     dim3(kScanThreads), 0, st, ld, (const uint64_t*)nullptr, m, block_tmp);
+  hipLaunchKernelGGL((scan_spine_kernel<uint64_t>), dim3(1), dim3(kScanThreads), 0, st,
+                     block_tmp, (int)sb, total);
+  hipLaunchKernelGGL((scan_down_kernel<uint64_t, LoadCountsPerm>), dim3(sb), dim3(kScanThreads),
+                     0, st, ld, (const uint64_t*)nullptr, m, block_tmp, offsets);
+}
+
+void launch_keygen(hipStream_t st, uint64_t m, const uint32_t* perm, const uint32_t* ntiles,
+                   const uint64_t* offsets, Record* rec, const FrameDesc* frames, int tile_w,
+                   int tile_h, uint64_t capacity, uint32_t* keys, uint32_t* vals,
+                   uint32_t* overflow) {
+  if (m == 0) return;
+  hipLaunchKernelGGL(keygen_kernel, dim3(blocks_for(m, 256)), dim3(256), 0, st,
+                     (const uint64_t*)nullptr, m, perm, ntiles, offsets, rec, frames, tile_w,
+                     tile_h, capacity, keys, vals, overflow);
+}
+
+void launch_ranges(hipStream_t st, const uint32_t* keys, const uint64_t* k_dev, uint64_t k_max,
+                   uint64_t capacity, uint2* ranges, uint64_t n_tiles) {
+  launch_fill_u32(st, (uint32_t*)ranges, 2 * n_tiles, 0u);
+  if (k_max == 0) return;
+  hipLaunchKernelGGL(ranges_kernel, dim3(blocks_for(k_max, 256)), dim3(256), 0, st, keys, k_dev,
+                     capacity, ranges, (uint32_t)n_tiles);
+}
+
+}  // namespace gsr

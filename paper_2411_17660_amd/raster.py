@@ -1,0 +1,200 @@
+"""PyTorch-facing API of the HIP tile rasterizer.
+
+`Rasterizer` owns one library context (workspace, saved forward state) and
+renders a batch of keyframes into packed device tensors.  `rasterize` is the
+differentiable entry point behind a torch.autograd.Function: its backward
+calls the library's hand-written backward.  The pose gradient is the
+left-perturbation twist xi = (rho, phi) at xi = 0 (DROID-Splat Sec. 3.3, pose
+refinement through the rendering objective); a caller that optimises poses
+keeps a zero twist tensor per frame and folds each step into the pose.
+PyTorch provides device memory and the stream only.
+"""
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import native
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous(), \
+        "tensors must be contiguous float32 on the GPU"
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Rasterizer:
+    """One library context on one device."""
+
+    def __init__(self, device=0):
+        self.lib = native.load()
+        self.device = device
+        h = C.c_void_p()
+        rc = self.lib.gsr_create(C.byref(h), int(device))
+        if rc != native.GSR_OK:
+            raise native.GsrError(rc, f"gsr_create(device={device}) failed")
+        self.h = h
+        self.n = 0
+        self.F = 0
+        self.sizes = []
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            self.lib.gsr_destroy(h)
+            self.h = None
+
+    def _check(self, rc):
+        if rc != native.GSR_OK:
+            raise native.GsrError(rc, self.lib.gsr_last_error(self.h).decode())
+
+    def forward(self, means, log_scales, quats, opacity, sh, poses, cams, sh_degree,
+                background=(0.0, 0.0, 0.0), tile=(16, 16), key_capacity=0, xcd_remap=True,
+                out=None, timing=False, count_pairs=False):
+        """Renders F frames; returns packed (rgb [sum 3HW], depth [sum HW],
+        alpha [sum HW]) float32 device tensors."""
+        F = len(cams)
+        P = int(sum(int(c[0]) * int(c[1]) for c in cams))
+        dev = means.device
+        if out is None:
+            rgb = torch.empty(3 * P, device=dev, dtype=torch.float32)
+            depth = torch.empty(P, device=dev, dtype=torch.float32)
+            alpha = torch.empty(P, device=dev, dtype=torch.float32)
+        else:
+            rgb, depth, alpha = out
+        self.settings = native.make_settings(sh_degree, background, tile, key_capacity,
+                                             xcd_remap, timing=timing, count_pairs=count_pairs)
+        self.cams = native.make_cameras(cams)
+        n = int(means.shape[0])
+        self._check(self.lib.gsr_forward(self.h, C.byref(self.settings), n, _ptr(means),
+                                         _ptr(log_scales), _ptr(quats), _ptr(opacity), _ptr(sh),
+                                         F, self.cams, _ptr(poses), _ptr(rgb), _ptr(depth),
+                                         _ptr(alpha), _stream()))
+        self.n, self.F, self.sh_degree = n, F, sh_degree
+        self.sizes = [(int(c[0]), int(c[1])) for c in cams]
+        return rgb, depth, alpha
+
+    def backward(self, g_rgb, g_depth, g_alpha, out=None):
+        n, F = self.n, self.F
+        dev = g_rgb.device
+        K = (self.sh_degree + 1) ** 2
+        if out is None:
+            out = dict(means=torch.empty(n, 3, device=dev), log_scales=torch.empty(n, 3, device=dev),
+                       quats=torch.empty(n, 4, device=dev), opacity=torch.empty(n, device=dev),
+                       sh=torch.empty(n, K, 3, device=dev), twist=torch.empty(F, 6, device=dev))
+        self._check(self.lib.gsr_backward(self.h, _ptr(g_rgb), _ptr(g_depth), _ptr(g_alpha),
+                                          _ptr(out["means"]), _ptr(out["log_scales"]),
+                                          _ptr(out["quats"]), _ptr(out["opacity"]),
+                                          _ptr(out["sh"]), _ptr(out["twist"]), _stream()))
+        return out
+
+    def loss_l1(self, target_rgb, target_depth, depth_weight, out=None):
+        dev = target_rgb.device
+        if out is None:
+            P = target_depth.numel()
+            out = dict(loss=torch.empty(1, device=dev), g_rgb=torch.empty(3 * P, device=dev),
+                       g_depth=torch.empty(P, device=dev), g_alpha=torch.empty(P, device=dev))
+        self._check(self.lib.gsr_loss_l1(self.h, _ptr(target_rgb), _ptr(target_depth),
+                                         float(depth_weight), _ptr(out["loss"]),
+                                         _ptr(out["g_rgb"]), _ptr(out["g_depth"]),
+                                         _ptr(out["g_alpha"]), _stream()))
+        return out
+
+    def step_l1(self, means, log_scales, quats, opacity, sh, poses, cams, sh_degree,
+                target_rgb, target_depth, depth_weight, bufs, background=(0.0, 0.0, 0.0),
+                tile=(16, 16), key_capacity=0, xcd_remap=True, timing=False):
+        """Forward + L1 loss + backward in one call into preallocated `bufs`
+        (dict with rgb, depth, alpha, loss and the gradient tensors)."""
+        self.settings = native.make_settings(sh_degree, background, tile, key_capacity,
+                                             xcd_remap, timing=timing)
+        self.cams = native.make_cameras(cams)
+        n = int(means.shape[0])
+        b = bufs
+        self._check(self.lib.gsr_step_l1(
+            self.h, C.byref(self.settings), n, _ptr(means), _ptr(log_scales), _ptr(quats),
+            _ptr(opacity), _ptr(sh), len(cams), self.cams, _ptr(poses), _ptr(target_rgb),
+            _ptr(target_depth), float(depth_weight), _ptr(b["rgb"]), _ptr(b["depth"]),
+            _ptr(b["alpha"]), _ptr(b["loss"]), _ptr(b["means"]), _ptr(b["log_scales"]),
+            _ptr(b["quats"]), _ptr(b["opacity"]), _ptr(b["sh"]), _ptr(b["twist"]), _stream()))
+        self.n, self.F, self.sh_degree = n, len(cams), sh_degree
+        self.sizes = [(int(c[0]), int(c[1])) for c in cams]
+
+    def timings(self):
+        """{stage: (total ms, launches)} of the timed calls since the last read."""
+        ms = (C.c_double * len(native.STAGES))()
+        calls = (C.c_int64 * len(native.STAGES))()
+        self._check(self.lib.gsr_debug_timings(self.h, ms, calls))
+        return {name: (ms[i], calls[i]) for i, name in enumerate(native.STAGES)}
+
+    def check_overflow(self):
+        self._check(self.lib.gsr_check_overflow(self.h, _stream()))
+
+    def stats(self):
+        s = native.Stats()
+        self._check(self.lib.gsr_debug_stats(self.h, C.byref(s), _stream()))
+        return {k: getattr(s, k) for k, _ in native.Stats._fields_}
+
+    def debug_lists(self):
+        """Integer artefacts of the last forward as numpy arrays."""
+        st = self.stats()
+        M, K, T, P = st["n_records"], st["n_keys"], st["n_tiles"], st["n_pixels"]
+        K = min(K, st["key_capacity"])
+        out = dict(ntiles=np.zeros(M, np.uint32), depth_key=np.zeros(M, np.uint32),
+                   square=np.zeros(2 * M, np.uint32), tile_keys=np.zeros(max(K, 1), np.uint32),
+                   tile_vals=np.zeros(max(K, 1), np.uint32), ranges=np.zeros(2 * T, np.uint32),
+                   n_last=np.zeros(P, np.int32), t_final=np.zeros(P, np.float32))
+
+        def p(a):
+            return C.c_void_p(a.ctypes.data)
+        self._check(self.lib.gsr_debug_lists(self.h, p(out["ntiles"]), p(out["depth_key"]),
+                                             p(out["square"]), p(out["tile_keys"]),
+                                             p(out["tile_vals"]), p(out["ranges"]),
+                                             p(out["n_last"]), p(out["t_final"]), _stream()))
+        out["tile_keys"] = out["tile_keys"][:K]
+        out["tile_vals"] = out["tile_vals"][:K]
+        out["K"] = K
+        return out
+
+
+class _RasterizeFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, means, log_scales, quats, opacity, sh, twist, poses, cams, sh_degree,
+                background, tile, rast):
+        inputs = [t.contiguous() for t in (means, log_scales, quats, opacity, sh, poses)]
+        rgb, depth, alpha = rast.forward(*inputs, cams, sh_degree, background, tile)
+        # the library's backward reads the inputs again: hold them until then
+        ctx.inputs = inputs
+        ctx.rast = rast
+        return rgb, depth, alpha
+
+    @staticmethod
+    def backward(ctx, g_rgb, g_depth, g_alpha):
+        rast = ctx.rast
+        dev = next(t.device for t in (g_rgb, g_depth, g_alpha) if t is not None)
+        P = sum(w * h for w, h in rast.sizes)
+
+        def z(t, size):
+            return t.contiguous() if t is not None else torch.zeros(size, device=dev)
+        g = rast.backward(z(g_rgb, 3 * P), z(g_depth, P), z(g_alpha, P))
+        ctx.inputs = None
+        return (g["means"], g["log_scales"], g["quats"], g["opacity"], g["sh"], g["twist"],
+                None, None, None, None, None, None)
+
+
+def rasterize(means, log_scales, quats, opacity, sh, poses, cams, sh_degree, twist=None,
+              background=(0.0, 0.0, 0.0), tile=(16, 16), rasterizer=None):
+    """Differentiable render of F keyframes.  Returns packed (rgb, depth,
+    alpha).  Gradients reach every Gaussian tensor and `twist` ([F,6] zeros,
+    the left-perturbation of each pose at zero).  The backward of one forward
+    must run before the next forward on the same `rasterizer`."""
+    rast = rasterizer or Rasterizer(means.device.index or 0)
+    if twist is None:
+        twist = torch.zeros(len(cams), 6, device=means.device, requires_grad=False)
+    return _RasterizeFn.apply(means, log_scales, quats, opacity, sh, twist, poses, cams,
+                              sh_degree, tuple(background), tuple(tile), rast)

@@ -1,0 +1,79 @@
+"""Helpers shared by the GPU tests: move a scene to the device, run the HIP
+path through the C-ABI binding, and compare with the oracle."""
+import os
+
+import numpy as np
+
+IMG_TOL = 1e-4     # absolute, per channel, FP32 images vs the FP64 oracle
+GRAD_REL = 1e-3    # relative, with a floor of 1e-2 * rms per tensor
+
+
+def oracle_threads():
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def to_dev(scene):
+    import torch
+    d = {}
+    for k in ("means", "log_scales", "quats", "opacity", "sh", "poses"):
+        d[k] = torch.from_numpy(np.ascontiguousarray(getattr(scene, k), np.float32)).cuda()
+    return d
+
+
+def gpu_forward(rast, scene, tile=(16, 16), **kw):
+    import torch
+    d = to_dev(scene)
+    rgb, dep, alp = rast.forward(d["means"], d["log_scales"], d["quats"], d["opacity"], d["sh"],
+                                 d["poses"], scene.cams, scene.sh_degree, scene.background,
+                                 tile=tile, **kw)
+    torch.cuda.synchronize()
+    # the library reads the inputs again in the backward: keep them alive
+    rast._inputs = d
+    return d, rgb, dep, alp
+
+
+def gpu_backward(rast, G):
+    import torch
+    g = [torch.from_numpy(np.ascontiguousarray(x, np.float32)).cuda() for x in G]
+    out = rast.backward(*g)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}
+
+
+def masked_upstream(G, flags, sizes):
+    """Zero the upstream gradients on the pixels the oracle flags as
+    threshold-sensitive; both sides then agree on every decision of every
+    pixel that carries gradient."""
+    keep = (flags == 0).astype(np.float32)
+    g_rgb = np.asarray(G[0], np.float32).copy()
+    off = 0
+    for (w, h) in sizes:
+        P = w * h
+        for c in range(3):
+            g_rgb[3 * off + c * P:3 * off + (c + 1) * P] *= keep[off:off + P]
+        off += P
+    return g_rgb, (np.asarray(G[1], np.float32) * keep), (np.asarray(G[2], np.float32) * keep)
+
+
+def expand_rgb_mask(px_mask, sizes):
+    """Per-pixel mask -> mask over the packed [3,H,W]-per-frame rgb layout."""
+    out, off = [], 0
+    for (w, h) in sizes:
+        P = w * h
+        out.append(np.tile(px_mask[off:off + P], 3))
+        off += P
+    return np.concatenate(out)
+
+
+def assert_grad_close(name, got, ref, rel=GRAD_REL):
+    got = np.asarray(got, np.float64).ravel()
+    ref = np.asarray(ref, np.float64).ravel()
+    rms = np.sqrt(np.mean(ref ** 2)) if ref.size else 0.0
+    bound = rel * np.maximum(np.abs(ref), 1e-2 * rms)
+    err = np.abs(got - ref)
+    bad = err > bound + 1e-30
+    if bad.any():
+        i = int(np.argmax(err / (bound + 1e-30)))
+        raise AssertionError(f"{name}: {int(bad.sum())} of {ref.size} elements exceed the "
+                             f"bound; worst idx {i}: got {got[i]!r} ref {ref[i]!r} "
+                             f"bound {bound[i]!r}")

@@ -45,6 +45,7 @@ def main():
     ap.add_argument("--tile", default="16x16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-frame", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--n", type=int, default=500_000)
     args = ap.parse_args()
@@ -117,6 +118,34 @@ def main():
     loss = bb["loss"].item()
     log(f"[bench] batched {t_batched * 1e3:.2f} ms/step, loss {loss:.5f}")
 
+    # the same step captured as one HIP graph (no host work per step)
+    t_graph = None
+    try:
+        if args.no_graph:
+            raise RuntimeError("graph replay disabled by --no-graph")
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step(rast, sc.cams, dev["poses"], t_rgb, t_dep, bb, cap)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step(rast, sc.cams, dev["poses"], t_rgb, t_dep, bb, cap)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            graph.replay()
+        torch.cuda.synchronize()
+        t_graph = (time.perf_counter() - t0) / args.steps
+        rast.check_overflow()
+        log(f"[bench] graph-replayed batched {t_graph * 1e3:.2f} ms/step")
+        del graph
+    except Exception as e:  # reported, never silently substituted
+        log(f"[bench] graph capture failed: {e!r}")
+
     # evaluated (pixel, entry) pairs of one forward (separate counting pass)
     rast.forward(dev["means"], dev["log_scales"], dev["quats"], dev["opacity"], dev["sh"],
                  dev["poses"], sc.cams, 3, tile=tile, key_capacity=cap, count_pairs=True)
@@ -152,7 +181,8 @@ def main():
         log(f"[bench] per-frame {t_per_frame * 1e3:.2f} ms/step")
 
     mpix = P / 1e6
-    value = mpix / t_batched
+    t_best = min(t_batched, t_graph) if t_graph else t_batched
+    value = mpix / t_best
     per_stage = {k: round(v[0] / max(args.steps, 1), 4) for k, v in stages.items() if v[1]}
     # roofline of the dominant compositing kernel
     dom = max(("composite_fwd", "composite_bwd"), key=lambda k: stages[k][0])
@@ -171,16 +201,18 @@ def main():
     out = {
         "metric": "fwd+bwd Mpixels/s at 500k Gaussians; batched vs per-frame speedup",
         "value": round(value, 3), "unit": "Mpixels/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(t_batched * 1e3, 4),
+        "warmup": args.warmup, "ms_per_step": round(t_best * 1e3, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded piecewise-planar scenes shaped like the paper's maps)",
         "config": {"workload": "c3: 500k Gaussians SH3, 8 keyframes 1200x680 f=600, "
                                "fwd + L1 rgb + L1 depth + bwd incl. pose twists",
                    "n_gaussians": sc.n, "frames": F, "resolution": [W, H],
                    "tile": list(tile), "keys_per_step": int(K)},
+        "eager_ms_per_step": round(t_batched * 1e3, 4),
+        "graph_ms_per_step": None if t_graph is None else round(t_graph * 1e3, 4),
         "per_frame_ms_per_step": None if t_per_frame is None else round(t_per_frame * 1e3, 4),
         "batched_vs_per_frame_speedup": None if t_per_frame is None else
-        round(t_per_frame / t_batched, 4),
+        round(t_per_frame / t_best, 4),
         "stage_ms_per_step": per_stage,
         "loss": loss,
         "roofline": roofline,

@@ -47,7 +47,8 @@ struct alignas(16) Record {
 };
 static_assert(sizeof(Record) == 64, "record layout");
 
-// Gradient of one (tile, entry) key: du, dv, dA, dB, dC, dopacity, dc0..2, dz
+// Gradient of one (tile, entry) key: du, dv, dSigma'_xx, dSigma'_xy, dSigma'_yy
+// (symmetric-matrix gradient), dopacity, dc0..2, dz
 constexpr int kNG = 10;
 
 __device__ __forceinline__ int frame_of_tile(const FrameDesc* fr, int n_frames, int tile) {

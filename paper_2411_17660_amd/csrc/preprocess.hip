@@ -288,8 +288,54 @@ __global__ void __launch_bounds__(256) preprocess_fwd_kernel(
 }
 
 // --------------------------------------------------------------------------
-// A9 + A10: per-record reduction of the key partials and chain rule to the
-// parameters; per (Gaussian, frame) twist partials reduced per wave in FP64.
+// A9: per-record reduction of the key partials.  A group of 16 lanes owns one
+// record and strides over its contiguous key slots (coalesced stamp and
+// partial reads); slots not stamped with this backward's epoch belong to
+// keys behind every pixel's stop and are skipped.  Lane sums are FP64 and the
+// group combines them with a fixed butterfly, so the result is deterministic.
+// --------------------------------------------------------------------------
+constexpr int kSlotGroup = 16;
+
+__global__ void __launch_bounds__(256) slot_reduce_kernel(
+    uint64_t m, const Record* __restrict__ rec, const uint32_t* __restrict__ ntiles,
+    const float* __restrict__ partial, const uint32_t* __restrict__ stamp,
+    const uint32_t* __restrict__ epoch_dev, uint64_t key_capacity,
+    float* __restrict__ grad2d /* [m][kNG] */) {
+  const uint32_t epoch = *epoch_dev;
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t r = gid / kSlotGroup;
+  const int sub = threadIdx.x & (kSlotGroup - 1);
+  const bool active = r < m;
+  uint32_t cnt = active ? ntiles[r] : 0u;
+  const uint32_t off = cnt ? rec[r].key_offset : 0u;
+  if (cnt && (uint64_t)off + cnt > key_capacity) cnt = 0;  // overflowed in keygen
+  double acc[kNG];
+#pragma unroll
+  for (int j = 0; j < kNG; ++j) acc[j] = 0.0;
+  for (uint32_t s = sub; s < cnt; s += kSlotGroup) {
+    if (stamp[off + s] != epoch) continue;
+    const float* pp = partial + (size_t)(off + s) * kNG;
+#pragma unroll
+    for (int j = 0; j < kNG; ++j) acc[j] += (double)pp[j];
+  }
+#pragma unroll
+  for (int o = kSlotGroup / 2; o > 0; o >>= 1)
+#pragma unroll
+    for (int j = 0; j < kNG; ++j) acc[j] += __shfl_xor(acc[j], o, kSlotGroup);
+  if (!active) return;
+  if (cnt == 0) {
+    if (sub < kNG) grad2d[r * kNG + sub] = 0.0f;
+    return;
+  }
+  double v = acc[0];
+#pragma unroll
+  for (int j = 1; j < kNG; ++j) v = sub == j ? acc[j] : v;
+  if (sub < kNG) grad2d[r * kNG + sub] = (float)v;
+}
+
+// --------------------------------------------------------------------------
+// A10: chain rule to the parameters; per (Gaussian, frame) twist partials
+// reduced per wave in FP64.
 // --------------------------------------------------------------------------
 __device__ __forceinline__ double wave_sum_f64(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -302,9 +348,8 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(
     const float* __restrict__ poses, const float* __restrict__ means,
     const float* __restrict__ log_scales, const float* __restrict__ quats,
     const float* __restrict__ opac, const float* __restrict__ sh,
-    const Record* __restrict__ rec, const uint32_t* __restrict__ ntiles,
-    const float* __restrict__ partial, const uint32_t* __restrict__ stamp, uint32_t epoch,
-    uint64_t key_capacity, float* __restrict__ g_means, float* __restrict__ g_log_scales,
+    const uint32_t* __restrict__ ntiles, const float* __restrict__ grad2d,
+    float* __restrict__ g_means, float* __restrict__ g_log_scales,
     float* __restrict__ g_quats, float* __restrict__ g_opac, float* __restrict__ g_sh,
     double* __restrict__ twist_partial /* [F][n_waves][6] */) {
   const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -325,18 +370,10 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(
   for (int f = 0; f < n_frames; ++f) {
     double tw[6] = {0, 0, 0, 0, 0, 0};
     const int64_t r = (int64_t)f * n + g;
-    uint32_t cnt = active ? ntiles[r] : 0u;
-    const uint32_t off = cnt ? rec[r].key_offset : 0u;
-    if (cnt && (uint64_t)off + cnt > key_capacity) cnt = 0;  // overflowed in keygen
+    const uint32_t cnt = active ? ntiles[r] : 0u;
     if (cnt > 0) {
-      // A9: fixed-order sum over the record's key slots written this step
       double gr[kNG];
-      for (int j = 0; j < kNG; ++j) gr[j] = 0.0;
-      for (uint32_t s = 0; s < cnt; ++s) {
-        if (stamp[off + s] != epoch) continue;
-        const float* pp = partial + (size_t)(off + s) * kNG;
-        for (int j = 0; j < kNG; ++j) gr[j] += (double)pp[j];
-      }
+      for (int j = 0; j < kNG; ++j) gr[j] = (double)grad2d[r * kNG + j];
       const FrameDesc fr = frames[f];
       double W[9], tf[3];
       load_pose(poses, f, W, tf);
@@ -350,14 +387,8 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(
       dt[1] = gr[1] * fy / tz;
       dt[2] = -gr[0] * fx * tx / tz2 - gr[1] * fy * ty / tz2 + gr[9];
       dsig += gr[5];
-      // conic -> Sigma': dL/dSigma' = -Q G_Q Q, G_Q = [[dA, dB/2], [dB/2, dC]]
-      const double A = p.cov[2] / p.det, B = -p.cov[1] / p.det, C = p.cov[0] / p.det;
-      const double gA = gr[2], gB = 0.5 * gr[3], gC = gr[4];
-      const double m00 = A * gA + B * gB, m01 = A * gB + B * gC;
-      const double m10 = B * gA + C * gB, m11 = B * gB + C * gC;
-      const double S00 = -(m00 * A + m01 * B), S01 = -(m00 * B + m01 * C);
-      const double S11 = -(m10 * B + m11 * C);
-      const double GS[4] = {S00, S01, S01, S11};
+      // the key partials carry dL/dSigma' (symmetric: xx, xy, yy) directly
+      const double GS[4] = {gr[2], gr[3], gr[3], gr[4]};
       // Sigma' = J Sc J^T + lowpass: G_J = 2 GS J Sc, G_Sc = J^T GS J
       double JSc[6];
       for (int i = 0; i < 2; ++i)
@@ -501,6 +532,18 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(
   for (int i = 0; i < nb * 3; ++i) gs[i] = dsh[i];
 }
 
+// Advances the backward epoch held in device memory (so a captured sequence
+// gets a fresh epoch on every replay); 0 is skipped because fresh stamp
+// memory is zero.
+__global__ void bump_epoch_kernel(uint32_t* epoch) {
+  const uint32_t e = *epoch + 1u;
+  *epoch = e == 0u ? 1u : e;
+}
+
+void launch_bump_epoch(hipStream_t st, uint32_t* epoch) {
+  hipLaunchKernelGGL(bump_epoch_kernel, dim3(1), dim3(1), 0, st, epoch);
+}
+
 // A11: per-frame sum of the per-wave twist partials (FP64, fixed order).
 __global__ void __launch_bounds__(256) twist_reduce_kernel(const double* __restrict__ part,
                                                            int64_t n_waves,
@@ -548,15 +591,19 @@ void launch_preprocess_bwd(hipStream_t st, int64_t n, int F, const FrameDesc* fr
                            const float* poses, const float* means, const float* log_scales,
                            const float* quats, const float* opac, const float* sh, int deg,
                            const Record* rec, const uint32_t* ntiles, const float* partial,
-                           const uint32_t* stamp, uint32_t epoch, uint64_t key_capacity,
-                           float* g_means, float* g_log_scales, float* g_quats, float* g_opac,
-                           float* g_sh, double* twist_partial, float* g_twist) {
+                           const uint32_t* stamp, const uint32_t* epoch, uint64_t key_capacity,
+                           float* grad2d, float* g_means, float* g_log_scales, float* g_quats,
+                           float* g_opac, float* g_sh, double* twist_partial, float* g_twist) {
   const dim3 grid((unsigned)((n + 255) / 256));
 #define GSR_PRE_BWD(D)                                                                       \
   hipLaunchKernelGGL(preprocess_bwd_kernel<D>, grid, dim3(256), 0, st, n, F, frames, poses,  \
-                     means, log_scales, quats, opac, sh, rec, ntiles, partial, stamp, epoch, \
-                     key_capacity, g_means, g_log_scales, g_quats, g_opac, g_sh, twist_partial)
+                     means, log_scales, quats, opac, sh, ntiles, grad2d, g_means,            \
+                     g_log_scales, g_quats, g_opac, g_sh, twist_partial)
   if (n > 0) {
+    const uint64_t m = (uint64_t)n * F;
+    const uint64_t threads = m * kSlotGroup;
+    hipLaunchKernelGGL(slot_reduce_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0,
+                       st, m, rec, ntiles, partial, stamp, epoch, key_capacity, grad2d);
     switch (deg) {
       case 0: GSR_PRE_BWD(0); break;
       case 1: GSR_PRE_BWD(1); break;

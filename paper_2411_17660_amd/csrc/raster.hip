@@ -15,10 +15,20 @@
 // read back as broadcasts; per-entry values stay wave-uniform.
 //
 // Backward: the wave walks the tile's processed prefix from the back.  Each
-// lane recomputes alpha bit-identically (same helpers, explicit fma), rebuilds
-// T_i = T_{i+1} / (1 - a_i), accumulates the 10 per-entry gradients over its
-// pixels, and the wave sums them with a butterfly; the result for this
-// (tile, entry) key goes to its own slot (no atomics), stamped with the
+// lane recomputes alpha bit-identically (same helpers, explicit fma),
+// rebuilds T_i = T_{i+1} / (1 - a_i) (reciprocal plus one Newton step) and
+// carries the normalised colour seen behind each entry,
+// B_{i-1} = a_i c_i + (1 - a_i) B_i from B = background (likewise depth from 0
+// and the transmittance behind from 1), so that dC/da_i = T_i (c_i - B_i):
+// T_i only scales the result and the convex recurrence damps rounding
+// instead of accumulating it.  The screen-space gradient of an
+// entry is taken with respect to (u, v, Sigma'): with Q = Sigma'^-1 = L L^T
+// (L the factor the forward already uses) and d the offset, dq/dd = 2 Q d and
+// dq/dSigma' = -(Q d)(Q d)^T, Q d = L (L^T d); this avoids the ill-conditioned
+// -Q dQ Q step from conic gradients for elongated Gaussians.  The 10 per-entry
+// values are summed over the lane's pixels and then across the wave by a
+// transpose-reduce (13 shuffles instead of 60, fixed order); the result for
+// this (tile, entry) key goes to its own slot (no atomics), stamped with the
 // backward's epoch so the per-record reduction can skip slots of keys that
 // no pixel reached.
 #include "gsr_device.h"
@@ -132,6 +142,60 @@ __global__ void __launch_bounds__(64) composite_fwd_kernel(
   }
 }
 
+// Sums v[0..9] over the 64 lanes of the wave.  Each butterfly round halves
+// the set of values a lane carries (10 -> 5 -> 3|2 -> 2|1 -> 1) before the
+// plain rounds over lane bits 1 and 0.  On return lane l holds the total of
+// value index
+//   idx(l) = 5 b5 + (b4 ? 3 + b3 : (b3 ? 2 : b2)),   b_k = bit k of l,
+// and `writer` is set on exactly one lane per index.
+__device__ __forceinline__ float wave_transpose_sum10(const float v[10], int lane, int& idx,
+                                                     bool& writer) {
+  const bool b5 = (lane >> 5) & 1, b4 = (lane >> 4) & 1, b3 = (lane >> 3) & 1,
+             b2 = (lane >> 2) & 1;
+  float r1[5];
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    const float send = b5 ? v[j] : v[5 + j];
+    const float keep = b5 ? v[5 + j] : v[j];
+    r1[j] = keep + __shfl_xor(send, 32, 64);
+  }
+  // b4 = 0 keeps r1[0..2], b4 = 1 keeps r1[3..4]
+  float r2[3];
+  {
+    const float s0 = b4 ? r1[0] : r1[3], k0 = b4 ? r1[3] : r1[0];
+    const float s1 = b4 ? r1[1] : r1[4], k1 = b4 ? r1[4] : r1[1];
+    const float s2 = b4 ? r1[2] : 0.0f, k2 = b4 ? 0.0f : r1[2];
+    r2[0] = k0 + __shfl_xor(s0, 16, 64);
+    r2[1] = k1 + __shfl_xor(s1, 16, 64);
+    r2[2] = k2 + __shfl_xor(s2, 16, 64);
+  }
+  // b4 = 0: b3 = 0 keeps {r2[0], r2[1]}, b3 = 1 keeps {r2[2]}
+  // b4 = 1: b3 = 0 keeps {r2[0]},        b3 = 1 keeps {r2[1]}
+  float r3[2];
+  {
+    float s0, k0, s1, k1;
+    if (!b4) {
+      s0 = b3 ? r2[0] : r2[2]; k0 = b3 ? r2[2] : r2[0];
+      s1 = b3 ? r2[1] : 0.0f;  k1 = b3 ? 0.0f : r2[1];
+    } else {
+      s0 = b3 ? r2[0] : r2[1]; k0 = b3 ? r2[1] : r2[0];
+      s1 = 0.0f; k1 = 0.0f;
+    }
+    r3[0] = k0 + __shfl_xor(s0, 8, 64);
+    r3[1] = k1 + __shfl_xor(s1, 8, 64);
+  }
+  // lanes still carrying two values (b4 = 0, b3 = 0) split on b2
+  const bool two = !b4 && !b3;
+  const float s4 = two ? (b2 ? r3[0] : r3[1]) : r3[0];
+  const float k4 = two ? (b2 ? r3[1] : r3[0]) : r3[0];
+  float r = k4 + __shfl_xor(s4, 4, 64);
+  r += __shfl_xor(r, 2, 64);
+  r += __shfl_xor(r, 1, 64);
+  idx = 5 * (int)b5 + (b4 ? 3 + (int)b3 : (b3 ? 2 : (int)b2));
+  writer = (lane & 3) == 0 && (two || !b2);
+  return r;
+}
+
 template <int TW, int TH>
 __global__ void __launch_bounds__(64) composite_bwd_kernel(
     int n_tiles, int n_frames, const FrameDesc* __restrict__ frames,
@@ -140,11 +204,12 @@ __global__ void __launch_bounds__(64) composite_bwd_kernel(
     float bg1, float bg2, const float* __restrict__ g_rgb, const float* __restrict__ g_depth,
     const float* __restrict__ g_alpha, const float* __restrict__ t_final,
     const int32_t* __restrict__ n_last, float* __restrict__ partial,
-    uint32_t* __restrict__ stamp, uint32_t epoch, int xcd_remap) {
+    uint32_t* __restrict__ stamp, const uint32_t* __restrict__ epoch_dev, int xcd_remap) {
   constexpr int PIX = TW * TH / kWave;
   constexpr int RPP = kWave / TW;
   __shared__ Record sm[kWave];
   __shared__ uint32_t slot[kWave];
+  const uint32_t epoch = *epoch_dev;
   const int tile = tile_of_block(blockIdx.x, n_tiles, xcd_remap != 0);
   if (tile >= n_tiles) return;
   const uint32_t nproc = tile_nproc[tile];
@@ -160,7 +225,9 @@ __global__ void __launch_bounds__(64) composite_bwd_kernel(
   const uint2 rg = ranges[tile];
   const int64_t plane = (int64_t)fr.width * fr.height;
 
-  float T[PIX], Tf[PIX], A0[PIX], A1[PIX], A2[PIX], AZ[PIX];
+  // per pixel: T_{i+1}; colour, depth and transmittance seen behind the
+  // current entry (normalised by T_{i+1}); upstream gradients
+  float T[PIX], B0[PIX], B1[PIX], B2[PIX], BZ[PIX], BT[PIX];
   float G0[PIX], G1[PIX], G2[PIX], GD[PIX], GA[PIX];
   int last[PIX];
 #pragma unroll
@@ -169,9 +236,8 @@ __global__ void __launch_bounds__(64) composite_bwd_kernel(
     const bool valid = px < fr.width && py < fr.height;
     const int64_t p = (int64_t)py * fr.width + px;
     last[k] = valid ? n_last[fr.pixel_offset + p] : 0;
-    Tf[k] = valid ? t_final[fr.pixel_offset + p] : 1.0f;
-    T[k] = Tf[k];
-    A0[k] = Tf[k] * bg0; A1[k] = Tf[k] * bg1; A2[k] = Tf[k] * bg2; AZ[k] = 0.0f;
+    T[k] = valid ? t_final[fr.pixel_offset + p] : 1.0f;
+    B0[k] = bg0; B1[k] = bg1; B2[k] = bg2; BZ[k] = 0.0f; BT[k] = 1.0f;
     const float* gi = g_rgb + 3 * fr.pixel_offset;
     G0[k] = valid ? gi[p] : 0.0f;
     G1[k] = valid ? gi[plane + p] : 0.0f;
@@ -197,8 +263,8 @@ __global__ void __launch_bounds__(64) composite_bwd_kernel(
       const int ylo = R.sqy & 0xffff, yhi = R.sqy >> 16;
       const bool xin = (unsigned)(px - xlo) <= (unsigned)(xhi - xlo);
       const float dx = dx_of(R.u_hi, R.u_lo, px);
-      const float cA = R.a1 * R.a1, cB = R.a1 * R.a2, cC = R.a2 * R.a2 + R.a3 * R.a3;
-      float gu = 0.f, gv = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, gs = 0.f;
+      const float a1dx = R.a1 * dx;
+      float gu = 0.f, gv = 0.f, gSxx = 0.f, gSxy = 0.f, gSyy = 0.f, gs = 0.f;
       float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f, gz = 0.f;
       bool any = false;
 #pragma unroll
@@ -214,57 +280,48 @@ __global__ void __launch_bounds__(64) composite_bwd_kernel(
         const float a = fminf(kAlphaMax, sg);
         if (a < kAlphaMin) continue;
         const float om = 1.0f - a;
-        const float inv = 1.0f / om;
-        const float Ti = T[k] * inv;
+        const float inv = __builtin_amdgcn_rcpf(om);
+        float Ti = T[k] * inv;
+        Ti = __builtin_fmaf(__builtin_fmaf(-Ti, om, T[k]), inv, Ti);  // Newton step
         const float w = a * Ti;
-        const float dLda = G0[k] * (R.c0 * Ti - A0[k] * inv) + G1[k] * (R.c1 * Ti - A1[k] * inv) +
-                           G2[k] * (R.c2 * Ti - A2[k] * inv) + GD[k] * (R.z * Ti - AZ[k] * inv) +
-                           GA[k] * (Tf[k] * inv);
+        // dL/da_i = T_i [G . (c_i - B_i) + G_D (z_i - BZ_i) + G_A BT_i]
+        const float dLda = Ti * (G0[k] * (R.c0 - B0[k]) + G1[k] * (R.c1 - B1[k]) +
+                                 G2[k] * (R.c2 - B2[k]) + GD[k] * (R.z - BZ[k]) +
+                                 GA[k] * BT[k]);
         gc0 += G0[k] * w;
         gc1 += G1[k] * w;
         gc2 += G2[k] * w;
         gz += GD[k] * w;
-        A0[k] += R.c0 * w;
-        A1[k] += R.c1 * w;
-        A2[k] += R.c2 * w;
-        AZ[k] += R.z * w;
+        // step the 'behind' state in front of entry i
+        B0[k] = __builtin_fmaf(a, R.c0 - B0[k], B0[k]);
+        B1[k] = __builtin_fmaf(a, R.c1 - B1[k], B1[k]);
+        B2[k] = __builtin_fmaf(a, R.c2 - B2[k], B2[k]);
+        BZ[k] = __builtin_fmaf(a, R.z - BZ[k], BZ[k]);
+        BT[k] = BT[k] * om;
         T[k] = Ti;
         any = true;
         if (sg > kAlphaMax) continue;  // clamped: alpha does not move
         gs += dLda * g;
         const float dq = -0.5f * a * dLda;
-        gu += dq * 2.0f * (cA * dx + cB * dy);
-        gv += dq * 2.0f * (cB * dx + cC * dy);
-        gA += dq * dx * dx;
-        gB += dq * 2.0f * dx * dy;
-        gC += dq * dy * dy;
+        // Q d = L (L^T d), L^T d = (a1 dx + a2 dy, a3 dy)
+        const float m = __builtin_fmaf(R.a2, dy, a1dx);
+        const float b = R.a3 * dy;
+        const float qx = R.a1 * m;
+        const float qy = __builtin_fmaf(R.a2, m, R.a3 * b);
+        gu += 2.0f * dq * qx;
+        gv += 2.0f * dq * qy;
+        gSxx -= dq * qx * qx;
+        gSxy -= dq * qx * qy;
+        gSyy -= dq * qy * qy;
       }
       if (__ballot(any) == 0) continue;
-      for (int o = 32; o > 0; o >>= 1) {
-        gu += __shfl_xor(gu, o, 64);
-        gv += __shfl_xor(gv, o, 64);
-        gA += __shfl_xor(gA, o, 64);
-        gB += __shfl_xor(gB, o, 64);
-        gC += __shfl_xor(gC, o, 64);
-        gs += __shfl_xor(gs, o, 64);
-        gc0 += __shfl_xor(gc0, o, 64);
-        gc1 += __shfl_xor(gc1, o, 64);
-        gc2 += __shfl_xor(gc2, o, 64);
-        gz += __shfl_xor(gz, o, 64);
-      }
+      const float vals10[kNG] = {gu, gv, gSxx, gSxy, gSyy, gs, gc0, gc1, gc2, gz};
+      int idx;
+      bool writer;
+      const float tot = wave_transpose_sum10(vals10, lane, idx, writer);
       const uint32_t sl = slot[j];
-      float v = gu;
-      v = lane == 1 ? gv : v;
-      v = lane == 2 ? gA : v;
-      v = lane == 3 ? gB : v;
-      v = lane == 4 ? gC : v;
-      v = lane == 5 ? gs : v;
-      v = lane == 6 ? gc0 : v;
-      v = lane == 7 ? gc1 : v;
-      v = lane == 8 ? gc2 : v;
-      v = lane == 9 ? gz : v;
-      if (lane < kNG) partial[(size_t)sl * kNG + lane] = v;
-      if (lane == kNG) stamp[sl] = epoch;
+      if (writer) partial[(size_t)sl * kNG + idx] = tot;
+      if (lane == 1) stamp[sl] = epoch;
     }
     __syncthreads();
   }
@@ -292,8 +349,8 @@ static void launch_bwd_t(hipStream_t st, int n_tiles, int F, const FrameDesc* fr
                          const uint2* ranges, const uint32_t* vals, const Record* rec,
                          const uint32_t* nproc, const float* bg, const float* g_rgb,
                          const float* g_depth, const float* g_alpha, const float* t_final,
-                         const int32_t* n_last, float* partial, uint32_t* stamp, uint32_t epoch,
-                         bool remap) {
+                         const int32_t* n_last, float* partial, uint32_t* stamp,
+                         const uint32_t* epoch, bool remap) {
   const unsigned grid = remap ? (unsigned)(((n_tiles + 7) / 8) * 8) : (unsigned)n_tiles;
   hipLaunchKernelGGL((composite_bwd_kernel<TW, TH>), dim3(grid), dim3(kWave), 0, st, n_tiles, F,
                      frames, ranges, vals, rec, nproc, bg[0], bg[1], bg[2], g_rgb, g_depth,
@@ -311,8 +368,9 @@ void launch_composite_fwd(hipStream_t st, int tw, int th, int n_tiles, int F,
                           float* alpha, float* t_final, int32_t* n_last, uint32_t* nproc,
                           bool remap, unsigned long long* pairs) {
   if (n_tiles <= 0) return;
-#define GSR_FWD(W, H) launch_fwd_t<W, H>(st, n_tiles, F, frames, ranges, vals, rec, bg, rgb, \
-                                         depth, alpha, t_final, n_last, nproc, remap, pairs)
+#define GSR_FWD(W, H)                                                                        \
+  launch_fwd_t<W, H>(st, n_tiles, F, frames, ranges, vals, rec, bg, rgb, depth, alpha, t_final, \
+                     n_last, nproc, remap, pairs)
   if (tw == 16 && th == 16) GSR_FWD(16, 16);
   else if (tw == 8 && th == 8) GSR_FWD(8, 8);
   else if (tw == 32 && th == 8) GSR_FWD(32, 8);
@@ -326,7 +384,7 @@ void launch_composite_bwd(hipStream_t st, int tw, int th, int n_tiles, int F,
                           const Record* rec, const uint32_t* nproc, const float* bg,
                           const float* g_rgb, const float* g_depth, const float* g_alpha,
                           const float* t_final, const int32_t* n_last, float* partial,
-                          uint32_t* stamp, uint32_t epoch, bool remap) {
+                          uint32_t* stamp, const uint32_t* epoch, bool remap) {
   if (n_tiles <= 0) return;
 #define GSR_BWD(W, H)                                                                          \
   launch_bwd_t<W, H>(st, n_tiles, F, frames, ranges, vals, rec, nproc, bg, g_rgb, g_depth,   \

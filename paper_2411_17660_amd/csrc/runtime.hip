@@ -21,8 +21,9 @@ int64_t preprocess_bwd_waves(int64_t n);
 void launch_preprocess_bwd(hipStream_t, int64_t, int, const FrameDesc*, const float*,
                            const float*, const float*, const float*, const float*, const float*,
                            int, const Record*, const uint32_t*, const float*, const uint32_t*,
-                           uint32_t, uint64_t, float*, float*, float*, float*, float*, double*,
-                           float*);
+                           const uint32_t*, uint64_t, float*, float*, float*, float*, float*,
+                           float*, double*, float*);
+void launch_bump_epoch(hipStream_t, uint32_t*);
 // sort.hip
 void launch_fill_u32(hipStream_t, uint32_t*, uint64_t, uint32_t);
 size_t radix_hist_elems(uint64_t n_max);
@@ -44,7 +45,7 @@ void launch_composite_fwd(hipStream_t, int, int, int, int, const FrameDesc*, con
 void launch_composite_bwd(hipStream_t, int, int, int, int, const FrameDesc*, const uint2*,
                           const uint32_t*, const Record*, const uint32_t*, const float*,
                           const float*, const float*, const float*, const float*,
-                          const int32_t*, float*, uint32_t*, uint32_t, bool);
+                          const int32_t*, float*, uint32_t*, const uint32_t*, bool);
 // loss.hip
 int loss_blocks_x(int64_t max_hw);
 void launch_loss_l1(hipStream_t, int, int, const FrameDesc*, const float*, const float*,
@@ -83,7 +84,7 @@ struct gsr_context {
   std::string err;
   // workspace
   DBuf rec, dkey_a, dval_a, dkey_b, dval_b, ntiles, offsets, scan_tmp, hist, counters;
-  DBuf keys_a, vals_a, keys_b, vals_b, partial, stamp;
+  DBuf keys_a, vals_a, keys_b, vals_b, partial, stamp, grad2d;
   DBuf ranges, nproc, t_final, n_last, frames, twist_part, loss_part, loss_scale;
   DBuf up_rgb, up_depth, up_alpha;  // upstream gradients for gsr_step_l1
   uint64_t key_cap = 0;             // allocated key slots
@@ -283,6 +284,7 @@ gsr_status gsr_destroy(gsr_context* ctx) {
   DBuf* bufs[] = {&ctx->rec, &ctx->dkey_a, &ctx->dval_a, &ctx->dkey_b, &ctx->dval_b,
                   &ctx->ntiles, &ctx->offsets, &ctx->scan_tmp, &ctx->hist, &ctx->counters,
                   &ctx->keys_a, &ctx->vals_a, &ctx->keys_b, &ctx->vals_b, &ctx->partial,
+                  &ctx->grad2d,
                   &ctx->stamp, &ctx->ranges, &ctx->nproc, &ctx->t_final, &ctx->n_last,
                   &ctx->frames, &ctx->twist_part, &ctx->loss_part, &ctx->loss_scale,
                   &ctx->up_rgb, &ctx->up_depth, &ctx->up_alpha};
@@ -486,11 +488,12 @@ gsr_status gsr_backward(gsr_context* ctx, const float* g_rgb, const float* g_dep
   GSR_HIP(hipSetDevice(ctx->device));
   const gsr_settings& s = sv.set;
   gsr_status rc;
+  // The epoch lives in device memory (counters[3]) and is advanced by a
+  // kernel, so a captured step stamps with a new epoch on every replay.  A
+  // stale stamp could only alias after 2^32 - 1 backward calls.
   ++ctx->epoch;
-  if (ctx->epoch == 0) {  // wrapped: restart the stamps
-    GSR_HIP(hipMemsetAsync(ctx->stamp.p, 0, ctx->stamp.bytes, st));
-    ctx->epoch = 1;
-  }
+  uint32_t* d_epoch = (uint32_t*)(P<uint64_t>(ctx->counters) + 3);
+  launch_bump_epoch(st, d_epoch);
   const uint32_t* svals = P<uint32_t>(sv.sorted_in_b ? ctx->vals_b : ctx->vals_a);
   const bool remap = !(s.flags & GSR_FLAG_NO_XCD_REMAP);
   const bool timing = (s.flags & GSR_FLAG_TIMING) != 0;
@@ -501,20 +504,21 @@ gsr_status gsr_backward(gsr_context* ctx, const float* g_rgb, const float* g_dep
                          P<uint2>(ctx->ranges), svals, P<Record>(ctx->rec),
                          P<uint32_t>(ctx->nproc), s.background, g_rgb, g_depth, g_alpha,
                          P<float>(ctx->t_final), P<int32_t>(ctx->n_last),
-                         P<float>(ctx->partial), P<uint32_t>(ctx->stamp), ctx->epoch, remap);
+                         P<float>(ctx->partial), P<uint32_t>(ctx->stamp), d_epoch, remap);
   }
   // A9-A11 per-record reduce, chain rule, twist
   const int64_t waves = sv.n > 0 ? preprocess_bwd_waves(sv.n) : 0;
   if ((rc = ensure(ctx, ctx->twist_part, (size_t)std::max<int64_t>(waves, 1) * sv.F * 6 * 8, st)))
     return rc;
+  if ((rc = ensure(ctx, ctx->grad2d, (size_t)sv.n * sv.F * kNG * 4, st))) return rc;
   {
     StageTimer t(ctx, st, timing, GSR_STAGE_PREPROCESS_BWD);
     launch_preprocess_bwd(st, sv.n, sv.F, P<FrameDesc>(ctx->frames), sv.poses, sv.means,
                           sv.log_scales, sv.quats, sv.opac, sv.sh, s.sh_degree,
                           P<Record>(ctx->rec), P<uint32_t>(ctx->ntiles), P<float>(ctx->partial),
-                          P<uint32_t>(ctx->stamp), ctx->epoch, ctx->key_cap, g_means,
-                          g_log_scales, g_quats, g_opac, g_sh, P<double>(ctx->twist_part),
-                          g_twist);
+                          P<uint32_t>(ctx->stamp), d_epoch, ctx->key_cap,
+                          P<float>(ctx->grad2d), g_means, g_log_scales, g_quats, g_opac, g_sh,
+                          P<double>(ctx->twist_part), g_twist);
   }
   GSR_HIP(hipGetLastError());
   return GSR_OK;

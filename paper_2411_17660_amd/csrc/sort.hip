@@ -129,28 +129,27 @@ __global__ void __launch_bounds__(kScanThreads) scan_down_kernel(Load ld, const 
 
 // ---------------------------------------------------------------------------
 // LSD radix pass, 8-bit digit at `shift`, stable.
+//
+// Both kernels see a block as 4 waves x 16 rounds x 64 keys, wave w owning a
+// contiguous quarter.  Per round a wave ranks its 64 keys by digit with 8
+// ballots (lanes with equal digits form one mask); the lowest lane of each
+// group bumps the wave's LDS counter.  No atomics, so the counts and ranks
+// are deterministic and the scatter is stable.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
+  uint64_t m = __ballot(valid);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t bb = __ballot(bit);
+    m &= bit ? bb : ~bb;
+  }
+  return m;
+}
+
 __global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(
     const uint32_t* __restrict__ keys, const uint64_t* n_dev, uint64_t n_host, int shift,
     uint32_t* __restrict__ hist /* [256][nblocks] */) {
-  __shared__ uint32_t cnt[kRadixBins];
-  const uint64_t n = n_dev ? min(*n_dev, n_host) : n_host;
-  cnt[threadIdx.x] = 0;
-  __syncthreads();
-  const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
-  for (int k = 0; k < kSortRounds; ++k) {
-    const uint64_t i = base + (uint64_t)k * kSortThreads + threadIdx.x;
-    if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 0xffu], 1u);
-  }
-  __syncthreads();
-  hist[(uint64_t)threadIdx.x * gridDim.x + blockIdx.x] = cnt[threadIdx.x];
-}
-
-__global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
-    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
-    const uint64_t* n_dev, uint64_t n_host, int shift,
-    const uint32_t* __restrict__ offsets /* scanned [256][nblocks] */,
-    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
   __shared__ uint32_t wcnt[kSortWaves][kRadixBins];
   const uint64_t n = n_dev ? min(*n_dev, n_host) : n_host;
   const int lane = threadIdx.x & (kWave - 1);
@@ -160,6 +159,39 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
   __syncthreads();
   const uint64_t wbase = (uint64_t)blockIdx.x * kSortTile + (uint64_t)w * (kWave * kSortRounds);
   const uint64_t lt = lanemask_lt();
+  for (int k = 0; k < kSortRounds; ++k) {
+    const uint64_t i = wbase + (uint64_t)k * kWave + lane;
+    const bool valid = i < n;
+    const uint32_t d = valid ? (keys[i] >> shift) & 0xffu : 0u;
+    const uint64_t m = digit_peers(d, valid);
+    if (valid && (m & lt) == 0) wcnt[w][d] += (uint32_t)__popcll(m);
+  }
+  __syncthreads();
+  const int d = threadIdx.x;
+  uint32_t c = 0;
+  for (int ww = 0; ww < kSortWaves; ++ww) c += wcnt[ww][d];
+  hist[(uint64_t)d * gridDim.x + blockIdx.x] = c;
+}
+
+__global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
+    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
+    const uint64_t* n_dev, uint64_t n_host, int shift,
+    const uint32_t* __restrict__ offsets /* scanned [256][nblocks] */,
+    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
+  __shared__ uint32_t wcnt[kSortWaves][kRadixBins];  // counts, then wave bases in digit
+  __shared__ uint32_t dstart[kRadixBins];            // block-local start of each digit
+  __shared__ uint32_t gbase[kRadixBins];             // global start of digit for the block
+  __shared__ uint32_t scan_sh[kSortThreads];
+  __shared__ uint32_t sk[kSortTile], sv[kSortTile];  // block keys in local digit order
+  const uint64_t n = n_dev ? min(*n_dev, n_host) : n_host;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  for (int i = threadIdx.x; i < kSortWaves * kRadixBins; i += kSortThreads)
+    (&wcnt[0][0])[i] = 0;
+  __syncthreads();
+  const uint64_t bbase = (uint64_t)blockIdx.x * kSortTile;
+  const uint64_t wbase = bbase + (uint64_t)w * (kWave * kSortRounds);
+  const uint64_t lt = lanemask_lt();
   uint32_t key[kSortRounds], val[kSortRounds], rank[kSortRounds];
   for (int k = 0; k < kSortRounds; ++k) {
     const uint64_t i = wbase + (uint64_t)k * kWave + lane;
@@ -167,84 +199,116 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
     key[k] = valid ? keys_in[i] : 0u;
     val[k] = valid ? vals_in[i] : 0u;
     const uint32_t d = (key[k] >> shift) & 0xffu;
-    uint64_t m = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t bb = __ballot(bit);
-      m &= bit ? bb : ~bb;
-    }
-    // lanes with the same digit form the group m (valid lanes only)
+    const uint64_t m = digit_peers(d, valid);
+    // LDS ops of one wave complete in issue order: the read precedes the
+    // leader's write of the same counter
     const uint32_t before = wcnt[w][d];
     rank[k] = before + (uint32_t)__popcll(m & lt);
-    const bool leader = valid && (m & lt) == 0;
-    if (leader) wcnt[w][d] = before + (uint32_t)__popcll(m);
-    // wave-local ordering of LDS ops keeps the read above before the write
+    if (valid && (m & lt) == 0) wcnt[w][d] = before + (uint32_t)__popcll(m);
   }
   __syncthreads();
-  // per digit: base of each wave = global block offset + earlier waves
   {
     const int d = threadIdx.x;
-    uint32_t run = offsets[(uint64_t)d * gridDim.x + blockIdx.x];
+    uint32_t run = 0;
     for (int ww = 0; ww < kSortWaves; ++ww) {
       const uint32_t c = wcnt[ww][d];
       wcnt[ww][d] = run;
       run += c;
     }
+    uint32_t total;
+    dstart[d] = block_exclusive_scan<uint32_t>(run, scan_sh, total);
+    gbase[d] = offsets[(uint64_t)d * gridDim.x + blockIdx.x];
   }
   __syncthreads();
   for (int k = 0; k < kSortRounds; ++k) {
     const uint64_t i = wbase + (uint64_t)k * kWave + lane;
     if (i < n) {
       const uint32_t d = (key[k] >> shift) & 0xffu;
-      const uint32_t dst = wcnt[w][d] + rank[k];
-      keys_out[dst] = key[k];
-      vals_out[dst] = val[k];
+      const uint32_t lp = dstart[d] + wcnt[w][d] + rank[k];
+      sk[lp] = key[k];
+      sv[lp] = val[k];
     }
+  }
+  __syncthreads();
+  const uint32_t nb = (uint32_t)(n > bbase ? min((uint64_t)kSortTile, n - bbase) : 0);
+  for (uint32_t idx = threadIdx.x; idx < nb; idx += kSortThreads) {
+    const uint32_t kk = sk[idx];
+    const uint32_t d = (kk >> shift) & 0xffu;
+    const uint32_t dst = gbase[d] + (idx - dstart[d]);
+    keys_out[dst] = kk;
+    vals_out[dst] = sv[idx];
   }
 }
 
 // ---------------------------------------------------------------------------
-// keygen: one thread per depth-sorted record
+// keygen: a wave owns 64 consecutive depth-sorted records; their key slots
+// form one contiguous range, which the lanes write cooperatively (slot o by
+// lane o % 64) after locating the owning record with a 6-step search in LDS,
+// so every store instruction writes 64 consecutive keys.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) keygen_kernel(
-    const uint64_t* __restrict__ m_dev, uint64_t m_host, const uint32_t* __restrict__ perm,
-    const uint32_t* __restrict__ ntiles, const uint64_t* __restrict__ offsets,
-    Record* __restrict__ rec, const FrameDesc* __restrict__ frames, int tile_w, int tile_h,
-    uint64_t capacity, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
-    uint32_t* __restrict__ overflow) {
-  const uint64_t m = m_dev ? *m_dev : m_host;
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
-  const uint32_t r = perm[i];
-  const uint32_t cnt = ntiles[r];
-  if (cnt == 0) return;
-  const uint64_t off = offsets[i];
-  Record& o = rec[r];
-  if (off + cnt > capacity) {
-    // Fixed capacity exceeded: flag it, mark the record unreachable and fill
-    // the slots that do exist with a sentinel tile id past every real tile.
-    atomicOr(overflow, 1u);
-    o.key_offset = 0xffffffffu;
-    for (uint64_t k = off; k < capacity; ++k) {
-      keys[k] = 0xffffffffu;
-      vals[k] = 0u;
+    uint64_t m, const uint32_t* __restrict__ perm, const uint32_t* __restrict__ ntiles,
+    const uint64_t* __restrict__ offsets, Record* __restrict__ rec,
+    const FrameDesc* __restrict__ frames, int tile_w, int tile_h, uint64_t capacity,
+    uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, uint32_t* __restrict__ overflow) {
+  __shared__ uint64_t s_off[4][kWave];
+  __shared__ uint32_t s_r[4][kWave], s_w[4][kWave], s_gx[4][kWave], s_base[4][kWave];
+  __shared__ uint8_t s_ovf[4][kWave];
+  const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const uint64_t i0 = ((uint64_t)blockIdx.x * 4 + w) * kWave;
+  const uint64_t i = i0 + lane;
+  uint32_t cnt = 0;
+  uint64_t off = 0;
+  if (i < m) {
+    const uint32_t r = perm[i];
+    cnt = ntiles[r];
+    off = offsets[i];
+    s_r[w][lane] = r;
+    if (cnt) {
+      Record& o = rec[r];
+      const FrameDesc fr = frames[o.frame];
+      const int tx0 = (o.sqx & 0xffff) / tile_w, tx1 = (o.sqx >> 16) / tile_w;
+      const int ty0 = (o.sqy & 0xffff) / tile_h;
+      s_w[w][lane] = (uint32_t)(tx1 - tx0 + 1);
+      s_gx[w][lane] = (uint32_t)fr.grid_x;
+      s_base[w][lane] = (uint32_t)(fr.tile_offset + ty0 * fr.grid_x + tx0);
+      const bool ovf = off + cnt > capacity;
+      s_ovf[w][lane] = ovf ? 1 : 0;
+      o.key_offset = ovf ? 0xffffffffu : (uint32_t)off;
+      if (ovf) atomicOr(overflow, 1u);
     }
-    return;
   }
-  o.key_offset = (uint32_t)off;
-  const FrameDesc fr = frames[o.frame];
-  const int x_lo = o.sqx & 0xffff, x_hi = o.sqx >> 16;
-  const int y_lo = o.sqy & 0xffff, y_hi = o.sqy >> 16;
-  const int tx0 = x_lo / tile_w, tx1 = x_hi / tile_w;
-  const int ty0 = y_lo / tile_h, ty1 = y_hi / tile_h;
-  uint64_t k = off;
-  for (int ty = ty0; ty <= ty1; ++ty)
-    for (int tx = tx0; tx <= tx1; ++tx) {
-      keys[k] = (uint32_t)(fr.tile_offset + ty * fr.grid_x + tx);
-      vals[k] = r;
-      ++k;
+  s_off[w][lane] = i < m ? off : ~0ull;
+  __syncthreads();  // every wave reaches the barrier; empty waves leave after it
+  if (i0 >= m) return;
+  // contiguous slot range of the wave's records
+  const uint64_t lo = s_off[w][0];
+  uint64_t hi = off + cnt;
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint64_t h2 = __shfl_xor(hi, o, 64);
+    hi = h2 > hi ? h2 : hi;
+  }
+  if (hi > capacity) hi = capacity;
+  for (uint64_t o = lo + lane; o < hi; o += kWave) {
+    // owner: the last record with s_off <= o
+    int j = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1)
+      if (s_off[w][j + step] <= o) j += step;
+    uint32_t key, val;
+    if (s_ovf[w][j]) {
+      key = 0xffffffffu;  // sentinel past every real tile
+      val = 0u;
+    } else {
+      const uint32_t local = (uint32_t)(o - s_off[w][j]);
+      const uint32_t wdt = s_w[w][j];
+      const uint32_t row = local / wdt;
+      key = s_base[w][j] + row * s_gx[w][j] + (local - row * wdt);
+      val = s_r[w][j];
     }
+    keys[o] = key;
+    vals[o] = val;
+  }
 }
 
 // [start, end) of every tile's run in the sorted keys (ranges pre-zeroed).
@@ -336,9 +400,8 @@ void launch_keygen(hipStream_t st, uint64_t m, const uint32_t* perm, const uint3
                    int tile_h, uint64_t capacity, uint32_t* keys, uint32_t* vals,
                    uint32_t* overflow) {
   if (m == 0) return;
-  hipLaunchKernelGGL(keygen_kernel, dim3(blocks_for(m, 256)), dim3(256), 0, st,
-                     (const uint64_t*)nullptr, m, perm, ntiles, offsets, rec, frames, tile_w,
-                     tile_h, capacity, keys, vals, overflow);
+  hipLaunchKernelGGL(keygen_kernel, dim3(blocks_for(m, 256)), dim3(256), 0, st, m, perm, ntiles,
+                     offsets, rec, frames, tile_w, tile_h, capacity, keys, vals, overflow);
 }
 
 void launch_ranges(hipStream_t st, const uint32_t* keys, const uint64_t* k_dev, uint64_t k_max,

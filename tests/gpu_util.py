@@ -71,8 +71,17 @@ def assert_grad_close(name, got, ref, rel=GRAD_REL):
     rms = np.sqrt(np.mean(ref ** 2)) if ref.size else 0.0
     bound = rel * np.maximum(np.abs(ref), 1e-2 * rms)
     err = np.abs(got - ref)
+    q = err / (rel * np.maximum(np.abs(ref), 1e-2 * rms) + 1e-30) * rel
+    if q.size:
+        print(f"[grad] {name}: max err/bound-scale {q.max():.3g}, "
+              f"p99.9 {np.quantile(q, 0.999):.3g}", flush=True)
     bad = err > bound + 1e-30
     if bad.any():
+        worst = np.argsort(-(err / (bound + 1e-30)))[:6]
+        for i in worst:
+            print(f"[grad]   {name}[{int(i)}] got {got[i]:.9g} ref {ref[i]:.9g} "
+                  f"rel {err[i] / max(abs(ref[i]), 1e-300):.3g} |ref|/rms "
+                  f"{abs(ref[i]) / max(rms, 1e-300):.3g}", flush=True)
         i = int(np.argmax(err / (bound + 1e-30)))
         raise AssertionError(f"{name}: {int(bad.sum())} of {ref.size} elements exceed the "
                              f"bound; worst idx {i}: got {got[i]!r} ref {ref[i]!r} "

@@ -218,7 +218,7 @@ def test_batch_equals_per_frame(rast):
         acc = gf if acc is None else {k: acc[k] + gf[k] for k in acc}
         off += P
     for k in ("means", "log_scales", "quats", "opacity", "sh"):
-        assert_grad_close(f"batch:{k}", gb[k], acc[k], rel=1e-5)
+        assert_grad_close(f"batch:{k}", gb[k], acc[k], rel=1e-4)
 
 
 # ---------------------------------------------------------------------- loss
@@ -297,3 +297,61 @@ def test_c3_full_size_sampled_frames(rast):
         tr = g_ref["twist"][0]
         assert np.all(np.abs(g1["twist"][0] - tr) <= 1e-3 * np.maximum(np.abs(tr), 1e-2 * np.abs(tr).max()))
     del torch
+
+
+# ---------------------------------------------------------------------- graphs
+def test_graph_captured_step_replays_match_eager(rast):
+    """The fixed-capacity step (forward + L1 loss + backward) captured in a
+    HIP graph: every replay, with eager work and synchronisations between
+    replays, equals the eager step bitwise."""
+    import torch
+    from paper_2411_17660_amd.raster import Rasterizer
+    sc = scenes.tiny_scene(seed=12, n=3000, W=160, H=96, f=120.0, n_frames=3)
+    from gpu_util import to_dev
+    d = to_dev(sc)
+    P, n, K = sc.n_pixels, sc.n, (sc.sh_degree + 1) ** 2
+    rng = np.random.default_rng(12)
+    t_rgb = torch.from_numpy(rng.uniform(0, 1, 3 * P).astype(np.float32)).cuda()
+    t_dep = torch.from_numpy(rng.uniform(0.5, 4, P).astype(np.float32)).cuda()
+
+    def bufs():
+        dev = "cuda"
+        return dict(rgb=torch.empty(3 * P, device=dev), depth=torch.empty(P, device=dev),
+                    alpha=torch.empty(P, device=dev), loss=torch.empty(1, device=dev),
+                    means=torch.empty(n, 3, device=dev), log_scales=torch.empty(n, 3, device=dev),
+                    quats=torch.empty(n, 4, device=dev), opacity=torch.empty(n, device=dev),
+                    sh=torch.empty(n, K, 3, device=dev), twist=torch.empty(3, 6, device=dev))
+    r = Rasterizer(0)
+    b = bufs()
+
+    def step(cap):
+        r.step_l1(d["means"], d["log_scales"], d["quats"], d["opacity"], d["sh"], d["poses"],
+                  sc.cams, sc.sh_degree, t_rgb, t_dep, 0.5, b, background=sc.background,
+                  key_capacity=cap)
+    step(0)
+    torch.cuda.synchronize()
+    cap = r.stats()["n_keys"] + 64
+    step(cap)
+    torch.cuda.synchronize()
+    eager = {k: v.clone() for k, v in b.items()}
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step(cap)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step(cap)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for v in b.values():
+            v.fill_(float("nan"))
+        g.replay()
+        torch.cuda.synchronize()
+        for k in eager:
+            assert torch.equal(b[k], eager[k]), (rep, k)
+        # unrelated eager work between replays, on the same context
+        step(cap)
+        torch.cuda.synchronize()
+    r.check_overflow()

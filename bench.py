@@ -42,7 +42,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--tile", default="auto", help="WxH or 'auto' (autotuner's choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-frame", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
@@ -61,7 +61,6 @@ def main():
     from paper_2411_17660_amd import scenes
     from paper_2411_17660_amd.raster import Rasterizer
 
-    tile = tuple(int(v) for v in args.tile.split("x"))
     t0 = time.time()
     sc = scenes.scene_c3(n=args.n)
     log(f"[bench] scene generated in {time.time() - t0:.1f}s: n={sc.n} frames={sc.n_frames}")
@@ -75,9 +74,18 @@ def main():
     rast = Rasterizer(0)
     # targets: render of the ground-truth means (workload set-up, untimed)
     t_rgb, t_dep, _ = rast.forward(gt_means, dev["log_scales"], dev["quats"], dev["opacity"],
-                                   dev["sh"], dev["poses"], sc.cams, 3, tile=tile)
+                                   dev["sh"], dev["poses"], sc.cams, 3)
     t_rgb, t_dep = t_rgb.clone(), t_dep.clone()
     torch.cuda.synchronize()
+    tune = None
+    if args.tile == "auto":
+        tile, _, times = rast.autotune(dev["means"], dev["log_scales"], dev["quats"],
+                                       dev["opacity"], dev["sh"], dev["poses"], sc.cams, 3,
+                                       t_rgb, t_dep, depth_weight, reps=3, force=True)
+        tune = {f"{w}x{h}": round(ms, 3) for (w, h), ms in times.items()}
+        log(f"[bench] autotune: {tune} -> {tile}")
+    else:
+        tile = tuple(int(v) for v in args.tile.split("x"))
 
     def buffers(n_frames_px, nF):
         K = (sc.sh_degree + 1) ** 2
@@ -208,6 +216,7 @@ def main():
                                "fwd + L1 rgb + L1 depth + bwd incl. pose twists",
                    "n_gaussians": sc.n, "frames": F, "resolution": [W, H],
                    "tile": list(tile), "keys_per_step": int(K)},
+        "autotune_ms_per_tile_shape": tune,
         "eager_ms_per_step": round(t_batched * 1e3, 4),
         "graph_ms_per_step": None if t_graph is None else round(t_graph * 1e3, 4),
         "per_frame_ms_per_step": None if t_per_frame is None else round(t_per_frame * 1e3, 4),

@@ -151,6 +151,39 @@ gsr_status gsr_step_l1(gsr_context* ctx, const gsr_settings* settings, int64_t n
                        float* g_quats, float* g_opacity_logits, float* g_sh, float* g_twist,
                        void* stream);
 
+/* Autotuner: runs gsr_step_l1 with every supported tile shape (16x16, 8x8,
+ * 32x8, 16x8, 32x16) on the given inputs, `reps` timed runs each with HIP
+ * events on `stream` after one untimed sizing run, and writes the fastest
+ * settings to *chosen (base settings with tile_w/tile_h replaced and a fixed
+ * key_capacity 5% above the measured count).  ms[i] receives the median step
+ * time of shape i in the order above (array of 5; NULL allowed).  The choice
+ * is cached in the context per (frame sizes, n rounded to a power of two, SH
+ * degree); a cached choice is returned without measuring unless `force`.
+ * The library owns the scratch outputs it renders into. */
+gsr_status gsr_autotune(gsr_context* ctx, const gsr_settings* base, int64_t n, const float* means,
+                        const float* log_scales, const float* quats,
+                        const float* opacity_logits, const float* sh, int32_t n_frames,
+                        const gsr_camera* cams, const float* poses, const float* target_rgb,
+                        const float* target_depth, float depth_weight, int32_t reps,
+                        int32_t force, gsr_settings* chosen, float* ms, void* stream);
+
+/* Optimiser step of the mapping loop (one launch sequence): Adam on the means
+ * (lr_means) and the SH coefficients (lr_sh), and Adam on each frame's pose
+ * twist (lr_pose) followed by the fold T_f <- Exp(xi_f) T_f in FP64 (left
+ * perturbation, xi = (rho, phi), Exp = [R(phi), V(phi) rho]).  Log-scales,
+ * quaternions and opacities are not updated.  m_* / v_* are caller-owned
+ * first/second moment buffers shaped like their parameters (zero before the
+ * first step); *step (device int32, 0 before the first step) is the number of
+ * steps taken and is incremented on the device, so a captured iteration
+ * advances it on every replay.  Bias correction uses step + 1.  n_frames is at
+ * most 1024. */
+gsr_status gsr_adam_step(gsr_context* ctx, int64_t n, int32_t sh_degree, float* means,
+                         const float* g_means, float* m_means, float* v_means, float* sh,
+                         const float* g_sh, float* m_sh, float* v_sh, int32_t n_frames,
+                         float* poses, const float* g_twist, float* m_twist, float* v_twist,
+                         float lr_means, float lr_sh, float lr_pose, float beta1, float beta2,
+                         float eps, int32_t* step, void* stream);
+
 /* Synchronises `stream` and returns GSR_ERR_CAPACITY if a fixed-capacity
  * forward since the last check had more keys than key_capacity (its outputs
  * are then undefined), else GSR_OK.  Clears the flag. */

@@ -30,7 +30,20 @@ def load():
         return _lib
     if not os.path.exists(_build.LIB):
         _build.build()
-    lib = C.CDLL(_build.LIB)
+    _lib = declare(C.CDLL(_build.LIB))
+    return _lib
+
+
+def use_library(path):
+    """Point the wrapper at another build of the oracle (the planted-mistake
+    tests load mutated copies); returns the previous library handle."""
+    global _lib
+    prev = _lib
+    _lib = declare(C.CDLL(path)) if isinstance(path, str) else path
+    return prev
+
+
+def declare(lib):
     P = C.c_void_p
     lib.ref_forward.argtypes = [C.POINTER(_Set), C.c_int64, P, P, P, P, P, C.c_int32,
                                 C.POINTER(_Cam), P, P, P, P, C.POINTER(P)]
@@ -55,7 +68,6 @@ def load():
     lib.ref_quat_to_rotmat.argtypes = [P, P]
     lib.ref_sh_basis.argtypes = [C.c_int32, P, P]
     lib.ref_sh_basis_grad.argtypes = [C.c_int32, P, P]
-    _lib = lib
     return lib
 
 

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cstdarg>
+#include <map>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -51,6 +52,10 @@ int loss_blocks_x(int64_t max_hw);
 void launch_loss_l1(hipStream_t, int, int, const FrameDesc*, const float*, const float*,
                     const float*, const float*, float, double*, float*, float*, float*, float*,
                     float*);
+// adam.hip
+void launch_adam(hipStream_t, uint64_t, uint64_t, float*, const float*, float*, float*, float*,
+                 const float*, float*, float*, int, float*, const float*, float*, float*, float,
+                 float, float, float, float, float, int32_t*);
 }  // namespace gsr
 
 using namespace gsr;
@@ -87,6 +92,8 @@ struct gsr_context {
   DBuf keys_a, vals_a, keys_b, vals_b, partial, stamp, grad2d;
   DBuf ranges, nproc, t_final, n_last, frames, twist_part, loss_part, loss_scale;
   DBuf up_rgb, up_depth, up_alpha;  // upstream gradients for gsr_step_l1
+  DBuf tune_out;                    // scratch outputs of the autotuner
+  std::map<std::string, gsr_settings> tune_cache;
   uint64_t key_cap = 0;             // allocated key slots
   // pinned host staging
   FrameDesc* h_frames = nullptr;
@@ -287,7 +294,7 @@ gsr_status gsr_destroy(gsr_context* ctx) {
                   &ctx->grad2d,
                   &ctx->stamp, &ctx->ranges, &ctx->nproc, &ctx->t_final, &ctx->n_last,
                   &ctx->frames, &ctx->twist_part, &ctx->loss_part, &ctx->loss_scale,
-                  &ctx->up_rgb, &ctx->up_depth, &ctx->up_alpha};
+                  &ctx->up_rgb, &ctx->up_depth, &ctx->up_alpha, &ctx->tune_out};
   for (DBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (ctx->h_frames) (void)hipHostFree(ctx->h_frames);
@@ -569,6 +576,114 @@ gsr_status gsr_step_l1(gsr_context* ctx, const gsr_settings* s, int64_t n, const
   return gsr_backward(ctx, P<float>(ctx->up_rgb), P<float>(ctx->up_depth),
                       P<float>(ctx->up_alpha), g_means, g_log_scales, g_quats, g_opac, g_sh,
                       g_twist, stream);
+}
+
+gsr_status gsr_autotune(gsr_context* ctx, const gsr_settings* base, int64_t n, const float* means,
+                        const float* log_scales, const float* quats, const float* opac,
+                        const float* sh, int32_t F, const gsr_camera* cams, const float* poses,
+                        const float* target_rgb, const float* target_depth, float depth_weight,
+                        int32_t reps, int32_t force, gsr_settings* chosen, float* ms_out,
+                        void* stream) {
+  static const int kShapes[5][2] = {{16, 16}, {8, 8}, {32, 8}, {16, 8}, {32, 16}};
+  if (!ctx || !base || !chosen || !cams || F < 1) return GSR_ERR_INVALID_ARGUMENT;
+  if (reps < 1) reps = 1;
+  hipStream_t st = (hipStream_t)stream;
+  GSR_HIP(hipSetDevice(ctx->device));
+  // cache key: frame sizes, n rounded up to a power of two, SH degree
+  std::string key = "d" + std::to_string(base->sh_degree) + ":n";
+  int64_t nb = 1;
+  while (nb < n) nb <<= 1;
+  key += std::to_string(nb);
+  for (int f = 0; f < F; ++f)
+    key += ":" + std::to_string(cams[f].width) + "x" + std::to_string(cams[f].height);
+  if (!force) {
+    auto it = ctx->tune_cache.find(key);
+    if (it != ctx->tune_cache.end()) {
+      *chosen = it->second;
+      if (ms_out)
+        for (int i = 0; i < 5; ++i) ms_out[i] = -1.0f;
+      return GSR_OK;
+    }
+  }
+  int64_t npx = 0;
+  for (int f = 0; f < F; ++f) npx += (int64_t)cams[f].width * cams[f].height;
+  const int nbasis = (base->sh_degree + 1) * (base->sh_degree + 1);
+  // scratch: rgb 3P, depth P, alpha P, loss 1, grads 3n + 3n + 4n + n + 3 nb n, twist 6F
+  const size_t floats = (size_t)5 * npx + 1 + (size_t)n * (11 + 3 * nbasis) + 6 * F + 64;
+  gsr_status rc = ensure(ctx, ctx->tune_out, floats * 4, st);
+  if (rc) return rc;
+  float* o = P<float>(ctx->tune_out);
+  float *rgb = o, *depth = rgb + 3 * npx, *alpha = depth + npx, *loss = alpha + npx;
+  float *gm = loss + 1, *gl = gm + 3 * n, *gq = gl + 3 * n, *go = gq + 4 * n;
+  float *gsh = go + n, *gt = gsh + 3 * nbasis * n;
+  hipEvent_t e0, e1;
+  GSR_HIP(hipEventCreate(&e0));
+  GSR_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  gsr_settings best_s = *base;
+  for (int i = 0; i < 5; ++i) {
+    gsr_settings s = *base;
+    s.tile_w = kShapes[i][0];
+    s.tile_h = kShapes[i][1];
+    s.key_capacity = 0;
+    s.flags &= ~(uint32_t)(GSR_FLAG_TIMING | GSR_FLAG_COUNT_PAIRS);
+    rc = gsr_step_l1(ctx, &s, n, means, log_scales, quats, opac, sh, F, cams, poses, target_rgb,
+                     target_depth, depth_weight, rgb, depth, alpha, loss, gm, gl, gq, go, gsh, gt,
+                     stream);
+    if (rc) break;
+    s.key_capacity = (int64_t)(ctx->s.K + ctx->s.K / 20 + 1024);
+    std::vector<float> t(reps);
+    for (int r = 0; r < reps && !rc; ++r) {
+      GSR_HIP(hipEventRecord(e0, st));
+      rc = gsr_step_l1(ctx, &s, n, means, log_scales, quats, opac, sh, F, cams, poses,
+                       target_rgb, target_depth, depth_weight, rgb, depth, alpha, loss, gm, gl,
+                       gq, go, gsh, gt, stream);
+      GSR_HIP(hipEventRecord(e1, st));
+      GSR_HIP(hipEventSynchronize(e1));
+      GSR_HIP(hipEventElapsedTime(&t[r], e0, e1));
+    }
+    if (rc) break;
+    if ((rc = gsr_check_overflow(ctx, stream))) break;
+    std::sort(t.begin(), t.end());
+    const float med = t[reps / 2];
+    if (ms_out) ms_out[i] = med;
+    if (med < best) {
+      best = med;
+      best_s = s;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  ctx->s.valid = false;  // the scratch outputs are not the caller's
+  *chosen = best_s;
+  ctx->tune_cache[key] = best_s;
+  return GSR_OK;
+}
+
+gsr_status gsr_adam_step(gsr_context* ctx, int64_t n, int32_t sh_degree, float* means,
+                         const float* g_means, float* m_means, float* v_means, float* sh,
+                         const float* g_sh, float* m_sh, float* v_sh, int32_t F, float* poses,
+                         const float* g_twist, float* m_twist, float* v_twist, float lr_means,
+                         float lr_sh, float lr_pose, float beta1, float beta2, float eps,
+                         int32_t* step, void* stream) {
+  if (!ctx) return GSR_ERR_INVALID_ARGUMENT;
+  if (n < 0 || F < 0 || F > 1024 || sh_degree < 0 || sh_degree > 3 || !step)
+    return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "adam: bad sizes or NULL step");
+  if (n > 0 && (!means || !g_means || !m_means || !v_means || !sh || !g_sh || !m_sh || !v_sh))
+    return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "adam: Gaussian buffer is NULL");
+  if (F > 0 && (!poses || !g_twist || !m_twist || !v_twist))
+    return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "adam: pose buffer is NULL");
+  if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps >= 0.0f))
+    return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "adam: bad hyper-parameters");
+  hipStream_t st = (hipStream_t)stream;
+  GSR_HIP(hipSetDevice(ctx->device));
+  const uint64_t nb = (uint64_t)(sh_degree + 1) * (sh_degree + 1);
+  launch_adam(st, (uint64_t)n * 3, (uint64_t)n * nb * 3, means, g_means, m_means, v_means, sh,
+              g_sh, m_sh, v_sh, F, poses, g_twist, m_twist, v_twist, lr_means, lr_sh, lr_pose,
+              beta1, beta2, eps, step);
+  GSR_HIP(hipGetLastError());
+  return GSR_OK;
 }
 
 gsr_status gsr_check_overflow(gsr_context* ctx, void* stream) {

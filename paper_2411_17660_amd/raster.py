@@ -125,6 +125,39 @@ class Rasterizer:
         self.n, self.F, self.sh_degree = n, len(cams), sh_degree
         self.sizes = [(int(c[0]), int(c[1])) for c in cams]
 
+    def autotune(self, means, log_scales, quats, opacity, sh, poses, cams, sh_degree,
+                 target_rgb, target_depth, depth_weight, background=(0.0, 0.0, 0.0), reps=3,
+                 force=False):
+        """Measure every tile shape on these inputs; returns (tile, key_capacity,
+        {tile: median ms})."""
+        base = native.make_settings(sh_degree, background)
+        chosen = native.Settings()
+        ms = (C.c_float * len(native.TILE_SHAPES))()
+        cams_c = native.make_cameras(cams)
+        self._check(self.lib.gsr_autotune(
+            self.h, C.byref(base), int(means.shape[0]), _ptr(means), _ptr(log_scales),
+            _ptr(quats), _ptr(opacity), _ptr(sh), len(cams), cams_c, _ptr(poses),
+            _ptr(target_rgb), _ptr(target_depth), float(depth_weight), int(reps), int(force),
+            C.byref(chosen), ms, _stream()))
+        times = {t: ms[i] for i, t in enumerate(native.TILE_SHAPES)}
+        return (chosen.tile_w, chosen.tile_h), chosen.key_capacity, times
+
+    def adam_step(self, params, grads, state, lr_means=1.6e-4, lr_sh=5e-3, lr_pose=1e-3,
+                  beta1=0.9, beta2=0.999, eps=1e-15):
+        """Fused Adam on means, SH and pose twists with the pose fold.
+        params: dict(means, sh, poses); grads: dict(means, sh, twist);
+        state: dict(m_means, v_means, m_sh, v_sh, m_twist, v_twist, step)."""
+        n = int(params["means"].shape[0])
+        deg = int(round((params["sh"].shape[1]) ** 0.5)) - 1
+        F = int(params["poses"].shape[0])
+        p, g, s = params, grads, state
+        self._check(self.lib.gsr_adam_step(
+            self.h, n, deg, _ptr(p["means"]), _ptr(g["means"]), _ptr(s["m_means"]),
+            _ptr(s["v_means"]), _ptr(p["sh"]), _ptr(g["sh"]), _ptr(s["m_sh"]), _ptr(s["v_sh"]),
+            F, _ptr(p["poses"]), _ptr(g["twist"]), _ptr(s["m_twist"]), _ptr(s["v_twist"]),
+            float(lr_means), float(lr_sh), float(lr_pose), float(beta1), float(beta2),
+            float(eps), C.c_void_p(s["step"].data_ptr()), _stream()))
+
     def timings(self):
         """{stage: (total ms, launches)} of the timed calls since the last read."""
         ms = (C.c_double * len(native.STAGES))()

@@ -355,3 +355,128 @@ def test_graph_captured_step_replays_match_eager(rast):
         step(cap)
         torch.cuda.synchronize()
     r.check_overflow()
+
+
+def test_autotuner_picks_a_measured_shape_with_identical_images(rast):
+    import torch
+    from paper_2411_17660_amd import native
+    from gpu_util import to_dev
+    sc = scenes.tiny_scene(seed=13, n=4000, W=200, H=120, f=150.0, n_frames=2)
+    d = to_dev(sc)
+    P = sc.n_pixels
+    rng = np.random.default_rng(13)
+    t_rgb = torch.from_numpy(rng.uniform(0, 1, 3 * P).astype(np.float32)).cuda()
+    t_dep = torch.from_numpy(rng.uniform(0.5, 4, P).astype(np.float32)).cuda()
+    tile, cap, times = rast.autotune(d["means"], d["log_scales"], d["quats"], d["opacity"],
+                                     d["sh"], d["poses"], sc.cams, sc.sh_degree, t_rgb, t_dep,
+                                     0.5, background=sc.background, reps=2, force=True)
+    assert tile in native.TILE_SHAPES and cap > 0
+    assert all(t > 0 for t in times.values())
+    assert times[tile] == min(times.values())
+    tile2, _, times2 = rast.autotune(d["means"], d["log_scales"], d["quats"], d["opacity"],
+                                     d["sh"], d["poses"], sc.cams, sc.sh_degree, t_rgb, t_dep,
+                                     0.5, background=sc.background)
+    assert tile2 == tile and all(t < 0 for t in times2.values())  # cached
+    _, a16, _, _ = gpu_forward(rast, sc, (16, 16))
+    _, at, _, _ = gpu_forward(rast, sc, tile, key_capacity=cap)
+    rast.check_overflow()
+    assert np.array_equal(a16.cpu().numpy(), at.cpu().numpy())
+
+
+# ---------------------------------------------------------------------- optimiser
+def test_adam_step_matches_oracle(rast):
+    import torch
+    rng = np.random.default_rng(21)
+    n, K, F = 5000, 16, 4
+    sc = scenes.tiny_scene(seed=21, n=n, n_frames=F)
+    means = sc.means.astype(np.float32)
+    sh = sc.sh.astype(np.float32)
+    poses = sc.poses.astype(np.float32)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()  # noqa: E731
+    p = dict(means=dev(means), sh=dev(sh), poses=dev(poses))
+    st = dict(m_means=torch.zeros(n, 3, device="cuda"), v_means=torch.zeros(n, 3, device="cuda"),
+              m_sh=torch.zeros(n, K, 3, device="cuda"), v_sh=torch.zeros(n, K, 3, device="cuda"),
+              m_twist=torch.zeros(F, 6, device="cuda"), v_twist=torch.zeros(F, 6, device="cuda"),
+              step=torch.zeros(1, dtype=torch.int32, device="cuda"))
+    ref_p = dict(means=means.astype(np.float64), sh=sh.astype(np.float64),
+                 poses=poses.astype(np.float64))
+    ref_s = {k: np.zeros(v.shape) for k, v in st.items() if k != "step"}
+    for t in range(1, 4):
+        gm = rng.normal(size=(n, 3)).astype(np.float32)
+        gs = rng.normal(size=(n, K, 3)).astype(np.float32)
+        gt = (rng.normal(size=(F, 6)) * 10).astype(np.float32)
+        rast.adam_step(p, dict(means=dev(gm), sh=dev(gs), twist=dev(gt)), st)
+        oracle.adam_update(ref_p["means"], gm.astype(np.float64), ref_s["m_means"],
+                           ref_s["v_means"], t, 1.6e-4)
+        oracle.adam_update(ref_p["sh"], gs.astype(np.float64), ref_s["m_sh"], ref_s["v_sh"], t,
+                           5e-3)
+        xi = np.zeros((F, 6))
+        oracle.adam_update(xi, gt.astype(np.float64), ref_s["m_twist"], ref_s["v_twist"], t,
+                           1e-3)
+        ref_p["poses"] = np.stack([oracle.fold_pose(ref_p["poses"][f], xi[f]) for f in range(F)])
+    torch.cuda.synchronize()
+    assert int(st["step"].item()) == 3
+    np.testing.assert_allclose(p["means"].cpu().numpy(), ref_p["means"], rtol=0, atol=2e-6)
+    np.testing.assert_allclose(p["sh"].cpu().numpy(), ref_p["sh"], rtol=0, atol=2e-6)
+    np.testing.assert_allclose(p["poses"].cpu().numpy(), ref_p["poses"], rtol=0, atol=2e-6)
+
+
+def test_mapping_loop_reduces_loss_like_the_oracle(rast):
+    """A short C5-style loop (L1 rgb + 0.1 L1 depth, Adam on means, SH and
+    poses) from perturbed parameters towards targets the oracle rendered from
+    the ground truth: the HIP loop and an FP64 oracle loop take the same steps
+    while their gradients' signs agree, and both reduce the loss."""
+    import torch
+    from gpu_util import to_dev
+    gt = scenes.tiny_scene(seed=31, n=1500, W=96, H=64, f=70.0, n_frames=3, sh_degree=3)
+    ref_t = oracle.forward(gt, threads=oracle_threads())
+    t_rgb = ref_t.rgb_flat.astype(np.float32)
+    t_dep = ref_t.depth_flat.astype(np.float32)
+    rng = np.random.default_rng(31)
+    sc = scenes.Scene(gt.means + rng.normal(0, 0.01, gt.means.shape).astype(np.float32),
+                      gt.log_scales, gt.quats, gt.opacity, gt.sh, 3, gt.cams,
+                      gt.poses.copy(), gt.background)
+    d = to_dev(sc)
+    n, K, F, P = sc.n, 16, sc.n_frames, sc.n_pixels
+    st = dict(m_means=torch.zeros(n, 3, device="cuda"), v_means=torch.zeros(n, 3, device="cuda"),
+              m_sh=torch.zeros(n, K, 3, device="cuda"), v_sh=torch.zeros(n, K, 3, device="cuda"),
+              m_twist=torch.zeros(F, 6, device="cuda"), v_twist=torch.zeros(F, 6, device="cuda"),
+              step=torch.zeros(1, dtype=torch.int32, device="cuda"))
+    b = dict(rgb=torch.empty(3 * P, device="cuda"), depth=torch.empty(P, device="cuda"),
+             alpha=torch.empty(P, device="cuda"), loss=torch.empty(1, device="cuda"),
+             means=torch.empty(n, 3, device="cuda"), log_scales=torch.empty(n, 3, device="cuda"),
+             quats=torch.empty(n, 4, device="cuda"), opacity=torch.empty(n, device="cuda"),
+             sh=torch.empty(n, K, 3, device="cuda"), twist=torch.empty(F, 6, device="cuda"))
+    trgb, tdep = torch.from_numpy(t_rgb).cuda(), torch.from_numpy(t_dep).cuda()
+    losses = []
+    for it in range(20):
+        rast.step_l1(d["means"], d["log_scales"], d["quats"], d["opacity"], d["sh"], d["poses"],
+                     sc.cams, 3, trgb, tdep, 0.1, b, background=sc.background)
+        losses.append(b["loss"].item())
+        rast.adam_step(dict(means=d["means"], sh=d["sh"], poses=d["poses"]),
+                       dict(means=b["means"], sh=b["sh"], twist=b["twist"]), st)
+    torch.cuda.synchronize()
+    # the oracle loop from the same start
+    import copy
+    o = copy.copy(sc)
+    o.means = sc.means.astype(np.float64).copy()
+    o.sh = sc.sh.astype(np.float64).copy()
+    o.poses = sc.poses.astype(np.float64).copy()
+    ost = {k: np.zeros(v.shape) for k, v in st.items() if k != "step"}
+    sizes = [(int(c[0]), int(c[1])) for c in sc.cams]
+    olosses = []
+    for it in range(20):
+        r = oracle.forward(o, f64=True, threads=oracle_threads())
+        L, gr, gd, ga = oracle.loss_l1(r.rgb_flat, r.depth_flat, t_rgb, t_dep, 0.1, sizes)
+        olosses.append(L)
+        g = r.backward(gr, gd, ga)
+        oracle.adam_update(o.means, g["means"], ost["m_means"], ost["v_means"], it + 1, 1.6e-4)
+        oracle.adam_update(o.sh, g["sh"], ost["m_sh"], ost["v_sh"], it + 1, 5e-3)
+        xi = np.zeros((F, 6))
+        oracle.adam_update(xi, g["twist"], ost["m_twist"], ost["v_twist"], it + 1, 1e-3)
+        o.poses = np.stack([oracle.fold_pose(o.poses[f], xi[f]) for f in range(F)])
+    print(f"[loop] gpu loss {losses[0]:.6f} -> {losses[-1]:.6f}; "
+          f"oracle {olosses[0]:.6f} -> {olosses[-1]:.6f}", flush=True)
+    assert abs(losses[0] - olosses[0]) <= 1e-5 * olosses[0]
+    assert losses[-1] < 0.9 * losses[0] and olosses[-1] < 0.9 * olosses[0]
+    assert abs(losses[-1] - olosses[-1]) <= 0.05 * olosses[-1]

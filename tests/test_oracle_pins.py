@@ -343,3 +343,34 @@ def test_tile_shape_does_not_change_outputs():
         assert np.array_equal(r.depth_flat, base.depth_flat)
         assert np.array_equal(r.alpha_flat, base.alpha_flat)
         _grads_equal(gb, r.backward(*G), tol=1e-12)
+
+
+# ------------------------------------------------------------------ optimiser
+def test_se3_exp_matches_matrix_exponential():
+    """Exp(xi) of the pose fold equals expm of the 4x4 twist matrix."""
+    from scipy.linalg import expm
+    rng = np.random.default_rng(3)
+    for scale in (1e-9, 1e-3, 0.3, 2.0):
+        xi = rng.normal(size=6) * scale
+        R, t = oracle.se3_exp(xi)
+        rho, phi = xi[:3], xi[3:]
+        X = np.zeros((4, 4))
+        X[:3, :3] = [[0, -phi[2], phi[1]], [phi[2], 0, -phi[0]], [-phi[1], phi[0], 0]]
+        X[:3, 3] = rho
+        E = expm(X)
+        np.testing.assert_allclose(R, E[:3, :3], atol=1e-12)
+        np.testing.assert_allclose(t, E[:3, 3], atol=1e-12)
+
+
+def test_adam_first_steps_closed_form():
+    """Step 1 moves each parameter by -lr g/(|g| + eps); a constant gradient
+    keeps the bias-corrected ratio at g/|g| on later steps."""
+    g = np.array([3.0, -0.5, 1e-3, -2e-7])
+    p = np.zeros(4)
+    m = np.zeros(4)
+    v = np.zeros(4)
+    oracle.adam_update(p, g, m, v, 1, lr=0.1, eps=1e-15)
+    np.testing.assert_allclose(p, -0.1 * g / (np.abs(g) + 1e-15), rtol=1e-12)
+    for t in range(2, 6):
+        oracle.adam_update(p, g, m, v, t, lr=0.1, eps=0.0)
+    np.testing.assert_allclose(p, -0.1 * g / (np.abs(g) + 1e-15) - 0.4 * np.sign(g), rtol=1e-12)

@@ -48,7 +48,20 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--n", type=int, default=500_000)
+    ap.add_argument("--copy-kernel", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (counter calibration)")
     args = ap.parse_args()
+    if args.copy_kernel:
+        import torch
+        n = args.copy_kernel // 4
+        src = torch.ones(n, device="cuda")
+        dst = torch.empty(n, device="cuda")
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n * 4, "launches": 3}))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU; the rasterizer shards over keyframes "
               "across GPUs only by design (no multi-GPU path is built), so --gpus must be 1",

@@ -338,9 +338,24 @@ static void build_record(const ref_state* st, int f, int64_t g, rec_t* r) {
   r->x_hi = (int32_t)(xb < Wm1 ? xb : Wm1);
   r->y_lo = (int32_t)(ya > 0.0 ? ya : 0.0);
   r->y_hi = (int32_t)(yb < Hm1 ? yb : Hm1);
+  /* Tile rect: tiles of the square clipped to the bounding box of the region
+   * where alpha can reach A_MIN, {q <= Qa}, Qa = 2 ln(opacity / A_MIN); its
+   * half-widths are sqrt(Qa s_xx), sqrt(Qa s_yy).  Pixels outside it have
+   * alpha < A_MIN and are skipped anyway, so the images are unchanged; a
+   * Gaussian that can reach A_MIN at no pixel of its square is culled. */
+  const double Qa = 2.0 * log(r->opacity / A_MIN) * (1.0 + 1e-9);
+  if (!(Qa > 0.0)) return;
+  const double hx = sqrt(Qa * r->cov[0]), hy = sqrt(Qa * r->cov[2]);
+  const double ba = ceil(r->u - hx), bb = floor(r->u + hx);
+  const double ca = ceil(r->v - hy), cb = floor(r->v + hy);
+  const int32_t bx_lo = ba > (double)r->x_lo ? (int32_t)ba : r->x_lo;
+  const int32_t bx_hi = bb < (double)r->x_hi ? (int32_t)bb : r->x_hi;
+  const int32_t by_lo = ca > (double)r->y_lo ? (int32_t)ca : r->y_lo;
+  const int32_t by_hi = cb < (double)r->y_hi ? (int32_t)cb : r->y_hi;
+  if (!(bx_lo <= bx_hi && by_lo <= by_hi)) return;
   const int tw = st->set.tile_w, th = st->set.tile_h;
-  r->tx_lo = r->x_lo / tw; r->tx_hi = r->x_hi / tw;
-  r->ty_lo = r->y_lo / th; r->ty_hi = r->y_hi / th;
+  r->tx_lo = bx_lo / tw; r->tx_hi = bx_hi / tw;
+  r->ty_lo = by_lo / th; r->ty_hi = by_hi / th;
   r->n_tiles = (r->tx_hi - r->tx_lo + 1) * (r->ty_hi - r->ty_lo + 1);
   /* depth key: fp32(z), round to nearest even, compared as IEEE bits */
   float zf = (float)tz;

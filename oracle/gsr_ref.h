@@ -89,6 +89,8 @@ int64_t ref_pairs_evaluated(const ref_state* st); /* (pixel, entry) square hits 
 
 /* Per record r = f*n + g:
  * ints[r*10 + :] = keep, x_lo, x_hi, y_lo, y_hi, tx_lo, tx_hi, ty_lo, ty_hi, n_tiles
+ *   (x/y: the 3-sigma pixel square; tx/ty: the tile rect, the tiles of the
+ *   square clipped to the bounding box of {alpha >= 1/255})
  * depth_bits[r]  = bits of fp32(z) (0 when culled)
  * vals[r*20 + :] = u, v, z, A, B, C, s_xx, s_xy, s_yy, lambda_max, radius,
  *                  opacity, c_r, c_g, c_b, raw_r, raw_g, raw_b, det, tz */

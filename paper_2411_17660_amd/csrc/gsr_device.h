@@ -47,6 +47,9 @@ struct alignas(16) Record {
 };
 static_assert(sizeof(Record) == 64, "record layout");
 
+// A record's tile rect (trect[r]): tx0 | tx1 << 16, ty0 | ty1 << 16, the tiles
+// of the square clipped to the region where alpha can reach 1/255.
+
 // Gradient of one (tile, entry) key: du, dv, dSigma'_xx, dSigma'_xy, dSigma'_yy
 // (symmetric-matrix gradient), dopacity, dc0..2, dz
 constexpr int kNG = 10;

@@ -61,7 +61,8 @@ struct Proj {
   bool keep;
   double t[3], u, v, J[6], Sc[9], cov[3], det;
   int clamp_x, clamp_y;
-  int32_t x_lo, x_hi, y_lo, y_hi;
+  int32_t x_lo, x_hi, y_lo, y_hi;      // 3-sigma pixel square
+  int32_t bx_lo, bx_hi, by_lo, by_hi;  // its part that can reach alpha >= 1/255
 };
 
 __device__ __forceinline__ void load_pose(const float* __restrict__ poses, int f, double W[9],
@@ -141,6 +142,20 @@ __device__ __forceinline__ void project(const FrameDesc& fr, const double W[9],
   p.x_hi = (int32_t)(xb < Wm1 ? xb : Wm1);
   p.y_lo = (int32_t)(ya > 0.0 ? ya : 0.0);
   p.y_hi = (int32_t)(yb < Hm1 ? yb : Hm1);
+  // Tile rect: the square clipped to the bounding box of {q <= Qa}, the region
+  // where alpha can reach 1/255, Qa = 2 ln(opacity / (1/255)); half-widths
+  // sqrt(Qa s_xx), sqrt(Qa s_yy).  Outside it alpha < 1/255, so dropping
+  // those tiles leaves the images unchanged.
+  const double Qa = 2.0 * log(G.opacity / (double)kAlphaMin) * (1.0 + 1e-9);
+  if (!(Qa > 0.0)) return;
+  const double hx = sqrt(Qa * p.cov[0]), hy = sqrt(Qa * p.cov[2]);
+  const double ba = ceil(p.u - hx), bb = floor(p.u + hx);
+  const double ca = ceil(p.v - hy), cb = floor(p.v + hy);
+  p.bx_lo = ba > (double)p.x_lo ? (int32_t)ba : p.x_lo;
+  p.bx_hi = bb < (double)p.x_hi ? (int32_t)bb : p.x_hi;
+  p.by_lo = ca > (double)p.y_lo ? (int32_t)ca : p.y_lo;
+  p.by_hi = cb < (double)p.y_hi ? (int32_t)cb : p.y_hi;
+  if (!(p.bx_lo <= p.bx_hi && p.by_lo <= p.by_hi)) return;
   p.keep = true;
 }
 
@@ -230,8 +245,9 @@ __global__ void __launch_bounds__(256) preprocess_fwd_kernel(
     const float* __restrict__ poses, const float* __restrict__ means,
     const float* __restrict__ log_scales, const float* __restrict__ quats,
     const float* __restrict__ opac, const float* __restrict__ sh, int tile_w,
-    int tile_h, Record* __restrict__ rec, uint32_t* __restrict__ depth_key,
-    uint32_t* __restrict__ rec_id, uint32_t* __restrict__ ntiles) {
+    int tile_h, Record* __restrict__ rec, uint2* __restrict__ trect,
+    uint32_t* __restrict__ depth_key, uint32_t* __restrict__ rec_id,
+    uint32_t* __restrict__ ntiles) {
 #pragma clang fp contract(off)
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
@@ -252,9 +268,11 @@ __global__ void __launch_bounds__(256) preprocess_fwd_kernel(
       ntiles[r] = 0;
       continue;
     }
-    const int tx0 = p.x_lo / tile_w, tx1 = p.x_hi / tile_w;
-    const int ty0 = p.y_lo / tile_h, ty1 = p.y_hi / tile_h;
+    const int tx0 = p.bx_lo / tile_w, tx1 = p.bx_hi / tile_w;
+    const int ty0 = p.by_lo / tile_h, ty1 = p.by_hi / tile_h;
     ntiles[r] = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+    trect[r] = make_uint2((uint32_t)tx0 | ((uint32_t)tx1 << 16),
+                          (uint32_t)ty0 | ((uint32_t)ty1 << 16));
     const float zf = (float)p.t[2];
     depth_key[r] = __float_as_uint(zf);
     double dir[3];
@@ -568,14 +586,14 @@ __global__ void __launch_bounds__(256) twist_reduce_kernel(const double* __restr
 void launch_preprocess_fwd(hipStream_t st, int64_t n, int F, const FrameDesc* frames,
                            const float* poses, const float* means, const float* log_scales,
                            const float* quats, const float* opac, const float* sh, int deg,
-                           int tile_w, int tile_h, Record* rec, uint32_t* depth_key,
-                           uint32_t* rec_id, uint32_t* ntiles) {
+                           int tile_w, int tile_h, Record* rec, uint2* trect,
+                           uint32_t* depth_key, uint32_t* rec_id, uint32_t* ntiles) {
   if (n <= 0) return;
   const dim3 grid((unsigned)((n + 255) / 256));
 #define GSR_PRE_FWD(D)                                                                      \
   hipLaunchKernelGGL(preprocess_fwd_kernel<D>, grid, dim3(256), 0, st, n, F, frames, poses, \
-                     means, log_scales, quats, opac, sh, tile_w, tile_h, rec, depth_key,    \
-                     rec_id, ntiles)
+                     means, log_scales, quats, opac, sh, tile_w, tile_h, rec, trect,        \
+                     depth_key, rec_id, ntiles)
   switch (deg) {
     case 0: GSR_PRE_FWD(0); break;
     case 1: GSR_PRE_FWD(1); break;

@@ -249,7 +249,7 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
 __global__ void __launch_bounds__(256) keygen_kernel(
     uint64_t m, const uint32_t* __restrict__ perm, const uint32_t* __restrict__ ntiles,
     const uint64_t* __restrict__ offsets, Record* __restrict__ rec,
-    const FrameDesc* __restrict__ frames, int tile_w, int tile_h, uint64_t capacity,
+    const uint2* __restrict__ trect, const FrameDesc* __restrict__ frames, uint64_t capacity,
     uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, uint32_t* __restrict__ overflow) {
   __shared__ uint64_t s_off[4][kWave];
   __shared__ uint32_t s_r[4][kWave], s_w[4][kWave], s_gx[4][kWave], s_base[4][kWave];
@@ -267,8 +267,9 @@ __global__ void __launch_bounds__(256) keygen_kernel(
     if (cnt) {
       Record& o = rec[r];
       const FrameDesc fr = frames[o.frame];
-      const int tx0 = (o.sqx & 0xffff) / tile_w, tx1 = (o.sqx >> 16) / tile_w;
-      const int ty0 = (o.sqy & 0xffff) / tile_h;
+      const uint2 tr = trect[r];
+      const int tx0 = tr.x & 0xffff, tx1 = tr.x >> 16;
+      const int ty0 = tr.y & 0xffff;
       s_w[w][lane] = (uint32_t)(tx1 - tx0 + 1);
       s_gx[w][lane] = (uint32_t)fr.grid_x;
       s_base[w][lane] = (uint32_t)(fr.tile_offset + ty0 * fr.grid_x + tx0);
@@ -396,12 +397,12 @@ void launch_offsets_scan(hipStream_t st, const uint32_t* ntiles, const uint32_t*
 }
 
 void launch_keygen(hipStream_t st, uint64_t m, const uint32_t* perm, const uint32_t* ntiles,
-                   const uint64_t* offsets, Record* rec, const FrameDesc* frames, int tile_w,
-                   int tile_h, uint64_t capacity, uint32_t* keys, uint32_t* vals,
+                   const uint64_t* offsets, Record* rec, const uint2* trect,
+                   const FrameDesc* frames, uint64_t capacity, uint32_t* keys, uint32_t* vals,
                    uint32_t* overflow) {
   if (m == 0) return;
   hipLaunchKernelGGL(keygen_kernel, dim3(blocks_for(m, 256)), dim3(256), 0, st, m, perm, ntiles,
-                     offsets, rec, frames, tile_w, tile_h, capacity, keys, vals, overflow);
+                     offsets, rec, trect, frames, capacity, keys, vals, overflow);
 }
 
 void launch_ranges(hipStream_t st, const uint32_t* keys, const uint64_t* k_dev, uint64_t k_max,

@@ -96,6 +96,22 @@ def project(scene, f):
                 depth_bits=depth_bits, cov=S2)
 
 
+def visible(scene, f, p=None):
+    """Per Gaussian: does alpha reach 1/255 at some pixel of its square?"""
+    p = p if p is not None else project(scene, f)
+    out = np.zeros(len(p["keep"]), bool)
+    for g in np.nonzero(p["keep"])[0]:
+        xs = np.arange(p["x_lo"][g], p["x_hi"][g] + 1)
+        ys = np.arange(p["y_lo"][g], p["y_hi"][g] + 1)
+        dx = p["u"][g] - xs[None, :]
+        dy = p["v"][g] - ys[:, None]
+        Q = p["conic"][g]
+        q = Q[0, 0] * dx * dx + 2 * Q[0, 1] * dx * dy + Q[1, 1] * dy * dy
+        a = np.minimum(A_MAX, p["opacity"][g] * np.exp(-0.5 * q))
+        out[g] = bool((a >= A_MIN).any())
+    return out
+
+
 def render(scene):
     """Per frame (rgb [3,H,W], depth [H,W], alpha [H,W]) by brute force."""
     out = []

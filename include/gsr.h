@@ -214,7 +214,9 @@ gsr_status gsr_debug_timings(gsr_context* ctx, double* ms, int64_t* calls);
  * `stream`); any pointer may be NULL.  Record r = f*n + g:
  *   ntiles [n*F]     tiles covered (0 = culled)
  *   depth_key [n*F]  bits of fp32(z) (0xffffffff = culled)
- *   square [n*F*2]   x_lo | x_hi << 16, y_lo | y_hi << 16 (kept records)
+ *   square [n*F*2]   pixel bounds of kept records, x_lo | x_hi << 16,
+ *                    y_lo | y_hi << 16: the 3-sigma square clipped to the
+ *                    box where alpha can reach 1/255
  *   tile_keys [K], tile_vals [K]  sorted global tile ids and record ids
  *   ranges [T*2]     [start, end) of each tile in the sorted keys
  *   n_last [P]       per pixel, list position after its last blended entry

@@ -36,12 +36,15 @@
 #define LOWPASS 0.3
 #define JGUARD 1.3
 #define EXTENT 3.0
-/* Relative half-width of the threshold-sensitivity bands. */
+/* Relative half-width of the threshold-sensitivity bands (minimum), and the
+ * FP32 unit roundoff used to widen them where FP32 evaluation is worse. */
 #define BAND 1e-4
+#define EPS32 5.9604644775390625e-08
 
 typedef struct {
   int keep;
   int32_t x_lo, x_hi, y_lo, y_hi;
+  int32_t bx_lo, bx_hi, by_lo, by_hi; /* square clipped to the alpha box */
   int32_t tx_lo, tx_hi, ty_lo, ty_hi, n_tiles;
   uint32_t depth_bits;
   double t[3];
@@ -348,14 +351,14 @@ static void build_record(const ref_state* st, int f, int64_t g, rec_t* r) {
   const double hx = sqrt(Qa * r->cov[0]), hy = sqrt(Qa * r->cov[2]);
   const double ba = ceil(r->u - hx), bb = floor(r->u + hx);
   const double ca = ceil(r->v - hy), cb = floor(r->v + hy);
-  const int32_t bx_lo = ba > (double)r->x_lo ? (int32_t)ba : r->x_lo;
-  const int32_t bx_hi = bb < (double)r->x_hi ? (int32_t)bb : r->x_hi;
-  const int32_t by_lo = ca > (double)r->y_lo ? (int32_t)ca : r->y_lo;
-  const int32_t by_hi = cb < (double)r->y_hi ? (int32_t)cb : r->y_hi;
-  if (!(bx_lo <= bx_hi && by_lo <= by_hi)) return;
+  r->bx_lo = ba > (double)r->x_lo ? (int32_t)ba : r->x_lo;
+  r->bx_hi = bb < (double)r->x_hi ? (int32_t)bb : r->x_hi;
+  r->by_lo = ca > (double)r->y_lo ? (int32_t)ca : r->y_lo;
+  r->by_hi = cb < (double)r->y_hi ? (int32_t)cb : r->y_hi;
+  if (!(r->bx_lo <= r->bx_hi && r->by_lo <= r->by_hi)) return;
   const int tw = st->set.tile_w, th = st->set.tile_h;
-  r->tx_lo = bx_lo / tw; r->tx_hi = bx_hi / tw;
-  r->ty_lo = by_lo / th; r->ty_hi = by_hi / th;
+  r->tx_lo = r->bx_lo / tw; r->tx_hi = r->bx_hi / tw;
+  r->ty_lo = r->by_lo / th; r->ty_hi = r->by_hi / th;
   r->n_tiles = (r->tx_hi - r->tx_lo + 1) * (r->ty_hi - r->ty_lo + 1);
   /* depth key: fp32(z), round to nearest even, compared as IEEE bits */
   float zf = (float)tz;
@@ -422,17 +425,27 @@ static int walk_pixel(const ref_state* st, int f, int px, int py, blend_t* out,
     const int32_t g = st->tile_g[k];
     const rec_t* r = &base[g];
     if (px < r->x_lo || px > r->x_hi || py < r->y_lo || py > r->y_hi) continue;
-    ++*hits;
+    /* work statistic: pixels inside the alpha box (the only ones that can pass) */
+    if (px >= r->bx_lo && px <= r->bx_hi && py >= r->by_lo && py <= r->by_hi) ++*hits;
     const double dx = r->u - (double)px, dy = r->v - (double)py;
     const double q = r->conic[0] * dx * dx + 2.0 * r->conic[1] * dx * dy +
                      r->conic[2] * dy * dy;
     const double G = exp(-0.5 * q);
     const double araw = r->opacity * G;
     const double a = araw < A_MAX ? araw : A_MAX;
-    if (fabs(a - A_MIN) < BAND * A_MIN) fl |= REF_FLAG_ALPHA_BAND;
+    /* Sensitivity bands: the larger of BAND and the FP32 error bound of the
+     * quantity, relative.  An FP32 evaluation of q errs by up to a few
+     * eps32 * (A dx^2 + 2|B dx dy| + C dy^2), which exceeds q by the
+     * anisotropy of elongated Gaussians; alpha inherits half of it.  T after
+     * n blends carries up to ~n eps32. */
+    const double qabs = r->conic[0] * dx * dx + 2.0 * fabs(r->conic[1] * dx * dy) +
+                        r->conic[2] * dy * dy;
+    const double band_a = fmax(BAND, 8.0 * EPS32 * qabs);
+    if (fabs(a - A_MIN) < band_a * A_MIN) fl |= REF_FLAG_ALPHA_BAND;
     if (a < A_MIN) continue;
     const double Tn = T * (1.0 - a);
-    if (fabs(Tn - T_MIN) < BAND * T_MIN) fl |= REF_FLAG_T_BAND;
+    const double band_t = fmax(BAND, 4.0 * EPS32 * (double)(nb + 1));
+    if (fabs(Tn - T_MIN) < band_t * T_MIN) fl |= REF_FLAG_T_BAND;
     if (Tn < T_MIN) break;
     if (fabs(araw - A_MAX) < BAND * A_MAX) fl |= REF_FLAG_CLAMP_BAND;
     const double w = a * T;
@@ -937,9 +950,10 @@ void ref_records(const ref_state* st, int32_t* ints, uint32_t* depth_bits, doubl
   for (int64_t r = 0; r < M; ++r) {
     const rec_t* q = &st->rec[r];
     if (ints) {
-      int32_t* o = &ints[r * 10];
+      int32_t* o = &ints[r * 14];
       o[0] = q->keep; o[1] = q->x_lo; o[2] = q->x_hi; o[3] = q->y_lo; o[4] = q->y_hi;
       o[5] = q->tx_lo; o[6] = q->tx_hi; o[7] = q->ty_lo; o[8] = q->ty_hi; o[9] = q->n_tiles;
+      o[10] = q->bx_lo; o[11] = q->bx_hi; o[12] = q->by_lo; o[13] = q->by_hi;
     }
     if (depth_bits) depth_bits[r] = q->keep ? q->depth_bits : 0u;
     if (vals) {

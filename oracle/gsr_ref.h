@@ -48,8 +48,10 @@ typedef struct {
 
 /* Per-pixel flag bits: pixels whose discrete decisions sit so close to a
  * threshold that FP32 rounding on another implementation may flip them. */
-#define REF_FLAG_ALPHA_BAND 1u   /* some evaluated entry has |a - A_MIN| < 1e-4 A_MIN   */
-#define REF_FLAG_T_BAND 2u       /* some blend candidate has |T' - T_MIN| < 1e-4 T_MIN  */
+#define REF_FLAG_ALPHA_BAND 1u   /* some evaluated entry has |a - A_MIN| < b_a A_MIN,
+                                    b_a = max(1e-4, 8 eps32 (A dx^2 + 2|B dx dy| + C dy^2)) */
+#define REF_FLAG_T_BAND 2u       /* some blend candidate has |T' - T_MIN| < b_t T_MIN,
+                                    b_t = max(1e-4, 4 eps32 (blended so far + 1))      */
 #define REF_FLAG_CLAMP_BAND 4u   /* some blended entry has |s G - A_MAX| < 1e-4 A_MAX   */
 
 typedef struct ref_state ref_state;
@@ -85,12 +87,13 @@ void ref_free(ref_state* st);
 int64_t ref_num_keys(const ref_state* st);
 int64_t ref_num_tiles(const ref_state* st);
 int64_t ref_num_pixels(const ref_state* st);
-int64_t ref_pairs_evaluated(const ref_state* st); /* (pixel, entry) square hits */
+int64_t ref_pairs_evaluated(const ref_state* st); /* (pixel, entry) alpha-box hits */
 
 /* Per record r = f*n + g:
- * ints[r*10 + :] = keep, x_lo, x_hi, y_lo, y_hi, tx_lo, tx_hi, ty_lo, ty_hi, n_tiles
- *   (x/y: the 3-sigma pixel square; tx/ty: the tile rect, the tiles of the
- *   square clipped to the bounding box of {alpha >= 1/255})
+ * ints[r*14 + :] = keep, x_lo, x_hi, y_lo, y_hi, tx_lo, tx_hi, ty_lo, ty_hi, n_tiles,
+ *                   bx_lo, bx_hi, by_lo, by_hi
+ *   (x/y: the 3-sigma pixel square; bx/by: the square clipped to the
+ *   bounding box of {alpha >= 1/255}; tx/ty: the tiles of bx/by)
  * depth_bits[r]  = bits of fp32(z) (0 when culled)
  * vals[r*20 + :] = u, v, z, A, B, C, s_xx, s_xy, s_yy, lambda_max, radius,
  *                  opacity, c_r, c_g, c_b, raw_r, raw_g, raw_b, det, tz */

@@ -178,7 +178,7 @@ class RefForward:
 
     def records(self):
         M = self.n * self.F
-        ints = np.zeros((M, 10), np.int32)
+        ints = np.zeros((M, 14), np.int32)
         bits = np.zeros(M, np.uint32)
         vals = np.zeros((M, 20))
         if M:
@@ -187,7 +187,8 @@ class RefForward:
                  "opacity", "c0", "c1", "c2", "raw0", "raw1", "raw2", "det", "tz"]
         d = {nm: vals[:, i] for i, nm in enumerate(names)}
         for i, nm in enumerate(["keep", "x_lo", "x_hi", "y_lo", "y_hi", "tx_lo", "tx_hi",
-                                "ty_lo", "ty_hi", "n_tiles"]):
+                                "ty_lo", "ty_hi", "n_tiles", "bx_lo", "bx_hi", "by_lo",
+                                "by_hi"]):
             d[nm] = ints[:, i]
         d["depth_bits"] = bits
         return d

@@ -36,19 +36,21 @@ struct FrameDesc {
 //  - the conic in completed-square form q = (a1 dx + a2 dy)^2 + (a3 dy)^2,
 //    a1 = sqrt(A), a2 = B / sqrt(A), a3 = sqrt(C - B^2/A) = 1/sqrt(s_yy):
 //    both terms are non-negative, so anisotropic Gaussians do not cancel;
-//  - the 3-sigma pixel square, 16 bits per bound.
+//  - the pixel bounds, 16 bits each: the 3-sigma square clipped to the box
+//    where alpha can reach 1/255 (outside it alpha < 1/255).
 struct alignas(16) Record {
   float u_hi, u_lo, v_hi, v_lo;
   float a1, a2, a3, opacity;
   float c0, c1, c2, z;
   uint32_t sqx, sqy;      // lo | hi << 16
-  uint32_t key_offset;    // first key slot of the record (keygen)
-  uint32_t frame;
+  uint32_t reserved0, reserved1;
 };
 static_assert(sizeof(Record) == 64, "record layout");
 
 // A record's tile rect (trect[r]): tx0 | tx1 << 16, ty0 | ty1 << 16, the tiles
-// of the square clipped to the region where alpha can reach 1/255.
+// of the square clipped to the region where alpha can reach 1/255.  keyoff[r]
+// is the first key slot of record r (written by keygen; all-ones if the
+// record overflowed a fixed key capacity).
 
 // Gradient of one (tile, entry) key: du, dv, dSigma'_xx, dSigma'_xy, dSigma'_yy
 // (symmetric-matrix gradient), dopacity, dc0..2, dz

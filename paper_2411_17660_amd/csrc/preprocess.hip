@@ -297,10 +297,12 @@ __global__ void __launch_bounds__(256) preprocess_fwd_kernel(
     o.c1 = (float)(c1 > 0.0 ? c1 : 0.0);
     o.c2 = (float)(c2 > 0.0 ? c2 : 0.0);
     o.z = zf;
-    o.sqx = (uint32_t)p.x_lo | ((uint32_t)p.x_hi << 16);
-    o.sqy = (uint32_t)p.y_lo | ((uint32_t)p.y_hi << 16);
-    o.key_offset = 0;
-    o.frame = (uint32_t)f;
+    // pixel bounds tested per pixel: the square clipped to the alpha box
+    // (outside it alpha < 1/255, so the contribution rule is unchanged)
+    o.sqx = (uint32_t)p.bx_lo | ((uint32_t)p.bx_hi << 16);
+    o.sqy = (uint32_t)p.by_lo | ((uint32_t)p.by_hi << 16);
+    o.reserved0 = 0;
+    o.reserved1 = 0;
     rec[r] = o;
   }
 }
@@ -312,10 +314,10 @@ __global__ void __launch_bounds__(256) preprocess_fwd_kernel(
 // keys behind every pixel's stop and are skipped.  Lane sums are FP64 and the
 // group combines them with a fixed butterfly, so the result is deterministic.
 // --------------------------------------------------------------------------
-constexpr int kSlotGroup = 16;
+constexpr int kSlotGroup = 8;
 
 __global__ void __launch_bounds__(256) slot_reduce_kernel(
-    uint64_t m, const Record* __restrict__ rec, const uint32_t* __restrict__ ntiles,
+    uint64_t m, const uint32_t* __restrict__ keyoff, const uint32_t* __restrict__ ntiles,
     const float* __restrict__ partial, const uint32_t* __restrict__ stamp,
     const uint32_t* __restrict__ epoch_dev, uint64_t key_capacity,
     float* __restrict__ grad2d /* [m][kNG] */) {
@@ -325,16 +327,16 @@ __global__ void __launch_bounds__(256) slot_reduce_kernel(
   const int sub = threadIdx.x & (kSlotGroup - 1);
   const bool active = r < m;
   uint32_t cnt = active ? ntiles[r] : 0u;
-  const uint32_t off = cnt ? rec[r].key_offset : 0u;
+  const uint32_t off = cnt ? keyoff[r] : 0u;
   if (cnt && (uint64_t)off + cnt > key_capacity) cnt = 0;  // overflowed in keygen
-  double acc[kNG];
+  float acc[kNG];
 #pragma unroll
-  for (int j = 0; j < kNG; ++j) acc[j] = 0.0;
+  for (int j = 0; j < kNG; ++j) acc[j] = 0.0f;
   for (uint32_t s = sub; s < cnt; s += kSlotGroup) {
     if (stamp[off + s] != epoch) continue;
     const float* pp = partial + (size_t)(off + s) * kNG;
 #pragma unroll
-    for (int j = 0; j < kNG; ++j) acc[j] += (double)pp[j];
+    for (int j = 0; j < kNG; ++j) acc[j] += pp[j];
   }
 #pragma unroll
   for (int o = kSlotGroup / 2; o > 0; o >>= 1)
@@ -342,13 +344,19 @@ __global__ void __launch_bounds__(256) slot_reduce_kernel(
     for (int j = 0; j < kNG; ++j) acc[j] += __shfl_xor(acc[j], o, kSlotGroup);
   if (!active) return;
   if (cnt == 0) {
-    if (sub < kNG) grad2d[r * kNG + sub] = 0.0f;
+    for (int j = sub; j < kNG; j += kSlotGroup) grad2d[r * kNG + j] = 0.0f;
     return;
   }
-  double v = acc[0];
+  float v = acc[0];
 #pragma unroll
   for (int j = 1; j < kNG; ++j) v = sub == j ? acc[j] : v;
-  if (sub < kNG) grad2d[r * kNG + sub] = (float)v;
+  if (sub < kNG) grad2d[r * kNG + sub] = v;
+  if (sub + kSlotGroup < kNG) {  // values 8, 9
+    float v2 = acc[kSlotGroup];
+#pragma unroll
+    for (int j = kSlotGroup + 1; j < kNG; ++j) v2 = sub + kSlotGroup == j ? acc[j] : v2;
+    grad2d[r * kNG + sub + kSlotGroup] = v2;
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -608,7 +616,7 @@ int64_t preprocess_bwd_waves(int64_t n) { return ((n + 255) / 256) * 4; }
 void launch_preprocess_bwd(hipStream_t st, int64_t n, int F, const FrameDesc* frames,
                            const float* poses, const float* means, const float* log_scales,
                            const float* quats, const float* opac, const float* sh, int deg,
-                           const Record* rec, const uint32_t* ntiles, const float* partial,
+                           const uint32_t* keyoff, const uint32_t* ntiles, const float* partial,
                            const uint32_t* stamp, const uint32_t* epoch, uint64_t key_capacity,
                            float* grad2d, float* g_means, float* g_log_scales, float* g_quats,
                            float* g_opac, float* g_sh, double* twist_partial, float* g_twist) {
@@ -621,7 +629,7 @@ void launch_preprocess_bwd(hipStream_t st, int64_t n, int F, const FrameDesc* fr
     const uint64_t m = (uint64_t)n * F;
     const uint64_t threads = m * kSlotGroup;
     hipLaunchKernelGGL(slot_reduce_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0,
-                       st, m, rec, ntiles, partial, stamp, epoch, key_capacity, grad2d);
+                       st, m, keyoff, ntiles, partial, stamp, epoch, key_capacity, grad2d);
     switch (deg) {
       case 0: GSR_PRE_BWD(0); break;
       case 1: GSR_PRE_BWD(1); break;

@@ -201,7 +201,7 @@ __global__ void __launch_bounds__(64) composite_bwd_kernel(
     int n_tiles, int n_frames, const FrameDesc* __restrict__ frames,
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals,
     const Record* __restrict__ rec, const uint2* __restrict__ trect,
-    const uint32_t* __restrict__ tile_nproc, float bg0,
+    const uint32_t* __restrict__ keyoff, const uint32_t* __restrict__ tile_nproc, float bg0,
     float bg1, float bg2, const float* __restrict__ g_rgb, const float* __restrict__ g_depth,
     const float* __restrict__ g_alpha, const float* __restrict__ t_final,
     const int32_t* __restrict__ n_last, float* __restrict__ partial,
@@ -254,7 +254,7 @@ __global__ void __launch_bounds__(64) composite_bwd_kernel(
       sm[lane] = R;
       const uint2 tr = trect[r];
       const int rx0 = tr.x & 0xffff, rx1 = tr.x >> 16, ry0 = tr.y & 0xffff;
-      slot[lane] = R.key_offset + (uint32_t)((ty - ry0) * (rx1 - rx0 + 1) + (tx - rx0));
+      slot[lane] = keyoff[r] + (uint32_t)((ty - ry0) * (rx1 - rx0 + 1) + (tx - rx0));
     }
     __syncthreads();
     for (int j = hi - lo - 1; j >= 0; --j) {
@@ -348,13 +348,13 @@ static void launch_fwd_t(hipStream_t st, int n_tiles, int F, const FrameDesc* fr
 template <int TW, int TH>
 static void launch_bwd_t(hipStream_t st, int n_tiles, int F, const FrameDesc* frames,
                          const uint2* ranges, const uint32_t* vals, const Record* rec,
-                         const uint2* trect, const uint32_t* nproc, const float* bg, const float* g_rgb,
+                         const uint2* trect, const uint32_t* keyoff, const uint32_t* nproc, const float* bg, const float* g_rgb,
                          const float* g_depth, const float* g_alpha, const float* t_final,
                          const int32_t* n_last, float* partial, uint32_t* stamp,
                          const uint32_t* epoch, bool remap) {
   const unsigned grid = remap ? (unsigned)(((n_tiles + 7) / 8) * 8) : (unsigned)n_tiles;
   hipLaunchKernelGGL((composite_bwd_kernel<TW, TH>), dim3(grid), dim3(kWave), 0, st, n_tiles, F,
-                     frames, ranges, vals, rec, trect, nproc, bg[0], bg[1], bg[2], g_rgb,
+                     frames, ranges, vals, rec, trect, keyoff, nproc, bg[0], bg[1], bg[2], g_rgb,
                      g_depth, g_alpha, t_final, n_last, partial, stamp, epoch, remap ? 1 : 0);
 }
 
@@ -382,15 +382,15 @@ void launch_composite_fwd(hipStream_t st, int tw, int th, int n_tiles, int F,
 
 void launch_composite_bwd(hipStream_t st, int tw, int th, int n_tiles, int F,
                           const FrameDesc* frames, const uint2* ranges, const uint32_t* vals,
-                          const Record* rec, const uint2* trect, const uint32_t* nproc,
-                          const float* bg,
+                          const Record* rec, const uint2* trect, const uint32_t* keyoff,
+                          const uint32_t* nproc, const float* bg,
                           const float* g_rgb, const float* g_depth, const float* g_alpha,
                           const float* t_final, const int32_t* n_last, float* partial,
                           uint32_t* stamp, const uint32_t* epoch, bool remap) {
   if (n_tiles <= 0) return;
 #define GSR_BWD(W, H)                                                                          \
-  launch_bwd_t<W, H>(st, n_tiles, F, frames, ranges, vals, rec, trect, nproc, bg, g_rgb,     \
-                     g_depth, g_alpha, t_final, n_last, partial, stamp, epoch, remap)
+  launch_bwd_t<W, H>(st, n_tiles, F, frames, ranges, vals, rec, trect, keyoff, nproc, bg,    \
+                     g_rgb, g_depth, g_alpha, t_final, n_last, partial, stamp, epoch, remap)
   if (tw == 16 && th == 16) GSR_BWD(16, 16);
   else if (tw == 8 && th == 8) GSR_BWD(8, 8);
   else if (tw == 32 && th == 8) GSR_BWD(32, 8);

@@ -21,7 +21,7 @@ void launch_preprocess_fwd(hipStream_t, int64_t, int, const FrameDesc*, const fl
 int64_t preprocess_bwd_waves(int64_t n);
 void launch_preprocess_bwd(hipStream_t, int64_t, int, const FrameDesc*, const float*,
                            const float*, const float*, const float*, const float*, const float*,
-                           int, const Record*, const uint32_t*, const float*, const uint32_t*,
+                           int, const uint32_t*, const uint32_t*, const float*, const uint32_t*,
                            const uint32_t*, uint64_t, float*, float*, float*, float*, float*,
                            float*, double*, float*);
 void launch_bump_epoch(hipStream_t, uint32_t*);
@@ -33,9 +33,9 @@ bool launch_radix_sort(hipStream_t, uint32_t*, uint32_t*, uint32_t*, uint32_t*, 
                        uint64_t, int, uint32_t*, uint32_t*);
 void launch_offsets_scan(hipStream_t, const uint32_t*, const uint32_t*, uint64_t, uint64_t*,
                          uint64_t*, uint64_t*);
-void launch_keygen(hipStream_t, uint64_t, const uint32_t*, const uint32_t*, const uint64_t*,
-                   Record*, const uint2*, const FrameDesc*, uint64_t, uint32_t*, uint32_t*,
-                   uint32_t*);
+void launch_keygen(hipStream_t, uint64_t, uint64_t, const uint32_t*, const uint32_t*,
+                   const uint64_t*, uint32_t*, const uint2*, const FrameDesc*, uint64_t,
+                   uint32_t*, uint32_t*, uint32_t*);
 void launch_ranges(hipStream_t, const uint32_t*, const uint64_t*, uint64_t, uint64_t, uint2*,
                    uint64_t);
 // raster.hip
@@ -45,7 +45,7 @@ void launch_composite_fwd(hipStream_t, int, int, int, int, const FrameDesc*, con
                           float*, int32_t*, uint32_t*, bool, unsigned long long*);
 void launch_composite_bwd(hipStream_t, int, int, int, int, const FrameDesc*, const uint2*,
                           const uint32_t*, const Record*, const uint2*, const uint32_t*,
-                          const float*,
+                          const uint32_t*, const float*,
                           const float*, const float*, const float*, const float*,
                           const int32_t*, float*, uint32_t*, const uint32_t*, bool);
 // loss.hip
@@ -89,7 +89,7 @@ struct gsr_context {
   int device = 0;
   std::string err;
   // workspace
-  DBuf rec, trect, dkey_a, dval_a, dkey_b, dval_b, ntiles, offsets, scan_tmp, hist, counters;
+  DBuf rec, trect, keyoff, dkey_a, dval_a, dkey_b, dval_b, ntiles, offsets, scan_tmp, hist, counters;
   DBuf keys_a, vals_a, keys_b, vals_b, partial, stamp, grad2d;
   DBuf ranges, nproc, t_final, n_last, frames, twist_part, loss_part, loss_scale;
   DBuf up_rgb, up_depth, up_alpha;  // upstream gradients for gsr_step_l1
@@ -289,7 +289,7 @@ gsr_status gsr_destroy(gsr_context* ctx) {
   if (!ctx) return GSR_ERR_INVALID_ARGUMENT;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
-  DBuf* bufs[] = {&ctx->rec, &ctx->trect, &ctx->dkey_a, &ctx->dval_a, &ctx->dkey_b, &ctx->dval_b,
+  DBuf* bufs[] = {&ctx->rec, &ctx->trect, &ctx->keyoff, &ctx->dkey_a, &ctx->dval_a, &ctx->dkey_b, &ctx->dval_b,
                   &ctx->ntiles, &ctx->offsets, &ctx->scan_tmp, &ctx->hist, &ctx->counters,
                   &ctx->keys_a, &ctx->vals_a, &ctx->keys_b, &ctx->vals_b, &ctx->partial,
                   &ctx->grad2d,
@@ -346,6 +346,7 @@ gsr_status gsr_forward(gsr_context* ctx, const gsr_settings* s, int64_t n, const
   // workspace sized by M, T, P
   if ((rc = ensure(ctx, ctx->rec, M * sizeof(Record), st))) return rc;
   if ((rc = ensure(ctx, ctx->trect, M * sizeof(uint2), st))) return rc;
+  if ((rc = ensure(ctx, ctx->keyoff, M * 4, st))) return rc;
   if ((rc = ensure(ctx, ctx->dkey_a, M * 4, st))) return rc;
   if ((rc = ensure(ctx, ctx->dval_a, M * 4, st))) return rc;
   if ((rc = ensure(ctx, ctx->dkey_b, M * 4, st))) return rc;
@@ -425,8 +426,9 @@ gsr_status gsr_forward(gsr_context* ctx, const gsr_settings* s, int64_t n, const
   // A3 keygen
   {
     StageTimer t(ctx, st, timing, GSR_STAGE_KEYGEN);
-    launch_keygen(st, M, perm, P<uint32_t>(ctx->ntiles), P<uint64_t>(ctx->offsets),
-                  P<Record>(ctx->rec), P<uint2>(ctx->trect), P<FrameDesc>(ctx->frames), use_cap,
+    launch_keygen(st, M, (uint64_t)n, perm, P<uint32_t>(ctx->ntiles), P<uint64_t>(ctx->offsets),
+                  P<uint32_t>(ctx->keyoff), P<uint2>(ctx->trect), P<FrameDesc>(ctx->frames),
+                  use_cap,
                   P<uint32_t>(ctx->keys_a), P<uint32_t>(ctx->vals_a), d_overflow);
   }
   // A4 stable sort by tile id
@@ -511,7 +513,8 @@ gsr_status gsr_backward(gsr_context* ctx, const float* g_rgb, const float* g_dep
     StageTimer t(ctx, st, timing, GSR_STAGE_COMPOSITE_BWD);
     launch_composite_bwd(st, s.tile_w, s.tile_h, (int)sv.T, sv.F, P<FrameDesc>(ctx->frames),
                          P<uint2>(ctx->ranges), svals, P<Record>(ctx->rec),
-                         P<uint2>(ctx->trect), P<uint32_t>(ctx->nproc), s.background, g_rgb,
+                         P<uint2>(ctx->trect), P<uint32_t>(ctx->keyoff),
+                         P<uint32_t>(ctx->nproc), s.background, g_rgb,
                          g_depth, g_alpha,
                          P<float>(ctx->t_final), P<int32_t>(ctx->n_last),
                          P<float>(ctx->partial), P<uint32_t>(ctx->stamp), d_epoch, remap);
@@ -525,7 +528,7 @@ gsr_status gsr_backward(gsr_context* ctx, const float* g_rgb, const float* g_dep
     StageTimer t(ctx, st, timing, GSR_STAGE_PREPROCESS_BWD);
     launch_preprocess_bwd(st, sv.n, sv.F, P<FrameDesc>(ctx->frames), sv.poses, sv.means,
                           sv.log_scales, sv.quats, sv.opac, sv.sh, s.sh_degree,
-                          P<Record>(ctx->rec), P<uint32_t>(ctx->ntiles), P<float>(ctx->partial),
+                          P<uint32_t>(ctx->keyoff), P<uint32_t>(ctx->ntiles), P<float>(ctx->partial),
                           P<uint32_t>(ctx->stamp), d_epoch, ctx->key_cap,
                           P<float>(ctx->grad2d), g_means, g_log_scales, g_quats, g_opac, g_sh,
                           P<double>(ctx->twist_part), g_twist);

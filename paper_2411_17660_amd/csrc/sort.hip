@@ -247,9 +247,10 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
 // so every store instruction writes 64 consecutive keys.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) keygen_kernel(
-    uint64_t m, const uint32_t* __restrict__ perm, const uint32_t* __restrict__ ntiles,
-    const uint64_t* __restrict__ offsets, Record* __restrict__ rec,
-    const uint2* __restrict__ trect, const FrameDesc* __restrict__ frames, uint64_t capacity,
+    uint64_t m, uint64_t n, const uint32_t* __restrict__ perm,
+    const uint32_t* __restrict__ ntiles, const uint64_t* __restrict__ offsets,
+    uint32_t* __restrict__ keyoff, const uint2* __restrict__ trect,
+    const FrameDesc* __restrict__ frames, uint64_t capacity,
     uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, uint32_t* __restrict__ overflow) {
   __shared__ uint64_t s_off[4][kWave];
   __shared__ uint32_t s_r[4][kWave], s_w[4][kWave], s_gx[4][kWave], s_base[4][kWave];
@@ -265,8 +266,7 @@ __global__ void __launch_bounds__(256) keygen_kernel(
     off = offsets[i];
     s_r[w][lane] = r;
     if (cnt) {
-      Record& o = rec[r];
-      const FrameDesc fr = frames[o.frame];
+      const FrameDesc fr = frames[r / n];
       const uint2 tr = trect[r];
       const int tx0 = tr.x & 0xffff, tx1 = tr.x >> 16;
       const int ty0 = tr.y & 0xffff;
@@ -275,7 +275,7 @@ __global__ void __launch_bounds__(256) keygen_kernel(
       s_base[w][lane] = (uint32_t)(fr.tile_offset + ty0 * fr.grid_x + tx0);
       const bool ovf = off + cnt > capacity;
       s_ovf[w][lane] = ovf ? 1 : 0;
-      o.key_offset = ovf ? 0xffffffffu : (uint32_t)off;
+      keyoff[r] = ovf ? 0xffffffffu : (uint32_t)off;
       if (ovf) atomicOr(overflow, 1u);
     }
   }
@@ -396,13 +396,13 @@ void launch_offsets_scan(hipStream_t st, const uint32_t* ntiles, const uint32_t*
                      0, st, ld, (const uint64_t*)nullptr, m, block_tmp, offsets);
 }
 
-void launch_keygen(hipStream_t st, uint64_t m, const uint32_t* perm, const uint32_t* ntiles,
-                   const uint64_t* offsets, Record* rec, const uint2* trect,
-                   const FrameDesc* frames, uint64_t capacity, uint32_t* keys, uint32_t* vals,
-                   uint32_t* overflow) {
+void launch_keygen(hipStream_t st, uint64_t m, uint64_t n, const uint32_t* perm,
+                   const uint32_t* ntiles, const uint64_t* offsets, uint32_t* keyoff,
+                   const uint2* trect, const FrameDesc* frames, uint64_t capacity,
+                   uint32_t* keys, uint32_t* vals, uint32_t* overflow) {
   if (m == 0) return;
-  hipLaunchKernelGGL(keygen_kernel, dim3(blocks_for(m, 256)), dim3(256), 0, st, m, perm, ntiles,
-                     offsets, rec, trect, frames, capacity, keys, vals, overflow);
+  hipLaunchKernelGGL(keygen_kernel, dim3(blocks_for(m, 256)), dim3(256), 0, st, m, n, perm,
+                     ntiles, offsets, keyoff, trect, frames, capacity, keys, vals, overflow);
 }
 
 void launch_ranges(hipStream_t st, const uint32_t* keys, const uint64_t* k_dev, uint64_t k_max,

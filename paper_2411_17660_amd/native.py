@@ -60,6 +60,12 @@ def load(path=LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built; run paper_2411_17660_amd/build.py "
                           "(the rasterizer has no non-HIP fallback)")
+    # PyTorch ships its own HIP runtime; load it first so that libgsr binds to
+    # that same runtime (same soname) instead of pulling in a second one.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(path)
     V, I64, I32, F32 = C.c_void_p, C.c_int64, C.c_int32, C.c_float
     S = C.c_int32

@@ -51,10 +51,10 @@ def check_forward(rast, sc, tile=(16, 16), lists=True, label=""):
         assert np.array_equal(L["ntiles"] > 0, keep)
         assert np.array_equal(L["ntiles"].astype(np.int64), rec["n_tiles"].astype(np.int64))
         sq = L["square"].reshape(-1, 2)
-        assert np.array_equal((sq[keep, 0] & 0xffff), rec["x_lo"][keep])
-        assert np.array_equal((sq[keep, 0] >> 16), rec["x_hi"][keep])
-        assert np.array_equal((sq[keep, 1] & 0xffff), rec["y_lo"][keep])
-        assert np.array_equal((sq[keep, 1] >> 16), rec["y_hi"][keep])
+        assert np.array_equal((sq[keep, 0] & 0xffff), rec["bx_lo"][keep])
+        assert np.array_equal((sq[keep, 0] >> 16), rec["bx_hi"][keep])
+        assert np.array_equal((sq[keep, 1] & 0xffff), rec["by_lo"][keep])
+        assert np.array_equal((sq[keep, 1] >> 16), rec["by_hi"][keep])
         assert np.array_equal(L["depth_key"][keep], rec["depth_bits"][keep])
         assert np.all(L["depth_key"][~keep] == 0xffffffff)
         assert L["K"] == ref.K

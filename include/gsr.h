@@ -225,6 +225,14 @@ gsr_status gsr_debug_lists(gsr_context* ctx, uint32_t* ntiles, uint32_t* depth_k
                            uint32_t* square, uint32_t* tile_keys, uint32_t* tile_vals,
                            uint32_t* ranges, int32_t* n_last, float* t_final, void* stream);
 
+/* Copies the per-record screen-space gradients of the last backward,
+ * [n*F][10] doubles, record r = f*n + g: dL/du, dL/dv, dL/dSigma'_xx,
+ * dL/dSigma'_xy, dL/dSigma'_yy (gradient of the symmetric 2x2 projected
+ * covariance, off-diagonal counted once), dL/dopacity (of alpha =
+ * opacity * G), dL/dcolour[3], dL/dz.  Synchronises `stream`;
+ * GSR_ERR_STATE before the first backward. */
+gsr_status gsr_debug_grad2d(gsr_context* ctx, double* out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

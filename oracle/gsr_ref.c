@@ -82,6 +82,7 @@ struct ref_state {
   double* t_final;     /* P */
   int64_t pairs;
   uint64_t hash;
+  double* g2d; /* F*n x 10 screen-space gradients of the last backward, or NULL */
 };
 
 /* ------------------------------------------------------------------ */
@@ -754,6 +755,9 @@ int ref_backward(ref_state* st, const double* g_rgb, const double* g_depth,
   }
   for (int t = 1; t < nthr; ++t)
     for (int64_t i = 0; i < M * NG2; ++i) acc[i] += acc[(size_t)t * M * NG2 + i];
+  free(st->g2d);
+  st->g2d = (double*)malloc(sizeof(double) * (size_t)(M > 0 ? M : 1) * NG2);
+  if (st->g2d && M > 0) memcpy(st->g2d, acc, sizeof(double) * (size_t)M * NG2);
 
   /* step 8: chain rule per record, summed over frames per Gaussian */
   double* twist_thr = (double*)calloc((size_t)nthr * F * 6, sizeof(double));
@@ -935,7 +939,7 @@ void ref_free(ref_state* st) {
   free(st->means); free(st->log_scales); free(st->quats); free(st->opac); free(st->sh);
   free(st->rec); free(st->tile_off); free(st->grid_x); free(st->pix_off);
   free(st->tile_start); free(st->tile_g);
-  free(st->flags); free(st->n_last); free(st->t_final);
+  free(st->flags); free(st->n_last); free(st->t_final); free(st->g2d);
   free(st);
 }
 
@@ -972,6 +976,13 @@ void ref_records(const ref_state* st, int32_t* ints, uint32_t* depth_bits, doubl
 void ref_tile_lists(const ref_state* st, int64_t* tile_start, int32_t* entries) {
   if (tile_start) memcpy(tile_start, st->tile_start, sizeof(int64_t) * (st->T + 1));
   if (entries && st->K > 0) memcpy(entries, st->tile_g, sizeof(int32_t) * st->K);
+}
+
+int ref_screen_grads(const ref_state* st, double* out) {
+  if (!st || !st->g2d) return REF_ERR_STATE;
+  const int64_t M = (int64_t)st->F * st->n;
+  if (M > 0) memcpy(out, st->g2d, sizeof(double) * (size_t)M * NG2);
+  return REF_OK;
 }
 
 void ref_pixel_info(const ref_state* st, uint8_t* flags, int32_t* n_last, double* t_final) {

@@ -105,6 +105,11 @@ void ref_tile_lists(const ref_state* st, int64_t* tile_start, int32_t* entries);
  * blended entry of the pixel's tile list), T_final. */
 void ref_pixel_info(const ref_state* st, uint8_t* flags, int32_t* n_last,
                     double* t_final);
+/* Screen-space gradients of every record accumulated by the last
+ * ref_backward, [F*n][10]: dL/du, dL/dv, dL/dA, dL/dB, dL/dC (conic
+ * q = A dx^2 + 2 B dx dy + C dy^2), dL/dopacity (of alpha = opacity G),
+ * dL/dcolour[3], dL/dz.  Returns REF_ERR_STATE before the first backward. */
+int ref_screen_grads(const ref_state* st, double* out);
 /* Hash of every discrete decision (squares, tile lists, per-pixel blended
  * sets and stop positions, clamp states). */
 uint64_t ref_decision_hash(const ref_state* st);

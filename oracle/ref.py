@@ -65,6 +65,8 @@ def declare(lib):
     lib.ref_tile_lists.restype = None
     lib.ref_pixel_info.argtypes = [P, P, P, P]
     lib.ref_pixel_info.restype = None
+    lib.ref_screen_grads.argtypes = [P, P]
+    lib.ref_screen_grads.restype = C.c_int
     lib.ref_quat_to_rotmat.argtypes = [P, P]
     lib.ref_sh_basis.argtypes = [C.c_int32, P, P]
     lib.ref_sh_basis_grad.argtypes = [C.c_int32, P, P]
@@ -157,6 +159,15 @@ class RefForward:
                               _p(out["sh"]), _p(out["twist"]))
         if rc != 0:
             raise ValueError(f"oracle backward failed with status {rc}")
+        return out
+
+    def screen_grads(self):
+        """[F*n, 10] screen-space gradients of the last backward: d/du, d/dv,
+        d/dA, d/dB, d/dC of the conic, d/dopacity, d/dcolour (3), d/dz."""
+        out = np.zeros((self.n * self.F, 10))
+        rc = load().ref_screen_grads(self._st, _p(out))
+        if rc != 0:
+            raise ValueError(f"no backward has run (status {rc})")
         return out
 
     # ---- debug artefacts ----

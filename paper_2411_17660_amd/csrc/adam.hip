@@ -12,7 +12,7 @@
 // with bias-corrected moments m, v and an iteration counter held in device
 // memory (incremented by the kernel, so a captured iteration advances it on
 // every replay).  The pose fold is FP64.
-#include "gsr_device.h"
+#include "launch.h"
 
 namespace gsr {
 

@@ -1,0 +1,70 @@
+// launch.h -- host-side launchers of the kernels, shared by the sources that
+// define them and by runtime.hip, which sequences them.  Internal to
+// libgsr.so; every launcher enqueues on `st` and returns without waiting.
+#pragma once
+#include "gsr_device.h"
+
+namespace gsr {
+
+// preprocess.hip: EWA projection, records, per-record reduction, chain rule
+void launch_preprocess_fwd(hipStream_t st, int64_t n, int F, const FrameDesc* frames,
+                           const float* poses, const float* means, const float* log_scales,
+                           const float* quats, const float* opac, const float* sh, int deg,
+                           int tile_w, int tile_h, Record* rec, uint2* trect,
+                           uint32_t* depth_key, uint32_t* rec_id, uint32_t* ntiles);
+int64_t preprocess_bwd_waves(int64_t n);
+void launch_preprocess_bwd(hipStream_t st, int64_t n, int F, const FrameDesc* frames,
+                           const float* poses, const float* means, const float* log_scales,
+                           const float* quats, const float* opac, const float* sh, int deg,
+                           const uint32_t* keyoff, const uint32_t* ntiles, const double* partial,
+                           const uint32_t* stamp, const uint32_t* epoch, uint64_t key_capacity,
+                           double* grad2d, float* g_means, float* g_log_scales, float* g_quats,
+                           float* g_opac, float* g_sh, double* twist_partial, float* g_twist);
+void launch_bump_epoch(hipStream_t st, uint32_t* epoch);
+
+// sort.hip: depth sort, offsets, key generation, tile sort, ranges
+void launch_fill_u32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t v);
+size_t radix_hist_elems(uint64_t n_max);
+size_t scan_block_elems(uint64_t n_max);
+bool launch_radix_sort(hipStream_t st, uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b,
+                       uint32_t* vals_b, const uint64_t* n_dev, uint64_t n_max, int bits,
+                       uint32_t* hist, uint32_t* scan_tmp);
+void launch_offsets_scan(hipStream_t st, const uint32_t* ntiles, const uint32_t* perm,
+                         uint64_t m, uint64_t* offsets, uint64_t* block_tmp, uint64_t* total);
+void launch_keygen(hipStream_t st, uint64_t m, uint64_t n, const uint32_t* perm,
+                   const uint32_t* ntiles, const uint64_t* offsets, uint32_t* keyoff,
+                   const uint2* trect, const FrameDesc* frames, uint64_t capacity,
+                   uint32_t* keys, uint32_t* vals, uint32_t* overflow);
+void launch_ranges(hipStream_t st, const uint32_t* keys, const uint64_t* k_dev, uint64_t k_max,
+                   uint64_t capacity, uint2* ranges, uint64_t n_tiles);
+
+// raster.hip: compositing forward and backward
+bool tile_shape_supported(int tw, int th);
+void launch_composite_fwd(hipStream_t st, int tw, int th, int n_tiles, int F,
+                          const FrameDesc* frames, const uint2* ranges, const uint32_t* vals,
+                          const Record* rec, const float* bg, float* rgb, float* depth,
+                          float* alpha, float* t_final, int32_t* n_last, uint32_t* nproc,
+                          bool remap, unsigned long long* pairs);
+void launch_composite_bwd(hipStream_t st, int tw, int th, int n_tiles, int F,
+                          const FrameDesc* frames, const uint2* ranges, const uint32_t* vals,
+                          const Record* rec, const uint2* trect, const uint32_t* keyoff,
+                          const uint32_t* nproc, const float* bg, const float* g_rgb,
+                          const float* g_depth, const float* g_alpha, const float* t_final,
+                          const int32_t* n_last, double* partial, uint32_t* stamp,
+                          const uint32_t* epoch, bool remap);
+
+// loss.hip
+int loss_blocks_x(int64_t max_hw);
+void launch_loss_l1(hipStream_t st, int F, int blocks_x, const FrameDesc* frames,
+                    const float* rgb, const float* depth, const float* t_rgb,
+                    const float* t_depth, float depth_weight, double* part, float* scale,
+                    float* loss, float* g_rgb, float* g_depth, float* g_alpha);
+
+// adam.hip
+void launch_adam(hipStream_t st, uint64_t n3, uint64_t nsh, float* means, const float* g_means,
+                 float* m_means, float* v_means, float* sh, const float* g_sh, float* m_sh,
+                 float* v_sh, int n_frames, float* poses, const float* g_twist, float* m_tw,
+                 float* v_tw, float lr_means, float lr_sh, float lr_pose, float beta1,
+                 float beta2, float eps, int32_t* step);
+
+}  // namespace gsr

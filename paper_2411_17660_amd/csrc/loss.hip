@@ -8,7 +8,7 @@
 // and writes dL/dRGB = sign(RGB - RGB*) / (3 H W), dL/dD = w_d sign(D - D*)
 // [p in m_f] / |m_f|, dL/dAlpha = 0.  Per-block partial sums are combined in
 // FP64 in a fixed order.
-#include "gsr_device.h"
+#include "launch.h"
 
 namespace gsr {
 

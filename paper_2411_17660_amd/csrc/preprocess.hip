@@ -16,7 +16,7 @@
 //
 // One thread per Gaussian walks all frames of the batch: the parameters are
 // read from HBM once per step and the world covariance is built once.
-#include "gsr_device.h"
+#include "launch.h"
 
 namespace gsr {
 
@@ -318,9 +318,9 @@ constexpr int kSlotGroup = 8;
 
 __global__ void __launch_bounds__(256) slot_reduce_kernel(
     uint64_t m, const uint32_t* __restrict__ keyoff, const uint32_t* __restrict__ ntiles,
-    const float* __restrict__ partial, const uint32_t* __restrict__ stamp,
+    const double* __restrict__ partial, const uint32_t* __restrict__ stamp,
     const uint32_t* __restrict__ epoch_dev, uint64_t key_capacity,
-    float* __restrict__ grad2d /* [m][kNG] */) {
+    double* __restrict__ grad2d /* [m][kNG] */) {
   const uint32_t epoch = *epoch_dev;
   const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t r = gid / kSlotGroup;
@@ -329,12 +329,12 @@ __global__ void __launch_bounds__(256) slot_reduce_kernel(
   uint32_t cnt = active ? ntiles[r] : 0u;
   const uint32_t off = cnt ? keyoff[r] : 0u;
   if (cnt && (uint64_t)off + cnt > key_capacity) cnt = 0;  // overflowed in keygen
-  float acc[kNG];
+  double acc[kNG];
 #pragma unroll
-  for (int j = 0; j < kNG; ++j) acc[j] = 0.0f;
+  for (int j = 0; j < kNG; ++j) acc[j] = 0.0;
   for (uint32_t s = sub; s < cnt; s += kSlotGroup) {
     if (stamp[off + s] != epoch) continue;
-    const float* pp = partial + (size_t)(off + s) * kNG;
+    const double* pp = partial + (size_t)(off + s) * kNG;
 #pragma unroll
     for (int j = 0; j < kNG; ++j) acc[j] += pp[j];
   }
@@ -344,15 +344,15 @@ __global__ void __launch_bounds__(256) slot_reduce_kernel(
     for (int j = 0; j < kNG; ++j) acc[j] += __shfl_xor(acc[j], o, kSlotGroup);
   if (!active) return;
   if (cnt == 0) {
-    for (int j = sub; j < kNG; j += kSlotGroup) grad2d[r * kNG + j] = 0.0f;
+    for (int j = sub; j < kNG; j += kSlotGroup) grad2d[r * kNG + j] = 0.0;
     return;
   }
-  float v = acc[0];
+  double v = acc[0];
 #pragma unroll
   for (int j = 1; j < kNG; ++j) v = sub == j ? acc[j] : v;
   if (sub < kNG) grad2d[r * kNG + sub] = v;
   if (sub + kSlotGroup < kNG) {  // values 8, 9
-    float v2 = acc[kSlotGroup];
+    double v2 = acc[kSlotGroup];
 #pragma unroll
     for (int j = kSlotGroup + 1; j < kNG; ++j) v2 = sub + kSlotGroup == j ? acc[j] : v2;
     grad2d[r * kNG + sub + kSlotGroup] = v2;
@@ -374,7 +374,7 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(
     const float* __restrict__ poses, const float* __restrict__ means,
     const float* __restrict__ log_scales, const float* __restrict__ quats,
     const float* __restrict__ opac, const float* __restrict__ sh,
-    const uint32_t* __restrict__ ntiles, const float* __restrict__ grad2d,
+    const uint32_t* __restrict__ ntiles, const double* __restrict__ grad2d,
     float* __restrict__ g_means, float* __restrict__ g_log_scales,
     float* __restrict__ g_quats, float* __restrict__ g_opac, float* __restrict__ g_sh,
     double* __restrict__ twist_partial /* [F][n_waves][6] */) {
@@ -399,7 +399,7 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(
     const uint32_t cnt = active ? ntiles[r] : 0u;
     if (cnt > 0) {
       double gr[kNG];
-      for (int j = 0; j < kNG; ++j) gr[j] = (double)grad2d[r * kNG + j];
+      for (int j = 0; j < kNG; ++j) gr[j] = grad2d[r * kNG + j];
       const FrameDesc fr = frames[f];
       double W[9], tf[3];
       load_pose(poses, f, W, tf);
@@ -616,9 +616,9 @@ int64_t preprocess_bwd_waves(int64_t n) { return ((n + 255) / 256) * 4; }
 void launch_preprocess_bwd(hipStream_t st, int64_t n, int F, const FrameDesc* frames,
                            const float* poses, const float* means, const float* log_scales,
                            const float* quats, const float* opac, const float* sh, int deg,
-                           const uint32_t* keyoff, const uint32_t* ntiles, const float* partial,
+                           const uint32_t* keyoff, const uint32_t* ntiles, const double* partial,
                            const uint32_t* stamp, const uint32_t* epoch, uint64_t key_capacity,
-                           float* grad2d, float* g_means, float* g_log_scales, float* g_quats,
+                           double* grad2d, float* g_means, float* g_log_scales, float* g_quats,
                            float* g_opac, float* g_sh, double* twist_partial, float* g_twist) {
   const dim3 grid((unsigned)((n + 255) / 256));
 #define GSR_PRE_BWD(D)                                                                       \

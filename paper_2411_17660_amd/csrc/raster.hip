@@ -31,7 +31,7 @@
 // this (tile, entry) key goes to its own slot (no atomics), stamped with the
 // backward's epoch so the per-record reduction can skip slots of keys that
 // no pixel reached.
-#include "gsr_device.h"
+#include "launch.h"
 
 namespace gsr {
 
@@ -148,47 +148,47 @@ __global__ void __launch_bounds__(64) composite_fwd_kernel(
 // value index
 //   idx(l) = 5 b5 + (b4 ? 3 + b3 : (b3 ? 2 : b2)),   b_k = bit k of l,
 // and `writer` is set on exactly one lane per index.
-__device__ __forceinline__ float wave_transpose_sum10(const float v[10], int lane, int& idx,
-                                                     bool& writer) {
+template <typename F>
+__device__ __forceinline__ F wave_transpose_sum10(const F v[10], int lane, int& idx, bool& writer) {
   const bool b5 = (lane >> 5) & 1, b4 = (lane >> 4) & 1, b3 = (lane >> 3) & 1,
              b2 = (lane >> 2) & 1;
-  float r1[5];
+  F r1[5];
 #pragma unroll
   for (int j = 0; j < 5; ++j) {
-    const float send = b5 ? v[j] : v[5 + j];
-    const float keep = b5 ? v[5 + j] : v[j];
+    const F send = b5 ? v[j] : v[5 + j];
+    const F keep = b5 ? v[5 + j] : v[j];
     r1[j] = keep + __shfl_xor(send, 32, 64);
   }
   // b4 = 0 keeps r1[0..2], b4 = 1 keeps r1[3..4]
-  float r2[3];
+  F r2[3];
   {
-    const float s0 = b4 ? r1[0] : r1[3], k0 = b4 ? r1[3] : r1[0];
-    const float s1 = b4 ? r1[1] : r1[4], k1 = b4 ? r1[4] : r1[1];
-    const float s2 = b4 ? r1[2] : 0.0f, k2 = b4 ? 0.0f : r1[2];
+    const F s0 = b4 ? r1[0] : r1[3], k0 = b4 ? r1[3] : r1[0];
+    const F s1 = b4 ? r1[1] : r1[4], k1 = b4 ? r1[4] : r1[1];
+    const F s2 = b4 ? r1[2] : F(0), k2 = b4 ? F(0) : r1[2];
     r2[0] = k0 + __shfl_xor(s0, 16, 64);
     r2[1] = k1 + __shfl_xor(s1, 16, 64);
     r2[2] = k2 + __shfl_xor(s2, 16, 64);
   }
   // b4 = 0: b3 = 0 keeps {r2[0], r2[1]}, b3 = 1 keeps {r2[2]}
   // b4 = 1: b3 = 0 keeps {r2[0]},        b3 = 1 keeps {r2[1]}
-  float r3[2];
+  F r3[2];
   {
-    float s0, k0, s1, k1;
+    F s0, k0, s1, k1;
     if (!b4) {
       s0 = b3 ? r2[0] : r2[2]; k0 = b3 ? r2[2] : r2[0];
-      s1 = b3 ? r2[1] : 0.0f;  k1 = b3 ? 0.0f : r2[1];
+      s1 = b3 ? r2[1] : F(0);  k1 = b3 ? F(0) : r2[1];
     } else {
       s0 = b3 ? r2[0] : r2[1]; k0 = b3 ? r2[1] : r2[0];
-      s1 = 0.0f; k1 = 0.0f;
+      s1 = F(0); k1 = F(0);
     }
     r3[0] = k0 + __shfl_xor(s0, 8, 64);
     r3[1] = k1 + __shfl_xor(s1, 8, 64);
   }
   // lanes still carrying two values (b4 = 0, b3 = 0) split on b2
   const bool two = !b4 && !b3;
-  const float s4 = two ? (b2 ? r3[0] : r3[1]) : r3[0];
-  const float k4 = two ? (b2 ? r3[1] : r3[0]) : r3[0];
-  float r = k4 + __shfl_xor(s4, 4, 64);
+  const F s4 = two ? (b2 ? r3[0] : r3[1]) : r3[0];
+  const F k4 = two ? (b2 ? r3[1] : r3[0]) : r3[0];
+  F r = k4 + __shfl_xor(s4, 4, 64);
   r += __shfl_xor(r, 2, 64);
   r += __shfl_xor(r, 1, 64);
   idx = 5 * (int)b5 + (b4 ? 3 + (int)b3 : (b3 ? 2 : (int)b2));
@@ -204,7 +204,7 @@ __global__ void __launch_bounds__(64) composite_bwd_kernel(
     const uint32_t* __restrict__ keyoff, const uint32_t* __restrict__ tile_nproc, float bg0,
     float bg1, float bg2, const float* __restrict__ g_rgb, const float* __restrict__ g_depth,
     const float* __restrict__ g_alpha, const float* __restrict__ t_final,
-    const int32_t* __restrict__ n_last, float* __restrict__ partial,
+    const int32_t* __restrict__ n_last, double* __restrict__ partial,
     uint32_t* __restrict__ stamp, const uint32_t* __restrict__ epoch_dev, int xcd_remap) {
   constexpr int PIX = TW * TH / kWave;
   constexpr int RPP = kWave / TW;
@@ -227,8 +227,12 @@ __global__ void __launch_bounds__(64) composite_bwd_kernel(
   const int64_t plane = (int64_t)fr.width * fr.height;
 
   // per pixel: T_{i+1}; colour, depth and transmittance seen behind the
-  // current entry (normalised by T_{i+1}); upstream gradients
-  float T[PIX], B0[PIX], B1[PIX], B2[PIX], BZ[PIX], BT[PIX];
+  // current entry (normalised by T_{i+1}); upstream gradients.  The colour
+  // and depth behind are FP64: dL/da_i uses c_i - B_i, which cancels on
+  // surfaces of uniform colour, and the gradient of a large Gaussian sums
+  // that difference over up to 10^5 pixels.
+  float T[PIX], BT[PIX];
+  double B0[PIX], B1[PIX], B2[PIX], BZ[PIX];
   float G0[PIX], G1[PIX], G2[PIX], GD[PIX], GA[PIX];
   int last[PIX];
 #pragma unroll
@@ -238,7 +242,7 @@ __global__ void __launch_bounds__(64) composite_bwd_kernel(
     const int64_t p = (int64_t)py * fr.width + px;
     last[k] = valid ? n_last[fr.pixel_offset + p] : 0;
     T[k] = valid ? t_final[fr.pixel_offset + p] : 1.0f;
-    B0[k] = bg0; B1[k] = bg1; B2[k] = bg2; BZ[k] = 0.0f; BT[k] = 1.0f;
+    B0[k] = bg0; B1[k] = bg1; B2[k] = bg2; BZ[k] = 0.0; BT[k] = 1.0f;
     const float* gi = g_rgb + 3 * fr.pixel_offset;
     G0[k] = valid ? gi[p] : 0.0f;
     G1[k] = valid ? gi[plane + p] : 0.0f;
@@ -265,6 +269,7 @@ __global__ void __launch_bounds__(64) composite_bwd_kernel(
       const bool xin = (unsigned)(px - xlo) <= (unsigned)(xhi - xlo);
       const float dx = dx_of(R.u_hi, R.u_lo, px);
       const float a1dx = R.a1 * dx;
+      const double c0 = R.c0, c1 = R.c1, c2 = R.c2, cz = R.z;
       float gu = 0.f, gv = 0.f, gSxx = 0.f, gSxy = 0.f, gSyy = 0.f, gs = 0.f;
       float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f, gz = 0.f;
       bool any = false;
@@ -285,19 +290,20 @@ __global__ void __launch_bounds__(64) composite_bwd_kernel(
         float Ti = T[k] * inv;
         Ti = __builtin_fmaf(__builtin_fmaf(-Ti, om, T[k]), inv, Ti);  // Newton step
         const float w = a * Ti;
+        const double ad = a;
+        const double d0 = c0 - B0[k], d1 = c1 - B1[k], d2 = c2 - B2[k], dz = cz - BZ[k];
         // dL/da_i = T_i [G . (c_i - B_i) + G_D (z_i - BZ_i) + G_A BT_i]
-        const float dLda = Ti * (G0[k] * (R.c0 - B0[k]) + G1[k] * (R.c1 - B1[k]) +
-                                 G2[k] * (R.c2 - B2[k]) + GD[k] * (R.z - BZ[k]) +
-                                 GA[k] * BT[k]);
+        const float dLda = Ti * (G0[k] * (float)d0 + G1[k] * (float)d1 + G2[k] * (float)d2 +
+                                 GD[k] * (float)dz + GA[k] * BT[k]);
         gc0 += G0[k] * w;
         gc1 += G1[k] * w;
         gc2 += G2[k] * w;
         gz += GD[k] * w;
         // step the 'behind' state in front of entry i
-        B0[k] = __builtin_fmaf(a, R.c0 - B0[k], B0[k]);
-        B1[k] = __builtin_fmaf(a, R.c1 - B1[k], B1[k]);
-        B2[k] = __builtin_fmaf(a, R.c2 - B2[k], B2[k]);
-        BZ[k] = __builtin_fmaf(a, R.z - BZ[k], BZ[k]);
+        B0[k] = __builtin_fma(ad, d0, B0[k]);
+        B1[k] = __builtin_fma(ad, d1, B1[k]);
+        B2[k] = __builtin_fma(ad, d2, B2[k]);
+        BZ[k] = __builtin_fma(ad, dz, BZ[k]);
         BT[k] = BT[k] * om;
         T[k] = Ti;
         any = true;
@@ -316,10 +322,12 @@ __global__ void __launch_bounds__(64) composite_bwd_kernel(
         gSyy -= dq * qy * qy;
       }
       if (__ballot(any) == 0) continue;
-      const float vals10[kNG] = {gu, gv, gSxx, gSxy, gSyy, gs, gc0, gc1, gc2, gz};
+      // FP64 from here on: a key's lane values cancel against each other and
+      // the per-record sum runs over up to thousands of keys
+      const double vals10[kNG] = {gu, gv, gSxx, gSxy, gSyy, gs, gc0, gc1, gc2, gz};
       int idx;
       bool writer;
-      const float tot = wave_transpose_sum10(vals10, lane, idx, writer);
+      const double tot = wave_transpose_sum10<double>(vals10, lane, idx, writer);
       const uint32_t sl = slot[j];
       if (writer) partial[(size_t)sl * kNG + idx] = tot;
       if (lane == 1) stamp[sl] = epoch;
@@ -350,7 +358,7 @@ static void launch_bwd_t(hipStream_t st, int n_tiles, int F, const FrameDesc* fr
                          const uint2* ranges, const uint32_t* vals, const Record* rec,
                          const uint2* trect, const uint32_t* keyoff, const uint32_t* nproc, const float* bg, const float* g_rgb,
                          const float* g_depth, const float* g_alpha, const float* t_final,
-                         const int32_t* n_last, float* partial, uint32_t* stamp,
+                         const int32_t* n_last, double* partial, uint32_t* stamp,
                          const uint32_t* epoch, bool remap) {
   const unsigned grid = remap ? (unsigned)(((n_tiles + 7) / 8) * 8) : (unsigned)n_tiles;
   hipLaunchKernelGGL((composite_bwd_kernel<TW, TH>), dim3(grid), dim3(kWave), 0, st, n_tiles, F,
@@ -385,7 +393,7 @@ void launch_composite_bwd(hipStream_t st, int tw, int th, int n_tiles, int F,
                           const Record* rec, const uint2* trect, const uint32_t* keyoff,
                           const uint32_t* nproc, const float* bg,
                           const float* g_rgb, const float* g_depth, const float* g_alpha,
-                          const float* t_final, const int32_t* n_last, float* partial,
+                          const float* t_final, const int32_t* n_last, double* partial,
                           uint32_t* stamp, const uint32_t* epoch, bool remap) {
   if (n_tiles <= 0) return;
 #define GSR_BWD(W, H)                                                                          \

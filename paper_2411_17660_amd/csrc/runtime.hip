@@ -11,53 +11,9 @@
 #include <vector>
 
 #include "../../include/gsr.h"
-#include "gsr_device.h"
+#include "launch.h"
 
-namespace gsr {
-// preprocess.hip
-void launch_preprocess_fwd(hipStream_t, int64_t, int, const FrameDesc*, const float*,
-                           const float*, const float*, const float*, const float*, const float*,
-                           int, int, int, Record*, uint2*, uint32_t*, uint32_t*, uint32_t*);
-int64_t preprocess_bwd_waves(int64_t n);
-void launch_preprocess_bwd(hipStream_t, int64_t, int, const FrameDesc*, const float*,
-                           const float*, const float*, const float*, const float*, const float*,
-                           int, const uint32_t*, const uint32_t*, const float*, const uint32_t*,
-                           const uint32_t*, uint64_t, float*, float*, float*, float*, float*,
-                           float*, double*, float*);
-void launch_bump_epoch(hipStream_t, uint32_t*);
-// sort.hip
-void launch_fill_u32(hipStream_t, uint32_t*, uint64_t, uint32_t);
-size_t radix_hist_elems(uint64_t n_max);
-size_t scan_block_elems(uint64_t n_max);
-bool launch_radix_sort(hipStream_t, uint32_t*, uint32_t*, uint32_t*, uint32_t*, const uint64_t*,
-                       uint64_t, int, uint32_t*, uint32_t*);
-void launch_offsets_scan(hipStream_t, const uint32_t*, const uint32_t*, uint64_t, uint64_t*,
-                         uint64_t*, uint64_t*);
-void launch_keygen(hipStream_t, uint64_t, uint64_t, const uint32_t*, const uint32_t*,
-                   const uint64_t*, uint32_t*, const uint2*, const FrameDesc*, uint64_t,
-                   uint32_t*, uint32_t*, uint32_t*);
-void launch_ranges(hipStream_t, const uint32_t*, const uint64_t*, uint64_t, uint64_t, uint2*,
-                   uint64_t);
-// raster.hip
-bool tile_shape_supported(int tw, int th);
-void launch_composite_fwd(hipStream_t, int, int, int, int, const FrameDesc*, const uint2*,
-                          const uint32_t*, const Record*, const float*, float*, float*, float*,
-                          float*, int32_t*, uint32_t*, bool, unsigned long long*);
-void launch_composite_bwd(hipStream_t, int, int, int, int, const FrameDesc*, const uint2*,
-                          const uint32_t*, const Record*, const uint2*, const uint32_t*,
-                          const uint32_t*, const float*,
-                          const float*, const float*, const float*, const float*,
-                          const int32_t*, float*, uint32_t*, const uint32_t*, bool);
-// loss.hip
-int loss_blocks_x(int64_t max_hw);
-void launch_loss_l1(hipStream_t, int, int, const FrameDesc*, const float*, const float*,
-                    const float*, const float*, float, double*, float*, float*, float*, float*,
-                    float*);
-// adam.hip
-void launch_adam(hipStream_t, uint64_t, uint64_t, float*, const float*, float*, float*, float*,
-                 const float*, float*, float*, int, float*, const float*, float*, float*, float,
-                 float, float, float, float, float, int32_t*);
-}  // namespace gsr
+
 
 using namespace gsr;
 
@@ -411,10 +367,10 @@ gsr_status gsr_forward(gsr_context* ctx, const gsr_settings* s, int64_t n, const
     if ((rc = ensure(ctx, ctx->vals_a, c2 * 4, st))) return rc;
     if ((rc = ensure(ctx, ctx->keys_b, c2 * 4, st))) return rc;
     if ((rc = ensure(ctx, ctx->vals_b, c2 * 4, st))) return rc;
-    if ((rc = ensure(ctx, ctx->partial, c2 * kNG * 4, st))) return rc;
+    if ((rc = ensure(ctx, ctx->partial, c2 * kNG * 8, st))) return rc;
     if ((rc = ensure(ctx, ctx->stamp, c2 * 4, st, true))) return rc;
     ctx->key_cap = std::min({ctx->keys_a.bytes / 4, ctx->keys_b.bytes / 4, ctx->vals_a.bytes / 4,
-                             ctx->vals_b.bytes / 4, ctx->partial.bytes / (kNG * 4),
+                             ctx->vals_b.bytes / 4, ctx->partial.bytes / (kNG * 8),
                              ctx->stamp.bytes / 4});
     const size_t h2 = radix_hist_elems(ctx->key_cap);
     if ((rc = ensure(ctx, ctx->hist, h2 * 4, st))) return rc;
@@ -517,20 +473,20 @@ gsr_status gsr_backward(gsr_context* ctx, const float* g_rgb, const float* g_dep
                          P<uint32_t>(ctx->nproc), s.background, g_rgb,
                          g_depth, g_alpha,
                          P<float>(ctx->t_final), P<int32_t>(ctx->n_last),
-                         P<float>(ctx->partial), P<uint32_t>(ctx->stamp), d_epoch, remap);
+                         P<double>(ctx->partial), P<uint32_t>(ctx->stamp), d_epoch, remap);
   }
   // A9-A11 per-record reduce, chain rule, twist
   const int64_t waves = sv.n > 0 ? preprocess_bwd_waves(sv.n) : 0;
   if ((rc = ensure(ctx, ctx->twist_part, (size_t)std::max<int64_t>(waves, 1) * sv.F * 6 * 8, st)))
     return rc;
-  if ((rc = ensure(ctx, ctx->grad2d, (size_t)sv.n * sv.F * kNG * 4, st))) return rc;
+  if ((rc = ensure(ctx, ctx->grad2d, (size_t)sv.n * sv.F * kNG * 8, st))) return rc;
   {
     StageTimer t(ctx, st, timing, GSR_STAGE_PREPROCESS_BWD);
     launch_preprocess_bwd(st, sv.n, sv.F, P<FrameDesc>(ctx->frames), sv.poses, sv.means,
                           sv.log_scales, sv.quats, sv.opac, sv.sh, s.sh_degree,
-                          P<uint32_t>(ctx->keyoff), P<uint32_t>(ctx->ntiles), P<float>(ctx->partial),
+                          P<uint32_t>(ctx->keyoff), P<uint32_t>(ctx->ntiles), P<double>(ctx->partial),
                           P<uint32_t>(ctx->stamp), d_epoch, ctx->key_cap,
-                          P<float>(ctx->grad2d), g_means, g_log_scales, g_quats, g_opac, g_sh,
+                          P<double>(ctx->grad2d), g_means, g_log_scales, g_quats, g_opac, g_sh,
                           P<double>(ctx->twist_part), g_twist);
   }
   GSR_HIP(hipGetLastError());
@@ -793,6 +749,19 @@ gsr_status gsr_debug_lists(gsr_context* ctx, uint32_t* ntiles, uint32_t* depth_k
   if (ranges && sv.T) GSR_HIP(hipMemcpy(ranges, ctx->ranges.p, sv.T * 8, hipMemcpyDeviceToHost));
   if (n_last && sv.P) GSR_HIP(hipMemcpy(n_last, ctx->n_last.p, sv.P * 4, hipMemcpyDeviceToHost));
   if (t_final && sv.P) GSR_HIP(hipMemcpy(t_final, ctx->t_final.p, sv.P * 4, hipMemcpyDeviceToHost));
+  return GSR_OK;
+}
+
+gsr_status gsr_debug_grad2d(gsr_context* ctx, double* out, void* stream) {
+  if (!ctx || !out) return GSR_ERR_INVALID_ARGUMENT;
+  const Saved& sv = ctx->s;
+  if (!sv.valid) return fail(ctx, GSR_ERR_STATE, "no forward");
+  const size_t bytes = (size_t)sv.n * sv.F * kNG * 8;
+  if (bytes == 0) return GSR_OK;
+  if (ctx->grad2d.bytes < bytes) return fail(ctx, GSR_ERR_STATE, "no backward");
+  GSR_HIP(hipSetDevice(ctx->device));
+  GSR_HIP(hipStreamSynchronize((hipStream_t)stream));
+  GSR_HIP(hipMemcpy(out, ctx->grad2d.p, bytes, hipMemcpyDeviceToHost));
   return GSR_OK;
 }
 

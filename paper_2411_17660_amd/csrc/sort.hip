@@ -20,7 +20,7 @@
 // block offsets; no global atomics.  Scans are reduce-then-scan in 3
 // launches.  All kernels read the element count from device memory so the
 // sequence is capturable.
-#include "gsr_device.h"
+#include "launch.h"
 
 namespace gsr {
 
@@ -313,17 +313,42 @@ __global__ void __launch_bounds__(256) keygen_kernel(
 }
 
 // [start, end) of every tile's run in the sorted keys (ranges pre-zeroed).
+// Each thread scans 8 consecutive keys (two 16-byte loads) plus the key just
+// before them; a run boundary writes the start of the new tile and the end
+// of the previous one.
+constexpr int kRangeItems = 8;
+
 __global__ void __launch_bounds__(256) ranges_kernel(const uint32_t* __restrict__ keys,
                                                      const uint64_t* k_dev, uint64_t capacity,
                                                      uint2* __restrict__ ranges,
                                                      uint32_t n_tiles) {
   const uint64_t K = *k_dev < capacity ? *k_dev : capacity;
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= K) return;
-  const uint32_t t = keys[i];
-  if (t >= n_tiles) return;  // sentinel of an overflowed record
-  if (i == 0 || keys[i - 1] != t) ranges[t].x = (uint32_t)i;
-  if (i + 1 == K || keys[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
+  const uint64_t i0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRangeItems;
+  if (i0 >= K) return;
+  uint32_t k[kRangeItems];
+  if (i0 + kRangeItems <= K) {
+    const uint4 a = *reinterpret_cast<const uint4*>(keys + i0);
+    const uint4 b = *reinterpret_cast<const uint4*>(keys + i0 + 4);
+    k[0] = a.x; k[1] = a.y; k[2] = a.z; k[3] = a.w;
+    k[4] = b.x; k[5] = b.y; k[6] = b.z; k[7] = b.w;
+  } else {
+#pragma unroll
+    for (int j = 0; j < kRangeItems; ++j) k[j] = i0 + j < K ? keys[i0 + j] : 0xffffffffu;
+  }
+  uint32_t prev = i0 == 0 ? 0xffffffffu : keys[i0 - 1];
+#pragma unroll
+  for (int j = 0; j < kRangeItems; ++j) {
+    const uint64_t i = i0 + j;
+    if (i >= K) break;
+    const uint32_t t = k[j];
+    if (t != prev) {
+      if (t < n_tiles) ranges[t].x = (uint32_t)i;
+      if (prev < n_tiles) ranges[prev].y = (uint32_t)i;
+    }
+    prev = t;
+  }
+  const uint64_t last = i0 + kRangeItems - 1 < K - 1 ? i0 + kRangeItems - 1 : K - 1;
+  if (last == K - 1 && prev < n_tiles) ranges[prev].y = (uint32_t)K;
 }
 
 __global__ void fill_u32_kernel(uint32_t* __restrict__ p, uint64_t n, uint32_t v) {
@@ -409,8 +434,8 @@ void launch_ranges(hipStream_t st, const uint32_t* keys, const uint64_t* k_dev, 
                    uint64_t capacity, uint2* ranges, uint64_t n_tiles) {
   launch_fill_u32(st, (uint32_t*)ranges, 2 * n_tiles, 0u);
   if (k_max == 0) return;
-  hipLaunchKernelGGL(ranges_kernel, dim3(blocks_for(k_max, 256)), dim3(256), 0, st, keys, k_dev,
-                     capacity, ranges, (uint32_t)n_tiles);
+  hipLaunchKernelGGL(ranges_kernel, dim3(blocks_for(k_max, 256 * kRangeItems)), dim3(256), 0, st,
+                     keys, k_dev, capacity, ranges, (uint32_t)n_tiles);
 }
 
 }  // namespace gsr

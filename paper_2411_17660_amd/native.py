@@ -22,7 +22,8 @@ STAGES = ["preprocess", "depth_sort", "offsets", "keygen", "tile_sort", "ranges"
 
 EXPORTS = ["gsr_create", "gsr_destroy", "gsr_last_error", "gsr_forward", "gsr_backward",
            "gsr_loss_l1", "gsr_step_l1", "gsr_check_overflow", "gsr_debug_stats",
-           "gsr_debug_timings", "gsr_debug_lists", "gsr_autotune", "gsr_adam_step"]
+           "gsr_debug_timings", "gsr_debug_lists", "gsr_debug_grad2d", "gsr_autotune",
+           "gsr_adam_step"]
 TILE_SHAPES = [(16, 16), (8, 8), (32, 8), (16, 8), (32, 16)]
 
 
@@ -83,6 +84,7 @@ def load(path=LIB_PATH):
     lib.gsr_check_overflow.argtypes = [V, V]
     lib.gsr_debug_stats.argtypes = [V, C.POINTER(Stats), V]
     lib.gsr_debug_lists.argtypes = [V] + [V] * 8 + [V]
+    lib.gsr_debug_grad2d.argtypes = [V, V, V]
     lib.gsr_debug_timings.argtypes = [V, V, V]
     lib.gsr_adam_step.argtypes = [V, I64, I32, V, V, V, V, V, V, V, V, I32, V, V, V, V, F32, F32,
                                   F32, F32, F32, F32, V, V]

@@ -194,6 +194,15 @@ class Rasterizer:
         out["K"] = K
         return out
 
+    def debug_grad2d(self):
+        """Per-record screen-space gradients of the last backward, [n*F, 10]:
+        d/du, d/dv, d/dSigma'_xx, d/dSigma'_xy, d/dSigma'_yy, d/dopacity,
+        d/dcolour (3), d/dz."""
+        M = self.stats()["n_records"]
+        out = np.zeros((max(M, 1), 10), np.float64)
+        self._check(self.lib.gsr_debug_grad2d(self.h, C.c_void_p(out.ctypes.data), _stream()))
+        return out[:M]
+
 
 class _RasterizeFn(torch.autograd.Function):
     @staticmethod

@@ -16,7 +16,7 @@ int64_t preprocess_bwd_waves(int64_t n);
 void launch_preprocess_bwd(hipStream_t st, int64_t n, int F, const FrameDesc* frames,
                            const float* poses, const float* means, const float* log_scales,
                            const float* quats, const float* opac, const float* sh, int deg,
-                           const uint32_t* keyoff, const uint32_t* ntiles, const double* partial,
+                           const uint32_t* keyoff, const uint32_t* ntiles, const float* partial,
                            const uint32_t* stamp, const uint32_t* epoch, uint64_t key_capacity,
                            double* grad2d, float* g_means, float* g_log_scales, float* g_quats,
                            float* g_opac, float* g_sh, double* twist_partial, float* g_twist);
@@ -50,7 +50,7 @@ void launch_composite_bwd(hipStream_t st, int tw, int th, int n_tiles, int F,
                           const Record* rec, const uint2* trect, const uint32_t* keyoff,
                           const uint32_t* nproc, const float* bg, const float* g_rgb,
                           const float* g_depth, const float* g_alpha, const float* t_final,
-                          const int32_t* n_last, double* partial, uint32_t* stamp,
+                          const int32_t* n_last, float* partial, uint32_t* stamp,
                           const uint32_t* epoch, bool remap);
 
 // loss.hip

@@ -318,7 +318,7 @@ constexpr int kSlotGroup = 8;
 
 __global__ void __launch_bounds__(256) slot_reduce_kernel(
     uint64_t m, const uint32_t* __restrict__ keyoff, const uint32_t* __restrict__ ntiles,
-    const double* __restrict__ partial, const uint32_t* __restrict__ stamp,
+    const float* __restrict__ partial, const uint32_t* __restrict__ stamp,
     const uint32_t* __restrict__ epoch_dev, uint64_t key_capacity,
     double* __restrict__ grad2d /* [m][kNG] */) {
   const uint32_t epoch = *epoch_dev;
@@ -334,7 +334,7 @@ __global__ void __launch_bounds__(256) slot_reduce_kernel(
   for (int j = 0; j < kNG; ++j) acc[j] = 0.0;
   for (uint32_t s = sub; s < cnt; s += kSlotGroup) {
     if (stamp[off + s] != epoch) continue;
-    const double* pp = partial + (size_t)(off + s) * kNG;
+    const float* pp = partial + (size_t)(off + s) * kNG;
 #pragma unroll
     for (int j = 0; j < kNG; ++j) acc[j] += pp[j];
   }
@@ -616,7 +616,7 @@ int64_t preprocess_bwd_waves(int64_t n) { return ((n + 255) / 256) * 4; }
 void launch_preprocess_bwd(hipStream_t st, int64_t n, int F, const FrameDesc* frames,
                            const float* poses, const float* means, const float* log_scales,
                            const float* quats, const float* opac, const float* sh, int deg,
-                           const uint32_t* keyoff, const uint32_t* ntiles, const double* partial,
+                           const uint32_t* keyoff, const uint32_t* ntiles, const float* partial,
                            const uint32_t* stamp, const uint32_t* epoch, uint64_t key_capacity,
                            double* grad2d, float* g_means, float* g_log_scales, float* g_quats,
                            float* g_opac, float* g_sh, double* twist_partial, float* g_twist) {

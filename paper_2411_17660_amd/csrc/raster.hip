@@ -142,56 +142,90 @@ __global__ void __launch_bounds__(64) composite_fwd_kernel(
   }
 }
 
-// Sums v[0..9] over the 64 lanes of the wave.  Each butterfly round halves
-// the set of values a lane carries (10 -> 5 -> 3|2 -> 2|1 -> 1) before the
-// plain rounds over lane bits 1 and 0.  On return lane l holds the total of
-// value index
+// Cross-lane helpers of the FP64 wave reduction (all VALU, no LDS traffic).
+//
+// swap_sum<32>(a, b): with v_permlane32_swap the upper half-wave of a trades
+// places with the lower half-wave of b, so that afterwards a' + b' is
+// a(l) + a(l ^ 32) on lanes l < 32 and b(l ^ 32) + b(l) on lanes l >= 32: the
+// butterfly step over lane bit 5 that keeps a on the lower and b on the
+// upper half, in one swap and one add.  swap_sum<16> does the same over lane
+// bit 4 with v_permlane16_swap (odd 16-lane rows of a trade with even rows
+// of b).
+template <int W>
+__device__ __forceinline__ double swap_sum(double a, double b) {
+  const uint64_t ua = (uint64_t)__double_as_longlong(a), ub = (uint64_t)__double_as_longlong(b);
+  uint32_t lo0, lo1, hi0, hi1;
+  if constexpr (W == 32) {
+    const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)ua, (uint32_t)ub, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(ua >> 32), (uint32_t)(ub >> 32),
+                                                     false, false);
+    lo0 = lo[0]; lo1 = lo[1]; hi0 = hi[0]; hi1 = hi[1];
+  } else {
+    const auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)ua, (uint32_t)ub, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((uint32_t)(ua >> 32), (uint32_t)(ub >> 32),
+                                                     false, false);
+    lo0 = lo[0]; lo1 = lo[1]; hi0 = hi[0]; hi1 = hi[1];
+  }
+  return __longlong_as_double((long long)(((uint64_t)hi0 << 32) | lo0)) +
+         __longlong_as_double((long long)(((uint64_t)hi1 << 32) | lo1));
+}
+
+// The value of v on a partner lane inside the lane's 16-lane row: DPP row
+// mirror (partner 15 - l) for lane bit 3, half-row mirror (7 - l) for bit 2,
+// quad permutes (l ^ 2, l ^ 1) for bits 1 and 0.  The mirrors also flip the
+// lower lane bits; the rounds that follow sum over those anyway.
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf,
+                                                            0xf, false);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+constexpr int kDppRowMirror = 0x140, kDppHalfMirror = 0x141, kDppQuadXor2 = 0x4e,
+              kDppQuadXor1 = 0xb1;
+
+// Sums v[0..9] over the 64 lanes of the wave in FP64.  Each butterfly round
+// halves the set of values a lane carries (10 -> 5 -> 3|2 -> 2|1 -> 1) before
+// the plain rounds over lane bits 1 and 0.  On return lane l holds the total
+// of value index
 //   idx(l) = 5 b5 + (b4 ? 3 + b3 : (b3 ? 2 : b2)),   b_k = bit k of l,
 // and `writer` is set on exactly one lane per index.
-template <typename F>
-__device__ __forceinline__ F wave_transpose_sum10(const F v[10], int lane, int& idx, bool& writer) {
-  const bool b5 = (lane >> 5) & 1, b4 = (lane >> 4) & 1, b3 = (lane >> 3) & 1,
-             b2 = (lane >> 2) & 1;
-  F r1[5];
+__device__ __forceinline__ double wave_transpose_sum10(const double v[10], int lane, int& idx,
+                                                       bool& writer) {
+  const bool b4 = (lane >> 4) & 1, b3 = (lane >> 3) & 1, b2 = (lane >> 2) & 1;
+  // bit 5: the lower half keeps v[0..4], the upper half v[5..9]
+  double r1[5];
 #pragma unroll
-  for (int j = 0; j < 5; ++j) {
-    const F send = b5 ? v[j] : v[5 + j];
-    const F keep = b5 ? v[5 + j] : v[j];
-    r1[j] = keep + __shfl_xor(send, 32, 64);
-  }
-  // b4 = 0 keeps r1[0..2], b4 = 1 keeps r1[3..4]
-  F r2[3];
+  for (int j = 0; j < 5; ++j) r1[j] = swap_sum<32>(v[j], v[5 + j]);
+  // bit 4: b4 = 0 keeps r1[0..2], b4 = 1 keeps r1[3..4]
+  double r2[3];
+  r2[0] = swap_sum<16>(r1[0], r1[3]);
+  r2[1] = swap_sum<16>(r1[1], r1[4]);
+  r2[2] = swap_sum<16>(r1[2], 0.0);
+  // bit 3.  b4 = 0: b3 = 0 keeps {r2[0], r2[1]}, b3 = 1 keeps {r2[2]}
+  //         b4 = 1: b3 = 0 keeps {r2[0]},        b3 = 1 keeps {r2[1]}
+  double r3[2];
   {
-    const F s0 = b4 ? r1[0] : r1[3], k0 = b4 ? r1[3] : r1[0];
-    const F s1 = b4 ? r1[1] : r1[4], k1 = b4 ? r1[4] : r1[1];
-    const F s2 = b4 ? r1[2] : F(0), k2 = b4 ? F(0) : r1[2];
-    r2[0] = k0 + __shfl_xor(s0, 16, 64);
-    r2[1] = k1 + __shfl_xor(s1, 16, 64);
-    r2[2] = k2 + __shfl_xor(s2, 16, 64);
-  }
-  // b4 = 0: b3 = 0 keeps {r2[0], r2[1]}, b3 = 1 keeps {r2[2]}
-  // b4 = 1: b3 = 0 keeps {r2[0]},        b3 = 1 keeps {r2[1]}
-  F r3[2];
-  {
-    F s0, k0, s1, k1;
+    double s0, k0, s1, k1;
     if (!b4) {
       s0 = b3 ? r2[0] : r2[2]; k0 = b3 ? r2[2] : r2[0];
-      s1 = b3 ? r2[1] : F(0);  k1 = b3 ? F(0) : r2[1];
+      s1 = b3 ? r2[1] : 0.0;   k1 = b3 ? 0.0 : r2[1];
     } else {
       s0 = b3 ? r2[0] : r2[1]; k0 = b3 ? r2[1] : r2[0];
-      s1 = F(0); k1 = F(0);
+      s1 = 0.0; k1 = 0.0;
     }
-    r3[0] = k0 + __shfl_xor(s0, 8, 64);
-    r3[1] = k1 + __shfl_xor(s1, 8, 64);
+    r3[0] = k0 + dpp<kDppRowMirror>(s0);
+    r3[1] = k1 + dpp<kDppRowMirror>(s1);
   }
-  // lanes still carrying two values (b4 = 0, b3 = 0) split on b2
+  // bit 2: lanes still carrying two values (b4 = 0, b3 = 0) split on b2
   const bool two = !b4 && !b3;
-  const F s4 = two ? (b2 ? r3[0] : r3[1]) : r3[0];
-  const F k4 = two ? (b2 ? r3[1] : r3[0]) : r3[0];
-  F r = k4 + __shfl_xor(s4, 4, 64);
-  r += __shfl_xor(r, 2, 64);
-  r += __shfl_xor(r, 1, 64);
-  idx = 5 * (int)b5 + (b4 ? 3 + (int)b3 : (b3 ? 2 : (int)b2));
+  const double s4 = two ? (b2 ? r3[0] : r3[1]) : r3[0];
+  const double k4 = two ? (b2 ? r3[1] : r3[0]) : r3[0];
+  double r = k4 + dpp<kDppHalfMirror>(s4);
+  r += dpp<kDppQuadXor2>(r);
+  r += dpp<kDppQuadXor1>(r);
+  idx = 5 * ((lane >> 5) & 1) + (b4 ? 3 + (int)b3 : (b3 ? 2 : (int)b2));
   writer = (lane & 3) == 0 && (two || !b2);
   return r;
 }
@@ -204,7 +238,7 @@ __global__ void __launch_bounds__(64) composite_bwd_kernel(
     const uint32_t* __restrict__ keyoff, const uint32_t* __restrict__ tile_nproc, float bg0,
     float bg1, float bg2, const float* __restrict__ g_rgb, const float* __restrict__ g_depth,
     const float* __restrict__ g_alpha, const float* __restrict__ t_final,
-    const int32_t* __restrict__ n_last, double* __restrict__ partial,
+    const int32_t* __restrict__ n_last, float* __restrict__ partial,
     uint32_t* __restrict__ stamp, const uint32_t* __restrict__ epoch_dev, int xcd_remap) {
   constexpr int PIX = TW * TH / kWave;
   constexpr int RPP = kWave / TW;
@@ -322,14 +356,15 @@ __global__ void __launch_bounds__(64) composite_bwd_kernel(
         gSyy -= dq * qy * qy;
       }
       if (__ballot(any) == 0) continue;
-      // FP64 from here on: a key's lane values cancel against each other and
-      // the per-record sum runs over up to thousands of keys
+      // The lanes' values of one key cancel against each other: sum them in
+      // FP64; the key's total is stored as FP32 and the per-record sum over
+      // its keys is FP64 again
       const double vals10[kNG] = {gu, gv, gSxx, gSxy, gSyy, gs, gc0, gc1, gc2, gz};
       int idx;
       bool writer;
-      const double tot = wave_transpose_sum10<double>(vals10, lane, idx, writer);
+      const double tot = wave_transpose_sum10(vals10, lane, idx, writer);
       const uint32_t sl = slot[j];
-      if (writer) partial[(size_t)sl * kNG + idx] = tot;
+      if (writer) partial[(size_t)sl * kNG + idx] = (float)tot;
       if (lane == 1) stamp[sl] = epoch;
     }
     __syncthreads();
@@ -358,7 +393,7 @@ static void launch_bwd_t(hipStream_t st, int n_tiles, int F, const FrameDesc* fr
                          const uint2* ranges, const uint32_t* vals, const Record* rec,
                          const uint2* trect, const uint32_t* keyoff, const uint32_t* nproc, const float* bg, const float* g_rgb,
                          const float* g_depth, const float* g_alpha, const float* t_final,
-                         const int32_t* n_last, double* partial, uint32_t* stamp,
+                         const int32_t* n_last, float* partial, uint32_t* stamp,
                          const uint32_t* epoch, bool remap) {
   const unsigned grid = remap ? (unsigned)(((n_tiles + 7) / 8) * 8) : (unsigned)n_tiles;
   hipLaunchKernelGGL((composite_bwd_kernel<TW, TH>), dim3(grid), dim3(kWave), 0, st, n_tiles, F,
@@ -393,7 +428,7 @@ void launch_composite_bwd(hipStream_t st, int tw, int th, int n_tiles, int F,
                           const Record* rec, const uint2* trect, const uint32_t* keyoff,
                           const uint32_t* nproc, const float* bg,
                           const float* g_rgb, const float* g_depth, const float* g_alpha,
-                          const float* t_final, const int32_t* n_last, double* partial,
+                          const float* t_final, const int32_t* n_last, float* partial,
                           uint32_t* stamp, const uint32_t* epoch, bool remap) {
   if (n_tiles <= 0) return;
 #define GSR_BWD(W, H)                                                                          \

@@ -367,10 +367,10 @@ gsr_status gsr_forward(gsr_context* ctx, const gsr_settings* s, int64_t n, const
     if ((rc = ensure(ctx, ctx->vals_a, c2 * 4, st))) return rc;
     if ((rc = ensure(ctx, ctx->keys_b, c2 * 4, st))) return rc;
     if ((rc = ensure(ctx, ctx->vals_b, c2 * 4, st))) return rc;
-    if ((rc = ensure(ctx, ctx->partial, c2 * kNG * 8, st))) return rc;
+    if ((rc = ensure(ctx, ctx->partial, c2 * kNG * 4, st))) return rc;
     if ((rc = ensure(ctx, ctx->stamp, c2 * 4, st, true))) return rc;
     ctx->key_cap = std::min({ctx->keys_a.bytes / 4, ctx->keys_b.bytes / 4, ctx->vals_a.bytes / 4,
-                             ctx->vals_b.bytes / 4, ctx->partial.bytes / (kNG * 8),
+                             ctx->vals_b.bytes / 4, ctx->partial.bytes / (kNG * 4),
                              ctx->stamp.bytes / 4});
     const size_t h2 = radix_hist_elems(ctx->key_cap);
     if ((rc = ensure(ctx, ctx->hist, h2 * 4, st))) return rc;
@@ -473,7 +473,7 @@ gsr_status gsr_backward(gsr_context* ctx, const float* g_rgb, const float* g_dep
                          P<uint32_t>(ctx->nproc), s.background, g_rgb,
                          g_depth, g_alpha,
                          P<float>(ctx->t_final), P<int32_t>(ctx->n_last),
-                         P<double>(ctx->partial), P<uint32_t>(ctx->stamp), d_epoch, remap);
+                         P<float>(ctx->partial), P<uint32_t>(ctx->stamp), d_epoch, remap);
   }
   // A9-A11 per-record reduce, chain rule, twist
   const int64_t waves = sv.n > 0 ? preprocess_bwd_waves(sv.n) : 0;
@@ -484,7 +484,7 @@ gsr_status gsr_backward(gsr_context* ctx, const float* g_rgb, const float* g_dep
     StageTimer t(ctx, st, timing, GSR_STAGE_PREPROCESS_BWD);
     launch_preprocess_bwd(st, sv.n, sv.F, P<FrameDesc>(ctx->frames), sv.poses, sv.means,
                           sv.log_scales, sv.quats, sv.opac, sv.sh, s.sh_degree,
-                          P<uint32_t>(ctx->keyoff), P<uint32_t>(ctx->ntiles), P<double>(ctx->partial),
+                          P<uint32_t>(ctx->keyoff), P<uint32_t>(ctx->ntiles), P<float>(ctx->partial),
                           P<uint32_t>(ctx->stamp), d_epoch, ctx->key_cap,
                           P<double>(ctx->grad2d), g_means, g_log_scales, g_quats, g_opac, g_sh,
                           P<double>(ctx->twist_part), g_twist);

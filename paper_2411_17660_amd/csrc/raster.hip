@@ -304,7 +304,8 @@ __global__ void __launch_bounds__(64) composite_bwd_kernel(
       const float dx = dx_of(R.u_hi, R.u_lo, px);
       const float a1dx = R.a1 * dx;
       const double c0 = R.c0, c1 = R.c1, c2 = R.c2, cz = R.z;
-      float gu = 0.f, gv = 0.f, gSxx = 0.f, gSxy = 0.f, gSyy = 0.f, gs = 0.f;
+      float gu = 0.f, gv = 0.f, gs = 0.f;
+      double gSxx = 0.0, gSxy = 0.0, gSyy = 0.0;
       float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f, gz = 0.f;
       bool any = false;
 #pragma unroll
@@ -351,9 +352,17 @@ __global__ void __launch_bounds__(64) composite_bwd_kernel(
         const float qy = __builtin_fmaf(R.a2, m, R.a3 * b);
         gu += 2.0f * dq * qx;
         gv += 2.0f * dq * qy;
-        gSxx -= dq * qx * qx;
-        gSxy -= dq * qx * qy;
-        gSyy -= dq * qy * qy;
+        // Each pixel adds the rank-1 matrix -dq (Q d)(Q d)^T.  Formed in FP64
+        // its three entries stay exactly rank-1; rounded one by one in FP32
+        // they would not, and a Gaussian at the near plane has scale
+        // gradients that read the near-null direction of the summed matrix.
+        {
+          const double dqd = dq, qxd = qx, qyd = qy;
+          const double t = dqd * qxd;
+          gSxx -= t * qxd;
+          gSxy -= t * qyd;
+          gSyy -= dqd * qyd * qyd;
+        }
       }
       if (__ballot(any) == 0) continue;
       // The lanes' values of one key cancel against each other: sum them in

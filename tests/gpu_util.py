@@ -84,8 +84,33 @@ def grad_bound(ref, rel=GRAD_REL):
     return rel * np.maximum(np.maximum(np.abs(flat), 1e-2 * blk), 1e-2 * rms)
 
 
-def assert_grad_close(name, got, ref, rel=GRAD_REL):
+PIXEL_REL = 1e-6   # modelled relative error of one pixel's FP32 contribution
+NOISE_MULT = 3.0
+
+
+def perturbed(G, seed=7):
+    """The upstream gradients with every pixel value scaled by (1 + 1e-6 xi),
+    xi ~ N(0, 1): the oracle's response to it is the size of gradient change
+    that per-pixel FP32 rounding can cause."""
+    rng = np.random.default_rng(seed)
+    return [np.asarray(x, np.float64) * (1.0 + PIXEL_REL * rng.standard_normal(np.size(x)))
+            for x in G]
+
+
+def noise_floor(ref, G, g_ref):
+    """|g(G') - g(G)| per element for the perturbed upstream G' (oracle)."""
+    g2 = ref.backward(*perturbed(G))
+    return {k: np.abs(g2[k] - g_ref[k]) for k in g_ref}
+
+
+def assert_grad_close(name, got, ref, rel=GRAD_REL, noise=None):
+    """|got - ref| <= max(rel * max(|g*|, 1e-2 |g*_block|, 1e-2 rms), 3 * noise):
+    the second term admits elements whose value the chain rule makes
+    sensitive to per-pixel FP32 rounding (a quadratic form in an indefinite
+    covariance gradient, a near-plane Gaussian), measured on the oracle."""
     bound = grad_bound(ref, rel)
+    if noise is not None:
+        bound = np.maximum(bound, NOISE_MULT * np.asarray(noise, np.float64).ravel())
     got = np.asarray(got, np.float64).ravel()
     ref = np.asarray(ref, np.float64).ravel()
     rms = np.sqrt(np.mean(ref ** 2)) if ref.size else 0.0
@@ -105,3 +130,43 @@ def assert_grad_close(name, got, ref, rel=GRAD_REL):
         raise AssertionError(f"{name}: {int(bad.sum())} of {ref.size} elements exceed the "
                              f"bound; worst idx {i}: got {got[i]!r} ref {ref[i]!r} "
                              f"bound {bound[i]!r}")
+
+
+def check_sampled_frames(rast, sc, out, G, frames, tile=(16, 16), label="", key_capacity=0):
+    """Full-size parity on sampled frames.  `out` = (rgb, depth, alpha) of the
+    batched GPU forward of `sc`; G = its upstream gradients.  For each sampled
+    frame the oracle renders that frame alone: the batched images must match
+    it on the pixels it does not flag, and a single-frame GPU forward and
+    backward on the masked upstream must match its gradients."""
+    import oracle
+    rgb, dep, alp = (np.asarray(x) for x in out)
+    sizes = [(int(c[0]), int(c[1])) for c in sc.cams]
+    offs = np.concatenate([[0], np.cumsum([w * h for w, h in sizes])])
+    for f in frames:
+        P0, P1 = int(offs[f]), int(offs[f + 1])
+        sf = sc.subset_frames([f])
+        print(f"[parity] {label} frame {f} {sizes[f]}: oracle", flush=True)
+        ref = oracle.forward(sf, tile=tile, threads=oracle_threads())
+        flags = ref.pixel_info()[0]
+        ok = flags == 0
+        ok3 = np.tile(ok, 3)
+        e_rgb = np.abs(rgb[3 * P0:3 * P1] - ref.rgb_flat)[ok3].max(initial=0.0)
+        e_dep = np.abs(dep[P0:P1] - ref.depth_flat)[ok].max(initial=0.0)
+        e_alp = np.abs(alp[P0:P1] - ref.alpha_flat)[ok].max(initial=0.0)
+        print(f"[parity]   max err rgb {e_rgb:.3g} depth {e_dep:.3g} alpha {e_alp:.3g}; "
+              f"flagged px {int((~ok).sum())} of {ok.size}; K {ref.K}", flush=True)
+        assert e_rgb <= IMG_TOL and e_dep <= IMG_TOL and e_alp <= IMG_TOL
+        Gf = masked_upstream((G[0][3 * P0:3 * P1], G[1][P0:P1], G[2][P0:P1]), flags, [sizes[f]])
+        g_ref = ref.backward(*[x.astype(np.float64) for x in Gf])
+        gpu_forward(rast, sf, tile, key_capacity=key_capacity)
+        L = rast.debug_lists()
+        assert L["K"] == ref.K
+        assert np.array_equal(L["n_last"][ok], ref.pixel_info()[1][ok])
+        g1 = gpu_backward(rast, Gf)
+        nz = noise_floor(ref, Gf, g_ref)
+        for k in ("means", "log_scales", "quats", "opacity", "sh"):
+            assert_grad_close(f"{label}f{f}:{k}", g1[k], g_ref[k], noise=nz[k])
+        tr = g_ref["twist"][0]
+        assert np.all(np.abs(g1["twist"][0] - tr)
+                      <= GRAD_REL * np.maximum(np.abs(tr), 1e-2 * np.abs(tr).max()))
+        del ref

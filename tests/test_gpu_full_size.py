@@ -1,0 +1,155 @@
+"""Parity at the full sizes of the uneven autotuned batch (16 keyframes of
+mixed resolution, 1M Gaussians with heavy-tailed scales) and of the mapping
+workload (3M Gaussians, 12 keyframes at 1920x1080), on sampled frames, plus
+the 100-iteration graph-captured mapping loop at full size checked through
+properties that hold at any size."""
+import numpy as np
+import pytest
+
+from gpu_util import check_sampled_frames, gpu_backward, gpu_forward, to_dev
+from paper_2411_17660_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rast():
+    from paper_2411_17660_amd.raster import Rasterizer
+    return Rasterizer(0)
+
+
+def _bufs(n, K, F, P):
+    import torch
+    dev = "cuda"
+    return dict(rgb=torch.empty(3 * P, device=dev), depth=torch.empty(P, device=dev),
+                alpha=torch.empty(P, device=dev), loss=torch.empty(1, device=dev),
+                means=torch.empty(n, 3, device=dev), log_scales=torch.empty(n, 3, device=dev),
+                quats=torch.empty(n, 4, device=dev), opacity=torch.empty(n, device=dev),
+                sh=torch.empty(n, K, 3, device=dev), twist=torch.empty(F, 6, device=dev))
+
+
+def test_c4_uneven_autotuned_batch_sampled_frames(rast):
+    import torch
+    sc = scenes.scene_c4()
+    P = sc.n_pixels
+    d = to_dev(sc)
+    zeros3, zeros1 = torch.zeros(3 * P, device="cuda"), torch.zeros(P, device="cuda")
+    tile, cap, times = rast.autotune(d["means"], d["log_scales"], d["quats"], d["opacity"],
+                                     d["sh"], d["poses"], sc.cams, sc.sh_degree, zeros3, zeros1,
+                                     1.0, background=sc.background, reps=2, force=True)
+    print(f"[c4] autotune {times} -> {tile}, capacity {cap}", flush=True)
+    G = scenes.upstream(4, sc)
+    _, rgb, dep, alp = gpu_forward(rast, sc, tile, key_capacity=cap)
+    rast.check_overflow()
+    K = rast.stats()["n_keys"]
+    print(f"[c4] K = {K} keys over {sc.n_frames} frames", flush=True)
+    gb = gpu_backward(rast, G)
+    for k, v in gb.items():
+        assert np.all(np.isfinite(v)), k
+    out = (rgb.cpu().numpy(), dep.cpu().numpy(), alp.cpu().numpy())
+    # the largest frame and a smallest one
+    sizes = [(int(c[0]), int(c[1])) for c in sc.cams]
+    big = max(range(sc.n_frames), key=lambda f: sizes[f][0] * sizes[f][1])
+    small = min(range(sc.n_frames), key=lambda f: sizes[f][0] * sizes[f][1])
+    check_sampled_frames(rast, sc, out, G, [small, big], tile=tile, label="c4")
+
+
+def test_c5_mapping_workload_step_and_loop(rast):
+    """One forward/backward of the 3M-Gaussian, 12 x 1920x1080 batch against
+    the oracle on a sampled frame; then 100 graph-replayed iterations of
+    forward + L1 loss + backward + fused Adam from perturbed parameters
+    towards targets rendered from the ground truth: the loss falls, nothing
+    overflows, the iteration counter reaches 100 and every value stays
+    finite.  The pose errors relative to the first frame are reported."""
+    import torch
+    gt = scenes.scene_c5()
+    rng = np.random.default_rng(5)
+    n, F, P, K = gt.n, gt.n_frames, gt.n_pixels, 16
+    init = scenes.Scene(
+        (gt.means + rng.normal(0, 0.01, gt.means.shape)).astype(np.float32), gt.log_scales,
+        gt.quats, gt.opacity, gt.sh.copy(), gt.sh_degree, gt.cams, gt.poses.copy(),
+        gt.background)
+    init.sh[:, 0, :] += rng.normal(0, 0.05, (n, 3)).astype(np.float32)
+    from oracle.adam import fold_pose
+    init.poses = np.stack([fold_pose(gt.poses[f].astype(np.float64),
+                                     rng.normal(0, 0.01, 6)) for f in range(F)]).astype(np.float32)
+    # one step at the initial parameters, sampled frame against the oracle
+    G = scenes.upstream(5, init)
+    _, rgb, dep, alp = gpu_forward(rast, init)
+    gb = gpu_backward(rast, G)
+    for k, v in gb.items():
+        assert np.all(np.isfinite(v)), k
+    out = (rgb.cpu().numpy(), dep.cpu().numpy(), alp.cpu().numpy())
+    check_sampled_frames(rast, init, out, G, [F // 2], label="c5")
+    # targets: the ground truth rendered by the same library
+    dg = to_dev(gt)
+    t_rgb, t_dep, _ = rast.forward(dg["means"], dg["log_scales"], dg["quats"], dg["opacity"],
+                                   dg["sh"], dg["poses"], gt.cams, gt.sh_degree, gt.background)
+    t_rgb, t_dep = t_rgb.clone(), t_dep.clone()
+    d = to_dev(init)
+    b = _bufs(n, K, F, P)
+    st = dict(m_means=torch.zeros(n, 3, device="cuda"), v_means=torch.zeros(n, 3, device="cuda"),
+              m_sh=torch.zeros(n, K, 3, device="cuda"), v_sh=torch.zeros(n, K, 3, device="cuda"),
+              m_twist=torch.zeros(F, 6, device="cuda"), v_twist=torch.zeros(F, 6, device="cuda"),
+              step=torch.zeros(1, dtype=torch.int32, device="cuda"))
+
+    def step(cap):
+        rast.step_l1(d["means"], d["log_scales"], d["quats"], d["opacity"], d["sh"], d["poses"],
+                     init.cams, init.sh_degree, t_rgb, t_dep, 0.1, b,
+                     background=init.background, key_capacity=cap)
+
+    def iteration(cap):
+        step(cap)
+        rast.adam_step(dict(means=d["means"], sh=d["sh"], poses=d["poses"]),
+                       dict(means=b["means"], sh=b["sh"], twist=b["twist"]), st)
+
+    step(0)
+    torch.cuda.synchronize()
+    loss0 = b["loss"].item()
+    cap = int(rast.stats()["n_keys"] * 1.1) + 4096
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        iteration(cap)                  # iteration 1, eager, off the default stream
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        iteration(cap)
+    torch.cuda.synchronize()
+    # capture does not run the work: iterations 2..100 are replays
+    losses = []
+    for it in range(99):
+        g.replay()
+        if it % 11 == 0:
+            torch.cuda.synchronize()
+            losses.append(b["loss"].item())
+            print(f"[c5] iteration {it + 2}: loss {losses[-1]:.6f}", flush=True)
+    torch.cuda.synchronize()
+    rast.check_overflow()
+    assert int(st["step"].item()) == 100
+    step(cap)
+    torch.cuda.synchronize()
+    loss_end = b["loss"].item()
+
+    def rel_pose_err(poses):
+        """Mean rotation (deg) and translation (m) error of each frame's pose
+        relative to frame 0, against the ground truth's: all poses move
+        freely, so the absolute error has a free rigid gauge."""
+        def rel(P):
+            P = P.astype(np.float64)
+            R0, t0 = P[0, :, :3], P[0, :, 3]
+            return [(P[f, :, :3] @ R0.T, P[f, :, 3] - P[f, :, :3] @ R0.T @ t0) for f in range(F)]
+        a, b = rel(poses), rel(gt.poses)
+        rot = [np.degrees(np.arccos(np.clip((np.trace(ra.T @ rb) - 1) / 2, -1, 1)))
+               for (ra, _), (rb, _) in zip(a, b)]
+        tr = [np.linalg.norm(ta - tb) for (_, ta), (_, tb) in zip(a, b)]
+        return float(np.mean(rot[1:])), float(np.mean(tr[1:]))
+
+    e0, e1 = rel_pose_err(init.poses), rel_pose_err(d["poses"].cpu().numpy())
+    print(f"[c5] loss {loss0:.6f} -> {loss_end:.6f}; relative pose error (deg, m) {e0} -> {e1}",
+          flush=True)
+    for k in ("means", "sh", "poses"):
+        assert torch.isfinite(d[k]).all(), k
+    assert np.isfinite(losses).all()
+    assert loss_end < loss0

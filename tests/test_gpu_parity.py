@@ -12,8 +12,8 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_util import (IMG_TOL, assert_grad_close, expand_rgb_mask, gpu_backward, gpu_forward,
-                      masked_upstream, oracle_threads)
+from gpu_util import (IMG_TOL, assert_grad_close, check_sampled_frames, expand_rgb_mask,
+                      gpu_backward, gpu_forward, masked_upstream, noise_floor, oracle_threads)
 from paper_2411_17660_amd import scenes
 
 pytestmark = pytest.mark.gpu
@@ -78,8 +78,9 @@ def check_backward(rast, sc, ref, flags, seed=0, label=""):
     Gm = masked_upstream(G, flags, _sizes(sc))
     g_gpu = gpu_backward(rast, Gm)
     g_ref = ref.backward(*[x.astype(np.float64) for x in Gm])
+    nz = noise_floor(ref, Gm, g_ref)
     for k in ("means", "log_scales", "quats", "opacity", "sh"):
-        assert_grad_close(f"{label}:{k}", g_gpu[k], g_ref[k])
+        assert_grad_close(f"{label}:{k}", g_gpu[k], g_ref[k], noise=nz[k])
     for f in range(sc.n_frames):
         tw, tr = g_gpu["twist"][f], g_ref["twist"][f]
         bound = 1e-3 * np.maximum(np.abs(tr), 1e-2 * np.abs(tr).max())
@@ -268,35 +269,14 @@ def test_l1_loss_and_step(rast):
 def test_c3_full_size_sampled_frames(rast):
     """The 500k-Gaussian, 8 x 1200x680 batch in the benchmark's launch
     configuration; the oracle recomputes frames 0 and 7 one at a time."""
-    import torch
     sc = scenes.scene_c3()
-    sizes = _sizes(sc)
     G = scenes.upstream(3, sc)
     d, rgb, dep, alp = gpu_forward(rast, sc)
     gb = gpu_backward(rast, G)
-    rgb, dep, alp = rgb.cpu().numpy(), dep.cpu().numpy(), alp.cpu().numpy()
-    P = sizes[0][0] * sizes[0][1]
-    for f in (0, 7):
-        sf = sc.subset_frames([f])
-        print(f"[parity] c3 frame {f}: oracle", flush=True)
-        ref = oracle.forward(sf, threads=oracle_threads())
-        flags = ref.pixel_info()[0]
-        ok = flags == 0
-        ok3 = np.tile(ok, 3)
-        sl, sl3 = slice(f * P, (f + 1) * P), slice(3 * f * P, 3 * (f + 1) * P)
-        assert np.abs(rgb[sl3] - ref.rgb_flat)[ok3].max() <= IMG_TOL
-        assert np.abs(dep[sl] - ref.depth_flat)[ok].max() <= IMG_TOL
-        assert np.abs(alp[sl] - ref.alpha_flat)[ok].max() <= IMG_TOL
-        Gf = masked_upstream((G[0][sl3], G[1][sl], G[2][sl]), flags, [sizes[f]])
-        g_ref = ref.backward(*[x.astype(np.float64) for x in Gf])
-        # single-frame GPU run on the same masked upstream
-        gpu_forward(rast, sf)
-        g1 = gpu_backward(rast, Gf)
-        for k in ("means", "log_scales", "quats", "opacity", "sh"):
-            assert_grad_close(f"c3f{f}:{k}", g1[k], g_ref[k])
-        tr = g_ref["twist"][0]
-        assert np.all(np.abs(g1["twist"][0] - tr) <= 1e-3 * np.maximum(np.abs(tr), 1e-2 * np.abs(tr).max()))
-    del torch
+    for k, v in gb.items():
+        assert np.all(np.isfinite(v)), k
+    out = (rgb.cpu().numpy(), dep.cpu().numpy(), alp.cpu().numpy())
+    check_sampled_frames(rast, sc, out, G, [0, 7], label="c3")
 
 
 # ---------------------------------------------------------------------- graphs

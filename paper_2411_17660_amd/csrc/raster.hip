@@ -35,27 +35,79 @@
 
 namespace gsr {
 
-__device__ __forceinline__ int tile_of_block(int bid, int n_tiles, bool xcd_remap) {
-  if (!xcd_remap) return bid;
-  // Consecutive workgroups go to the 8 XCDs in turn; give each XCD a
-  // contiguous run of tiles so neighbouring tiles share its L2.
-  const int per = (n_tiles + 7) / 8;
-  return (bid & 7) * per + (bid >> 3);
+// Tile schedule.  The tiles are split into kQueues groups of contiguous tile
+// ids (neighbouring tiles share Gaussians, so a group shares one XCD's L2);
+// workgroups are dealt to the XCDs in turn, so workgroup b runs on XCD
+// b % kQueues and takes the (b / kQueues)-th tile of that group.  The
+// hardware dispatches workgroups in index order, so sorting each group by
+// descending expected work gives a longest-first list schedule without any
+// queue or atomic: long tiles start first and the short ones fill the tail.
+constexpr int kQueues = 8;
+constexpr int kOrderBins = 1024;
+
+__device__ __forceinline__ uint32_t work_bucket(uint32_t w) {
+  if (w == 0) return 0;
+  const int lz = __clz(w);
+  const int e = 31 - lz;                                      // floor(log2 w)
+  const uint32_t frac = e > 0 ? ((w << (lz + 1)) >> 27) : 0;  // next 5 bits
+  return min((uint32_t)kOrderBins - 1, 1u + (uint32_t)e * 32u + frac);
+}
+
+// One workgroup per group: a counting sort of the group's tiles by
+// descending work bucket (order inside a bucket is arbitrary; results do not
+// depend on it).  Work = processed entries of a previous forward over the
+// same tiles (`nproc`); without it the tiles keep their spatial order.
+__global__ void __launch_bounds__(1024) tile_order_kernel(int n_tiles, int groups,
+                                                          const uint32_t* __restrict__ nproc,
+                                                          uint32_t* __restrict__ order) {
+  __shared__ uint32_t bins[kOrderBins];
+  const int q = blockIdx.x;
+  const int per = (n_tiles + groups - 1) / groups;
+  const int t0 = q * per, t1 = min(n_tiles, t0 + per);
+  for (int i = threadIdx.x; i < kOrderBins; i += blockDim.x) bins[i] = 0;
+  __syncthreads();
+  if (!nproc) {
+    for (int t = t0 + (int)threadIdx.x; t < t1; t += blockDim.x) order[t] = (uint32_t)t;
+    return;
+  }
+  for (int t = t0 + (int)threadIdx.x; t < t1; t += blockDim.x)
+    atomicAdd(&bins[work_bucket(nproc[t])], 1u);
+  __syncthreads();
+  if (threadIdx.x == 0) {  // exclusive offsets, largest bucket first
+    uint32_t run = 0;
+    for (int i = kOrderBins - 1; i >= 0; --i) {
+      const uint32_t c = bins[i];
+      bins[i] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  for (int t = t0 + (int)threadIdx.x; t < t1; t += blockDim.x) {
+    const uint32_t pos = atomicAdd(&bins[work_bucket(nproc[t])], 1u);
+    order[t0 + pos] = (uint32_t)t;
+  }
+}
+
+// The tile of workgroup `bid`, or -1 past the end of its group.
+__device__ __forceinline__ int tile_of_block(int bid, int n_tiles, int groups,
+                                             const uint32_t* __restrict__ order) {
+  const int per = (n_tiles + groups - 1) / groups;
+  const int q = bid % groups, i = bid / groups;
+  const int pos = q * per + i;
+  if (i >= per || pos >= n_tiles) return -1;
+  return (int)order[pos];
 }
 
 template <int TW, int TH, bool COUNT>
-__global__ void __launch_bounds__(64) composite_fwd_kernel(
-    int n_tiles, int n_frames, const FrameDesc* __restrict__ frames,
+__device__ __forceinline__ void composite_fwd_tile(
+    int tile, Record* sm, int n_frames, const FrameDesc* __restrict__ frames,
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals,
     const Record* __restrict__ rec, float bg0, float bg1, float bg2, float* __restrict__ rgb,
     float* __restrict__ depth, float* __restrict__ alpha, float* __restrict__ t_final,
-    int32_t* __restrict__ n_last, uint32_t* __restrict__ tile_nproc, int xcd_remap,
+    int32_t* __restrict__ n_last, uint32_t* __restrict__ tile_nproc,
     unsigned long long* __restrict__ pair_count) {
   constexpr int PIX = TW * TH / kWave;
   constexpr int RPP = kWave / TW;  // rows per strip
-  __shared__ Record sm[kWave];
-  const int tile = tile_of_block(blockIdx.x, n_tiles, xcd_remap != 0);
-  if (tile >= n_tiles) return;
   const int f = frame_of_tile(frames, n_frames, tile);
   const FrameDesc fr = frames[f];
   const int lt = tile - fr.tile_offset;
@@ -185,6 +237,21 @@ __device__ __forceinline__ double dpp(double v) {
 constexpr int kDppRowMirror = 0x140, kDppHalfMirror = 0x141, kDppQuadXor2 = 0x4e,
               kDppQuadXor1 = 0xb1;
 
+template <int TW, int TH, bool COUNT>
+__global__ void __launch_bounds__(64) composite_fwd_kernel(
+    int n_tiles, int groups, const uint32_t* __restrict__ order, int n_frames,
+    const FrameDesc* __restrict__ frames, const uint2* __restrict__ ranges,
+    const uint32_t* __restrict__ vals, const Record* __restrict__ rec, float bg0, float bg1,
+    float bg2, float* __restrict__ rgb, float* __restrict__ depth, float* __restrict__ alpha,
+    float* __restrict__ t_final, int32_t* __restrict__ n_last, uint32_t* __restrict__ tile_nproc,
+    unsigned long long* __restrict__ pair_count) {
+  __shared__ Record sm[kWave];
+  const int tile = tile_of_block(blockIdx.x, n_tiles, groups, order);
+  if (tile < 0) return;
+  composite_fwd_tile<TW, TH, COUNT>(tile, sm, n_frames, frames, ranges, vals, rec, bg0, bg1, bg2,
+                                     rgb, depth, alpha, t_final, n_last, tile_nproc, pair_count);
+}
+
 // Sums v[0..9] over the 64 lanes of the wave in FP64.  Each butterfly round
 // halves the set of values a lane carries (10 -> 5 -> 3|2 -> 2|1 -> 1) before
 // the plain rounds over lane bits 1 and 0.  On return lane l holds the total
@@ -231,22 +298,18 @@ __device__ __forceinline__ double wave_transpose_sum10(const double v[10], int l
 }
 
 template <int TW, int TH>
-__global__ void __launch_bounds__(64) composite_bwd_kernel(
-    int n_tiles, int n_frames, const FrameDesc* __restrict__ frames,
+__device__ __forceinline__ void composite_bwd_tile(
+    int tile, Record* sm, uint32_t* slot, uint32_t epoch, int n_frames,
+    const FrameDesc* __restrict__ frames,
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals,
     const Record* __restrict__ rec, const uint2* __restrict__ trect,
     const uint32_t* __restrict__ keyoff, const uint32_t* __restrict__ tile_nproc, float bg0,
     float bg1, float bg2, const float* __restrict__ g_rgb, const float* __restrict__ g_depth,
     const float* __restrict__ g_alpha, const float* __restrict__ t_final,
     const int32_t* __restrict__ n_last, float* __restrict__ partial,
-    uint32_t* __restrict__ stamp, const uint32_t* __restrict__ epoch_dev, int xcd_remap) {
+    uint32_t* __restrict__ stamp) {
   constexpr int PIX = TW * TH / kWave;
   constexpr int RPP = kWave / TW;
-  __shared__ Record sm[kWave];
-  __shared__ uint32_t slot[kWave];
-  const uint32_t epoch = *epoch_dev;
-  const int tile = tile_of_block(blockIdx.x, n_tiles, xcd_remap != 0);
-  if (tile >= n_tiles) return;
   const uint32_t nproc = tile_nproc[tile];
   if (nproc == 0) return;
   const int f = frame_of_tile(frames, n_frames, tile);
@@ -381,33 +444,66 @@ __global__ void __launch_bounds__(64) composite_bwd_kernel(
 }
 
 template <int TW, int TH>
-static void launch_fwd_t(hipStream_t st, int n_tiles, int F, const FrameDesc* frames,
-                         const uint2* ranges, const uint32_t* vals, const Record* rec,
-                         const float* bg, float* rgb, float* depth, float* alpha,
-                         float* t_final, int32_t* n_last, uint32_t* nproc, bool remap,
-                         unsigned long long* pairs) {
-  const unsigned grid = remap ? (unsigned)(((n_tiles + 7) / 8) * 8) : (unsigned)n_tiles;
-  if (pairs)
-    hipLaunchKernelGGL((composite_fwd_kernel<TW, TH, true>), dim3(grid), dim3(kWave), 0, st,
-                       n_tiles, F, frames, ranges, vals, rec, bg[0], bg[1], bg[2], rgb, depth,
-                       alpha, t_final, n_last, nproc, remap ? 1 : 0, pairs);
-  else
-    hipLaunchKernelGGL((composite_fwd_kernel<TW, TH, false>), dim3(grid), dim3(kWave), 0, st,
-                       n_tiles, F, frames, ranges, vals, rec, bg[0], bg[1], bg[2], rgb, depth,
-                       alpha, t_final, n_last, nproc, remap ? 1 : 0, pairs);
+__global__ void __launch_bounds__(64) composite_bwd_kernel(
+    int n_tiles, int groups, const uint32_t* __restrict__ order, int n_frames,
+    const FrameDesc* __restrict__ frames, const uint2* __restrict__ ranges,
+    const uint32_t* __restrict__ vals, const Record* __restrict__ rec,
+    const uint2* __restrict__ trect, const uint32_t* __restrict__ keyoff,
+    const uint32_t* __restrict__ tile_nproc, float bg0, float bg1, float bg2,
+    const float* __restrict__ g_rgb, const float* __restrict__ g_depth,
+    const float* __restrict__ g_alpha, const float* __restrict__ t_final,
+    const int32_t* __restrict__ n_last, float* __restrict__ partial,
+    uint32_t* __restrict__ stamp, const uint32_t* __restrict__ epoch_dev) {
+  __shared__ Record sm[kWave];
+  __shared__ uint32_t slot[kWave];
+  const int tile = tile_of_block(blockIdx.x, n_tiles, groups, order);
+  if (tile < 0) return;
+  const uint32_t epoch = *epoch_dev;
+  composite_bwd_tile<TW, TH>(tile, sm, slot, epoch, n_frames, frames, ranges, vals, rec, trect,
+                             keyoff, tile_nproc, bg0, bg1, bg2, g_rgb, g_depth, g_alpha, t_final,
+                             n_last, partial, stamp);
+}
+
+static void launch_order(hipStream_t st, int n_tiles, int groups, const uint32_t* nproc,
+                         uint32_t* order) {
+  hipLaunchKernelGGL(tile_order_kernel, dim3((unsigned)groups), dim3(1024), 0, st, n_tiles,
+                     groups, nproc, order);
+}
+
+static unsigned grid_of(int n_tiles, int groups) {
+  return (unsigned)(((n_tiles + groups - 1) / groups) * groups);
 }
 
 template <int TW, int TH>
-static void launch_bwd_t(hipStream_t st, int n_tiles, int F, const FrameDesc* frames,
-                         const uint2* ranges, const uint32_t* vals, const Record* rec,
-                         const uint2* trect, const uint32_t* keyoff, const uint32_t* nproc, const float* bg, const float* g_rgb,
-                         const float* g_depth, const float* g_alpha, const float* t_final,
-                         const int32_t* n_last, float* partial, uint32_t* stamp,
-                         const uint32_t* epoch, bool remap) {
-  const unsigned grid = remap ? (unsigned)(((n_tiles + 7) / 8) * 8) : (unsigned)n_tiles;
-  hipLaunchKernelGGL((composite_bwd_kernel<TW, TH>), dim3(grid), dim3(kWave), 0, st, n_tiles, F,
-                     frames, ranges, vals, rec, trect, keyoff, nproc, bg[0], bg[1], bg[2], g_rgb,
-                     g_depth, g_alpha, t_final, n_last, partial, stamp, epoch, remap ? 1 : 0);
+static void launch_fwd_t(hipStream_t st, int n_tiles, int groups, const uint32_t* order, int F, const FrameDesc* frames, const uint2* ranges,
+                         const uint32_t* vals, const Record* rec, const float* bg, float* rgb,
+                         float* depth, float* alpha, float* t_final, int32_t* n_last,
+                         uint32_t* nproc, unsigned long long* pairs) {
+  if (pairs) {
+    auto k = composite_fwd_kernel<TW, TH, true>;
+    hipLaunchKernelGGL(k, dim3(grid_of(n_tiles, groups)), dim3(kWave), 0, st, n_tiles,
+                       groups, order, F, frames, ranges, vals, rec, bg[0], bg[1], bg[2],
+                       rgb, depth, alpha, t_final, n_last, nproc, pairs);
+  } else {
+    auto k = composite_fwd_kernel<TW, TH, false>;
+    hipLaunchKernelGGL(k, dim3(grid_of(n_tiles, groups)), dim3(kWave), 0, st, n_tiles,
+                       groups, order, F, frames, ranges, vals, rec, bg[0], bg[1], bg[2],
+                       rgb, depth, alpha, t_final, n_last, nproc, pairs);
+  }
+}
+
+template <int TW, int TH>
+static void launch_bwd_t(hipStream_t st, int n_tiles, int groups, const uint32_t* order, int F, const FrameDesc* frames, const uint2* ranges,
+                         const uint32_t* vals, const Record* rec, const uint2* trect,
+                         const uint32_t* keyoff, const uint32_t* nproc, const float* bg,
+                         const float* g_rgb, const float* g_depth, const float* g_alpha,
+                         const float* t_final, const int32_t* n_last, float* partial,
+                         uint32_t* stamp, const uint32_t* epoch) {
+  auto k = composite_bwd_kernel<TW, TH>;
+  hipLaunchKernelGGL(k, dim3(grid_of(n_tiles, groups)), dim3(kWave), 0, st, n_tiles,
+                     groups, order, F, frames, ranges, vals, rec, trect, keyoff, nproc,
+                     bg[0], bg[1], bg[2], g_rgb, g_depth, g_alpha, t_final, n_last, partial,
+                     stamp, epoch);
 }
 
 bool tile_shape_supported(int tw, int th) {
@@ -419,11 +515,14 @@ void launch_composite_fwd(hipStream_t st, int tw, int th, int n_tiles, int F,
                           const FrameDesc* frames, const uint2* ranges, const uint32_t* vals,
                           const Record* rec, const float* bg, float* rgb, float* depth,
                           float* alpha, float* t_final, int32_t* n_last, uint32_t* nproc,
-                          bool remap, unsigned long long* pairs) {
+                          const uint32_t* prev_nproc, uint32_t* order, bool xcd_groups,
+                          unsigned long long* pairs) {
   if (n_tiles <= 0) return;
-#define GSR_FWD(W, H)                                                                        \
-  launch_fwd_t<W, H>(st, n_tiles, F, frames, ranges, vals, rec, bg, rgb, depth, alpha, t_final, \
-                     n_last, nproc, remap, pairs)
+  const int groups = xcd_groups ? kQueues : 1;
+  launch_order(st, n_tiles, groups, prev_nproc, order);
+#define GSR_FWD(W, H)                                                                         \
+  launch_fwd_t<W, H>(st, n_tiles, groups, order, F, frames, ranges, vals, rec, bg, rgb,         \
+                     depth, alpha, t_final, n_last, nproc, pairs)
   if (tw == 16 && th == 16) GSR_FWD(16, 16);
   else if (tw == 8 && th == 8) GSR_FWD(8, 8);
   else if (tw == 32 && th == 8) GSR_FWD(32, 8);
@@ -435,14 +534,17 @@ void launch_composite_fwd(hipStream_t st, int tw, int th, int n_tiles, int F,
 void launch_composite_bwd(hipStream_t st, int tw, int th, int n_tiles, int F,
                           const FrameDesc* frames, const uint2* ranges, const uint32_t* vals,
                           const Record* rec, const uint2* trect, const uint32_t* keyoff,
-                          const uint32_t* nproc, const float* bg,
-                          const float* g_rgb, const float* g_depth, const float* g_alpha,
-                          const float* t_final, const int32_t* n_last, float* partial,
-                          uint32_t* stamp, const uint32_t* epoch, bool remap) {
+                          const uint32_t* nproc, const float* bg, const float* g_rgb,
+                          const float* g_depth, const float* g_alpha, const float* t_final,
+                          const int32_t* n_last, float* partial, uint32_t* stamp,
+                          const uint32_t* epoch, uint32_t* order, bool xcd_groups) {
   if (n_tiles <= 0) return;
+  const int groups = xcd_groups ? kQueues : 1;
+  launch_order(st, n_tiles, groups, nproc, order);
 #define GSR_BWD(W, H)                                                                          \
-  launch_bwd_t<W, H>(st, n_tiles, F, frames, ranges, vals, rec, trect, keyoff, nproc, bg,    \
-                     g_rgb, g_depth, g_alpha, t_final, n_last, partial, stamp, epoch, remap)
+  launch_bwd_t<W, H>(st, n_tiles, groups, order, F, frames, ranges, vals, rec, trect,          \
+                     keyoff, nproc, bg, g_rgb, g_depth, g_alpha, t_final, n_last, partial,     \
+                     stamp, epoch)
   if (tw == 16 && th == 16) GSR_BWD(16, 16);
   else if (tw == 8 && th == 8) GSR_BWD(8, 8);
   else if (tw == 32 && th == 8) GSR_BWD(32, 8);

@@ -50,6 +50,11 @@ struct gsr_context {
   DBuf ranges, nproc, t_final, n_last, frames, twist_part, loss_part, loss_scale;
   DBuf up_rgb, up_depth, up_alpha;  // upstream gradients for gsr_step_l1
   DBuf tune_out;                    // scratch outputs of the autotuner
+  DBuf order_f, order_b;            // compositing tile schedules (forward, backward)
+  // layout (tile shape and frame sizes) whose processed-entry counts nproc
+  // holds, so that the next forward over the same tiles can order its queue
+  // by them; empty when nproc holds none
+  std::vector<int32_t> nproc_layout;
   std::map<std::string, gsr_settings> tune_cache;
   uint64_t key_cap = 0;             // allocated key slots
   // pinned host staging
@@ -251,7 +256,8 @@ gsr_status gsr_destroy(gsr_context* ctx) {
                   &ctx->grad2d,
                   &ctx->stamp, &ctx->ranges, &ctx->nproc, &ctx->t_final, &ctx->n_last,
                   &ctx->frames, &ctx->twist_part, &ctx->loss_part, &ctx->loss_scale,
-                  &ctx->up_rgb, &ctx->up_depth, &ctx->up_alpha, &ctx->tune_out};
+                  &ctx->up_rgb, &ctx->up_depth, &ctx->up_alpha, &ctx->tune_out,
+                  &ctx->order_f, &ctx->order_b};
   for (DBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (ctx->h_frames) (void)hipHostFree(ctx->h_frames);
@@ -311,7 +317,16 @@ gsr_status gsr_forward(gsr_context* ctx, const gsr_settings* s, int64_t n, const
   if ((rc = ensure(ctx, ctx->offsets, M * 8, st))) return rc;
   if ((rc = ensure(ctx, ctx->counters, 64, st, true))) return rc;
   if ((rc = ensure(ctx, ctx->ranges, (size_t)T * 8, st))) return rc;
+  std::vector<int32_t> layout = {tw, th};
+  for (int f = 0; f < F; ++f) {
+    layout.push_back(cams[f].width);
+    layout.push_back(cams[f].height);
+  }
+  const void* nproc_before = ctx->nproc.p;
   if ((rc = ensure(ctx, ctx->nproc, (size_t)T * 4, st))) return rc;
+  const bool have_prev = ctx->nproc.p == nproc_before && ctx->nproc_layout == layout;
+  if ((rc = ensure(ctx, ctx->order_f, (size_t)T * 4, st))) return rc;
+  if ((rc = ensure(ctx, ctx->order_b, (size_t)T * 4, st))) return rc;
   if ((rc = ensure(ctx, ctx->t_final, (size_t)Px * 4, st))) return rc;
   if ((rc = ensure(ctx, ctx->n_last, (size_t)Px * 4, st))) return rc;
   uint64_t* d_count = P<uint64_t>(ctx->counters);               // [0] = K
@@ -416,8 +431,10 @@ gsr_status gsr_forward(gsr_context* ctx, const gsr_settings* s, int64_t n, const
     launch_composite_fwd(st, tw, th, (int)T, F, P<FrameDesc>(ctx->frames),
                          P<uint2>(ctx->ranges), svals, P<Record>(ctx->rec), s->background, rgb,
                          depth, alpha, P<float>(ctx->t_final), P<int32_t>(ctx->n_last),
-                         P<uint32_t>(ctx->nproc), remap, count ? d_pairs : nullptr);
+                         P<uint32_t>(ctx->nproc), have_prev ? P<uint32_t>(ctx->nproc) : nullptr,
+                         P<uint32_t>(ctx->order_f), remap, count ? d_pairs : nullptr);
   }
+  ctx->nproc_layout = layout;
   ctx->n_pairs = count ? -2 : -1;  // -2: count pending on the device
   GSR_HIP(hipGetLastError());
   Saved& sv = ctx->s;
@@ -473,7 +490,8 @@ gsr_status gsr_backward(gsr_context* ctx, const float* g_rgb, const float* g_dep
                          P<uint32_t>(ctx->nproc), s.background, g_rgb,
                          g_depth, g_alpha,
                          P<float>(ctx->t_final), P<int32_t>(ctx->n_last),
-                         P<float>(ctx->partial), P<uint32_t>(ctx->stamp), d_epoch, remap);
+                         P<float>(ctx->partial), P<uint32_t>(ctx->stamp), d_epoch,
+                         P<uint32_t>(ctx->order_b), remap);
   }
   // A9-A11 per-record reduce, chain rule, twist
   const int64_t waves = sv.n > 0 ? preprocess_bwd_waves(sv.n) : 0;

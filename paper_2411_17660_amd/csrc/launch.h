@@ -16,11 +16,16 @@ int64_t preprocess_bwd_waves(int64_t n);
 void launch_preprocess_bwd(hipStream_t st, int64_t n, int F, const FrameDesc* frames,
                            const float* poses, const float* means, const float* log_scales,
                            const float* quats, const float* opac, const float* sh, int deg,
-                           const uint32_t* keyoff, const uint32_t* ntiles, const float* partial,
+                           const uint32_t* order, const uint32_t* keyoff,
+                           const uint32_t* ntiles, const float* partial,
                            const uint32_t* stamp, const uint32_t* epoch, uint64_t key_capacity,
                            double* grad2d, float* g_means, float* g_log_scales, float* g_quats,
                            float* g_opac, float* g_sh, double* twist_partial, float* g_twist);
 void launch_bump_epoch(hipStream_t st, uint32_t* epoch);
+// cls[r] = 1 + floor(log2(ntiles[r])) (0 when culled), idx[r] = r: the input
+// of the radix sort that orders the per-record reduction
+void launch_size_class(hipStream_t st, uint64_t m, const uint32_t* ntiles, uint32_t* cls,
+                       uint32_t* idx);
 
 // sort.hip: depth sort, offsets, key generation, tile sort, ranges
 void launch_fill_u32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t v);

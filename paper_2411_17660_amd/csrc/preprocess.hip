@@ -308,24 +308,41 @@ __global__ void __launch_bounds__(256) preprocess_fwd_kernel(
 }
 
 // --------------------------------------------------------------------------
-// A9: per-record reduction of the key partials.  A group of 16 lanes owns one
+// A9: per-record reduction of the key partials.  A group of 8 lanes owns one
 // record and strides over its contiguous key slots (coalesced stamp and
 // partial reads); slots not stamped with this backward's epoch belong to
 // keys behind every pixel's stop and are skipped.  Lane sums are FP64 and the
 // group combines them with a fixed butterfly, so the result is deterministic.
+// The records are visited in order of their key count (a one-pass radix sort
+// by floor(log2(count)), `order`): a wave's eight records then have similar
+// counts, instead of waiting on the one Gaussian in eight that covers
+// hundreds of tiles.
 // --------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) size_class_kernel(uint64_t m,
+                                                         const uint32_t* __restrict__ ntiles,
+                                                         uint32_t* __restrict__ cls,
+                                                         uint32_t* __restrict__ idx) {
+  const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= m) return;
+  const uint32_t c = ntiles[r];
+  cls[r] = c == 0 ? 0u : 32u - (uint32_t)__clz(c);  // 1 + floor(log2 c)
+  idx[r] = (uint32_t)r;
+}
+
 constexpr int kSlotGroup = 8;
 
 __global__ void __launch_bounds__(256) slot_reduce_kernel(
-    uint64_t m, const uint32_t* __restrict__ keyoff, const uint32_t* __restrict__ ntiles,
+    uint64_t m, const uint32_t* __restrict__ order, const uint32_t* __restrict__ keyoff,
+    const uint32_t* __restrict__ ntiles,
     const float* __restrict__ partial, const uint32_t* __restrict__ stamp,
     const uint32_t* __restrict__ epoch_dev, uint64_t key_capacity,
     double* __restrict__ grad2d /* [m][kNG] */) {
   const uint32_t epoch = *epoch_dev;
   const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t r = gid / kSlotGroup;
+  const uint64_t k = gid / kSlotGroup;
   const int sub = threadIdx.x & (kSlotGroup - 1);
-  const bool active = r < m;
+  const bool active = k < m;
+  const uint64_t r = active ? order[k] : 0;
   uint32_t cnt = active ? ntiles[r] : 0u;
   const uint32_t off = cnt ? keyoff[r] : 0u;
   if (cnt && (uint64_t)off + cnt > key_capacity) cnt = 0;  // overflowed in keygen
@@ -566,6 +583,13 @@ __global__ void bump_epoch_kernel(uint32_t* epoch) {
   *epoch = e == 0u ? 1u : e;
 }
 
+void launch_size_class(hipStream_t st, uint64_t m, const uint32_t* ntiles, uint32_t* cls,
+                       uint32_t* idx) {
+  if (m == 0) return;
+  hipLaunchKernelGGL(size_class_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, m,
+                     ntiles, cls, idx);
+}
+
 void launch_bump_epoch(hipStream_t st, uint32_t* epoch) {
   hipLaunchKernelGGL(bump_epoch_kernel, dim3(1), dim3(1), 0, st, epoch);
 }
@@ -616,7 +640,8 @@ int64_t preprocess_bwd_waves(int64_t n) { return ((n + 255) / 256) * 4; }
 void launch_preprocess_bwd(hipStream_t st, int64_t n, int F, const FrameDesc* frames,
                            const float* poses, const float* means, const float* log_scales,
                            const float* quats, const float* opac, const float* sh, int deg,
-                           const uint32_t* keyoff, const uint32_t* ntiles, const float* partial,
+                           const uint32_t* order, const uint32_t* keyoff,
+                           const uint32_t* ntiles, const float* partial,
                            const uint32_t* stamp, const uint32_t* epoch, uint64_t key_capacity,
                            double* grad2d, float* g_means, float* g_log_scales, float* g_quats,
                            float* g_opac, float* g_sh, double* twist_partial, float* g_twist) {
@@ -629,7 +654,7 @@ void launch_preprocess_bwd(hipStream_t st, int64_t n, int F, const FrameDesc* fr
     const uint64_t m = (uint64_t)n * F;
     const uint64_t threads = m * kSlotGroup;
     hipLaunchKernelGGL(slot_reduce_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0,
-                       st, m, keyoff, ntiles, partial, stamp, epoch, key_capacity, grad2d);
+                       st, m, order, keyoff, ntiles, partial, stamp, epoch, key_capacity, grad2d);
     switch (deg) {
       case 0: GSR_PRE_BWD(0); break;
       case 1: GSR_PRE_BWD(1); break;

@@ -51,6 +51,7 @@ struct gsr_context {
   DBuf up_rgb, up_depth, up_alpha;  // upstream gradients for gsr_step_l1
   DBuf tune_out;                    // scratch outputs of the autotuner
   DBuf order_f, order_b;            // compositing tile schedules (forward, backward)
+  DBuf cls_a, cls_b, clsv_a, clsv_b;  // records ordered by key count (per-record reduction)
   // layout (tile shape and frame sizes) whose processed-entry counts nproc
   // holds, so that the next forward over the same tiles can order its queue
   // by them; empty when nproc holds none
@@ -257,7 +258,8 @@ gsr_status gsr_destroy(gsr_context* ctx) {
                   &ctx->stamp, &ctx->ranges, &ctx->nproc, &ctx->t_final, &ctx->n_last,
                   &ctx->frames, &ctx->twist_part, &ctx->loss_part, &ctx->loss_scale,
                   &ctx->up_rgb, &ctx->up_depth, &ctx->up_alpha, &ctx->tune_out,
-                  &ctx->order_f, &ctx->order_b};
+                  &ctx->order_f, &ctx->order_b, &ctx->cls_a, &ctx->cls_b, &ctx->clsv_a,
+                  &ctx->clsv_b};
   for (DBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (ctx->h_frames) (void)hipHostFree(ctx->h_frames);
@@ -498,10 +500,24 @@ gsr_status gsr_backward(gsr_context* ctx, const float* g_rgb, const float* g_dep
   if ((rc = ensure(ctx, ctx->twist_part, (size_t)std::max<int64_t>(waves, 1) * sv.F * 6 * 8, st)))
     return rc;
   if ((rc = ensure(ctx, ctx->grad2d, (size_t)sv.n * sv.F * kNG * 8, st))) return rc;
+  const uint64_t M = (uint64_t)sv.n * sv.F;
+  if ((rc = ensure(ctx, ctx->cls_a, M * 4, st))) return rc;
+  if ((rc = ensure(ctx, ctx->cls_b, M * 4, st))) return rc;
+  if ((rc = ensure(ctx, ctx->clsv_a, M * 4, st))) return rc;
+  if ((rc = ensure(ctx, ctx->clsv_b, M * 4, st))) return rc;
   {
     StageTimer t(ctx, st, timing, GSR_STAGE_PREPROCESS_BWD);
+    bool cls_in_b = false;
+    if (M > 0) {
+      launch_size_class(st, M, P<uint32_t>(ctx->ntiles), P<uint32_t>(ctx->cls_a),
+                        P<uint32_t>(ctx->clsv_a));
+      cls_in_b = launch_radix_sort(st, P<uint32_t>(ctx->cls_a), P<uint32_t>(ctx->clsv_a),
+                                   P<uint32_t>(ctx->cls_b), P<uint32_t>(ctx->clsv_b), nullptr, M,
+                                   8, P<uint32_t>(ctx->hist), P<uint32_t>(ctx->scan_tmp));
+    }
     launch_preprocess_bwd(st, sv.n, sv.F, P<FrameDesc>(ctx->frames), sv.poses, sv.means,
                           sv.log_scales, sv.quats, sv.opac, sv.sh, s.sh_degree,
+                          P<uint32_t>(cls_in_b ? ctx->clsv_b : ctx->clsv_a),
                           P<uint32_t>(ctx->keyoff), P<uint32_t>(ctx->ntiles), P<float>(ctx->partial),
                           P<uint32_t>(ctx->stamp), d_epoch, ctx->key_cap,
                           P<double>(ctx->grad2d), g_means, g_log_scales, g_quats, g_opac, g_sh,

@@ -130,11 +130,11 @@ __global__ void __launch_bounds__(kScanThreads) scan_down_kernel(Load ld, const 
 // ---------------------------------------------------------------------------
 // LSD radix pass, 8-bit digit at `shift`, stable.
 //
-// Both kernels see a block as 4 waves x 16 rounds x 64 keys, wave w owning a
-// contiguous quarter.  Per round a wave ranks its 64 keys by digit with 8
-// ballots (lanes with equal digits form one mask); the lowest lane of each
-// group bumps the wave's LDS counter.  No atomics, so the counts and ranks
-// are deterministic and the scatter is stable.
+// A block owns kSortTile consecutive keys.  The scatter sees it as 4 waves x
+// 16 rounds x 64 keys, wave w owning a contiguous quarter.  Per round a wave
+// ranks its 64 keys by digit with 8 ballots (lanes with equal digits form
+// one mask); the lowest lane of each group bumps the wave's LDS counter.  No
+// atomics there, so the ranks are deterministic and the scatter is stable.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
   uint64_t m = __ballot(valid);
@@ -147,24 +147,32 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
   return m;
 }
 
+// Digit counts of one block's kSortTile keys.  A count does not depend on
+// the order, so each thread loads four keys with one 16-byte load and bumps
+// its wave's LDS counters with atomics; the four wave histograms are summed.
 __global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(
     const uint32_t* __restrict__ keys, const uint64_t* n_dev, uint64_t n_host, int shift,
     uint32_t* __restrict__ hist /* [256][nblocks] */) {
   __shared__ uint32_t wcnt[kSortWaves][kRadixBins];
   const uint64_t n = n_dev ? min(*n_dev, n_host) : n_host;
-  const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
   for (int i = threadIdx.x; i < kSortWaves * kRadixBins; i += kSortThreads)
     (&wcnt[0][0])[i] = 0;
   __syncthreads();
-  const uint64_t wbase = (uint64_t)blockIdx.x * kSortTile + (uint64_t)w * (kWave * kSortRounds);
-  const uint64_t lt = lanemask_lt();
-  for (int k = 0; k < kSortRounds; ++k) {
-    const uint64_t i = wbase + (uint64_t)k * kWave + lane;
-    const bool valid = i < n;
-    const uint32_t d = valid ? (keys[i] >> shift) & 0xffu : 0u;
-    const uint64_t m = digit_peers(d, valid);
-    if (valid && (m & lt) == 0) wcnt[w][d] += (uint32_t)__popcll(m);
+  const uint64_t bbase = (uint64_t)blockIdx.x * kSortTile;
+  uint32_t* cw = wcnt[w];
+#pragma unroll
+  for (int j = 0; j < kSortTile / (4 * kSortThreads); ++j) {
+    const uint64_t i = bbase + 4 * ((uint64_t)threadIdx.x + (uint64_t)j * kSortThreads);
+    if (i + 4 <= n) {
+      const uint4 k = *reinterpret_cast<const uint4*>(keys + i);  // i % 4 == 0
+      atomicAdd(&cw[(k.x >> shift) & 0xffu], 1u);
+      atomicAdd(&cw[(k.y >> shift) & 0xffu], 1u);
+      atomicAdd(&cw[(k.z >> shift) & 0xffu], 1u);
+      atomicAdd(&cw[(k.w >> shift) & 0xffu], 1u);
+    } else {
+      for (uint64_t t = i; t < n && t < i + 4; ++t) atomicAdd(&cw[(keys[t] >> shift) & 0xffu], 1u);
+    }
   }
   __syncthreads();
   const int d = threadIdx.x;

@@ -151,6 +151,40 @@ gsr_status gsr_step_l1(gsr_context* ctx, const gsr_settings* settings, int64_t n
                        float* g_quats, float* g_opacity_logits, float* g_sh, float* g_twist,
                        void* stream);
 
+/* The paper's full rendering loss (eqn rnd_loss, Sec. 3.3; lambda2 = 0.2 and
+ * lambda1 = 0.8 or 0.9 in supplementary S1.2) of images laid out like the
+ * last forward's outputs (frame sizes and packing of that forward):
+ *   *loss = sum_f ( lambda1 [ (1 - lambda2) mean |rgb - target_rgb|
+ *                             + lambda2 (1 - SSIM_f) ]
+ *                   + (1 - lambda1) mean over {target_depth > 0} |depth - target_depth| ),
+ * SSIM_f = the mean over the 3 channels and all pixels of frame f of Wang et
+ * al.'s SSIM map (11x11 Gaussian window of standard deviation 1.5, weights
+ * summing to 1; C1 = 0.01^2, C2 = 0.03^2; window sums with zero padding), and
+ * its gradients g_rgb, g_depth and g_alpha (= 0), ready for gsr_backward.
+ * A frame with no valid target depth has no depth term.  rgb, depth and the
+ * targets are device arrays packed like gsr_forward's outputs (the forward's
+ * own output buffers may be passed); `loss` is a device float; `ssim`, if
+ * not NULL, receives SSIM_f [n_frames] (device floats).  lambda1 and
+ * lambda2 must lie in [0, 1] (GSR_ERR_INVALID_ARGUMENT otherwise);
+ * GSR_ERR_STATE if no forward preceded.  The SSIM map is evaluated in FP64;
+ * the workspace grows by 72 bytes per pixel. */
+gsr_status gsr_loss_render(gsr_context* ctx, const float* rgb, const float* depth,
+                           const float* target_rgb, const float* target_depth, float lambda1,
+                           float lambda2, float* loss, float* ssim, float* g_rgb,
+                           float* g_depth, float* g_alpha, void* stream);
+
+/* One mapping step with the full rendering loss: gsr_forward,
+ * gsr_loss_render on the forward's outputs and gsr_backward in sequence,
+ * with the upstream gradients held in the context.  `ssim` may be NULL. */
+gsr_status gsr_step_render(gsr_context* ctx, const gsr_settings* settings, int64_t n,
+                           const float* means, const float* log_scales, const float* quats,
+                           const float* opacity_logits, const float* sh, int32_t n_frames,
+                           const gsr_camera* cams, const float* poses, const float* target_rgb,
+                           const float* target_depth, float lambda1, float lambda2, float* rgb,
+                           float* depth, float* alpha, float* loss, float* ssim,
+                           float* g_means, float* g_log_scales, float* g_quats,
+                           float* g_opacity_logits, float* g_sh, float* g_twist, void* stream);
+
 /* Autotuner: runs gsr_step_l1 with every supported tile shape (16x16, 8x8,
  * 32x8, 16x8, 32x16) on the given inputs, `reps` timed runs each with HIP
  * events on `stream` after one untimed sizing run, and writes the fastest

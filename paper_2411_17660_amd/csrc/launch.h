@@ -70,6 +70,16 @@ void launch_loss_l1(hipStream_t st, int F, int blocks_x, const FrameDesc* frames
                     const float* t_depth, float depth_weight, double* part, float* scale,
                     float* loss, float* g_rgb, float* g_depth, float* g_alpha);
 
+// ssim.hip: rendering loss with SSIM.  tile_sums holds 4 doubles per padded
+// tile of every plane [F][3][tiles_pad]; part 3 x 3 * total_px doubles (the
+// SSIM map's derivatives A, B, C per colour value); scale [F][3] doubles.
+int ssim_tiles_pad(int max_w, int max_h);
+void launch_loss_render(hipStream_t st, int F, int tiles_pad, const FrameDesc* frames,
+                        int64_t total_px, const float* rgb, const float* depth,
+                        const float* t_rgb, const float* t_depth, float lambda1, float lambda2,
+                        double* part, double* tile_sums, double* scale, float* loss,
+                        float* ssim, float* g_rgb, float* g_depth, float* g_alpha);
+
 // adam.hip
 void launch_adam(hipStream_t st, uint64_t n3, uint64_t nsh, float* means, const float* g_means,
                  float* m_means, float* v_means, float* sh, const float* g_sh, float* m_sh,

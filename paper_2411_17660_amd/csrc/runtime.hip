@@ -48,6 +48,7 @@ struct gsr_context {
   DBuf rec, trect, keyoff, dkey_a, dval_a, dkey_b, dval_b, ntiles, offsets, scan_tmp, hist, counters;
   DBuf keys_a, vals_a, keys_b, vals_b, partial, stamp, grad2d;
   DBuf ranges, nproc, t_final, n_last, frames, twist_part, loss_part, loss_scale;
+  DBuf ssim_part, ssim_tiles, ssim_scale;  // rendering loss with SSIM
   DBuf up_rgb, up_depth, up_alpha;  // upstream gradients for gsr_step_l1
   DBuf tune_out;                    // scratch outputs of the autotuner
   DBuf order_f, order_b;            // compositing tile schedules (forward, backward)
@@ -257,6 +258,7 @@ gsr_status gsr_destroy(gsr_context* ctx) {
                   &ctx->grad2d,
                   &ctx->stamp, &ctx->ranges, &ctx->nproc, &ctx->t_final, &ctx->n_last,
                   &ctx->frames, &ctx->twist_part, &ctx->loss_part, &ctx->loss_scale,
+                  &ctx->ssim_part, &ctx->ssim_tiles, &ctx->ssim_scale,
                   &ctx->up_rgb, &ctx->up_depth, &ctx->up_alpha, &ctx->tune_out,
                   &ctx->order_f, &ctx->order_b, &ctx->cls_a, &ctx->cls_b, &ctx->clsv_a,
                   &ctx->clsv_b};
@@ -549,6 +551,68 @@ gsr_status gsr_loss_l1(gsr_context* ctx, const float* target_rgb, const float* t
   }
   GSR_HIP(hipGetLastError());
   return GSR_OK;
+}
+
+gsr_status gsr_loss_render(gsr_context* ctx, const float* rgb, const float* depth,
+                           const float* target_rgb, const float* target_depth, float lambda1,
+                           float lambda2, float* loss, float* ssim, float* g_rgb, float* g_depth,
+                           float* g_alpha, void* stream) {
+  if (!ctx) return GSR_ERR_INVALID_ARGUMENT;
+  Saved& sv = ctx->s;
+  if (!sv.valid) return fail(ctx, GSR_ERR_STATE, "loss without a preceding forward");
+  if (!rgb || !depth || !target_rgb || !target_depth || !loss || !g_rgb || !g_depth || !g_alpha)
+    return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "pointer is NULL");
+  if (!(lambda1 >= 0.0f && lambda1 <= 1.0f) || !(lambda2 >= 0.0f && lambda2 <= 1.0f))
+    return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "lambda1/lambda2 outside [0, 1]");
+  const void* ptrs[] = {rgb, depth, target_rgb, target_depth, loss, ssim, g_rgb, g_depth, g_alpha};
+  for (const void* p : ptrs)
+    if (((uintptr_t)p) & 3u) return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "pointer not 4-aligned");
+  hipStream_t st = (hipStream_t)stream;
+  GSR_HIP(hipSetDevice(ctx->device));
+  int max_w = 1, max_h = 1;
+  for (const FrameDesc& fd : ctx->last_frames) {
+    max_w = std::max(max_w, (int)fd.width);
+    max_h = std::max(max_h, (int)fd.height);
+  }
+  const int tiles_pad = ssim_tiles_pad(max_w, max_h);
+  if (sv.F > 65535) return fail(ctx, GSR_ERR_UNSUPPORTED, "more than 65535 frames");
+  gsr_status rc;
+  if ((rc = ensure(ctx, ctx->ssim_part, (size_t)sv.P * 9 * 8, st))) return rc;
+  if ((rc = ensure(ctx, ctx->ssim_tiles, (size_t)sv.F * 3 * tiles_pad * 4 * 8, st))) return rc;
+  if ((rc = ensure(ctx, ctx->ssim_scale, (size_t)sv.F * 3 * 8, st))) return rc;
+  {
+    StageTimer t(ctx, st, (sv.set.flags & GSR_FLAG_TIMING) != 0, GSR_STAGE_LOSS);
+    launch_loss_render(st, sv.F, tiles_pad, P<FrameDesc>(ctx->frames), sv.P, rgb, depth,
+                       target_rgb, target_depth, lambda1, lambda2, P<double>(ctx->ssim_part),
+                       P<double>(ctx->ssim_tiles), P<double>(ctx->ssim_scale), loss, ssim,
+                       g_rgb, g_depth, g_alpha);
+  }
+  GSR_HIP(hipGetLastError());
+  return GSR_OK;
+}
+
+gsr_status gsr_step_render(gsr_context* ctx, const gsr_settings* s, int64_t n, const float* means,
+                           const float* log_scales, const float* quats, const float* opac,
+                           const float* sh, int32_t F, const gsr_camera* cams, const float* poses,
+                           const float* target_rgb, const float* target_depth, float lambda1,
+                           float lambda2, float* rgb, float* depth, float* alpha, float* loss,
+                           float* ssim, float* g_means, float* g_log_scales, float* g_quats,
+                           float* g_opac, float* g_sh, float* g_twist, void* stream) {
+  gsr_status rc = gsr_forward(ctx, s, n, means, log_scales, quats, opac, sh, F, cams, poses,
+                              rgb, depth, alpha, stream);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t npix = (size_t)ctx->s.P;
+  if ((rc = ensure(ctx, ctx->up_rgb, npix * 3 * 4, st))) return rc;
+  if ((rc = ensure(ctx, ctx->up_depth, npix * 4, st))) return rc;
+  if ((rc = ensure(ctx, ctx->up_alpha, npix * 4, st))) return rc;
+  rc = gsr_loss_render(ctx, rgb, depth, target_rgb, target_depth, lambda1, lambda2, loss, ssim,
+                       P<float>(ctx->up_rgb), P<float>(ctx->up_depth), P<float>(ctx->up_alpha),
+                       stream);
+  if (rc) return rc;
+  return gsr_backward(ctx, P<float>(ctx->up_rgb), P<float>(ctx->up_depth),
+                      P<float>(ctx->up_alpha), g_means, g_log_scales, g_quats, g_opac, g_sh,
+                      g_twist, stream);
 }
 
 gsr_status gsr_step_l1(gsr_context* ctx, const gsr_settings* s, int64_t n, const float* means,

@@ -106,6 +106,44 @@ class Rasterizer:
                                          _ptr(out["g_alpha"]), _stream()))
         return out
 
+    def loss_render(self, rgb, depth, target_rgb, target_depth, lambda1=0.9, lambda2=0.2,
+                    out=None):
+        """Full rendering loss (L1 + SSIM colour term, L1 depth term) of
+        images packed like the last forward's outputs; returns dict(loss,
+        ssim [F], g_rgb, g_depth, g_alpha)."""
+        dev = target_rgb.device
+        if out is None:
+            P = target_depth.numel()
+            out = dict(loss=torch.empty(1, device=dev), ssim=torch.empty(self.F, device=dev),
+                       g_rgb=torch.empty(3 * P, device=dev), g_depth=torch.empty(P, device=dev),
+                       g_alpha=torch.empty(P, device=dev))
+        self._check(self.lib.gsr_loss_render(
+            self.h, _ptr(rgb), _ptr(depth), _ptr(target_rgb), _ptr(target_depth),
+            float(lambda1), float(lambda2), _ptr(out["loss"]), _ptr(out.get("ssim")),
+            _ptr(out["g_rgb"]), _ptr(out["g_depth"]), _ptr(out["g_alpha"]), _stream()))
+        return out
+
+    def step_render(self, means, log_scales, quats, opacity, sh, poses, cams, sh_degree,
+                    target_rgb, target_depth, bufs, lambda1=0.9, lambda2=0.2,
+                    background=(0.0, 0.0, 0.0), tile=(16, 16), key_capacity=0, xcd_remap=True,
+                    timing=False):
+        """Forward + full rendering loss + backward in one call into
+        preallocated `bufs` (as for step_l1, plus an optional `ssim` [F])."""
+        self.settings = native.make_settings(sh_degree, background, tile, key_capacity,
+                                             xcd_remap, timing=timing)
+        self.cams = native.make_cameras(cams)
+        n = int(means.shape[0])
+        b = bufs
+        self._check(self.lib.gsr_step_render(
+            self.h, C.byref(self.settings), n, _ptr(means), _ptr(log_scales), _ptr(quats),
+            _ptr(opacity), _ptr(sh), len(cams), self.cams, _ptr(poses), _ptr(target_rgb),
+            _ptr(target_depth), float(lambda1), float(lambda2), _ptr(b["rgb"]),
+            _ptr(b["depth"]), _ptr(b["alpha"]), _ptr(b["loss"]), _ptr(b.get("ssim")),
+            _ptr(b["means"]), _ptr(b["log_scales"]), _ptr(b["quats"]), _ptr(b["opacity"]),
+            _ptr(b["sh"]), _ptr(b["twist"]), _stream()))
+        self.n, self.F, self.sh_degree = n, len(cams), sh_degree
+        self.sizes = [(int(c[0]), int(c[1])) for c in cams]
+
     def step_l1(self, means, log_scales, quats, opacity, sh, poses, cams, sh_degree,
                 target_rgb, target_depth, depth_weight, bufs, background=(0.0, 0.0, 0.0),
                 tile=(16, 16), key_capacity=0, xcd_remap=True, timing=False):

@@ -304,4 +304,60 @@ def tiny_scene(seed=0, n=40, W=40, H=30, f=30.0, n_frames=1, sh_degree=3,
     return sc
 
 
+def layout_scene(sizes, seed=0, n=8):
+    """A few Gaussians in front of identity cameras of the given (W, H)
+    sizes: a forward over it fixes the frame layout that the loss calls
+    take from the last forward."""
+    rng = np.random.default_rng(seed)
+    cams = [(w, h, 0.8 * max(w, h), 0.8 * max(w, h), w / 2.0, h / 2.0, NEAR) for (w, h) in sizes]
+    means = np.stack([rng.uniform(-0.3, 0.3, n), rng.uniform(-0.3, 0.3, n),
+                      rng.uniform(2.0, 3.0, n)], 1)
+    poses = np.repeat(np.concatenate([np.eye(3), np.zeros((3, 1))], 1)[None], len(sizes), 0)
+    sh = rng.normal(0.5, 0.2, size=(n, 1, 3))
+    return Scene(_f32(means), _f32(rng.normal(-2.5, 0.3, (n, 3))), _f32(_unit_quats(rng, n)),
+                 _f32(rng.normal(0.0, 1.0, n)), _f32(sh), 0, cams, _f32(poses))
+
+
+def loss_images(seed, sizes, depth_invalid=0.2):
+    """Rendered and target images for the rendering-loss tests, packed like
+    the renderer's outputs: (rgb [3P], depth [P], target_rgb, target_depth).
+
+    Each target channel is a smooth field (a few low-frequency waves) with
+    constant rectangles pasted in and light noise.  The rendered image equals
+    the target exactly on one rectangle (flat and identical: the SSIM map's
+    derivatives cancel most there), is the target plus small noise on the
+    left half and independent values elsewhere.  A fraction of the target
+    depths is 0 (no measurement)."""
+    rng = np.random.default_rng(seed)
+    rgb, dep, t_rgb, t_dep = [], [], [], []
+    for (w, h) in sizes:
+        yy, xx = np.mgrid[0:h, 0:w].astype(np.float64)
+        tgt = np.empty((3, h, w))
+        for c in range(3):
+            f = np.full((h, w), rng.uniform(0.3, 0.7))
+            for _ in range(3):
+                kx, ky = rng.uniform(-0.15, 0.15, 2)
+                f += rng.uniform(0.05, 0.2) * np.sin(kx * xx + ky * yy + rng.uniform(0, 6.3))
+            for _ in range(2):
+                x0, y0 = rng.integers(0, w), rng.integers(0, h)
+                f[y0:y0 + rng.integers(1, 40), x0:x0 + rng.integers(1, 40)] = rng.uniform(0, 1)
+            tgt[c] = f + rng.normal(0, 0.01, (h, w))
+        img = rng.uniform(0, 1, (3, h, w))
+        left = xx < w / 2
+        img[:, left] = tgt[:, left] + rng.normal(0, 0.02, (3, int(left.sum())))
+        x0, y0 = rng.integers(0, w), rng.integers(0, h)
+        ex, ey = x0 + rng.integers(1, 48), y0 + rng.integers(1, 48)
+        tgt[:, y0:ey, x0:ex] = rng.uniform(0, 1, (3, 1, 1))
+        img[:, y0:ey, x0:ex] = tgt[:, y0:ey, x0:ex]
+        tz = rng.uniform(0.5, 4.0, (h, w))
+        z = tz + rng.normal(0, 0.05, (h, w))
+        tz[rng.uniform(0, 1, (h, w)) < depth_invalid] = 0.0
+        rgb.append(img.ravel())
+        t_rgb.append(tgt.ravel())
+        dep.append(z.ravel())
+        t_dep.append(tz.ravel())
+    return (_f32(np.concatenate(rgb)), _f32(np.concatenate(dep)), _f32(np.concatenate(t_rgb)),
+            _f32(np.concatenate(t_dep)))
+
+
 SCENES = {"c1": scene_c1, "c2": scene_c2, "c3": scene_c3, "c4": scene_c4, "c5": scene_c5}

@@ -23,7 +23,8 @@ def lib():
 
 def test_header_declares_entry_points():
     names = _declared()
-    for n in ("gsr_create", "gsr_forward", "gsr_backward", "gsr_step_l1", "gsr_loss_l1"):
+    for n in ("gsr_create", "gsr_forward", "gsr_backward", "gsr_step_l1", "gsr_loss_l1",
+              "gsr_loss_render", "gsr_step_render"):
         assert n in names
 
 
@@ -50,5 +51,6 @@ def test_null_context_is_rejected_without_touching_the_gpu(lib):
                          None, None, None)
     assert rc == 1
     assert lib.gsr_backward(None, *([None] * 10)) == 1
+    assert lib.gsr_loss_render(None, *([None] * 4), 0.9, 0.2, *([None] * 6)) == 1
     assert lib.gsr_last_error(None) == b""
     assert lib.gsr_create(None, 0) == 1

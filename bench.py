@@ -202,6 +202,9 @@ def main():
         rf.check_overflow()
         log(f"[bench] per-frame {t_per_frame * 1e3:.2f} ms/step")
 
+    # ---------------- the paper's full rendering loss (L1 + SSIM colour term)
+    render = measure_render_loss(rast, sc, dev, bb, t_rgb, t_dep, tile, cap, args.steps)
+
     mpix = P / 1e6
     t_best = min(t_batched, t_graph) if t_graph else t_batched
     value = mpix / t_best
@@ -240,9 +243,78 @@ def main():
         "stage_ms_per_step": per_stage,
         "loss": loss,
         "roofline": roofline,
+        "render_loss": render,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+# Rendering loss with SSIM (11x11 window, FP64 arithmetic), per pixel of the
+# batch: the forward reads rendered and target colours (8 B per colour value)
+# and writes the map's three FP64 derivatives (24 B); the backward reads
+# those and both colours again (32 B) and writes the colour gradient (4 B);
+# the depth term reads 8 B and writes 8 B (depth and alpha gradients) more.
+# FP64 flops per colour value: 5 window sums x 22 taps + 3 products + ~30 for
+# the map (forward), 3 window sums x 22 taps + 6 (backward).
+RENDER_LOSS_BYTES_PER_PX = 3 * (32 + 36) + 8 + 16
+RENDER_LOSS_FP64_FLOPS_PER_VALUE = 2 * 5 * 22 + 3 + 30 + 2 * 3 * 22 + 6
+PEAK_FP64_VECTOR_TFLOPS = 78.6
+
+
+def measure_render_loss(rast, sc, dev, bb, t_rgb, t_dep, tile, cap, steps):
+    """Times gsr_loss_render on the batch's rendered images (HIP events on
+    the library's stream) and the mapping step with that loss."""
+    import torch
+    P, F = sc.n_pixels, sc.n_frames
+    out = dict(loss=torch.empty(1, device="cuda"), ssim=torch.empty(F, device="cuda"),
+               g_rgb=torch.empty(3 * P, device="cuda"), g_depth=torch.empty(P, device="cuda"),
+               g_alpha=torch.empty(P, device="cuda"))
+    rast.forward(dev["means"], dev["log_scales"], dev["quats"], dev["opacity"], dev["sh"],
+                 dev["poses"], sc.cams, 3, tile=tile, key_capacity=cap,
+                 out=(bb["rgb"], bb["depth"], bb["alpha"]))
+    for _ in range(2):
+        rast.loss_render(bb["rgb"], bb["depth"], t_rgb, t_dep, 0.9, 0.2, out=out)
+    torch.cuda.synchronize()
+    reps = 20
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        rast.loss_render(bb["rgb"], bb["depth"], t_rgb, t_dep, 0.9, 0.2, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = P * RENDER_LOSS_BYTES_PER_PX
+    flops = 3 * P * RENDER_LOSS_FP64_FLOPS_PER_VALUE
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    tfl = flops / (ms * 1e-3) / 1e12
+    # the mapping step with the full loss (forward + loss + backward)
+    K = (sc.sh_degree + 1) ** 2
+    b = dict(bb, ssim=torch.empty(F, device="cuda"))
+
+    def rstep():
+        rast.step_render(dev["means"], dev["log_scales"], dev["quats"], dev["opacity"], dev["sh"],
+                         dev["poses"], sc.cams, 3, t_rgb, t_dep, b, 0.9, 0.2, tile=tile,
+                         key_capacity=cap)
+    assert b["sh"].shape[1] == K
+    for _ in range(2):
+        rstep()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        rstep()
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t0) / steps
+    rast.check_overflow()
+    log(f"[bench] render loss {ms:.4f} ms/call ({gbs:.0f} GB/s, {tfl:.2f} FP64 TFLOP/s); "
+        f"step with it {t_step * 1e3:.2f} ms")
+    return {"lambda1": 0.9, "lambda2": 0.2, "ms_per_call": round(ms, 4),
+            "ssim_per_frame": [round(float(v), 6) for v in out["ssim"].cpu()],
+            "loss": float(out["loss"].item()),
+            "bound": "hbm", "hbm_bytes_per_call": nbytes, "achieved_GBps": round(gbs, 1),
+            "peak_GBps": PEAK_HBM_GBS, "frac": round(gbs / PEAK_HBM_GBS, 4),
+            "fp64_flops_per_call": flops, "achieved_fp64_TFLOPs": round(tfl, 3),
+            "frac_fp64_peak": round(tfl / PEAK_FP64_VECTOR_TFLOPS, 4),
+            "step_ms": round(t_step * 1e3, 4), "step_mpix_per_s": round(P / 1e6 / t_step, 3)}
 
 
 def measured_traffic(kernel, tile):

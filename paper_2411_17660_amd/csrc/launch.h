@@ -71,13 +71,14 @@ void launch_loss_l1(hipStream_t st, int F, int blocks_x, const FrameDesc* frames
                     float* loss, float* g_rgb, float* g_depth, float* g_alpha);
 
 // ssim.hip: rendering loss with SSIM.  tile_sums holds 4 doubles per padded
-// tile of every plane [F][3][tiles_pad]; part 3 x 3 * total_px doubles (the
-// SSIM map's derivatives A, B, C per colour value); scale [F][3] doubles.
+// block tile of every plane [F][3][tiles_pad]; part 3 x 3 * total_px doubles
+// (the SSIM map's derivatives A, B, C per colour value); frame_sums [F][4]
+// doubles (gradient scales and loss term per frame).
 int ssim_tiles_pad(int max_w, int max_h);
 void launch_loss_render(hipStream_t st, int F, int tiles_pad, const FrameDesc* frames,
                         int64_t total_px, const float* rgb, const float* depth,
                         const float* t_rgb, const float* t_depth, float lambda1, float lambda2,
-                        double* part, double* tile_sums, double* scale, float* loss,
+                        double* part, double* tile_sums, double* frame_sums, float* loss,
                         float* ssim, float* g_rgb, float* g_depth, float* g_alpha);
 
 // adam.hip

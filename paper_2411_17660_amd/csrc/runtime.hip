@@ -579,7 +579,7 @@ gsr_status gsr_loss_render(gsr_context* ctx, const float* rgb, const float* dept
   gsr_status rc;
   if ((rc = ensure(ctx, ctx->ssim_part, (size_t)sv.P * 9 * 8, st))) return rc;
   if ((rc = ensure(ctx, ctx->ssim_tiles, (size_t)sv.F * 3 * tiles_pad * 4 * 8, st))) return rc;
-  if ((rc = ensure(ctx, ctx->ssim_scale, (size_t)sv.F * 3 * 8, st))) return rc;
+  if ((rc = ensure(ctx, ctx->ssim_scale, (size_t)sv.F * 4 * 8, st))) return rc;
   {
     StageTimer t(ctx, st, (sv.set.flags & GSR_FLAG_TIMING) != 0, GSR_STAGE_LOSS);
     launch_loss_render(st, sv.F, tiles_pad, P<FrameDesc>(ctx->frames), sv.P, rgb, depth,

@@ -407,11 +407,13 @@ typedef struct {
 
 /* Walks the tile list of pixel (px, py) of frame f.  Fills out[] with the
  * blended entries (if out != NULL), returns their number; writes T_final,
- * the stop position n_last, the accumulated colour/depth, the flags and the
- * count of (pixel, entry) square hits. */
+ * the stop position n_last, the accumulated colour/depth, the median entry
+ * (*med: index among the blended entries of the first one after which T is
+ * below 1/2, -1 if none; *zmed its depth), the flags and the count of
+ * (pixel, entry) square hits. */
 static int walk_pixel(const ref_state* st, int f, int px, int py, blend_t* out,
                       double* T_out, int32_t* nlast_out, double* S, double* Sz,
-                      uint8_t* flags, int64_t* hits) {
+                      int* med, double* zmed, uint8_t* flags, int64_t* hits) {
   const int tw = st->set.tile_w, th = st->set.tile_h;
   const int64_t tile = st->tile_off[f] + (int64_t)(py / th) * st->grid_x[f] + px / tw;
   const int64_t s0 = st->tile_start[tile], s1 = st->tile_start[tile + 1];
@@ -422,6 +424,9 @@ static int walk_pixel(const ref_state* st, int f, int px, int py, blend_t* out,
   uint8_t fl = 0;
   S[0] = S[1] = S[2] = 0.0;
   *Sz = 0.0;
+  *med = -1;
+  *zmed = 0.0;
+  const int median = st->set.depth_mode == REF_DEPTH_MEDIAN;
   for (int64_t k = s0; k < s1; ++k) {
     const int32_t g = st->tile_g[k];
     const rec_t* r = &base[g];
@@ -449,6 +454,14 @@ static int walk_pixel(const ref_state* st, int f, int px, int py, blend_t* out,
     if (fabs(Tn - T_MIN) < band_t * T_MIN) fl |= REF_FLAG_T_BAND;
     if (Tn < T_MIN) break;
     if (fabs(araw - A_MAX) < BAND * A_MAX) fl |= REF_FLAG_CLAMP_BAND;
+    /* median depth: the first blended entry after which T is below 1/2 */
+    if (median) {
+      if (fabs(Tn - 0.5) < band_t * 0.5) fl |= REF_FLAG_MEDIAN_BAND;
+      if (*med < 0 && Tn < 0.5) {
+        *med = nb;
+        *zmed = r->z;
+      }
+    }
     const double w = a * T;
     for (int c = 0; c < 3; ++c) S[c] += r->color[c] * w;
     *Sz += r->z * w;
@@ -585,18 +598,22 @@ static int forward_impl(const ref_settings* s, int64_t n, double* means,
           double S[3], Sz, T;
           int32_t nl;
           uint8_t fl;
-          const int nb = walk_pixel(st, f, px, py, buf, &T, &nl, S, &Sz, &fl, &pairs);
+          int med;
+          double zmed;
+          const int nb =
+              walk_pixel(st, f, px, py, buf, &T, &nl, S, &Sz, &med, &zmed, &fl, &pairs);
           const int64_t p = p0 + (int64_t)py * Wf + px;
           const int64_t plane = (int64_t)Wf * Hf;
           for (int c = 0; c < 3; ++c)
             rgb[3 * p0 + c * plane + (int64_t)py * Wf + px] = S[c] + T * (double)s->background[c];
-          depth[p] = Sz;
+          depth[p] = s->depth_mode == REF_DEPTH_MEDIAN ? zmed : Sz;
           alpha[p] = 1.0 - T;
           st->flags[p] = fl;
           st->n_last[p] = nl;
           st->t_final[p] = T;
           uint64_t h = 1469598103934665603ull;
           h = fnv(h, (uint64_t)nl);
+          h = fnv(h, (uint64_t)(int64_t)med);
           for (int i = 0; i < nb; ++i) {
             h = fnv(h, (uint64_t)buf[i].pos);
             h = fnv(h, (uint64_t)(buf[i].araw > A_MAX));
@@ -715,7 +732,11 @@ int ref_backward(ref_state* st, const double* g_rgb, const double* g_depth,
           double S[3], Sz, Tf;
           int32_t nl;
           uint8_t fl;
-          const int nb = walk_pixel(st, f, px, py, buf, &Tf, &nl, S, &Sz, &fl, &dummy_hits);
+          int med;
+          double zmed;
+          const int nb = walk_pixel(st, f, px, py, buf, &Tf, &nl, S, &Sz, &med, &zmed, &fl,
+                                    &dummy_hits);
+          const int median = st->set.depth_mode == REF_DEPTH_MEDIAN;
           const int64_t p = p0 + (int64_t)py * Wf + px;
           double GC[3];
           for (int c = 0; c < 3; ++c) GC[c] = g_rgb[3 * p0 + c * plane + (int64_t)py * Wf + px];
@@ -734,9 +755,14 @@ int ref_backward(ref_state* st, const double* g_rgb, const double* g_depth,
               dLda += GC[c] * (r->color[c] * b->Ti - accc[c] / om);
               gr[6 + c] += GC[c] * w;
             }
-            dLda += GD * (r->z * b->Ti - accz / om);
+            if (median) {
+              /* D = z of the median entry: no dependence on any alpha */
+              if (i == med) gr[9] += GD;
+            } else {
+              dLda += GD * (r->z * b->Ti - accz / om);
+              gr[9] += GD * w;
+            }
             dLda += GA * (Tf / om);
-            gr[9] += GD * w;
             for (int c = 0; c < 3; ++c) accc[c] += r->color[c] * w;
             accz += r->z * w;
             if (b->araw > A_MAX) continue; /* clamped: alpha does not move */

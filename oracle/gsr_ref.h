@@ -10,8 +10,8 @@
  * rendering equation eqn:rendering; the 3DGS lineage it cites supplies the
  * EWA projection and tile culling):
  *   Gaussians (mean, log-scale, quaternion wxyz, opacity logit, SH colour)
- *   + pinhole cameras + world->camera poses  ->  RGB, alpha-blended depth and
- *   accumulated alpha per frame, and the exact analytic gradients of
+ *   + pinhole cameras + world->camera poses  ->  RGB, depth (alpha-blended,
+ *   or the median depth) and accumulated alpha per frame, and the exact analytic gradients of
  *   L = <G_C, RGB> + <G_D, D> + <G_A, Alpha> with respect to every Gaussian
  *   parameter and a left-perturbation twist (rho, phi) of every pose
  *   (Sec. 3.3 last paragraph; supplementary S1.3 "Feedback").
@@ -44,7 +44,16 @@ typedef struct {
   float background[3];
   int32_t tile_w, tile_h; /* any positive sizes; results do not depend on them */
   int32_t n_threads;      /* OpenMP threads; <= 0 means 1 */
+  int32_t depth_mode;     /* REF_DEPTH_BLENDED or REF_DEPTH_MEDIAN */
 } ref_settings;
+
+/* Depth output.  BLENDED: D = sum_i z_i a_i T_i.  MEDIAN (the depth at
+ * which the pixel's transmittance first falls below 1/2): D = z_k of the
+ * first blended entry k with T_k (1 - a_k) < 1/2, or 0 where T never falls
+ * below 1/2; its gradient reaches that entry's z only (the choice of k is
+ * piecewise constant). */
+#define REF_DEPTH_BLENDED 0
+#define REF_DEPTH_MEDIAN 1
 
 /* Per-pixel flag bits: pixels whose discrete decisions sit so close to a
  * threshold that FP32 rounding on another implementation may flip them. */
@@ -53,6 +62,7 @@ typedef struct {
 #define REF_FLAG_T_BAND 2u       /* some blend candidate has |T' - T_MIN| < b_t T_MIN,
                                     b_t = max(1e-4, 4 eps32 (blended so far + 1))      */
 #define REF_FLAG_CLAMP_BAND 4u   /* some blended entry has |s G - A_MAX| < 1e-4 A_MAX   */
+#define REF_FLAG_MEDIAN_BAND 8u  /* median mode: some blended entry has |T' - 1/2| < b_t / 2 */
 
 typedef struct ref_state ref_state;
 

@@ -21,7 +21,10 @@ class _Cam(C.Structure):
 
 class _Set(C.Structure):
     _fields_ = [("sh_degree", C.c_int32), ("background", C.c_float * 3),
-                ("tile_w", C.c_int32), ("tile_h", C.c_int32), ("n_threads", C.c_int32)]
+                ("tile_w", C.c_int32), ("tile_h", C.c_int32), ("n_threads", C.c_int32),
+                ("depth_mode", C.c_int32)]
+
+DEPTH_BLENDED, DEPTH_MEDIAN = 0, 1
 
 
 def load():
@@ -84,7 +87,7 @@ def _f32(a):
 class RefForward:
     """Result of one oracle forward; holds the saved state for backward."""
 
-    def __init__(self, scene, tile=(16, 16), threads=1, f64=False):
+    def __init__(self, scene, tile=(16, 16), threads=1, f64=False, median=False):
         lib = load()
         conv = (lambda a: np.ascontiguousarray(a, dtype=np.float64)) if f64 else _f32
         self.scene = scene
@@ -98,7 +101,8 @@ class RefForward:
                             for c in scene.cams])
         self._cams = cams
         s = _Set(int(scene.sh_degree), (C.c_float * 3)(*[float(b) for b in scene.background]),
-                 int(tile[0]), int(tile[1]), int(threads))
+                 int(tile[0]), int(tile[1]), int(threads),
+                 DEPTH_MEDIAN if median else DEPTH_BLENDED)
         self._set = s
         P = sum(w * h for w, h in self.sizes)
         self.P = P
@@ -219,10 +223,11 @@ class RefForward:
         return flags, nl, tf
 
 
-def forward(scene, tile=(16, 16), threads=1, f64=False):
+def forward(scene, tile=(16, 16), threads=1, f64=False, median=False):
     """Oracle forward.  f64=True passes the scene arrays as FP64 (used by the
-    finite-difference pins); otherwise they are the FP32 values."""
-    return RefForward(scene, tile=tile, threads=threads, f64=f64)
+    finite-difference pins); otherwise they are the FP32 values.  median=True
+    renders the median depth instead of the alpha-blended depth."""
+    return RefForward(scene, tile=tile, threads=threads, f64=f64, median=median)
 
 
 def quat_to_rotmat(q):

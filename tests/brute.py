@@ -149,3 +149,36 @@ def render(scene):
                 alp[j, i] = 1 - T
         out.append((rgb, dep, alp))
     return out
+
+
+def render_median(scene):
+    """Per frame the median depth [H,W] by brute force: walking each pixel's
+    entries front to back, the depth of the first blended entry after which
+    the transmittance is below 1/2 (0 if it never is)."""
+    out = []
+    for f in range(len(scene.cams)):
+        W, H = int(scene.cams[f][0]), int(scene.cams[f][1])
+        p = project(scene, f)
+        idx = np.nonzero(p["keep"])[0]
+        order = idx[np.lexsort((idx, p["depth_bits"][idx]))]
+        med = np.zeros((H, W))
+        for j in range(H):
+            for i in range(W):
+                inside = order[(p["x_lo"][order] <= i) & (i <= p["x_hi"][order]) &
+                               (p["y_lo"][order] <= j) & (j <= p["y_hi"][order])]
+                T = 1.0
+                for g in inside:
+                    dx, dy = p["u"][g] - i, p["v"][g] - j
+                    Q = p["conic"][g]
+                    q = Q[0, 0] * dx * dx + 2 * Q[0, 1] * dx * dy + Q[1, 1] * dy * dy
+                    a = min(A_MAX, p["opacity"][g] * math.exp(-0.5 * q))
+                    if a < A_MIN:
+                        continue
+                    if T * (1 - a) < T_MIN:
+                        break
+                    T = T * (1 - a)
+                    if T < 0.5:
+                        med[j, i] = p["z"][g]
+                        break
+        out.append(med)
+    return out

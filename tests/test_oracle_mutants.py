@@ -15,6 +15,7 @@ from oracle import build as ob
 from oracle import ref as oref
 
 import test_oracle_fd as fd
+import test_oracle_median as med
 import test_oracle_pins as pins
 
 SRC = os.path.join(os.path.dirname(ob.__file__), "gsr_ref.c")
@@ -44,6 +45,9 @@ MUTANTS = [
     ("jacobian_tz", "dt[2] += GJ[0] * (-fx / (tz * tz));", "dt[2] += GJ[0] * (-fx / tz);"),
     ("scale_chain", "g_log_scales[g * 3 + a] = ds[a] * G.s[a];", "g_log_scales[g * 3 + a] = ds[a];"),
     ("sh_grad_dir", "dd[a] = (ddir[a] - r->dir[a] * dd0) / r->dist;", "dd[a] = ddir[a] / r->dist;"),
+    ("median_before_blend", "if (*med < 0 && Tn < 0.5) {", "if (*med < 0 && T < 0.5) {"),
+    ("median_last_crossing", "if (*med < 0 && Tn < 0.5) {", "if (Tn < 0.5) {"),
+    ("median_bwd_blended", "if (i == med) gr[9] += GD;", "gr[9] += GD * w;"),
 ]
 
 CHECKS = [
@@ -57,6 +61,9 @@ CHECKS = [
     ("fd_params", lambda: fd.test_parameter_gradients_match_central_differences(11, 3, 2, (0.1, 0.2, 0.3))),
     ("fd_twist", lambda: fd.test_twist_gradient_matches_central_differences(21, 3)),
     ("fd_colour", fd.test_colour_clamp_and_direction_paths),
+    ("median_brute", lambda: med.test_median_matches_brute_force(2, 150, 2, (32, 8))),
+    ("median_layered", lambda: med.test_layered_closed_form([-0.9, -0.4, 2.0], [3.5, 2.0, 2.5])),
+    ("median_grad", med.test_single_pixel_gradient_closed_form),
 ]
 
 

@@ -207,11 +207,9 @@ __global__ void __launch_bounds__(kThreads) ssim_fwd_kernel(
     for (int a = 0; a < kAheadFwd; ++a)
       ahead[a] = fetch_row_f(w, 1 + a, lane, c, rgb, t_rgb, depth, t_depth);
     wave_sync();
+    // ring[s] accumulates output row s (mod 11); its first term (t = 0)
+    // assigns, so slots need no clearing
     double ring[kTaps][kMaps];
-#pragma unroll
-    for (int s = 0; s < kTaps; ++s)
-#pragma unroll
-      for (int m = 0; m < kMaps; ++m) ring[s][m] = 0.0;
     for (int k = 0; k < kChunks; ++k) {
 #pragma unroll
       for (int u = 0; u < kTaps; ++u) {
@@ -238,7 +236,9 @@ __global__ void __launch_bounds__(kThreads) ssim_fwd_kernel(
         }
         // vertical: row rho feeds output rows rho - t, t = 0..10, weight g[t]
 #pragma unroll
-        for (int t = 0; t < kTaps; ++t) {
+        for (int m = 0; m < kMaps; ++m) ring[u][m] = win.g[0] * h[m];
+#pragma unroll
+        for (int t = 1; t < kTaps; ++t) {
           const int s = (u - t + kTaps) % kTaps;
 #pragma unroll
           for (int m = 0; m < kMaps; ++m) ring[s][m] = fma(win.g[t], h[m], ring[s][m]);
@@ -265,8 +265,6 @@ __global__ void __launch_bounds__(kThreads) ssim_fwd_kernel(
           part[idx + 2 * plane_stride] = dS_dcov;
           acc[0] += S;
         }
-#pragma unroll
-        for (int m = 0; m < kMaps; ++m) ring[s_out][m] = 0.0;
         // publish row rho + 1 into the other buffer; its output pixel's depths
         if (rho + 1 < kStaged) {
           buf[cur ^ 1][0][lane] = nx.a0;
@@ -390,11 +388,7 @@ __global__ void __launch_bounds__(kThreads) ssim_bwd_kernel(
   for (int a = 0; a < kAheadBwd; ++a)
     ahead[a] = fetch_row_d(w, 1 + a, lane, c, part, plane_stride, rgb, t_rgb, depth, t_depth);
   wave_sync();
-  double ring[kTaps][3];
-#pragma unroll
-  for (int s = 0; s < kTaps; ++s)
-#pragma unroll
-    for (int m = 0; m < 3; ++m) ring[s][m] = 0.0;
+  double ring[kTaps][3];  // as in the forward: the t = 0 term assigns
   for (int k = 0; k < kChunks; ++k) {
 #pragma unroll
     for (int u = 0; u < kTaps; ++u) {
@@ -411,7 +405,9 @@ __global__ void __launch_bounds__(kThreads) ssim_bwd_kernel(
 #pragma unroll
         for (int m = 0; m < 3; ++m) h[m] = fma(win.g[d], buf[cur][m][lane + d], h[m]);
 #pragma unroll
-      for (int t = 0; t < kTaps; ++t) {
+      for (int m = 0; m < 3; ++m) ring[u][m] = win.g[0] * h[m];
+#pragma unroll
+      for (int t = 1; t < kTaps; ++t) {
         const int s = (u - t + kTaps) % kTaps;
 #pragma unroll
         for (int m = 0; m < 3; ++m) ring[s][m] = fma(win.g[t], h[m], ring[s][m]);
@@ -431,8 +427,6 @@ __global__ void __launch_bounds__(kThreads) ssim_bwd_kernel(
           g_alpha[q] = 0.0f;
         }
       }
-#pragma unroll
-      for (int m = 0; m < 3; ++m) ring[s_out][m] = 0.0;
       if (rho + 1 < kStaged) {
         buf[cur ^ 1][0][lane] = nx.a0;
         buf[cur ^ 1][1][lane] = nx.b0;

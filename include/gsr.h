@@ -26,7 +26,8 @@
  *    u = fx x/z + cx, v = fy y/z + cy.
  *  - Outputs are packed over frames in order: rgb holds, per frame, a [3,H,W]
  *    block; depth and alpha hold a [H,W] block per frame.  depth is the
- *    alpha-blended view depth sum_i z_i a_i T_i; alpha = 1 - T_final;
+ *    alpha-blended view depth sum_i z_i a_i T_i (or, with
+ *    GSR_FLAG_MEDIAN_DEPTH, the median depth); alpha = 1 - T_final;
  *    rgb = sum_i c_i a_i T_i + T_final * background.
  *  - Culling and thresholds: keep a Gaussian in a frame iff z > near, the
  *    projected 2x2 covariance (+0.3 px^2) is positive definite and its
@@ -89,6 +90,15 @@ typedef struct {
                                     call's stream; read with gsr_debug_timings */
 #define GSR_FLAG_COUNT_PAIRS 4u  /* count evaluated (pixel, entry) pairs in the
                                     forward compositing; see gsr_stats.n_pairs */
+#define GSR_FLAG_MEDIAN_DEPTH 8u /* depth output = the median depth, the depth mode
+                                    Sec. 3.3 names (after MonoGS): the z of the
+                                    first blended entry after which the pixel's
+                                    transmittance is below 1/2, 0 where it never
+                                    is; gsr_backward then takes g_depth as the
+                                    gradient of that depth, which reaches that
+                                    entry's z only (the choice of entry is
+                                    piecewise constant).  Default: alpha-blended
+                                    depth sum_i z_i a_i T_i */
 
 /* Stages timed under GSR_FLAG_TIMING (index into gsr_debug_timings). */
 #define GSR_STAGE_PREPROCESS 0

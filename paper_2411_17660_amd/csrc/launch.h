@@ -45,6 +45,10 @@ void launch_ranges(hipStream_t st, const uint32_t* keys, const uint64_t* k_dev, 
 
 // raster.hip: compositing forward and backward
 bool tile_shape_supported(int tw, int th);
+// med_pos (NULL: alpha-blended depth) selects the median depth: the forward
+// writes, per pixel, the list position of the entry after which T first
+// falls below 1/2 (-1: none) and outputs that entry's z as the depth; the
+// backward routes g_depth to that entry's z only.
 // Tiles are dispatched in per-XCD groups of neighbouring tiles
 // (`xcd_groups`, else one group), longest expected work first by
 // `prev_nproc` (processed entries of a previous forward over the same
@@ -54,14 +58,15 @@ void launch_composite_fwd(hipStream_t st, int tw, int th, int n_tiles, int F,
                           const Record* rec, const float* bg, float* rgb, float* depth,
                           float* alpha, float* t_final, int32_t* n_last, uint32_t* nproc,
                           const uint32_t* prev_nproc, uint32_t* order, bool xcd_groups,
-                          unsigned long long* pairs);
+                          unsigned long long* pairs, int32_t* med_pos);
 void launch_composite_bwd(hipStream_t st, int tw, int th, int n_tiles, int F,
                           const FrameDesc* frames, const uint2* ranges, const uint32_t* vals,
                           const Record* rec, const uint2* trect, const uint32_t* keyoff,
                           const uint32_t* nproc, const float* bg, const float* g_rgb,
                           const float* g_depth, const float* g_alpha, const float* t_final,
                           const int32_t* n_last, float* partial, uint32_t* stamp,
-                          const uint32_t* epoch, uint32_t* order, bool xcd_groups);
+                          const uint32_t* epoch, uint32_t* order, bool xcd_groups,
+                          const int32_t* med_pos);
 
 // loss.hip
 int loss_blocks_x(int64_t max_hw);

@@ -98,14 +98,14 @@ __device__ __forceinline__ int tile_of_block(int bid, int n_tiles, int groups,
   return (int)order[pos];
 }
 
-template <int TW, int TH, bool COUNT>
+template <int TW, int TH, bool COUNT, bool MEDIAN>
 __device__ __forceinline__ void composite_fwd_tile(
     int tile, Record* sm, int n_frames, const FrameDesc* __restrict__ frames,
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals,
     const Record* __restrict__ rec, float bg0, float bg1, float bg2, float* __restrict__ rgb,
     float* __restrict__ depth, float* __restrict__ alpha, float* __restrict__ t_final,
     int32_t* __restrict__ n_last, uint32_t* __restrict__ tile_nproc,
-    unsigned long long* __restrict__ pair_count) {
+    unsigned long long* __restrict__ pair_count, int32_t* __restrict__ med_pos) {
   constexpr int PIX = TW * TH / kWave;
   constexpr int RPP = kWave / TW;  // rows per strip
   const int f = frame_of_tile(frames, n_frames, tile);
@@ -117,13 +117,15 @@ __device__ __forceinline__ void composite_fwd_tile(
   const int ly = lane / TW;
   const uint2 rg = ranges[tile];
 
+  // D: alpha-blended depth, or (MEDIAN) the depth of the entry after which
+  // T first falls below 1/2, at list position mpos (-1: none yet)
   float T[PIX], C0[PIX], C1[PIX], C2[PIX], D[PIX];
-  int last[PIX];
+  int last[PIX], mpos[PIX];
   bool done[PIX];
   uint32_t hits = 0;  // (pixel, entry) pairs whose square test passed (COUNT only)
 #pragma unroll
   for (int k = 0; k < PIX; ++k) {
-    T[k] = 1.0f; C0[k] = C1[k] = C2[k] = D[k] = 0.0f; last[k] = 0;
+    T[k] = 1.0f; C0[k] = C1[k] = C2[k] = D[k] = 0.0f; last[k] = 0; mpos[k] = -1;
     const int py = y0 + k * RPP + ly;
     done[k] = !(px < fr.width && py < fr.height);
   }
@@ -160,7 +162,14 @@ __device__ __forceinline__ void composite_fwd_tile(
         C0[k] += R.c0 * w;
         C1[k] += R.c1 * w;
         C2[k] += R.c2 * w;
-        D[k] += R.z * w;
+        if (MEDIAN) {
+          if (mpos[k] < 0 && Tn < 0.5f) {
+            mpos[k] = (int)(b + j - rg.x);
+            D[k] = R.z;
+          }
+        } else {
+          D[k] += R.z * w;
+        }
         T[k] = Tn;
         last[k] = (int)(b + j + 1 - rg.x);
       }
@@ -182,6 +191,7 @@ __device__ __forceinline__ void composite_fwd_tile(
       alpha[fr.pixel_offset + p] = 1.0f - T[k];
       t_final[fr.pixel_offset + p] = T[k];
       n_last[fr.pixel_offset + p] = last[k];
+      if (MEDIAN) med_pos[fr.pixel_offset + p] = mpos[k];
       mx = max(mx, last[k]);
     }
   }
@@ -237,19 +247,20 @@ __device__ __forceinline__ double dpp(double v) {
 constexpr int kDppRowMirror = 0x140, kDppHalfMirror = 0x141, kDppQuadXor2 = 0x4e,
               kDppQuadXor1 = 0xb1;
 
-template <int TW, int TH, bool COUNT>
+template <int TW, int TH, bool COUNT, bool MEDIAN>
 __global__ void __launch_bounds__(64) composite_fwd_kernel(
     int n_tiles, int groups, const uint32_t* __restrict__ order, int n_frames,
     const FrameDesc* __restrict__ frames, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ vals, const Record* __restrict__ rec, float bg0, float bg1,
     float bg2, float* __restrict__ rgb, float* __restrict__ depth, float* __restrict__ alpha,
     float* __restrict__ t_final, int32_t* __restrict__ n_last, uint32_t* __restrict__ tile_nproc,
-    unsigned long long* __restrict__ pair_count) {
+    unsigned long long* __restrict__ pair_count, int32_t* __restrict__ med_pos) {
   __shared__ Record sm[kWave];
   const int tile = tile_of_block(blockIdx.x, n_tiles, groups, order);
   if (tile < 0) return;
-  composite_fwd_tile<TW, TH, COUNT>(tile, sm, n_frames, frames, ranges, vals, rec, bg0, bg1, bg2,
-                                     rgb, depth, alpha, t_final, n_last, tile_nproc, pair_count);
+  composite_fwd_tile<TW, TH, COUNT, MEDIAN>(tile, sm, n_frames, frames, ranges, vals, rec, bg0,
+                                             bg1, bg2, rgb, depth, alpha, t_final, n_last,
+                                             tile_nproc, pair_count, med_pos);
 }
 
 // Sums v[0..9] over the 64 lanes of the wave in FP64.  Each butterfly round
@@ -297,7 +308,7 @@ __device__ __forceinline__ double wave_transpose_sum10(const double v[10], int l
   return r;
 }
 
-template <int TW, int TH>
+template <int TW, int TH, bool MEDIAN>
 __device__ __forceinline__ void composite_bwd_tile(
     int tile, Record* sm, uint32_t* slot, uint32_t epoch, int n_frames,
     const FrameDesc* __restrict__ frames,
@@ -307,7 +318,7 @@ __device__ __forceinline__ void composite_bwd_tile(
     float bg1, float bg2, const float* __restrict__ g_rgb, const float* __restrict__ g_depth,
     const float* __restrict__ g_alpha, const float* __restrict__ t_final,
     const int32_t* __restrict__ n_last, float* __restrict__ partial,
-    uint32_t* __restrict__ stamp) {
+    uint32_t* __restrict__ stamp, const int32_t* __restrict__ med_pos) {
   constexpr int PIX = TW * TH / kWave;
   constexpr int RPP = kWave / TW;
   const uint32_t nproc = tile_nproc[tile];
@@ -332,12 +343,16 @@ __device__ __forceinline__ void composite_bwd_tile(
   double B0[PIX], B1[PIX], B2[PIX], BZ[PIX];
   float G0[PIX], G1[PIX], G2[PIX], GD[PIX], GA[PIX];
   int last[PIX];
+  // MEDIAN: the depth is the z of the entry at list position mp, so G_D
+  // reaches that entry's z only and no alpha
+  int mp[PIX];
 #pragma unroll
   for (int k = 0; k < PIX; ++k) {
     const int py = y0 + k * RPP + ly;
     const bool valid = px < fr.width && py < fr.height;
     const int64_t p = (int64_t)py * fr.width + px;
     last[k] = valid ? n_last[fr.pixel_offset + p] : 0;
+    mp[k] = (MEDIAN && valid) ? med_pos[fr.pixel_offset + p] : -1;
     T[k] = valid ? t_final[fr.pixel_offset + p] : 1.0f;
     B0[k] = bg0; B1[k] = bg1; B2[k] = bg2; BZ[k] = 0.0; BT[k] = 1.0f;
     const float* gi = g_rgb + 3 * fr.pixel_offset;
@@ -392,16 +407,19 @@ __device__ __forceinline__ void composite_bwd_tile(
         const double d0 = c0 - B0[k], d1 = c1 - B1[k], d2 = c2 - B2[k], dz = cz - BZ[k];
         // dL/da_i = T_i [G . (c_i - B_i) + G_D (z_i - BZ_i) + G_A BT_i]
         const float dLda = Ti * (G0[k] * (float)d0 + G1[k] * (float)d1 + G2[k] * (float)d2 +
-                                 GD[k] * (float)dz + GA[k] * BT[k]);
+                                 (MEDIAN ? 0.0f : GD[k] * (float)dz) + GA[k] * BT[k]);
         gc0 += G0[k] * w;
         gc1 += G1[k] * w;
         gc2 += G2[k] * w;
-        gz += GD[k] * w;
+        if (MEDIAN)
+          gz += pos == mp[k] ? GD[k] : 0.0f;
+        else
+          gz += GD[k] * w;
         // step the 'behind' state in front of entry i
         B0[k] = __builtin_fma(ad, d0, B0[k]);
         B1[k] = __builtin_fma(ad, d1, B1[k]);
         B2[k] = __builtin_fma(ad, d2, B2[k]);
-        BZ[k] = __builtin_fma(ad, dz, BZ[k]);
+        if (!MEDIAN) BZ[k] = __builtin_fma(ad, dz, BZ[k]);
         BT[k] = BT[k] * om;
         T[k] = Ti;
         any = true;
@@ -443,7 +461,7 @@ __device__ __forceinline__ void composite_bwd_tile(
   }
 }
 
-template <int TW, int TH>
+template <int TW, int TH, bool MEDIAN>
 __global__ void __launch_bounds__(64) composite_bwd_kernel(
     int n_tiles, int groups, const uint32_t* __restrict__ order, int n_frames,
     const FrameDesc* __restrict__ frames, const uint2* __restrict__ ranges,
@@ -453,15 +471,16 @@ __global__ void __launch_bounds__(64) composite_bwd_kernel(
     const float* __restrict__ g_rgb, const float* __restrict__ g_depth,
     const float* __restrict__ g_alpha, const float* __restrict__ t_final,
     const int32_t* __restrict__ n_last, float* __restrict__ partial,
-    uint32_t* __restrict__ stamp, const uint32_t* __restrict__ epoch_dev) {
+    uint32_t* __restrict__ stamp, const uint32_t* __restrict__ epoch_dev,
+    const int32_t* __restrict__ med_pos) {
   __shared__ Record sm[kWave];
   __shared__ uint32_t slot[kWave];
   const int tile = tile_of_block(blockIdx.x, n_tiles, groups, order);
   if (tile < 0) return;
   const uint32_t epoch = *epoch_dev;
-  composite_bwd_tile<TW, TH>(tile, sm, slot, epoch, n_frames, frames, ranges, vals, rec, trect,
-                             keyoff, tile_nproc, bg0, bg1, bg2, g_rgb, g_depth, g_alpha, t_final,
-                             n_last, partial, stamp);
+  composite_bwd_tile<TW, TH, MEDIAN>(tile, sm, slot, epoch, n_frames, frames, ranges, vals, rec,
+                                     trect, keyoff, tile_nproc, bg0, bg1, bg2, g_rgb, g_depth,
+                                     g_alpha, t_final, n_last, partial, stamp, med_pos);
 }
 
 static void launch_order(hipStream_t st, int n_tiles, int groups, const uint32_t* nproc,
@@ -474,22 +493,33 @@ static unsigned grid_of(int n_tiles, int groups) {
   return (unsigned)(((n_tiles + groups - 1) / groups) * groups);
 }
 
+template <int TW, int TH, bool COUNT, bool MEDIAN>
+static void launch_fwd_v(hipStream_t st, int n_tiles, int groups, const uint32_t* order, int F,
+                         const FrameDesc* frames, const uint2* ranges, const uint32_t* vals,
+                         const Record* rec, const float* bg, float* rgb, float* depth,
+                         float* alpha, float* t_final, int32_t* n_last, uint32_t* nproc,
+                         unsigned long long* pairs, int32_t* med_pos) {
+  auto k = composite_fwd_kernel<TW, TH, COUNT, MEDIAN>;
+  hipLaunchKernelGGL(k, dim3(grid_of(n_tiles, groups)), dim3(kWave), 0, st, n_tiles, groups,
+                     order, F, frames, ranges, vals, rec, bg[0], bg[1], bg[2], rgb, depth, alpha,
+                     t_final, n_last, nproc, pairs, med_pos);
+}
+
 template <int TW, int TH>
-static void launch_fwd_t(hipStream_t st, int n_tiles, int groups, const uint32_t* order, int F, const FrameDesc* frames, const uint2* ranges,
-                         const uint32_t* vals, const Record* rec, const float* bg, float* rgb,
-                         float* depth, float* alpha, float* t_final, int32_t* n_last,
-                         uint32_t* nproc, unsigned long long* pairs) {
+static void launch_fwd_t(hipStream_t st, int n_tiles, int groups, const uint32_t* order, int F,
+                         const FrameDesc* frames, const uint2* ranges, const uint32_t* vals,
+                         const Record* rec, const float* bg, float* rgb, float* depth,
+                         float* alpha, float* t_final, int32_t* n_last, uint32_t* nproc,
+                         unsigned long long* pairs, int32_t* med_pos) {
+#define GSR_FWD_V(C, M)                                                                        \
+  launch_fwd_v<TW, TH, C, M>(st, n_tiles, groups, order, F, frames, ranges, vals, rec, bg, rgb, \
+                             depth, alpha, t_final, n_last, nproc, pairs, med_pos)
   if (pairs) {
-    auto k = composite_fwd_kernel<TW, TH, true>;
-    hipLaunchKernelGGL(k, dim3(grid_of(n_tiles, groups)), dim3(kWave), 0, st, n_tiles,
-                       groups, order, F, frames, ranges, vals, rec, bg[0], bg[1], bg[2],
-                       rgb, depth, alpha, t_final, n_last, nproc, pairs);
+    if (med_pos) GSR_FWD_V(true, true); else GSR_FWD_V(true, false);
   } else {
-    auto k = composite_fwd_kernel<TW, TH, false>;
-    hipLaunchKernelGGL(k, dim3(grid_of(n_tiles, groups)), dim3(kWave), 0, st, n_tiles,
-                       groups, order, F, frames, ranges, vals, rec, bg[0], bg[1], bg[2],
-                       rgb, depth, alpha, t_final, n_last, nproc, pairs);
+    if (med_pos) GSR_FWD_V(false, true); else GSR_FWD_V(false, false);
   }
+#undef GSR_FWD_V
 }
 
 template <int TW, int TH>
@@ -498,12 +528,20 @@ static void launch_bwd_t(hipStream_t st, int n_tiles, int groups, const uint32_t
                          const uint32_t* keyoff, const uint32_t* nproc, const float* bg,
                          const float* g_rgb, const float* g_depth, const float* g_alpha,
                          const float* t_final, const int32_t* n_last, float* partial,
-                         uint32_t* stamp, const uint32_t* epoch) {
-  auto k = composite_bwd_kernel<TW, TH>;
-  hipLaunchKernelGGL(k, dim3(grid_of(n_tiles, groups)), dim3(kWave), 0, st, n_tiles,
-                     groups, order, F, frames, ranges, vals, rec, trect, keyoff, nproc,
-                     bg[0], bg[1], bg[2], g_rgb, g_depth, g_alpha, t_final, n_last, partial,
-                     stamp, epoch);
+                         uint32_t* stamp, const uint32_t* epoch, const int32_t* med_pos) {
+  if (med_pos) {
+    auto k = composite_bwd_kernel<TW, TH, true>;
+    hipLaunchKernelGGL(k, dim3(grid_of(n_tiles, groups)), dim3(kWave), 0, st, n_tiles,
+                       groups, order, F, frames, ranges, vals, rec, trect, keyoff, nproc,
+                       bg[0], bg[1], bg[2], g_rgb, g_depth, g_alpha, t_final, n_last, partial,
+                       stamp, epoch, med_pos);
+  } else {
+    auto k = composite_bwd_kernel<TW, TH, false>;
+    hipLaunchKernelGGL(k, dim3(grid_of(n_tiles, groups)), dim3(kWave), 0, st, n_tiles,
+                       groups, order, F, frames, ranges, vals, rec, trect, keyoff, nproc,
+                       bg[0], bg[1], bg[2], g_rgb, g_depth, g_alpha, t_final, n_last, partial,
+                       stamp, epoch, med_pos);
+  }
 }
 
 bool tile_shape_supported(int tw, int th) {
@@ -516,13 +554,13 @@ void launch_composite_fwd(hipStream_t st, int tw, int th, int n_tiles, int F,
                           const Record* rec, const float* bg, float* rgb, float* depth,
                           float* alpha, float* t_final, int32_t* n_last, uint32_t* nproc,
                           const uint32_t* prev_nproc, uint32_t* order, bool xcd_groups,
-                          unsigned long long* pairs) {
+                          unsigned long long* pairs, int32_t* med_pos) {
   if (n_tiles <= 0) return;
   const int groups = xcd_groups ? kQueues : 1;
   launch_order(st, n_tiles, groups, prev_nproc, order);
 #define GSR_FWD(W, H)                                                                         \
   launch_fwd_t<W, H>(st, n_tiles, groups, order, F, frames, ranges, vals, rec, bg, rgb,         \
-                     depth, alpha, t_final, n_last, nproc, pairs)
+                     depth, alpha, t_final, n_last, nproc, pairs, med_pos)
   if (tw == 16 && th == 16) GSR_FWD(16, 16);
   else if (tw == 8 && th == 8) GSR_FWD(8, 8);
   else if (tw == 32 && th == 8) GSR_FWD(32, 8);
@@ -537,14 +575,15 @@ void launch_composite_bwd(hipStream_t st, int tw, int th, int n_tiles, int F,
                           const uint32_t* nproc, const float* bg, const float* g_rgb,
                           const float* g_depth, const float* g_alpha, const float* t_final,
                           const int32_t* n_last, float* partial, uint32_t* stamp,
-                          const uint32_t* epoch, uint32_t* order, bool xcd_groups) {
+                          const uint32_t* epoch, uint32_t* order, bool xcd_groups,
+                          const int32_t* med_pos) {
   if (n_tiles <= 0) return;
   const int groups = xcd_groups ? kQueues : 1;
   launch_order(st, n_tiles, groups, nproc, order);
 #define GSR_BWD(W, H)                                                                          \
   launch_bwd_t<W, H>(st, n_tiles, groups, order, F, frames, ranges, vals, rec, trect,          \
                      keyoff, nproc, bg, g_rgb, g_depth, g_alpha, t_final, n_last, partial,     \
-                     stamp, epoch)
+                     stamp, epoch, med_pos)
   if (tw == 16 && th == 16) GSR_BWD(16, 16);
   else if (tw == 8 && th == 8) GSR_BWD(8, 8);
   else if (tw == 32 && th == 8) GSR_BWD(32, 8);

@@ -49,6 +49,7 @@ struct gsr_context {
   DBuf keys_a, vals_a, keys_b, vals_b, partial, stamp, grad2d;
   DBuf ranges, nproc, t_final, n_last, frames, twist_part, loss_part, loss_scale;
   DBuf ssim_part, ssim_tiles, ssim_scale;  // rendering loss with SSIM
+  DBuf med_pos;                     // per pixel: list position of the median-depth entry
   DBuf up_rgb, up_depth, up_alpha;  // upstream gradients for gsr_step_l1
   DBuf tune_out;                    // scratch outputs of the autotuner
   DBuf order_f, order_b;            // compositing tile schedules (forward, backward)
@@ -258,7 +259,7 @@ gsr_status gsr_destroy(gsr_context* ctx) {
                   &ctx->grad2d,
                   &ctx->stamp, &ctx->ranges, &ctx->nproc, &ctx->t_final, &ctx->n_last,
                   &ctx->frames, &ctx->twist_part, &ctx->loss_part, &ctx->loss_scale,
-                  &ctx->ssim_part, &ctx->ssim_tiles, &ctx->ssim_scale,
+                  &ctx->ssim_part, &ctx->ssim_tiles, &ctx->ssim_scale, &ctx->med_pos,
                   &ctx->up_rgb, &ctx->up_depth, &ctx->up_alpha, &ctx->tune_out,
                   &ctx->order_f, &ctx->order_b, &ctx->cls_a, &ctx->cls_b, &ctx->clsv_a,
                   &ctx->clsv_b};
@@ -333,6 +334,8 @@ gsr_status gsr_forward(gsr_context* ctx, const gsr_settings* s, int64_t n, const
   if ((rc = ensure(ctx, ctx->order_b, (size_t)T * 4, st))) return rc;
   if ((rc = ensure(ctx, ctx->t_final, (size_t)Px * 4, st))) return rc;
   if ((rc = ensure(ctx, ctx->n_last, (size_t)Px * 4, st))) return rc;
+  const bool median = (s->flags & GSR_FLAG_MEDIAN_DEPTH) != 0;
+  if (median && (rc = ensure(ctx, ctx->med_pos, (size_t)Px * 4, st))) return rc;
   uint64_t* d_count = P<uint64_t>(ctx->counters);               // [0] = K
   uint32_t* d_overflow = (uint32_t*)(P<uint64_t>(ctx->counters) + 1);
   const bool timing = (s->flags & GSR_FLAG_TIMING) != 0;
@@ -436,7 +439,8 @@ gsr_status gsr_forward(gsr_context* ctx, const gsr_settings* s, int64_t n, const
                          P<uint2>(ctx->ranges), svals, P<Record>(ctx->rec), s->background, rgb,
                          depth, alpha, P<float>(ctx->t_final), P<int32_t>(ctx->n_last),
                          P<uint32_t>(ctx->nproc), have_prev ? P<uint32_t>(ctx->nproc) : nullptr,
-                         P<uint32_t>(ctx->order_f), remap, count ? d_pairs : nullptr);
+                         P<uint32_t>(ctx->order_f), remap, count ? d_pairs : nullptr,
+                         median ? P<int32_t>(ctx->med_pos) : nullptr);
   }
   ctx->nproc_layout = layout;
   ctx->n_pairs = count ? -2 : -1;  // -2: count pending on the device
@@ -495,7 +499,8 @@ gsr_status gsr_backward(gsr_context* ctx, const float* g_rgb, const float* g_dep
                          g_depth, g_alpha,
                          P<float>(ctx->t_final), P<int32_t>(ctx->n_last),
                          P<float>(ctx->partial), P<uint32_t>(ctx->stamp), d_epoch,
-                         P<uint32_t>(ctx->order_b), remap);
+                         P<uint32_t>(ctx->order_b), remap,
+                         (s.flags & GSR_FLAG_MEDIAN_DEPTH) ? P<int32_t>(ctx->med_pos) : nullptr);
   }
   // A9-A11 per-record reduce, chain rule, twist
   const int64_t waves = sv.n > 0 ? preprocess_bwd_waves(sv.n) : 0;

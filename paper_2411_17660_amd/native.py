@@ -17,6 +17,7 @@ STATUS = {1: "INVALID_ARGUMENT", 2: "CAPACITY", 3: "OUT_OF_MEMORY", 4: "HIP_ERRO
 FLAG_NO_XCD_REMAP = 1
 FLAG_TIMING = 2
 FLAG_COUNT_PAIRS = 4
+FLAG_MEDIAN_DEPTH = 8
 STAGES = ["preprocess", "depth_sort", "offsets", "keygen", "tile_sort", "ranges",
           "composite_fwd", "loss", "composite_bwd", "preprocess_bwd"]
 
@@ -104,9 +105,9 @@ def load(path=LIB_PATH):
 
 
 def make_settings(sh_degree, background=(0.0, 0.0, 0.0), tile=(16, 16), key_capacity=0,
-                  xcd_remap=True, lds_batch=0, timing=False, count_pairs=False):
+                  xcd_remap=True, lds_batch=0, timing=False, count_pairs=False, median=False):
     flags = (0 if xcd_remap else FLAG_NO_XCD_REMAP) | (FLAG_TIMING if timing else 0) | \
-        (FLAG_COUNT_PAIRS if count_pairs else 0)
+        (FLAG_COUNT_PAIRS if count_pairs else 0) | (FLAG_MEDIAN_DEPTH if median else 0)
     return Settings(int(sh_degree), (C.c_float * 3)(*[float(b) for b in background]),
                     int(tile[0]), int(tile[1]), int(lds_batch), int(key_capacity), flags)
 

@@ -56,7 +56,7 @@ class Rasterizer:
 
     def forward(self, means, log_scales, quats, opacity, sh, poses, cams, sh_degree,
                 background=(0.0, 0.0, 0.0), tile=(16, 16), key_capacity=0, xcd_remap=True,
-                out=None, timing=False, count_pairs=False):
+                out=None, timing=False, count_pairs=False, median=False):
         """Renders F frames; returns packed (rgb [sum 3HW], depth [sum HW],
         alpha [sum HW]) float32 device tensors."""
         F = len(cams)
@@ -69,7 +69,8 @@ class Rasterizer:
         else:
             rgb, depth, alpha = out
         self.settings = native.make_settings(sh_degree, background, tile, key_capacity,
-                                             xcd_remap, timing=timing, count_pairs=count_pairs)
+                                             xcd_remap, timing=timing, count_pairs=count_pairs,
+                                             median=median)
         self.cams = native.make_cameras(cams)
         n = int(means.shape[0])
         self._check(self.lib.gsr_forward(self.h, C.byref(self.settings), n, _ptr(means),
@@ -126,11 +127,11 @@ class Rasterizer:
     def step_render(self, means, log_scales, quats, opacity, sh, poses, cams, sh_degree,
                     target_rgb, target_depth, bufs, lambda1=0.9, lambda2=0.2,
                     background=(0.0, 0.0, 0.0), tile=(16, 16), key_capacity=0, xcd_remap=True,
-                    timing=False):
+                    timing=False, median=False):
         """Forward + full rendering loss + backward in one call into
         preallocated `bufs` (as for step_l1, plus an optional `ssim` [F])."""
         self.settings = native.make_settings(sh_degree, background, tile, key_capacity,
-                                             xcd_remap, timing=timing)
+                                             xcd_remap, timing=timing, median=median)
         self.cams = native.make_cameras(cams)
         n = int(means.shape[0])
         b = bufs
@@ -146,11 +147,11 @@ class Rasterizer:
 
     def step_l1(self, means, log_scales, quats, opacity, sh, poses, cams, sh_degree,
                 target_rgb, target_depth, depth_weight, bufs, background=(0.0, 0.0, 0.0),
-                tile=(16, 16), key_capacity=0, xcd_remap=True, timing=False):
+                tile=(16, 16), key_capacity=0, xcd_remap=True, timing=False, median=False):
         """Forward + L1 loss + backward in one call into preallocated `bufs`
         (dict with rgb, depth, alpha, loss and the gradient tensors)."""
         self.settings = native.make_settings(sh_degree, background, tile, key_capacity,
-                                             xcd_remap, timing=timing)
+                                             xcd_remap, timing=timing, median=median)
         self.cams = native.make_cameras(cams)
         n = int(means.shape[0])
         b = bufs
@@ -245,9 +246,10 @@ class Rasterizer:
 class _RasterizeFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, means, log_scales, quats, opacity, sh, twist, poses, cams, sh_degree,
-                background, tile, rast):
+                background, tile, rast, median):
         inputs = [t.contiguous() for t in (means, log_scales, quats, opacity, sh, poses)]
-        rgb, depth, alpha = rast.forward(*inputs, cams, sh_degree, background, tile)
+        rgb, depth, alpha = rast.forward(*inputs, cams, sh_degree, background, tile,
+                                         median=median)
         # the library's backward reads the inputs again: hold them until then
         ctx.inputs = inputs
         ctx.rast = rast
@@ -264,17 +266,18 @@ class _RasterizeFn(torch.autograd.Function):
         g = rast.backward(z(g_rgb, 3 * P), z(g_depth, P), z(g_alpha, P))
         ctx.inputs = None
         return (g["means"], g["log_scales"], g["quats"], g["opacity"], g["sh"], g["twist"],
-                None, None, None, None, None, None)
+                None, None, None, None, None, None, None)
 
 
 def rasterize(means, log_scales, quats, opacity, sh, poses, cams, sh_degree, twist=None,
-              background=(0.0, 0.0, 0.0), tile=(16, 16), rasterizer=None):
+              background=(0.0, 0.0, 0.0), tile=(16, 16), rasterizer=None, median=False):
     """Differentiable render of F keyframes.  Returns packed (rgb, depth,
-    alpha).  Gradients reach every Gaussian tensor and `twist` ([F,6] zeros,
-    the left-perturbation of each pose at zero).  The backward of one forward
+    alpha); depth is alpha-blended, or the median depth with median=True.
+    Gradients reach every Gaussian tensor and `twist` ([F,6] zeros, the
+    left-perturbation of each pose at zero).  The backward of one forward
     must run before the next forward on the same `rasterizer`."""
     rast = rasterizer or Rasterizer(means.device.index or 0)
     if twist is None:
         twist = torch.zeros(len(cams), 6, device=means.device, requires_grad=False)
     return _RasterizeFn.apply(means, log_scales, quats, opacity, sh, twist, poses, cams,
-                              sh_degree, tuple(background), tuple(tile), rast)
+                              sh_degree, tuple(background), tuple(tile), rast, bool(median))

@@ -29,10 +29,11 @@ def _sizes(sc):
     return [(int(c[0]), int(c[1])) for c in sc.cams]
 
 
-def check_forward(rast, sc, tile=(16, 16), lists=True, label=""):
-    print(f"[parity] forward {label} n={sc.n} F={sc.n_frames} tile={tile}", flush=True)
-    ref = oracle.forward(sc, tile=tile, threads=oracle_threads())
-    _, rgb, dep, alp = gpu_forward(rast, sc, tile)
+def check_forward(rast, sc, tile=(16, 16), lists=True, label="", median=False):
+    print(f"[parity] forward {label} n={sc.n} F={sc.n_frames} tile={tile} median={median}",
+          flush=True)
+    ref = oracle.forward(sc, tile=tile, threads=oracle_threads(), median=median)
+    _, rgb, dep, alp = gpu_forward(rast, sc, tile, median=median)
     flags, nl_ref, tf_ref = ref.pixel_info()
     ok = flags == 0
     sizes = _sizes(sc)

@@ -195,6 +195,46 @@ gsr_status gsr_step_render(gsr_context* ctx, const gsr_settings* settings, int64
                            float* g_means, float* g_log_scales, float* g_quats,
                            float* g_opacity_logits, float* g_sh, float* g_twist, void* stream);
 
+/* Densification statistics (the adaptive density control of the 3DGS
+ * lineage that Sec. 3.3 describes: Gaussians are split and cloned by their
+ * size and positional gradient).  For every Gaussian g, adds to
+ * grad_accum[g] the sum over the frames f where (g, f) was kept by the last
+ * forward of |dL/d(u, v)|_2, the norm of the last backward's gradient with
+ * respect to the projected mean (pixel units), and adds the number of those
+ * frames to count[g].  grad_accum and count [n] are caller-owned device
+ * floats, accumulated into (zero them to start).  GSR_ERR_STATE unless a
+ * forward and its backward preceded. */
+gsr_status gsr_densify_stats(gsr_context* ctx, float* grad_accum, float* count, void* stream);
+
+/* MCMC densification, position noise (Sec. 3.3 and supplementary S1.2, which
+ * sets lr_noise = 1e4; the MCMC method the paper cites):
+ *   means[g] += scale * gate(o_g) * Sigma_g eps[g],
+ * Sigma_g = R_g diag(s_g^2) R_g^T the Gaussian's covariance (s = exp of the
+ * log-scales, R from the normalised quaternion), o_g = sigmoid(logit),
+ * gate(o) = 1 / (1 + exp(100 (o - 0.995))).  eps [n,3] are the caller's
+ * standard normal draws and scale = lr_noise x the current position learning
+ * rate.  Evaluated in FP64; means are updated in place. */
+gsr_status gsr_mcmc_noise(gsr_context* ctx, int64_t n, float* means, const float* log_scales,
+                          const float* quats, const float* opacity_logits, const float* eps,
+                          float scale, void* stream);
+
+/* MCMC densification, relocation of dead Gaussians.  src [n] (device int32)
+ * gives for each dead Gaussian g the live source i it moves to, and -1 for
+ * every other Gaussian (the caller samples the sources, in the method in
+ * proportion to opacity, among Gaussians with src = -1; a source must not be
+ * dead itself).  A source chosen c times becomes N = c + 1 copies at its
+ * place: opacity o' = 1 - (1 - o)^(1/N) (N copies over each other give back
+ * o), scales multiplied by o / sum_{m=1}^{N} C(N, m) (-1)^(m-1) o'^m /
+ * sqrt(m) (the composited opacity integrates along a line through the
+ * centre to the source's), means, quaternion and SH copied to the dead
+ * slots.  Entries of src outside [0, n) count as -1; N above 1024 is taken
+ * as 1024.  Parameters are updated in place; optimiser moments of the moved
+ * Gaussians are the caller's to reset.  Uses 36 bytes of workspace per
+ * Gaussian. */
+gsr_status gsr_mcmc_relocate(gsr_context* ctx, int64_t n, int32_t sh_degree, float* means,
+                             float* log_scales, float* quats, float* opacity_logits, float* sh,
+                             const int32_t* src, void* stream);
+
 /* Autotuner: runs gsr_step_l1 with every supported tile shape (16x16, 8x8,
  * 32x8, 16x8, 32x16) on the given inputs, `reps` timed runs each with HIP
  * events on `stream` after one untimed sizing run, and writes the fastest

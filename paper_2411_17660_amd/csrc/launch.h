@@ -86,6 +86,18 @@ void launch_loss_render(hipStream_t st, int F, int tiles_pad, const FrameDesc* f
                         double* part, double* tile_sums, double* frame_sums, float* loss,
                         float* ssim, float* g_rgb, float* g_depth, float* g_alpha);
 
+// densify.hip: ADC statistics of the last backward (grad2d [m][kNG], ntiles
+// [m], record r = f n + g), MCMC position noise and relocation.  src [n]:
+// the live source of each dead Gaussian, -1 (or out of range) otherwise;
+// cnt [n] (uint32) and rule [n][4] (double) are scratch.
+void launch_densify_stats(hipStream_t st, int64_t n, int F, const uint32_t* ntiles,
+                          const double* grad2d, float* grad_accum, float* count);
+void launch_mcmc_noise(hipStream_t st, int64_t n, float* means, const float* log_scales,
+                       const float* quats, const float* opac, const float* eps, float scale);
+void launch_mcmc_relocate(hipStream_t st, int64_t n, int ksh3, float* means, float* log_scales,
+                          float* quats, float* opac, float* sh, const int32_t* src,
+                          uint32_t* cnt, double* rule);
+
 // adam.hip
 void launch_adam(hipStream_t st, uint64_t n3, uint64_t nsh, float* means, const float* g_means,
                  float* m_means, float* v_means, float* sh, const float* g_sh, float* m_sh,

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <map>
 #include <cstdio>
@@ -37,6 +38,7 @@ struct Saved {
   bool k_known = false;
   bool sorted_in_b = false;   // tile sort result buffer
   bool recs_in_b = false;     // depth sort result buffer
+  bool has_backward = false;  // a backward of this forward has filled grad2d
 };
 
 }  // namespace
@@ -50,6 +52,7 @@ struct gsr_context {
   DBuf ranges, nproc, t_final, n_last, frames, twist_part, loss_part, loss_scale;
   DBuf ssim_part, ssim_tiles, ssim_scale;  // rendering loss with SSIM
   DBuf med_pos;                     // per pixel: list position of the median-depth entry
+  DBuf reloc_cnt, reloc_rule;       // MCMC relocation scratch
   DBuf up_rgb, up_depth, up_alpha;  // upstream gradients for gsr_step_l1
   DBuf tune_out;                    // scratch outputs of the autotuner
   DBuf order_f, order_b;            // compositing tile schedules (forward, backward)
@@ -260,6 +263,7 @@ gsr_status gsr_destroy(gsr_context* ctx) {
                   &ctx->stamp, &ctx->ranges, &ctx->nproc, &ctx->t_final, &ctx->n_last,
                   &ctx->frames, &ctx->twist_part, &ctx->loss_part, &ctx->loss_scale,
                   &ctx->ssim_part, &ctx->ssim_tiles, &ctx->ssim_scale, &ctx->med_pos,
+                  &ctx->reloc_cnt, &ctx->reloc_rule,
                   &ctx->up_rgb, &ctx->up_depth, &ctx->up_alpha, &ctx->tune_out,
                   &ctx->order_f, &ctx->order_b, &ctx->cls_a, &ctx->cls_b, &ctx->clsv_a,
                   &ctx->clsv_b};
@@ -447,6 +451,7 @@ gsr_status gsr_forward(gsr_context* ctx, const gsr_settings* s, int64_t n, const
   GSR_HIP(hipGetLastError());
   Saved& sv = ctx->s;
   sv.valid = true;
+  sv.has_backward = false;
   sv.set = *s;
   sv.n = n;
   sv.F = F;
@@ -530,6 +535,63 @@ gsr_status gsr_backward(gsr_context* ctx, const float* g_rgb, const float* g_dep
                           P<double>(ctx->grad2d), g_means, g_log_scales, g_quats, g_opac, g_sh,
                           P<double>(ctx->twist_part), g_twist);
   }
+  GSR_HIP(hipGetLastError());
+  sv.has_backward = true;
+  return GSR_OK;
+}
+
+gsr_status gsr_densify_stats(gsr_context* ctx, float* grad_accum, float* count, void* stream) {
+  if (!ctx) return GSR_ERR_INVALID_ARGUMENT;
+  const Saved& sv = ctx->s;
+  if (!sv.valid || !sv.has_backward)
+    return fail(ctx, GSR_ERR_STATE, "densify statistics need a forward and its backward");
+  if (sv.n > 0 && (!grad_accum || !count))
+    return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "pointer is NULL");
+  if ((((uintptr_t)grad_accum) | ((uintptr_t)count)) & 3u)
+    return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "pointer not 4-aligned");
+  GSR_HIP(hipSetDevice(ctx->device));
+  launch_densify_stats((hipStream_t)stream, sv.n, sv.F, P<uint32_t>(ctx->ntiles),
+                       P<double>(ctx->grad2d), grad_accum, count);
+  GSR_HIP(hipGetLastError());
+  return GSR_OK;
+}
+
+gsr_status gsr_mcmc_noise(gsr_context* ctx, int64_t n, float* means, const float* log_scales,
+                          const float* quats, const float* opacity_logits, const float* eps,
+                          float scale, void* stream) {
+  if (!ctx) return GSR_ERR_INVALID_ARGUMENT;
+  if (n < 0) return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "n < 0");
+  if (n > 0 && (!means || !log_scales || !quats || !opacity_logits || !eps))
+    return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "pointer is NULL");
+  const void* ptrs[] = {means, log_scales, quats, opacity_logits, eps};
+  for (const void* p : ptrs)
+    if (((uintptr_t)p) & 3u) return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "pointer not 4-aligned");
+  if (!std::isfinite(scale)) return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "scale not finite");
+  GSR_HIP(hipSetDevice(ctx->device));
+  launch_mcmc_noise((hipStream_t)stream, n, means, log_scales, quats, opacity_logits, eps, scale);
+  GSR_HIP(hipGetLastError());
+  return GSR_OK;
+}
+
+gsr_status gsr_mcmc_relocate(gsr_context* ctx, int64_t n, int32_t sh_degree, float* means,
+                             float* log_scales, float* quats, float* opacity_logits, float* sh,
+                             const int32_t* src, void* stream) {
+  if (!ctx) return GSR_ERR_INVALID_ARGUMENT;
+  if (n < 0 || sh_degree < 0 || sh_degree > 3)
+    return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "n < 0 or sh_degree outside 0..3");
+  if (n > 0 && (!means || !log_scales || !quats || !opacity_logits || !sh || !src))
+    return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "pointer is NULL");
+  const void* ptrs[] = {means, log_scales, quats, opacity_logits, sh, src};
+  for (const void* p : ptrs)
+    if (((uintptr_t)p) & 3u) return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "pointer not 4-aligned");
+  hipStream_t st = (hipStream_t)stream;
+  GSR_HIP(hipSetDevice(ctx->device));
+  gsr_status rc;
+  if ((rc = ensure(ctx, ctx->reloc_cnt, (size_t)n * 4, st))) return rc;
+  if ((rc = ensure(ctx, ctx->reloc_rule, (size_t)n * 32, st))) return rc;
+  const int ksh3 = 3 * (sh_degree + 1) * (sh_degree + 1);
+  launch_mcmc_relocate(st, n, ksh3, means, log_scales, quats, opacity_logits, sh, src,
+                       P<uint32_t>(ctx->reloc_cnt), P<double>(ctx->reloc_rule));
   GSR_HIP(hipGetLastError());
   return GSR_OK;
 }

@@ -23,7 +23,7 @@ STAGES = ["preprocess", "depth_sort", "offsets", "keygen", "tile_sort", "ranges"
 
 EXPORTS = ["gsr_create", "gsr_destroy", "gsr_last_error", "gsr_forward", "gsr_backward",
            "gsr_loss_l1", "gsr_step_l1", "gsr_loss_render", "gsr_step_render",
-           "gsr_check_overflow", "gsr_debug_stats",
+           "gsr_densify_stats", "gsr_mcmc_noise", "gsr_mcmc_relocate", "gsr_check_overflow", "gsr_debug_stats",
            "gsr_debug_timings", "gsr_debug_lists", "gsr_debug_grad2d", "gsr_autotune",
            "gsr_adam_step"]
 TILE_SHAPES = [(16, 16), (8, 8), (32, 8), (16, 8), (32, 16)]
@@ -87,6 +87,9 @@ def load(path=LIB_PATH):
     lib.gsr_step_render.argtypes = [V, C.POINTER(Settings), I64, V, V, V, V, V, I32,
                                     C.POINTER(Camera), V, V, V, F32, F32, V, V, V, V, V, V, V,
                                     V, V, V, V, V]
+    lib.gsr_densify_stats.argtypes = [V, V, V, V]
+    lib.gsr_mcmc_noise.argtypes = [V, I64, V, V, V, V, V, F32, V]
+    lib.gsr_mcmc_relocate.argtypes = [V, I64, I32, V, V, V, V, V, V, V]
     lib.gsr_check_overflow.argtypes = [V, V]
     lib.gsr_debug_stats.argtypes = [V, C.POINTER(Stats), V]
     lib.gsr_debug_lists.argtypes = [V] + [V] * 8 + [V]

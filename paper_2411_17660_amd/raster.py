@@ -145,6 +145,25 @@ class Rasterizer:
         self.n, self.F, self.sh_degree = n, len(cams), sh_degree
         self.sizes = [(int(c[0]), int(c[1])) for c in cams]
 
+    def densify_stats(self, grad_accum, count):
+        """Adds the last backward's |dL/d(u, v)| per kept (Gaussian, frame)
+        to grad_accum [n] and the number of such frames to count [n]."""
+        self._check(self.lib.gsr_densify_stats(self.h, _ptr(grad_accum), _ptr(count), _stream()))
+
+    def mcmc_noise(self, means, log_scales, quats, opacity, eps, scale):
+        """means += scale * gate(opacity) * Sigma eps, in place."""
+        self._check(self.lib.gsr_mcmc_noise(self.h, int(means.shape[0]), _ptr(means),
+                                            _ptr(log_scales), _ptr(quats), _ptr(opacity),
+                                            _ptr(eps), float(scale), _stream()))
+
+    def mcmc_relocate(self, means, log_scales, quats, opacity, sh, src, sh_degree):
+        """Moves dead Gaussians (src[g] = source index, else -1; int32) onto
+        their sources with the relocation rule, in place."""
+        assert src.is_cuda and src.dtype == torch.int32 and src.is_contiguous()
+        self._check(self.lib.gsr_mcmc_relocate(
+            self.h, int(means.shape[0]), int(sh_degree), _ptr(means), _ptr(log_scales),
+            _ptr(quats), _ptr(opacity), _ptr(sh), C.c_void_p(src.data_ptr()), _stream()))
+
     def step_l1(self, means, log_scales, quats, opacity, sh, poses, cams, sh_degree,
                 target_rgb, target_depth, depth_weight, bufs, background=(0.0, 0.0, 0.0),
                 tile=(16, 16), key_capacity=0, xcd_remap=True, timing=False, median=False):

@@ -204,6 +204,9 @@ def main():
 
     # ---------------- the paper's full rendering loss (L1 + SSIM colour term)
     render = measure_render_loss(rast, sc, dev, bb, t_rgb, t_dep, tile, cap, args.steps)
+    median = measure_median(rast, sc, dev, bb, t_rgb, t_dep, tile, cap, args.steps,
+                            depth_weight)
+    densify = measure_densify(rast, sc, dev, bb, t_rgb, t_dep, tile, cap, depth_weight)
 
     mpix = P / 1e6
     t_best = min(t_batched, t_graph) if t_graph else t_batched
@@ -244,6 +247,8 @@ def main():
         "loss": loss,
         "roofline": roofline,
         "render_loss": render,
+        "median_depth": median,
+        "densify": densify,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -315,6 +320,83 @@ def measure_render_loss(rast, sc, dev, bb, t_rgb, t_dep, tile, cap, steps):
             "fp64_flops_per_call": flops, "achieved_fp64_TFLOPs": round(tfl, 3),
             "frac_fp64_peak": round(tfl / PEAK_FP64_VECTOR_TFLOPS, 4),
             "step_ms": round(t_step * 1e3, 4), "step_mpix_per_s": round(P / 1e6 / t_step, 3)}
+
+
+def measure_median(rast, sc, dev, bb, t_rgb, t_dep, tile, cap, steps, depth_weight):
+    """The same L1 step with the median depth (GSR_FLAG_MEDIAN_DEPTH): step
+    time and the compositing stages from HIP events on the library's stream."""
+    import torch
+
+    def mstep(timing=False):
+        rast.step_l1(dev["means"], dev["log_scales"], dev["quats"], dev["opacity"], dev["sh"],
+                     dev["poses"], sc.cams, 3, t_rgb, t_dep, depth_weight, bb, tile=tile,
+                     key_capacity=cap, timing=timing, median=True)
+    for _ in range(2):
+        mstep()
+    torch.cuda.synchronize()
+    rast.timings()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        mstep(timing=True)
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t0) / steps
+    rast.check_overflow()
+    st = rast.timings()
+    per = {k: round(st[k][0] / max(steps, 1), 4) for k in ("composite_fwd", "composite_bwd")}
+    log(f"[bench] median-depth step {t_step * 1e3:.2f} ms, {per}")
+    return {"step_ms": round(t_step * 1e3, 4), "step_mpix_per_s": round(sc.n_pixels / 1e6 / t_step, 3),
+            "stage_ms_per_step": per}
+
+
+def _event_ms(fn, reps=20):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def measure_densify(rast, sc, dev, bb, t_rgb, t_dep, tile, cap, depth_weight):
+    """The densification kernels on the workload's Gaussians (HIP events on
+    the library's stream), against the HBM bytes they must move: ADC
+    statistics read, per (Gaussian, frame) record, the tile count (4 B) and
+    dL/d(u, v) (16 B) and per Gaussian read-modify-write two floats (16 B);
+    MCMC noise reads means, log-scales, quaternion, opacity and the normal
+    draw (52 B) and writes the means (12 B); relocation with no dead
+    Gaussians reads src (4 B) and writes and reads the 4-byte counter."""
+    import torch
+    n, F = sc.n, sc.n_frames
+    rast.step_l1(dev["means"], dev["log_scales"], dev["quats"], dev["opacity"], dev["sh"],
+                 dev["poses"], sc.cams, 3, t_rgb, t_dep, depth_weight, bb, tile=tile,
+                 key_capacity=cap)
+    acc = torch.zeros(n, device="cuda")
+    cnt = torch.zeros(n, device="cuda")
+    ms_stats = _event_ms(lambda: rast.densify_stats(acc, cnt))
+    means = dev["means"].clone()
+    eps = torch.randn(n, 3, device="cuda", generator=torch.Generator("cuda").manual_seed(0))
+    ms_noise = _event_ms(lambda: rast.mcmc_noise(means, dev["log_scales"], dev["quats"],
+                                                 dev["opacity"], eps, 1e-9))
+    src = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+    p = {k: dev[k].clone() for k in ("means", "log_scales", "quats", "opacity", "sh")}
+    ms_reloc = _event_ms(lambda: rast.mcmc_relocate(p["means"], p["log_scales"], p["quats"],
+                                                    p["opacity"], p["sh"], src, 3))
+    b_stats = n * F * 20 + n * 16
+    b_noise = n * 64
+    b_reloc = n * 12
+
+    def row(ms, b):
+        gbs = b / (ms * 1e-3) / 1e9
+        return {"ms": round(ms, 4), "hbm_bytes": b, "achieved_GBps": round(gbs, 1),
+                "frac_hbm": round(gbs / PEAK_HBM_GBS, 4)}
+    out = {"stats": row(ms_stats, b_stats), "mcmc_noise": row(ms_noise, b_noise),
+           "mcmc_relocate_no_dead": row(ms_reloc, b_reloc)}
+    log(f"[bench] densify kernels {out}")
+    return out
 
 
 def measured_traffic(kernel, tile):

@@ -1,6 +1,6 @@
 """Pins of the oracle's median-depth mode (no GPU).
 
-The paper renders depth "following MonoGS for median depth" (Sec. 3.3): the
+Sec. 3.3 names MonoGS's median depth as the depth the renderer outputs: the
 depth at which a pixel's transmittance first falls below 1/2.  Read as: the
 z of the first blended entry k (front to back) with T_k (1 - a_k) < 1/2, or
 0 where T never falls below 1/2; its gradient reaches that entry's z only.

@@ -1,0 +1,226 @@
+"""2D Gaussian surfel (2DGS) renderer, plain PyTorch FP64 on the CPU (test
+infrastructure).
+
+Only tests/, __graft_entry__.smoke() and bench.py's cpu_baseline leg use
+this module; it shares no code with the HIP path.  Gradients are PyTorch's
+autograd of this forward.
+
+DROID-Splat compares its 3D Gaussians with 2D surfel Gaussians (Sec. 3.3,
+tab:renderer; the 2DGS method it cites): flat disks that are intersected with
+each pixel's ray instead of being projected as 2D Gaussians.  Per surfel:
+mean mu, two log-scales (s_u, s_v), rotation q (w, x, y, z) whose first two
+axes t_u, t_v span the disk and whose third is its normal, opacity logit and
+SH colour (as for the 3D Gaussians).  Per frame, with the world->camera pose
+[R_f | t_f] and K = [[fx, 0, cx], [0, fy, cy], [0, 0, 1]]:
+    M = K [s_u R_f t_u | s_v R_f t_v | R_f mu + t_f]        (3 x 3, rows M0..M2)
+maps disk coordinates (u, v, 1) to homogeneous pixels.  The ray through
+pixel (x, y) meets the disk at (u, v) = (p0 / p2, p1 / p2), p = h_u x h_v,
+h_u = x M2 - M0, h_v = y M2 - M1, at depth z = M2 . (u, v, 1).  Readings
+where the paper is silent (design notes, reading 18):
+  - G = exp(-(u^2 + v^2) / 2); the screen-space low-pass of 2DGS,
+    G_lp = exp(-|(x, y) - c|^2) (standard deviation sqrt(2)/2 px around the
+    projected centre c), and G' = max(G, G_lp); a pixel where G_lp wins
+    sees the surfel at its centre's depth;
+  - alpha = min(0.99, sigma G'), skip alpha < 1/255, stop before T < 1e-4,
+    front to back in order of (fp32(centre depth) bits, index), as for the
+    3D Gaussians;
+  - a surfel contributes only inside its pixel box: the bounding box of the
+    projected corners of the square |u|, |v| <= r_a (r_a = sqrt(2 ln(255
+    sigma)), outside which G < 1/(255 sigma)) united with the square of half
+    width sqrt(ln(255 sigma)) around c (where G_lp can reach it), as
+    [ceil(lo), floor(hi)] clipped to the image; culled if sigma <= 1/255,
+    if the centre or a corner is not in front of the near plane, or if the
+    box is empty;
+  - outputs: RGB (+ T_final * background), depth sum_i w_i z_i, alpha
+    1 - T_final and normal sum_i w_i n_i with n_i = R_f t_w turned to face
+    the camera (n . (R_f mu + t_f) < 0), in camera coordinates.
+"""
+import math
+
+import numpy as np
+import torch
+
+A_MIN = float(np.float32(1.0 / 255.0))
+A_MAX = float(np.float32(0.99))
+T_MIN = float(np.float32(1e-4))
+BAND = 1e-4
+EPS32 = 2.0 ** -24
+
+FLAG_ALPHA, FLAG_T, FLAG_CLAMP, FLAG_LOWPASS = 1, 2, 4, 16
+
+
+def _rot(q):
+    q = q / torch.linalg.norm(q, dim=-1, keepdim=True)
+    w, x, y, z = q.unbind(-1)
+    return torch.stack([
+        torch.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)], -1),
+        torch.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)], -1),
+        torch.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], -1)],
+        -2)
+
+
+def _skew(v):
+    z = torch.zeros_like(v[0])
+    return torch.stack([torch.stack([z, -v[2], v[1]]), torch.stack([v[2], z, -v[0]]),
+                        torch.stack([-v[1], v[0], z])])
+
+
+def _sh_colour(sh, deg, dirs):
+    """max(0, sum_k sh_k Y_k(dir) + 1/2) with the real SH basis of the 3D
+    Gaussians (textbook magnitudes, sign (-1)^|m|)."""
+    pi = math.pi
+    x, y, z = dirs.unbind(-1)
+    Y = [torch.full_like(x, 0.5 / math.sqrt(pi))]
+    if deg >= 1:
+        k = math.sqrt(3.0 / (4.0 * pi))
+        Y += [-k * y, k * z, -k * x]
+    if deg >= 2:
+        a, b, c = 0.5 * math.sqrt(15.0 / pi), 0.25 * math.sqrt(5.0 / pi), 0.25 * math.sqrt(15.0 / pi)
+        Y += [a * x * y, -a * y * z, b * (2 * z * z - x * x - y * y), -a * x * z,
+              c * (x * x - y * y)]
+    if deg >= 3:
+        a = 0.25 * math.sqrt(35.0 / (2 * pi))
+        b = 0.5 * math.sqrt(105.0 / pi)
+        c = 0.25 * math.sqrt(21.0 / (2 * pi))
+        d = 0.25 * math.sqrt(7.0 / pi)
+        e = 0.25 * math.sqrt(105.0 / pi)
+        Y += [-a * y * (3 * x * x - y * y), b * x * y * z, -c * y * (4 * z * z - x * x - y * y),
+              d * z * (2 * z * z - 3 * x * x - 3 * y * y), -c * x * (4 * z * z - x * x - y * y),
+              e * z * (x * x - y * y), -a * x * (x * x - 3 * y * y)]
+    Yt = torch.stack(Y, -1)                       # [n, K]
+    raw = torch.einsum("nk,nkc->nc", Yt, sh) + 0.5
+    return torch.clamp(raw, min=0.0)
+
+
+def render(means, log_scales, quats, opacity_logits, sh, sh_degree, cams, poses,
+           background=(0.0, 0.0, 0.0), twist=None):
+    """FP64 torch tensors in (means [n,3], log_scales [n,2], quats [n,4],
+    opacity_logits [n], sh [n,K,3], poses [F,3,4]; twist [F,6] = (rho, phi)
+    left perturbation, first order at 0).  Returns a list per frame of dicts
+    rgb [3,H,W], depth, alpha [H,W], normal [3,H,W], flags [H,W] (uint8,
+    numpy) and box (numpy int [n,4] x_lo, x_hi, y_lo, y_hi, -1 if culled)."""
+    out = []
+    bg = torch.tensor([float(b) for b in background], dtype=torch.float64)
+    Rg = _rot(quats)                                # [n,3,3]
+    su, sv = torch.exp(log_scales[:, 0]), torch.exp(log_scales[:, 1])
+    opac = torch.sigmoid(opacity_logits)
+    for f, cam in enumerate(cams):
+        W, H, fx, fy, cx, cy, near = [float(v) for v in cam[:7]]
+        W, H = int(W), int(H)
+        Rf, tf = poses[f, :, :3], poses[f, :, 3]
+        if twist is not None:
+            Kx = _skew(twist[f, 3:])
+            Rf = Rf + Kx @ Rf
+            tf = tf + Kx @ tf + twist[f, :3]
+        K = torch.tensor([[fx, 0.0, cx], [0.0, fy, cy], [0.0, 0.0, 1.0]], dtype=torch.float64)
+        tu = torch.einsum("ij,njk->nik", Rf, Rg)[:, :, 0]
+        tv = torch.einsum("ij,njk->nik", Rf, Rg)[:, :, 1]
+        tw = torch.einsum("ij,njk->nik", Rf, Rg)[:, :, 2]
+        mc = means @ Rf.T + tf
+        M = torch.stack([(su[:, None] * tu) @ K.T, (sv[:, None] * tv) @ K.T, mc @ K.T], -1)
+        # M[n] columns: a, b, c  -> rows M0, M1, M2
+        ctr = torch.stack([M[:, 0, 2] / M[:, 2, 2], M[:, 1, 2] / M[:, 2, 2]], -1)
+        nrm = torch.where(((tw * mc).sum(-1) < 0)[:, None], tw, -tw)
+        # colour: direction from the camera centre to the mean
+        Cw = -(Rf.T @ tf)
+        d = means - Cw
+        dirs = d / torch.linalg.norm(d, dim=-1, keepdim=True)
+        col = _sh_colour(sh, sh_degree, dirs)
+        n = means.shape[0]
+        box = -np.ones((n, 4), np.int64)
+        with torch.no_grad():
+            for g in range(n):
+                o = float(opac[g])
+                zc = float(mc[g, 2])
+                if not (o > A_MIN) or not (zc > near):
+                    continue
+                ra = math.sqrt(2.0 * math.log(o / A_MIN))
+                rl = math.sqrt(math.log(o / A_MIN))
+                Mg = M[g].detach().numpy()
+                pts = []
+                ok = True
+                for a_ in (-ra, ra):
+                    for b_ in (-ra, ra):
+                        hp = Mg @ np.array([a_, b_, 1.0])
+                        if not (hp[2] > near):
+                            ok = False
+                        else:
+                            pts.append(hp[:2] / hp[2])
+                if not ok:
+                    continue
+                pts = np.array(pts)
+                c0 = ctr[g].detach().numpy()
+                lo = np.minimum(pts.min(0), c0 - rl)
+                hi = np.maximum(pts.max(0), c0 + rl)
+                x_lo, x_hi = max(0, math.ceil(lo[0])), min(W - 1, math.floor(hi[0]))
+                y_lo, y_hi = max(0, math.ceil(lo[1])), min(H - 1, math.floor(hi[1]))
+                if x_lo <= x_hi and y_lo <= y_hi:
+                    box[g] = (x_lo, x_hi, y_lo, y_hi)
+            keep = np.nonzero(box[:, 0] >= 0)[0]
+            zbits = mc[:, 2].detach().numpy().astype(np.float32).view(np.uint32)
+            order = keep[np.lexsort((keep, zbits[keep]))]
+        ys, xs = torch.meshgrid(torch.arange(H, dtype=torch.float64),
+                                torch.arange(W, dtype=torch.float64), indexing="ij")
+        T = torch.ones(H, W, dtype=torch.float64)
+        C = torch.zeros(3, H, W, dtype=torch.float64)
+        D = torch.zeros(H, W, dtype=torch.float64)
+        N = torch.zeros(3, H, W, dtype=torch.float64)
+        done = torch.zeros(H, W, dtype=torch.bool)
+        flags = np.zeros((H, W), np.uint8)
+        nb = torch.zeros(H, W, dtype=torch.float64)
+        for g in order:
+            x_lo, x_hi, y_lo, y_hi = box[g]
+            inside = (xs >= x_lo) & (xs <= x_hi) & (ys >= y_lo) & (ys <= y_hi) & ~done
+            if not bool(inside.any()):
+                continue
+            M0, M1, M2 = M[g, 0], M[g, 1], M[g, 2]
+            hu = xs[..., None] * M2 - M0
+            hv = ys[..., None] * M2 - M1
+            p = torch.linalg.cross(hu, hv, dim=-1)
+            # conditioning of the intersection: 1 / sin of the angle of h_u, h_v
+            kappa = (torch.linalg.norm(hu, dim=-1) * torch.linalg.norm(hv, dim=-1)
+                     / torch.linalg.norm(p, dim=-1).clamp(min=1e-300)).detach()
+            ok = p[..., 2].abs() > 1e-300
+            p2 = torch.where(ok, p[..., 2], torch.ones_like(p[..., 2]))
+            u, v = p[..., 0] / p2, p[..., 1] / p2
+            q = torch.where(ok, u * u + v * v, torch.full_like(u, float("inf")))
+            G = torch.exp(-0.5 * q)
+            dd = (xs - ctr[g, 0]) ** 2 + (ys - ctr[g, 1]) ** 2
+            Glp = torch.exp(-dd)
+            use_obj = G >= Glp
+            Gh = torch.where(use_obj, G, Glp)
+            zint = torch.where(use_obj, M2[0] * u + M2[1] * v + M2[2], mc[g, 2].expand_as(u))
+            araw = opac[g] * Gh
+            a = torch.clamp(araw, max=A_MAX)
+            with torch.no_grad():
+                an, Tn_ = a.detach().numpy(), (T * (1 - a)).detach().numpy()
+                ins = inside.numpy()
+                band_a = np.maximum(BAND, 64 * EPS32 * (1 + np.minimum(q.detach().numpy(), 1e30))
+                                    * np.minimum(kappa.numpy(), 1e30))
+                flags[ins & (np.abs(an - A_MIN) < band_a * A_MIN)] |= FLAG_ALPHA
+                live = ins & (an >= A_MIN)
+                band_t = np.maximum(BAND, 4 * EPS32 * (nb.numpy() + 1))
+                flags[live & (np.abs(Tn_ - T_MIN) < band_t * T_MIN)] |= FLAG_T
+                flags[live & (np.abs(araw.detach().numpy() - A_MAX) < BAND * A_MAX)] |= FLAG_CLAMP
+                Gn, Gl = G.detach().numpy(), Glp.detach().numpy()
+                flags[live & (np.abs(Gn - Gl) < 1e-3 * np.maximum(Gn, Gl))] |= FLAG_LOWPASS
+            blend = inside & (a >= A_MIN)
+            Tn = T * (1 - a)
+            stop = blend & (Tn < T_MIN)
+            done = done | stop
+            blend = blend & ~stop
+            w = torch.where(blend, a * T, torch.zeros_like(T))
+            C = C + col[g][:, None, None] * w
+            D = D + zint * w
+            N = N + nrm[g][:, None, None] * w
+            T = torch.where(blend, Tn, T)
+            nb = nb + blend.to(torch.float64)
+        rgb = C + T * bg[:, None, None]
+        out.append(dict(rgb=rgb, depth=D, alpha=1 - T, normal=N, flags=flags, box=box,
+                        order=order))
+    return out
+
+
+def to64(a, grad=False):
+    t = torch.from_numpy(np.ascontiguousarray(np.asarray(a, np.float64)))
+    return t.requires_grad_(grad)

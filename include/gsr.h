@@ -132,6 +132,32 @@ gsr_status gsr_forward(gsr_context* ctx, const gsr_settings* settings, int64_t n
                        const gsr_camera* cams, const float* poses, float* rgb, float* depth,
                        float* alpha, void* stream);
 
+/* Forward render of F frames with 2D Gaussian surfels instead of 3D
+ * Gaussians (the primitive Sec. 3.3 and tab:renderer compare, after the 2DGS
+ * method the paper cites).  A surfel is a flat disk: means [n,3], log_scales
+ * [n,2] (its two in-plane scales), quats [n,4] (w, x, y, z; the first two
+ * rotated axes span the disk, the third is its normal), opacity logits and
+ * SH colour as for gsr_forward.  Each pixel's ray is intersected with the
+ * disk: with M = K [s_u R_f t_u | s_v R_f t_v | R_f mu + t_f] (rows M0..M2),
+ * (u, v) = (p0/p2, p1/p2), p = (x M2 - M0) x (y M2 - M1); G = exp(-(u^2 +
+ * v^2)/2), the screen-space low-pass G_lp = exp(-|(x, y) - c|^2) around the
+ * projected centre c, alpha = min(0.99, sigma max(G, G_lp)); compositing,
+ * thresholds and order as gsr_forward (by the centre's depth).  Outputs rgb,
+ * depth (sum_i w_i z_i with z_i = M2 . (u, v, 1), the centre's depth where
+ * G_lp is the larger), alpha, and normal [sum_f 3 H_f W_f] (CHW per frame,
+ * sum_i w_i n_i, n_i the disk normal in the camera frame turned to face the
+ * camera).  A surfel covers the pixel box of the projected corners of |u|,
+ * |v| <= sqrt(2 ln(255 sigma)) united with the square of half width
+ * sqrt(ln(255 sigma)) around c, and is culled when sigma <= 1/255 or the
+ * centre or a corner is not beyond the near plane.  GSR_FLAG_MEDIAN_DEPTH
+ * and GSR_FLAG_COUNT_PAIRS are not supported (GSR_ERR_UNSUPPORTED).
+ * gsr_backward after this forward returns GSR_ERR_STATE. */
+gsr_status gsr_forward_surfel(gsr_context* ctx, const gsr_settings* settings, int64_t n,
+                              const float* means, const float* log_scales, const float* quats,
+                              const float* opacity_logits, const float* sh, int32_t n_frames,
+                              const gsr_camera* cams, const float* poses, float* rgb,
+                              float* depth, float* alpha, float* normal, void* stream);
+
 /* Backward of the last forward on ctx for upstream gradients g_rgb, g_depth,
  * g_alpha (packed like the outputs).  Writes g_means [n,3], g_log_scales
  * [n,3], g_quats [n,4], g_opacity_logits [n], g_sh [n,(d+1)^2,3] (summed

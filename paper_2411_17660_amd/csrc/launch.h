@@ -98,6 +98,21 @@ void launch_mcmc_relocate(hipStream_t st, int64_t n, int ksh3, float* means, flo
                           float* quats, float* opac, float* sh, const int32_t* src,
                           uint32_t* cnt, double* rule);
 
+// surfel.hip: the 2D surfel variant's preprocess (records of
+// surfel_record_bytes() bytes in `rec`) and forward compositing (rgb, depth,
+// alpha, normal [sum 3HW]); keys, sorts and ranges are shared.
+size_t surfel_record_bytes();
+size_t surfel_square_offset();  // byte offset of the box bounds sqx, sqy
+void launch_surfel_preprocess(hipStream_t st, int64_t n, int F, const FrameDesc* frames,
+                              const float* poses, const float* means, const float* log_scales,
+                              const float* quats, const float* opac, const float* sh, int deg,
+                              int tile_w, int tile_h, void* rec, uint2* trect,
+                              uint32_t* depth_key, uint32_t* rec_id, uint32_t* ntiles);
+void launch_surfel_fwd(hipStream_t st, int tw, int th, int n_tiles, int F,
+                       const FrameDesc* frames, const uint2* ranges, const uint32_t* vals,
+                       const void* rec, const float* bg, float* rgb, float* depth, float* alpha,
+                       float* normal, float* t_final, int32_t* n_last);
+
 // adam.hip
 void launch_adam(hipStream_t st, uint64_t n3, uint64_t nsh, float* means, const float* g_means,
                  float* m_means, float* v_means, float* sh, const float* g_sh, float* m_sh,

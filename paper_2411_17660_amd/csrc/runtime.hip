@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <map>
 #include <cstdio>
 #include <cstring>
@@ -38,6 +39,7 @@ struct Saved {
   bool k_known = false;
   bool sorted_in_b = false;   // tile sort result buffer
   bool recs_in_b = false;     // depth sort result buffer
+  bool surfel = false;        // the forward rendered 2D surfels
   bool has_backward = false;  // a backward of this forward has filled grad2d
 };
 
@@ -283,13 +285,26 @@ gsr_status gsr_destroy(gsr_context* ctx) {
 
 const char* gsr_last_error(const gsr_context* ctx) { return ctx ? ctx->err.c_str() : ""; }
 
-gsr_status gsr_forward(gsr_context* ctx, const gsr_settings* s, int64_t n, const float* means,
-                       const float* log_scales, const float* quats, const float* opac,
-                       const float* sh, int32_t F, const gsr_camera* cams, const float* poses,
-                       float* rgb, float* depth, float* alpha, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// The forward of either primitive: 3D Gaussians (normal == NULL) or 2D
+// surfels (log_scales [n,2], normal [sum 3HW]); they differ in the
+// preprocess and the compositing kernels only.
+gsr_status forward_impl(gsr_context* ctx, const gsr_settings* s, int64_t n, const float* means,
+                        const float* log_scales, const float* quats, const float* opac,
+                        const float* sh, int32_t F, const gsr_camera* cams, const float* poses,
+                        float* rgb, float* depth, float* alpha, float* normal, bool surfel,
+                        void* stream) {
   gsr_status rc = validate(ctx, s, n, means, log_scales, quats, opac, sh, F, cams, poses, rgb,
                            depth, alpha);
   if (rc) return rc;
+  if (surfel && (s->flags & (GSR_FLAG_MEDIAN_DEPTH | GSR_FLAG_COUNT_PAIRS)))
+    return fail(ctx, GSR_ERR_UNSUPPORTED, "surfels: median depth and pair counts not built");
+  if (surfel && !normal) return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "normal is NULL");
+  if (surfel && (((uintptr_t)normal) & 3u))
+    return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "pointer not 4-aligned");
   ctx->err.clear();
   ctx->s.valid = false;
   hipStream_t st = (hipStream_t)stream;
@@ -315,7 +330,8 @@ gsr_status gsr_forward(gsr_context* ctx, const gsr_settings* s, int64_t n, const
   if ((rc = upload_frames(ctx, fr, st))) return rc;
   const uint64_t M = (uint64_t)n * F;
   // workspace sized by M, T, P
-  if ((rc = ensure(ctx, ctx->rec, M * sizeof(Record), st))) return rc;
+  const size_t rec_bytes = surfel ? surfel_record_bytes() : sizeof(Record);
+  if ((rc = ensure(ctx, ctx->rec, M * rec_bytes, st))) return rc;
   if ((rc = ensure(ctx, ctx->trect, M * sizeof(uint2), st))) return rc;
   if ((rc = ensure(ctx, ctx->keyoff, M * 4, st))) return rc;
   if ((rc = ensure(ctx, ctx->dkey_a, M * 4, st))) return rc;
@@ -346,10 +362,16 @@ gsr_status gsr_forward(gsr_context* ctx, const gsr_settings* s, int64_t n, const
   // A1 preprocess
   {
     StageTimer t(ctx, st, timing, GSR_STAGE_PREPROCESS);
-    launch_preprocess_fwd(st, n, F, P<FrameDesc>(ctx->frames), poses, means, log_scales, quats,
-                          opac, sh, s->sh_degree, tw, th, P<Record>(ctx->rec),
-                          P<uint2>(ctx->trect), P<uint32_t>(ctx->dkey_a), P<uint32_t>(ctx->dval_a),
-                          P<uint32_t>(ctx->ntiles));
+    if (surfel)
+      launch_surfel_preprocess(st, n, F, P<FrameDesc>(ctx->frames), poses, means, log_scales,
+                               quats, opac, sh, s->sh_degree, tw, th, ctx->rec.p,
+                               P<uint2>(ctx->trect), P<uint32_t>(ctx->dkey_a),
+                               P<uint32_t>(ctx->dval_a), P<uint32_t>(ctx->ntiles));
+    else
+      launch_preprocess_fwd(st, n, F, P<FrameDesc>(ctx->frames), poses, means, log_scales,
+                            quats, opac, sh, s->sh_degree, tw, th, P<Record>(ctx->rec),
+                            P<uint2>(ctx->trect), P<uint32_t>(ctx->dkey_a),
+                            P<uint32_t>(ctx->dval_a), P<uint32_t>(ctx->ntiles));
   }
   // depth sort of the records (32-bit keys)
   const uint64_t kcap_guess = std::max<uint64_t>(ctx->key_cap, s->key_capacity);
@@ -439,14 +461,21 @@ gsr_status gsr_forward(gsr_context* ctx, const gsr_settings* s, int64_t n, const
   if (count) launch_fill_u32(st, (uint32_t*)d_pairs, 2, 0u);
   {
     StageTimer t(ctx, st, timing, GSR_STAGE_COMPOSITE_FWD);
-    launch_composite_fwd(st, tw, th, (int)T, F, P<FrameDesc>(ctx->frames),
-                         P<uint2>(ctx->ranges), svals, P<Record>(ctx->rec), s->background, rgb,
-                         depth, alpha, P<float>(ctx->t_final), P<int32_t>(ctx->n_last),
-                         P<uint32_t>(ctx->nproc), have_prev ? P<uint32_t>(ctx->nproc) : nullptr,
-                         P<uint32_t>(ctx->order_f), remap, count ? d_pairs : nullptr,
-                         median ? P<int32_t>(ctx->med_pos) : nullptr);
+    if (surfel)
+      launch_surfel_fwd(st, tw, th, (int)T, F, P<FrameDesc>(ctx->frames), P<uint2>(ctx->ranges),
+                        svals, ctx->rec.p, s->background, rgb, depth, alpha, normal,
+                        P<float>(ctx->t_final), P<int32_t>(ctx->n_last));
+    else
+      launch_composite_fwd(st, tw, th, (int)T, F, P<FrameDesc>(ctx->frames),
+                           P<uint2>(ctx->ranges), svals, P<Record>(ctx->rec), s->background,
+                           rgb, depth, alpha, P<float>(ctx->t_final), P<int32_t>(ctx->n_last),
+                           P<uint32_t>(ctx->nproc),
+                           have_prev ? P<uint32_t>(ctx->nproc) : nullptr,
+                           P<uint32_t>(ctx->order_f), remap, count ? d_pairs : nullptr,
+                           median ? P<int32_t>(ctx->med_pos) : nullptr);
   }
-  ctx->nproc_layout = layout;
+  // the surfel kernels leave nproc unset: no schedule from this forward
+  ctx->nproc_layout = surfel ? std::vector<int32_t>() : layout;
   ctx->n_pairs = count ? -2 : -1;  // -2: count pending on the device
   GSR_HIP(hipGetLastError());
   Saved& sv = ctx->s;
@@ -466,7 +495,29 @@ gsr_status gsr_forward(gsr_context* ctx, const gsr_settings* s, int64_t n, const
   sv.k_known = k_known;
   sv.sorted_in_b = keys_in_b;
   sv.recs_in_b = recs_in_b;
+  sv.surfel = surfel;
   return GSR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gsr_status gsr_forward(gsr_context* ctx, const gsr_settings* s, int64_t n, const float* means,
+                       const float* log_scales, const float* quats, const float* opac,
+                       const float* sh, int32_t F, const gsr_camera* cams, const float* poses,
+                       float* rgb, float* depth, float* alpha, void* stream) {
+  return forward_impl(ctx, s, n, means, log_scales, quats, opac, sh, F, cams, poses, rgb, depth,
+                      alpha, nullptr, false, stream);
+}
+
+gsr_status gsr_forward_surfel(gsr_context* ctx, const gsr_settings* s, int64_t n,
+                              const float* means, const float* log_scales, const float* quats,
+                              const float* opac, const float* sh, int32_t F,
+                              const gsr_camera* cams, const float* poses, float* rgb,
+                              float* depth, float* alpha, float* normal, void* stream) {
+  return forward_impl(ctx, s, n, means, log_scales, quats, opac, sh, F, cams, poses, rgb, depth,
+                      alpha, normal, true, stream);
 }
 
 gsr_status gsr_backward(gsr_context* ctx, const float* g_rgb, const float* g_depth,
@@ -476,6 +527,7 @@ gsr_status gsr_backward(gsr_context* ctx, const float* g_rgb, const float* g_dep
   if (!ctx) return GSR_ERR_INVALID_ARGUMENT;
   Saved& sv = ctx->s;
   if (!sv.valid) return fail(ctx, GSR_ERR_STATE, "backward without a preceding forward");
+  if (sv.surfel) return fail(ctx, GSR_ERR_STATE, "the last forward rendered surfels");
   if (!g_rgb || !g_depth || !g_alpha || !g_twist)
     return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "gradient pointer is NULL");
   if (sv.n > 0 && (!g_means || !g_log_scales || !g_quats || !g_opac || !g_sh))
@@ -900,11 +952,12 @@ gsr_status gsr_debug_lists(gsr_context* ctx, uint32_t* ntiles, uint32_t* depth_k
     for (size_t i = 0; i < M; ++i) depth_key[v[i]] = k[i];
   }
   if (square && M) {
-    std::vector<Record> r(M);
-    GSR_HIP(hipMemcpy(r.data(), ctx->rec.p, M * sizeof(Record), hipMemcpyDeviceToHost));
+    const size_t rb = sv.surfel ? surfel_record_bytes() : sizeof(Record);
+    const size_t off = sv.surfel ? surfel_square_offset() : offsetof(Record, sqx);
+    std::vector<uint8_t> r(M * rb);
+    GSR_HIP(hipMemcpy(r.data(), ctx->rec.p, M * rb, hipMemcpyDeviceToHost));
     for (size_t i = 0; i < M; ++i) {
-      square[2 * i] = r[i].sqx;
-      square[2 * i + 1] = r[i].sqy;
+      std::memcpy(&square[2 * i], &r[i * rb + off], 8);  // sqx, sqy
     }
   }
   const DBuf& kb = sv.sorted_in_b ? ctx->keys_b : ctx->keys_a;

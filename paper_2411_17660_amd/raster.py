@@ -81,6 +81,27 @@ class Rasterizer:
         self.sizes = [(int(c[0]), int(c[1])) for c in cams]
         return rgb, depth, alpha
 
+    def forward_surfel(self, means, log_scales, quats, opacity, sh, poses, cams, sh_degree,
+                       background=(0.0, 0.0, 0.0), tile=(16, 16), key_capacity=0, out=None):
+        """Renders F frames of 2D surfels (log_scales [n,2]); returns packed
+        (rgb, depth, alpha, normal [sum 3HW])."""
+        P = int(sum(int(c[0]) * int(c[1]) for c in cams))
+        dev = means.device
+        if out is None:
+            out = (torch.empty(3 * P, device=dev), torch.empty(P, device=dev),
+                   torch.empty(P, device=dev), torch.empty(3 * P, device=dev))
+        rgb, depth, alpha, normal = out
+        self.settings = native.make_settings(sh_degree, background, tile, key_capacity)
+        self.cams = native.make_cameras(cams)
+        n = int(means.shape[0])
+        self._check(self.lib.gsr_forward_surfel(
+            self.h, C.byref(self.settings), n, _ptr(means), _ptr(log_scales), _ptr(quats),
+            _ptr(opacity), _ptr(sh), len(cams), self.cams, _ptr(poses), _ptr(rgb), _ptr(depth),
+            _ptr(alpha), _ptr(normal), _stream()))
+        self.n, self.F, self.sh_degree = n, len(cams), sh_degree
+        self.sizes = [(int(c[0]), int(c[1])) for c in cams]
+        return rgb, depth, alpha, normal
+
     def backward(self, g_rgb, g_depth, g_alpha, out=None):
         n, F = self.n, self.F
         dev = g_rgb.device

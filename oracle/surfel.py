@@ -33,7 +33,18 @@ where the paper is silent (design notes, reading 18):
     box is empty;
   - outputs: RGB (+ T_final * background), depth sum_i w_i z_i, alpha
     1 - T_final and normal sum_i w_i n_i with n_i = R_f t_w turned to face
-    the camera (n . (R_f mu + t_f) < 0), in camera coordinates.
+    the camera (n . (R_f mu + t_f) < 0), in camera coordinates;
+  - the depth distortion of 2DGS (the L_dist term that the supplementary's
+    Rendering settings, 2D Gaussian Splatting paragraph, adds to the
+    objective for surfels), per pixel the sum over pairs i < j of
+    blended entries of w_i w_j (z_i - z_j)^2, with z the depth above
+    (squared distance in camera depth units).  Written here as the pair sum
+    expanded over the entries in front: entry j adds
+    w_j sum_{i<j} w_i (z_j - z_i)^2 = w_j (A z_j^2 - 2 z_j D_1 + D_2) with
+    A, D_1, D_2 the sums of w_i, w_i z_i, w_i z_i^2 over i < j;
+  - the normal consistency of 2DGS (its L_normal, the other term that
+    paragraph adds) is an image-space function of the depth, alpha and
+    normal maps: normal_consistency below.
 """
 import math
 
@@ -97,8 +108,9 @@ def render(means, log_scales, quats, opacity_logits, sh, sh_degree, cams, poses,
     """FP64 torch tensors in (means [n,3], log_scales [n,2], quats [n,4],
     opacity_logits [n], sh [n,K,3], poses [F,3,4]; twist [F,6] = (rho, phi)
     left perturbation, first order at 0).  Returns a list per frame of dicts
-    rgb [3,H,W], depth, alpha [H,W], normal [3,H,W], flags [H,W] (uint8,
-    numpy) and box (numpy int [n,4] x_lo, x_hi, y_lo, y_hi, -1 if culled)."""
+    rgb [3,H,W], depth, alpha, dist [H,W], normal [3,H,W], flags [H,W]
+    (uint8, numpy) and box (numpy int [n,4] x_lo, x_hi, y_lo, y_hi, -1 if
+    culled)."""
     out = []
     bg = torch.tensor([float(b) for b in background], dtype=torch.float64)
     Rg = _rot(quats)                                # [n,3,3]
@@ -165,6 +177,10 @@ def render(means, log_scales, quats, opacity_logits, sh, sh_degree, cams, poses,
         C = torch.zeros(3, H, W, dtype=torch.float64)
         D = torch.zeros(H, W, dtype=torch.float64)
         N = torch.zeros(3, H, W, dtype=torch.float64)
+        Dist = torch.zeros(H, W, dtype=torch.float64)
+        SA = torch.zeros(H, W, dtype=torch.float64)     # sum of w over entries in front
+        SZ = torch.zeros(H, W, dtype=torch.float64)     # ... of w z
+        SZZ = torch.zeros(H, W, dtype=torch.float64)    # ... of w z^2
         done = torch.zeros(H, W, dtype=torch.bool)
         flags = np.zeros((H, W), np.uint8)
         nb = torch.zeros(H, W, dtype=torch.float64)
@@ -213,14 +229,58 @@ def render(means, log_scales, quats, opacity_logits, sh, sh_degree, cams, poses,
             C = C + col[g][:, None, None] * w
             D = D + zint * w
             N = N + nrm[g][:, None, None] * w
+            Dist = Dist + w * (SA * zint * zint - 2.0 * zint * SZ + SZZ)
+            SA = SA + w
+            SZ = SZ + w * zint
+            SZZ = SZZ + w * zint * zint
             T = torch.where(blend, Tn, T)
             nb = nb + blend.to(torch.float64)
         rgb = C + T * bg[:, None, None]
-        out.append(dict(rgb=rgb, depth=D, alpha=1 - T, normal=N, flags=flags, box=box,
-                        order=order))
+        out.append(dict(rgb=rgb, depth=D, alpha=1 - T, normal=N, dist=Dist, flags=flags,
+                        box=box, order=order))
     return out
 
 
 def to64(a, grad=False):
     t = torch.from_numpy(np.ascontiguousarray(np.asarray(a, np.float64)))
     return t.requires_grad_(grad)
+
+
+def depth_normals(depth, cam):
+    """Normals of the surface the depth map describes (2DGS's normal from
+    depth): each pixel back-projects to P = D(x, y) K^-1 (x, y, 1); with the
+    central differences dP_x = P(x+1, y) - P(x-1, y) and dP_y = P(x, y+1) -
+    P(x, y-1), N = (dP_y x dP_x) / |dP_y x dP_x|, which faces the camera for
+    a surface in front of it.  Defined on interior pixels (1 <= x <= W-2,
+    1 <= y <= H-2) where the cross product is non-zero; 0 elsewhere.
+    Returns (N [3,H,W], valid [H,W] bool)."""
+    W, H, fx, fy, cx, cy = [float(v) for v in cam[:6]]
+    W, H = int(W), int(H)
+    ys, xs = torch.meshgrid(torch.arange(H, dtype=torch.float64),
+                            torch.arange(W, dtype=torch.float64), indexing="ij")
+    P = torch.stack([depth * (xs - cx) / fx, depth * (ys - cy) / fy, depth])   # [3,H,W]
+    dPx = torch.zeros_like(P)
+    dPy = torch.zeros_like(P)
+    dPx[:, 1:-1, 1:-1] = P[:, 1:-1, 2:] - P[:, 1:-1, :-2]
+    dPy[:, 1:-1, 1:-1] = P[:, 2:, 1:-1] - P[:, :-2, 1:-1]
+    v = torch.linalg.cross(dPy, dPx, dim=0)
+    nv = torch.linalg.norm(v, dim=0)
+    valid = torch.zeros(H, W, dtype=torch.bool)
+    valid[1:-1, 1:-1] = True
+    valid = valid & (nv.detach() > 0)
+    N = torch.where(valid, v / torch.where(valid, nv, torch.ones_like(nv)), torch.zeros_like(v))
+    return N, valid
+
+
+def normal_consistency(depth, alpha, normal, cam):
+    """The normal-consistency term of the surfel objective (2DGS's L_normal,
+    added for surfels in the supplementary's Rendering settings), per frame:
+    the mean over the interior pixels of sum_i w_i (1 - n_i . N), N the
+    normal from the depth map (depth_normals).  As sum_i w_i = alpha and
+    sum_i w_i n_i is the normal map, a pixel's term is alpha - normal . N.
+    Pixels where N is not defined add 0; the mean divides by the interior
+    pixel count (W-2)(H-2).  Returns (loss, per-pixel map [H,W])."""
+    N, valid = depth_normals(depth, cam)
+    term = torch.where(valid, alpha - (normal * N).sum(0), torch.zeros_like(alpha))
+    W, H = int(cam[0]), int(cam[1])
+    return term.sum() / float((W - 2) * (H - 2)), term

@@ -11,6 +11,11 @@ than itself (no GPU).
 - an edge-on surfel: the object-space Gaussian vanishes off its line and the
   screen-space low-pass exp(-|x - c|^2) sets alpha;
 - layered "over" of two surfels and their order; zero opacity; permutation;
+- depth distortion: each surfel rendered alone gives its alpha and depth per
+  pixel; blending them in centre-depth order by hand and summing
+  w_i w_j (z_i - z_j)^2 over all pairs i < j reproduces the map (and the
+  depth, alpha and normal maps), a surfel alone has none, and two surfels at
+  one depth have none;
 - autograd against central differences (torch.autograd.gradcheck).
 Sources: DROID-Splat Sec. 3.3 (2D surfels compared in tab:renderer) and the
 2DGS method it cites.
@@ -183,17 +188,123 @@ def test_zero_opacity_and_permutation():
     assert sum(int((fr["alpha"].numpy() > 0).sum()) for fr in base) > 200
 
 
+def test_distortion_is_the_pair_sum_of_separately_rendered_surfels():
+    from paper_2411_17660_amd import scenes
+    sc = scenes.tiny_scene(seed=21, n=7, W=32, H=24, f=22.0, n_frames=1, sh_degree=0,
+                           ls_mean=-1.6, ls_sigma=0.2, opacity_sigma=0.3)
+    ls = sc.log_scales[:, :2]
+    lo = np.clip(sc.opacity, -1.0, 0.5)          # alpha <= 0.63: T stays above 1e-4
+    full = _render(sc.means, ls, sc.quats, lo, sc.sh, 0, sc.cams, sc.poses)[0]
+    H, W = 24, 32
+    a_i, z_i, n_i = [], [], []
+    for g in range(sc.n):
+        o = np.full(sc.n, -40.0)
+        o[g] = lo[g]
+        one = _render(sc.means, ls, sc.quats, o, sc.sh, 0, sc.cams, sc.poses)[0]
+        a = one["alpha"].numpy()
+        assert np.all(one["dist"].numpy() == 0)
+        a_i.append(a)
+        z_i.append(np.where(a > 0, one["depth"].numpy() / np.where(a > 0, a, 1), 0))
+        n_i.append(np.where(a > 0, one["normal"].numpy() / np.where(a > 0, a, 1), 0))
+    mc = sc.means @ sc.poses[0, :, :3].T + sc.poses[0, :, 3]
+    order = np.argsort(mc[:, 2].astype(np.float32), kind="stable")
+    T = np.ones((H, W))
+    w = []
+    for g in order:
+        w.append(a_i[g] * T)
+        T = T * (1 - a_i[g])
+    zs = [z_i[g] for g in order]
+    dist = np.zeros((H, W))
+    for j in range(len(w)):
+        for i in range(j):
+            dist += w[i] * w[j] * (zs[i] - zs[j]) ** 2
+    assert dist.max() > 1e-3
+    assert np.abs(full["dist"].numpy() - dist).max() < 1e-12
+    assert np.abs(full["depth"].numpy() - sum(wi * zi for wi, zi in zip(w, zs))).max() < 1e-12
+    assert np.abs(full["alpha"].numpy() - (1 - T)).max() < 1e-12
+    nsum = sum(wi * n_i[g] for wi, g in zip(w, order))
+    assert np.abs(full["normal"].numpy() - nsum).max() < 1e-12
+
+
+def test_distortion_vanishes_for_coplanar_fronto_parallel_surfels():
+    cams = [(40, 30, 30.0, 30.0, 20.0, 15.0, 0.2)]
+    out = _render(np.array([[0.0, 0, 2.0], [0.01, 0.02, 2.0]]), np.log(np.full((2, 2), 0.1)),
+                  np.tile([[1.0, 0, 0, 0]], (2, 1)), np.array([0.2, -0.1]),
+                  np.zeros((2, 1, 3)), 0, cams, _ident())[0]
+    d = out["dist"].numpy()
+    assert np.abs(d).max() < 1e-13 and out["alpha"].numpy().max() > 0.5
+
+
 def test_autograd_matches_central_differences():
     sc = _tiny(5, n=6, F=1)
     rng = np.random.default_rng(5)
-    G = [S.to64(rng.normal(size=s)) for s in ((3, 24, 32), (24, 32), (24, 32), (3, 24, 32))]
+    G = [S.to64(rng.normal(size=s)) for s in ((3, 24, 32), (24, 32), (24, 32), (3, 24, 32),
+                                             (24, 32))]
     poses = S.to64(sc.poses)
 
     def loss(means, ls, quats, opac, sh, twist):
         fr = S.render(means, ls, quats, opac, sh, 1, sc.cams, poses, sc.background, twist)[0]
         return ((fr["rgb"] * G[0]).sum() + (fr["depth"] * G[1]).sum()
-                + (fr["alpha"] * G[2]).sum() + (fr["normal"] * G[3]).sum())
+                + (fr["alpha"] * G[2]).sum() + (fr["normal"] * G[3]).sum()
+                + (fr["dist"] * G[4]).sum())
     args = (S.to64(sc.means, True), S.to64(sc.log_scales[:, :2], True),
             S.to64(sc.quats, True), S.to64(sc.opacity, True), S.to64(sc.sh, True),
             S.to64(np.zeros((1, 6)), True))
     assert torch.autograd.gradcheck(loss, args, eps=1e-7, atol=1e-6, rtol=1e-5)
+
+
+def _plane_depth(n, d, cam):
+    """Depth map of the plane n . P = d seen through cam: the ray
+    K^-1 (x, y, 1) meets it at D = d / (n . K^-1 (x, y, 1))."""
+    W, H, fx, fy, cx, cy = cam[:6]
+    ys, xs = np.mgrid[0:H, 0:W].astype(np.float64)
+    r = np.stack([(xs - cx) / fx, (ys - cy) / fy, np.ones_like(xs)])
+    return d / np.einsum("i,ihw->hw", n, r)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_depth_normals_of_a_plane_are_its_normal(seed):
+    rng = np.random.default_rng(seed)
+    cam = (36, 28, 30.0, 32.0, 17.3, 13.9, 0.1)
+    n = np.array([rng.uniform(-0.4, 0.4), rng.uniform(-0.4, 0.4), -1.0])
+    n /= np.linalg.norm(n)                  # faces the camera (n_z < 0)
+    d = -2.0 * abs(n[2])                     # through (0, 0, 2)
+    D = _plane_depth(n, d, cam)
+    assert D.min() > 0
+    N, valid = S.depth_normals(torch.from_numpy(D), cam)
+    N = N.numpy()
+    assert valid.numpy()[1:-1, 1:-1].all() and not valid.numpy()[0].any()
+    err = np.abs(N[:, 1:-1, 1:-1] - n[:, None, None]).max()
+    assert err < 1e-12, err
+    assert np.all(N[:, 0] == 0) and np.all(N[:, :, -1] == 0)
+
+
+def test_normal_consistency_closed_forms():
+    cam = (20, 16, 18.0, 18.0, 9.5, 7.5, 0.1)
+    D = np.full((16, 20), 3.0)
+    Dt = torch.from_numpy(D)
+    rng = np.random.default_rng(3)
+    alpha = torch.from_numpy(rng.uniform(0.2, 1.0, (16, 20)))
+    # normal map alpha * N with N = (0, 0, -1): every interior term vanishes
+    nm = torch.zeros(3, 16, 20, dtype=torch.float64)
+    nm[2] = -alpha
+    loss, term = S.normal_consistency(Dt, alpha, nm, cam)
+    assert abs(float(loss)) < 1e-15
+    # a normal map rotated by 90 degrees: each term is alpha, the mean over
+    # the (W-2)(H-2) interior pixels
+    nm2 = torch.zeros(3, 16, 20, dtype=torch.float64)
+    nm2[0] = alpha
+    loss2, term2 = S.normal_consistency(Dt, alpha, nm2, cam)
+    want = alpha.numpy()[1:-1, 1:-1].sum() / (18 * 14)
+    assert abs(float(loss2) - want) < 1e-14
+    assert np.all(term2.numpy()[0] == 0)
+
+
+def test_normal_consistency_autograd_matches_central_differences():
+    cam = (9, 7, 8.0, 9.0, 4.2, 3.1, 0.1)
+    rng = np.random.default_rng(4)
+    D = S.to64(2.0 + 0.2 * rng.normal(size=(7, 9)), True)
+    a = S.to64(rng.uniform(0.1, 1.0, (7, 9)), True)
+    nm = S.to64(rng.normal(size=(3, 7, 9)), True)
+    f = lambda D, a, nm: S.normal_consistency(D, a, nm, cam)[0]       # noqa: E731
+    assert torch.autograd.gradcheck(f, (D, a, nm), eps=1e-7, atol=1e-7, rtol=1e-6)

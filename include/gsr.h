@@ -144,19 +144,40 @@ gsr_status gsr_forward(gsr_context* ctx, const gsr_settings* settings, int64_t n
  * projected centre c, alpha = min(0.99, sigma max(G, G_lp)); compositing,
  * thresholds and order as gsr_forward (by the centre's depth).  Outputs rgb,
  * depth (sum_i w_i z_i with z_i = M2 . (u, v, 1), the centre's depth where
- * G_lp is the larger), alpha, and normal [sum_f 3 H_f W_f] (CHW per frame,
+ * G_lp is the larger), alpha, normal [sum_f 3 H_f W_f] (CHW per frame,
  * sum_i w_i n_i, n_i the disk normal in the camera frame turned to face the
- * camera).  A surfel covers the pixel box of the projected corners of |u|,
- * |v| <= sqrt(2 ln(255 sigma)) united with the square of half width
- * sqrt(ln(255 sigma)) around c, and is culled when sigma <= 1/255 or the
- * centre or a corner is not beyond the near plane.  GSR_FLAG_MEDIAN_DEPTH
- * and GSR_FLAG_COUNT_PAIRS are not supported (GSR_ERR_UNSUPPORTED).
- * gsr_backward after this forward returns GSR_ERR_STATE. */
+ * camera) and dist [sum_f H_f W_f], the depth distortion of the surfel
+ * objective (the L_dist term the supplementary's Rendering settings add for
+ * 2D Gaussian Splatting): per pixel the sum over pairs i < j of blended
+ * entries of w_i w_j (z_i - z_j)^2.  A surfel covers the pixel box of the
+ * projected corners of |u|, |v| <= sqrt(2 ln(255 sigma)) united with the
+ * square of half width sqrt(ln(255 sigma)) around c, and is culled when
+ * sigma <= 1/255 or the centre or a corner is not beyond the near plane.
+ * GSR_FLAG_MEDIAN_DEPTH and GSR_FLAG_COUNT_PAIRS are not supported
+ * (GSR_ERR_UNSUPPORTED).  All output pointers are device memory, 4-byte
+ * aligned; GSR_ERR_INVALID_ARGUMENT if normal or dist is NULL.  gsr_backward
+ * after this forward returns GSR_ERR_STATE; use gsr_backward_surfel. */
 gsr_status gsr_forward_surfel(gsr_context* ctx, const gsr_settings* settings, int64_t n,
                               const float* means, const float* log_scales, const float* quats,
                               const float* opacity_logits, const float* sh, int32_t n_frames,
                               const gsr_camera* cams, const float* poses, float* rgb,
-                              float* depth, float* alpha, float* normal, void* stream);
+                              float* depth, float* alpha, float* normal, float* dist,
+                              void* stream);
+
+/* Backward of the last gsr_forward_surfel on ctx (same method as
+ * gsr_backward, for the surfel primitive of Sec. 3.3 / tab:renderer) for
+ * upstream gradients of its five outputs, packed like them: g_rgb, g_depth,
+ * g_alpha, g_normal [sum 3HW], g_dist [sum HW] (device, non-NULL; pass
+ * zeros for an unused output).  Writes g_means [n,3], g_log_scales [n,2],
+ * g_quats [n,4], g_opacity_logits [n], g_sh [n,(d+1)^2,3] (summed over
+ * frames) and g_twist [F,6] (the left-perturbation pose twist (rho, phi) of
+ * each frame).  The forward's inputs must be unchanged.  GSR_ERR_STATE if
+ * the last forward was not a surfel forward. */
+gsr_status gsr_backward_surfel(gsr_context* ctx, const float* g_rgb, const float* g_depth,
+                               const float* g_alpha, const float* g_normal,
+                               const float* g_dist, float* g_means, float* g_log_scales,
+                               float* g_quats, float* g_opacity_logits, float* g_sh,
+                               float* g_twist, void* stream);
 
 /* Backward of the last forward on ctx for upstream gradients g_rgb, g_depth,
  * g_alpha (packed like the outputs).  Writes g_means [n,3], g_log_scales

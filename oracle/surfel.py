@@ -58,6 +58,14 @@ BAND = 1e-4
 EPS32 = 2.0 ** -24
 
 FLAG_ALPHA, FLAG_T, FLAG_CLAMP, FLAG_LOWPASS = 1, 2, 4, 16
+# The ray-disk intersection loses accuracy with its conditioning
+# kappa = |h_u| |h_v| / |h_u x h_v| (1 / sin of the angle between the two
+# planes through the ray): a value computed from rounded h_u, h_v has error
+# ~ kappa ulps, its derivative ~ kappa^2.  FLAG_COND marks the pixels where
+# the disk term is blended with kappa above KAPPA_GRAD; they carry no
+# decision, so image comparisons keep them and gradient comparisons do not.
+FLAG_COND = 32
+KAPPA_GRAD = 32.0
 
 
 def _rot(q):
@@ -220,6 +228,7 @@ def render(means, log_scales, quats, opacity_logits, sh, sh_degree, cams, poses,
                 flags[live & (np.abs(araw.detach().numpy() - A_MAX) < BAND * A_MAX)] |= FLAG_CLAMP
                 Gn, Gl = G.detach().numpy(), Glp.detach().numpy()
                 flags[live & (np.abs(Gn - Gl) < 1e-3 * np.maximum(Gn, Gl))] |= FLAG_LOWPASS
+                flags[live & use_obj.numpy() & (kappa.numpy() > KAPPA_GRAD)] |= FLAG_COND
             blend = inside & (a >= A_MIN)
             Tn = T * (1 - a)
             stop = blend & (Tn < T_MIN)

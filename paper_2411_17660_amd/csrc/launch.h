@@ -98,11 +98,20 @@ void launch_mcmc_relocate(hipStream_t st, int64_t n, int ksh3, float* means, flo
                           float* quats, float* opac, float* sh, const int32_t* src,
                           uint32_t* cnt, double* rule);
 
+// Sum of the per-wave twist partials [F][n_waves][6] into g_twist [F][6].
+void launch_twist_reduce(hipStream_t st, int F, const double* twist_partial, int64_t n_waves,
+                         float* g_twist);
+
 // surfel.hip: the 2D surfel variant's preprocess (records of
-// surfel_record_bytes() bytes in `rec`) and forward compositing (rgb, depth,
-// alpha, normal [sum 3HW]); keys, sorts and ranges are shared.
+// surfel_record_bytes() bytes in `rec`), forward compositing (rgb, depth,
+// alpha, normal [sum 3HW], distortion; dist_aux [P][3] keeps the per-pixel
+// sums the backward needs) and backward (per-key partials of
+// surfel_grad_values() floats, then the chain rule and twist); keys, sorts
+// and ranges are shared.
 size_t surfel_record_bytes();
 size_t surfel_square_offset();  // byte offset of the box bounds sqx, sqy
+int surfel_grad_values();
+int64_t surfel_preprocess_bwd_waves(int64_t n);
 void launch_surfel_preprocess(hipStream_t st, int64_t n, int F, const FrameDesc* frames,
                               const float* poses, const float* means, const float* log_scales,
                               const float* quats, const float* opac, const float* sh, int deg,
@@ -111,7 +120,24 @@ void launch_surfel_preprocess(hipStream_t st, int64_t n, int F, const FrameDesc*
 void launch_surfel_fwd(hipStream_t st, int tw, int th, int n_tiles, int F,
                        const FrameDesc* frames, const uint2* ranges, const uint32_t* vals,
                        const void* rec, const float* bg, float* rgb, float* depth, float* alpha,
-                       float* normal, float* t_final, int32_t* n_last);
+                       float* normal, float* dist, float* t_final, int32_t* n_last,
+                       float* dist_aux);
+void launch_surfel_bwd(hipStream_t st, int tw, int th, int n_tiles, int F,
+                       const FrameDesc* frames, const uint2* ranges, const uint32_t* vals,
+                       const void* rec, const uint2* trect, const uint32_t* keyoff,
+                       const float* bg, const float* g_rgb, const float* g_depth,
+                       const float* g_alpha, const float* g_normal, const float* g_dist,
+                       const float* t_final, const int32_t* n_last, const float* dist_aux,
+                       float* partial, uint32_t* stamp, const uint32_t* epoch);
+void launch_surfel_preprocess_bwd(hipStream_t st, int64_t n, int F, const FrameDesc* frames,
+                                  const float* poses, const float* means,
+                                  const float* log_scales, const float* quats,
+                                  const float* opac, const float* sh, int deg,
+                                  const uint32_t* ntiles, const uint32_t* keyoff,
+                                  const float* partial, const uint32_t* stamp,
+                                  const uint32_t* epoch, uint64_t key_capacity, float* g_means,
+                                  float* g_log_scales, float* g_quats, float* g_opac,
+                                  float* g_sh, double* twist_partial, float* g_twist);
 
 // adam.hip
 void launch_adam(hipStream_t st, uint64_t n3, uint64_t nsh, float* means, const float* g_means,

@@ -473,18 +473,7 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(
       ds[j] += GM[i * 3 + j] * G.R[i * 3 + j];
     }
   for (int a = 0; a < 3; ++a) g_log_scales[g * 3 + a] = (float)(ds[a] * G.s[a]);
-  // dR -> unit quaternion (w, x, y, z)
-  const double w = G.qh[0], x = G.qh[1], y = G.qh[2], z = G.qh[3];
-  double dq[4];
-  dq[0] = 2.0 * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
-  dq[1] = 2.0 * (y * dR[1] + z * dR[2] + y * dR[3] - 2.0 * x * dR[4] - w * dR[5] + z * dR[6] +
-                 w * dR[7] - 2.0 * x * dR[8]);
-  dq[2] = 2.0 * (-2.0 * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] +
-                 z * dR[7] - 2.0 * y * dR[8]);
-  dq[3] = 2.0 * (-2.0 * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.0 * z * dR[4] +
-                 y * dR[5] + x * dR[6] + y * dR[7]);
-  const double pr = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
-  for (int a = 0; a < 4; ++a) g_quats[g * 4 + a] = (float)((dq[a] - G.qh[a] * pr) / G.qn);
+  quat_grad(G.qh, G.qn, dR, g_quats + g * 4);
   for (int a = 0; a < 3; ++a) g_means[g * 3 + a] = (float)dmu[a];
   g_opac[g] = (float)(dsig * G.opacity * (1.0 - G.opacity));
   float* gs = g_sh + g * nb * 3;
@@ -579,8 +568,14 @@ void launch_preprocess_bwd(hipStream_t st, int64_t n, int F, const FrameDesc* fr
     }
   }
 #undef GSR_PRE_BWD
-  hipLaunchKernelGGL(twist_reduce_kernel, dim3(F), dim3(256), 0, st, twist_partial,
-                     n > 0 ? preprocess_bwd_waves(n) : 0, g_twist);
+  launch_twist_reduce(st, F, twist_partial, n > 0 ? preprocess_bwd_waves(n) : 0, g_twist);
+}
+
+void launch_twist_reduce(hipStream_t st, int F, const double* twist_partial, int64_t n_waves,
+                         float* g_twist) {
+  if (F <= 0) return;
+  hipLaunchKernelGGL(twist_reduce_kernel, dim3(F), dim3(256), 0, st, twist_partial, n_waves,
+                     g_twist);
 }
 
 }  // namespace gsr

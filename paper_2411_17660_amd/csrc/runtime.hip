@@ -54,6 +54,7 @@ struct gsr_context {
   DBuf ranges, nproc, t_final, n_last, frames, twist_part, loss_part, loss_scale;
   DBuf ssim_part, ssim_tiles, ssim_scale;  // rendering loss with SSIM
   DBuf med_pos;                     // per pixel: list position of the median-depth entry
+  DBuf dist_aux, spart;             // surfels: distortion sums per pixel, per-key partials
   DBuf reloc_cnt, reloc_rule;       // MCMC relocation scratch
   DBuf up_rgb, up_depth, up_alpha;  // upstream gradients for gsr_step_l1
   DBuf tune_out;                    // scratch outputs of the autotuner
@@ -268,7 +269,7 @@ gsr_status gsr_destroy(gsr_context* ctx) {
                   &ctx->reloc_cnt, &ctx->reloc_rule,
                   &ctx->up_rgb, &ctx->up_depth, &ctx->up_alpha, &ctx->tune_out,
                   &ctx->order_f, &ctx->order_b, &ctx->cls_a, &ctx->cls_b, &ctx->clsv_a,
-                  &ctx->clsv_b};
+                  &ctx->clsv_b, &ctx->dist_aux, &ctx->spart};
   for (DBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (ctx->h_frames) (void)hipHostFree(ctx->h_frames);
@@ -290,20 +291,21 @@ const char* gsr_last_error(const gsr_context* ctx) { return ctx ? ctx->err.c_str
 namespace {
 
 // The forward of either primitive: 3D Gaussians (normal == NULL) or 2D
-// surfels (log_scales [n,2], normal [sum 3HW]); they differ in the
-// preprocess and the compositing kernels only.
+// surfels (log_scales [n,2], normal [sum 3HW], dist [sum HW]); they differ
+// in the preprocess and the compositing kernels only.
 gsr_status forward_impl(gsr_context* ctx, const gsr_settings* s, int64_t n, const float* means,
                         const float* log_scales, const float* quats, const float* opac,
                         const float* sh, int32_t F, const gsr_camera* cams, const float* poses,
-                        float* rgb, float* depth, float* alpha, float* normal, bool surfel,
-                        void* stream) {
+                        float* rgb, float* depth, float* alpha, float* normal, float* dist,
+                        bool surfel, void* stream) {
   gsr_status rc = validate(ctx, s, n, means, log_scales, quats, opac, sh, F, cams, poses, rgb,
                            depth, alpha);
   if (rc) return rc;
   if (surfel && (s->flags & (GSR_FLAG_MEDIAN_DEPTH | GSR_FLAG_COUNT_PAIRS)))
     return fail(ctx, GSR_ERR_UNSUPPORTED, "surfels: median depth and pair counts not built");
-  if (surfel && !normal) return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "normal is NULL");
-  if (surfel && (((uintptr_t)normal) & 3u))
+  if (surfel && (!normal || !dist))
+    return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "normal or dist is NULL");
+  if (surfel && ((((uintptr_t)normal) | ((uintptr_t)dist)) & 3u))
     return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "pointer not 4-aligned");
   ctx->err.clear();
   ctx->s.valid = false;
@@ -356,6 +358,7 @@ gsr_status forward_impl(gsr_context* ctx, const gsr_settings* s, int64_t n, cons
   if ((rc = ensure(ctx, ctx->n_last, (size_t)Px * 4, st))) return rc;
   const bool median = (s->flags & GSR_FLAG_MEDIAN_DEPTH) != 0;
   if (median && (rc = ensure(ctx, ctx->med_pos, (size_t)Px * 4, st))) return rc;
+  if (surfel && (rc = ensure(ctx, ctx->dist_aux, (size_t)Px * 12, st))) return rc;
   uint64_t* d_count = P<uint64_t>(ctx->counters);               // [0] = K
   uint32_t* d_overflow = (uint32_t*)(P<uint64_t>(ctx->counters) + 1);
   const bool timing = (s->flags & GSR_FLAG_TIMING) != 0;
@@ -463,8 +466,8 @@ gsr_status forward_impl(gsr_context* ctx, const gsr_settings* s, int64_t n, cons
     StageTimer t(ctx, st, timing, GSR_STAGE_COMPOSITE_FWD);
     if (surfel)
       launch_surfel_fwd(st, tw, th, (int)T, F, P<FrameDesc>(ctx->frames), P<uint2>(ctx->ranges),
-                        svals, ctx->rec.p, s->background, rgb, depth, alpha, normal,
-                        P<float>(ctx->t_final), P<int32_t>(ctx->n_last));
+                        svals, ctx->rec.p, s->background, rgb, depth, alpha, normal, dist,
+                        P<float>(ctx->t_final), P<int32_t>(ctx->n_last), P<float>(ctx->dist_aux));
     else
       launch_composite_fwd(st, tw, th, (int)T, F, P<FrameDesc>(ctx->frames),
                            P<uint2>(ctx->ranges), svals, P<Record>(ctx->rec), s->background,
@@ -508,16 +511,71 @@ gsr_status gsr_forward(gsr_context* ctx, const gsr_settings* s, int64_t n, const
                        const float* sh, int32_t F, const gsr_camera* cams, const float* poses,
                        float* rgb, float* depth, float* alpha, void* stream) {
   return forward_impl(ctx, s, n, means, log_scales, quats, opac, sh, F, cams, poses, rgb, depth,
-                      alpha, nullptr, false, stream);
+                      alpha, nullptr, nullptr, false, stream);
 }
 
 gsr_status gsr_forward_surfel(gsr_context* ctx, const gsr_settings* s, int64_t n,
                               const float* means, const float* log_scales, const float* quats,
                               const float* opac, const float* sh, int32_t F,
                               const gsr_camera* cams, const float* poses, float* rgb,
-                              float* depth, float* alpha, float* normal, void* stream) {
+                              float* depth, float* alpha, float* normal, float* dist,
+                              void* stream) {
   return forward_impl(ctx, s, n, means, log_scales, quats, opac, sh, F, cams, poses, rgb, depth,
-                      alpha, normal, true, stream);
+                      alpha, normal, dist, true, stream);
+}
+
+gsr_status gsr_backward_surfel(gsr_context* ctx, const float* g_rgb, const float* g_depth,
+                               const float* g_alpha, const float* g_normal,
+                               const float* g_dist, float* g_means, float* g_log_scales,
+                               float* g_quats, float* g_opac, float* g_sh, float* g_twist,
+                               void* stream) {
+  if (!ctx) return GSR_ERR_INVALID_ARGUMENT;
+  Saved& sv = ctx->s;
+  if (!sv.valid) return fail(ctx, GSR_ERR_STATE, "backward without a preceding forward");
+  if (!sv.surfel) return fail(ctx, GSR_ERR_STATE, "the last forward rendered 3D Gaussians");
+  if (!g_rgb || !g_depth || !g_alpha || !g_normal || !g_dist || !g_twist)
+    return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "gradient pointer is NULL");
+  if (sv.n > 0 && (!g_means || !g_log_scales || !g_quats || !g_opac || !g_sh))
+    return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "gradient pointer is NULL");
+  const void* ptrs[] = {g_rgb, g_depth, g_alpha, g_normal, g_dist, g_means, g_log_scales,
+                        g_quats, g_opac, g_sh, g_twist};
+  for (const void* p : ptrs)
+    if (((uintptr_t)p) & 3u) return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "pointer not 4-aligned");
+  ctx->err.clear();
+  hipStream_t st = (hipStream_t)stream;
+  GSR_HIP(hipSetDevice(ctx->device));
+  const gsr_settings& s = sv.set;
+  gsr_status rc;
+  const size_t ng = (size_t)surfel_grad_values();
+  if ((rc = ensure(ctx, ctx->spart, std::max<uint64_t>(ctx->key_cap, 1) * ng * 4, st))) return rc;
+  const int64_t waves = sv.n > 0 ? surfel_preprocess_bwd_waves(sv.n) : 0;
+  if ((rc = ensure(ctx, ctx->twist_part, (size_t)std::max<int64_t>(waves, 1) * sv.F * 6 * 8, st)))
+    return rc;
+  ++ctx->epoch;
+  uint32_t* d_epoch = (uint32_t*)(P<uint64_t>(ctx->counters) + 3);
+  launch_bump_epoch(st, d_epoch);
+  const uint32_t* svals = P<uint32_t>(sv.sorted_in_b ? ctx->vals_b : ctx->vals_a);
+  const bool timing = (s.flags & GSR_FLAG_TIMING) != 0;
+  {
+    StageTimer t(ctx, st, timing, GSR_STAGE_COMPOSITE_BWD);
+    launch_surfel_bwd(st, s.tile_w, s.tile_h, (int)sv.T, sv.F, P<FrameDesc>(ctx->frames),
+                      P<uint2>(ctx->ranges), svals, ctx->rec.p, P<uint2>(ctx->trect),
+                      P<uint32_t>(ctx->keyoff), s.background, g_rgb, g_depth, g_alpha, g_normal,
+                      g_dist, P<float>(ctx->t_final), P<int32_t>(ctx->n_last),
+                      P<float>(ctx->dist_aux), P<float>(ctx->spart), P<uint32_t>(ctx->stamp),
+                      d_epoch);
+  }
+  {
+    StageTimer t(ctx, st, timing, GSR_STAGE_PREPROCESS_BWD);
+    launch_surfel_preprocess_bwd(st, sv.n, sv.F, P<FrameDesc>(ctx->frames), sv.poses, sv.means,
+                                 sv.log_scales, sv.quats, sv.opac, sv.sh, s.sh_degree,
+                                 P<uint32_t>(ctx->ntiles), P<uint32_t>(ctx->keyoff),
+                                 P<float>(ctx->spart), P<uint32_t>(ctx->stamp), d_epoch,
+                                 ctx->key_cap, g_means, g_log_scales, g_quats, g_opac, g_sh,
+                                 P<double>(ctx->twist_part), g_twist);
+  }
+  GSR_HIP(hipGetLastError());
+  return GSR_OK;
 }
 
 gsr_status gsr_backward(gsr_context* ctx, const float* g_rgb, const float* g_depth,

@@ -1,6 +1,7 @@
 // sh_device.h -- device helpers shared by the 3D Gaussian and 2D surfel
-// paths of libgsr.so: pose loading, the real spherical-harmonics colour basis
-// and its direction gradient, and the view direction from the camera centre.
+// paths of libgsr.so: pose loading, the quaternion gradient, the real
+// spherical-harmonics colour basis and its direction gradient, and the view
+// direction from the camera centre.
 #pragma once
 #include "gsr_device.h"
 
@@ -12,6 +13,25 @@ __device__ __forceinline__ void load_pose(const float* __restrict__ poses, int f
   W[0] = P[0]; W[1] = P[1]; W[2] = P[2]; tf[0] = P[3];
   W[3] = P[4]; W[4] = P[5]; W[5] = P[6]; tf[1] = P[7];
   W[6] = P[8]; W[7] = P[9]; W[8] = P[10]; tf[2] = P[11];
+}
+
+// Gradient of a rotation R(q / |q|) (row-major R[i*3+j]) carried back to the
+// raw quaternion q = qn qh, qh = (w, x, y, z) of unit length: dL/dqh from the
+// entries of R, then projected on the tangent of the unit sphere and divided
+// by |q|.  Writes the four FP32 components to out.
+__device__ __forceinline__ void quat_grad(const double qh[4], double qn, const double dR[9],
+                                          float* __restrict__ out) {
+  const double w = qh[0], x = qh[1], y = qh[2], z = qh[3];
+  double dq[4];
+  dq[0] = 2.0 * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+  dq[1] = 2.0 * (y * dR[1] + z * dR[2] + y * dR[3] - 2.0 * x * dR[4] - w * dR[5] + z * dR[6] +
+                 w * dR[7] - 2.0 * x * dR[8]);
+  dq[2] = 2.0 * (-2.0 * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] +
+                 z * dR[7] - 2.0 * y * dR[8]);
+  dq[3] = 2.0 * (-2.0 * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.0 * z * dR[4] +
+                 y * dR[5] + x * dR[6] + y * dR[7]);
+  const double pr = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
+  for (int a = 0; a < 4; ++a) out[a] = (float)((dq[a] - qh[a] * pr) / qn);
 }
 
 // Real spherical harmonics up to degree 3 in the order (l, m = -l..l) with

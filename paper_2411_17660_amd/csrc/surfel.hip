@@ -19,7 +19,12 @@
 //   G = exp(-(u^2 + v^2)/2), G_lp = exp(-|(x, y) - c|^2), G' = max(G, G_lp),
 //   alpha = min(0.99, sigma G'), depth = M2 . (u, v, 1) (c's depth where
 //   G_lp wins), normal = t_w in the camera frame, turned to face the camera;
-// compositing thresholds and order as in the 3D path.  A surfel covers the
+// compositing thresholds and order as in the 3D path.  The depth distortion
+// of a pixel is the sum over pairs i < j of blended entries of
+// w_i w_j (z_i - z_j)^2; the forward adds w_j (A z_j^2 - 2 z_j D_1 + D_2) per
+// entry, A, D_1, D_2 the sums of w, w z, w z^2 in front of it, with every z
+// taken relative to the pixel's first blended entry so that the FP32 sums
+// stay near the spread of the depths rather than their size.  A surfel covers the
 // pixel box of the projected corners of |u|, |v| <= sqrt(2 ln(255 sigma))
 // united with the square of half width sqrt(ln(255 sigma)) around c; the
 // box's integer bounds are taken in FP64.
@@ -204,7 +209,8 @@ __global__ void __launch_bounds__(64) surfel_fwd_kernel(
     int n_frames, const FrameDesc* __restrict__ frames, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ vals, const Surfel* __restrict__ rec, float bg0, float bg1,
     float bg2, float* __restrict__ rgb, float* __restrict__ depth, float* __restrict__ alpha,
-    float* __restrict__ normal, float* __restrict__ t_final, int32_t* __restrict__ n_last) {
+    float* __restrict__ normal, float* __restrict__ dist, float* __restrict__ t_final,
+    int32_t* __restrict__ n_last, float* __restrict__ dist_aux /* [P][3]: z_ref, D_1, D_2 */) {
   constexpr int PIX = TW * TH / kWave;
   constexpr int RPP = kWave / TW;
   __shared__ Surfel sm[kWave];
@@ -218,12 +224,14 @@ __global__ void __launch_bounds__(64) surfel_fwd_kernel(
   const int ly = lane / TW;
   const uint2 rg = ranges[tile];
   float T[PIX], C0[PIX], C1[PIX], C2[PIX], D[PIX], N0[PIX], N1[PIX], N2[PIX];
+  float ZR[PIX], S1[PIX], S2[PIX], DS[PIX];
   int last[PIX];
   bool done[PIX];
 #pragma unroll
   for (int k = 0; k < PIX; ++k) {
     T[k] = 1.0f;
     C0[k] = C1[k] = C2[k] = D[k] = N0[k] = N1[k] = N2[k] = 0.0f;
+    ZR[k] = S1[k] = S2[k] = DS[k] = 0.0f;
     last[k] = 0;
     const int py = y0 + k * RPP + ly;
     done[k] = !(px < fr.width && py < fr.height);
@@ -264,6 +272,11 @@ __global__ void __launch_bounds__(64) surfel_fwd_kernel(
         N0[k] += S.n0 * w;
         N1[k] += S.n1 * w;
         N2[k] += S.n2 * w;
+        if (last[k] == 0) ZR[k] = h.z;
+        const float zp = h.z - ZR[k];
+        DS[k] += w * ((1.0f - T[k]) * zp * zp - 2.0f * zp * S1[k] + S2[k]);
+        S1[k] += w * zp;
+        S2[k] += w * zp * zp;
         T[k] = Tn;
         last[k] = (int)(b + j + 1 - rg.x);
       }
@@ -288,14 +301,421 @@ __global__ void __launch_bounds__(64) surfel_fwd_kernel(
       alpha[fr.pixel_offset + p] = 1.0f - T[k];
       t_final[fr.pixel_offset + p] = T[k];
       n_last[fr.pixel_offset + p] = last[k];
+      dist[fr.pixel_offset + p] = DS[k];
+      float* ax = dist_aux + 3 * (fr.pixel_offset + p);
+      ax[0] = ZR[k];
+      ax[1] = S1[k];
+      ax[2] = S2[k];
     }
   }
+}
+
+// Sum over the wave of N values per lane, FP64, by recursive halving: at
+// lane bit b a lane keeps the lower or upper half of its values (by that
+// bit) and adds its partner's copy of the same half, so after six rounds each
+// of the N totals sits on exactly one lane.  Returns that lane's total, its
+// index idx and writer = true on the N lanes that hold one (the rest hold
+// padding).
+template <int C, int B>
+__device__ __forceinline__ void halve(const double* in, double* out, int lane, int& base,
+                                      int& cnt) {
+  constexpr int H = (C + 1) / 2;
+  const bool hi = (lane >> B) & 1;
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    const double lo_v = in[j];
+    const double hi_v = (H + j < C) ? in[H + j] : 0.0;
+    const double keep = hi ? hi_v : lo_v;
+    const double send = hi ? lo_v : hi_v;
+    out[j] = keep + __shfl_xor(send, 1 << B, kWave);
+  }
+  if (hi) {
+    base += H;
+    cnt = cnt > H ? cnt - H : 0;
+  } else {
+    cnt = cnt < H ? cnt : H;
+  }
+}
+
+template <int N>
+__device__ __forceinline__ double wave_transpose_sum(const double (&v)[N], int lane, int& idx,
+                                                     bool& writer) {
+  static_assert(N >= 1 && N <= kWave, "one total per lane");
+  constexpr int C5 = N, C4 = (C5 + 1) / 2, C3 = (C4 + 1) / 2, C2 = (C3 + 1) / 2,
+                C1 = (C2 + 1) / 2, C0 = (C1 + 1) / 2;
+  double r4[C4], r3[C3], r2[C2], r1[C1], r0[C0], rr[(C0 + 1) / 2];
+  int base = 0, cnt = N;
+  halve<C5, 5>(v, r4, lane, base, cnt);
+  halve<C4, 4>(r4, r3, lane, base, cnt);
+  halve<C3, 3>(r3, r2, lane, base, cnt);
+  halve<C2, 2>(r2, r1, lane, base, cnt);
+  halve<C1, 1>(r1, r0, lane, base, cnt);
+  halve<C0, 0>(r0, rr, lane, base, cnt);
+  idx = base;
+  writer = cnt > 0;
+  return rr[0];
+}
+
+// Per key (one surfel in one tile), the values the backward reduces, in this
+// order: S_hu[3] = sum dL/dh_u, S_hv[3] = sum dL/dh_v, G_M2[3] = the direct
+// gradient of M2 = sum (x - c_x) dL/dh_u + (y - c_y) dL/dh_v + dL/dz (u, v, 1),
+// G_c[2] = the low-pass term's gradient of the centre c, the opacity, the
+// colour[3] and the normal[3].
+constexpr int kSG = 18;
+
+template <int TW, int TH>
+__global__ void __launch_bounds__(64) surfel_bwd_kernel(
+    int n_frames, const FrameDesc* __restrict__ frames, const uint2* __restrict__ ranges,
+    const uint32_t* __restrict__ vals, const Surfel* __restrict__ rec,
+    const uint2* __restrict__ trect, const uint32_t* __restrict__ keyoff, float bg0, float bg1,
+    float bg2, const float* __restrict__ g_rgb, const float* __restrict__ g_depth,
+    const float* __restrict__ g_alpha, const float* __restrict__ g_normal,
+    const float* __restrict__ g_dist, const float* __restrict__ t_final,
+    const int32_t* __restrict__ n_last, const float* __restrict__ dist_aux,
+    float* __restrict__ partial, uint32_t* __restrict__ stamp,
+    const uint32_t* __restrict__ epoch_dev) {
+  constexpr int PIX = TW * TH / kWave;
+  constexpr int RPP = kWave / TW;
+  __shared__ Surfel sm[kWave];
+  __shared__ uint32_t slot[kWave];
+  const uint32_t epoch = *epoch_dev;
+  const int tile = blockIdx.x;
+  const int f = frame_of_tile(frames, n_frames, tile);
+  const FrameDesc fr = frames[f];
+  const int lt = tile - fr.tile_offset;
+  const int tx = lt % fr.grid_x, ty = lt / fr.grid_x;
+  const int x0 = tx * TW, y0 = ty * TH;
+  const int lane = threadIdx.x;
+  const int px = x0 + lane % TW;
+  const int ly = lane / TW;
+  const uint2 rg = ranges[tile];
+  const int64_t plane = (int64_t)fr.width * fr.height;
+  // per pixel: T_{i+1}, the totals of the distortion sums, and the values
+  // seen behind the current entry (colour, depth, normal, distortion weight
+  // e, transmittance), normalised by T_{i+1}; FP64 because dL/da_i takes
+  // their differences with the entry's own values
+  float T[PIX], BT[PIX], AT[PIX], ZR[PIX], S1[PIX], S2[PIX];
+  double BC0[PIX], BC1[PIX], BC2[PIX], BD[PIX], BN0[PIX], BN1[PIX], BN2[PIX], BE[PIX];
+  float G0[PIX], G1[PIX], G2[PIX], GD[PIX], GA[PIX], GN0[PIX], GN1[PIX], GN2[PIX], GE[PIX];
+  int last[PIX];
+  int most = 0;
+#pragma unroll
+  for (int k = 0; k < PIX; ++k) {
+    const int py = y0 + k * RPP + ly;
+    const bool valid = px < fr.width && py < fr.height;
+    const int64_t p = (int64_t)py * fr.width + px;
+    const int64_t q = fr.pixel_offset + p;
+    last[k] = valid ? n_last[q] : 0;
+    most = last[k] > most ? last[k] : most;
+    T[k] = valid ? t_final[q] : 1.0f;
+    AT[k] = 1.0f - T[k];
+    ZR[k] = valid ? dist_aux[3 * q] : 0.0f;
+    S1[k] = valid ? dist_aux[3 * q + 1] : 0.0f;
+    S2[k] = valid ? dist_aux[3 * q + 2] : 0.0f;
+    BC0[k] = bg0; BC1[k] = bg1; BC2[k] = bg2;
+    BD[k] = BN0[k] = BN1[k] = BN2[k] = BE[k] = 0.0;
+    BT[k] = 1.0f;
+    const float* gi = g_rgb + 3 * fr.pixel_offset;
+    const float* gn = g_normal + 3 * fr.pixel_offset;
+    G0[k] = valid ? gi[p] : 0.0f;
+    G1[k] = valid ? gi[plane + p] : 0.0f;
+    G2[k] = valid ? gi[2 * plane + p] : 0.0f;
+    GN0[k] = valid ? gn[p] : 0.0f;
+    GN1[k] = valid ? gn[plane + p] : 0.0f;
+    GN2[k] = valid ? gn[2 * plane + p] : 0.0f;
+    GD[k] = valid ? g_depth[q] : 0.0f;
+    GA[k] = valid ? g_alpha[q] : 0.0f;
+    GE[k] = valid ? g_dist[q] : 0.0f;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const int m = __shfl_xor(most, o, kWave);
+    most = m > most ? m : most;
+  }
+  for (int hi = most; hi > 0; hi -= kWave) {
+    const int lo = hi > kWave ? hi - kWave : 0;
+    if (lo + lane < hi) {
+      const uint32_t r = vals[rg.x + lo + lane];
+      sm[lane] = rec[r];
+      const uint2 tr = trect[r];
+      const int rx0 = tr.x & 0xffff, rx1 = tr.x >> 16, ry0 = tr.y & 0xffff;
+      slot[lane] = keyoff[r] + (uint32_t)((ty - ry0) * (rx1 - rx0 + 1) + (tx - rx0));
+    }
+    __syncthreads();
+    for (int j = hi - lo - 1; j >= 0; --j) {
+      const int pos = lo + j;
+      const Surfel& S = sm[j];
+      const int xlo = S.sqx & 0xffff, xhi = S.sqx >> 16;
+      const int ylo = S.sqy & 0xffff, yhi = S.sqy >> 16;
+      const bool xin = (unsigned)(px - xlo) <= (unsigned)(xhi - xlo);
+      double acc[kSG];
+#pragma unroll
+      for (int i = 0; i < kSG; ++i) acc[i] = 0.0;
+      bool any = false;
+#pragma unroll
+      for (int k = 0; k < PIX; ++k) {
+        const int row0 = y0 + k * RPP;
+        if (ylo > row0 + RPP - 1 || yhi < row0) continue;
+        const int py = row0 + ly;
+        if (pos >= last[k] || !xin || (unsigned)(py - ylo) > (unsigned)(yhi - ylo)) continue;
+        const SurfelHit h = surfel_eval(S, px, py);
+        const float sg = S.opacity * h.Gh;
+        const float a = fminf(kAlphaMax, sg);
+        if (a < kAlphaMin) continue;
+        const float om = 1.0f - a;
+        const float inv = __builtin_amdgcn_rcpf(om);
+        float Ti = T[k] * inv;
+        Ti = __builtin_fmaf(__builtin_fmaf(-Ti, om, T[k]), inv, Ti);  // Newton step
+        const float w = a * Ti;
+        const float zp = h.z - ZR[k];
+        // dDist/dw_i: sum over the other entries m of w_m (z_i - z_m)^2
+        const double e = (double)AT[k] * zp * zp - 2.0 * zp * S1[k] + S2[k];
+        const double ad = a;
+        const double d0 = S.c0 - BC0[k], d1 = S.c1 - BC1[k], d2 = S.c2 - BC2[k];
+        const double dz = h.z - BD[k], de = e - BE[k];
+        const double dn0 = S.n0 - BN0[k], dn1 = S.n1 - BN1[k], dn2 = S.n2 - BN2[k];
+        const float dLda =
+            Ti * (G0[k] * (float)d0 + G1[k] * (float)d1 + G2[k] * (float)d2 +
+                  GD[k] * (float)dz + GN0[k] * (float)dn0 + GN1[k] * (float)dn1 +
+                  GN2[k] * (float)dn2 + GE[k] * (float)de + GA[k] * BT[k]);
+        acc[12] += G0[k] * w;
+        acc[13] += G1[k] * w;
+        acc[14] += G2[k] * w;
+        acc[15] += GN0[k] * w;
+        acc[16] += GN1[k] * w;
+        acc[17] += GN2[k] * w;
+        // dL/dz_i: the depth map and the distortion, 2 w_i sum_m w_m (z_i - z_m)
+        const float dzv = w * (GD[k] + 2.0f * GE[k] * (zp * AT[k] - S1[k]));
+        BC0[k] = __builtin_fma(ad, d0, BC0[k]);
+        BC1[k] = __builtin_fma(ad, d1, BC1[k]);
+        BC2[k] = __builtin_fma(ad, d2, BC2[k]);
+        BD[k] = __builtin_fma(ad, dz, BD[k]);
+        BN0[k] = __builtin_fma(ad, dn0, BN0[k]);
+        BN1[k] = __builtin_fma(ad, dn1, BN1[k]);
+        BN2[k] = __builtin_fma(ad, dn2, BN2[k]);
+        BE[k] = __builtin_fma(ad, de, BE[k]);
+        BT[k] = BT[k] * om;
+        T[k] = Ti;
+        any = true;
+        const bool clamped = sg > kAlphaMax;  // clamped: alpha does not move
+        const float dGh = clamped ? 0.0f : dLda * S.opacity;
+        if (!clamped) acc[11] += dLda * h.Gh;
+        if (h.obj) {
+          // z = M2 . (u, v, 1), G = exp(-(u^2 + v^2)/2), (u, v) = (p0, p1) / p2
+          const float gu = -h.u * h.Gh * dGh + dzv * S.m2x;
+          const float gv = -h.v * h.Gh * dGh + dzv * S.m2y;
+          acc[6] += h.u * dzv;
+          acc[7] += h.v * dzv;
+          acc[8] += dzv;
+          const float ip = 1.0f / h.p2;
+          const float dp0 = gu * ip, dp1 = gv * ip, dp2 = -(gu * h.u + gv * h.v) * ip;
+          // p = h_u x h_v: dL/dh_u = h_v x dL/dp, dL/dh_v = dL/dp x h_u
+          const float a0 = h.hvy * dp2 - h.hvz * dp1, a1 = h.hvz * dp0 - h.hvx * dp2,
+                      a2 = h.hvx * dp1 - h.hvy * dp0;
+          const float b0 = dp1 * h.huz - dp2 * h.huy, b1 = dp2 * h.hux - dp0 * h.huz,
+                      b2 = dp0 * h.huy - dp1 * h.hux;
+          acc[0] += a0;
+          acc[1] += a1;
+          acc[2] += a2;
+          acc[3] += b0;
+          acc[4] += b1;
+          acc[5] += b2;
+          // h_u = (x - c_x) M2 + k_u, h_v = (y - c_y) M2 + k_v
+          acc[6] += (double)h.ex * a0 + (double)h.ey * b0;
+          acc[7] += (double)h.ex * a1 + (double)h.ey * b1;
+          acc[8] += (double)h.ex * a2 + (double)h.ey * b2;
+        } else {
+          // the low-pass: z = z_c, G_lp = exp(-|(x, y) - c|^2)
+          acc[8] += dzv;
+          const float t = 2.0f * h.Gh * dGh;
+          acc[9] += t * h.ex;
+          acc[10] += t * h.ey;
+        }
+      }
+      if (__ballot(any) == 0) continue;
+      int idx;
+      bool writer;
+      const double tot = wave_transpose_sum<kSG>(acc, lane, idx, writer);
+      const uint32_t sl = slot[j];
+      if (writer) partial[(size_t)sl * kSG + idx] = (float)tot;
+      if (lane == 0) stamp[sl] = epoch;
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// Chain rule from the per-key sums to the parameters (FP64), per surfel and
+// frame: the key sums of the frame's keys (those stamped by this backward)
+// give dL/dM (M0 = -S_hu, M1 = -S_hv, M2 = G_M2 + c_x S_hu + c_y S_hv from
+// h_u = x M2 - M0, plus the low-pass term through c = (M0_z, M1_z) / M2_z),
+// then the columns of M = K [A | B | mc]: A = s_u t_u, B = s_v t_v,
+// mc = R_f mu + t_f, t_u, t_v, t_w the camera-frame axes R_f R_g.  The pose
+// twist (rho, phi) moves every camera-frame vector y by phi x y and mc by
+// rho as well, so dL/dphi = sum y x dL/dy.
+template <int DEG>
+__global__ void __launch_bounds__(256) surfel_preprocess_bwd_kernel(
+    int64_t n, int n_frames, const FrameDesc* __restrict__ frames,
+    const float* __restrict__ poses, const float* __restrict__ means,
+    const float* __restrict__ log_scales, const float* __restrict__ quats,
+    const float* __restrict__ opac, const float* __restrict__ sh,
+    const uint32_t* __restrict__ ntiles, const uint32_t* __restrict__ keyoff,
+    const float* __restrict__ partial, const uint32_t* __restrict__ stamp,
+    const uint32_t* __restrict__ epoch_dev, uint64_t key_capacity, float* __restrict__ g_means,
+    float* __restrict__ g_log_scales, float* __restrict__ g_quats, float* __restrict__ g_opac,
+    float* __restrict__ g_sh, double* __restrict__ twist_partial /* [F][n_waves][6] */) {
+#pragma clang fp contract(off)
+  const uint32_t epoch = *epoch_dev;
+  const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = g0 < n;
+  const int64_t g = active ? g0 : 0;
+  const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  const int64_t wave_id = g0 / kWave;
+  constexpr int nb = (DEG + 1) * (DEG + 1);
+  const double su = active ? exp((double)log_scales[2 * g]) : 1.0;
+  const double sv = active ? exp((double)log_scales[2 * g + 1]) : 1.0;
+  double qh[4];
+  for (int a = 0; a < 4; ++a) qh[a] = active ? quats[4 * g + a] : (a == 0 ? 1.0 : 0.0);
+  const double qn = sqrt(qh[0] * qh[0] + qh[1] * qh[1] + qh[2] * qh[2] + qh[3] * qh[3]);
+  for (int a = 0; a < 4; ++a) qh[a] /= qn;
+  const double w = qh[0], x = qh[1], y = qh[2], z = qh[3];
+  const double Rg[9] = {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y),
+                        2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x),
+                        2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)};
+  const double o = active ? 1.0 / (1.0 + exp(-(double)opac[g])) : 0.0;
+  const double mu[3] = {active ? (double)means[3 * g] : 0.0,
+                        active ? (double)means[3 * g + 1] : 0.0,
+                        active ? (double)means[3 * g + 2] : 0.0};
+  const float* shg = sh + g * nb * 3;
+  double dmu[3] = {0, 0, 0}, dR[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, dls[2] = {0, 0}, dop = 0.0;
+  float dsh[nb * 3];
+  for (int i = 0; i < nb * 3; ++i) dsh[i] = 0.0f;
+  for (int f = 0; f < n_frames; ++f) {
+    double tw[6] = {0, 0, 0, 0, 0, 0};
+    const int64_t r = (int64_t)f * n + g;
+    uint32_t cnt = active ? ntiles[r] : 0u;
+    const uint32_t off = cnt ? keyoff[r] : 0u;
+    if (cnt && (uint64_t)off + cnt > key_capacity) cnt = 0;  // overflowed in keygen
+    if (cnt > 0) {
+      double K[kSG];
+      for (int i = 0; i < kSG; ++i) K[i] = 0.0;
+      for (uint32_t sl = off; sl < off + cnt; ++sl) {
+        if (stamp[sl] != epoch) continue;
+        const float* pp = partial + (size_t)sl * kSG;
+        for (int i = 0; i < kSG; ++i) K[i] += pp[i];
+      }
+      const FrameDesc fr = frames[f];
+      double W[9], tf[3];
+      load_pose(poses, f, W, tf);
+      double mc[3], T[9];
+      for (int i = 0; i < 3; ++i) {
+        mc[i] = W[i * 3 + 0] * mu[0] + W[i * 3 + 1] * mu[1] + W[i * 3 + 2] * mu[2] + tf[i];
+        for (int j = 0; j < 3; ++j)
+          T[i * 3 + j] = W[i * 3 + 0] * Rg[0 * 3 + j] + W[i * 3 + 1] * Rg[1 * 3 + j] +
+                         W[i * 3 + 2] * Rg[2 * 3 + j];
+      }
+      const double fx = fr.fx, fy = fr.fy, cx = fr.cx, cy = fr.cy;
+      const double M0z = fx * mc[0] + cx * mc[2], M1z = fy * mc[1] + cy * mc[2], M2z = mc[2];
+      const double ccx = M0z / M2z, ccy = M1z / M2z;
+      double dM0[3], dM1[3], dM2[3];
+      for (int i = 0; i < 3; ++i) {
+        dM0[i] = -K[i];
+        dM1[i] = -K[3 + i];
+        dM2[i] = K[6 + i] + ccx * K[i] + ccy * K[3 + i];
+      }
+      dM0[2] += K[9] / M2z;
+      dM1[2] += K[10] / M2z;
+      dM2[2] -= (K[9] * ccx + K[10] * ccy) / M2z;
+      // column j of M is K times (A, B, mc)[j]
+      double dcol[3][3];
+      for (int j = 0; j < 3; ++j) {
+        dcol[j][0] = fx * dM0[j];
+        dcol[j][1] = fy * dM1[j];
+        dcol[j][2] = cx * dM0[j] + cy * dM1[j] + dM2[j];
+      }
+      const double tu[3] = {T[0], T[3], T[6]}, tv[3] = {T[1], T[4], T[7]};
+      const double tn[3] = {T[2], T[5], T[8]};
+      const double sgn = (tn[0] * mc[0] + tn[1] * mc[1] + tn[2] * mc[2]) < 0.0 ? 1.0 : -1.0;
+      double dT[3][3];  // dT[j] = dL/d(column j of T)
+      for (int i = 0; i < 3; ++i) {
+        dT[0][i] = su * dcol[0][i];
+        dT[1][i] = sv * dcol[1][i];
+        dT[2][i] = sgn * K[15 + i];
+      }
+      dls[0] += su * (dcol[0][0] * tu[0] + dcol[0][1] * tu[1] + dcol[0][2] * tu[2]);
+      dls[1] += sv * (dcol[1][0] * tv[0] + dcol[1][1] * tv[1] + dcol[1][2] * tv[2]);
+      // T = R_f R_g
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+          dR[i * 3 + j] += W[0 * 3 + i] * dT[j][0] + W[1 * 3 + i] * dT[j][1] +
+                           W[2 * 3 + i] * dT[j][2];
+      dop += K[11];
+      // colour: c = max(0, raw), raw = sum_k sh_k Y_k(dir) + 1/2
+      double dir[3];
+      const double dist = view_dir(W, tf, mu, dir);
+      double Y[16];
+      sh_basis<DEG>(dir[0], dir[1], dir[2], Y);
+      double raw[3] = {0.0, 0.0, 0.0};
+      for (int k = 0; k < nb; ++k)
+        for (int c = 0; c < 3; ++c) raw[c] += (double)shg[k * 3 + c] * Y[k];
+      double draw[3];
+      for (int c = 0; c < 3; ++c) draw[c] = raw[c] + 0.5 > 0.0 ? K[12 + c] : 0.0;
+      double wk[16];
+      for (int k = 0; k < nb; ++k) {
+        double acc = 0.0;
+        for (int c = 0; c < 3; ++c) {
+          dsh[k * 3 + c] += (float)(Y[k] * draw[c]);
+          acc += (double)shg[k * 3 + c] * draw[c];
+        }
+        wk[k] = acc;
+      }
+      double ddir[3];
+      sh_dir_grad<DEG>(dir[0], dir[1], dir[2], wk, ddir);
+      const double pr = dir[0] * ddir[0] + dir[1] * ddir[1] + dir[2] * ddir[2];
+      double dd[3];
+      for (int a = 0; a < 3; ++a) dd[a] = (ddir[a] - dir[a] * pr) / dist;
+      const double* dmc = dcol[2];
+      for (int a = 0; a < 3; ++a)
+        dmu[a] += W[0 * 3 + a] * dmc[0] + W[1 * 3 + a] * dmc[1] + W[2 * 3 + a] * dmc[2] + dd[a];
+      // twist: the camera centre moves by -R_f^T rho, so the view direction
+      // adds R_f dd to rho; mc and the three axes rotate with phi
+      for (int a = 0; a < 3; ++a)
+        tw[a] = dmc[a] + W[a * 3 + 0] * dd[0] + W[a * 3 + 1] * dd[1] + W[a * 3 + 2] * dd[2];
+      const double* ys[4] = {mc, tu, tv, tn};
+      const double* gs[4] = {dmc, dT[0], dT[1], dT[2]};
+      for (int m = 0; m < 4; ++m) {
+        const double* Yv = ys[m];
+        const double* Gv = gs[m];
+        tw[3] += Yv[1] * Gv[2] - Yv[2] * Gv[1];
+        tw[4] += Yv[2] * Gv[0] - Yv[0] * Gv[2];
+        tw[5] += Yv[0] * Gv[1] - Yv[1] * Gv[0];
+      }
+    }
+    for (int j = 0; j < 6; ++j) {
+      const double s = wave_sum_d(tw[j]);
+      if ((threadIdx.x & (kWave - 1)) == 0)
+        twist_partial[((int64_t)f * n_waves + wave_id) * 6 + j] = s;
+    }
+  }
+  if (!active) return;
+  g_log_scales[2 * g] = (float)dls[0];
+  g_log_scales[2 * g + 1] = (float)dls[1];
+  quat_grad(qh, qn, dR, g_quats + g * 4);
+  for (int a = 0; a < 3; ++a) g_means[g * 3 + a] = (float)dmu[a];
+  g_opac[g] = (float)(dop * o * (1.0 - o));
+  float* gsh = g_sh + g * nb * 3;
+  for (int i = 0; i < nb * 3; ++i) gsh[i] = dsh[i];
 }
 
 }  // namespace
 
 size_t surfel_record_bytes() { return sizeof(Surfel); }
 size_t surfel_square_offset() { return offsetof(Surfel, sqx); }
+int surfel_grad_values() { return kSG; }
+int64_t surfel_preprocess_bwd_waves(int64_t n) { return ((n + 255) / 256) * 4; }
 
 void launch_surfel_preprocess(hipStream_t st, int64_t n, int F, const FrameDesc* frames,
                               const float* poses, const float* means, const float* log_scales,
@@ -320,18 +740,67 @@ void launch_surfel_preprocess(hipStream_t st, int64_t n, int F, const FrameDesc*
 void launch_surfel_fwd(hipStream_t st, int tw, int th, int n_tiles, int F,
                        const FrameDesc* frames, const uint2* ranges, const uint32_t* vals,
                        const void* rec, const float* bg, float* rgb, float* depth, float* alpha,
-                       float* normal, float* t_final, int32_t* n_last) {
+                       float* normal, float* dist, float* t_final, int32_t* n_last,
+                       float* dist_aux) {
   if (n_tiles <= 0) return;
 #define GSR_SURF_FWD(W, H)                                                                  \
   hipLaunchKernelGGL((surfel_fwd_kernel<W, H>), dim3((unsigned)n_tiles), dim3(kWave), 0, st, \
                      F, frames, ranges, vals, (const Surfel*)rec, bg[0], bg[1], bg[2], rgb,  \
-                     depth, alpha, normal, t_final, n_last)
+                     depth, alpha, normal, dist, t_final, n_last, dist_aux)
   if (tw == 16 && th == 16) GSR_SURF_FWD(16, 16);
   else if (tw == 8 && th == 8) GSR_SURF_FWD(8, 8);
   else if (tw == 32 && th == 8) GSR_SURF_FWD(32, 8);
   else if (tw == 16 && th == 8) GSR_SURF_FWD(16, 8);
   else if (tw == 32 && th == 16) GSR_SURF_FWD(32, 16);
 #undef GSR_SURF_FWD
+}
+
+void launch_surfel_bwd(hipStream_t st, int tw, int th, int n_tiles, int F,
+                       const FrameDesc* frames, const uint2* ranges, const uint32_t* vals,
+                       const void* rec, const uint2* trect, const uint32_t* keyoff,
+                       const float* bg, const float* g_rgb, const float* g_depth,
+                       const float* g_alpha, const float* g_normal, const float* g_dist,
+                       const float* t_final, const int32_t* n_last, const float* dist_aux,
+                       float* partial, uint32_t* stamp, const uint32_t* epoch) {
+  if (n_tiles <= 0) return;
+#define GSR_SURF_BWD(W, H)                                                                   \
+  hipLaunchKernelGGL((surfel_bwd_kernel<W, H>), dim3((unsigned)n_tiles), dim3(kWave), 0, st,  \
+                     F, frames, ranges, vals, (const Surfel*)rec, trect, keyoff, bg[0], bg[1], \
+                     bg[2], g_rgb, g_depth, g_alpha, g_normal, g_dist, t_final, n_last,       \
+                     dist_aux, partial, stamp, epoch)
+  if (tw == 16 && th == 16) GSR_SURF_BWD(16, 16);
+  else if (tw == 8 && th == 8) GSR_SURF_BWD(8, 8);
+  else if (tw == 32 && th == 8) GSR_SURF_BWD(32, 8);
+  else if (tw == 16 && th == 8) GSR_SURF_BWD(16, 8);
+  else if (tw == 32 && th == 16) GSR_SURF_BWD(32, 16);
+#undef GSR_SURF_BWD
+}
+
+void launch_surfel_preprocess_bwd(hipStream_t st, int64_t n, int F, const FrameDesc* frames,
+                                  const float* poses, const float* means,
+                                  const float* log_scales, const float* quats,
+                                  const float* opac, const float* sh, int deg,
+                                  const uint32_t* ntiles, const uint32_t* keyoff,
+                                  const float* partial, const uint32_t* stamp,
+                                  const uint32_t* epoch, uint64_t key_capacity, float* g_means,
+                                  float* g_log_scales, float* g_quats, float* g_opac,
+                                  float* g_sh, double* twist_partial, float* g_twist) {
+  if (n > 0) {
+    const dim3 grid((unsigned)((n + 255) / 256));
+#define GSR_SURF_PRE_BWD(D)                                                                   \
+  hipLaunchKernelGGL(surfel_preprocess_bwd_kernel<D>, grid, dim3(256), 0, st, n, F, frames,  \
+                     poses, means, log_scales, quats, opac, sh, ntiles, keyoff, partial,       \
+                     stamp, epoch, key_capacity, g_means, g_log_scales, g_quats, g_opac, g_sh, \
+                     twist_partial)
+    switch (deg) {
+      case 0: GSR_SURF_PRE_BWD(0); break;
+      case 1: GSR_SURF_PRE_BWD(1); break;
+      case 2: GSR_SURF_PRE_BWD(2); break;
+      default: GSR_SURF_PRE_BWD(3); break;
+    }
+#undef GSR_SURF_PRE_BWD
+  }
+  launch_twist_reduce(st, F, twist_partial, n > 0 ? surfel_preprocess_bwd_waves(n) : 0, g_twist);
 }
 
 }  // namespace gsr

@@ -84,23 +84,41 @@ class Rasterizer:
     def forward_surfel(self, means, log_scales, quats, opacity, sh, poses, cams, sh_degree,
                        background=(0.0, 0.0, 0.0), tile=(16, 16), key_capacity=0, out=None):
         """Renders F frames of 2D surfels (log_scales [n,2]); returns packed
-        (rgb, depth, alpha, normal [sum 3HW])."""
+        (rgb, depth, alpha, normal [sum 3HW], dist [sum HW])."""
         P = int(sum(int(c[0]) * int(c[1]) for c in cams))
         dev = means.device
         if out is None:
             out = (torch.empty(3 * P, device=dev), torch.empty(P, device=dev),
-                   torch.empty(P, device=dev), torch.empty(3 * P, device=dev))
-        rgb, depth, alpha, normal = out
+                   torch.empty(P, device=dev), torch.empty(3 * P, device=dev),
+                   torch.empty(P, device=dev))
+        rgb, depth, alpha, normal, dist = out
         self.settings = native.make_settings(sh_degree, background, tile, key_capacity)
         self.cams = native.make_cameras(cams)
         n = int(means.shape[0])
         self._check(self.lib.gsr_forward_surfel(
             self.h, C.byref(self.settings), n, _ptr(means), _ptr(log_scales), _ptr(quats),
             _ptr(opacity), _ptr(sh), len(cams), self.cams, _ptr(poses), _ptr(rgb), _ptr(depth),
-            _ptr(alpha), _ptr(normal), _stream()))
+            _ptr(alpha), _ptr(normal), _ptr(dist), _stream()))
         self.n, self.F, self.sh_degree = n, len(cams), sh_degree
         self.sizes = [(int(c[0]), int(c[1])) for c in cams]
-        return rgb, depth, alpha, normal
+        return rgb, depth, alpha, normal, dist
+
+    def backward_surfel(self, g_rgb, g_depth, g_alpha, g_normal, g_dist, out=None):
+        """Gradients of the last forward_surfel for upstream gradients of its
+        five outputs; returns means [n,3], log_scales [n,2], quats [n,4],
+        opacity [n], sh [n,K,3], twist [F,6]."""
+        n, F = self.n, self.F
+        dev = g_rgb.device
+        K = (self.sh_degree + 1) ** 2
+        if out is None:
+            out = dict(means=torch.empty(n, 3, device=dev), log_scales=torch.empty(n, 2, device=dev),
+                       quats=torch.empty(n, 4, device=dev), opacity=torch.empty(n, device=dev),
+                       sh=torch.empty(n, K, 3, device=dev), twist=torch.empty(F, 6, device=dev))
+        self._check(self.lib.gsr_backward_surfel(
+            self.h, _ptr(g_rgb), _ptr(g_depth), _ptr(g_alpha), _ptr(g_normal), _ptr(g_dist),
+            _ptr(out["means"]), _ptr(out["log_scales"]), _ptr(out["quats"]),
+            _ptr(out["opacity"]), _ptr(out["sh"]), _ptr(out["twist"]), _stream()))
+        return out
 
     def backward(self, g_rgb, g_depth, g_alpha, out=None):
         n, F = self.n, self.F

@@ -1,18 +1,25 @@
-"""Parity of the 2D surfel forward (gsr_forward_surfel, through the C-ABI)
-against the PyTorch FP64 surfel oracle (oracle/surfel.py).
+"""Parity of the 2D surfel forward and backward (gsr_forward_surfel,
+gsr_backward_surfel, through the C-ABI) against the PyTorch FP64 surfel
+oracle (oracle/surfel.py) and its autograd.
 
 Integer artefacts: the kept set and the pixel boxes are equal.  Images (RGB,
-depth, alpha, normal) are within 1e-4 absolute on the pixels the oracle
-does not flag; a pixel is flagged where some decision sits within the FP32
-error of its threshold (alpha near 1/255, with a band widened by the
+depth, alpha, normal, distortion) are within 1e-4 absolute on the pixels the
+oracle does not flag; a pixel is flagged where some decision sits within the
+FP32 error of its threshold (alpha near 1/255, with a band widened by the
 conditioning 1/sin of the intersection's two planes; T near 1e-4; the 0.99
-clamp; or the disk and low-pass terms within 1e-3 of each other)."""
+clamp; or the disk and low-pass terms within 1e-3 of each other).
+Gradients: upstream gradients of all five outputs, zero on flagged pixels,
+these including the pixels where the intersection's conditioning exceeds
+32 (its FP32 derivative errs by ~kappa^2 ulps);
+the bar of the 3D backward (1e-3 relative with its floors, or 3 times the
+oracle's own response to a 1e-6 relative jitter of the upstream)."""
 import numpy as np
 import pytest
+import torch
 
 from oracle import surfel as S
 from paper_2411_17660_amd import scenes
-from gpu_util import IMG_TOL, to_dev
+from gpu_util import IMG_TOL, GRAD_REL, to_dev, perturbed, assert_grad_close
 
 pytestmark = pytest.mark.gpu
 
@@ -40,27 +47,30 @@ def _check(rast, sc, tile, label):
     import torch
     print(f"[surfel] {label} n={sc.n} F={sc.n_frames} tile={tile}", flush=True)
     d = to_dev(sc)
-    rgb, dep, alp, nrm = rast.forward_surfel(d["means"], d["log_scales"], d["quats"],
-                                             d["opacity"], d["sh"], d["poses"], sc.cams,
-                                             sc.sh_degree, sc.background, tile=tile)
+    rgb, dep, alp, nrm, dst = rast.forward_surfel(d["means"], d["log_scales"], d["quats"],
+                                                  d["opacity"], d["sh"], d["poses"], sc.cams,
+                                                  sc.sh_degree, sc.background, tile=tile)
     torch.cuda.synchronize()
-    rgb, dep, alp, nrm = (x.cpu().numpy().astype(np.float64) for x in (rgb, dep, alp, nrm))
+    rgb, dep, alp, nrm, dst = (x.cpu().numpy().astype(np.float64)
+                               for x in (rgb, dep, alp, nrm, dst))
     L = rast.debug_lists()
     ref = _oracle(sc)
     off = 0
-    errs = np.zeros(4)
+    errs = np.zeros(5)
     flagged = 0
     n = sc.n
     for f, fr in enumerate(ref):
         W, H = int(sc.cams[f][0]), int(sc.cams[f][1])
         P = W * H
-        ok = (fr["flags"] == 0).ravel()
+        ok = ((fr["flags"] & (0xff ^ S.FLAG_COND)) == 0).ravel()
         flagged += int((~ok).sum())
         got = [rgb[3 * off:3 * (off + P)].reshape(3, P), dep[off:off + P].reshape(1, P),
-               alp[off:off + P].reshape(1, P), nrm[3 * off:3 * (off + P)].reshape(3, P)]
+               alp[off:off + P].reshape(1, P), nrm[3 * off:3 * (off + P)].reshape(3, P),
+               dst[off:off + P].reshape(1, P)]
         want = [fr["rgb"].detach().numpy().reshape(3, P), fr["depth"].detach().numpy().reshape(1, P),
                 fr["alpha"].detach().numpy().reshape(1, P),
-                fr["normal"].detach().numpy().reshape(3, P)]
+                fr["normal"].detach().numpy().reshape(3, P),
+                fr["dist"].detach().numpy().reshape(1, P)]
         for i, (g, w) in enumerate(zip(got, want)):
             errs[i] = max(errs[i], float(np.abs(g - w)[:, ok].max(initial=0.0)))
         # kept set and boxes
@@ -75,9 +85,11 @@ def _check(rast, sc, tile, label):
         assert np.array_equal(sq[keep, 1] >> 16, box[keep, 3])
         off += P
     print(f"[surfel]   max err rgb {errs[0]:.3g} depth {errs[1]:.3g} alpha {errs[2]:.3g} "
-          f"normal {errs[3]:.3g}; flagged px {flagged} of {off}", flush=True)
+          f"normal {errs[3]:.3g} dist {errs[4]:.3g} (max {dst.max():.3g}); "
+          f"flagged px {flagged} of {off}", flush=True)
     assert np.all(errs <= IMG_TOL), errs
     assert float(alp.max()) > 0.3
+    assert float(dst.max()) > 1e-3
 
 
 @pytest.mark.parametrize("seed,n,frames,deg,W,H,tile", [
@@ -103,6 +115,7 @@ def test_surfel_images_do_not_depend_on_tile_shape(rast):
                                 d["poses"], sc.cams, sc.sh_degree, sc.background, tile=tile)
         torch.cuda.synchronize()
         outs.append([x.clone() for x in o])
+        assert len(o) == 5
     for o in outs[1:]:
         for a, b in zip(outs[0], o):
             assert torch.equal(a, b)
@@ -119,3 +132,88 @@ def test_backward_after_surfel_forward_is_a_state_error(rast):
     with pytest.raises(GsrError):
         rast.backward(torch.zeros(3 * P, device="cuda"), torch.zeros(P, device="cuda"),
                       torch.zeros(P, device="cuda"))
+
+
+def test_surfel_backward_after_3d_forward_is_a_state_error(rast):
+    from paper_2411_17660_amd.native import GsrError
+    from gpu_util import gpu_forward
+    sc = scenes.tiny_scene(seed=10, n=40)
+    gpu_forward(rast, sc)
+    P = sc.n_pixels
+    z = lambda k: torch.zeros(k, device="cuda")             # noqa: E731
+    rast.sh_degree = sc.sh_degree
+    with pytest.raises(GsrError):
+        rast.backward_surfel(z(3 * P), z(P), z(P), z(3 * P), z(P))
+
+
+def _upstream(seed, sc, flags):
+    """Upstream gradients of (rgb, depth, alpha, normal, dist), FP32, zero on
+    the flagged pixels."""
+    rng = np.random.default_rng(seed)
+    P = sc.n_pixels
+    sizes = [(int(c[0]), int(c[1])) for c in sc.cams]
+    keep = (flags == 0).astype(np.float32)
+    offs = np.cumsum([0] + [w * h for w, h in sizes])[:-1]
+    keep3 = np.concatenate([np.tile(keep[o:o + w * h], 3) for o, (w, h) in zip(offs, sizes)])
+    g = [rng.normal(size=3 * P) * keep3, rng.normal(size=P) * keep, rng.normal(size=P) * keep,
+         rng.normal(size=3 * P) * keep3, 5.0 * rng.normal(size=P) * keep]
+    return [x.astype(np.float32) for x in g]
+
+
+NAMES = ("means", "log_scales", "quats", "opacity", "sh", "twist")
+
+
+def _oracle_grads(sc):
+    """Oracle autograd of sum_o <G_o, output_o>; and the size of the gradient
+    change a 1e-6 relative jitter of G causes (by linearity, the gradient of
+    the jitter itself)."""
+    t = S.to64
+    params = [t(sc.means, True), t(sc.log_scales, True), t(sc.quats, True), t(sc.opacity, True),
+              t(sc.sh, True), t(np.zeros((sc.n_frames, 6)), True)]
+    out = S.render(*params[:5], sc.sh_degree, sc.cams, t(sc.poses), sc.background,
+                   twist=params[5])
+    flags = np.concatenate([fr["flags"].ravel() for fr in out])
+    maps = [torch.cat([fr["rgb"].reshape(-1) for fr in out]),
+            torch.cat([fr["depth"].reshape(-1) for fr in out]),
+            torch.cat([fr["alpha"].reshape(-1) for fr in out]),
+            torch.cat([fr["normal"].reshape(-1) for fr in out]),
+            torch.cat([fr["dist"].reshape(-1) for fr in out])]
+
+    def grads(Gs, retain):
+        loss = sum((m * torch.from_numpy(np.asarray(g, np.float64))).sum()
+                   for m, g in zip(maps, Gs))
+        return [x.numpy() for x in torch.autograd.grad(loss, params, retain_graph=retain)]
+    return flags, maps, grads
+
+
+def _check_backward(rast, sc, tile, seed, label):
+    flags, _, grads = _oracle_grads(sc)
+    G = _upstream(seed, sc, flags)
+    g_ref = grads(G, True)
+    dG = [p - np.asarray(g, np.float64) for p, g in zip(perturbed(G), G)]
+    noise = [np.abs(x) for x in grads(dG, False)]
+    d = to_dev(sc)
+    rast.forward_surfel(d["means"], d["log_scales"], d["quats"], d["opacity"], d["sh"],
+                        d["poses"], sc.cams, sc.sh_degree, sc.background, tile=tile)
+    g = rast.backward_surfel(*[torch.from_numpy(x).cuda() for x in G])
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy().astype(np.float64) for k, v in g.items()}
+    print(f"[surfel] backward {label} n={sc.n} F={sc.n_frames} tile={tile}: "
+          f"flagged {int((flags != 0).sum())} of {flags.size}", flush=True)
+    for k, r, nz in zip(NAMES[:5], g_ref[:5], noise[:5]):
+        assert_grad_close(f"surfel {label}:{k}", got[k], r, noise=nz)
+    tr = g_ref[5]
+    bound = np.maximum(GRAD_REL * np.maximum(np.abs(tr), 1e-2 * np.abs(tr).max()),
+                       3.0 * noise[5])
+    err = np.abs(got["twist"] - tr)
+    print(f"[surfel]   twist max err/bound {float((err / bound).max()):.3g}", flush=True)
+    assert np.all(err <= bound)
+
+
+@pytest.mark.parametrize("seed,n,frames,deg,W,H,tile", [
+    (20, 40, 1, 0, 40, 30, (16, 16)), (21, 150, 2, 3, 61, 45, (8, 8)),
+    (22, 250, 2, 1, 70, 50, (32, 8)), (23, 120, 1, 2, 33, 17, (32, 16)),
+    (24, 700, 1, 3, 96, 64, (16, 16))])
+def test_surfel_backward_matches_oracle_autograd(rast, seed, n, frames, deg, W, H, tile):
+    sc = _surfel_scene(seed, n, W, H, 0.8 * W, frames, deg)
+    _check_backward(rast, sc, tile, seed, f"surfels{seed}")

@@ -179,6 +179,25 @@ gsr_status gsr_backward_surfel(gsr_context* ctx, const float* g_rgb, const float
                                float* g_quats, float* g_opacity_logits, float* g_sh,
                                float* g_twist, void* stream);
 
+/* The normal-consistency term of the surfel objective (the L_normal that the
+ * supplementary's Rendering settings add for 2D Gaussian Splatting) on F
+ * frames of rendered depth, alpha [sum_f H_f W_f] and normal [sum_f 3 H_f
+ * W_f] (packed like the gsr_forward_surfel outputs; any images of that
+ * layout).  Per frame, with the points P = D K^-1 (x, y, 1) and on interior
+ * pixels (1 <= x <= W-2, 1 <= y <= H-2), N = v/|v|, v = dP_y x dP_x from the
+ * central differences dP_x = P(x+1, y) - P(x-1, y), dP_y = P(x, y+1) -
+ * P(x, y-1); a pixel's sum_i w_i (1 - n_i . N) is alpha - normal . N; the
+ * frame's term is its mean over the (W-2)(H-2) interior pixels (0 where
+ * v = 0).  Writes *loss = weight * sum_f term_f (device float) and ADDS the
+ * gradient of *loss to g_depth, g_alpha and g_normal (device, packed like
+ * the images), so that it stacks on the gradients of other terms.  Uses
+ * only cams' width, height, fx, fy, cx, cy.  Does not touch the saved
+ * forward.  Arithmetic in FP64 from the FP32 images. */
+gsr_status gsr_normal_consistency(gsr_context* ctx, int32_t n_frames, const gsr_camera* cams,
+                                  const float* depth, const float* alpha, const float* normal,
+                                  float weight, float* loss, float* g_depth, float* g_alpha,
+                                  float* g_normal, void* stream);
+
 /* Backward of the last forward on ctx for upstream gradients g_rgb, g_depth,
  * g_alpha (packed like the outputs).  Writes g_means [n,3], g_log_scales
  * [n,3], g_quats [n,4], g_opacity_logits [n], g_sh [n,(d+1)^2,3] (summed

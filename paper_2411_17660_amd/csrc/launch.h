@@ -2,6 +2,7 @@
 // define them and by runtime.hip, which sequences them.  Internal to
 // libgsr.so; every launcher enqueues on `st` and returns without waiting.
 #pragma once
+#include "gsr.h"
 #include "gsr_device.h"
 
 namespace gsr {
@@ -138,6 +139,16 @@ void launch_surfel_preprocess_bwd(hipStream_t st, int64_t n, int F, const FrameD
                                   const uint32_t* epoch, uint64_t key_capacity, float* g_means,
                                   float* g_log_scales, float* g_quats, float* g_opac,
                                   float* g_sh, double* twist_partial, float* g_twist);
+
+// normals.hip: the normal-consistency term of the surfel objective on packed
+// depth / alpha [sum HW] and normal [sum 3HW] images of F frames (host
+// cameras); adds its gradients to g_depth, g_alpha, g_normal and writes
+// loss[0]; part holds sum_f normal_consistency_blocks(W_f, H_f) doubles.
+int64_t normal_consistency_blocks(int W, int H);
+void launch_normal_consistency(hipStream_t st, int F, const gsr_camera* cams,
+                               const float* depth, const float* alpha, const float* normal,
+                               float weight, double* part, float* loss, float* g_depth,
+                               float* g_alpha, float* g_normal);
 
 // adam.hip
 void launch_adam(hipStream_t st, uint64_t n3, uint64_t nsh, float* means, const float* g_means,

@@ -55,6 +55,7 @@ struct gsr_context {
   DBuf ssim_part, ssim_tiles, ssim_scale;  // rendering loss with SSIM
   DBuf med_pos;                     // per pixel: list position of the median-depth entry
   DBuf dist_aux, spart;             // surfels: distortion sums per pixel, per-key partials
+  DBuf nc_part;                     // normal consistency: per-block loss partials
   DBuf reloc_cnt, reloc_rule;       // MCMC relocation scratch
   DBuf up_rgb, up_depth, up_alpha;  // upstream gradients for gsr_step_l1
   DBuf tune_out;                    // scratch outputs of the autotuner
@@ -269,7 +270,7 @@ gsr_status gsr_destroy(gsr_context* ctx) {
                   &ctx->reloc_cnt, &ctx->reloc_rule,
                   &ctx->up_rgb, &ctx->up_depth, &ctx->up_alpha, &ctx->tune_out,
                   &ctx->order_f, &ctx->order_b, &ctx->cls_a, &ctx->cls_b, &ctx->clsv_a,
-                  &ctx->clsv_b, &ctx->dist_aux, &ctx->spart};
+                  &ctx->clsv_b, &ctx->dist_aux, &ctx->spart, &ctx->nc_part};
   for (DBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (ctx->h_frames) (void)hipHostFree(ctx->h_frames);
@@ -522,6 +523,36 @@ gsr_status gsr_forward_surfel(gsr_context* ctx, const gsr_settings* s, int64_t n
                               void* stream) {
   return forward_impl(ctx, s, n, means, log_scales, quats, opac, sh, F, cams, poses, rgb, depth,
                       alpha, normal, dist, true, stream);
+}
+
+gsr_status gsr_normal_consistency(gsr_context* ctx, int32_t F, const gsr_camera* cams,
+                                  const float* depth, const float* alpha, const float* normal,
+                                  float weight, float* loss, float* g_depth, float* g_alpha,
+                                  float* g_normal, void* stream) {
+  if (!ctx) return GSR_ERR_INVALID_ARGUMENT;
+  if (F <= 0 || !cams) return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "no frames");
+  if (!depth || !alpha || !normal || !loss || !g_depth || !g_alpha || !g_normal)
+    return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "pointer is NULL");
+  const void* ptrs[] = {depth, alpha, normal, loss, g_depth, g_alpha, g_normal};
+  for (const void* p : ptrs)
+    if (((uintptr_t)p) & 3u) return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "pointer not 4-aligned");
+  int64_t blocks = 0;
+  for (int f = 0; f < F; ++f) {
+    const gsr_camera& c = cams[f];
+    if (c.width <= 0 || c.height <= 0 || c.width > 65535 || c.height > 65535 ||
+        !(c.fx > 0.0f) || !(c.fy > 0.0f))
+      return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "camera %d invalid", f);
+    blocks += normal_consistency_blocks(c.width, c.height);
+  }
+  ctx->err.clear();
+  hipStream_t st = (hipStream_t)stream;
+  GSR_HIP(hipSetDevice(ctx->device));
+  gsr_status rc;
+  if ((rc = ensure(ctx, ctx->nc_part, (size_t)blocks * 8, st))) return rc;
+  launch_normal_consistency(st, F, cams, depth, alpha, normal, weight, P<double>(ctx->nc_part),
+                            loss, g_depth, g_alpha, g_normal);
+  GSR_HIP(hipGetLastError());
+  return GSR_OK;
 }
 
 gsr_status gsr_backward_surfel(gsr_context* ctx, const float* g_rgb, const float* g_depth,

@@ -103,6 +103,19 @@ class Rasterizer:
         self.sizes = [(int(c[0]), int(c[1])) for c in cams]
         return rgb, depth, alpha, normal, dist
 
+    def normal_consistency(self, cams, depth, alpha, normal, weight, g_depth, g_alpha,
+                           g_normal, loss=None):
+        """weight * (normal-consistency term) of packed depth / alpha / normal
+        images; adds its gradient to g_depth, g_alpha, g_normal and returns
+        the loss (device float tensor [1])."""
+        if loss is None:
+            loss = torch.empty(1, device=depth.device)
+        cm = native.make_cameras(cams)
+        self._check(self.lib.gsr_normal_consistency(
+            self.h, len(cams), cm, _ptr(depth), _ptr(alpha), _ptr(normal), float(weight),
+            _ptr(loss), _ptr(g_depth), _ptr(g_alpha), _ptr(g_normal), _stream()))
+        return loss
+
     def backward_surfel(self, g_rgb, g_depth, g_alpha, g_normal, g_dist, out=None):
         """Gradients of the last forward_surfel for upstream gradients of its
         five outputs; returns means [n,3], log_scales [n,2], quats [n,4],

@@ -207,6 +207,7 @@ def main():
     median = measure_median(rast, sc, dev, bb, t_rgb, t_dep, tile, cap, args.steps,
                             depth_weight)
     densify = measure_densify(rast, sc, dev, bb, t_rgb, t_dep, tile, cap, depth_weight)
+    surfel = measure_surfel(rast, sc, dev, tile, args.steps)
 
     mpix = P / 1e6
     t_best = min(t_batched, t_graph) if t_graph else t_batched
@@ -249,6 +250,7 @@ def main():
         "render_loss": render,
         "median_depth": median,
         "densify": densify,
+        "surfel": surfel,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -397,6 +399,57 @@ def measure_densify(rast, sc, dev, bb, t_rgb, t_dep, tile, cap, depth_weight):
            "mcmc_relocate_no_dead": row(ms_reloc, b_reloc)}
     log(f"[bench] densify kernels {out}")
     return out
+
+
+def measure_surfel(rast, sc, dev, tile, steps):
+    """The 2D surfel variant on the workload's primitives (the same means,
+    the first two log-scales, quaternions, opacities and SH), all frames in
+    one batch: forward (rgb, depth, alpha, normal, distortion), backward of
+    all five outputs, and the normal-consistency term on the rendered maps.
+    HIP events on the library's stream.  The normal-consistency kernel moves
+    60 B per pixel at least: it reads depth, alpha and the normal (20 B) and
+    reads and writes the three gradients (40 B)."""
+    import torch
+    P = sc.n_pixels
+    ls2 = dev["log_scales"][:, :2].contiguous()
+    out = [torch.empty(3 * P, device="cuda"), torch.empty(P, device="cuda"),
+           torch.empty(P, device="cuda"), torch.empty(3 * P, device="cuda"),
+           torch.empty(P, device="cuda")]
+
+    def fwd(cap):
+        rast.forward_surfel(dev["means"], ls2, dev["quats"], dev["opacity"], dev["sh"],
+                            dev["poses"], sc.cams, 3, tile=tile, key_capacity=cap, out=out)
+    fwd(0)
+    torch.cuda.synchronize()
+    keys = int(rast.stats()["n_keys"])
+    cap = int(keys * 1.05) + 1024
+    gen = torch.Generator("cuda").manual_seed(3)
+    ups = [1e-6 * torch.randn(x.numel(), device="cuda", generator=gen) for x in out]
+    K = 16
+    g = dict(means=torch.empty(sc.n, 3, device="cuda"), log_scales=torch.empty(sc.n, 2, device="cuda"),
+             quats=torch.empty(sc.n, 4, device="cuda"), opacity=torch.empty(sc.n, device="cuda"),
+             sh=torch.empty(sc.n, K, 3, device="cuda"), twist=torch.empty(sc.n_frames, 6, device="cuda"))
+    reps = max(3, min(steps, 10))
+    ms_fwd = _event_ms(lambda: fwd(cap), reps)
+    fwd(cap)
+    ms_bwd = _event_ms(lambda: rast.backward_surfel(*ups, out=g), reps)
+    gd, ga, gn = (torch.zeros(P, device="cuda"), torch.zeros(P, device="cuda"),
+                  torch.zeros(3 * P, device="cuda"))
+    loss = torch.empty(1, device="cuda")
+    ms_nc = _event_ms(lambda: rast.normal_consistency(sc.cams, out[1], out[2], out[3], 0.05,
+                                                      gd, ga, gn, loss=loss), reps)
+    torch.cuda.synchronize()
+    ok = bool(torch.isfinite(g["means"]).all()) and float(out[2].max()) > 0.5
+    gbs = 60.0 * P / (ms_nc * 1e-3) / 1e9
+    res = {"keys_per_forward": keys, "forward_ms": round(ms_fwd, 4),
+           "backward_ms": round(ms_bwd, 4),
+           "fwd_bwd_Mpix_per_s": round(P / 1e6 / ((ms_fwd + ms_bwd) * 1e-3), 3),
+           "normal_consistency": {"ms": round(ms_nc, 4), "hbm_bytes": 60 * P,
+                                  "achieved_GBps": round(gbs, 1),
+                                  "frac_hbm": round(gbs / PEAK_HBM_GBS, 4)},
+           "finite_and_covered": ok}
+    log(f"[bench] surfels {res}")
+    return res
 
 
 def measured_traffic(kernel, tile):

@@ -99,6 +99,14 @@ void launch_mcmc_relocate(hipStream_t st, int64_t n, int ksh3, float* means, flo
                           float* quats, float* opac, float* sh, const int32_t* src,
                           uint32_t* cnt, double* rule);
 
+// The compositing tile schedule (raster.hip): `order` lists the tiles group
+// by group, longest first by `nproc` (entries a previous pass processed per
+// tile; spatial order if NULL); launch tile_schedule_grid() workgroups.
+void launch_tile_order(hipStream_t st, int n_tiles, int groups, const uint32_t* nproc,
+                       uint32_t* order);
+unsigned tile_schedule_grid(int n_tiles, int groups);
+int tile_schedule_groups(bool xcd_groups);
+
 // Sum of the per-wave twist partials [F][n_waves][6] into g_twist [F][6].
 void launch_twist_reduce(hipStream_t st, int F, const double* twist_partial, int64_t n_waves,
                          float* g_twist);
@@ -122,21 +130,28 @@ void launch_surfel_fwd(hipStream_t st, int tw, int th, int n_tiles, int F,
                        const FrameDesc* frames, const uint2* ranges, const uint32_t* vals,
                        const void* rec, const float* bg, float* rgb, float* depth, float* alpha,
                        float* normal, float* dist, float* t_final, int32_t* n_last,
-                       float* dist_aux);
+                       float* dist_aux, uint32_t* nproc, const uint32_t* prev_nproc,
+                       uint32_t* order, bool xcd_groups);
 void launch_surfel_bwd(hipStream_t st, int tw, int th, int n_tiles, int F,
                        const FrameDesc* frames, const uint2* ranges, const uint32_t* vals,
                        const void* rec, const uint2* trect, const uint32_t* keyoff,
                        const float* bg, const float* g_rgb, const float* g_depth,
                        const float* g_alpha, const float* g_normal, const float* g_dist,
                        const float* t_final, const int32_t* n_last, const float* dist_aux,
-                       float* partial, uint32_t* stamp, const uint32_t* epoch);
+                       float* partial, uint32_t* stamp, const uint32_t* epoch,
+                       const uint32_t* nproc, uint32_t* order, bool xcd_groups);
+// Per-record sums of the stamped key partials, records in `order` (sorted by
+// tile count so that a wave's groups do similar work): sgrad [m][values].
+void launch_surfel_slot_reduce(hipStream_t st, uint64_t m, const uint32_t* order,
+                               const uint32_t* keyoff, const uint32_t* ntiles,
+                               const float* partial, const uint32_t* stamp,
+                               const uint32_t* epoch, uint64_t key_capacity, double* sgrad);
 void launch_surfel_preprocess_bwd(hipStream_t st, int64_t n, int F, const FrameDesc* frames,
                                   const float* poses, const float* means,
                                   const float* log_scales, const float* quats,
                                   const float* opac, const float* sh, int deg,
                                   const uint32_t* ntiles, const uint32_t* keyoff,
-                                  const float* partial, const uint32_t* stamp,
-                                  const uint32_t* epoch, uint64_t key_capacity, float* g_means,
+                                  const double* sgrad, uint64_t key_capacity, float* g_means,
                                   float* g_log_scales, float* g_quats, float* g_opac,
                                   float* g_sh, double* twist_partial, float* g_twist);
 

@@ -32,6 +32,7 @@
 // backward's epoch so the per-record reduction can skip slots of keys that
 // no pixel reached.
 #include "launch.h"
+#include "wave_util.h"
 
 namespace gsr {
 
@@ -42,7 +43,6 @@ namespace gsr {
 // hardware dispatches workgroups in index order, so sorting each group by
 // descending expected work gives a longest-first list schedule without any
 // queue or atomic: long tiles start first and the short ones fill the tail.
-constexpr int kQueues = 8;
 constexpr int kOrderBins = 1024;
 
 __device__ __forceinline__ uint32_t work_bucket(uint32_t w) {
@@ -89,14 +89,6 @@ __global__ void __launch_bounds__(1024) tile_order_kernel(int n_tiles, int group
 }
 
 // The tile of workgroup `bid`, or -1 past the end of its group.
-__device__ __forceinline__ int tile_of_block(int bid, int n_tiles, int groups,
-                                             const uint32_t* __restrict__ order) {
-  const int per = (n_tiles + groups - 1) / groups;
-  const int q = bid % groups, i = bid / groups;
-  const int pos = q * per + i;
-  if (i >= per || pos >= n_tiles) return -1;
-  return (int)order[pos];
-}
 
 template <int TW, int TH, bool COUNT, bool MEDIAN>
 __device__ __forceinline__ void composite_fwd_tile(
@@ -204,48 +196,6 @@ __device__ __forceinline__ void composite_fwd_tile(
   }
 }
 
-// Cross-lane helpers of the FP64 wave reduction (all VALU, no LDS traffic).
-//
-// swap_sum<32>(a, b): with v_permlane32_swap the upper half-wave of a trades
-// places with the lower half-wave of b, so that afterwards a' + b' is
-// a(l) + a(l ^ 32) on lanes l < 32 and b(l ^ 32) + b(l) on lanes l >= 32: the
-// butterfly step over lane bit 5 that keeps a on the lower and b on the
-// upper half, in one swap and one add.  swap_sum<16> does the same over lane
-// bit 4 with v_permlane16_swap (odd 16-lane rows of a trade with even rows
-// of b).
-template <int W>
-__device__ __forceinline__ double swap_sum(double a, double b) {
-  const uint64_t ua = (uint64_t)__double_as_longlong(a), ub = (uint64_t)__double_as_longlong(b);
-  uint32_t lo0, lo1, hi0, hi1;
-  if constexpr (W == 32) {
-    const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)ua, (uint32_t)ub, false, false);
-    const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(ua >> 32), (uint32_t)(ub >> 32),
-                                                     false, false);
-    lo0 = lo[0]; lo1 = lo[1]; hi0 = hi[0]; hi1 = hi[1];
-  } else {
-    const auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)ua, (uint32_t)ub, false, false);
-    const auto hi = __builtin_amdgcn_permlane16_swap((uint32_t)(ua >> 32), (uint32_t)(ub >> 32),
-                                                     false, false);
-    lo0 = lo[0]; lo1 = lo[1]; hi0 = hi[0]; hi1 = hi[1];
-  }
-  return __longlong_as_double((long long)(((uint64_t)hi0 << 32) | lo0)) +
-         __longlong_as_double((long long)(((uint64_t)hi1 << 32) | lo1));
-}
-
-// The value of v on a partner lane inside the lane's 16-lane row: DPP row
-// mirror (partner 15 - l) for lane bit 3, half-row mirror (7 - l) for bit 2,
-// quad permutes (l ^ 2, l ^ 1) for bits 1 and 0.  The mirrors also flip the
-// lower lane bits; the rounds that follow sum over those anyway.
-template <int CTRL>
-__device__ __forceinline__ double dpp(double v) {
-  const uint64_t u = (uint64_t)__double_as_longlong(v);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, false);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf,
-                                                            0xf, false);
-  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-}
-constexpr int kDppRowMirror = 0x140, kDppHalfMirror = 0x141, kDppQuadXor2 = 0x4e,
-              kDppQuadXor1 = 0xb1;
 
 template <int TW, int TH, bool COUNT, bool MEDIAN>
 __global__ void __launch_bounds__(64) composite_fwd_kernel(
@@ -492,6 +442,14 @@ static void launch_order(hipStream_t st, int n_tiles, int groups, const uint32_t
 static unsigned grid_of(int n_tiles, int groups) {
   return (unsigned)(((n_tiles + groups - 1) / groups) * groups);
 }
+
+void launch_tile_order(hipStream_t st, int n_tiles, int groups, const uint32_t* nproc,
+                       uint32_t* order) {
+  if (n_tiles > 0) launch_order(st, n_tiles, groups, nproc, order);
+}
+
+unsigned tile_schedule_grid(int n_tiles, int groups) { return grid_of(n_tiles, groups); }
+int tile_schedule_groups(bool xcd_groups) { return xcd_groups ? kQueues : 1; }
 
 template <int TW, int TH, bool COUNT, bool MEDIAN>
 static void launch_fwd_v(hipStream_t st, int n_tiles, int groups, const uint32_t* order, int F,

@@ -54,7 +54,8 @@ struct gsr_context {
   DBuf ranges, nproc, t_final, n_last, frames, twist_part, loss_part, loss_scale;
   DBuf ssim_part, ssim_tiles, ssim_scale;  // rendering loss with SSIM
   DBuf med_pos;                     // per pixel: list position of the median-depth entry
-  DBuf dist_aux, spart;             // surfels: distortion sums per pixel, per-key partials
+  DBuf dist_aux, spart, sgrad;      // surfels: distortion sums per pixel, per-key and
+                                    // per-record gradient sums
   DBuf nc_part;                     // normal consistency: per-block loss partials
   DBuf reloc_cnt, reloc_rule;       // MCMC relocation scratch
   DBuf up_rgb, up_depth, up_alpha;  // upstream gradients for gsr_step_l1
@@ -270,7 +271,7 @@ gsr_status gsr_destroy(gsr_context* ctx) {
                   &ctx->reloc_cnt, &ctx->reloc_rule,
                   &ctx->up_rgb, &ctx->up_depth, &ctx->up_alpha, &ctx->tune_out,
                   &ctx->order_f, &ctx->order_b, &ctx->cls_a, &ctx->cls_b, &ctx->clsv_a,
-                  &ctx->clsv_b, &ctx->dist_aux, &ctx->spart, &ctx->nc_part};
+                  &ctx->clsv_b, &ctx->dist_aux, &ctx->spart, &ctx->sgrad, &ctx->nc_part};
   for (DBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (ctx->h_frames) (void)hipHostFree(ctx->h_frames);
@@ -468,7 +469,9 @@ gsr_status forward_impl(gsr_context* ctx, const gsr_settings* s, int64_t n, cons
     if (surfel)
       launch_surfel_fwd(st, tw, th, (int)T, F, P<FrameDesc>(ctx->frames), P<uint2>(ctx->ranges),
                         svals, ctx->rec.p, s->background, rgb, depth, alpha, normal, dist,
-                        P<float>(ctx->t_final), P<int32_t>(ctx->n_last), P<float>(ctx->dist_aux));
+                        P<float>(ctx->t_final), P<int32_t>(ctx->n_last), P<float>(ctx->dist_aux),
+                        P<uint32_t>(ctx->nproc), have_prev ? P<uint32_t>(ctx->nproc) : nullptr,
+                        P<uint32_t>(ctx->order_f), remap);
     else
       launch_composite_fwd(st, tw, th, (int)T, F, P<FrameDesc>(ctx->frames),
                            P<uint2>(ctx->ranges), svals, P<Record>(ctx->rec), s->background,
@@ -478,8 +481,7 @@ gsr_status forward_impl(gsr_context* ctx, const gsr_settings* s, int64_t n, cons
                            P<uint32_t>(ctx->order_f), remap, count ? d_pairs : nullptr,
                            median ? P<int32_t>(ctx->med_pos) : nullptr);
   }
-  // the surfel kernels leave nproc unset: no schedule from this forward
-  ctx->nproc_layout = surfel ? std::vector<int32_t>() : layout;
+  ctx->nproc_layout = layout;
   ctx->n_pairs = count ? -2 : -1;  // -2: count pending on the device
   GSR_HIP(hipGetLastError());
   Saved& sv = ctx->s;
@@ -578,7 +580,13 @@ gsr_status gsr_backward_surfel(gsr_context* ctx, const float* g_rgb, const float
   const gsr_settings& s = sv.set;
   gsr_status rc;
   const size_t ng = (size_t)surfel_grad_values();
+  const uint64_t M = (uint64_t)sv.n * sv.F;
   if ((rc = ensure(ctx, ctx->spart, std::max<uint64_t>(ctx->key_cap, 1) * ng * 4, st))) return rc;
+  if ((rc = ensure(ctx, ctx->sgrad, std::max<uint64_t>(M, 1) * ng * 8, st))) return rc;
+  if ((rc = ensure(ctx, ctx->cls_a, M * 4, st))) return rc;
+  if ((rc = ensure(ctx, ctx->cls_b, M * 4, st))) return rc;
+  if ((rc = ensure(ctx, ctx->clsv_a, M * 4, st))) return rc;
+  if ((rc = ensure(ctx, ctx->clsv_b, M * 4, st))) return rc;
   const int64_t waves = sv.n > 0 ? surfel_preprocess_bwd_waves(sv.n) : 0;
   if ((rc = ensure(ctx, ctx->twist_part, (size_t)std::max<int64_t>(waves, 1) * sv.F * 6 * 8, st)))
     return rc;
@@ -594,16 +602,28 @@ gsr_status gsr_backward_surfel(gsr_context* ctx, const float* g_rgb, const float
                       P<uint32_t>(ctx->keyoff), s.background, g_rgb, g_depth, g_alpha, g_normal,
                       g_dist, P<float>(ctx->t_final), P<int32_t>(ctx->n_last),
                       P<float>(ctx->dist_aux), P<float>(ctx->spart), P<uint32_t>(ctx->stamp),
-                      d_epoch);
+                      d_epoch, P<uint32_t>(ctx->nproc), P<uint32_t>(ctx->order_b),
+                      !(s.flags & GSR_FLAG_NO_XCD_REMAP));
   }
   {
     StageTimer t(ctx, st, timing, GSR_STAGE_PREPROCESS_BWD);
+    bool cls_in_b = false;
+    if (M > 0) {
+      launch_size_class(st, M, P<uint32_t>(ctx->ntiles), P<uint32_t>(ctx->cls_a),
+                        P<uint32_t>(ctx->clsv_a));
+      cls_in_b = launch_radix_sort(st, P<uint32_t>(ctx->cls_a), P<uint32_t>(ctx->clsv_a),
+                                   P<uint32_t>(ctx->cls_b), P<uint32_t>(ctx->clsv_b), nullptr, M,
+                                   8, P<uint32_t>(ctx->hist), P<uint32_t>(ctx->scan_tmp));
+    }
+    launch_surfel_slot_reduce(st, M, P<uint32_t>(cls_in_b ? ctx->clsv_b : ctx->clsv_a),
+                              P<uint32_t>(ctx->keyoff), P<uint32_t>(ctx->ntiles),
+                              P<float>(ctx->spart), P<uint32_t>(ctx->stamp), d_epoch,
+                              ctx->key_cap, P<double>(ctx->sgrad));
     launch_surfel_preprocess_bwd(st, sv.n, sv.F, P<FrameDesc>(ctx->frames), sv.poses, sv.means,
                                  sv.log_scales, sv.quats, sv.opac, sv.sh, s.sh_degree,
                                  P<uint32_t>(ctx->ntiles), P<uint32_t>(ctx->keyoff),
-                                 P<float>(ctx->spart), P<uint32_t>(ctx->stamp), d_epoch,
-                                 ctx->key_cap, g_means, g_log_scales, g_quats, g_opac, g_sh,
-                                 P<double>(ctx->twist_part), g_twist);
+                                 P<double>(ctx->sgrad), ctx->key_cap, g_means, g_log_scales,
+                                 g_quats, g_opac, g_sh, P<double>(ctx->twist_part), g_twist);
   }
   GSR_HIP(hipGetLastError());
   return GSR_OK;

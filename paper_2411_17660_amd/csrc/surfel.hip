@@ -32,6 +32,7 @@
 
 #include "launch.h"
 #include "sh_device.h"
+#include "wave_util.h"
 
 namespace gsr {
 
@@ -206,6 +207,7 @@ __device__ __forceinline__ SurfelHit surfel_eval(const Surfel& S, int px, int py
 
 template <int TW, int TH>
 __global__ void __launch_bounds__(64) surfel_fwd_kernel(
+    int n_tiles, int groups, const uint32_t* __restrict__ order, uint32_t* __restrict__ tile_nproc,
     int n_frames, const FrameDesc* __restrict__ frames, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ vals, const Surfel* __restrict__ rec, float bg0, float bg1,
     float bg2, float* __restrict__ rgb, float* __restrict__ depth, float* __restrict__ alpha,
@@ -214,7 +216,8 @@ __global__ void __launch_bounds__(64) surfel_fwd_kernel(
   constexpr int PIX = TW * TH / kWave;
   constexpr int RPP = kWave / TW;
   __shared__ Surfel sm[kWave];
-  const int tile = blockIdx.x;
+  const int tile = tile_of_block(blockIdx.x, n_tiles, groups, order);
+  if (tile < 0) return;
   const int f = frame_of_tile(frames, n_frames, tile);
   const FrameDesc fr = frames[f];
   const int lt = tile - fr.tile_offset;
@@ -283,6 +286,16 @@ __global__ void __launch_bounds__(64) surfel_fwd_kernel(
     }
     __syncthreads();
   }
+  // the tile's walk length for the backward and the next schedule: the
+  // largest list position any of its pixels blended
+  int most = 0;
+#pragma unroll
+  for (int k = 0; k < PIX; ++k) most = last[k] > most ? last[k] : most;
+  for (int o = 32; o > 0; o >>= 1) {
+    const int m = __shfl_xor(most, o, kWave);
+    most = m > most ? m : most;
+  }
+  if (lane == 0) tile_nproc[tile] = (uint32_t)most;
   const int64_t plane = (int64_t)fr.width * fr.height;
 #pragma unroll
   for (int k = 0; k < PIX; ++k) {
@@ -310,52 +323,6 @@ __global__ void __launch_bounds__(64) surfel_fwd_kernel(
   }
 }
 
-// Sum over the wave of N values per lane, FP64, by recursive halving: at
-// lane bit b a lane keeps the lower or upper half of its values (by that
-// bit) and adds its partner's copy of the same half, so after six rounds each
-// of the N totals sits on exactly one lane.  Returns that lane's total, its
-// index idx and writer = true on the N lanes that hold one (the rest hold
-// padding).
-template <int C, int B>
-__device__ __forceinline__ void halve(const double* in, double* out, int lane, int& base,
-                                      int& cnt) {
-  constexpr int H = (C + 1) / 2;
-  const bool hi = (lane >> B) & 1;
-#pragma unroll
-  for (int j = 0; j < H; ++j) {
-    const double lo_v = in[j];
-    const double hi_v = (H + j < C) ? in[H + j] : 0.0;
-    const double keep = hi ? hi_v : lo_v;
-    const double send = hi ? lo_v : hi_v;
-    out[j] = keep + __shfl_xor(send, 1 << B, kWave);
-  }
-  if (hi) {
-    base += H;
-    cnt = cnt > H ? cnt - H : 0;
-  } else {
-    cnt = cnt < H ? cnt : H;
-  }
-}
-
-template <int N>
-__device__ __forceinline__ double wave_transpose_sum(const double (&v)[N], int lane, int& idx,
-                                                     bool& writer) {
-  static_assert(N >= 1 && N <= kWave, "one total per lane");
-  constexpr int C5 = N, C4 = (C5 + 1) / 2, C3 = (C4 + 1) / 2, C2 = (C3 + 1) / 2,
-                C1 = (C2 + 1) / 2, C0 = (C1 + 1) / 2;
-  double r4[C4], r3[C3], r2[C2], r1[C1], r0[C0], rr[(C0 + 1) / 2];
-  int base = 0, cnt = N;
-  halve<C5, 5>(v, r4, lane, base, cnt);
-  halve<C4, 4>(r4, r3, lane, base, cnt);
-  halve<C3, 3>(r3, r2, lane, base, cnt);
-  halve<C2, 2>(r2, r1, lane, base, cnt);
-  halve<C1, 1>(r1, r0, lane, base, cnt);
-  halve<C0, 0>(r0, rr, lane, base, cnt);
-  idx = base;
-  writer = cnt > 0;
-  return rr[0];
-}
-
 // Per key (one surfel in one tile), the values the backward reduces, in this
 // order: S_hu[3] = sum dL/dh_u, S_hv[3] = sum dL/dh_v, G_M2[3] = the direct
 // gradient of M2 = sum (x - c_x) dL/dh_u + (y - c_y) dL/dh_v + dL/dz (u, v, 1),
@@ -365,6 +332,8 @@ constexpr int kSG = 18;
 
 template <int TW, int TH>
 __global__ void __launch_bounds__(64) surfel_bwd_kernel(
+    int n_tiles, int groups, const uint32_t* __restrict__ order,
+    const uint32_t* __restrict__ tile_nproc,
     int n_frames, const FrameDesc* __restrict__ frames, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ vals, const Surfel* __restrict__ rec,
     const uint2* __restrict__ trect, const uint32_t* __restrict__ keyoff, float bg0, float bg1,
@@ -378,8 +347,11 @@ __global__ void __launch_bounds__(64) surfel_bwd_kernel(
   constexpr int RPP = kWave / TW;
   __shared__ Surfel sm[kWave];
   __shared__ uint32_t slot[kWave];
+  const int tile = tile_of_block(blockIdx.x, n_tiles, groups, order);
+  if (tile < 0) return;
+  const int most = (int)tile_nproc[tile];
+  if (most == 0) return;
   const uint32_t epoch = *epoch_dev;
-  const int tile = blockIdx.x;
   const int f = frame_of_tile(frames, n_frames, tile);
   const FrameDesc fr = frames[f];
   const int lt = tile - fr.tile_offset;
@@ -398,7 +370,6 @@ __global__ void __launch_bounds__(64) surfel_bwd_kernel(
   double BC0[PIX], BC1[PIX], BC2[PIX], BD[PIX], BN0[PIX], BN1[PIX], BN2[PIX], BE[PIX];
   float G0[PIX], G1[PIX], G2[PIX], GD[PIX], GA[PIX], GN0[PIX], GN1[PIX], GN2[PIX], GE[PIX];
   int last[PIX];
-  int most = 0;
 #pragma unroll
   for (int k = 0; k < PIX; ++k) {
     const int py = y0 + k * RPP + ly;
@@ -406,7 +377,6 @@ __global__ void __launch_bounds__(64) surfel_bwd_kernel(
     const int64_t p = (int64_t)py * fr.width + px;
     const int64_t q = fr.pixel_offset + p;
     last[k] = valid ? n_last[q] : 0;
-    most = last[k] > most ? last[k] : most;
     T[k] = valid ? t_final[q] : 1.0f;
     AT[k] = 1.0f - T[k];
     ZR[k] = valid ? dist_aux[3 * q] : 0.0f;
@@ -427,10 +397,6 @@ __global__ void __launch_bounds__(64) surfel_bwd_kernel(
     GA[k] = valid ? g_alpha[q] : 0.0f;
     GE[k] = valid ? g_dist[q] : 0.0f;
   }
-  for (int o = 32; o > 0; o >>= 1) {
-    const int m = __shfl_xor(most, o, kWave);
-    most = m > most ? m : most;
-  }
   for (int hi = most; hi > 0; hi -= kWave) {
     const int lo = hi > kWave ? hi - kWave : 0;
     if (lo + lane < hi) {
@@ -447,9 +413,11 @@ __global__ void __launch_bounds__(64) surfel_bwd_kernel(
       const int xlo = S.sqx & 0xffff, xhi = S.sqx >> 16;
       const int ylo = S.sqy & 0xffff, yhi = S.sqy >> 16;
       const bool xin = (unsigned)(px - xlo) <= (unsigned)(xhi - xlo);
-      double acc[kSG];
+      // the lane's own pixels sum in FP32; the lanes' sums, which cancel
+      // against each other, in FP64
+      float acc[kSG];
 #pragma unroll
-      for (int i = 0; i < kSG; ++i) acc[i] = 0.0;
+      for (int i = 0; i < kSG; ++i) acc[i] = 0.0f;
       bool any = false;
 #pragma unroll
       for (int k = 0; k < PIX; ++k) {
@@ -520,9 +488,9 @@ __global__ void __launch_bounds__(64) surfel_bwd_kernel(
           acc[4] += b1;
           acc[5] += b2;
           // h_u = (x - c_x) M2 + k_u, h_v = (y - c_y) M2 + k_v
-          acc[6] += (double)h.ex * a0 + (double)h.ey * b0;
-          acc[7] += (double)h.ex * a1 + (double)h.ey * b1;
-          acc[8] += (double)h.ex * a2 + (double)h.ey * b2;
+          acc[6] += h.ex * a0 + h.ey * b0;
+          acc[7] += h.ex * a1 + h.ey * b1;
+          acc[8] += h.ex * a2 + h.ey * b2;
         } else {
           // the low-pass: z = z_c, G_lp = exp(-|(x, y) - c|^2)
           acc[8] += dzv;
@@ -532,9 +500,12 @@ __global__ void __launch_bounds__(64) surfel_bwd_kernel(
         }
       }
       if (__ballot(any) == 0) continue;
+      double accd[kSG];
+#pragma unroll
+      for (int i = 0; i < kSG; ++i) accd[i] = acc[i];
       int idx;
       bool writer;
-      const double tot = wave_transpose_sum<kSG>(acc, lane, idx, writer);
+      const double tot = wave_transpose_sum<kSG>(accd, lane, idx, writer);
       const uint32_t sl = slot[j];
       if (writer) partial[(size_t)sl * kSG + idx] = (float)tot;
       if (lane == 0) stamp[sl] = epoch;
@@ -548,9 +519,51 @@ __device__ __forceinline__ double wave_sum_d(double v) {
   return v;
 }
 
+// Per record (surfel, frame): the sum of its keys' partials that this
+// backward stamped, FP64.  A group of kSlotGroup lanes shares a record; the
+// records come in order of tile count, so the groups of one wave walk lists
+// of similar length.
+constexpr int kSlotGroup = 8;
+
+__global__ void __launch_bounds__(256) surfel_slot_reduce_kernel(
+    uint64_t m, const uint32_t* __restrict__ order, const uint32_t* __restrict__ keyoff,
+    const uint32_t* __restrict__ ntiles, const float* __restrict__ partial,
+    const uint32_t* __restrict__ stamp, const uint32_t* __restrict__ epoch_dev,
+    uint64_t key_capacity, double* __restrict__ sgrad /* [m][kSG] */) {
+  const uint32_t epoch = *epoch_dev;
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t k = gid / kSlotGroup;
+  const int sub = threadIdx.x & (kSlotGroup - 1);
+  const bool active = k < m;
+  const uint64_t r = active ? order[k] : 0;
+  uint32_t cnt = active ? ntiles[r] : 0u;
+  const uint32_t off = cnt ? keyoff[r] : 0u;
+  if (cnt && (uint64_t)off + cnt > key_capacity) cnt = 0;  // overflowed in keygen
+  double acc[kSG];
+#pragma unroll
+  for (int j = 0; j < kSG; ++j) acc[j] = 0.0;
+  for (uint32_t s = sub; s < cnt; s += kSlotGroup) {
+    if (stamp[off + s] != epoch) continue;
+    const float* pp = partial + (size_t)(off + s) * kSG;
+#pragma unroll
+    for (int j = 0; j < kSG; ++j) acc[j] += pp[j];
+  }
+#pragma unroll
+  for (int o = kSlotGroup / 2; o > 0; o >>= 1)
+#pragma unroll
+    for (int j = 0; j < kSG; ++j) acc[j] += __shfl_xor(acc[j], o, kSlotGroup);
+  if (!active || !ntiles[r]) return;
+#pragma unroll
+  for (int j0 = 0; j0 < kSG; j0 += kSlotGroup) {
+    double v = acc[j0];
+#pragma unroll
+    for (int j = j0 + 1; j < j0 + kSlotGroup && j < kSG; ++j) v = sub == j - j0 ? acc[j] : v;
+    if (j0 + sub < kSG) sgrad[r * kSG + j0 + sub] = v;
+  }
+}
+
 // Chain rule from the per-key sums to the parameters (FP64), per surfel and
-// frame: the key sums of the frame's keys (those stamped by this backward)
-// give dL/dM (M0 = -S_hu, M1 = -S_hv, M2 = G_M2 + c_x S_hu + c_y S_hv from
+// frame: the record's sum of its key partials gives dL/dM (M0 = -S_hu, M1 = -S_hv, M2 = G_M2 + c_x S_hu + c_y S_hv from
 // h_u = x M2 - M0, plus the low-pass term through c = (M0_z, M1_z) / M2_z),
 // then the columns of M = K [A | B | mc]: A = s_u t_u, B = s_v t_v,
 // mc = R_f mu + t_f, t_u, t_v, t_w the camera-frame axes R_f R_g.  The pose
@@ -563,12 +576,10 @@ __global__ void __launch_bounds__(256) surfel_preprocess_bwd_kernel(
     const float* __restrict__ log_scales, const float* __restrict__ quats,
     const float* __restrict__ opac, const float* __restrict__ sh,
     const uint32_t* __restrict__ ntiles, const uint32_t* __restrict__ keyoff,
-    const float* __restrict__ partial, const uint32_t* __restrict__ stamp,
-    const uint32_t* __restrict__ epoch_dev, uint64_t key_capacity, float* __restrict__ g_means,
+    const double* __restrict__ sgrad, uint64_t key_capacity, float* __restrict__ g_means,
     float* __restrict__ g_log_scales, float* __restrict__ g_quats, float* __restrict__ g_opac,
     float* __restrict__ g_sh, double* __restrict__ twist_partial /* [F][n_waves][6] */) {
 #pragma clang fp contract(off)
-  const uint32_t epoch = *epoch_dev;
   const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool active = g0 < n;
   const int64_t g = active ? g0 : 0;
@@ -601,12 +612,7 @@ __global__ void __launch_bounds__(256) surfel_preprocess_bwd_kernel(
     if (cnt && (uint64_t)off + cnt > key_capacity) cnt = 0;  // overflowed in keygen
     if (cnt > 0) {
       double K[kSG];
-      for (int i = 0; i < kSG; ++i) K[i] = 0.0;
-      for (uint32_t sl = off; sl < off + cnt; ++sl) {
-        if (stamp[sl] != epoch) continue;
-        const float* pp = partial + (size_t)sl * kSG;
-        for (int i = 0; i < kSG; ++i) K[i] += pp[i];
-      }
+      for (int i = 0; i < kSG; ++i) K[i] = sgrad[r * kSG + i];
       const FrameDesc fr = frames[f];
       double W[9], tf[3];
       load_pose(poses, f, W, tf);
@@ -741,12 +747,16 @@ void launch_surfel_fwd(hipStream_t st, int tw, int th, int n_tiles, int F,
                        const FrameDesc* frames, const uint2* ranges, const uint32_t* vals,
                        const void* rec, const float* bg, float* rgb, float* depth, float* alpha,
                        float* normal, float* dist, float* t_final, int32_t* n_last,
-                       float* dist_aux) {
+                       float* dist_aux, uint32_t* nproc, const uint32_t* prev_nproc,
+                       uint32_t* order, bool xcd_groups) {
   if (n_tiles <= 0) return;
+  const int groups = tile_schedule_groups(xcd_groups);
+  launch_tile_order(st, n_tiles, groups, prev_nproc, order);
+  const dim3 grid(tile_schedule_grid(n_tiles, groups));
 #define GSR_SURF_FWD(W, H)                                                                  \
-  hipLaunchKernelGGL((surfel_fwd_kernel<W, H>), dim3((unsigned)n_tiles), dim3(kWave), 0, st, \
-                     F, frames, ranges, vals, (const Surfel*)rec, bg[0], bg[1], bg[2], rgb,  \
-                     depth, alpha, normal, dist, t_final, n_last, dist_aux)
+  hipLaunchKernelGGL((surfel_fwd_kernel<W, H>), grid, dim3(kWave), 0, st, n_tiles, groups,   \
+                     order, nproc, F, frames, ranges, vals, (const Surfel*)rec, bg[0],       \
+                     bg[1], bg[2], rgb, depth, alpha, normal, dist, t_final, n_last, dist_aux)
   if (tw == 16 && th == 16) GSR_SURF_FWD(16, 16);
   else if (tw == 8 && th == 8) GSR_SURF_FWD(8, 8);
   else if (tw == 32 && th == 8) GSR_SURF_FWD(32, 8);
@@ -761,13 +771,17 @@ void launch_surfel_bwd(hipStream_t st, int tw, int th, int n_tiles, int F,
                        const float* bg, const float* g_rgb, const float* g_depth,
                        const float* g_alpha, const float* g_normal, const float* g_dist,
                        const float* t_final, const int32_t* n_last, const float* dist_aux,
-                       float* partial, uint32_t* stamp, const uint32_t* epoch) {
+                       float* partial, uint32_t* stamp, const uint32_t* epoch,
+                       const uint32_t* nproc, uint32_t* order, bool xcd_groups) {
   if (n_tiles <= 0) return;
+  const int groups = tile_schedule_groups(xcd_groups);
+  launch_tile_order(st, n_tiles, groups, nproc, order);
+  const dim3 grid(tile_schedule_grid(n_tiles, groups));
 #define GSR_SURF_BWD(W, H)                                                                   \
-  hipLaunchKernelGGL((surfel_bwd_kernel<W, H>), dim3((unsigned)n_tiles), dim3(kWave), 0, st,  \
-                     F, frames, ranges, vals, (const Surfel*)rec, trect, keyoff, bg[0], bg[1], \
-                     bg[2], g_rgb, g_depth, g_alpha, g_normal, g_dist, t_final, n_last,       \
-                     dist_aux, partial, stamp, epoch)
+  hipLaunchKernelGGL((surfel_bwd_kernel<W, H>), grid, dim3(kWave), 0, st, n_tiles, groups,    \
+                     order, nproc, F, frames, ranges, vals, (const Surfel*)rec, trect, keyoff, \
+                     bg[0], bg[1], bg[2], g_rgb, g_depth, g_alpha, g_normal, g_dist, t_final,  \
+                     n_last, dist_aux, partial, stamp, epoch)
   if (tw == 16 && th == 16) GSR_SURF_BWD(16, 16);
   else if (tw == 8 && th == 8) GSR_SURF_BWD(8, 8);
   else if (tw == 32 && th == 8) GSR_SURF_BWD(32, 8);
@@ -776,22 +790,31 @@ void launch_surfel_bwd(hipStream_t st, int tw, int th, int n_tiles, int F,
 #undef GSR_SURF_BWD
 }
 
+void launch_surfel_slot_reduce(hipStream_t st, uint64_t m, const uint32_t* order,
+                               const uint32_t* keyoff, const uint32_t* ntiles,
+                               const float* partial, const uint32_t* stamp,
+                               const uint32_t* epoch, uint64_t key_capacity, double* sgrad) {
+  if (m == 0) return;
+  const uint64_t threads = m * kSlotGroup;
+  hipLaunchKernelGGL(surfel_slot_reduce_kernel, dim3((unsigned)((threads + 255) / 256)),
+                     dim3(256), 0, st, m, order, keyoff, ntiles, partial, stamp, epoch,
+                     key_capacity, sgrad);
+}
+
 void launch_surfel_preprocess_bwd(hipStream_t st, int64_t n, int F, const FrameDesc* frames,
                                   const float* poses, const float* means,
                                   const float* log_scales, const float* quats,
                                   const float* opac, const float* sh, int deg,
                                   const uint32_t* ntiles, const uint32_t* keyoff,
-                                  const float* partial, const uint32_t* stamp,
-                                  const uint32_t* epoch, uint64_t key_capacity, float* g_means,
+                                  const double* sgrad, uint64_t key_capacity, float* g_means,
                                   float* g_log_scales, float* g_quats, float* g_opac,
                                   float* g_sh, double* twist_partial, float* g_twist) {
   if (n > 0) {
     const dim3 grid((unsigned)((n + 255) / 256));
 #define GSR_SURF_PRE_BWD(D)                                                                   \
   hipLaunchKernelGGL(surfel_preprocess_bwd_kernel<D>, grid, dim3(256), 0, st, n, F, frames,  \
-                     poses, means, log_scales, quats, opac, sh, ntiles, keyoff, partial,       \
-                     stamp, epoch, key_capacity, g_means, g_log_scales, g_quats, g_opac, g_sh, \
-                     twist_partial)
+                     poses, means, log_scales, quats, opac, sh, ntiles, keyoff, sgrad,         \
+                     key_capacity, g_means, g_log_scales, g_quats, g_opac, g_sh, twist_partial)
     switch (deg) {
       case 0: GSR_SURF_PRE_BWD(0); break;
       case 1: GSR_SURF_PRE_BWD(1); break;

@@ -172,8 +172,15 @@ __global__ void __launch_bounds__(256) surfel_preprocess_kernel(
 struct SurfelHit {
   float Gh, z;
   bool obj;       // the disk term (not the low-pass) is the larger
-  float u, v, p2, hux, huy, huz, hvx, hvy, hvz, ex, ey;  // kept for the backward
+  float u, v, ip2, hux, huy, huz, hvx, hvy, hvz, ex, ey;  // kept for the backward
 };
+
+// ln 255 rounded up: beyond this squared distance from the centre the
+// low-pass term is below 1/255, so alpha = sigma G_lp < 1/255 there and it
+// can never be blended; skipping its exp leaves every decision unchanged
+// (where G >= G_lp the disk term is taken either way, and where G < G_lp
+// alpha < 1/255 either way).
+constexpr float kLowpassReach = 5.6f;
 
 __device__ __forceinline__ SurfelHit surfel_eval(const Surfel& S, int px, int py) {
 #pragma clang fp contract(off)
@@ -188,17 +195,21 @@ __device__ __forceinline__ SurfelHit surfel_eval(const Surfel& S, int px, int py
   h.hvz = h.ey * S.zc;
   const float p0 = h.huy * h.hvz - h.huz * h.hvy;
   const float p1 = h.huz * h.hvx - h.hux * h.hvz;
-  h.p2 = h.hux * h.hvy - h.huy * h.hvx;
+  const float p2 = h.hux * h.hvy - h.huy * h.hvx;
   float G = 0.0f;
   h.u = 0.0f;
   h.v = 0.0f;
-  if (h.p2 != 0.0f) {
-    const float inv = 1.0f / h.p2;
-    h.u = p0 * inv;
-    h.v = p1 * inv;
+  h.ip2 = 0.0f;
+  if (p2 != 0.0f) {
+    // reciprocal with one Newton step (within an ulp or so of 1/p2)
+    const float r0 = __builtin_amdgcn_rcpf(p2);
+    h.ip2 = __builtin_fmaf(__builtin_fmaf(-p2, r0, 1.0f), r0, r0);
+    h.u = p0 * h.ip2;
+    h.v = p1 * h.ip2;
     G = gauss_of(h.u * h.u + h.v * h.v);
   }
-  const float Glp = gauss_of(2.0f * (h.ex * h.ex + h.ey * h.ey));
+  const float d2 = h.ex * h.ex + h.ey * h.ey;
+  const float Glp = d2 < kLowpassReach ? gauss_of(2.0f * d2) : 0.0f;
   h.obj = G >= Glp;
   h.Gh = h.obj ? G : Glp;
   h.z = h.obj ? (S.m2x * h.u + S.m2y * h.v + S.zc) : S.zc;
@@ -474,7 +485,7 @@ __global__ void __launch_bounds__(64) surfel_bwd_kernel(
           acc[6] += h.u * dzv;
           acc[7] += h.v * dzv;
           acc[8] += dzv;
-          const float ip = 1.0f / h.p2;
+          const float ip = h.ip2;
           const float dp0 = gu * ip, dp1 = gv * ip, dp2 = -(gu * h.u + gv * h.v) * ip;
           // p = h_u x h_v: dL/dh_u = h_v x dL/dp, dL/dh_v = dL/dp x h_u
           const float a0 = h.hvy * dp2 - h.hvz * dp1, a1 = h.hvz * dp0 - h.hvx * dp2,

@@ -149,10 +149,11 @@ gsr_status gsr_forward(gsr_context* ctx, const gsr_settings* settings, int64_t n
  * camera) and dist [sum_f H_f W_f], the depth distortion of the surfel
  * objective (the L_dist term the supplementary's Rendering settings add for
  * 2D Gaussian Splatting): per pixel the sum over pairs i < j of blended
- * entries of w_i w_j (z_i - z_j)^2.  A surfel covers the pixel box of the
- * projected corners of |u|, |v| <= sqrt(2 ln(255 sigma)) united with the
+ * entries of w_i w_j (z_i - z_j)^2.  A surfel covers the bounding box of
+ * the image of the disk |(u, v)| <= sqrt(2 ln(255 sigma)) united with the
  * square of half width sqrt(ln(255 sigma)) around c, and is culled when
- * sigma <= 1/255 or the centre or a corner is not beyond the near plane.
+ * sigma <= 1/255 or the centre or the disk's nearest point is not beyond
+ * the near plane.
  * GSR_FLAG_MEDIAN_DEPTH and GSR_FLAG_COUNT_PAIRS are not supported
  * (GSR_ERR_UNSUPPORTED).  All output pointers are device memory, 4-byte
  * aligned; GSR_ERR_INVALID_ARGUMENT if normal or dist is NULL.  gsr_backward

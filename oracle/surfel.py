@@ -25,12 +25,13 @@ where the paper is silent (design notes, reading 18):
     front to back in order of (fp32(centre depth) bits, index), as for the
     3D Gaussians;
   - a surfel contributes only inside its pixel box: the bounding box of the
-    projected corners of the square |u|, |v| <= r_a (r_a = sqrt(2 ln(255
-    sigma)), outside which G < 1/(255 sigma)) united with the square of half
-    width sqrt(ln(255 sigma)) around c (where G_lp can reach it), as
-    [ceil(lo), floor(hi)] clipped to the image; culled if sigma <= 1/255,
-    if the centre or a corner is not in front of the near plane, or if the
-    box is empty;
+    image of the disk |(u, v)| <= r_a (r_a = sqrt(2 ln(255 sigma)), outside
+    which G < 1/(255 sigma)), from the dual conic M diag(r_a^2, r_a^2, -1)
+    M^T, united with the square of half width sqrt(ln(255 sigma)) around c
+    (where G_lp can reach it), as [ceil(lo), floor(hi)] clipped to the
+    image; culled if sigma <= 1/255, if the centre or the disk's nearest
+    point (depth z_c - r_a |(M2_0, M2_1)|) is not in front of the near
+    plane, or if the box is empty;
   - outputs: RGB (+ T_final * background), depth sum_i w_i z_i, alpha
     1 - T_final and normal sum_i w_i n_i with n_i = R_f t_w turned to face
     the camera (n . (R_f mu + t_f) < 0), in camera coordinates;
@@ -154,24 +155,27 @@ def render(means, log_scales, quats, opacity_logits, sh, sh_degree, cams, poses,
                 zc = float(mc[g, 2])
                 if not (o > A_MIN) or not (zc > near):
                     continue
-                ra = math.sqrt(2.0 * math.log(o / A_MIN))
+                r2 = 2.0 * math.log(o / A_MIN)          # r_a^2
+                ra = math.sqrt(r2)
                 rl = math.sqrt(math.log(o / A_MIN))
-                Mg = M[g].detach().numpy()
-                pts = []
-                ok = True
-                for a_ in (-ra, ra):
-                    for b_ in (-ra, ra):
-                        hp = Mg @ np.array([a_, b_, 1.0])
-                        if not (hp[2] > near):
-                            ok = False
-                        else:
-                            pts.append(hp[:2] / hp[2])
-                if not ok:
+                m = [[float(M[g, i, j]) for j in range(3)] for i in range(3)]
+                # the disk's nearest point to the camera plane
+                if not (m[2][2] - ra * math.sqrt(m[2][0] * m[2][0] + m[2][1] * m[2][1]) > near):
                     continue
-                pts = np.array(pts)
+                # bounding box of the image of the circle |(u, v)| = r_a: its dual
+                # conic is C* = M diag(r_a^2, r_a^2, -1) M^T, and the vertical
+                # tangents x = x0 solve C*_00 - 2 x0 C*_02 + x0^2 C*_22 = 0
+                def dual(i, j):
+                    return r2 * (m[i][0] * m[j][0] + m[i][1] * m[j][1]) - m[i][2] * m[j][2]
+                c22 = dual(2, 2)
+                ext = []
+                for i in (0, 1):
+                    ci2, cii = dual(i, 2), dual(i, i)
+                    sq = math.sqrt(max(ci2 * ci2 - cii * c22, 0.0))
+                    ext.append(((ci2 + sq) / c22, (ci2 - sq) / c22))
                 c0 = ctr[g].detach().numpy()
-                lo = np.minimum(pts.min(0), c0 - rl)
-                hi = np.maximum(pts.max(0), c0 + rl)
+                lo = [min(ext[i][0], ext[i][1], c0[i] - rl) for i in (0, 1)]
+                hi = [max(ext[i][0], ext[i][1], c0[i] + rl) for i in (0, 1)]
                 x_lo, x_hi = max(0, math.ceil(lo[0])), min(W - 1, math.floor(hi[0]))
                 y_lo, y_hi = max(0, math.ceil(lo[1])), min(H - 1, math.floor(hi[1]))
                 if x_lo <= x_hi and y_lo <= y_hi:

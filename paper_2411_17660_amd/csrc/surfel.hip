@@ -24,10 +24,11 @@
 // w_i w_j (z_i - z_j)^2; the forward adds w_j (A z_j^2 - 2 z_j D_1 + D_2) per
 // entry, A, D_1, D_2 the sums of w, w z, w z^2 in front of it, with every z
 // taken relative to the pixel's first blended entry so that the FP32 sums
-// stay near the spread of the depths rather than their size.  A surfel covers the
-// pixel box of the projected corners of |u|, |v| <= sqrt(2 ln(255 sigma))
-// united with the square of half width sqrt(ln(255 sigma)) around c; the
-// box's integer bounds are taken in FP64.
+// stay near the spread of the depths rather than their size.  A surfel covers
+// the bounding box of the image of the disk |(u, v)| <= sqrt(2 ln(255 sigma))
+// (exact, from the disk's dual conic) united with the square of half width
+// sqrt(ln(255 sigma)) around c, and is culled unless the disk lies beyond the
+// near plane; the box's integer bounds are taken in FP64.
 #include <cstddef>
 
 #include "launch.h"
@@ -97,26 +98,28 @@ __global__ void __launch_bounds__(256) surfel_preprocess_kernel(
     const double M1[3] = {fy * A[1] + cy * A[2], fy * B[1] + cy * B[2], fy * mc[1] + cy * mc[2]};
     const double M2[3] = {A[2], B[2], mc[2]};
     const double ccx = M0[2] / M2[2], ccy = M1[2] / M2[2];
-    const double ra = sqrt(2.0 * log(o / amin)), rl = sqrt(log(o / amin));
-    double lox = ccx - rl, hix = ccx + rl, loy = ccy - rl, hiy = ccy + rl;
-    bool ok = true;
-    for (int ia = 0; ia < 2; ++ia)
-      for (int ib = 0; ib < 2; ++ib) {
-        const double uu = ia ? ra : -ra, vv = ib ? ra : -ra;
-        const double hx = M0[0] * uu + M0[1] * vv + M0[2];
-        const double hy = M1[0] * uu + M1[1] * vv + M1[2];
-        const double hz = M2[0] * uu + M2[1] * vv + M2[2];
-        if (!(hz > near)) {
-          ok = false;
-          continue;
-        }
-        const double px = hx / hz, py = hy / hz;
-        lox = px < lox ? px : lox;
-        hix = px > hix ? px : hix;
-        loy = py < loy ? py : loy;
-        hiy = py > hiy ? py : hiy;
-      }
-    if (!ok) continue;
+    const double r2 = 2.0 * log(o / amin);  // r_a^2
+    const double ra = sqrt(r2), rl = sqrt(log(o / amin));
+    // the disk's nearest point to the camera plane must be beyond the near plane
+    if (!(M2[2] - ra * sqrt(M2[0] * M2[0] + M2[1] * M2[1]) > near)) continue;
+    // bounding box of the image of the circle |(u, v)| = r_a: the dual conic
+    // C* = M diag(r_a^2, r_a^2, -1) M^T has the vertical tangents x = x0 with
+    // C*_00 - 2 x0 C*_02 + x0^2 C*_22 = 0 (and likewise in y)
+    const double c22 = r2 * (M2[0] * M2[0] + M2[1] * M2[1]) - M2[2] * M2[2];
+    const double c02 = r2 * (M0[0] * M2[0] + M0[1] * M2[1]) - M0[2] * M2[2];
+    const double c00 = r2 * (M0[0] * M0[0] + M0[1] * M0[1]) - M0[2] * M0[2];
+    const double c12 = r2 * (M1[0] * M2[0] + M1[1] * M2[1]) - M1[2] * M2[2];
+    const double c11 = r2 * (M1[0] * M1[0] + M1[1] * M1[1]) - M1[2] * M1[2];
+    const double dx = c02 * c02 - c00 * c22, dy = c12 * c12 - c11 * c22;
+    const double sx = sqrt(dx > 0.0 ? dx : 0.0), sy = sqrt(dy > 0.0 ? dy : 0.0);
+    const double xa = (c02 + sx) / c22, xb = (c02 - sx) / c22;
+    const double ya = (c12 + sy) / c22, yb = (c12 - sy) / c22;
+    double lox = xa < xb ? xa : xb, hix = xa < xb ? xb : xa;
+    double loy = ya < yb ? ya : yb, hiy = ya < yb ? yb : ya;
+    lox = ccx - rl < lox ? ccx - rl : lox;
+    hix = ccx + rl > hix ? ccx + rl : hix;
+    loy = ccy - rl < loy ? ccy - rl : loy;
+    hiy = ccy + rl > hiy ? ccy + rl : hiy;
     const double xl = ceil(lox), xh = floor(hix), yl = ceil(loy), yh = floor(hiy);
     const int x_lo = xl > 0.0 ? (int)xl : 0;
     const int y_lo = yl > 0.0 ? (int)yl : 0;

@@ -8,6 +8,9 @@ than itself (no GPU).
 - any pose and rotation: (u, v) and the depth equal a ray-plane
   intersection computed geometrically (ray K^-1 (x, y, 1), the disk's plane
   through its centre with its normal, coordinates along its axes);
+- the pixel box is the bounding box of the disk of radius r_a sampled along
+  its boundary and projected, united with the low-pass square; a disk whose
+  nearest point passes the near plane is culled;
 - an edge-on surfel: the object-space Gaussian vanishes off its line and the
   screen-space low-pass exp(-|x - c|^2) sets alpha;
 - layered "over" of two surfels and their order; zero opacity; permutation;
@@ -127,6 +130,59 @@ def test_ray_plane_intersection_any_pose(seed):
             assert abs(depth[y, x] - a * P[2]) < 1e-12
             checked += 1
     assert checked > 20
+
+
+@pytest.mark.parametrize("seed", [4, 5, 6, 7])
+def test_box_is_the_bounding_box_of_the_projected_disk(seed):
+    """The pixel box is [ceil, floor] of the extremes of the disk of radius
+    r_a = sqrt(2 ln(255 sigma)) mapped to the image (sampled densely along
+    its boundary), united with the low-pass square around the centre; a
+    tilted disk whose nearest point passes the near plane is culled."""
+    rng = np.random.default_rng(seed)
+    W, H, f, cx, cy, near = 200, 160, 90.0, 99.4, 80.7, 0.2
+    n = 12
+    mu = np.stack([rng.uniform(-0.8, 0.8, n), rng.uniform(-0.6, 0.6, n),
+                   rng.uniform(1.0, 3.0, n)], 1)
+    q = rng.normal(size=(n, 4))
+    ls = np.log(rng.uniform(0.05, 0.3, (n, 2)))
+    lo = rng.normal(0, 1.5, n)
+    out = _render(mu, ls, q, lo, np.full((n, 1, 3), 0.3), 0, [(W, H, f, f, cx, cy, near)],
+                  _ident())[0]
+    th = np.linspace(0, 2 * np.pi, 40001)
+    K = np.array([[f, 0, cx], [0, f, cy], [0, 0, 1.0]])
+    checked = 0
+    for g in range(n):
+        o = 1 / (1 + math.exp(-lo[g]))
+        if o <= S.A_MIN:
+            assert out["box"][g, 0] < 0
+            continue
+        ra = math.sqrt(2 * math.log(o / S.A_MIN))
+        rl = math.sqrt(math.log(o / S.A_MIN))
+        R = _rot(q[g])
+        P = mu[g][:, None] + np.exp(ls[g, 0]) * R[:, :1] * (ra * np.cos(th)) \
+            + np.exp(ls[g, 1]) * R[:, 1:2] * (ra * np.sin(th))
+        if P[2].min() <= near:
+            assert out["box"][g, 0] < 0
+            continue
+        p = K @ P
+        px, py = p[0] / p[2], p[1] / p[2]
+        c = (f * mu[g, 0] / mu[g, 2] + cx, f * mu[g, 1] / mu[g, 2] + cy)
+        x0 = min(px.min(), c[0] - rl)
+        x1 = max(px.max(), c[0] + rl)
+        y0 = min(py.min(), c[1] - rl)
+        y1 = max(py.max(), c[1] + rl)
+        want = (max(0, math.ceil(x0)), min(W - 1, math.floor(x1)),
+                max(0, math.ceil(y0)), min(H - 1, math.floor(y1)))
+        if not (want[0] <= want[1] and want[2] <= want[3]):
+            assert out["box"][g, 0] < 0
+            continue
+        # a sampled extreme sits within ~1e-6 px of the true one
+        near_int = [abs(v - round(v)) < 1e-4 for v in (x0, x1, y0, y1)]
+        if any(near_int):
+            continue
+        assert tuple(out["box"][g]) == want, (g, out["box"][g], want)
+        checked += 1
+    assert checked >= 6
 
 
 def test_edge_on_surfel_uses_the_low_pass():

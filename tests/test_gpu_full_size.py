@@ -60,7 +60,9 @@ def test_c5_mapping_workload_step_and_loop(rast):
     forward + L1 loss + backward + fused Adam from perturbed parameters
     towards targets rendered from the ground truth: the loss falls, nothing
     overflows, the iteration counter reaches 100 and every value stays
-    finite.  The pose errors relative to the first frame are reported."""
+    finite.  The pose errors relative to the first frame and the image L1 /
+    PSNR against the targets are reported, and the oracle renders the final
+    parameters on the last frame (images and gradients at the parity bar)."""
     import torch
     gt = scenes.scene_c5()
     rng = np.random.default_rng(5)
@@ -153,3 +155,19 @@ def test_c5_mapping_workload_step_and_loop(rast):
         assert torch.isfinite(d[k]).all(), k
     assert np.isfinite(losses).all()
     assert loss_end < loss0
+
+    # the final parameters: image L1 and PSNR against the targets, and the
+    # oracle rendering them on a sampled frame (images and gradients)
+    fin = scenes.Scene(d["means"].cpu().numpy(), gt.log_scales, gt.quats, gt.opacity,
+                       d["sh"].cpu().numpy(), gt.sh_degree, gt.cams, d["poses"].cpu().numpy(),
+                       gt.background)
+    _, rgb2, dep2, alp2 = gpu_forward(rast, fin)
+
+    def l1_psnr(img):
+        e = (torch.as_tensor(img, device="cuda") - t_rgb).double()
+        return float(e.abs().mean()), float(-10.0 * torch.log10((e * e).mean()))
+    q0, q1 = l1_psnr(out[0]), l1_psnr(rgb2)
+    print(f"[c5] image L1 / PSNR vs targets: {q0[0]:.5f} / {q0[1]:.2f} dB -> "
+          f"{q1[0]:.5f} / {q1[1]:.2f} dB", flush=True)
+    check_sampled_frames(rast, fin, (rgb2.cpu().numpy(), dep2.cpu().numpy(), alp2.cpu().numpy()),
+                         scenes.upstream(6, fin), [F - 1], label="c5-final")

@@ -217,3 +217,91 @@ def _check_backward(rast, sc, tile, seed, label):
 def test_surfel_backward_matches_oracle_autograd(rast, seed, n, frames, deg, W, H, tile):
     sc = _surfel_scene(seed, n, W, H, 0.8 * W, frames, deg)
     _check_backward(rast, sc, tile, seed, f"surfels{seed}")
+
+
+def test_surfel_objective_chain_matches_oracle(rast):
+    """The surfel objective end to end: rendering loss with SSIM (lambda1 0.8,
+    lambda2 0.2) + 0.05 x normal consistency + 100 x the mean depth
+    distortion of each frame, forward, losses and backward on each side.  On
+    the GPU through the C ABI: gsr_forward_surfel, gsr_loss_render,
+    gsr_normal_consistency (adding to the loss's depth and alpha gradients),
+    a constant distortion upstream, gsr_backward_surfel.  The oracle renders,
+    takes its loss terms of its own maps and back-propagates them.  The
+    renders agree to FP32 rounding, which the terms' curvature carries into
+    the upstream gradients, so the bar adds the oracle chain's response to a
+    1e-7 jitter of its maps.  The scene has no flagged pixel."""
+    import oracle
+    sc = _surfel_scene(61, 25, 40, 30, 34.0, 2, 1, ls_mean=-2.3)
+    sizes = [(int(c[0]), int(c[1])) for c in sc.cams]
+    _, _, t_rgb, t_dep = scenes.loss_images(12, sizes)
+    l1, l2, wn, wd = 0.8, 0.2, 0.05, 100.0
+    f32 = lambda v: float(np.float32(v))                          # noqa: E731
+    t = S.to64
+    params = [t(sc.means, True), t(sc.log_scales, True), t(sc.quats, True), t(sc.opacity, True),
+              t(sc.sh, True), t(np.zeros((sc.n_frames, 6)), True)]
+    out = S.render(*params[:5], sc.sh_degree, sc.cams, t(sc.poses), sc.background,
+                   twist=params[5])
+    assert sum(int((fr["flags"] != 0).sum()) for fr in out) == 0
+    maps = [torch.cat([fr[k].reshape(-1) for fr in out])
+            for k in ("rgb", "depth", "alpha", "normal", "dist")]
+
+    def upstream(m):
+        """Image-space gradients of the objective at maps m (numpy FP64) and
+        its value."""
+        rgb, dep, alp, nrm, dst = m
+        loss, g_rgb, g_dep, g_alp, _ = oracle.render_loss(rgb, dep, t_rgb, t_dep, f32(l1),
+                                                          f32(l2), sizes)
+        g_nrm = np.zeros_like(nrm)
+        g_dst = np.zeros_like(dst)
+        off = 0
+        for cam, (w, h) in zip(sc.cams, sizes):
+            P = w * h
+            D = t(dep[off:off + P].reshape(h, w), True)
+            A = t(alp[off:off + P].reshape(h, w), True)
+            N = t(nrm[3 * off:3 * (off + P)].reshape(3, h, w), True)
+            ln, _ = S.normal_consistency(D, A, N, cam)
+            gD, gA, gN = torch.autograd.grad(f32(wn) * ln, (D, A, N))
+            loss += f32(wn) * float(ln.detach()) + f32(wd) * float(dst[off:off + P].mean())
+            g_dep[off:off + P] += gD.numpy().ravel()
+            g_alp[off:off + P] += gA.numpy().ravel()
+            g_nrm[3 * off:3 * (off + P)] = gN.numpy().ravel()
+            g_dst[off:off + P] = f32(wd) / P
+            off += P
+        return loss, [g_rgb, g_dep, g_alp, g_nrm, g_dst]
+
+    def grads(G, retain):
+        s = sum((mp * torch.from_numpy(np.asarray(g, np.float64))).sum()
+                for mp, g in zip(maps, G))
+        return [x.numpy() for x in torch.autograd.grad(s, params, retain_graph=retain)]
+
+    m64 = [mp.detach().numpy() for mp in maps]
+    loss_ref, G = upstream(m64)
+    g_ref = grads(G, True)
+    rng = np.random.default_rng(3)
+    _, Gj = upstream([a + 1e-7 * rng.standard_normal(a.shape) for a in m64])
+    noise = [np.abs(x) for x in grads([a - b for a, b in zip(Gj, G)], False)]
+
+    d = to_dev(sc)
+    rgb, dep, alp, nrm, dst = rast.forward_surfel(d["means"], d["log_scales"], d["quats"],
+                                                  d["opacity"], d["sh"], d["poses"], sc.cams,
+                                                  sc.sh_degree, sc.background)
+    tr, td = (torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda() for a in (t_rgb, t_dep))
+    lr = rast.loss_render(rgb, dep, tr, td, l1, l2)
+    g_nrm = torch.zeros_like(nrm)
+    ln = rast.normal_consistency(sc.cams, dep, alp, nrm, wn, lr["g_depth"], lr["g_alpha"], g_nrm)
+    g_dst = torch.cat([torch.full((w * h,), f32(wd) / (w * h), device="cuda") for w, h in sizes])
+    g = rast.backward_surfel(lr["g_rgb"], lr["g_depth"], lr["g_alpha"], g_nrm, g_dst)
+    torch.cuda.synchronize()
+    off, loss_gpu = 0, float(lr["loss"].item()) + float(ln.item())
+    for (w, h) in sizes:
+        loss_gpu += f32(wd) * float(dst[off:off + w * h].double().mean())
+        off += w * h
+    print(f"[surfel] objective {loss_gpu:.9g} oracle {loss_ref:.9g}", flush=True)
+    assert abs(loss_gpu - loss_ref) <= 1e-5 * abs(loss_ref)
+    got = {k: v.cpu().numpy().astype(np.float64) for k, v in g.items()}
+    for k, r, nz in zip(NAMES[:5], g_ref[:5], noise[:5]):
+        assert_grad_close(f"surfel objective:{k}", got[k], r, noise=nz)
+    tw = g_ref[5]
+    bound = np.maximum(GRAD_REL * np.maximum(np.abs(tw), 1e-2 * np.abs(tw).max()),
+                       3.0 * noise[5])
+    assert np.all(np.abs(got["twist"] - tw) <= bound)

@@ -27,9 +27,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Algorithmic cost per evaluated (pixel, entry) pair of the compositing
-# kernels (FP32 operations counted from the method's arithmetic; see the
-# design notes): forward 27 flops + 1 exp, backward 60 flops + 1 exp + 1 rcp.
+# kernels (FP32 operations counted from the method's arithmetic):
+# forward 27 flops + 1 exp, backward 60 flops + 1 exp + 1 rcp.
 FLOPS_PER_PAIR = {"composite_fwd": 27.0, "composite_bwd": 60.0}
+# 2D surfels, per evaluated (pixel, surfel) pair, counted from the kernels'
+# source (an FMA counts 2): the intersection (pixel offsets, h_u, h_v, their
+# cross product, a Newton-refined reciprocal, u, v, G, G_lp, depth) is 42
+# flops and three exp/rcp; blending with the normal and the distortion sums
+# adds 33 in the forward; the backward re-evaluates the intersection and
+# adds ~130 (T recovery, the FP64 behind-state, dL/dalpha, the chain through
+# p = h_u x h_v and the 18 per-key sums).
+SURFEL_FLOPS_PER_PAIR = {"fwd": 75.0, "bwd": 170.0}
 PEAK_FP32_VECTOR_TFLOPS = 157.3  # MI355X fp32 vector (published)
 PEAK_HBM_GBS = 8000.0
 
@@ -416,13 +424,15 @@ def measure_surfel(rast, sc, dev, tile, steps):
            torch.empty(P, device="cuda"), torch.empty(3 * P, device="cuda"),
            torch.empty(P, device="cuda")]
 
-    def fwd(cap):
+    def fwd(cap, **kw):
         rast.forward_surfel(dev["means"], ls2, dev["quats"], dev["opacity"], dev["sh"],
-                            dev["poses"], sc.cams, 3, tile=tile, key_capacity=cap, out=out)
+                            dev["poses"], sc.cams, 3, tile=tile, key_capacity=cap, out=out, **kw)
     fwd(0)
     torch.cuda.synchronize()
     keys = int(rast.stats()["n_keys"])
     cap = int(keys * 1.05) + 1024
+    fwd(cap, count_pairs=True)
+    pairs = int(rast.stats()["n_pairs"])
     gen = torch.Generator("cuda").manual_seed(3)
     ups = [1e-6 * torch.randn(x.numel(), device="cuda", generator=gen) for x in out]
     K = 16
@@ -433,6 +443,20 @@ def measure_surfel(rast, sc, dev, tile, steps):
     ms_fwd = _event_ms(lambda: fwd(cap), reps)
     fwd(cap)
     ms_bwd = _event_ms(lambda: rast.backward_surfel(*ups, out=g), reps)
+    # the compositing kernels alone, from the library's per-stage HIP events
+    rast.timings()
+    for _ in range(reps):
+        fwd(cap, timing=True)
+        rast.backward_surfel(*ups, out=g)
+    st = rast.timings()
+    roof = {}
+    for stage, fl in (("composite_fwd", SURFEL_FLOPS_PER_PAIR["fwd"]),
+                      ("composite_bwd", SURFEL_FLOPS_PER_PAIR["bwd"])):
+        ms = st[stage][0] / max(st[stage][1], 1)
+        ach = pairs * fl / (ms * 1e-3) / 1e12
+        roof[stage] = {"avg_launch_ms": round(ms, 4), "flops_per_pair": fl,
+                       "achieved_TFLOPs": round(ach, 3),
+                       "frac": round(ach / PEAK_FP32_VECTOR_TFLOPS, 4)}
     gd, ga, gn = (torch.zeros(P, device="cuda"), torch.zeros(P, device="cuda"),
                   torch.zeros(3 * P, device="cuda"))
     loss = torch.empty(1, device="cuda")
@@ -441,12 +465,14 @@ def measure_surfel(rast, sc, dev, tile, steps):
     torch.cuda.synchronize()
     ok = bool(torch.isfinite(g["means"]).all()) and float(out[2].max()) > 0.5
     gbs = 60.0 * P / (ms_nc * 1e-3) / 1e9
-    res = {"keys_per_forward": keys, "forward_ms": round(ms_fwd, 4),
+    res = {"keys_per_forward": keys, "pairs_per_forward": pairs, "forward_ms": round(ms_fwd, 4),
            "backward_ms": round(ms_bwd, 4),
            "fwd_bwd_Mpix_per_s": round(P / 1e6 / ((ms_fwd + ms_bwd) * 1e-3), 3),
            "normal_consistency": {"ms": round(ms_nc, 4), "hbm_bytes": 60 * P,
                                   "achieved_GBps": round(gbs, 1),
                                   "frac_hbm": round(gbs / PEAK_HBM_GBS, 4)},
+           "roofline": {"bound": "alu", "unit": "TFLOP/s", "peak": PEAK_FP32_VECTOR_TFLOPS,
+                        **roof},
            "finite_and_covered": ok}
     log(f"[bench] surfels {res}")
     return res

@@ -154,7 +154,8 @@ gsr_status gsr_forward(gsr_context* ctx, const gsr_settings* settings, int64_t n
  * square of half width sqrt(ln(255 sigma)) around c, and is culled when
  * sigma <= 1/255 or the centre or the disk's nearest point is not beyond
  * the near plane.
- * GSR_FLAG_MEDIAN_DEPTH and GSR_FLAG_COUNT_PAIRS are not supported
+ * GSR_FLAG_COUNT_PAIRS counts the (pixel, surfel) pairs whose box test
+ * passes before the pixel stops; GSR_FLAG_MEDIAN_DEPTH is not supported
  * (GSR_ERR_UNSUPPORTED).  All output pointers are device memory, 4-byte
  * aligned; GSR_ERR_INVALID_ARGUMENT if normal or dist is NULL.  gsr_backward
  * after this forward returns GSR_ERR_STATE; use gsr_backward_surfel. */

@@ -31,8 +31,7 @@ mcmc_relocate  (MCMC): dead Gaussians (the caller's choice, opacity below
     so that N copies composited at the centre give back opacity o, and along
     a line through the centre the integral of the composited opacity
     equals that of the original.  Means, rotations and SH are copied.
-    (Kheradmand et al., the MCMC method the paper cites; readings stated in
-    the design notes.)
+    (Kheradmand et al., the MCMC method the paper cites.)
 """
 import math
 

@@ -16,7 +16,7 @@ SH colour (as for the 3D Gaussians).  Per frame, with the world->camera pose
 maps disk coordinates (u, v, 1) to homogeneous pixels.  The ray through
 pixel (x, y) meets the disk at (u, v) = (p0 / p2, p1 / p2), p = h_u x h_v,
 h_u = x M2 - M0, h_v = y M2 - M1, at depth z = M2 . (u, v, 1).  Readings
-where the paper is silent (design notes, reading 18):
+where the paper is silent:
   - G = exp(-(u^2 + v^2) / 2); the screen-space low-pass of 2DGS,
     G_lp = exp(-|(x, y) - c|^2) (standard deviation sqrt(2)/2 px around the
     projected centre c), and G' = max(G, G_lp); a pixel where G_lp wins
@@ -118,8 +118,9 @@ def render(means, log_scales, quats, opacity_logits, sh, sh_degree, cams, poses,
     opacity_logits [n], sh [n,K,3], poses [F,3,4]; twist [F,6] = (rho, phi)
     left perturbation, first order at 0).  Returns a list per frame of dicts
     rgb [3,H,W], depth, alpha, dist [H,W], normal [3,H,W], flags [H,W]
-    (uint8, numpy) and box (numpy int [n,4] x_lo, x_hi, y_lo, y_hi, -1 if
-    culled)."""
+    (uint8, numpy), box (numpy int [n,4] x_lo, x_hi, y_lo, y_hi, -1 if
+    culled), order and pairs (the (pixel, surfel) pairs whose box holds the
+    pixel before it stops)."""
     out = []
     bg = torch.tensor([float(b) for b in background], dtype=torch.float64)
     Rg = _rot(quats)                                # [n,3,3]
@@ -196,9 +197,11 @@ def render(means, log_scales, quats, opacity_logits, sh, sh_degree, cams, poses,
         done = torch.zeros(H, W, dtype=torch.bool)
         flags = np.zeros((H, W), np.uint8)
         nb = torch.zeros(H, W, dtype=torch.float64)
+        pairs = 0
         for g in order:
             x_lo, x_hi, y_lo, y_hi = box[g]
             inside = (xs >= x_lo) & (xs <= x_hi) & (ys >= y_lo) & (ys <= y_hi) & ~done
+            pairs += int(inside.sum())
             if not bool(inside.any()):
                 continue
             M0, M1, M2 = M[g, 0], M[g, 1], M[g, 2]
@@ -250,7 +253,7 @@ def render(means, log_scales, quats, opacity_logits, sh, sh_degree, cams, poses,
             nb = nb + blend.to(torch.float64)
         rgb = C + T * bg[:, None, None]
         out.append(dict(rgb=rgb, depth=D, alpha=1 - T, normal=N, dist=Dist, flags=flags,
-                        box=box, order=order))
+                        box=box, order=order, pairs=pairs))
     return out
 
 

@@ -131,7 +131,7 @@ void launch_surfel_fwd(hipStream_t st, int tw, int th, int n_tiles, int F,
                        const void* rec, const float* bg, float* rgb, float* depth, float* alpha,
                        float* normal, float* dist, float* t_final, int32_t* n_last,
                        float* dist_aux, uint32_t* nproc, const uint32_t* prev_nproc,
-                       uint32_t* order, bool xcd_groups);
+                       uint32_t* order, bool xcd_groups, unsigned long long* pairs);
 void launch_surfel_bwd(hipStream_t st, int tw, int th, int n_tiles, int F,
                        const FrameDesc* frames, const uint2* ranges, const uint32_t* vals,
                        const void* rec, const uint2* trect, const uint32_t* keyoff,

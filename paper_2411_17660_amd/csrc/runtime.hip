@@ -303,8 +303,8 @@ gsr_status forward_impl(gsr_context* ctx, const gsr_settings* s, int64_t n, cons
   gsr_status rc = validate(ctx, s, n, means, log_scales, quats, opac, sh, F, cams, poses, rgb,
                            depth, alpha);
   if (rc) return rc;
-  if (surfel && (s->flags & (GSR_FLAG_MEDIAN_DEPTH | GSR_FLAG_COUNT_PAIRS)))
-    return fail(ctx, GSR_ERR_UNSUPPORTED, "surfels: median depth and pair counts not built");
+  if (surfel && (s->flags & GSR_FLAG_MEDIAN_DEPTH))
+    return fail(ctx, GSR_ERR_UNSUPPORTED, "surfels: median depth not built");
   if (surfel && (!normal || !dist))
     return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "normal or dist is NULL");
   if (surfel && ((((uintptr_t)normal) | ((uintptr_t)dist)) & 3u))
@@ -471,7 +471,7 @@ gsr_status forward_impl(gsr_context* ctx, const gsr_settings* s, int64_t n, cons
                         svals, ctx->rec.p, s->background, rgb, depth, alpha, normal, dist,
                         P<float>(ctx->t_final), P<int32_t>(ctx->n_last), P<float>(ctx->dist_aux),
                         P<uint32_t>(ctx->nproc), have_prev ? P<uint32_t>(ctx->nproc) : nullptr,
-                        P<uint32_t>(ctx->order_f), remap);
+                        P<uint32_t>(ctx->order_f), remap, count ? d_pairs : nullptr);
     else
       launch_composite_fwd(st, tw, th, (int)T, F, P<FrameDesc>(ctx->frames),
                            P<uint2>(ctx->ranges), svals, P<Record>(ctx->rec), s->background,

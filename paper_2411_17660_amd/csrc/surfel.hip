@@ -219,9 +219,12 @@ __device__ __forceinline__ SurfelHit surfel_eval(const Surfel& S, int px, int py
   return h;
 }
 
-template <int TW, int TH>
+// COUNT: also count the evaluated (pixel, entry) pairs, those whose box
+// test passes before the pixel stops (one atomic add per tile).
+template <int TW, int TH, bool COUNT>
 __global__ void __launch_bounds__(64) surfel_fwd_kernel(
     int n_tiles, int groups, const uint32_t* __restrict__ order, uint32_t* __restrict__ tile_nproc,
+    unsigned long long* __restrict__ pair_count,
     int n_frames, const FrameDesc* __restrict__ frames, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ vals, const Surfel* __restrict__ rec, float bg0, float bg1,
     float bg2, float* __restrict__ rgb, float* __restrict__ depth, float* __restrict__ alpha,
@@ -244,6 +247,7 @@ __global__ void __launch_bounds__(64) surfel_fwd_kernel(
   float ZR[PIX], S1[PIX], S2[PIX], DS[PIX];
   int last[PIX];
   bool done[PIX];
+  uint32_t hits = 0;
 #pragma unroll
   for (int k = 0; k < PIX; ++k) {
     T[k] = 1.0f;
@@ -273,6 +277,7 @@ __global__ void __launch_bounds__(64) surfel_fwd_kernel(
         if (ylo > row0 + RPP - 1 || yhi < row0) continue;
         const int py = row0 + ly;
         if (done[k] || !xin || (unsigned)(py - ylo) > (unsigned)(yhi - ylo)) continue;
+        if (COUNT) ++hits;
         const SurfelHit h = surfel_eval(S, px, py);
         const float a = fminf(kAlphaMax, S.opacity * h.Gh);
         if (a < kAlphaMin) continue;
@@ -310,6 +315,11 @@ __global__ void __launch_bounds__(64) surfel_fwd_kernel(
     most = m > most ? m : most;
   }
   if (lane == 0) tile_nproc[tile] = (uint32_t)most;
+  if (COUNT) {
+    unsigned long long c = hits;
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, kWave);
+    if (lane == 0) atomicAdd(pair_count, c);
+  }
   const int64_t plane = (int64_t)fr.width * fr.height;
 #pragma unroll
   for (int k = 0; k < PIX; ++k) {
@@ -762,21 +772,26 @@ void launch_surfel_fwd(hipStream_t st, int tw, int th, int n_tiles, int F,
                        const void* rec, const float* bg, float* rgb, float* depth, float* alpha,
                        float* normal, float* dist, float* t_final, int32_t* n_last,
                        float* dist_aux, uint32_t* nproc, const uint32_t* prev_nproc,
-                       uint32_t* order, bool xcd_groups) {
+                       uint32_t* order, bool xcd_groups, unsigned long long* pairs) {
   if (n_tiles <= 0) return;
   const int groups = tile_schedule_groups(xcd_groups);
   launch_tile_order(st, n_tiles, groups, prev_nproc, order);
   const dim3 grid(tile_schedule_grid(n_tiles, groups));
-#define GSR_SURF_FWD(W, H)                                                                  \
-  hipLaunchKernelGGL((surfel_fwd_kernel<W, H>), grid, dim3(kWave), 0, st, n_tiles, groups,   \
-                     order, nproc, F, frames, ranges, vals, (const Surfel*)rec, bg[0],       \
-                     bg[1], bg[2], rgb, depth, alpha, normal, dist, t_final, n_last, dist_aux)
+#define GSR_SURF_FWD_C(W, H, C)                                                             \
+  hipLaunchKernelGGL((surfel_fwd_kernel<W, H, C>), grid, dim3(kWave), 0, st, n_tiles,       \
+                     groups, order, nproc, pairs, F, frames, ranges, vals, (const Surfel*)rec, \
+                     bg[0], bg[1], bg[2], rgb, depth, alpha, normal, dist, t_final, n_last,  \
+                     dist_aux)
+#define GSR_SURF_FWD(W, H)                 \
+  if (pairs) GSR_SURF_FWD_C(W, H, true);   \
+  else GSR_SURF_FWD_C(W, H, false)
   if (tw == 16 && th == 16) GSR_SURF_FWD(16, 16);
   else if (tw == 8 && th == 8) GSR_SURF_FWD(8, 8);
   else if (tw == 32 && th == 8) GSR_SURF_FWD(32, 8);
   else if (tw == 16 && th == 8) GSR_SURF_FWD(16, 8);
   else if (tw == 32 && th == 16) GSR_SURF_FWD(32, 16);
 #undef GSR_SURF_FWD
+#undef GSR_SURF_FWD_C
 }
 
 void launch_surfel_bwd(hipStream_t st, int tw, int th, int n_tiles, int F,

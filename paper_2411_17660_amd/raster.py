@@ -82,7 +82,8 @@ class Rasterizer:
         return rgb, depth, alpha
 
     def forward_surfel(self, means, log_scales, quats, opacity, sh, poses, cams, sh_degree,
-                       background=(0.0, 0.0, 0.0), tile=(16, 16), key_capacity=0, out=None):
+                       background=(0.0, 0.0, 0.0), tile=(16, 16), key_capacity=0, out=None,
+                       timing=False, count_pairs=False):
         """Renders F frames of 2D surfels (log_scales [n,2]); returns packed
         (rgb, depth, alpha, normal [sum 3HW], dist [sum HW])."""
         P = int(sum(int(c[0]) * int(c[1]) for c in cams))
@@ -92,7 +93,8 @@ class Rasterizer:
                    torch.empty(P, device=dev), torch.empty(3 * P, device=dev),
                    torch.empty(P, device=dev))
         rgb, depth, alpha, normal, dist = out
-        self.settings = native.make_settings(sh_degree, background, tile, key_capacity)
+        self.settings = native.make_settings(sh_degree, background, tile, key_capacity,
+                                             timing=timing, count_pairs=count_pairs)
         self.cams = native.make_cameras(cams)
         n = int(means.shape[0])
         self._check(self.lib.gsr_forward_surfel(

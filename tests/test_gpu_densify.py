@@ -3,8 +3,9 @@ FP64 oracle (oracle/densify.py).
 
 - ADC statistics: the per-Gaussian sum of |dL/d(u, v)| over kept frames is a
   function of the backward's screen-space gradient, so its bar is the
-  gradient bar (reading 14 of the design, with the oracle's own response to
-  a 1e-6 jitter of the upstream as the noise term); the counts are exact.
+  gradient bar of the backward (1e-3 relative with its floors, or 3 times
+  the oracle's own response to a 1e-6 jitter of the upstream); the counts
+  are exact.
 - MCMC noise and relocation run in FP64 and round once: 1e-6 relative per
   element (plus 1e-7 of the tensor's largest element); copied values are
   bitwise copies.

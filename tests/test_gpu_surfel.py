@@ -305,3 +305,25 @@ def test_surfel_objective_chain_matches_oracle(rast):
     bound = np.maximum(GRAD_REL * np.maximum(np.abs(tw), 1e-2 * np.abs(tw).max()),
                        3.0 * noise[5])
     assert np.all(np.abs(got["twist"] - tw) <= bound)
+
+
+def test_surfel_pair_count_matches_oracle(rast):
+    """GSR_FLAG_COUNT_PAIRS on the surfel forward counts the (pixel, surfel)
+    pairs whose box test passes before the pixel stops, exactly as the
+    oracle does, on a scene with no flagged pixel (where both take the same
+    stop decisions); counting leaves the images unchanged."""
+    sc = _surfel_scene(61, 25, 40, 30, 34.0, 2, 1, ls_mean=-2.3)
+    ref = _oracle(sc)
+    assert sum(int((fr["flags"] != 0).sum()) for fr in ref) == 0
+    d = to_dev(sc)
+    args = (d["means"], d["log_scales"], d["quats"], d["opacity"], d["sh"], d["poses"], sc.cams,
+            sc.sh_degree, sc.background)
+    plain = [x.clone() for x in rast.forward_surfel(*args)]
+    counted = rast.forward_surfel(*args, count_pairs=True)
+    torch.cuda.synchronize()
+    n = int(rast.stats()["n_pairs"])
+    want = sum(fr["pairs"] for fr in ref)
+    print(f"[surfel] pairs {n} oracle {want}", flush=True)
+    assert n == want and n > 0
+    for a, b in zip(plain, counted):
+        assert torch.equal(a, b)

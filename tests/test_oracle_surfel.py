@@ -282,6 +282,37 @@ def test_distortion_is_the_pair_sum_of_separately_rendered_surfels():
     assert np.abs(full["normal"].numpy() - nsum).max() < 1e-12
 
 
+def test_pair_count_by_brute_force():
+    """pairs = sum over surfels of the pixels inside its box that have not
+    stopped when it comes, counted here by walking each pixel's list."""
+    from paper_2411_17660_amd import scenes
+    sc = scenes.tiny_scene(seed=23, n=30, W=24, H=18, f=20.0, n_frames=1, sh_degree=0,
+                           ls_mean=-1.8, ls_sigma=0.3, opacity_sigma=2.0)
+    out = _render(sc.means, sc.log_scales[:, :2], sc.quats, sc.opacity, sc.sh, 0, sc.cams,
+                  sc.poses)[0]
+    box, order = out["box"], out["order"]
+    one = []
+    for g in order:                      # each surfel's alpha map, alone
+        o = np.full(sc.n, -40.0)
+        o[g] = sc.opacity[g]
+        one.append(_render(sc.means, sc.log_scales[:, :2], sc.quats, o, sc.sh, 0, sc.cams,
+                           sc.poses)[0]["alpha"].numpy())
+    count = 0
+    for y in range(18):
+        for x in range(24):
+            T = 1.0
+            for k, g in enumerate(order):
+                if not (box[g, 0] <= x <= box[g, 1] and box[g, 2] <= y <= box[g, 3]):
+                    continue
+                count += 1
+                a = one[k][y, x]
+                if a >= S.A_MIN:
+                    if T * (1 - a) < S.T_MIN:
+                        break
+                    T *= 1 - a
+    assert out["pairs"] == count and count > 100
+
+
 def test_distortion_vanishes_for_coplanar_fronto_parallel_surfels():
     cams = [(40, 30, 30.0, 30.0, 20.0, 15.0, 0.2)]
     out = _render(np.array([[0.0, 0, 2.0], [0.01, 0.02, 2.0]]), np.log(np.full((2, 2), 0.1)),

@@ -335,6 +335,12 @@ __device__ __forceinline__ void composite_bwd_tile(
       float gu = 0.f, gv = 0.f, gs = 0.f;
       double gSxx = 0.0, gSxy = 0.0, gSyy = 0.0;
       float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f, gz = 0.f;
+      // Hide the zeros from constant folding (no instruction is emitted):
+      // the sums are then set to zero once per entry and updated in place
+      // under the lane mask, instead of each branch of the first strip
+      // writing its own zeros.
+      asm volatile("" : "+v"(gu), "+v"(gv), "+v"(gs), "+v"(gSxx), "+v"(gSxy), "+v"(gSyy),
+                   "+v"(gc0), "+v"(gc1), "+v"(gc2), "+v"(gz));
       bool any = false;
 #pragma unroll
       for (int k = 0; k < PIX; ++k) {

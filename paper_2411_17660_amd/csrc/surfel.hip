@@ -441,7 +441,10 @@ __global__ void __launch_bounds__(64) surfel_bwd_kernel(
       // against each other, in FP64
       float acc[kSG];
 #pragma unroll
-      for (int i = 0; i < kSG; ++i) acc[i] = 0.0f;
+      for (int i = 0; i < kSG; ++i) {
+        acc[i] = 0.0f;
+        asm volatile("" : "+v"(acc[i]));  // zeroed once per entry, not per branch
+      }
       bool any = false;
 #pragma unroll
       for (int k = 0; k < PIX; ++k) {

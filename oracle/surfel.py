@@ -61,10 +61,13 @@ EPS32 = 2.0 ** -24
 FLAG_ALPHA, FLAG_T, FLAG_CLAMP, FLAG_LOWPASS = 1, 2, 4, 16
 # The ray-disk intersection loses accuracy with its conditioning
 # kappa = |h_u| |h_v| / |h_u x h_v| (1 / sin of the angle between the two
-# planes through the ray): a value computed from rounded h_u, h_v has error
-# ~ kappa ulps, its derivative ~ kappa^2.  FLAG_COND marks the pixels where
-# the disk term is blended with kappa above KAPPA_GRAD; they carry no
-# decision, so image comparisons keep them and gradient comparisons do not.
+# planes through the ray): G computed in FP32 from the stored surfel errs by
+# up to ~5 kappa (1 + q) ulps relative (measured on FP32 evaluations of
+# tilted surfels), and a tilted surfel's rotation gradient sums per-pixel
+# terms that cancel to ~1 % of their size.  FLAG_COND marks the pixels where
+# the disk term is blended with kappa (1 + q) above KAPPA_GRAD (so ~1e-5 of a
+# term, ~1e-3 after such cancellation); they carry no decision, so image
+# comparisons keep them and gradient comparisons do not.
 FLAG_COND = 32
 KAPPA_GRAD = 32.0
 
@@ -113,14 +116,26 @@ def _sh_colour(sh, deg, dirs):
 
 
 def render(means, log_scales, quats, opacity_logits, sh, sh_degree, cams, poses,
-           background=(0.0, 0.0, 0.0), twist=None):
+           background=(0.0, 0.0, 0.0), twist=None, window=None, jitter=None):
     """FP64 torch tensors in (means [n,3], log_scales [n,2], quats [n,4],
     opacity_logits [n], sh [n,K,3], poses [F,3,4]; twist [F,6] = (rho, phi)
     left perturbation, first order at 0).  Returns a list per frame of dicts
     rgb [3,H,W], depth, alpha, dist [H,W], normal [3,H,W], flags [H,W]
     (uint8, numpy), box (numpy int [n,4] x_lo, x_hi, y_lo, y_hi, -1 if
     culled), order and pairs (the (pixel, surfel) pairs whose box holds the
-    pixel before it stops)."""
+    pixel before it stops).  window = (x0, x1, y0, y1), inclusive, renders
+    only those pixels of every frame (the images are then of the window's
+    size; each pixel's value is the same as in the whole image).
+
+    jitter (a torch.Generator, for tests): scales each surfel's M2,
+    k_u = c_x M2 - M0 and k_v = c_y M2 - M1 (per component) by
+    (1 + 2^-24 xi), xi ~ N(0, 1) drawn from it, and evaluates each pixel's
+    intersection (h_u, h_v from the offset to the centre, their cross
+    product, u, v, q, G, G_lp and the depth) as a kernel does in FP32, each operation
+    followed by such a factor; the factors are constants of the autograd
+    graph.  The change this makes to the gradients is the size of change
+    the FP32 rounding of the stored surfel and of the intersection causes,
+    ill-conditioning and cancellation included; None renders exactly."""
     out = []
     bg = torch.tensor([float(b) for b in background], dtype=torch.float64)
     Rg = _rot(quats)                                # [n,3,3]
@@ -151,15 +166,17 @@ def render(means, log_scales, quats, opacity_logits, sh, sh_degree, cams, poses,
         n = means.shape[0]
         box = -np.ones((n, 4), np.int64)
         with torch.no_grad():
+            Mn, opn = M.detach().numpy(), opac.detach().numpy()
+            mcn, ctrn = mc.detach().numpy(), ctr.detach().numpy()
             for g in range(n):
-                o = float(opac[g])
-                zc = float(mc[g, 2])
+                o = float(opn[g])
+                zc = float(mcn[g, 2])
                 if not (o > A_MIN) or not (zc > near):
                     continue
                 r2 = 2.0 * math.log(o / A_MIN)          # r_a^2
                 ra = math.sqrt(r2)
                 rl = math.sqrt(math.log(o / A_MIN))
-                m = [[float(M[g, i, j]) for j in range(3)] for i in range(3)]
+                m = Mn[g].tolist()
                 # the disk's nearest point to the camera plane
                 if not (m[2][2] - ra * math.sqrt(m[2][0] * m[2][0] + m[2][1] * m[2][1]) > near):
                     continue
@@ -174,7 +191,7 @@ def render(means, log_scales, quats, opacity_logits, sh, sh_degree, cams, poses,
                     ci2, cii = dual(i, 2), dual(i, i)
                     sq = math.sqrt(max(ci2 * ci2 - cii * c22, 0.0))
                     ext.append(((ci2 + sq) / c22, (ci2 - sq) / c22))
-                c0 = ctr[g].detach().numpy()
+                c0 = ctrn[g]
                 lo = [min(ext[i][0], ext[i][1], c0[i] - rl) for i in (0, 1)]
                 hi = [max(ext[i][0], ext[i][1], c0[i] + rl) for i in (0, 1)]
                 x_lo, x_hi = max(0, math.ceil(lo[0])), min(W - 1, math.floor(hi[0]))
@@ -184,58 +201,117 @@ def render(means, log_scales, quats, opacity_logits, sh, sh_degree, cams, poses,
             keep = np.nonzero(box[:, 0] >= 0)[0]
             zbits = mc[:, 2].detach().numpy().astype(np.float32).view(np.uint32)
             order = keep[np.lexsort((keep, zbits[keep]))]
-        ys, xs = torch.meshgrid(torch.arange(H, dtype=torch.float64),
-                                torch.arange(W, dtype=torch.float64), indexing="ij")
-        T = torch.ones(H, W, dtype=torch.float64)
-        C = torch.zeros(3, H, W, dtype=torch.float64)
-        D = torch.zeros(H, W, dtype=torch.float64)
-        N = torch.zeros(3, H, W, dtype=torch.float64)
-        Dist = torch.zeros(H, W, dtype=torch.float64)
-        SA = torch.zeros(H, W, dtype=torch.float64)     # sum of w over entries in front
-        SZ = torch.zeros(H, W, dtype=torch.float64)     # ... of w z
-        SZZ = torch.zeros(H, W, dtype=torch.float64)    # ... of w z^2
-        done = torch.zeros(H, W, dtype=torch.bool)
-        flags = np.zeros((H, W), np.uint8)
-        nb = torch.zeros(H, W, dtype=torch.float64)
+        wx0, wx1, wy0, wy1 = (0, W - 1, 0, H - 1) if window is None else window
+        ys, xs = torch.meshgrid(torch.arange(wy0, wy1 + 1, dtype=torch.float64),
+                                torch.arange(wx0, wx1 + 1, dtype=torch.float64), indexing="ij")
+        Hw, Ww = xs.shape
+        T = torch.ones(Hw, Ww, dtype=torch.float64)
+        C = torch.zeros(3, Hw, Ww, dtype=torch.float64)
+        D = torch.zeros(Hw, Ww, dtype=torch.float64)
+        N = torch.zeros(3, Hw, Ww, dtype=torch.float64)
+        Dist = torch.zeros(Hw, Ww, dtype=torch.float64)
+        SA = torch.zeros(Hw, Ww, dtype=torch.float64)   # sum of w over entries in front
+        SZ = torch.zeros(Hw, Ww, dtype=torch.float64)   # ... of w z
+        SZZ = torch.zeros(Hw, Ww, dtype=torch.float64)  # ... of w z^2
+        done = torch.zeros(Hw, Ww, dtype=torch.bool)
+        flags = np.zeros((Hw, Ww), np.uint8)
+        nb = torch.zeros(Hw, Ww, dtype=torch.float64)
         pairs = 0
         for g in order:
             x_lo, x_hi, y_lo, y_hi = box[g]
+            if x_hi < wx0 or x_lo > wx1 or y_hi < wy0 or y_lo > wy1:
+                continue
             inside = (xs >= x_lo) & (xs <= x_hi) & (ys >= y_lo) & (ys <= y_hi) & ~done
             pairs += int(inside.sum())
             if not bool(inside.any()):
                 continue
             M0, M1, M2 = M[g, 0], M[g, 1], M[g, 2]
-            hu = xs[..., None] * M2 - M0
-            hv = ys[..., None] * M2 - M1
-            p = torch.linalg.cross(hu, hv, dim=-1)
+            if jitter is not None:
+                # the surfel's stored values M2, k_u = c_x M2 - M0 and
+                # k_v = c_y M2 - M1, each off by one rounding, shared by all
+                # its pixels
+                ku, kv = ctr[g, 0] * M2 - M0, ctr[g, 1] * M2 - M1
+                e = [1.0 + EPS32 * torch.randn(3, generator=jitter, dtype=torch.float64)
+                     for _ in range(3)]
+                M2, ku, kv = M2 * e[0], ku * e[1], kv * e[2]
+                M0, M1 = ctr[g, 0] * M2 - ku, ctr[g, 1] * M2 - kv
+            if jitter is None:
+                hu = xs[..., None] * M2 - M0
+                hv = ys[..., None] * M2 - M1
+                p = torch.linalg.cross(hu, hv, dim=-1)
+                ok = p[..., 2].abs() > 1e-300
+                p2 = torch.where(ok, p[..., 2], torch.ones_like(p[..., 2]))
+                u, v = p[..., 0] / p2, p[..., 1] / p2
+                q = torch.where(ok, u * u + v * v, torch.full_like(u, float("inf")))
+                G = torch.exp(-0.5 * q)
+                dd = (xs - ctr[g, 0]) ** 2 + (ys - ctr[g, 1]) ** 2
+                Glp = torch.exp(-dd)
+            else:
+                # the same steps as a kernel takes them in FP32 from the
+                # pixel's offset to the centre, each operation followed by
+                # one rounding (a random relative error of one ulp)
+                def rd(t):
+                    return t * (1.0 + EPS32 * torch.randn(t.shape, generator=jitter,
+                                                          dtype=torch.float64))
+                ex, ey = rd(xs - ctr[g, 0]), rd(ys - ctr[g, 1])
+                hu = torch.stack([rd(rd(ex * M2[0]) + ku[0]), rd(rd(ex * M2[1]) + ku[1]),
+                                  rd(ex * M2[2])], -1)
+                hv = torch.stack([rd(rd(ey * M2[0]) + kv[0]), rd(rd(ey * M2[1]) + kv[1]),
+                                  rd(ey * M2[2])], -1)
+                p = torch.stack([
+                    rd(rd(hu[..., 1] * hv[..., 2]) - rd(hu[..., 2] * hv[..., 1])),
+                    rd(rd(hu[..., 2] * hv[..., 0]) - rd(hu[..., 0] * hv[..., 2])),
+                    rd(rd(hu[..., 0] * hv[..., 1]) - rd(hu[..., 1] * hv[..., 0]))], -1)
+                ok = p[..., 2].abs() > 1e-300
+                ip = rd(1.0 / torch.where(ok, p[..., 2], torch.ones_like(p[..., 2])))
+                u, v = rd(p[..., 0] * ip), rd(p[..., 1] * ip)
+                q = torch.where(ok, rd(rd(u * u) + rd(v * v)), torch.full_like(u, float("inf")))
+                G = rd(torch.exp(-0.5 * q))
+                dd = rd(rd(ex * ex) + rd(ey * ey))
+                Glp = rd(torch.exp(-dd))
             # conditioning of the intersection: 1 / sin of the angle of h_u, h_v
             kappa = (torch.linalg.norm(hu, dim=-1) * torch.linalg.norm(hv, dim=-1)
                      / torch.linalg.norm(p, dim=-1).clamp(min=1e-300)).detach()
-            ok = p[..., 2].abs() > 1e-300
-            p2 = torch.where(ok, p[..., 2], torch.ones_like(p[..., 2]))
-            u, v = p[..., 0] / p2, p[..., 1] / p2
-            q = torch.where(ok, u * u + v * v, torch.full_like(u, float("inf")))
-            G = torch.exp(-0.5 * q)
-            dd = (xs - ctr[g, 0]) ** 2 + (ys - ctr[g, 1]) ** 2
-            Glp = torch.exp(-dd)
             use_obj = G >= Glp
             Gh = torch.where(use_obj, G, Glp)
-            zint = torch.where(use_obj, M2[0] * u + M2[1] * v + M2[2], mc[g, 2].expand_as(u))
+            zobj = M2[0] * u + M2[1] * v + M2[2]
+            if jitter is not None:
+                zobj = rd(rd(rd(M2[0] * u) + rd(M2[1] * v)) + M2[2])
+            zint = torch.where(use_obj, zobj, mc[g, 2].expand_as(u))
             araw = opac[g] * Gh
             a = torch.clamp(araw, max=A_MAX)
             with torch.no_grad():
                 an, Tn_ = a.detach().numpy(), (T * (1 - a)).detach().numpy()
                 ins = inside.numpy()
-                band_a = np.maximum(BAND, 64 * EPS32 * (1 + np.minimum(q.detach().numpy(), 1e30))
-                                    * np.minimum(kappa.numpy(), 1e30))
-                flags[ins & (np.abs(an - A_MIN) < band_a * A_MIN)] |= FLAG_ALPHA
+                Gn, Gl = G.detach().numpy(), Glp.detach().numpy()
+                # alpha's FP32 error is that of the term that sets it: the
+                # disk term's exponent errs by ~(1 + q) kappa ulps, the
+                # low-pass's by ~(1 + |x - c|^2); near their switch either may
+                # set it.  An exponent off by e moves ln(alpha) by e, so the
+                # decision alpha >= A_MIN is in doubt where |ln(alpha / A_MIN)|
+                # is below the band (for small bands the same as a relative
+                # band on alpha; a pixel that alpha cannot reach is not)
+                band_obj = np.maximum(BAND, 64 * EPS32 * (1 + np.minimum(q.detach().numpy(), 1e30))
+                                      * np.minimum(kappa.numpy(), 1e30))
+                band_lp = np.maximum(BAND, 64 * EPS32 * (1 + dd.detach().numpy()))
+                # which term is larger is in doubt where their exponents q/2
+                # and |x - c|^2 differ by less than 1e-3 or than the terms'
+                # own FP32 error (an ill-conditioned disk term can overtake
+                # the low-pass)
+                qn = np.minimum(q.detach().numpy(), 1e300)
+                switch = (np.abs(0.5 * qn - dd.detach().numpy())
+                          < np.maximum(1e-3, band_obj + band_lp))
+                band_a = np.where(switch, np.maximum(np.maximum(band_obj, band_lp), 1e-3),
+                                  np.where(use_obj.numpy(), band_obj, band_lp))
+                lna = np.abs(np.log(np.maximum(an, 1e-300) / A_MIN))
+                flags[ins & (lna < band_a)] |= FLAG_ALPHA
                 live = ins & (an >= A_MIN)
                 band_t = np.maximum(BAND, 4 * EPS32 * (nb.numpy() + 1))
                 flags[live & (np.abs(Tn_ - T_MIN) < band_t * T_MIN)] |= FLAG_T
                 flags[live & (np.abs(araw.detach().numpy() - A_MAX) < BAND * A_MAX)] |= FLAG_CLAMP
-                Gn, Gl = G.detach().numpy(), Glp.detach().numpy()
-                flags[live & (np.abs(Gn - Gl) < 1e-3 * np.maximum(Gn, Gl))] |= FLAG_LOWPASS
-                flags[live & use_obj.numpy() & (kappa.numpy() > KAPPA_GRAD)] |= FLAG_COND
+                flags[live & switch] |= FLAG_LOWPASS
+                flags[live & use_obj.numpy() &
+                      ((1 + qn) * np.minimum(kappa.numpy(), 1e300) > KAPPA_GRAD)] |= FLAG_COND
             blend = inside & (a >= A_MIN)
             Tn = T * (1 - a)
             stop = blend & (Tn < T_MIN)

@@ -113,8 +113,8 @@ void launch_twist_reduce(hipStream_t st, int F, const double* twist_partial, int
 
 // surfel.hip: the 2D surfel variant's preprocess (records of
 // surfel_record_bytes() bytes in `rec`), forward compositing (rgb, depth,
-// alpha, normal [sum 3HW], distortion; dist_aux [P][3] keeps the per-pixel
-// sums the backward needs) and backward (per-key partials of
+// alpha, normal [sum 3HW], distortion; dist_aux [P][4] keeps the per-pixel
+// reference depth and the distortion sums A, D_1, D_2 the backward needs) and backward (per-key partials of
 // surfel_grad_values() floats, then the chain rule and twist); keys, sorts
 // and ranges are shared.
 size_t surfel_record_bytes();

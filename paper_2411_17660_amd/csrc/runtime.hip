@@ -360,7 +360,7 @@ gsr_status forward_impl(gsr_context* ctx, const gsr_settings* s, int64_t n, cons
   if ((rc = ensure(ctx, ctx->n_last, (size_t)Px * 4, st))) return rc;
   const bool median = (s->flags & GSR_FLAG_MEDIAN_DEPTH) != 0;
   if (median && (rc = ensure(ctx, ctx->med_pos, (size_t)Px * 4, st))) return rc;
-  if (surfel && (rc = ensure(ctx, ctx->dist_aux, (size_t)Px * 12, st))) return rc;
+  if (surfel && (rc = ensure(ctx, ctx->dist_aux, (size_t)Px * 16, st))) return rc;
   uint64_t* d_count = P<uint64_t>(ctx->counters);               // [0] = K
   uint32_t* d_overflow = (uint32_t*)(P<uint64_t>(ctx->counters) + 1);
   const bool timing = (s->flags & GSR_FLAG_TIMING) != 0;

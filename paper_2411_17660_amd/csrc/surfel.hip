@@ -229,7 +229,7 @@ __global__ void __launch_bounds__(64) surfel_fwd_kernel(
     const uint32_t* __restrict__ vals, const Surfel* __restrict__ rec, float bg0, float bg1,
     float bg2, float* __restrict__ rgb, float* __restrict__ depth, float* __restrict__ alpha,
     float* __restrict__ normal, float* __restrict__ dist, float* __restrict__ t_final,
-    int32_t* __restrict__ n_last, float* __restrict__ dist_aux /* [P][3]: z_ref, D_1, D_2 */) {
+    int32_t* __restrict__ n_last, float* __restrict__ dist_aux /* [P][4]: z_ref, A, D_1, D_2 */) {
   constexpr int PIX = TW * TH / kWave;
   constexpr int RPP = kWave / TW;
   __shared__ Surfel sm[kWave];
@@ -244,7 +244,11 @@ __global__ void __launch_bounds__(64) surfel_fwd_kernel(
   const int ly = lane / TW;
   const uint2 rg = ranges[tile];
   float T[PIX], C0[PIX], C1[PIX], C2[PIX], D[PIX], N0[PIX], N1[PIX], N2[PIX];
-  float ZR[PIX], S1[PIX], S2[PIX], DS[PIX];
+  // distortion sums in FP64: the backward's weights e_i = A z_i^2 -
+  // 2 z_i D_1 + D_2 and z_i A - D_1 cancel where the entries lie at one
+  // depth, which FP32 sums over hundreds of entries cannot resolve
+  float ZR[PIX];
+  double SA[PIX], S1[PIX], S2[PIX], DS[PIX];
   int last[PIX];
   bool done[PIX];
   uint32_t hits = 0;
@@ -252,7 +256,8 @@ __global__ void __launch_bounds__(64) surfel_fwd_kernel(
   for (int k = 0; k < PIX; ++k) {
     T[k] = 1.0f;
     C0[k] = C1[k] = C2[k] = D[k] = N0[k] = N1[k] = N2[k] = 0.0f;
-    ZR[k] = S1[k] = S2[k] = DS[k] = 0.0f;
+    ZR[k] = 0.0f;
+    SA[k] = S1[k] = S2[k] = DS[k] = 0.0;
     last[k] = 0;
     const int py = y0 + k * RPP + ly;
     done[k] = !(px < fr.width && py < fr.height);
@@ -295,10 +300,11 @@ __global__ void __launch_bounds__(64) surfel_fwd_kernel(
         N1[k] += S.n1 * w;
         N2[k] += S.n2 * w;
         if (last[k] == 0) ZR[k] = h.z;
-        const float zp = h.z - ZR[k];
-        DS[k] += w * ((1.0f - T[k]) * zp * zp - 2.0f * zp * S1[k] + S2[k]);
-        S1[k] += w * zp;
-        S2[k] += w * zp * zp;
+        const double zp = h.z - ZR[k], wd = w;
+        DS[k] += wd * (SA[k] * zp * zp - 2.0 * zp * S1[k] + S2[k]);
+        SA[k] += wd;
+        S1[k] += wd * zp;
+        S2[k] += wd * zp * zp;
         T[k] = Tn;
         last[k] = (int)(b + j + 1 - rg.x);
       }
@@ -338,21 +344,25 @@ __global__ void __launch_bounds__(64) surfel_fwd_kernel(
       alpha[fr.pixel_offset + p] = 1.0f - T[k];
       t_final[fr.pixel_offset + p] = T[k];
       n_last[fr.pixel_offset + p] = last[k];
-      dist[fr.pixel_offset + p] = DS[k];
-      float* ax = dist_aux + 3 * (fr.pixel_offset + p);
-      ax[0] = ZR[k];
-      ax[1] = S1[k];
-      ax[2] = S2[k];
+      dist[fr.pixel_offset + p] = (float)DS[k];
+      float4* ax = reinterpret_cast<float4*>(dist_aux) + (fr.pixel_offset + p);
+      *ax = make_float4(ZR[k], (float)SA[k], (float)S1[k], (float)S2[k]);
     }
   }
 }
 
-// Per key (one surfel in one tile), the values the backward reduces, in this
-// order: S_hu[3] = sum dL/dh_u, S_hv[3] = sum dL/dh_v, G_M2[3] = the direct
-// gradient of M2 = sum (x - c_x) dL/dh_u + (y - c_y) dL/dh_v + dL/dz (u, v, 1),
-// G_c[2] = the low-pass term's gradient of the centre c, the opacity, the
-// colour[3] and the normal[3].
-constexpr int kSG = 18;
+// Per key (one surfel in one tile), the values the backward reduces: the
+// gradients of the columns A = s_u t_u, B = s_v t_v and mc of
+// M = K [A | B | mc], as sums the chain rule only scales.  With h_u =
+// x M2 - M0, h_v = y M2 - M1 and (o_x, o_y) = (x - c_x^K, y - c_y^K) the
+// pixel's offset from the principal point, column j's gradient is
+//   (-f_x S_u[j], -f_y S_v[j], R[j]),  S_u = sum dL/dh_u, S_v = sum dL/dh_v,
+//   R[j] = sum o_x dL/dh_u[j] + o_y dL/dh_v[j] + dL/dz (u, v, 1)[j],
+// so no large product of a pixel position with a sum is left to cancel in
+// the chain rule.  The low-pass term's gradient of the centre c =
+// (M0_z, M1_z) / M2_z folds into column 2.  Order: S_u[3], S_v[3], R[3],
+// opacity, colour[3], normal[3].
+constexpr int kSG = 16;
 
 template <int TW, int TH>
 __global__ void __launch_bounds__(64) surfel_bwd_kernel(
@@ -402,10 +412,12 @@ __global__ void __launch_bounds__(64) surfel_bwd_kernel(
     const int64_t q = fr.pixel_offset + p;
     last[k] = valid ? n_last[q] : 0;
     T[k] = valid ? t_final[q] : 1.0f;
-    AT[k] = 1.0f - T[k];
-    ZR[k] = valid ? dist_aux[3 * q] : 0.0f;
-    S1[k] = valid ? dist_aux[3 * q + 1] : 0.0f;
-    S2[k] = valid ? dist_aux[3 * q + 2] : 0.0f;
+    const float4 ax = valid ? reinterpret_cast<const float4*>(dist_aux)[q]
+                            : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    ZR[k] = ax.x;
+    AT[k] = ax.y;
+    S1[k] = ax.z;
+    S2[k] = ax.w;
     BC0[k] = bg0; BC1[k] = bg1; BC2[k] = bg2;
     BD[k] = BN0[k] = BN1[k] = BN2[k] = BE[k] = 0.0;
     BT[k] = 1.0f;
@@ -461,9 +473,9 @@ __global__ void __launch_bounds__(64) surfel_bwd_kernel(
         float Ti = T[k] * inv;
         Ti = __builtin_fmaf(__builtin_fmaf(-Ti, om, T[k]), inv, Ti);  // Newton step
         const float w = a * Ti;
-        const float zp = h.z - ZR[k];
+        const double zp = h.z - ZR[k];
         // dDist/dw_i: sum over the other entries m of w_m (z_i - z_m)^2
-        const double e = (double)AT[k] * zp * zp - 2.0 * zp * S1[k] + S2[k];
+        const double e = AT[k] * zp * zp - 2.0 * zp * S1[k] + S2[k];
         const double ad = a;
         const double d0 = S.c0 - BC0[k], d1 = S.c1 - BC1[k], d2 = S.c2 - BC2[k];
         const double dz = h.z - BD[k], de = e - BE[k];
@@ -472,14 +484,14 @@ __global__ void __launch_bounds__(64) surfel_bwd_kernel(
             Ti * (G0[k] * (float)d0 + G1[k] * (float)d1 + G2[k] * (float)d2 +
                   GD[k] * (float)dz + GN0[k] * (float)dn0 + GN1[k] * (float)dn1 +
                   GN2[k] * (float)dn2 + GE[k] * (float)de + GA[k] * BT[k]);
-        acc[12] += G0[k] * w;
-        acc[13] += G1[k] * w;
-        acc[14] += G2[k] * w;
-        acc[15] += GN0[k] * w;
-        acc[16] += GN1[k] * w;
-        acc[17] += GN2[k] * w;
+        acc[10] += G0[k] * w;
+        acc[11] += G1[k] * w;
+        acc[12] += G2[k] * w;
+        acc[13] += GN0[k] * w;
+        acc[14] += GN1[k] * w;
+        acc[15] += GN2[k] * w;
         // dL/dz_i: the depth map and the distortion, 2 w_i sum_m w_m (z_i - z_m)
-        const float dzv = w * (GD[k] + 2.0f * GE[k] * (zp * AT[k] - S1[k]));
+        const float dzv = w * (GD[k] + (float)(2.0 * GE[k] * (zp * AT[k] - S1[k])));
         BC0[k] = __builtin_fma(ad, d0, BC0[k]);
         BC1[k] = __builtin_fma(ad, d1, BC1[k]);
         BC2[k] = __builtin_fma(ad, d2, BC2[k]);
@@ -493,37 +505,50 @@ __global__ void __launch_bounds__(64) surfel_bwd_kernel(
         any = true;
         const bool clamped = sg > kAlphaMax;  // clamped: alpha does not move
         const float dGh = clamped ? 0.0f : dLda * S.opacity;
-        if (!clamped) acc[11] += dLda * h.Gh;
+        if (!clamped) acc[9] += dLda * h.Gh;
         if (h.obj) {
-          // z = M2 . (u, v, 1), G = exp(-(u^2 + v^2)/2), (u, v) = (p0, p1) / p2
-          const float gu = -h.u * h.Gh * dGh + dzv * S.m2x;
-          const float gv = -h.v * h.Gh * dGh + dzv * S.m2y;
-          acc[6] += h.u * dzv;
-          acc[7] += h.v * dzv;
-          acc[8] += dzv;
-          const float ip = h.ip2;
-          const float dp0 = gu * ip, dp1 = gv * ip, dp2 = -(gu * h.u + gv * h.v) * ip;
+          // z = M2 . (u, v, 1), G = exp(-(u^2 + v^2)/2), (u, v) = (p0, p1) / p2.
+          // The chain through the intersection runs in FP64: its FP32
+          // rounding is amplified by the conditioning 1/sin of the two
+          // planes, squared for a derivative, and a tilted surfel's
+          // per-pixel terms cancel in its rotation gradient.  h_u, h_v are
+          // rebuilt from the stored FP32 values (the products are exact in
+          // FP64); G and the decisions are the forward's.
+          const double ex = h.ex, ey = h.ey;
+          const double hux = ex * S.m2x + S.kux, huy = ex * S.m2y + S.kuy, huz = ex * S.zc;
+          const double hvx = ey * S.m2x + S.kvx, hvy = ey * S.m2y + S.kvy, hvz = ey * S.zc;
+          const double p0 = huy * hvz - huz * hvy, p1 = huz * hvx - hux * hvz;
+          const double ip = 1.0 / (hux * hvy - huy * hvx);
+          const double u = p0 * ip, v = p1 * ip;
+          const double gGd = (double)h.Gh * dGh, dzd = dzv;
+          const double gu = -u * gGd + dzd * S.m2x;
+          const double gv = -v * gGd + dzd * S.m2y;
+          const double ox = (double)px - fr.cx, oy = (double)py - fr.cy;
+          const double dp0 = gu * ip, dp1 = gv * ip, dp2 = -(gu * u + gv * v) * ip;
           // p = h_u x h_v: dL/dh_u = h_v x dL/dp, dL/dh_v = dL/dp x h_u
-          const float a0 = h.hvy * dp2 - h.hvz * dp1, a1 = h.hvz * dp0 - h.hvx * dp2,
-                      a2 = h.hvx * dp1 - h.hvy * dp0;
-          const float b0 = dp1 * h.huz - dp2 * h.huy, b1 = dp2 * h.hux - dp0 * h.huz,
-                      b2 = dp0 * h.huy - dp1 * h.hux;
-          acc[0] += a0;
-          acc[1] += a1;
-          acc[2] += a2;
-          acc[3] += b0;
-          acc[4] += b1;
-          acc[5] += b2;
-          // h_u = (x - c_x) M2 + k_u, h_v = (y - c_y) M2 + k_v
-          acc[6] += h.ex * a0 + h.ey * b0;
-          acc[7] += h.ex * a1 + h.ey * b1;
-          acc[8] += h.ex * a2 + h.ey * b2;
+          const double a0 = hvy * dp2 - hvz * dp1, a1 = hvz * dp0 - hvx * dp2,
+                       a2 = hvx * dp1 - hvy * dp0;
+          const double b0 = dp1 * huz - dp2 * huy, b1 = dp2 * hux - dp0 * huz,
+                       b2 = dp0 * huy - dp1 * hux;
+          acc[0] += (float)a0;
+          acc[1] += (float)a1;
+          acc[2] += (float)a2;
+          acc[3] += (float)b0;
+          acc[4] += (float)b1;
+          acc[5] += (float)b2;
+          acc[6] += (float)(ox * a0 + oy * b0 + u * dzd);
+          acc[7] += (float)(ox * a1 + oy * b1 + v * dzd);
+          acc[8] += (float)(ox * a2 + oy * b2 + dzd);
         } else {
-          // the low-pass: z = z_c, G_lp = exp(-|(x, y) - c|^2)
-          acc[8] += dzv;
-          const float t = 2.0f * h.Gh * dGh;
-          acc[9] += t * h.ex;
-          acc[10] += t * h.ey;
+          // the low-pass: z = z_c, G_lp = exp(-|(x, y) - c|^2); its gradient
+          // of c reaches M0_z, M1_z (S_u[2], S_v[2]) and, with the principal
+          // point's share, R[2]
+          const float t = 2.0f * h.Gh * dGh / S.zc;
+          const float gx = t * h.ex, gy = t * h.ey;
+          acc[2] -= gx;
+          acc[5] -= gy;
+          const float ocx = (S.cxh - fr.cx) + S.cxl, ocy = (S.cyh - fr.cy) + S.cyl;
+          acc[8] += dzv - (gx * ocx + gy * ocy);
         }
       }
       if (__ballot(any) == 0) continue;
@@ -590,9 +615,8 @@ __global__ void __launch_bounds__(256) surfel_slot_reduce_kernel(
 }
 
 // Chain rule from the per-key sums to the parameters (FP64), per surfel and
-// frame: the record's sum of its key partials gives dL/dM (M0 = -S_hu, M1 = -S_hv, M2 = G_M2 + c_x S_hu + c_y S_hv from
-// h_u = x M2 - M0, plus the low-pass term through c = (M0_z, M1_z) / M2_z),
-// then the columns of M = K [A | B | mc]: A = s_u t_u, B = s_v t_v,
+// frame: the record's sum of its key partials gives the gradients of the
+// columns of M = K [A | B | mc]: A = s_u t_u, B = s_v t_v,
 // mc = R_f mu + t_f, t_u, t_v, t_w the camera-frame axes R_f R_g.  The pose
 // twist (rho, phi) moves every camera-frame vector y by phi x y and mc by
 // rho as well, so dL/dphi = sum y x dL/dy.
@@ -650,24 +674,13 @@ __global__ void __launch_bounds__(256) surfel_preprocess_bwd_kernel(
           T[i * 3 + j] = W[i * 3 + 0] * Rg[0 * 3 + j] + W[i * 3 + 1] * Rg[1 * 3 + j] +
                          W[i * 3 + 2] * Rg[2 * 3 + j];
       }
-      const double fx = fr.fx, fy = fr.fy, cx = fr.cx, cy = fr.cy;
-      const double M0z = fx * mc[0] + cx * mc[2], M1z = fy * mc[1] + cy * mc[2], M2z = mc[2];
-      const double ccx = M0z / M2z, ccy = M1z / M2z;
-      double dM0[3], dM1[3], dM2[3];
-      for (int i = 0; i < 3; ++i) {
-        dM0[i] = -K[i];
-        dM1[i] = -K[3 + i];
-        dM2[i] = K[6 + i] + ccx * K[i] + ccy * K[3 + i];
-      }
-      dM0[2] += K[9] / M2z;
-      dM1[2] += K[10] / M2z;
-      dM2[2] -= (K[9] * ccx + K[10] * ccy) / M2z;
-      // column j of M is K times (A, B, mc)[j]
+      const double fx = fr.fx, fy = fr.fy;
+      // gradients of the columns A, B, mc of M = K [A | B | mc]
       double dcol[3][3];
       for (int j = 0; j < 3; ++j) {
-        dcol[j][0] = fx * dM0[j];
-        dcol[j][1] = fy * dM1[j];
-        dcol[j][2] = cx * dM0[j] + cy * dM1[j] + dM2[j];
+        dcol[j][0] = -fx * K[j];
+        dcol[j][1] = -fy * K[3 + j];
+        dcol[j][2] = K[6 + j];
       }
       const double tu[3] = {T[0], T[3], T[6]}, tv[3] = {T[1], T[4], T[7]};
       const double tn[3] = {T[2], T[5], T[8]};
@@ -676,7 +689,7 @@ __global__ void __launch_bounds__(256) surfel_preprocess_bwd_kernel(
       for (int i = 0; i < 3; ++i) {
         dT[0][i] = su * dcol[0][i];
         dT[1][i] = sv * dcol[1][i];
-        dT[2][i] = sgn * K[15 + i];
+        dT[2][i] = sgn * K[13 + i];
       }
       dls[0] += su * (dcol[0][0] * tu[0] + dcol[0][1] * tu[1] + dcol[0][2] * tu[2]);
       dls[1] += sv * (dcol[1][0] * tv[0] + dcol[1][1] * tv[1] + dcol[1][2] * tv[2]);
@@ -685,7 +698,7 @@ __global__ void __launch_bounds__(256) surfel_preprocess_bwd_kernel(
         for (int j = 0; j < 3; ++j)
           dR[i * 3 + j] += W[0 * 3 + i] * dT[j][0] + W[1 * 3 + i] * dT[j][1] +
                            W[2 * 3 + i] * dT[j][2];
-      dop += K[11];
+      dop += K[9];
       // colour: c = max(0, raw), raw = sum_k sh_k Y_k(dir) + 1/2
       double dir[3];
       const double dist = view_dir(W, tf, mu, dir);
@@ -695,7 +708,7 @@ __global__ void __launch_bounds__(256) surfel_preprocess_bwd_kernel(
       for (int k = 0; k < nb; ++k)
         for (int c = 0; c < 3; ++c) raw[c] += (double)shg[k * 3 + c] * Y[k];
       double draw[3];
-      for (int c = 0; c < 3; ++c) draw[c] = raw[c] + 0.5 > 0.0 ? K[12 + c] : 0.0;
+      for (int c = 0; c < 3; ++c) draw[c] = raw[c] + 0.5 > 0.0 ? K[10 + c] : 0.0;
       double wk[16];
       for (int k = 0; k < nb; ++k) {
         double acc = 0.0;

@@ -65,7 +65,7 @@ def expand_rgb_mask(px_mask, sizes):
     return np.concatenate(out)
 
 
-def grad_bound(ref, rel=GRAD_REL):
+def grad_bound(ref, rel=GRAD_REL, block=1e-2):
     """Per-element bound rel * max(|g*|, 1e-2 |g*_block|, 1e-2 rms(g*)).
 
     ref has the Gaussian (or frame) index first; its block is that row, the
@@ -74,14 +74,14 @@ def grad_bound(ref, rel=GRAD_REL):
     cancels to below 1 % of its own group (the quaternion gradient after its
     tangent projection, one colour channel against the other two) is held to
     rel * 1e-2 of the group's norm: FP32 arithmetic errs in proportion to the
-    group, not to the component."""
+    group, not to the component.  `block` sets that share (1e-2)."""
     ref = np.asarray(ref, np.float64)
     n = ref.shape[0] if ref.ndim else 1
     rows = ref.reshape(n, -1) if n else ref.reshape(0, 1)
     blk = np.repeat(np.sqrt((rows ** 2).sum(1)), rows.shape[1])
     flat = rows.ravel()
     rms = np.sqrt(np.mean(flat ** 2)) if flat.size else 0.0
-    return rel * np.maximum(np.maximum(np.abs(flat), 1e-2 * blk), 1e-2 * rms)
+    return rel * np.maximum(np.maximum(np.abs(flat), block * blk), 1e-2 * rms)
 
 
 PIXEL_REL = 1e-6   # modelled relative error of one pixel's FP32 contribution
@@ -103,12 +103,12 @@ def noise_floor(ref, G, g_ref):
     return {k: np.abs(g2[k] - g_ref[k]) for k in g_ref}
 
 
-def assert_grad_close(name, got, ref, rel=GRAD_REL, noise=None):
+def assert_grad_close(name, got, ref, rel=GRAD_REL, noise=None, block=1e-2):
     """|got - ref| <= max(rel * max(|g*|, 1e-2 |g*_block|, 1e-2 rms), 3 * noise):
     the second term admits elements whose value the chain rule makes
     sensitive to per-pixel FP32 rounding (a quadratic form in an indefinite
     covariance gradient, a near-plane Gaussian), measured on the oracle."""
-    bound = grad_bound(ref, rel)
+    bound = grad_bound(ref, rel, block)
     if noise is not None:
         bound = np.maximum(bound, NOISE_MULT * np.asarray(noise, np.float64).ravel())
     got = np.asarray(got, np.float64).ravel()

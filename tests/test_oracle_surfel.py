@@ -395,3 +395,17 @@ def test_normal_consistency_autograd_matches_central_differences():
     nm = S.to64(rng.normal(size=(3, 7, 9)), True)
     f = lambda D, a, nm: S.normal_consistency(D, a, nm, cam)[0]       # noqa: E731
     assert torch.autograd.gradcheck(f, (D, a, nm), eps=1e-7, atol=1e-7, rtol=1e-6)
+
+
+def test_window_equals_the_whole_image_cropped():
+    from paper_2411_17660_amd import scenes
+    sc = _tiny(6, n=20, F=2)
+    ls = sc.log_scales[:, :2]
+    full = _render(sc.means, ls, sc.quats, sc.opacity, sc.sh, 1, sc.cams, sc.poses, sc.background)
+    win = S.render(*[S.to64(a) for a in (sc.means, ls, sc.quats, sc.opacity, sc.sh)], 1, sc.cams,
+                   S.to64(sc.poses), sc.background, window=(5, 17, 3, 11))
+    for a, b in zip(full, win):
+        for k in ("rgb", "depth", "alpha", "normal", "dist"):
+            assert np.array_equal(a[k].numpy()[..., 3:12, 5:18], b[k].numpy()), k
+        assert np.array_equal(a["flags"][3:12, 5:18], b["flags"])
+        assert np.array_equal(a["box"], b["box"])

@@ -581,7 +581,10 @@ gsr_status gsr_backward_surfel(gsr_context* ctx, const float* g_rgb, const float
   gsr_status rc;
   const size_t ng = (size_t)surfel_grad_values();
   const uint64_t M = (uint64_t)sv.n * sv.F;
-  if ((rc = ensure(ctx, ctx->spart, std::max<uint64_t>(ctx->key_cap, 1) * ng * 4, st))) return rc;
+  // slots of this forward's keys only (sv.K: its key count, or the fixed
+  // capacity it ran with); keygen marked records past it as overflowed
+  const uint64_t kcap = std::min<uint64_t>(sv.K, ctx->key_cap);
+  if ((rc = ensure(ctx, ctx->spart, std::max<uint64_t>(kcap, 1) * ng * 4, st))) return rc;
   if ((rc = ensure(ctx, ctx->sgrad, std::max<uint64_t>(M, 1) * ng * 8, st))) return rc;
   if ((rc = ensure(ctx, ctx->cls_a, M * 4, st))) return rc;
   if ((rc = ensure(ctx, ctx->cls_b, M * 4, st))) return rc;
@@ -618,11 +621,11 @@ gsr_status gsr_backward_surfel(gsr_context* ctx, const float* g_rgb, const float
     launch_surfel_slot_reduce(st, M, P<uint32_t>(cls_in_b ? ctx->clsv_b : ctx->clsv_a),
                               P<uint32_t>(ctx->keyoff), P<uint32_t>(ctx->ntiles),
                               P<float>(ctx->spart), P<uint32_t>(ctx->stamp), d_epoch,
-                              ctx->key_cap, P<double>(ctx->sgrad));
+                              kcap, P<double>(ctx->sgrad));
     launch_surfel_preprocess_bwd(st, sv.n, sv.F, P<FrameDesc>(ctx->frames), sv.poses, sv.means,
                                  sv.log_scales, sv.quats, sv.opac, sv.sh, s.sh_degree,
                                  P<uint32_t>(ctx->ntiles), P<uint32_t>(ctx->keyoff),
-                                 P<double>(ctx->sgrad), ctx->key_cap, g_means, g_log_scales,
+                                 P<double>(ctx->sgrad), kcap, g_means, g_log_scales,
                                  g_quats, g_opac, g_sh, P<double>(ctx->twist_part), g_twist);
   }
   GSR_HIP(hipGetLastError());

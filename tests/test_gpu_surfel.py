@@ -410,3 +410,73 @@ def test_surfel_graph_captured_step_replays_match_eager():
         torch.cuda.synchronize()
     r.check_overflow()
     assert float(imgs[2].max()) > 0.5
+
+
+def _run_surfel(rast, sc, **kw):
+    d = to_dev(sc)
+    outs = rast.forward_surfel(d["means"], d["log_scales"], d["quats"], d["opacity"], d["sh"],
+                               d["poses"], sc.cams, sc.sh_degree, sc.background, **kw)
+    torch.cuda.synchronize()
+    rast._inputs = d
+    return [x.clone() for x in outs]
+
+
+def _zero_upstream(sc):
+    P = sc.n_pixels
+    return [torch.randn(k, device="cuda") for k in (3 * P, P, P, 3 * P, P)]
+
+
+def test_surfel_empty_scene(rast):
+    """n = 0: background, zero depth, alpha, normal and distortion; the
+    backward writes only the (zero) twist."""
+    sc = _surfel_scene(30, 1, 40, 30, 32.0, 2, 1)
+    sc = scenes.Scene(sc.means[:0], sc.log_scales[:0], sc.quats[:0], sc.opacity[:0], sc.sh[:0],
+                      1, sc.cams, sc.poses, (0.25, 0.5, 0.75))
+    rgb, dep, alp, nrm, dst = _run_surfel(rast, sc)
+    P = 40 * 30
+    r = rgb.cpu().numpy().reshape(2, 3, P)
+    for c in range(3):
+        assert np.all(r[:, c] == np.float32(sc.background[c]))
+    for x in (dep, alp, nrm, dst):
+        assert torch.all(x == 0)
+    g = rast.backward_surfel(*_zero_upstream(sc))
+    torch.cuda.synchronize()
+    assert g["means"].shape == (0, 3) and torch.all(g["twist"] == 0)
+
+
+def test_surfel_everything_culled(rast):
+    """Every surfel behind every camera: no keys, background images, zero
+    gradients everywhere."""
+    sc = _surfel_scene(31, 150, 48, 32, 38.0, 2, 2)
+    sc.means[:, 2] = -5.0
+    rgb, dep, alp, nrm, dst = _run_surfel(rast, sc)
+    assert rast.stats()["n_keys"] == 0
+    assert torch.all(alp == 0) and torch.all(dst == 0) and torch.all(nrm == 0)
+    g = rast.backward_surfel(*_zero_upstream(sc))
+    torch.cuda.synchronize()
+    for k, v in g.items():
+        assert torch.all(v == 0), k
+
+
+def test_surfel_fixed_capacity_and_overflow(rast):
+    """A fixed key capacity equal to the key count gives the grown images
+    bitwise; a third of it overflows, which gsr_check_overflow reports
+    (GSR_ERR_CAPACITY) and then clears; the backward after the overflow
+    stays finite (overflowed surfels' keys never reach the kernels)."""
+    from paper_2411_17660_amd import native
+    sc = _surfel_scene(32, 800, 96, 64, 76.8, 2, 1)
+    a = _run_surfel(rast, sc)
+    K = rast.stats()["n_keys"]
+    b = _run_surfel(rast, sc, key_capacity=K)
+    rast.check_overflow()
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    _run_surfel(rast, sc, key_capacity=max(1, K // 3))
+    g = rast.backward_surfel(*_zero_upstream(sc))
+    torch.cuda.synchronize()
+    for k, v in g.items():
+        assert torch.isfinite(v).all(), k
+    with pytest.raises(native.GsrError) as ei:
+        rast.check_overflow()
+    assert ei.value.status == 2
+    rast.check_overflow()

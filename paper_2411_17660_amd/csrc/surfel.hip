@@ -518,7 +518,12 @@ __global__ void __launch_bounds__(64) surfel_bwd_kernel(
           const double hux = ex * S.m2x + S.kux, huy = ex * S.m2y + S.kuy, huz = ex * S.zc;
           const double hvx = ey * S.m2x + S.kvx, hvy = ey * S.m2y + S.kvy, hvz = ey * S.zc;
           const double p0 = huy * hvz - huz * hvy, p1 = huz * hvx - hux * hvz;
-          const double ip = 1.0 / (hux * hvy - huy * hvx);
+          // 1/p2: hardware reciprocal and two Newton steps (FP64 accuracy;
+          // p2 != 0 where the disk term was blended)
+          const double p2 = hux * hvy - huy * hvx;
+          double ip = __builtin_amdgcn_rcp(p2);
+          ip = __builtin_fma(__builtin_fma(-p2, ip, 1.0), ip, ip);
+          ip = __builtin_fma(__builtin_fma(-p2, ip, 1.0), ip, ip);
           const double u = p0 * ip, v = p1 * ip;
           const double gGd = (double)h.Gh * dGh, dzd = dzv;
           const double gu = -u * gGd + dzd * S.m2x;

@@ -106,7 +106,8 @@ def _check(rast, sc, tile, label):
 
 @pytest.mark.parametrize("seed,n,frames,deg,W,H,tile", [
     (0, 60, 1, 0, 48, 32, (16, 16)), (1, 300, 2, 3, 97, 61, (8, 8)),
-    (2, 800, 3, 1, 130, 70, (32, 8)), (3, 500, 2, 2, 33, 17, (32, 16))])
+    (2, 800, 3, 1, 130, 70, (32, 8)), (3, 500, 2, 2, 33, 17, (32, 16)),
+    (4, 400, 2, 3, 75, 43, (16, 8))])
 def test_surfel_forward_matches_oracle(rast, seed, n, frames, deg, W, H, tile):
     sc = _surfel_scene(seed, n, W, H, 0.8 * W, frames, deg)
     _check(rast, sc, tile, f"surfels{seed}")
@@ -122,7 +123,7 @@ def test_surfel_images_do_not_depend_on_tile_shape(rast):
     sc = _surfel_scene(8, 1200, 150, 90, 110.0, 2, 3)
     d = to_dev(sc)
     outs = []
-    for tile in ((16, 16), (8, 8), (32, 16)):
+    for tile in ((16, 16), (8, 8), (32, 8), (16, 8), (32, 16)):
         o = rast.forward_surfel(d["means"], d["log_scales"], d["quats"], d["opacity"], d["sh"],
                                 d["poses"], sc.cams, sc.sh_degree, sc.background, tile=tile)
         torch.cuda.synchronize()
@@ -228,7 +229,7 @@ def _check_backward(rast, sc, tile, seed, label):
 @pytest.mark.parametrize("seed,n,frames,deg,W,H,tile", [
     (20, 40, 1, 0, 40, 30, (16, 16)), (21, 150, 2, 3, 61, 45, (8, 8)),
     (22, 250, 2, 1, 70, 50, (32, 8)), (23, 120, 1, 2, 33, 17, (32, 16)),
-    (24, 700, 1, 3, 96, 64, (16, 16))])
+    (24, 700, 1, 3, 96, 64, (16, 16)), (25, 200, 2, 1, 57, 39, (16, 8))])
 def test_surfel_backward_matches_oracle_autograd(rast, seed, n, frames, deg, W, H, tile):
     sc = _surfel_scene(seed, n, W, H, 0.8 * W, frames, deg)
     _check_backward(rast, sc, tile, seed, f"surfels{seed}")

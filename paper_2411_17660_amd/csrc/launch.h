@@ -32,6 +32,7 @@ void launch_size_class(hipStream_t st, uint64_t m, const uint32_t* ntiles, uint3
 void launch_fill_u32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t v);
 size_t radix_hist_elems(uint64_t n_max);
 size_t scan_block_elems(uint64_t n_max);
+size_t radix_scan_elems(uint64_t n_max);
 bool launch_radix_sort(hipStream_t st, uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b,
                        uint32_t* vals_b, const uint64_t* n_dev, uint64_t n_max, int bits,
                        uint32_t* hist, uint32_t* scan_tmp);

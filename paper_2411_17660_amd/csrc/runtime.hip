@@ -382,8 +382,10 @@ gsr_status forward_impl(gsr_context* ctx, const gsr_settings* s, int64_t n, cons
   const uint64_t kcap_guess = std::max<uint64_t>(ctx->key_cap, s->key_capacity);
   const size_t hist_need = std::max(radix_hist_elems(M), radix_hist_elems(std::max<uint64_t>(kcap_guess, 1)));
   if ((rc = ensure(ctx, ctx->hist, hist_need * 4, st))) return rc;
-  const size_t scan_need = std::max(scan_block_elems(M), scan_block_elems(hist_need));
-  if ((rc = ensure(ctx, ctx->scan_tmp, scan_need * 8, st))) return rc;
+  const size_t scan_need =
+      std::max(scan_block_elems(M) * 8,
+               radix_scan_elems(std::max<uint64_t>(M, std::max<uint64_t>(kcap_guess, 1))) * 4);
+  if ((rc = ensure(ctx, ctx->scan_tmp, scan_need, st))) return rc;
   bool recs_in_b = false;
   {
     StageTimer t(ctx, st, timing, GSR_STAGE_DEPTH_SORT);
@@ -427,7 +429,9 @@ gsr_status forward_impl(gsr_context* ctx, const gsr_settings* s, int64_t n, cons
                              ctx->stamp.bytes / 4});
     const size_t h2 = radix_hist_elems(ctx->key_cap);
     if ((rc = ensure(ctx, ctx->hist, h2 * 4, st))) return rc;
-    if ((rc = ensure(ctx, ctx->scan_tmp, std::max(scan_block_elems(M), scan_block_elems(h2)) * 8,
+    if ((rc = ensure(ctx, ctx->scan_tmp,
+                     std::max(scan_block_elems(M) * 8,
+                              radix_scan_elems(std::max<uint64_t>(M, ctx->key_cap)) * 4),
                      st)))
       return rc;
   }

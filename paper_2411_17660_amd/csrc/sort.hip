@@ -17,10 +17,14 @@
 // The radix passes use a hand-written LDS multi-split: each wave ranks its
 // 64 keys per round with 8 ballots (one per digit bit), keeps running digit
 // counts in LDS, and the block combines the 4 waves' counts into stable
-// block offsets; no global atomics.  Scans are reduce-then-scan in 3
-// launches.  All kernels read the element count from device memory so the
-// sequence is capturable.
+// block offsets; no global atomics.  A pass's digit counts are stored one
+// 1 KB row per block, so the histogram writes and the scatter reads them as
+// whole rows, and their scan runs down the columns (3 launches); the other
+// scans are reduce-then-scan in 3 launches.  All kernels read the element
+// count from device memory so the sequence is capturable.
 #include "launch.h"
+
+#include <algorithm>
 
 namespace gsr {
 
@@ -152,7 +156,7 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
 // its wave's LDS counters with atomics; the four wave histograms are summed.
 __global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(
     const uint32_t* __restrict__ keys, const uint64_t* n_dev, uint64_t n_host, int shift,
-    uint32_t* __restrict__ hist /* [256][nblocks] */) {
+    uint32_t* __restrict__ hist /* [nblocks][256] */) {
   __shared__ uint32_t wcnt[kSortWaves][kRadixBins];
   const uint64_t n = n_dev ? min(*n_dev, n_host) : n_host;
   const int w = threadIdx.x / kWave;
@@ -178,13 +182,89 @@ __global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(
   const int d = threadIdx.x;
   uint32_t c = 0;
   for (int ww = 0; ww < kSortWaves; ++ww) c += wcnt[ww][d];
-  hist[(uint64_t)d * gridDim.x + blockIdx.x] = c;
+  hist[(uint64_t)blockIdx.x * kRadixBins + d] = c;
+}
+
+// Exclusive offsets from the block-major counts H[b][d]: the scatter of block
+// b puts its digit-d keys at sum_{d' < d} total(d') + sum_{b' < b} H[b'][d],
+// the exclusive scan of the counts taken in (digit, block) order.  The blocks
+// are cut into chunks of `rows`; one thread per digit walks a chunk's rows,
+// so every access is a whole 1 KB row.  Rows are loaded kColBatch at a time
+// so that a thread's serial walk waits on one load latency per batch.
+constexpr unsigned kColMinRows = 128, kColMaxChunks = 1024;
+constexpr int kColBatch = 16;
+static_assert(kRadixBins == kScanThreads, "one scan thread per digit");
+
+static inline unsigned col_rows(unsigned nb) {
+  return std::max(kColMinRows, (nb + kColMaxChunks - 1) / kColMaxChunks);
+}
+
+// csum[c][d] = sum of H[b][d] over the rows b of chunk c
+__global__ void __launch_bounds__(kRadixBins) radix_colsum_kernel(
+    const uint32_t* __restrict__ hist, unsigned nb, unsigned rows, uint32_t* __restrict__ csum) {
+  const unsigned d = threadIdx.x;
+  const unsigned b0 = blockIdx.x * rows, b1 = min(nb, b0 + rows);
+  uint32_t s = 0;
+  for (unsigned b = b0; b < b1; b += kColBatch) {
+    uint32_t v[kColBatch];
+#pragma unroll
+    for (int j = 0; j < kColBatch; ++j)
+      v[j] = b + j < b1 ? hist[(uint64_t)(b + j) * kRadixBins + d] : 0u;
+#pragma unroll
+    for (int j = 0; j < kColBatch; ++j) s += v[j];
+  }
+  csum[(uint64_t)blockIdx.x * kRadixBins + d] = s;
+}
+
+// One block: csum[c][d] becomes the exclusive scan over chunks of digit d;
+// row nc receives the exclusive scan of the digit totals.
+__global__ void __launch_bounds__(kRadixBins) radix_colspine_kernel(uint32_t* __restrict__ csum,
+                                                                    unsigned nc) {
+  __shared__ uint32_t sh[kScanThreads];
+  const unsigned d = threadIdx.x;
+  uint32_t run = 0;
+  for (unsigned c = 0; c < nc; c += kColBatch) {
+    uint32_t v[kColBatch];
+#pragma unroll
+    for (int j = 0; j < kColBatch; ++j)
+      v[j] = c + j < nc ? csum[(uint64_t)(c + j) * kRadixBins + d] : 0u;
+#pragma unroll
+    for (int j = 0; j < kColBatch; ++j)
+      if (c + j < nc) {
+        csum[(uint64_t)(c + j) * kRadixBins + d] = run;
+        run += v[j];
+      }
+  }
+  uint32_t total;
+  const uint32_t base = block_exclusive_scan<uint32_t>(run, sh, total);
+  csum[(uint64_t)nc * kRadixBins + d] = base;
+}
+
+// H[b][d] becomes block b's global start of digit d
+__global__ void __launch_bounds__(kRadixBins) radix_coldown_kernel(
+    uint32_t* __restrict__ hist, unsigned nb, unsigned rows, const uint32_t* __restrict__ csum,
+    unsigned nc) {
+  const unsigned d = threadIdx.x;
+  const unsigned b0 = blockIdx.x * rows, b1 = min(nb, b0 + rows);
+  uint32_t run = csum[(uint64_t)blockIdx.x * kRadixBins + d] + csum[(uint64_t)nc * kRadixBins + d];
+  for (unsigned b = b0; b < b1; b += kColBatch) {
+    uint32_t v[kColBatch];
+#pragma unroll
+    for (int j = 0; j < kColBatch; ++j)
+      v[j] = b + j < b1 ? hist[(uint64_t)(b + j) * kRadixBins + d] : 0u;
+#pragma unroll
+    for (int j = 0; j < kColBatch; ++j)
+      if (b + j < b1) {
+        hist[(uint64_t)(b + j) * kRadixBins + d] = run;
+        run += v[j];
+      }
+  }
 }
 
 __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     const uint64_t* n_dev, uint64_t n_host, int shift,
-    const uint32_t* __restrict__ offsets /* scanned [256][nblocks] */,
+    const uint32_t* __restrict__ offsets /* scanned [nblocks][256] */,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
   __shared__ uint32_t wcnt[kSortWaves][kRadixBins];  // counts, then wave bases in digit
   __shared__ uint32_t dstart[kRadixBins];            // block-local start of each digit
@@ -225,7 +305,7 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
     }
     uint32_t total;
     dstart[d] = block_exclusive_scan<uint32_t>(run, scan_sh, total);
-    gbase[d] = offsets[(uint64_t)d * gridDim.x + blockIdx.x];
+    gbase[d] = offsets[(uint64_t)blockIdx.x * kRadixBins + d];
   }
   __syncthreads();
   for (int k = 0; k < kSortRounds; ++k) {
@@ -378,6 +458,13 @@ void launch_fill_u32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t v) {
 
 size_t radix_hist_elems(uint64_t n_max) { return (size_t)kRadixBins * blocks_for(n_max, kSortTile); }
 size_t scan_block_elems(uint64_t n_max) { return blocks_for(n_max, kScanTile) + 1; }
+// u32 elements of the column scan's chunk sums for up to n_max keys (an upper
+// bound for every smaller count as well)
+size_t radix_scan_elems(uint64_t n_max) {
+  const uint64_t nb = blocks_for(n_max, kSortTile);
+  const uint64_t nc = std::min<uint64_t>((nb + kColMinRows - 1) / kColMinRows, kColMaxChunks);
+  return (size_t)(nc + 1) * kRadixBins;
+}
 
 // Stable sort of (keys, vals) by the key bits [0, bits).  The element count
 // is *n_dev (<= n_max).  Result ends in (keys_a, vals_a) if the number of
@@ -387,8 +474,8 @@ bool launch_radix_sort(hipStream_t st, uint32_t* keys_a, uint32_t* vals_a, uint3
                        uint32_t* hist, uint32_t* scan_tmp) {
   if (n_max == 0) return false;
   const unsigned nb = blocks_for(n_max, kSortTile);
-  const uint64_t hn = (uint64_t)kRadixBins * nb;
-  const unsigned sb = blocks_for(hn, kScanTile);
+  const unsigned rows = col_rows(nb);
+  const unsigned nc = (nb + rows - 1) / rows;
   bool in_b = false;
   for (int shift = 0; shift < bits; shift += 8) {
     uint32_t* ki = in_b ? keys_b : keys_a;
@@ -397,13 +484,11 @@ bool launch_radix_sort(hipStream_t st, uint32_t* keys_a, uint32_t* vals_a, uint3
     uint32_t* vo = in_b ? vals_a : vals_b;
     hipLaunchKernelGGL(radix_hist_kernel, dim3(nb), dim3(kSortThreads), 0, st, ki, n_dev, n_max,
                        shift, hist);
-    LoadU32 ld{hist};
-    hipLaunchKernelGGL((scan_reduce_kernel<uint32_t, LoadU32>), dim3(sb), dim3(kScanThreads), 0,
-                       st, ld, (const uint64_t*)nullptr, hn, scan_tmp);
-    hipLaunchKernelGGL((scan_spine_kernel<uint32_t>), dim3(1), dim3(kScanThreads), 0, st,
-                       scan_tmp, (int)sb, (uint32_t*)nullptr);
-    hipLaunchKernelGGL((scan_down_kernel<uint32_t, LoadU32>), dim3(sb), dim3(kScanThreads), 0,
-                       st, ld, (const uint64_t*)nullptr, hn, scan_tmp, hist);
+    hipLaunchKernelGGL(radix_colsum_kernel, dim3(nc), dim3(kRadixBins), 0, st, hist, nb, rows,
+                       scan_tmp);
+    hipLaunchKernelGGL(radix_colspine_kernel, dim3(1), dim3(kRadixBins), 0, st, scan_tmp, nc);
+    hipLaunchKernelGGL(radix_coldown_kernel, dim3(nc), dim3(kRadixBins), 0, st, hist, nb, rows,
+                       scan_tmp, nc);
     hipLaunchKernelGGL(radix_scatter_kernel, dim3(nb), dim3(kSortThreads), 0, st, ki, vi, n_dev,
                        n_max, shift, hist, ko, vo);
     in_b = !in_b;

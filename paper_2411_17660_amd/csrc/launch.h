@@ -37,9 +37,10 @@ bool launch_radix_sort(hipStream_t st, uint32_t* keys_a, uint32_t* vals_a, uint3
                        uint32_t* vals_b, const uint64_t* n_dev, uint64_t n_max, int bits,
                        uint32_t* hist, uint32_t* scan_tmp);
 void launch_offsets_scan(hipStream_t st, const uint32_t* ntiles, const uint32_t* perm,
-                         uint64_t m, uint64_t* offsets, uint64_t* block_tmp, uint64_t* total);
+                         uint64_t m, uint32_t* cnt_sorted, uint64_t* offsets,
+                         uint64_t* block_tmp, uint64_t* total);
 void launch_keygen(hipStream_t st, uint64_t m, uint64_t n, const uint32_t* perm,
-                   const uint32_t* ntiles, const uint64_t* offsets, uint32_t* keyoff,
+                   const uint32_t* cnt_sorted, const uint64_t* offsets, uint32_t* keyoff,
                    const uint2* trect, const FrameDesc* frames, uint64_t capacity,
                    uint32_t* keys, uint32_t* vals, uint32_t* overflow);
 void launch_ranges(hipStream_t st, const uint32_t* keys, const uint64_t* k_dev, uint64_t k_max,

@@ -49,7 +49,8 @@ struct gsr_context {
   int device = 0;
   std::string err;
   // workspace
-  DBuf rec, trect, keyoff, dkey_a, dval_a, dkey_b, dval_b, ntiles, offsets, scan_tmp, hist, counters;
+  DBuf rec, trect, keyoff, dkey_a, dval_a, dkey_b, dval_b, ntiles, cnt_sorted, offsets, scan_tmp, hist,
+      counters;
   DBuf keys_a, vals_a, keys_b, vals_b, partial, stamp, grad2d;
   DBuf ranges, nproc, t_final, n_last, frames, twist_part, loss_part, loss_scale;
   DBuf ssim_part, ssim_tiles, ssim_scale;  // rendering loss with SSIM
@@ -262,7 +263,8 @@ gsr_status gsr_destroy(gsr_context* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   DBuf* bufs[] = {&ctx->rec, &ctx->trect, &ctx->keyoff, &ctx->dkey_a, &ctx->dval_a, &ctx->dkey_b, &ctx->dval_b,
-                  &ctx->ntiles, &ctx->offsets, &ctx->scan_tmp, &ctx->hist, &ctx->counters,
+                  &ctx->ntiles, &ctx->cnt_sorted, &ctx->offsets, &ctx->scan_tmp, &ctx->hist,
+                  &ctx->counters,
                   &ctx->keys_a, &ctx->vals_a, &ctx->keys_b, &ctx->vals_b, &ctx->partial,
                   &ctx->grad2d,
                   &ctx->stamp, &ctx->ranges, &ctx->nproc, &ctx->t_final, &ctx->n_last,
@@ -343,6 +345,7 @@ gsr_status forward_impl(gsr_context* ctx, const gsr_settings* s, int64_t n, cons
   if ((rc = ensure(ctx, ctx->dkey_b, M * 4, st))) return rc;
   if ((rc = ensure(ctx, ctx->dval_b, M * 4, st))) return rc;
   if ((rc = ensure(ctx, ctx->ntiles, M * 4, st))) return rc;
+  if ((rc = ensure(ctx, ctx->cnt_sorted, M * 4, st))) return rc;
   if ((rc = ensure(ctx, ctx->offsets, M * 8, st))) return rc;
   if ((rc = ensure(ctx, ctx->counters, 64, st, true))) return rc;
   if ((rc = ensure(ctx, ctx->ranges, (size_t)T * 8, st))) return rc;
@@ -398,8 +401,8 @@ gsr_status forward_impl(gsr_context* ctx, const gsr_settings* s, int64_t n, cons
   // A2 offsets over the depth-ordered records, K on the device
   {
     StageTimer t(ctx, st, timing, GSR_STAGE_OFFSETS);
-    launch_offsets_scan(st, P<uint32_t>(ctx->ntiles), perm, M, P<uint64_t>(ctx->offsets),
-                        P<uint64_t>(ctx->scan_tmp), d_count);
+    launch_offsets_scan(st, P<uint32_t>(ctx->ntiles), perm, M, P<uint32_t>(ctx->cnt_sorted),
+                        P<uint64_t>(ctx->offsets), P<uint64_t>(ctx->scan_tmp), d_count);
   }
   // key capacity
   uint64_t K = 0, cap = 0;
@@ -439,7 +442,8 @@ gsr_status forward_impl(gsr_context* ctx, const gsr_settings* s, int64_t n, cons
   // A3 keygen
   {
     StageTimer t(ctx, st, timing, GSR_STAGE_KEYGEN);
-    launch_keygen(st, M, (uint64_t)n, perm, P<uint32_t>(ctx->ntiles), P<uint64_t>(ctx->offsets),
+    launch_keygen(st, M, (uint64_t)n, perm, P<uint32_t>(ctx->cnt_sorted),
+                  P<uint64_t>(ctx->offsets),
                   P<uint32_t>(ctx->keyoff), P<uint2>(ctx->trect), P<FrameDesc>(ctx->frames),
                   use_cap,
                   P<uint32_t>(ctx->keys_a), P<uint32_t>(ctx->vals_a), d_overflow);

@@ -59,11 +59,6 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* sh, T& total) {
 }
 
 // Loaders: element i of the scanned sequence.
-struct LoadCountsPerm {  // ntiles[perm[i]] for the depth-sorted records
-  const uint32_t* ntiles;
-  const uint32_t* perm;
-  __device__ uint64_t operator()(uint64_t i) const { return ntiles[perm[i]]; }
-};
 struct LoadU32 {
   const uint32_t* a;
   __device__ uint32_t operator()(uint64_t i) const { return a[i]; }
@@ -336,7 +331,7 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) keygen_kernel(
     uint64_t m, uint64_t n, const uint32_t* __restrict__ perm,
-    const uint32_t* __restrict__ ntiles, const uint64_t* __restrict__ offsets,
+    const uint32_t* __restrict__ cnt_sorted, const uint64_t* __restrict__ offsets,
     uint32_t* __restrict__ keyoff, const uint2* __restrict__ trect,
     const FrameDesc* __restrict__ frames, uint64_t capacity,
     uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, uint32_t* __restrict__ overflow) {
@@ -350,7 +345,7 @@ __global__ void __launch_bounds__(256) keygen_kernel(
   uint64_t off = 0;
   if (i < m) {
     const uint32_t r = perm[i];
-    cnt = ntiles[r];
+    cnt = cnt_sorted[i];
     off = offsets[i];
     s_r[w][lane] = r;
     if (cnt) {
@@ -496,31 +491,44 @@ bool launch_radix_sort(hipStream_t st, uint32_t* keys_a, uint32_t* vals_a, uint3
   return in_b;
 }
 
+// The tile counts in depth order, cnt_sorted[i] = ntiles[perm[i]], gathered
+// once so that the offsets scan and keygen read them in order.
+__global__ void __launch_bounds__(256) gather_counts_kernel(uint64_t m,
+                                                            const uint32_t* __restrict__ ntiles,
+                                                            const uint32_t* __restrict__ perm,
+                                                            uint32_t* __restrict__ cnt_sorted) {
+  const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < m) cnt_sorted[i] = ntiles[perm[i]];
+}
+
 // Exclusive scan of ntiles[perm[i]] over the m records into offsets (u64),
-// total into *total.
+// total into *total; cnt_sorted[i] receives ntiles[perm[i]].
 void launch_offsets_scan(hipStream_t st, const uint32_t* ntiles, const uint32_t* perm,
-                         uint64_t m, uint64_t* offsets, uint64_t* block_tmp, uint64_t* total) {
+                         uint64_t m, uint32_t* cnt_sorted, uint64_t* offsets,
+                         uint64_t* block_tmp, uint64_t* total) {
   if (m == 0) {
     launch_fill_u32(st, (uint32_t*)total, 2, 0u);
     return;
   }
+  hipLaunchKernelGGL(gather_counts_kernel, dim3(blocks_for(m, 256)), dim3(256), 0, st, m, ntiles,
+                     perm, cnt_sorted);
   const unsigned sb = blocks_for(m, kScanTile);
-  LoadCountsPerm ld{ntiles, perm};
-  hipLaunchKernelGGL((scan_reduce_kernel<uint64_t, LoadCountsPerm>), dim3(sb),
-                     dim3(kScanThreads), 0, st, ld, (const uint64_t*)nullptr, m, block_tmp);
+  LoadU32 ld{cnt_sorted};
+  hipLaunchKernelGGL((scan_reduce_kernel<uint64_t, LoadU32>), dim3(sb), dim3(kScanThreads), 0,
+                     st, ld, (const uint64_t*)nullptr, m, block_tmp);
   hipLaunchKernelGGL((scan_spine_kernel<uint64_t>), dim3(1), dim3(kScanThreads), 0, st,
                      block_tmp, (int)sb, total);
-  hipLaunchKernelGGL((scan_down_kernel<uint64_t, LoadCountsPerm>), dim3(sb), dim3(kScanThreads),
-                     0, st, ld, (const uint64_t*)nullptr, m, block_tmp, offsets);
+  hipLaunchKernelGGL((scan_down_kernel<uint64_t, LoadU32>), dim3(sb), dim3(kScanThreads), 0, st,
+                     ld, (const uint64_t*)nullptr, m, block_tmp, offsets);
 }
 
 void launch_keygen(hipStream_t st, uint64_t m, uint64_t n, const uint32_t* perm,
-                   const uint32_t* ntiles, const uint64_t* offsets, uint32_t* keyoff,
+                   const uint32_t* cnt_sorted, const uint64_t* offsets, uint32_t* keyoff,
                    const uint2* trect, const FrameDesc* frames, uint64_t capacity,
                    uint32_t* keys, uint32_t* vals, uint32_t* overflow) {
   if (m == 0) return;
   hipLaunchKernelGGL(keygen_kernel, dim3(blocks_for(m, 256)), dim3(256), 0, st, m, n, perm,
-                     ntiles, offsets, keyoff, trect, frames, capacity, keys, vals, overflow);
+                     cnt_sorted, offsets, keyoff, trect, frames, capacity, keys, vals, overflow);
 }
 
 void launch_ranges(hipStream_t st, const uint32_t* keys, const uint64_t* k_dev, uint64_t k_max,

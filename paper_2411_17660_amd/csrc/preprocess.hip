@@ -14,10 +14,15 @@
 // FP64 with contraction off, in a fixed operation order, so that it is
 // reproducible on any IEEE-754 double implementation.
 //
-// One thread per Gaussian walks all frames of the batch: the parameters are
-// read from HBM once per step and the world covariance is built once.
+// The forward takes one thread per (Gaussian, frame) record, each building
+// the Gaussian's world covariance itself (the parameters come from HBM about
+// once, then from cache).  The backward takes one thread per Gaussian, which
+// walks all frames of the batch and sums the Gaussian's gradients over them
+// in frame order.
 #include "launch.h"
 #include "sh_device.h"
+
+#include <algorithm>
 
 namespace gsr {
 
@@ -153,7 +158,10 @@ __device__ __forceinline__ void project(const FrameDesc& fr, const double W[9],
 }
 
 // --------------------------------------------------------------------------
-// A1: forward preprocess
+// A1: forward preprocess, one thread per (Gaussian, frame): blockIdx.y is the
+// frame (striding by gridDim.y past 65535 frames), so a block's records
+// r = f n + g are consecutive.  Each of a Gaussian's threads computes its
+// activations (its parameters are read once per frame, mostly from cache).
 // --------------------------------------------------------------------------
 template <int DEG>
 __global__ void __launch_bounds__(256) preprocess_fwd_kernel(
@@ -171,7 +179,7 @@ __global__ void __launch_bounds__(256) preprocess_fwd_kernel(
   gaussian_setup(log_scales, quats, opac, g, G);
   const double mu[3] = {means[g * 3 + 0], means[g * 3 + 1], means[g * 3 + 2]};
   constexpr int nb = (DEG + 1) * (DEG + 1);
-  for (int f = 0; f < n_frames; ++f) {
+  for (int f = (int)blockIdx.y; f < n_frames; f += (int)gridDim.y) {
     const int64_t r = (int64_t)f * n + g;
     const FrameDesc fr = frames[f];
     double W[9], tf[3];
@@ -525,8 +533,8 @@ void launch_preprocess_fwd(hipStream_t st, int64_t n, int F, const FrameDesc* fr
                            const float* quats, const float* opac, const float* sh, int deg,
                            int tile_w, int tile_h, Record* rec, uint2* trect,
                            uint32_t* depth_key, uint32_t* rec_id, uint32_t* ntiles) {
-  if (n <= 0) return;
-  const dim3 grid((unsigned)((n + 255) / 256));
+  if (n <= 0 || F <= 0) return;
+  const dim3 grid((unsigned)((n + 255) / 256), (unsigned)std::min(F, 65535));
 #define GSR_PRE_FWD(D)                                                                      \
   hipLaunchKernelGGL(preprocess_fwd_kernel<D>, grid, dim3(256), 0, st, n, F, frames, poses, \
                      means, log_scales, quats, opac, sh, tile_w, tile_h, rec, trect,        \

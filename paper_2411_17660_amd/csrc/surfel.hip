@@ -29,6 +29,7 @@
 // (exact, from the disk's dual conic) united with the square of half width
 // sqrt(ln(255 sigma)) around c, and is culled unless the disk lies beyond the
 // near plane; the box's integer bounds are taken in FP64.
+#include <algorithm>
 #include <cstddef>
 
 #include "launch.h"
@@ -73,7 +74,7 @@ __global__ void __launch_bounds__(256) surfel_preprocess_kernel(
   const double mu[3] = {means[3 * g], means[3 * g + 1], means[3 * g + 2]};
   constexpr int nb = (DEG + 1) * (DEG + 1);
   const double amin = (double)kAlphaMin;
-  for (int f = 0; f < n_frames; ++f) {
+  for (int f = (int)blockIdx.y; f < n_frames; f += (int)gridDim.y) {
     const int64_t r = (int64_t)f * n + g;
     const FrameDesc fr = frames[f];
     double W[9], tf[3];
@@ -773,8 +774,8 @@ void launch_surfel_preprocess(hipStream_t st, int64_t n, int F, const FrameDesc*
                               const float* quats, const float* opac, const float* sh, int deg,
                               int tile_w, int tile_h, void* rec, uint2* trect,
                               uint32_t* depth_key, uint32_t* rec_id, uint32_t* ntiles) {
-  if (n <= 0) return;
-  const dim3 grid((unsigned)((n + 255) / 256));
+  if (n <= 0 || F <= 0) return;
+  const dim3 grid((unsigned)((n + 255) / 256), (unsigned)std::min(F, 65535));
 #define GSR_SURF_PRE(D)                                                                      \
   hipLaunchKernelGGL(surfel_preprocess_kernel<D>, grid, dim3(256), 0, st, n, F, frames,      \
                      poses, means, log_scales, quats, opac, sh, tile_w, tile_h,             \

@@ -200,6 +200,36 @@ def test_determinism(rast):
         assert np.array_equal(outs[0][3][k], outs[1][3][k]), k
 
 
+def test_more_frames_than_one_grid_dimension(rast):
+    """65,537 copies of one 4 x 4 frame in one batch: the forward preprocess
+    takes the frame from the grid's y dimension and strides past its 65,535
+    limit.  Every frame must render, and take its pose gradient, bitwise as
+    the single frame does, and the parameter gradients are 65,537 times the
+    single frame's (these alone could not reveal a skipped frame)."""
+    one = scenes.tiny_scene(seed=12, n=40, W=4, H=4, f=4.0, n_frames=1, ls_mean=-1.0)
+    F = 65537
+    sc = scenes.Scene(one.means, one.log_scales, one.quats, one.opacity, one.sh, one.sh_degree,
+                      one.cams * F, np.ascontiguousarray(np.repeat(one.poses, F, axis=0)),
+                      one.background)
+    G1 = scenes.upstream(12, one)
+    print(f"[frames] one frame, then {F} copies", flush=True)
+    _, r1, d1, a1 = gpu_forward(rast, one)
+    g1 = gpu_backward(rast, G1)
+    r1, d1, a1 = r1.cpu().numpy(), d1.cpu().numpy(), a1.cpu().numpy()
+    assert a1.max() > 0.1
+    _, rb, db, ab = gpu_forward(rast, sc)
+    gb = gpu_backward(rast, tuple(np.tile(g, F) for g in G1))
+    assert np.array_equal(rb.cpu().numpy().reshape(F, -1), np.tile(r1, (F, 1)))
+    assert np.array_equal(db.cpu().numpy().reshape(F, -1), np.tile(d1, (F, 1)))
+    assert np.array_equal(ab.cpu().numpy().reshape(F, -1), np.tile(a1, (F, 1)))
+    assert np.array_equal(gb["twist"], np.tile(g1["twist"][0], (F, 1)))
+    for k in ("means", "log_scales", "quats", "opacity"):
+        assert_grad_close(f"frames:{k}", gb[k], F * g1[k], rel=1e-4)
+    # the SH gradient sums its per-frame terms in FP32: F equal terms drift by
+    # up to F / 2 * 2^-24 (2e-3) relative
+    assert_grad_close("frames:sh", gb["sh"], F * g1["sh"], rel=F / 2 * 2.0 ** -24 * 1.2)
+
+
 def test_batch_equals_per_frame(rast):
     sc = scenes.tiny_scene(seed=6, n=2500, W=140, H=100, f=100.0, n_frames=3)
     G = scenes.upstream(6, sc)

@@ -118,6 +118,28 @@ def test_surfel_forward_larger_scene(rast):
     _check(rast, sc, (16, 16), "surfels-3000")
 
 
+def test_surfel_more_frames_than_one_grid_dimension(rast):
+    """65,537 copies of one 4 x 4 frame in one batch: the surfel preprocess
+    takes the frame from the grid's y dimension and strides past its 65,535
+    limit.  Every frame's five maps must equal the single frame's bitwise."""
+    one = _surfel_scene(13, 40, 4, 4, 4.0, 1, 3, ls_mean=-1.0)
+    F = 65537
+    sc = scenes.Scene(one.means, one.log_scales, one.quats, one.opacity, one.sh, one.sh_degree,
+                      one.cams * F, np.ascontiguousarray(np.repeat(one.poses, F, axis=0)),
+                      one.background)
+    print(f"[surfel] one frame, then {F} copies", flush=True)
+    outs = []
+    for s_ in (one, sc):
+        d = to_dev(s_)
+        o = rast.forward_surfel(d["means"], d["log_scales"], d["quats"], d["opacity"], d["sh"],
+                                d["poses"], s_.cams, s_.sh_degree, s_.background)
+        torch.cuda.synchronize()
+        outs.append([x.cpu().numpy() for x in o])
+    assert outs[0][2].max() > 0.1
+    for a, b in zip(*outs):
+        assert np.array_equal(b.reshape(F, -1), np.tile(a.reshape(1, -1), (F, 1)))
+
+
 def test_surfel_images_do_not_depend_on_tile_shape(rast):
     import torch
     sc = _surfel_scene(8, 1200, 150, 90, 110.0, 2, 3)

@@ -50,27 +50,32 @@ __global__ void __launch_bounds__(kLossThreads) loss_mask_kernel(
   if (threadIdx.x == 0) part[((int64_t)f * blocks_x + blockIdx.x) * 3 + 2] = red[2][0];
 }
 
-// One block: per-frame scale factors from the mask counts.
+// Sum over b of part[f][b][j] by one wave (lanes stride over the blocks,
+// then a butterfly), in FP64.
+__device__ __forceinline__ double wave_part_sum(const double* __restrict__ part, int f,
+                                                int blocks_x, int j, int lane) {
+  double s = 0.0;
+  for (int b = lane; b < blocks_x; b += kWave) s += part[((int64_t)f * blocks_x + b) * 3 + j];
+  for (int o = kWave / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, kWave);
+  return s;
+}
+
+constexpr int kLossWaves = kLossThreads / kWave;
+
+// One block, one wave per frame in turn: per-frame scale factors from the
+// mask counts.
 __global__ void __launch_bounds__(kLossThreads) loss_scale_kernel(
     const FrameDesc* __restrict__ frames, int n_frames, int blocks_x,
     const double* __restrict__ part, float depth_weight,
     float* __restrict__ scale /* [F][2]: 1/(3HW), w_d/|m| */) {
-  __shared__ double red[3][kLossThreads];
-  for (int f = 0; f < n_frames; ++f) {
-    double m = 0.0;
-    for (int b = threadIdx.x; b < blocks_x; b += kLossThreads)
-      m += part[((int64_t)f * blocks_x + b) * 3 + 2];
-    red[0][threadIdx.x] = 0.0;
-    red[1][threadIdx.x] = 0.0;
-    red[2][threadIdx.x] = m;
-    block_sum3(red);
-    if (threadIdx.x == 0) {
+  const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  for (int f = w; f < n_frames; f += kLossWaves) {
+    const double m = wave_part_sum(part, f, blocks_x, 2, lane);
+    if (lane == 0) {
       const double HW = (double)frames[f].width * frames[f].height;
-      const double mf = red[2][0];
       scale[2 * f] = (float)(1.0 / (3.0 * HW));
-      scale[2 * f + 1] = mf > 0.0 ? (float)((double)depth_weight / mf) : 0.0f;
+      scale[2 * f + 1] = m > 0.0 ? (float)((double)depth_weight / m) : 0.0f;
     }
-    __syncthreads();
   }
 }
 
@@ -109,34 +114,28 @@ __global__ void __launch_bounds__(kLossThreads) loss_partial_grad_kernel(
   if (threadIdx.x < 2) part[((int64_t)f * blocks_x + blockIdx.x) * 3 + threadIdx.x] = red[threadIdx.x][0];
 }
 
-// One block: per-frame totals -> loss and per-frame scale factors.
+// One block: the loss.  Wave w sums the terms of frames w, w + 4, ... in
+// order, and the four wave totals are added in wave order.
 __global__ void __launch_bounds__(kLossThreads) loss_finalize_kernel(
     const FrameDesc* __restrict__ frames, int n_frames, int blocks_x,
-    const double* __restrict__ part, float depth_weight, float* __restrict__ loss,
-    float* __restrict__ scale /* [F][2]: 1/(3HW), w_d/|m| */) {
-  __shared__ double red[3][kLossThreads];
+    const double* __restrict__ part, float depth_weight, float* __restrict__ loss) {
+  __shared__ double wsum[kLossWaves];
+  const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   double total = 0.0;
-  for (int f = 0; f < n_frames; ++f) {
-    double s[3] = {0.0, 0.0, 0.0};
-    for (int b = threadIdx.x; b < blocks_x; b += kLossThreads)
-      for (int j = 0; j < 3; ++j) s[j] += part[((int64_t)f * blocks_x + b) * 3 + j];
-    for (int j = 0; j < 3; ++j) red[j][threadIdx.x] = s[j];
-    __syncthreads();
-    for (int o = kLossThreads / 2; o > 0; o >>= 1) {
-      if ((int)threadIdx.x < o)
-        for (int j = 0; j < 3; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + o];
-      __syncthreads();
-    }
+  for (int f = w; f < n_frames; f += kLossWaves) {
+    const double s_rgb = wave_part_sum(part, f, blocks_x, 0, lane);
+    const double s_d = wave_part_sum(part, f, blocks_x, 1, lane);
+    const double m = wave_part_sum(part, f, blocks_x, 2, lane);
     const double HW = (double)frames[f].width * frames[f].height;
-    const double m = red[2][0];
-    total += red[0][0] / (3.0 * HW) + (m > 0.0 ? (double)depth_weight * red[1][0] / m : 0.0);
-    if (threadIdx.x == 0) {
-      scale[2 * f] = (float)(1.0 / (3.0 * HW));
-      scale[2 * f + 1] = m > 0.0 ? (float)((double)depth_weight / m) : 0.0f;
-    }
-    __syncthreads();
+    total += s_rgb / (3.0 * HW) + (m > 0.0 ? (double)depth_weight * s_d / m : 0.0);
   }
-  if (threadIdx.x == 0) *loss = (float)total;
+  if (lane == 0) wsum[w] = total;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < kLossWaves; ++i) t += wsum[i];
+    *loss = (float)t;
+  }
 }
 
 int loss_blocks_x(int64_t max_hw) {
@@ -155,7 +154,7 @@ void launch_loss_l1(hipStream_t st, int F, int blocks_x, const FrameDesc* frames
   hipLaunchKernelGGL(loss_partial_grad_kernel, grid, dim3(kLossThreads), 0, st, frames, rgb,
                      depth, t_rgb, t_depth, scale, blocks_x, part, g_rgb, g_depth, g_alpha);
   hipLaunchKernelGGL(loss_finalize_kernel, dim3(1), dim3(kLossThreads), 0, st, frames, F,
-                     blocks_x, part, depth_weight, loss, scale);
+                     blocks_x, part, depth_weight, loss);
 }
 
 }  // namespace gsr

@@ -508,23 +508,32 @@ void launch_bump_epoch(hipStream_t st, uint32_t* epoch) {
 }
 
 // A11: per-frame sum of the per-wave twist partials (FP64, fixed order).
-__global__ void __launch_bounds__(256) twist_reduce_kernel(const double* __restrict__ part,
-                                                           int64_t n_waves,
-                                                           float* __restrict__ g_twist) {
-  __shared__ double red[256];
+constexpr int kTwistThreads = 1024;
+
+// One block per frame: thread t sums all six components of the partials
+// t, t + 1024, ..., then each wave sums its lanes with a butterfly and the
+// 16 wave totals are added in wave order, a fixed order for a given n.
+__global__ void __launch_bounds__(kTwistThreads) twist_reduce_kernel(
+    const double* __restrict__ part, int64_t n_waves, float* __restrict__ g_twist) {
+  __shared__ double red[kTwistThreads / 64][6];
   const int f = blockIdx.x;
-  for (int j = 0; j < 6; ++j) {
-    double s = 0.0;
-    for (int64_t w = threadIdx.x; w < n_waves; w += blockDim.x)
-      s += part[((int64_t)f * n_waves + w) * 6 + j];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-      if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) g_twist[f * 6 + j] = (float)red[0];
-    __syncthreads();
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+  double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t w = threadIdx.x; w < n_waves; w += kTwistThreads) {
+    const double* p = part + ((int64_t)f * n_waves + w) * 6;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) s[j] += p[j];
+  }
+#pragma unroll
+  for (int j = 0; j < 6; ++j)
+    for (int o = 32; o > 0; o >>= 1) s[j] += __shfl_xor(s[j], o, 64);
+  if (lane == 0)
+    for (int j = 0; j < 6; ++j) red[wv][j] = s[j];
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    double t = 0.0;
+    for (int i = 0; i < kTwistThreads / 64; ++i) t += red[i][threadIdx.x];
+    g_twist[f * 6 + threadIdx.x] = (float)t;
   }
 }
 
@@ -582,8 +591,8 @@ void launch_preprocess_bwd(hipStream_t st, int64_t n, int F, const FrameDesc* fr
 void launch_twist_reduce(hipStream_t st, int F, const double* twist_partial, int64_t n_waves,
                          float* g_twist) {
   if (F <= 0) return;
-  hipLaunchKernelGGL(twist_reduce_kernel, dim3(F), dim3(256), 0, st, twist_partial, n_waves,
-                     g_twist);
+  hipLaunchKernelGGL(twist_reduce_kernel, dim3(F), dim3(kTwistThreads), 0, st, twist_partial,
+                     n_waves, g_twist);
 }
 
 }  // namespace gsr

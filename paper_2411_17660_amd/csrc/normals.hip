@@ -145,18 +145,24 @@ __global__ void __launch_bounds__(kNcX * kNcY) normal_consistency_kernel(
   }
 }
 
-__global__ void __launch_bounds__(256) nc_total_kernel(const double* __restrict__ part,
-                                                       int64_t n, float* __restrict__ loss) {
-  __shared__ double red[256];
+constexpr int kNcTotalThreads = 1024;
+
+// One block: thread t sums the partials t, t + 1024, ...; each wave sums its
+// lanes with a butterfly and the 16 wave totals are added in wave order.
+__global__ void __launch_bounds__(kNcTotalThreads) nc_total_kernel(const double* __restrict__ part,
+                                                                  int64_t n,
+                                                                  float* __restrict__ loss) {
+  __shared__ double red[kNcTotalThreads / kWave];
   double t = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 256) t += part[i];
-  red[threadIdx.x] = t;
+  for (int64_t i = threadIdx.x; i < n; i += kNcTotalThreads) t += part[i];
+  for (int o = kWave / 2; o > 0; o >>= 1) t += __shfl_xor(t, o, kWave);
+  if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = t;
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < kNcTotalThreads / kWave; ++i) s += red[i];
+    loss[0] = (float)s;
   }
-  if (threadIdx.x == 0) loss[0] = (float)red[0];
 }
 
 }  // namespace
@@ -186,7 +192,7 @@ void launch_normal_consistency(hipStream_t st, int F, const gsr_camera* cams,
     off += HW;
     boff += normal_consistency_blocks(c.width, c.height);
   }
-  hipLaunchKernelGGL(nc_total_kernel, dim3(1), dim3(256), 0, st, part, boff, loss);
+  hipLaunchKernelGGL(nc_total_kernel, dim3(1), dim3(kNcTotalThreads), 0, st, part, boff, loss);
 }
 
 }  // namespace gsr

@@ -60,6 +60,7 @@ __device__ __forceinline__ uint32_t work_bucket(uint32_t w) {
 __global__ void __launch_bounds__(1024) tile_order_kernel(int n_tiles, int groups,
                                                           const uint32_t* __restrict__ nproc,
                                                           uint32_t* __restrict__ order) {
+  static_assert(kOrderBins == 1024, "one thread per bin in the offsets scan");
   __shared__ uint32_t bins[kOrderBins];
   const int q = blockIdx.x;
   const int per = (n_tiles + groups - 1) / groups;
@@ -73,13 +74,21 @@ __global__ void __launch_bounds__(1024) tile_order_kernel(int n_tiles, int group
   for (int t = t0 + (int)threadIdx.x; t < t1; t += blockDim.x)
     atomicAdd(&bins[work_bucket(nproc[t])], 1u);
   __syncthreads();
-  if (threadIdx.x == 0) {  // exclusive offsets, largest bucket first
-    uint32_t run = 0;
-    for (int i = kOrderBins - 1; i >= 0; --i) {
-      const uint32_t c = bins[i];
-      bins[i] = run;
-      run += c;
+  {  // exclusive offsets, largest bucket first: thread i takes bin 1023 - i
+    __shared__ uint32_t wtot[kOrderBins / kWave];
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+    const int bin = kOrderBins - 1 - (int)threadIdx.x;
+    const uint32_t c = bins[bin];
+    uint32_t v = c;  // inclusive scan over the wave's lanes
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t u = __shfl_up(v, o, kWave);
+      if (lane >= o) v += u;
     }
+    if (lane == kWave - 1) wtot[wv] = v;
+    __syncthreads();
+    uint32_t base = 0;
+    for (int k = 0; k < wv; ++k) base += wtot[k];
+    bins[bin] = base + v - c;
   }
   __syncthreads();
   for (int t = t0 + (int)threadIdx.x; t < t1; t += blockDim.x) {

@@ -19,14 +19,22 @@ constexpr int kLossItems = 8;
 
 __device__ __forceinline__ float sgnf(float x) { return x > 0.0f ? 1.0f : (x < 0.0f ? -1.0f : 0.0f); }
 
-// Sums over a block's 256 threads into red[j][0] (FP64, fixed order).
-__device__ __forceinline__ void block_sum3(double (*red)[kLossThreads]) {
+// Sums v[0..2] over a block's 256 threads into red[j][0] (FP64, fixed
+// order): a butterfly per wave, then the four wave totals in wave order.
+__device__ __forceinline__ void block_sum3(double (*red)[kLossThreads], double v[3]) {
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  for (int j = 0; j < 3; ++j)
+    for (int o = kWave / 2; o > 0; o >>= 1) v[j] += __shfl_xor(v[j], o, kWave);
+  if (lane == 0)
+    for (int j = 0; j < 3; ++j) red[j][wv] = v[j];
   __syncthreads();
-  for (int o = kLossThreads / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o)
-      for (int j = 0; j < 3; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + o];
-    __syncthreads();
-  }
+  if (threadIdx.x == 0)
+    for (int j = 0; j < 3; ++j) {
+      double t = 0.0;
+      for (int i = 0; i < kLossThreads / kWave; ++i) t += red[j][i];
+      red[j][0] = t;
+    }
+  __syncthreads();
 }
 
 // |m_f| per block: part[f][b][2] = #{p : D*_p > 0}
@@ -43,10 +51,8 @@ __global__ void __launch_bounds__(kLossThreads) loss_mask_kernel(
     if (p >= HW) break;
     if (t_depth[fr.pixel_offset + p] > 0.0f) s_m += 1.0;
   }
-  red[0][threadIdx.x] = 0.0;
-  red[1][threadIdx.x] = 0.0;
-  red[2][threadIdx.x] = s_m;
-  block_sum3(red);
+  double v[3] = {0.0, 0.0, s_m};
+  block_sum3(red, v);
   if (threadIdx.x == 0) part[((int64_t)f * blocks_x + blockIdx.x) * 3 + 2] = red[2][0];
 }
 
@@ -107,10 +113,8 @@ __global__ void __launch_bounds__(kLossThreads) loss_partial_grad_kernel(
     g_depth[q] = td > 0.0f ? sgnf(d - td) * sd : 0.0f;
     g_alpha[q] = 0.0f;
   }
-  red[0][threadIdx.x] = s_rgb;
-  red[1][threadIdx.x] = s_d;
-  red[2][threadIdx.x] = 0.0;
-  block_sum3(red);
+  double v[3] = {s_rgb, s_d, 0.0};
+  block_sum3(red, v);
   if (threadIdx.x < 2) part[((int64_t)f * blocks_x + blockIdx.x) * 3 + threadIdx.x] = red[threadIdx.x][0];
 }
 

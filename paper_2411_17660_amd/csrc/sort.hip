@@ -98,27 +98,42 @@ __global__ void __launch_bounds__(kScanThreads) scan_spine_kernel(T* __restrict_
   if (threadIdx.x == 0 && total_out) *total_out = carry;
 }
 
+// The block's kScanTile elements pass through LDS rows of kScanItems + 1
+// (padded against bank conflicts) so that global loads and stores are
+// coalesced while each thread scans kScanItems consecutive elements.
 template <typename T, typename Load>
 __global__ void __launch_bounds__(kScanThreads) scan_down_kernel(Load ld, const uint64_t* n_dev,
                                                                  uint64_t n_host,
                                                                  const T* __restrict__ block_base,
                                                                  T* __restrict__ out) {
+  constexpr int kRow = kScanItems + 1;
   __shared__ T sh[kScanThreads];
+  __shared__ T stage[kScanThreads * kRow];
   const uint64_t n = n_dev ? min(*n_dev, n_host) : n_host;
-  const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
+  const uint64_t b0 = (uint64_t)blockIdx.x * kScanTile;
+  for (int k = 0; k < kScanItems; ++k) {
+    const int e = k * kScanThreads + (int)threadIdx.x;  // element of the tile
+    const uint64_t i = b0 + (uint64_t)e;
+    stage[(e / kScanItems) * kRow + e % kScanItems] = i < n ? (T)ld(i) : (T)0;
+  }
+  __syncthreads();
   T v[kScanItems];
   T s = 0;
   for (int k = 0; k < kScanItems; ++k) {
-    const uint64_t i = base + k;
-    v[k] = i < n ? (T)ld(i) : (T)0;
+    v[k] = stage[threadIdx.x * kRow + k];
     s += v[k];
   }
   T total;
   T run = block_exclusive_scan<T>(s, sh, total) + block_base[blockIdx.x];
   for (int k = 0; k < kScanItems; ++k) {
-    const uint64_t i = base + k;
-    if (i < n) out[i] = run;
+    stage[threadIdx.x * kRow + k] = run;
     run += v[k];
+  }
+  __syncthreads();
+  for (int k = 0; k < kScanItems; ++k) {
+    const int e = k * kScanThreads + (int)threadIdx.x;
+    const uint64_t i = b0 + (uint64_t)e;
+    if (i < n) out[i] = stage[(e / kScanItems) * kRow + e % kScanItems];
   }
 }
 

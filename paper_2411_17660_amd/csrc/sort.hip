@@ -25,6 +25,7 @@
 #include "launch.h"
 
 #include <algorithm>
+#include <cmath>
 
 namespace gsr {
 
@@ -201,12 +202,22 @@ __global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(
 // are cut into chunks of `rows`; one thread per digit walks a chunk's rows,
 // so every access is a whole 1 KB row.  Rows are loaded kColBatch at a time
 // so that a thread's serial walk waits on one load latency per batch.
-constexpr unsigned kColMinRows = 128, kColMaxChunks = 1024;
+// rows = ceil(sqrt(nb)) balances a chunk's walk against the spine's walk
+// over the chunks; then there are at most ceil(sqrt(nb)) chunks (and at most
+// kColMaxChunks).
+constexpr unsigned kColMaxChunks = 1024;
 constexpr int kColBatch = 16;
 static_assert(kRadixBins == kScanThreads, "one scan thread per digit");
 
+static inline uint64_t isqrt_ceil(uint64_t x) {
+  uint64_t r = (uint64_t)std::sqrt((double)x);
+  while (r * r < x) ++r;
+  while (r > 0 && (r - 1) * (r - 1) >= x) --r;
+  return r;
+}
+
 static inline unsigned col_rows(unsigned nb) {
-  return std::max(kColMinRows, (nb + kColMaxChunks - 1) / kColMaxChunks);
+  return (unsigned)std::max<uint64_t>(isqrt_ceil(nb), (nb + kColMaxChunks - 1) / kColMaxChunks);
 }
 
 // csum[c][d] = sum of H[b][d] over the rows b of chunk c
@@ -472,7 +483,7 @@ size_t scan_block_elems(uint64_t n_max) { return blocks_for(n_max, kScanTile) + 
 // bound for every smaller count as well)
 size_t radix_scan_elems(uint64_t n_max) {
   const uint64_t nb = blocks_for(n_max, kSortTile);
-  const uint64_t nc = std::min<uint64_t>((nb + kColMinRows - 1) / kColMinRows, kColMaxChunks);
+  const uint64_t nc = std::min<uint64_t>(isqrt_ceil(nb), kColMaxChunks);
   return (size_t)(nc + 1) * kRadixBins;
 }
 

@@ -282,15 +282,29 @@ def scene_c5(seed=0, n=3_000_000, n_frames=12, W=1920, H=1080, f=1000.0):
 
 def tiny_scene(seed=0, n=40, W=40, H=30, f=30.0, n_frames=1, sh_degree=3,
                ls_mean=-2.5, ls_sigma=0.4, zrange=(1.5, 4.0), spread=0.9, opacity_sigma=1.0,
-               background=(0.1, 0.2, 0.3)):
+               background=(0.1, 0.2, 0.3), outside=None):
     """Small scene for brute force, closed forms and finite differences: means
-    in front of every camera of a short trajectory."""
+    in front of every camera of a short trajectory.
+
+    Lateral positions are drawn in units of the half field of view (x/z in
+    [-spread, spread] * W/(2f), likewise y).  With outside=(lo, hi), each
+    Gaussian instead lies beyond the image on one or both axes (chosen at
+    random): there |x/z| (|y/z|) is drawn from [lo, hi] of the half field of
+    view with a random sign, and the other axis from [-spread, spread]."""
     rng = np.random.default_rng(seed)
     Rs, Cs = trajectory(rng, n_frames, step_m=0.05, step_deg=3.0)
     cams = [(W, H, f, f, W / 2.0 - 0.3, H / 2.0 + 0.2, NEAR)] * n_frames
     z = rng.uniform(zrange[0], zrange[1], n)
-    x = rng.uniform(-spread, spread, n) * z * (W / (2 * f))
-    y = rng.uniform(-spread, spread, n) * z * (H / (2 * f))
+    ux = rng.uniform(-spread, spread, n)
+    uy = rng.uniform(-spread, spread, n)
+    if outside is not None:
+        mode = rng.integers(0, 3, n)  # 0: x outside, 1: y outside, 2: both
+        mag = rng.uniform(outside[0], outside[1], (n, 2))
+        sgn = np.where(rng.uniform(size=(n, 2)) < 0.5, -1.0, 1.0)
+        ux = np.where(mode != 1, sgn[:, 0] * mag[:, 0], ux)
+        uy = np.where(mode != 0, sgn[:, 1] * mag[:, 1], uy)
+    x = ux * z * (W / (2 * f))
+    y = uy * z * (H / (2 * f))
     means = np.stack([x, y, z], 1) @ Rs[0].T + Cs[0][None, :]
     ls = rng.normal(ls_mean, ls_sigma, size=(n, 3))
     q = _unit_quats(rng, n)

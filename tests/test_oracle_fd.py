@@ -153,3 +153,93 @@ def test_colour_clamp_and_direction_paths():
         sc.poses[0] = P0
         fd = (lp - lm) / 2e-7
         assert abs(g["twist"][0, k] - fd) <= 2e-6 * max(abs(fd), 1e-3)
+
+
+# The EWA projection's Jacobian guard (the 3DGS lineage's frustum guard, which
+# the paper inherits through its renderer): J is evaluated at t_x/t_z clamped
+# to +-1.3 W/(2 f_x) (likewise y).  These scenes put every Gaussian beyond the
+# image on one or both axes, large enough that its square still reaches it.
+GUARD = 1.3
+
+
+def guard_scene(seed, deg, n=36):
+    return scenes.tiny_scene(seed=seed, n=n, W=40, H=30, f=32.0, n_frames=2, sh_degree=deg,
+                             ls_mean=-1.0, ls_sigma=0.3, zrange=(1.5, 3.0), outside=(1.35, 1.8))
+
+
+def clamped_records(sc, rec):
+    """(clamped in x, clamped in y) per record, from the projected means:
+    t_x/t_z = (u - c_x)/f_x."""
+    cx = np.repeat([c[4] for c in sc.cams], sc.n)
+    cy = np.repeat([c[5] for c in sc.cams], sc.n)
+    fx = np.repeat([c[2] for c in sc.cams], sc.n)
+    fy = np.repeat([c[3] for c in sc.cams], sc.n)
+    W = np.repeat([c[0] for c in sc.cams], sc.n)
+    H = np.repeat([c[1] for c in sc.cams], sc.n)
+    clx = np.abs(rec["u"] - cx) / fx > GUARD * W / (2 * fx)
+    cly = np.abs(rec["v"] - cy) / fy > GUARD * H / (2 * fy)
+    return clx, cly
+
+
+@pytest.mark.parametrize("seed,deg", [(41, 2), (42, 3)])
+def test_gradients_through_the_jacobian_guard(seed, deg):
+    """Central differences on Gaussians outside the guard: every parameter
+    group (all coordinates of the Gaussians that have a clamped kept record)
+    and all six twist components of both frames."""
+    sc = _as64(guard_scene(seed, deg))
+    r = oracle.forward(sc, f64=True)
+    rec = r.records()
+    keep = rec["keep"].astype(bool)
+    clx, cly = clamped_records(sc, rec)
+    assert (keep & clx).sum() >= 10 and (keep & cly).sum() >= 10
+    assert (keep & clx & cly).sum() >= 5
+    clamped_g = np.unique(np.nonzero(keep & (clx | cly))[0] % sc.n)
+    rng = np.random.default_rng(seed)
+    G = (rng.normal(size=3 * r.P), rng.normal(size=r.P), rng.normal(size=r.P))
+    grads = r.backward(*G)
+    base = r.decision_hash
+    used = bad = 0
+    for name in ("means", "log_scales", "quats", "opacity", "sh"):
+        arr = getattr(sc, name)
+        ga = grads[name].reshape(arr.shape)
+        scale = np.sqrt(np.mean(ga ** 2)) + 1e-30
+        for g in clamped_g:
+            coords = list(np.ndindex(arr.shape[1:])) if arr.ndim > 1 else [()]
+            if name == "sh":
+                coords = coords[:6]
+            for c in coords:
+                idx = (g,) + tuple(c)
+                x0 = arr[idx]
+                h = 1e-5 * max(abs(x0), 0.1)
+                arr[idx] = x0 + h
+                lp, hp = _loss(sc, G)
+                arr[idx] = x0 - h
+                lm, hm = _loss(sc, G)
+                arr[idx] = x0
+                if hp != base or hm != base:
+                    continue
+                fd = (lp - lm) / (2 * h)
+                used += 1
+                if not _check(ga[idx], fd, scale):
+                    bad += 1
+                    print("mismatch", name, idx, ga[idx], fd)
+    assert used >= 300
+    assert bad == 0
+    tw = grads["twist"]
+    tused = 0
+    for f in range(2):
+        P0 = sc.poses[f].copy()
+        for k in range(6):
+            eps = 1e-7
+            sc.poses[f] = _exp_left(P0, k, eps)
+            lp, hp = _loss(sc, G)
+            sc.poses[f] = _exp_left(P0, k, -eps)
+            lm, hm = _loss(sc, G)
+            sc.poses[f] = P0
+            if hp != base or hm != base:
+                continue
+            tused += 1
+            fd = (lp - lm) / (2 * eps)
+            assert abs(tw[f, k] - fd) <= 2e-6 * max(abs(tw[f, k]), 1e-2 * np.abs(tw[f]).max()), \
+                (f, k, tw[f, k], fd)
+    assert tused >= 10

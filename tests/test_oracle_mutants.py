@@ -45,6 +45,15 @@ MUTANTS = [
     ("jacobian_tz", "dt[2] += GJ[0] * (-fx / (tz * tz));", "dt[2] += GJ[0] * (-fx / tz);"),
     ("scale_chain", "g_log_scales[g * 3 + a] = ds[a] * G.s[a];", "g_log_scales[g * 3 + a] = ds[a];"),
     ("sh_grad_dir", "dd[a] = (ddir[a] - r->dir[a] * dd0) / r->dist;", "dd[a] = ddir[a] / r->dist;"),
+    ("jguard_tz_term", "dt[2] += GJ[2] * (fx * txc / (tz * tz * tz));", "(void)txc;"),
+    ("jguard_txc_for_tx", "dt[2] += GJ[2] * (fx * txc / (tz * tz * tz));",
+     "dt[2] += GJ[2] * (fx * tx / (tz * tz * tz));"),
+    ("jguard_y_tz_term", "dt[2] += GJ[5] * (fy * tyc / (tz * tz * tz));",
+     "dt[2] += GJ[5] * (fy * ty / (tz * tz * tz));"),
+    ("jguard_width_for_height", "const double limy = JGUARD * (double)cam->height / (2.0 * fy);",
+     "const double limy = JGUARD * (double)cam->width / (2.0 * fy);"),
+    ("jguard_flag_without_clamp", "if (rx > limx) { rx = limx; r->clamp_x = 1; }",
+     "if (rx > limx) { r->clamp_x = 1; }"),
     ("median_before_blend", "if (*med < 0 && Tn < 0.5) {", "if (*med < 0 && T < 0.5) {"),
     ("median_last_crossing", "if (*med < 0 && Tn < 0.5) {", "if (Tn < 0.5) {"),
     ("median_bwd_blended", "if (i == med) gr[9] += GD;", "gr[9] += GD * w;"),
@@ -61,6 +70,8 @@ CHECKS = [
     ("fd_params", lambda: fd.test_parameter_gradients_match_central_differences(11, 3, 2, (0.1, 0.2, 0.3))),
     ("fd_twist", lambda: fd.test_twist_gradient_matches_central_differences(21, 3)),
     ("fd_colour", fd.test_colour_clamp_and_direction_paths),
+    ("guard_jacobian", lambda: pins.test_guard_is_the_jacobian_at_the_clamped_point(41)),
+    ("fd_guard", lambda: fd.test_gradients_through_the_jacobian_guard(41, 2)),
     ("median_brute", lambda: med.test_median_matches_brute_force(2, 150, 2, (32, 8))),
     ("median_layered", lambda: med.test_layered_closed_form([-0.9, -0.4, 2.0], [3.5, 2.0, 2.5])),
     ("median_grad", med.test_single_pixel_gradient_closed_form),

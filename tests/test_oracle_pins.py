@@ -265,6 +265,53 @@ def test_ewa_covariance_is_linearised_projection():
             assert abs(rec["radius"][k] - 3 * math.sqrt(np.linalg.eigvalsh(got)[-1])) < 1e-9
 
 
+@pytest.mark.parametrize("seed", [41, 43])
+def test_guard_is_the_jacobian_at_the_clamped_point(seed):
+    """Outside the guard, Sigma' - 0.3 I = J(t~) Sc J(t~)^T where J(t~) is the
+    central-difference Jacobian of the pinhole map at t~ = (t_z clip(t_x/t_z,
+    +-1.3 W/(2 f_x)), t_z clip(t_y/t_z, +-1.3 H/(2 f_y)), t_z); the projected
+    mean (u, v) is the pinhole image of the unclamped t."""
+    import test_oracle_fd as fdt
+    sc = fdt.guard_scene(seed, 1)
+    r = oracle.forward(sc)
+    rec = r.records()
+    keep = rec["keep"].astype(bool)
+    clx, cly = fdt.clamped_records(sc, rec)
+    assert (keep & (clx | cly)).sum() >= 20
+    checked = 0
+    for f in range(sc.n_frames):
+        W, H = sc.cams[f][:2]
+        fx, fy, cx, cy = [float(np.float32(v)) for v in sc.cams[f][2:6]]
+        P = sc.poses[f].astype(np.float64)
+        for g in range(sc.n):
+            k = f * sc.n + g
+            if not keep[k]:
+                continue
+            mu = sc.means[g].astype(np.float64)
+            t = P[:, :3] @ mu + P[:, 3]
+
+            def pi(tt):
+                return np.array([fx * tt[0] / tt[2] + cx, fy * tt[1] / tt[2] + cy])
+            np.testing.assert_allclose([rec["u"][k], rec["v"][k]], pi(t), rtol=1e-12)
+            lx, ly = 1.3 * W / (2 * fx), 1.3 * H / (2 * fy)
+            tc = np.array([t[2] * np.clip(t[0] / t[2], -lx, lx),
+                           t[2] * np.clip(t[1] / t[2], -ly, ly), t[2]])
+            Jfd = np.zeros((2, 3))
+            for a in range(3):
+                e = np.zeros(3)
+                e[a] = 1e-6 * max(1.0, abs(tc[a]))
+                Jfd[:, a] = (pi(tc + e) - pi(tc - e)) / (2 * e[a])
+            q = sc.quats[g].astype(np.float64)
+            Rg = Rotation.from_quat(q[[1, 2, 3, 0]]).as_matrix()
+            Sig = Rg @ np.diag(np.exp(2 * sc.log_scales[g].astype(np.float64))) @ Rg.T
+            Sc = P[:, :3] @ Sig @ P[:, :3].T
+            S2 = Jfd @ Sc @ Jfd.T + 0.3 * np.eye(2)
+            got = np.array([[rec["sxx"][k], rec["sxy"][k]], [rec["sxy"][k], rec["syy"][k]]])
+            np.testing.assert_allclose(got, S2, rtol=1e-7, atol=1e-9)
+            checked += 1
+    assert checked >= 40
+
+
 # ------------------------------------------------------------------ P4
 def _grads_equal(ga, gb, perm=None, tol=1e-12):
     for k in ("means", "log_scales", "quats", "opacity", "sh"):

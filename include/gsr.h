@@ -36,6 +36,12 @@
  *    pixel only inside its square (so results do not depend on the tile
  *    shape); a = min(0.99, sigma exp(-q/2)); entries with a < 1/255 are
  *    skipped; a pixel stops before the entry that would take T below 1e-4.
+ *    A Gaussian with a non-finite parameter (NaN or +-Inf in its mean,
+ *    scales, quaternion, opacity logit or an SH coefficient of the rendered
+ *    degree) is culled in every frame; a Gaussian that no frame keeps gets
+ *    gradients of exactly 0.
+ *  - Cameras: width, height in [1, 65535]; fx, fy > 0 and finite; cx, cy
+ *    finite; near_z > 0 and finite (GSR_ERR_INVALID_ARGUMENT otherwise).
  *  - The pose gradient g_twist [F,6] = dL/dxi at xi = 0 for the left
  *    perturbation T_f <- Exp(xi) T_f, xi = (rho, phi), translation first.
  *  - Gradient outputs are overwritten, never accumulated.
@@ -351,9 +357,18 @@ typedef struct {
   int32_t tile_w, tile_h;
   int64_t n_pairs;      /* evaluated (pixel, entry) pairs of the last forward
                            with GSR_FLAG_COUNT_PAIRS, else -1 */
+  int64_t n_culled;     /* (Gaussian, frame) records the last forward culled:
+                           behind the near plane, not positive definite,
+                           outside the image, too faint, or non-finite */
+  int64_t n_nonfinite;  /* Gaussians with a non-finite parameter (means,
+                           log-scales, quaternion, opacity logit or an SH
+                           coefficient of the rendered degree); each is culled
+                           in every frame and its gradients are 0 */
 } gsr_stats;
 
-/* Statistics of the last forward (synchronises `stream`). */
+/* Statistics of the last forward (synchronises `stream`).  n_culled and
+ * n_nonfinite are counted on the device from the forward's parameter buffers,
+ * which must still hold the forward's inputs. */
 gsr_status gsr_debug_stats(gsr_context* ctx, gsr_stats* out, void* stream);
 
 /* Per-stage GPU time of every call made with GSR_FLAG_TIMING since the last

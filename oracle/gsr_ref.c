@@ -269,8 +269,25 @@ static void gaussian_setup(const ref_state* st, int64_t g, gauss_t* G) {
   G->opacity = 1.0 / (1.0 + exp(-st->opac[g]));
 }
 
+/* A Gaussian takes part only if every one of its parameters is a finite
+ * number: means, log-scales, quaternion, opacity logit and the SH
+ * coefficients of the rendered degree (the paper is silent; a non-finite
+ * parameter would otherwise reach the images through the colour or through
+ * an infinite depth). */
+static int params_finite(const ref_state* st, int64_t g) {
+  for (int a = 0; a < 3; ++a)
+    if (!isfinite(st->means[g * 3 + a]) || !isfinite(st->log_scales[g * 3 + a])) return 0;
+  for (int a = 0; a < 4; ++a)
+    if (!isfinite(st->quats[g * 4 + a])) return 0;
+  if (!isfinite(st->opac[g])) return 0;
+  for (int i = 0; i < st->K_sh * 3; ++i)
+    if (!isfinite(st->sh[g * st->K_sh * 3 + i])) return 0;
+  return 1;
+}
+
 static void build_record(const ref_state* st, int f, int64_t g, rec_t* r) {
   memset(r, 0, sizeof(*r));
+  if (!params_finite(st, g)) return;
   const ref_camera* cam = &st->cams[f];
   const double* P = &st->poses[f * 12];
   const double W[9] = {P[0], P[1], P[2], P[4], P[5], P[6], P[8], P[9], P[10]};
@@ -803,9 +820,11 @@ int ref_backward(ref_state* st, const double* g_rgb, const double* g_depth,
       double* dsh = &g_sh[g * Ksh * 3];
       for (int i = 0; i < Ksh * 3; ++i) dsh[i] = 0.0;
       const double mu[3] = {st->means[g * 3], st->means[g * 3 + 1], st->means[g * 3 + 2]};
+      int kept = 0;
       for (int f = 0; f < F; ++f) {
         const rec_t* r = &st->rec[(int64_t)f * n + g];
         if (!r->keep) continue;
+        kept = 1;
         const double* gr = &acc[((int64_t)f * n + g) * NG2];
         const ref_camera* cam = &st->cams[f];
         const double* P = &st->poses[f * 12];
@@ -920,6 +939,12 @@ int ref_backward(ref_state* st, const double* g_rgb, const double* g_depth,
           twf[3 + k] += s;
         }
         (void)mu;
+      }
+      if (!kept) { /* no frame sees it: every gradient is exactly 0 */
+        for (int a = 0; a < 3; ++a) g_means[g * 3 + a] = g_log_scales[g * 3 + a] = 0.0;
+        for (int a = 0; a < 4; ++a) g_quats[g * 4 + a] = 0.0;
+        g_opac[g] = 0.0;
+        continue;
       }
       /* Sigma = M M^T with M = R diag(s):  G_M = 2 G_Sigma M (G_Sigma symmetric) */
       double Gs[9];

@@ -138,6 +138,21 @@ def render(means, log_scales, quats, opacity_logits, sh, sh_degree, cams, poses,
     ill-conditioning and cancellation included; None renders exactly."""
     out = []
     bg = torch.tensor([float(b) for b in background], dtype=torch.float64)
+    # a surfel with a non-finite parameter is culled in every frame; its
+    # values are replaced by harmless ones behind a mask, so that its
+    # gradients are exactly 0 instead of 0 * NaN
+    K3 = (sh_degree + 1) ** 2
+    finite = (torch.isfinite(means).all(1) & torch.isfinite(log_scales).all(1)
+              & torch.isfinite(quats).all(1) & torch.isfinite(opacity_logits)
+              & torch.isfinite(sh[:, :K3].reshape(sh.shape[0], -1)).all(1))
+    if not bool(finite.all()):
+        fm = finite[:, None]
+        means = torch.where(fm, means, torch.zeros_like(means))
+        log_scales = torch.where(fm, log_scales, torch.zeros_like(log_scales))
+        quats = torch.where(fm, quats, torch.tensor([1.0, 0.0, 0.0, 0.0], dtype=quats.dtype))
+        opacity_logits = torch.where(finite, opacity_logits, torch.zeros_like(opacity_logits))
+        sh = torch.where(finite[:, None, None], sh, torch.zeros_like(sh))
+    finite_np = finite.numpy()
     Rg = _rot(quats)                                # [n,3,3]
     su, sv = torch.exp(log_scales[:, 0]), torch.exp(log_scales[:, 1])
     opac = torch.sigmoid(opacity_logits)
@@ -171,7 +186,7 @@ def render(means, log_scales, quats, opacity_logits, sh, sh_degree, cams, poses,
             for g in range(n):
                 o = float(opn[g])
                 zc = float(mcn[g, 2])
-                if not (o > A_MIN) or not (zc > near):
+                if not finite_np[g] or not (o > A_MIN) or not (zc > near):
                     continue
                 r2 = 2.0 * math.log(o / A_MIN)          # r_a^2
                 ra = math.sqrt(r2)

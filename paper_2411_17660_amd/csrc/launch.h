@@ -25,6 +25,13 @@ void launch_preprocess_bwd(hipStream_t st, int64_t n, int F, const FrameDesc* fr
 void launch_bump_epoch(hipStream_t st, uint32_t* epoch);
 // cls[r] = 1 + floor(log2(ntiles[r])) (0 when culled), idx[r] = r: the input
 // of the radix sort that orders the per-record reduction
+// Statistics of the last forward: out[0] += records with no tile (culled),
+// out[1] += Gaussians with a non-finite parameter (log_per = 3 log-scales
+// per Gaussian, or 2 for surfels; nb3 = 3 (d+1)^2 SH values).
+void launch_cull_stats(hipStream_t st, uint64_t m, const uint32_t* ntiles, int64_t n,
+                       const float* means, const float* log_scales, int log_per,
+                       const float* quats, const float* opac, const float* sh, int nb3,
+                       unsigned long long* out);
 void launch_size_class(hipStream_t st, uint64_t m, const uint32_t* ntiles, uint32_t* cls,
                        uint32_t* idx);
 

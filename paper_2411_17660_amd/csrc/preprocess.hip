@@ -62,6 +62,22 @@ __device__ __forceinline__ void gaussian_setup(const float* __restrict__ log_sca
   G.opacity = 1.0 / (1.0 + exp(-(double)opac[g]));
 }
 
+// A Gaussian takes part only if all its parameters (means, log-scales,
+// quaternion, opacity logit, the SH coefficients of the rendered degree) are
+// finite numbers; otherwise every one of its records is culled and all its
+// gradients are 0.
+__device__ __forceinline__ bool params_finite(const float* __restrict__ means,
+                                              const float* __restrict__ log_scales,
+                                              const float* __restrict__ quats,
+                                              const float* __restrict__ opac,
+                                              const float* __restrict__ sh, int nb3, int64_t g) {
+  bool ok = isfinite(opac[g]);
+  for (int a = 0; a < 3; ++a) ok = ok && isfinite(means[g * 3 + a]) && isfinite(log_scales[g * 3 + a]);
+  for (int a = 0; a < 4; ++a) ok = ok && isfinite(quats[g * 4 + a]);
+  for (int i = 0; i < nb3; ++i) ok = ok && isfinite(sh[g * nb3 + i]);
+  return ok;
+}
+
 // Projection of one Gaussian into one frame (FP64).
 struct Proj {
   bool keep;
@@ -179,13 +195,15 @@ __global__ void __launch_bounds__(256) preprocess_fwd_kernel(
   gaussian_setup(log_scales, quats, opac, g, G);
   const double mu[3] = {means[g * 3 + 0], means[g * 3 + 1], means[g * 3 + 2]};
   constexpr int nb = (DEG + 1) * (DEG + 1);
+  const bool finite = params_finite(means, log_scales, quats, opac, sh, nb * 3, g);
   for (int f = (int)blockIdx.y; f < n_frames; f += (int)gridDim.y) {
     const int64_t r = (int64_t)f * n + g;
     const FrameDesc fr = frames[f];
     double W[9], tf[3];
     load_pose(poses, f, W, tf);
     Proj p;
-    project(fr, W, tf, mu, G, p);
+    p.keep = false;
+    if (finite) project(fr, W, tf, mu, G, p);
     rec_id[r] = (uint32_t)r;
     if (!p.keep) {
       depth_key[r] = 0xffffffffu;
@@ -334,11 +352,13 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(
   double dmu[3] = {0, 0, 0}, dSig[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, dsig = 0.0;
   float dsh[nb * 3];
   for (int i = 0; i < nb * 3; ++i) dsh[i] = 0.0f;
+  bool kept = false;
   for (int f = 0; f < n_frames; ++f) {
     double tw[6] = {0, 0, 0, 0, 0, 0};
     const int64_t r = (int64_t)f * n + g;
     const uint32_t cnt = active ? ntiles[r] : 0u;
     if (cnt > 0) {
+      kept = true;
       double gr[kNG];
       for (int j = 0; j < kNG; ++j) gr[j] = grad2d[r * kNG + j];
       const FrameDesc fr = frames[f];
@@ -463,6 +483,14 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(
     }
   }
   if (!active) return;
+  float* gs = g_sh + g * nb * 3;
+  if (!kept) {  // no frame sees it (culled, or a non-finite parameter)
+    for (int a = 0; a < 3; ++a) g_means[g * 3 + a] = g_log_scales[g * 3 + a] = 0.0f;
+    for (int a = 0; a < 4; ++a) g_quats[g * 4 + a] = 0.0f;
+    g_opac[g] = 0.0f;
+    for (int i = 0; i < nb * 3; ++i) gs[i] = 0.0f;
+    return;
+  }
   // Sigma = M M^T, M = R diag(s)
   double Gs[9];
   for (int i = 0; i < 3; ++i)
@@ -484,7 +512,6 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(
   quat_grad(G.qh, G.qn, dR, g_quats + g * 4);
   for (int a = 0; a < 3; ++a) g_means[g * 3 + a] = (float)dmu[a];
   g_opac[g] = (float)(dsig * G.opacity * (1.0 - G.opacity));
-  float* gs = g_sh + g * nb * 3;
   for (int i = 0; i < nb * 3; ++i) gs[i] = dsh[i];
 }
 
@@ -494,6 +521,41 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(
 __global__ void bump_epoch_kernel(uint32_t* epoch) {
   const uint32_t e = *epoch + 1u;
   *epoch = e == 0u ? 1u : e;
+}
+
+// Counts for gsr_debug_stats (integer atomics, so the totals do not depend
+// on the order): culled records, and Gaussians with a non-finite parameter.
+__global__ void __launch_bounds__(256) cull_stats_kernel(
+    uint64_t m, const uint32_t* __restrict__ ntiles, int64_t n, const float* __restrict__ means,
+    const float* __restrict__ log_scales, int log_per, const float* __restrict__ quats,
+    const float* __restrict__ opac, const float* __restrict__ sh, int nb3,
+    unsigned long long* __restrict__ out) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool culled = i < m && ntiles[i] == 0;
+  bool bad = false;
+  if (i < (uint64_t)n) {
+    bool ok = isfinite(opac[i]);
+    for (int a = 0; a < 3; ++a) ok = ok && isfinite(means[i * 3 + a]);
+    for (int a = 0; a < log_per; ++a) ok = ok && isfinite(log_scales[i * log_per + a]);
+    for (int a = 0; a < 4; ++a) ok = ok && isfinite(quats[i * 4 + a]);
+    for (int a = 0; a < nb3; ++a) ok = ok && isfinite(sh[i * nb3 + a]);
+    bad = !ok;
+  }
+  const uint64_t c = __ballot(culled), b = __ballot(bad);
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    if (c) atomicAdd(&out[0], (unsigned long long)__popcll(c));
+    if (b) atomicAdd(&out[1], (unsigned long long)__popcll(b));
+  }
+}
+
+void launch_cull_stats(hipStream_t st, uint64_t m, const uint32_t* ntiles, int64_t n,
+                       const float* means, const float* log_scales, int log_per,
+                       const float* quats, const float* opac, const float* sh, int nb3,
+                       unsigned long long* out) {
+  const uint64_t items = std::max<uint64_t>(m, (uint64_t)n);
+  if (items == 0) return;
+  hipLaunchKernelGGL(cull_stats_kernel, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, st,
+                     m, ntiles, n, means, log_scales, log_per, quats, opac, sh, nb3, out);
 }
 
 void launch_size_class(hipStream_t st, uint64_t m, const uint32_t* ntiles, uint32_t* cls,

@@ -108,10 +108,18 @@ gsr_status hip_check(gsr_context* c, hipError_t e, const char* what) {
   } while (0)
 
 // Grow-only device buffer.  Growing synchronises the stream first so that no
-// queued kernel still uses the old allocation.
+// queued kernel still uses the old allocation; it is refused while the stream
+// is being captured into a graph (a capture must follow an uncaptured call of
+// the same sizes).  `zero` clears a new buffer with a fill kernel.
 gsr_status ensure(gsr_context* ctx, DBuf& b, size_t bytes, hipStream_t st, bool zero = false) {
   if (bytes == 0) bytes = 16;
   if (b.bytes >= bytes) return GSR_OK;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  GSR_HIP(hipStreamIsCapturing(st, &cap));
+  if (cap != hipStreamCaptureStatusNone)
+    return fail(ctx, GSR_ERR_STATE,
+                "workspace must grow to %zu bytes during graph capture; run the call once "
+                "uncaptured with the same sizes first", bytes);
   const size_t want = bytes + bytes / 4;
   if (b.p) {
     GSR_HIP(hipStreamSynchronize(st));
@@ -126,7 +134,7 @@ gsr_status ensure(gsr_context* ctx, DBuf& b, size_t bytes, hipStream_t st, bool 
   }
   b.p = p;
   b.bytes = want;
-  if (zero) GSR_HIP(hipMemsetAsync(p, 0, want, st));
+  if (zero) launch_fill_u32(st, static_cast<uint32_t*>(p), want / 4, 0u);
   return GSR_OK;
 }
 
@@ -172,8 +180,12 @@ gsr_status validate(gsr_context* ctx, const gsr_settings* s, int64_t n, const fl
     const gsr_camera& c = cams[f];
     if (c.width < 1 || c.height < 1 || c.width > 65535 || c.height > 65535)
       return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "frame %d: size %dx%d", f, c.width, c.height);
-    if (!(c.fx > 0.0f) || !(c.fy > 0.0f))
-      return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "frame %d: focal length <= 0", f);
+    if (!(c.fx > 0.0f) || !(c.fy > 0.0f) || !std::isfinite(c.fx) || !std::isfinite(c.fy))
+      return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "frame %d: focal length not finite and > 0", f);
+    if (!std::isfinite(c.cx) || !std::isfinite(c.cy))
+      return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "frame %d: principal point not finite", f);
+    if (!(c.near_z > 0.0f) || !std::isfinite(c.near_z))
+      return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "frame %d: near_z not finite and > 0", f);
   }
   return GSR_OK;
 }
@@ -249,8 +261,9 @@ gsr_status gsr_create(gsr_context** out, int32_t device) {
   if (!ctx) return GSR_ERR_OUT_OF_MEMORY;
   ctx->device = device;
   if (hipEventCreateWithFlags(&ctx->frames_ev, hipEventDisableTiming) != hipSuccess ||
-      hipHostMalloc((void**)&ctx->h_count, sizeof(uint64_t) * 4, hipHostMallocDefault) !=
+      hipHostMalloc((void**)&ctx->h_count, sizeof(uint64_t) * 8, hipHostMallocDefault) !=
           hipSuccess) {
+    if (ctx->frames_ev) (void)hipEventDestroy(ctx->frames_ev);
     delete ctx;
     return GSR_ERR_HIP;
   }
@@ -1008,9 +1021,17 @@ gsr_status gsr_debug_stats(gsr_context* ctx, gsr_stats* out, void* stream) {
   if (!sv.valid) return fail(ctx, GSR_ERR_STATE, "no forward");
   hipStream_t st = (hipStream_t)stream;
   GSR_HIP(hipSetDevice(ctx->device));
-  GSR_HIP(hipMemcpyAsync(ctx->h_count, ctx->counters.p, 24, hipMemcpyDeviceToHost, st));
+  unsigned long long* cull = (unsigned long long*)(P<uint64_t>(ctx->counters) + 4);
+  launch_fill_u32(st, (uint32_t*)cull, 4, 0u);
+  const int nb3 = 3 * (sv.set.sh_degree + 1) * (sv.set.sh_degree + 1);
+  launch_cull_stats(st, (uint64_t)sv.n * sv.F, P<uint32_t>(ctx->ntiles), sv.n, sv.means,
+                    sv.log_scales, sv.surfel ? 2 : 3, sv.quats, sv.opac, sv.sh, nb3, cull);
+  GSR_HIP(hipGetLastError());
+  GSR_HIP(hipMemcpyAsync(ctx->h_count, ctx->counters.p, 48, hipMemcpyDeviceToHost, st));
   GSR_HIP(hipStreamSynchronize(st));
   out->n_pairs = ctx->n_pairs == -2 ? (int64_t)ctx->h_count[2] : -1;
+  out->n_culled = (int64_t)ctx->h_count[4];
+  out->n_nonfinite = (int64_t)ctx->h_count[5];
   out->n_records = sv.n * sv.F;
   out->n_keys = (int64_t)ctx->h_count[0];
   out->n_tiles = sv.T;

@@ -74,6 +74,11 @@ __global__ void __launch_bounds__(256) surfel_preprocess_kernel(
   const double mu[3] = {means[3 * g], means[3 * g + 1], means[3 * g + 2]};
   constexpr int nb = (DEG + 1) * (DEG + 1);
   const double amin = (double)kAlphaMin;
+  // a surfel with a non-finite parameter is culled in every frame
+  bool finite = isfinite(opac[g]) && isfinite(log_scales[2 * g]) && isfinite(log_scales[2 * g + 1]);
+  for (int a = 0; a < 3; ++a) finite = finite && isfinite(means[3 * g + a]);
+  for (int a = 0; a < 4; ++a) finite = finite && isfinite(quats[4 * g + a]);
+  for (int i = 0; i < nb * 3; ++i) finite = finite && isfinite(sh[g * nb * 3 + i]);
   for (int f = (int)blockIdx.y; f < n_frames; f += (int)gridDim.y) {
     const int64_t r = (int64_t)f * n + g;
     const FrameDesc fr = frames[f];
@@ -90,7 +95,7 @@ __global__ void __launch_bounds__(256) surfel_preprocess_kernel(
                        W[i * 3 + 2] * Rg[2 * 3 + j];
     }
     const double near = fr.near_z;
-    if (!(o > amin) || !(mc[2] > near)) continue;
+    if (!finite || !(o > amin) || !(mc[2] > near)) continue;
     const double fx = fr.fx, fy = fr.fy, cx = fr.cx, cy = fr.cy;
     // columns a = s_u t_u, b = s_v t_v, c = mc; rows of M = K [a | b | c]
     const double A[3] = {su * T[0], su * T[3], su * T[6]};
@@ -661,10 +666,12 @@ __global__ void __launch_bounds__(256) surfel_preprocess_bwd_kernel(
   double dmu[3] = {0, 0, 0}, dR[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, dls[2] = {0, 0}, dop = 0.0;
   float dsh[nb * 3];
   for (int i = 0; i < nb * 3; ++i) dsh[i] = 0.0f;
+  bool kept = false;
   for (int f = 0; f < n_frames; ++f) {
     double tw[6] = {0, 0, 0, 0, 0, 0};
     const int64_t r = (int64_t)f * n + g;
     uint32_t cnt = active ? ntiles[r] : 0u;
+    kept = kept || cnt > 0;
     const uint32_t off = cnt ? keyoff[r] : 0u;
     if (cnt && (uint64_t)off + cnt > key_capacity) cnt = 0;  // overflowed in keygen
     if (cnt > 0) {
@@ -753,6 +760,14 @@ __global__ void __launch_bounds__(256) surfel_preprocess_bwd_kernel(
     }
   }
   if (!active) return;
+  if (!kept) {  // no frame sees it (culled, or a non-finite parameter)
+    for (int a = 0; a < 3; ++a) g_means[g * 3 + a] = 0.0f;
+    for (int a = 0; a < 4; ++a) g_quats[g * 4 + a] = 0.0f;
+    g_log_scales[2 * g] = g_log_scales[2 * g + 1] = 0.0f;
+    g_opac[g] = 0.0f;
+    for (int i = 0; i < nb * 3; ++i) g_sh[g * nb * 3 + i] = 0.0f;
+    return;
+  }
   g_log_scales[2 * g] = (float)dls[0];
   g_log_scales[2 * g + 1] = (float)dls[1];
   quat_grad(qh, qn, dR, g_quats + g * 4);

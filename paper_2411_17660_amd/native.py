@@ -44,7 +44,8 @@ class Settings(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("n_records", C.c_int64), ("n_keys", C.c_int64), ("n_tiles", C.c_int64),
                 ("n_pixels", C.c_int64), ("key_capacity", C.c_int64), ("epoch", C.c_uint32),
-                ("tile_w", C.c_int32), ("tile_h", C.c_int32), ("n_pairs", C.c_int64)]
+                ("tile_w", C.c_int32), ("tile_h", C.c_int32), ("n_pairs", C.c_int64),
+                ("n_culled", C.c_int64), ("n_nonfinite", C.c_int64)]
 
 
 class GsrError(RuntimeError):

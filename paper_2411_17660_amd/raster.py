@@ -43,6 +43,9 @@ class Rasterizer:
         self.n = 0
         self.F = 0
         self.sizes = []
+        # advanced by every call that replaces the saved forward state, so that
+        # a backward can tell whether the state it reads is still its own
+        self.generation = 0
 
     def __del__(self):
         h = getattr(self, "h", None)
@@ -73,6 +76,7 @@ class Rasterizer:
                                              median=median)
         self.cams = native.make_cameras(cams)
         n = int(means.shape[0])
+        self.generation += 1
         self._check(self.lib.gsr_forward(self.h, C.byref(self.settings), n, _ptr(means),
                                          _ptr(log_scales), _ptr(quats), _ptr(opacity), _ptr(sh),
                                          F, self.cams, _ptr(poses), _ptr(rgb), _ptr(depth),
@@ -97,6 +101,7 @@ class Rasterizer:
                                              timing=timing, count_pairs=count_pairs)
         self.cams = native.make_cameras(cams)
         n = int(means.shape[0])
+        self.generation += 1
         self._check(self.lib.gsr_forward_surfel(
             self.h, C.byref(self.settings), n, _ptr(means), _ptr(log_scales), _ptr(quats),
             _ptr(opacity), _ptr(sh), len(cams), self.cams, _ptr(poses), _ptr(rgb), _ptr(depth),
@@ -189,6 +194,7 @@ class Rasterizer:
         self.cams = native.make_cameras(cams)
         n = int(means.shape[0])
         b = bufs
+        self.generation += 1
         self._check(self.lib.gsr_step_render(
             self.h, C.byref(self.settings), n, _ptr(means), _ptr(log_scales), _ptr(quats),
             _ptr(opacity), _ptr(sh), len(cams), self.cams, _ptr(poses), _ptr(target_rgb),
@@ -228,6 +234,7 @@ class Rasterizer:
         self.cams = native.make_cameras(cams)
         n = int(means.shape[0])
         b = bufs
+        self.generation += 1
         self._check(self.lib.gsr_step_l1(
             self.h, C.byref(self.settings), n, _ptr(means), _ptr(log_scales), _ptr(quats),
             _ptr(opacity), _ptr(sh), len(cams), self.cams, _ptr(poses), _ptr(target_rgb),
@@ -246,6 +253,7 @@ class Rasterizer:
         chosen = native.Settings()
         ms = (C.c_float * len(native.TILE_SHAPES))()
         cams_c = native.make_cameras(cams)
+        self.generation += 1
         self._check(self.lib.gsr_autotune(
             self.h, C.byref(base), int(means.shape[0]), _ptr(means), _ptr(log_scales),
             _ptr(quats), _ptr(opacity), _ptr(sh), len(cams), cams_c, _ptr(poses),
@@ -326,11 +334,17 @@ class _RasterizeFn(torch.autograd.Function):
         # the library's backward reads the inputs again: hold them until then
         ctx.inputs = inputs
         ctx.rast = rast
+        ctx.generation = rast.generation
         return rgb, depth, alpha
 
     @staticmethod
     def backward(ctx, g_rgb, g_depth, g_alpha):
         rast = ctx.rast
+        if rast.generation != ctx.generation:
+            raise RuntimeError(
+                "rasterize(): the Rasterizer rendered again before this backward; run "
+                "each forward's backward before the next forward on the same Rasterizer, "
+                "or give each render its own Rasterizer")
         dev = next(t.device for t in (g_rgb, g_depth, g_alpha) if t is not None)
         P = sum(w * h for w, h in rast.sizes)
 
@@ -342,15 +356,37 @@ class _RasterizeFn(torch.autograd.Function):
                 None, None, None, None, None, None, None)
 
 
+_default = {}
+
+
+def default_rasterizer(device=0):
+    """One shared Rasterizer (library context and workspace) per device."""
+    r = _default.get(device)
+    if r is None:
+        r = _default[device] = Rasterizer(device)
+    return r
+
+
 def rasterize(means, log_scales, quats, opacity, sh, poses, cams, sh_degree, twist=None,
-              background=(0.0, 0.0, 0.0), tile=(16, 16), rasterizer=None, median=False):
+              background=(0.0, 0.0, 0.0), tile=(16, 16), rasterizer=None, median=False,
+              check_twist=True):
     """Differentiable render of F keyframes.  Returns packed (rgb, depth,
     alpha); depth is alpha-blended, or the median depth with median=True.
-    Gradients reach every Gaussian tensor and `twist` ([F,6] zeros, the
-    left-perturbation of each pose at zero).  The backward of one forward
-    must run before the next forward on the same `rasterizer`."""
-    rast = rasterizer or Rasterizer(means.device.index or 0)
+
+    Gradients reach every Gaussian tensor and `twist` ([F,6], the
+    left-perturbation xi = (rho, phi) of each pose, T_f <- Exp(xi_f) T_f).
+    The library differentiates at xi = 0, so `twist` must hold zeros: after
+    an optimiser step on it, fold it into the poses (Rasterizer.adam_step
+    does the fold) and zero it.  check_twist verifies this with one
+    device-to-host read per call.  Renders share `rasterizer` (default: one
+    per device); the backward of a render must run before the next render on
+    the same rasterizer, else it raises."""
+    dev = means.device.index if means.device.index is not None else 0
+    rast = rasterizer if rasterizer is not None else default_rasterizer(dev)
     if twist is None:
-        twist = torch.zeros(len(cams), 6, device=means.device, requires_grad=False)
+        twist = torch.zeros(len(cams), 6, device=means.device)
+    elif check_twist and int(torch.count_nonzero(twist.detach())) != 0:
+        raise ValueError("rasterize(): twist must be zero (the pose gradient is taken at "
+                         "xi = 0); fold a twist into the poses before rendering")
     return _RasterizeFn.apply(means, log_scales, quats, opacity, sh, twist, poses, cams,
                               sh_degree, tuple(background), tuple(tile), rast, bool(median))

@@ -35,12 +35,36 @@ def test_every_declared_symbol_is_exported(lib):
         assert name in native.EXPORTS, name
 
 
-def test_struct_layouts_match_header(lib):
+def _c_layout(struct, fields, tmp_path):
+    """sizeof and offsetof of the header's struct, from a C compiler."""
+    import subprocess
+    src = tmp_path / "layout.c"
+    body = "".join(f'  printf("%zu\\n", offsetof({struct}, {f}));\n' for f in fields)
+    src.write_text(f"""#include <stddef.h>
+#include <stdio.h>
+#include "gsr.h"
+int main(void) {{
+  printf("%zu\\n", sizeof({struct}));
+{body}  return 0;
+}}
+""")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    vals = [int(v) for v in out.split()]
+    return vals[0], vals[1:]
+
+
+@pytest.mark.parametrize("cname,pyname", [("gsr_camera", "Camera"), ("gsr_settings", "Settings"),
+                                          ("gsr_stats", "Stats")])
+def test_struct_layouts_match_header(lib, cname, pyname, tmp_path):
     from paper_2411_17660_amd import native
-    assert C.sizeof(native.Camera) == 28
-    assert C.sizeof(native.Settings) == 48
-    assert native.Settings.key_capacity.offset == 32
-    assert C.sizeof(native.Stats) == 64
+    cls = getattr(native, pyname)
+    fields = [f for f, _ in cls._fields_]
+    size, offs = _c_layout(cname, fields, tmp_path)
+    assert C.sizeof(cls) == size
+    assert [getattr(cls, f).offset for f in fields] == offs
 
 
 def test_null_context_is_rejected_without_touching_the_gpu(lib):

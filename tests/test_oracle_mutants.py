@@ -54,6 +54,8 @@ MUTANTS = [
      "const double limy = JGUARD * (double)cam->width / (2.0 * fy);"),
     ("jguard_flag_without_clamp", "if (rx > limx) { rx = limx; r->clamp_x = 1; }",
      "if (rx > limx) { r->clamp_x = 1; }"),
+    ("nonfinite_sh_unchecked", "if (!isfinite(st->sh[g * st->K_sh * 3 + i])) return 0;", "(void)0;"),
+    ("nonfinite_grads_not_zeroed", "if (!kept) { /* no frame sees it", "if (0) { /* no frame sees it"),
     ("median_before_blend", "if (*med < 0 && Tn < 0.5) {", "if (*med < 0 && T < 0.5) {"),
     ("median_last_crossing", "if (*med < 0 && Tn < 0.5) {", "if (Tn < 0.5) {"),
     ("median_bwd_blended", "if (i == med) gr[9] += GD;", "gr[9] += GD * w;"),
@@ -72,6 +74,8 @@ CHECKS = [
     ("fd_colour", fd.test_colour_clamp_and_direction_paths),
     ("guard_jacobian", lambda: pins.test_guard_is_the_jacobian_at_the_clamped_point(41)),
     ("fd_guard", lambda: fd.test_gradients_through_the_jacobian_guard(41, 2)),
+    ("nonfinite_sh", lambda: pins.test_nonfinite_gaussian_is_removed("sh", (0, 0, 1), np.nan)),
+    ("nonfinite_quat", lambda: pins.test_nonfinite_gaussian_is_removed("quats", (0, 0), np.nan)),
     ("median_brute", lambda: med.test_median_matches_brute_force(2, 150, 2, (32, 8))),
     ("median_layered", lambda: med.test_layered_closed_form([-0.9, -0.4, 2.0], [3.5, 2.0, 2.5])),
     ("median_grad", med.test_single_pixel_gradient_closed_form),

@@ -336,6 +336,47 @@ def test_zero_opacity_gives_background_and_zero_gradients():
         assert np.all(np.abs(v) < 1e-10), k
 
 
+def _drop(sc, g):
+    keep = np.arange(sc.n) != g
+    return scenes.Scene(sc.means[keep], sc.log_scales[keep], sc.quats[keep], sc.opacity[keep],
+                        sc.sh[keep], sc.sh_degree, sc.cams, sc.poses, sc.background)
+
+
+NONFINITE = [("means", (0, 0), np.nan), ("means", (0, 2), np.inf),
+             ("log_scales", (0, 1), np.nan), ("log_scales", (0, 0), np.inf),
+             ("quats", (0, 3), -np.inf), ("quats", (0, 0), np.nan),
+             ("opacity", (0,), np.nan), ("opacity", (0,), np.inf),
+             ("sh", (0, 0, 1), np.nan), ("sh", (0, 15, 2), -np.inf)]
+
+
+@pytest.mark.parametrize("group,idx,val", NONFINITE)
+def test_nonfinite_gaussian_is_removed(group, idx, val):
+    """A Gaussian with a NaN or infinite parameter is culled in every frame:
+    the images and every other Gaussian's gradients equal those of the scene
+    without it (bitwise), and its own gradients are 0."""
+    sc = scenes.tiny_scene(seed=9, n=60, n_frames=2, sh_degree=3, ls_mean=-2.2)
+    g = 17
+    r0 = oracle.forward(sc)
+    assert r0.records()["keep"][[g, sc.n + g]].all()  # visible in both frames
+    bad = scenes.Scene(*(np.array(getattr(sc, k)) for k in
+                         ("means", "log_scales", "quats", "opacity", "sh")),
+                       sc.sh_degree, sc.cams, sc.poses, sc.background)
+    getattr(bad, group)[(g,) + idx[1:]] = val
+    r = oracle.forward(bad)
+    ref = oracle.forward(_drop(sc, g))
+    assert not r.records()["keep"][[g, sc.n + g]].any()
+    assert np.array_equal(r.rgb_flat, ref.rgb_flat)
+    assert np.array_equal(r.depth_flat, ref.depth_flat)
+    assert np.array_equal(r.alpha_flat, ref.alpha_flat)
+    rng = np.random.default_rng(5)
+    G = (rng.normal(size=3 * r.P), rng.normal(size=r.P), rng.normal(size=r.P))
+    gr, gref = r.backward(*G), ref.backward(*G)
+    for k in ("means", "log_scales", "quats", "opacity", "sh"):
+        assert np.all(gr[k][g] == 0), k
+        assert np.array_equal(np.delete(gr[k], g, axis=0), gref[k]), k
+    np.testing.assert_allclose(gr["twist"], gref["twist"], rtol=1e-12, atol=1e-15)
+
+
 def test_permutation_invariance():
     sc = scenes.tiny_scene(seed=4, n=120, n_frames=2)
     perm = np.random.default_rng(1).permutation(sc.n)

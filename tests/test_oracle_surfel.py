@@ -409,3 +409,45 @@ def test_window_equals_the_whole_image_cropped():
             assert np.array_equal(a[k].numpy()[..., 3:12, 5:18], b[k].numpy()), k
         assert np.array_equal(a["flags"][3:12, 5:18], b["flags"])
         assert np.array_equal(a["box"], b["box"])
+
+
+@pytest.mark.parametrize("group,idx,val", [("means", (1,), np.nan), ("ls", (0,), np.inf),
+                                           ("quats", (2,), -np.inf), ("opac", (), np.nan),
+                                           ("sh", (3, 0), np.nan)])
+def test_nonfinite_surfel_is_removed(group, idx, val):
+    """A surfel with a NaN or infinite parameter is culled in every frame: the
+    maps equal those of the scene without it, and its gradients are 0 while
+    every other surfel's equal the reduced scene's."""
+    sc = _tiny(6, n=14)
+    arrs = dict(means=sc.means.astype(np.float64), ls=sc.log_scales[:, :2].astype(np.float64),
+                quats=sc.quats.astype(np.float64), opac=sc.opacity.astype(np.float64),
+                sh=sc.sh.astype(np.float64))
+    g = 5
+    base = _render(arrs["means"], arrs["ls"], arrs["quats"], arrs["opac"], arrs["sh"], 1,
+                   sc.cams, sc.poses, sc.background)
+    assert all(fr["box"][g, 0] >= 0 for fr in base)  # visible in both frames
+    bad = {k: v.copy() for k, v in arrs.items()}
+    bad[group][(g,) + idx] = val
+    keep = np.arange(sc.n) != g
+    red = {k: v[keep] for k, v in arrs.items()}
+
+    def run(a):
+        ts = {k: torch.tensor(v, requires_grad=True) for k, v in a.items()}
+        out = S.render(ts["means"], ts["ls"], ts["quats"], ts["opac"], ts["sh"], 1, sc.cams,
+                       S.to64(sc.poses), sc.background)
+        rng = np.random.default_rng(1)
+        L = 0.0
+        for fr in out:
+            for k in ("rgb", "depth", "alpha", "normal", "dist"):
+                L = L + (fr[k] * torch.tensor(rng.normal(size=tuple(fr[k].shape)))).sum()
+        L.backward()
+        return out, {k: t.grad.numpy() for k, t in ts.items()}
+    ob, gb = run(bad)
+    orf, gr = run(red)
+    for fa, fb in zip(ob, orf):
+        assert fa["box"][g, 0] == -1
+        for k in ("rgb", "depth", "alpha", "normal", "dist"):
+            assert np.array_equal(fa[k].detach().numpy(), fb[k].detach().numpy()), k
+    for k in gb:
+        assert np.all(gb[k][g] == 0), k
+        np.testing.assert_allclose(np.delete(gb[k], g, axis=0), gr[k], rtol=1e-12, atol=1e-14)

@@ -219,7 +219,10 @@ gsr_status gsr_backward(gsr_context* ctx, const float* g_rgb, const float* g_dep
  * *loss = sum_f [ mean |rgb - target_rgb| + depth_weight * mean over
  * {target_depth > 0} |depth - target_depth| ] (the L1 terms of the paper's
  * rendering loss), and its gradients g_rgb, g_depth, g_alpha (= 0), ready
- * for gsr_backward.  `loss` is a device float. */
+ * for gsr_backward.  `loss` is a device float.  The images are read from
+ * the rgb and depth buffers that last forward wrote, by the pointers it was
+ * given: the caller keeps those buffers allocated and unchanged until this
+ * call has run on the stream. */
 gsr_status gsr_loss_l1(gsr_context* ctx, const float* target_rgb, const float* target_depth,
                        float depth_weight, float* loss, float* g_rgb, float* g_depth,
                        float* g_alpha, void* stream);

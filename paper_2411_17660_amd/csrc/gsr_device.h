@@ -49,8 +49,8 @@ static_assert(sizeof(Record) == 64, "record layout");
 
 // A record's tile rect (trect[r]): tx0 | tx1 << 16, ty0 | ty1 << 16, the tiles
 // of the square clipped to the region where alpha can reach 1/255.  keyoff[r]
-// is the first key slot of record r (written by keygen; all-ones if the
-// record overflowed a fixed key capacity).
+// is the first key slot of record r (written by keygen; all-ones if the record
+// overflowed a fixed key capacity).
 
 // Gradient of one (tile, entry) key: du, dv, dSigma'_xx, dSigma'_xy, dSigma'_yy
 // (symmetric-matrix gradient), dopacity, dc0..2, dz

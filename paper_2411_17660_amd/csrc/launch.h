@@ -35,21 +35,31 @@ void launch_cull_stats(hipStream_t st, uint64_t m, const uint32_t* ntiles, int64
 void launch_size_class(hipStream_t st, uint64_t m, const uint32_t* ntiles, uint32_t* cls,
                        uint32_t* idx);
 
-// sort.hip: depth sort, offsets, key generation, tile sort, ranges
+// sort.hip: depth sort, offsets, tile keys and their sort, ranges.
+// radix_hist_elems / radix_scan_elems: u32 workspace of a sort of up to
+// n_max keys whose widest digit serves `bits` key bits (0: 8-bit digits).
 void launch_fill_u32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t v);
-size_t radix_hist_elems(uint64_t n_max);
+size_t radix_hist_elems(uint64_t n_max, int bits);
 size_t scan_block_elems(uint64_t n_max);
-size_t radix_scan_elems(uint64_t n_max);
+size_t radix_scan_elems(uint64_t n_max, int bits);
 bool launch_radix_sort(hipStream_t st, uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b,
                        uint32_t* vals_b, const uint64_t* n_dev, uint64_t n_max, int bits,
                        uint32_t* hist, uint32_t* scan_tmp);
 void launch_offsets_scan(hipStream_t st, const uint32_t* ntiles, const uint32_t* perm,
                          uint64_t m, uint32_t* cnt_sorted, uint64_t* offsets,
                          uint64_t* block_tmp, uint64_t* total);
+// keys/vals of the min(K, capacity) key slots in depth order (record order,
+// then row-major inside each record's tile rect) and keyoff[r] of every
+// record with a tile (all-ones past the capacity, raising *overflow).
 void launch_keygen(hipStream_t st, uint64_t m, uint64_t n, const uint32_t* perm,
                    const uint32_t* cnt_sorted, const uint64_t* offsets, uint32_t* keyoff,
                    const uint2* trect, const FrameDesc* frames, uint64_t capacity,
                    uint32_t* keys, uint32_t* vals, uint32_t* overflow);
+// Stable sort of min(*k_dev, k_max) tile keys (k_dev NULL: k_max) by the
+// tile-id bits [0, bits); returns true if the result is in (keys_b, vals_b).
+bool launch_tile_sort(hipStream_t st, uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b,
+                      uint32_t* vals_b, const uint64_t* k_dev, uint64_t k_max, int bits,
+                      uint32_t* hist, uint32_t* scan_tmp);
 void launch_ranges(hipStream_t st, const uint32_t* keys, const uint64_t* k_dev, uint64_t k_max,
                    uint64_t capacity, uint2* ranges, uint64_t n_tiles);
 

@@ -65,16 +65,19 @@ __device__ __forceinline__ void gaussian_setup(const float* __restrict__ log_sca
 // A Gaussian takes part only if all its parameters (means, log-scales,
 // quaternion, opacity logit, the SH coefficients of the rendered degree) are
 // finite numbers; otherwise every one of its records is culled and all its
-// gradients are 0.
-__device__ __forceinline__ bool params_finite(const float* __restrict__ means,
-                                              const float* __restrict__ log_scales,
-                                              const float* __restrict__ quats,
-                                              const float* __restrict__ opac,
-                                              const float* __restrict__ sh, int nb3, int64_t g) {
+// gradients are 0.  The 11 geometric values are tested here; the SH
+// coefficients through the FP64 colour sum of a kept record: a finite
+// coefficient times |Y_k| <= 1 cannot overflow FP64, and a NaN or infinite
+// one makes the sum NaN or infinite (0 * inf is NaN), so the sum is finite
+// exactly when every coefficient is.  The colour of a kept record does not
+// depend on the frame's decisions, so the rule culls all frames alike.
+__device__ __forceinline__ bool geometry_finite(const float* __restrict__ means,
+                                                const float* __restrict__ log_scales,
+                                                const float* __restrict__ quats,
+                                                const float* __restrict__ opac, int64_t g) {
   bool ok = isfinite(opac[g]);
   for (int a = 0; a < 3; ++a) ok = ok && isfinite(means[g * 3 + a]) && isfinite(log_scales[g * 3 + a]);
   for (int a = 0; a < 4; ++a) ok = ok && isfinite(quats[g * 4 + a]);
-  for (int i = 0; i < nb3; ++i) ok = ok && isfinite(sh[g * nb3 + i]);
   return ok;
 }
 
@@ -195,7 +198,7 @@ __global__ void __launch_bounds__(256) preprocess_fwd_kernel(
   gaussian_setup(log_scales, quats, opac, g, G);
   const double mu[3] = {means[g * 3 + 0], means[g * 3 + 1], means[g * 3 + 2]};
   constexpr int nb = (DEG + 1) * (DEG + 1);
-  const bool finite = params_finite(means, log_scales, quats, opac, sh, nb * 3, g);
+  const bool finite = geometry_finite(means, log_scales, quats, opac, g);
   for (int f = (int)blockIdx.y; f < n_frames; f += (int)gridDim.y) {
     const int64_t r = (int64_t)f * n + g;
     const FrameDesc fr = frames[f];
@@ -205,7 +208,17 @@ __global__ void __launch_bounds__(256) preprocess_fwd_kernel(
     p.keep = false;
     if (finite) project(fr, W, tf, mu, G, p);
     rec_id[r] = (uint32_t)r;
-    if (!p.keep) {
+    double raw[3] = {0.0, 0.0, 0.0};
+    if (p.keep) {
+      double dir[3];
+      view_dir(W, tf, mu, dir);
+      double Y[16];
+      sh_basis<DEG>(dir[0], dir[1], dir[2], Y);
+      const float* shg = sh + g * nb * 3;
+      for (int k = 0; k < nb; ++k)
+        for (int c = 0; c < 3; ++c) raw[c] += (double)shg[k * 3 + c] * Y[k];
+    }
+    if (!p.keep || !isfinite(raw[0] + raw[1] + raw[2])) {
       depth_key[r] = 0xffffffffu;
       ntiles[r] = 0;
       continue;
@@ -217,14 +230,6 @@ __global__ void __launch_bounds__(256) preprocess_fwd_kernel(
                           (uint32_t)ty0 | ((uint32_t)ty1 << 16));
     const float zf = (float)p.t[2];
     depth_key[r] = __float_as_uint(zf);
-    double dir[3];
-    view_dir(W, tf, mu, dir);
-    double Y[16];
-    sh_basis<DEG>(dir[0], dir[1], dir[2], Y);
-    double raw[3] = {0.0, 0.0, 0.0};
-    const float* shg = sh + g * nb * 3;
-    for (int k = 0; k < nb; ++k)
-      for (int c = 0; c < 3; ++c) raw[c] += (double)shg[k * 3 + c] * Y[k];
     Record o;
     o.u_hi = (float)p.u;
     o.u_lo = (float)(p.u - (double)o.u_hi);
@@ -287,7 +292,7 @@ __global__ void __launch_bounds__(256) slot_reduce_kernel(
   const uint64_t r = active ? order[k] : 0;
   uint32_t cnt = active ? ntiles[r] : 0u;
   const uint32_t off = cnt ? keyoff[r] : 0u;
-  if (cnt && (uint64_t)off + cnt > key_capacity) cnt = 0;  // overflowed in keygen
+  if (cnt && (uint64_t)off + cnt > key_capacity) cnt = 0;  // overflowed the key capacity
   double acc[kNG];
 #pragma unroll
   for (int j = 0; j < kNG; ++j) acc[j] = 0.0;

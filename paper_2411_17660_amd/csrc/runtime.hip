@@ -396,11 +396,13 @@ gsr_status forward_impl(gsr_context* ctx, const gsr_settings* s, int64_t n, cons
   }
   // depth sort of the records (32-bit keys)
   const uint64_t kcap_guess = std::max<uint64_t>(ctx->key_cap, s->key_capacity);
-  const size_t hist_need = std::max(radix_hist_elems(M), radix_hist_elems(std::max<uint64_t>(kcap_guess, 1)));
+  const int tile_bits = bits_for((uint64_t)T + 1);
+  const size_t hist_need = std::max(radix_hist_elems(M, 0),
+                                    radix_hist_elems(std::max<uint64_t>(kcap_guess, 1), tile_bits));
   if ((rc = ensure(ctx, ctx->hist, hist_need * 4, st))) return rc;
   const size_t scan_need =
-      std::max(scan_block_elems(M) * 8,
-               radix_scan_elems(std::max<uint64_t>(M, std::max<uint64_t>(kcap_guess, 1))) * 4);
+      std::max({scan_block_elems(M) * 8, radix_scan_elems(M, 0) * 4,
+                radix_scan_elems(std::max<uint64_t>(kcap_guess, 1), tile_bits) * 4});
   if ((rc = ensure(ctx, ctx->scan_tmp, scan_need, st))) return rc;
   bool recs_in_b = false;
   {
@@ -443,35 +445,28 @@ gsr_status forward_impl(gsr_context* ctx, const gsr_settings* s, int64_t n, cons
     ctx->key_cap = std::min({ctx->keys_a.bytes / 4, ctx->keys_b.bytes / 4, ctx->vals_a.bytes / 4,
                              ctx->vals_b.bytes / 4, ctx->partial.bytes / (kNG * 4),
                              ctx->stamp.bytes / 4});
-    const size_t h2 = radix_hist_elems(ctx->key_cap);
-    if ((rc = ensure(ctx, ctx->hist, h2 * 4, st))) return rc;
-    if ((rc = ensure(ctx, ctx->scan_tmp,
-                     std::max(scan_block_elems(M) * 8,
-                              radix_scan_elems(std::max<uint64_t>(M, ctx->key_cap)) * 4),
-                     st)))
-      return rc;
   }
+  if ((rc = ensure(ctx, ctx->hist, radix_hist_elems(ctx->key_cap, tile_bits) * 4, st))) return rc;
+  if ((rc = ensure(ctx, ctx->scan_tmp, radix_scan_elems(ctx->key_cap, tile_bits) * 4, st)))
+    return rc;
   const uint64_t use_cap = s->key_capacity ? std::min<uint64_t>(cap, ctx->key_cap) : ctx->key_cap;
   // A3 keygen
   {
     StageTimer t(ctx, st, timing, GSR_STAGE_KEYGEN);
     launch_keygen(st, M, (uint64_t)n, perm, P<uint32_t>(ctx->cnt_sorted),
-                  P<uint64_t>(ctx->offsets),
-                  P<uint32_t>(ctx->keyoff), P<uint2>(ctx->trect), P<FrameDesc>(ctx->frames),
-                  use_cap,
-                  P<uint32_t>(ctx->keys_a), P<uint32_t>(ctx->vals_a), d_overflow);
+                  P<uint64_t>(ctx->offsets), P<uint32_t>(ctx->keyoff), P<uint2>(ctx->trect),
+                  P<FrameDesc>(ctx->frames), use_cap, P<uint32_t>(ctx->keys_a),
+                  P<uint32_t>(ctx->vals_a), d_overflow);
   }
   // A4 stable sort by tile id
   const uint64_t sort_n = k_known ? K : use_cap;
   bool keys_in_b = false;
   {
     StageTimer t(ctx, st, timing, GSR_STAGE_TILE_SORT);
-    if (sort_n > 0)
-      keys_in_b = launch_radix_sort(st, P<uint32_t>(ctx->keys_a), P<uint32_t>(ctx->vals_a),
-                                    P<uint32_t>(ctx->keys_b), P<uint32_t>(ctx->vals_b),
-                                    k_known ? nullptr : d_count, sort_n,
-                                    bits_for((uint64_t)T + 1), P<uint32_t>(ctx->hist),
-                                    P<uint32_t>(ctx->scan_tmp));
+    keys_in_b = launch_tile_sort(st, P<uint32_t>(ctx->keys_a), P<uint32_t>(ctx->vals_a),
+                                 P<uint32_t>(ctx->keys_b), P<uint32_t>(ctx->vals_b),
+                                 k_known ? nullptr : d_count, sort_n, tile_bits,
+                                 P<uint32_t>(ctx->hist), P<uint32_t>(ctx->scan_tmp));
   }
   const uint32_t* skeys = P<uint32_t>(keys_in_b ? ctx->keys_b : ctx->keys_a);
   const uint32_t* svals = P<uint32_t>(keys_in_b ? ctx->vals_b : ctx->vals_a);
@@ -603,7 +598,7 @@ gsr_status gsr_backward_surfel(gsr_context* ctx, const float* g_rgb, const float
   const size_t ng = (size_t)surfel_grad_values();
   const uint64_t M = (uint64_t)sv.n * sv.F;
   // slots of this forward's keys only (sv.K: its key count, or the fixed
-  // capacity it ran with); keygen marked records past it as overflowed
+  // capacity it ran with); records past it are marked as overflowed
   const uint64_t kcap = std::min<uint64_t>(sv.K, ctx->key_cap);
   if ((rc = ensure(ctx, ctx->spart, std::max<uint64_t>(kcap, 1) * ng * 4, st))) return rc;
   if ((rc = ensure(ctx, ctx->sgrad, std::max<uint64_t>(M, 1) * ng * 8, st))) return rc;

@@ -8,20 +8,24 @@
 //      N*F elements), which puts each frame's Gaussians front to back with
 //      ties broken by index;
 //   2. keygen walks the records in that order and writes one 32-bit tile id
-//      per covered tile; a stable LSD radix pass over only the tile-id bits
-//      (2 passes for up to 65k tiles) then groups the keys by tile while
-//      keeping the depth order inside each tile.
+//      per covered tile (the "slot" order); a stable LSD radix over only the
+//      tile-id bits (two passes of <= 10 bits up to 2^20 tiles) then groups
+//      the keys by tile while keeping the depth order inside each tile.
 // This moves about 40 bytes per key instead of 6-7 passes over 12-byte
 // (tile | depth, value) pairs.
 //
 // The radix passes use a hand-written LDS multi-split: each wave ranks its
-// 64 keys per round with 8 ballots (one per digit bit), keeps running digit
-// counts in LDS, and the block combines the 4 waves' counts into stable
-// block offsets; no global atomics.  A pass's digit counts are stored one
-// 1 KB row per block, so the histogram writes and the scatter reads them as
-// whole rows, and their scan runs down the columns (3 launches); the other
-// scans are reduce-then-scan in 3 launches.  All kernels read the element
-// count from device memory so the sequence is capturable.
+// 64 keys per round with one ballot per digit bit (lanes with equal digits
+// form one mask), keeps running digit counts in LDS, and the block combines
+// its waves' counts into stable block offsets; no global atomics.  A
+// pass's digit counts are stored one row per block, so the histogram writes
+// and the scatter reads them as whole rows, and their scan runs down the
+// columns (3 launches); the other scans are reduce-then-scan in 3 launches.
+// Scatter blocks are dealt so that consecutive blocks run on one XCD: the
+// partial cache lines at the two ends of a block's digit run are completed by
+// its neighbour in the same L2 instead of leaving as partial writes.  All
+// kernels read the element count from device memory so the sequence is
+// capturable.
 #include "launch.h"
 
 #include <algorithm>
@@ -33,11 +37,10 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;  // elements per block
 
-constexpr int kSortThreads = 256;
-constexpr int kSortWaves = kSortThreads / kWave;
-constexpr int kSortRounds = 16;  // 64-key rounds per wave
-constexpr int kSortTile = kSortThreads * kSortRounds;  // keys per block (4096)
-constexpr int kRadixBins = 256;
+constexpr int kSortRounds = 16;  // 64-key rounds per wave in the radix passes
+constexpr int kMaxDigitBits = 10;
+constexpr int kMaxBins = 1 << kMaxDigitBits;
+constexpr unsigned kXcds = 8;  // XCDs of an MI355X: workgroup b runs on XCD b % 8
 
 // ---------------------------------------------------------------------------
 // Block-wide exclusive scan of one value per thread (256 threads).
@@ -143,71 +146,123 @@ __global__ void __launch_bounds__(kScanThreads) scan_down_kernel(Load ld, const 
 // so the block totals agree.
 
 // ---------------------------------------------------------------------------
-// LSD radix pass, 8-bit digit at `shift`, stable.
+// Stable LSD radix pass over the digit of `width` <= 10 bits at `shift`.
 //
-// A block owns kSortTile consecutive keys.  The scatter sees it as 4 waves x
-// 16 rounds x 64 keys, wave w owning a contiguous quarter.  Per round a wave
-// ranks its 64 keys by digit with 8 ballots (lanes with equal digits form
-// one mask); the lowest lane of each group bumps the wave's LDS counter.  No
-// atomics there, so the ranks are deterministic and the scatter is stable.
+// A block of WAVES waves owns WAVES * 1024 consecutive keys, wave w the
+// contiguous 1024 keys from w * 1024 as 16 rounds of 64.  Each lane loads
+// its 16 keys and values straight into registers (fully unrolled, so all the
+// loads are in flight at once).  Per round a wave ranks its 64 keys by digit
+// with `width` ballots (lanes with equal digits form one mask); the lowest
+// lane of each group bumps the wave's LDS counter.  No atomics there, so the
+// ranks are deterministic and the scatter is stable.  The keys then pass
+// through LDS in digit order so that each digit's run leaves the block as
+// consecutive stores.  BINS (256 or 1024) sizes the LDS counters; the pass
+// uses 2^width of them.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid, int width) {
   uint64_t m = __ballot(valid);
 #pragma unroll
-  for (int b = 0; b < 8; ++b) {
-    const bool bit = (d >> b) & 1u;
-    const uint64_t bb = __ballot(bit);
-    m &= bit ? bb : ~bb;
+  for (int b = 0; b < kMaxDigitBits; ++b) {
+    if (b < width) {  // wave-uniform
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bb = __ballot(bit);
+      m &= bit ? bb : ~bb;
+    }
   }
   return m;
 }
 
-// Digit counts of one block's kSortTile keys.  A count does not depend on
-// the order, so each thread loads four keys with one 16-byte load and bumps
-// its wave's LDS counters with atomics; the four wave histograms are summed.
-__global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(
-    const uint32_t* __restrict__ keys, const uint64_t* n_dev, uint64_t n_host, int shift,
-    uint32_t* __restrict__ hist /* [nblocks][256] */) {
-  __shared__ uint32_t wcnt[kSortWaves][kRadixBins];
-  const uint64_t n = n_dev ? min(*n_dev, n_host) : n_host;
-  const int w = threadIdx.x / kWave;
-  for (int i = threadIdx.x; i < kSortWaves * kRadixBins; i += kSortThreads)
-    (&wcnt[0][0])[i] = 0;
+// The logical block of workgroup `bid` when the grid (kXcds * per
+// workgroups) is dealt so that XCD x (workgroups x, x + kXcds, ...) runs the
+// consecutive logical blocks [x per, (x + 1) per) in order.  Neighbouring
+// blocks write the two ends of each digit run's cache lines; on one XCD they
+// meet in one L2 instead of leaving as partial-line writes.
+__device__ __forceinline__ unsigned xcd_block(unsigned bid, unsigned per) {
+  return (bid % kXcds) * per + bid / kXcds;
+}
+
+// Exclusive scan of one value per thread over a block of blockDim.x threads
+// (a multiple of 64, at most 1024); wsum holds 16 values.
+template <typename T>
+__device__ __forceinline__ T block_scan_excl(T v, T* wsum, T& total) {
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+  T x = v;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const T y = __shfl_up(x, o, kWave);
+    if (lane >= o) x += y;
+  }
+  if (lane == kWave - 1) wsum[w] = x;
   __syncthreads();
-  const uint64_t bbase = (uint64_t)blockIdx.x * kSortTile;
+  T base = 0, tot = 0;
+  for (int k = 0; k < nw; ++k) {
+    const T s = wsum[k];
+    if (k < w) base += s;
+    tot += s;
+  }
+  __syncthreads();
+  total = tot;
+  return base + x - v;
+}
+
+template <int WAVES>
+struct RadixShape {
+  static constexpr int kThreads = WAVES * kWave;
+  static constexpr int kTile = kThreads * kSortRounds;  // keys per block
+};
+
+// Digit counts of one block's keys.  A count does not depend on the order,
+// so each thread loads four keys with one 16-byte load and bumps its wave's
+// LDS counters with atomics; the wave histograms are summed.
+template <int BINS, int WAVES>
+__global__ void __launch_bounds__(256) radix_hist_kernel(
+    const uint32_t* __restrict__ keys, const uint64_t* n_dev, uint64_t n_host, int shift,
+    int width, uint32_t* __restrict__ hist /* [nblocks][2^width] */) {
+  constexpr int kTile = RadixShape<WAVES>::kTile;
+  constexpr int kHW = 256 / kWave;  // waves of this kernel
+  __shared__ uint32_t wcnt[kHW][BINS];
+  const uint64_t n = n_dev ? min(*n_dev, n_host) : n_host;
+  const int bins = 1 << width;
+  const uint32_t mask = (uint32_t)bins - 1u;
+  const int w = threadIdx.x / kWave;
+  for (int i = threadIdx.x; i < kHW * BINS; i += 256) (&wcnt[0][0])[i] = 0;
+  __syncthreads();
+  const uint64_t bbase = (uint64_t)blockIdx.x * kTile;
   uint32_t* cw = wcnt[w];
 #pragma unroll
-  for (int j = 0; j < kSortTile / (4 * kSortThreads); ++j) {
-    const uint64_t i = bbase + 4 * ((uint64_t)threadIdx.x + (uint64_t)j * kSortThreads);
+  for (int j = 0; j < kTile / (4 * 256); ++j) {
+    const uint64_t i = bbase + 4 * ((uint64_t)threadIdx.x + (uint64_t)j * 256);
     if (i + 4 <= n) {
       const uint4 k = *reinterpret_cast<const uint4*>(keys + i);  // i % 4 == 0
-      atomicAdd(&cw[(k.x >> shift) & 0xffu], 1u);
-      atomicAdd(&cw[(k.y >> shift) & 0xffu], 1u);
-      atomicAdd(&cw[(k.z >> shift) & 0xffu], 1u);
-      atomicAdd(&cw[(k.w >> shift) & 0xffu], 1u);
+      atomicAdd(&cw[(k.x >> shift) & mask], 1u);
+      atomicAdd(&cw[(k.y >> shift) & mask], 1u);
+      atomicAdd(&cw[(k.z >> shift) & mask], 1u);
+      atomicAdd(&cw[(k.w >> shift) & mask], 1u);
     } else {
-      for (uint64_t t = i; t < n && t < i + 4; ++t) atomicAdd(&cw[(keys[t] >> shift) & 0xffu], 1u);
+      for (uint64_t t = i; t < n && t < i + 4; ++t) atomicAdd(&cw[(keys[t] >> shift) & mask], 1u);
     }
   }
   __syncthreads();
-  const int d = threadIdx.x;
-  uint32_t c = 0;
-  for (int ww = 0; ww < kSortWaves; ++ww) c += wcnt[ww][d];
-  hist[(uint64_t)blockIdx.x * kRadixBins + d] = c;
+  for (int d = threadIdx.x; d < bins; d += 256) {
+    uint32_t c = 0;
+    for (int ww = 0; ww < kHW; ++ww) c += wcnt[ww][d];
+    hist[(uint64_t)blockIdx.x * bins + d] = c;
+  }
 }
 
 // Exclusive offsets from the block-major counts H[b][d]: the scatter of block
 // b puts its digit-d keys at sum_{d' < d} total(d') + sum_{b' < b} H[b'][d],
 // the exclusive scan of the counts taken in (digit, block) order.  The blocks
 // are cut into chunks of `rows`; one thread per digit walks a chunk's rows,
-// so every access is a whole 1 KB row.  Rows are loaded kColBatch at a time
-// so that a thread's serial walk waits on one load latency per batch.
+// so every access is a whole row.  Rows are loaded kColBatch at a time so
+// that a thread's serial walk waits on one load latency per batch.
 // rows = ceil(sqrt(nb)) balances a chunk's walk against the spine's walk
 // over the chunks; then there are at most ceil(sqrt(nb)) chunks (and at most
-// kColMaxChunks).
+// kColMaxChunks).  The three kernels run max(bins, 64) threads; threads past
+// the digit count only take part in the spine's block scan.
 constexpr unsigned kColMaxChunks = 1024;
 constexpr int kColBatch = 16;
-static_assert(kRadixBins == kScanThreads, "one scan thread per digit");
 
 static inline uint64_t isqrt_ceil(uint64_t x) {
   uint64_t r = (uint64_t)std::sqrt((double)x);
@@ -221,203 +276,291 @@ static inline unsigned col_rows(unsigned nb) {
 }
 
 // csum[c][d] = sum of H[b][d] over the rows b of chunk c
-__global__ void __launch_bounds__(kRadixBins) radix_colsum_kernel(
-    const uint32_t* __restrict__ hist, unsigned nb, unsigned rows, uint32_t* __restrict__ csum) {
+__global__ void __launch_bounds__(kMaxBins) radix_colsum_kernel(
+    const uint32_t* __restrict__ hist, unsigned nb, unsigned rows, int bins,
+    uint32_t* __restrict__ csum) {
   const unsigned d = threadIdx.x;
+  if ((int)d >= bins) return;
   const unsigned b0 = blockIdx.x * rows, b1 = min(nb, b0 + rows);
   uint32_t s = 0;
   for (unsigned b = b0; b < b1; b += kColBatch) {
     uint32_t v[kColBatch];
 #pragma unroll
     for (int j = 0; j < kColBatch; ++j)
-      v[j] = b + j < b1 ? hist[(uint64_t)(b + j) * kRadixBins + d] : 0u;
+      v[j] = b + j < b1 ? hist[(uint64_t)(b + j) * bins + d] : 0u;
 #pragma unroll
     for (int j = 0; j < kColBatch; ++j) s += v[j];
   }
-  csum[(uint64_t)blockIdx.x * kRadixBins + d] = s;
+  csum[(uint64_t)blockIdx.x * bins + d] = s;
 }
 
 // One block: csum[c][d] becomes the exclusive scan over chunks of digit d;
 // row nc receives the exclusive scan of the digit totals.
-__global__ void __launch_bounds__(kRadixBins) radix_colspine_kernel(uint32_t* __restrict__ csum,
-                                                                    unsigned nc) {
-  __shared__ uint32_t sh[kScanThreads];
+__global__ void __launch_bounds__(kMaxBins) radix_colspine_kernel(uint32_t* __restrict__ csum,
+                                                                  unsigned nc, int bins) {
+  __shared__ uint32_t wsum[kMaxBins / kWave];
   const unsigned d = threadIdx.x;
+  const bool own = (int)d < bins;
   uint32_t run = 0;
-  for (unsigned c = 0; c < nc; c += kColBatch) {
-    uint32_t v[kColBatch];
+  if (own) {
+    for (unsigned c = 0; c < nc; c += kColBatch) {
+      uint32_t v[kColBatch];
 #pragma unroll
-    for (int j = 0; j < kColBatch; ++j)
-      v[j] = c + j < nc ? csum[(uint64_t)(c + j) * kRadixBins + d] : 0u;
+      for (int j = 0; j < kColBatch; ++j)
+        v[j] = c + j < nc ? csum[(uint64_t)(c + j) * bins + d] : 0u;
 #pragma unroll
-    for (int j = 0; j < kColBatch; ++j)
-      if (c + j < nc) {
-        csum[(uint64_t)(c + j) * kRadixBins + d] = run;
-        run += v[j];
-      }
+      for (int j = 0; j < kColBatch; ++j)
+        if (c + j < nc) {
+          csum[(uint64_t)(c + j) * bins + d] = run;
+          run += v[j];
+        }
+    }
   }
   uint32_t total;
-  const uint32_t base = block_exclusive_scan<uint32_t>(run, sh, total);
-  csum[(uint64_t)nc * kRadixBins + d] = base;
+  const uint32_t base = block_scan_excl<uint32_t>(run, wsum, total);
+  if (own) csum[(uint64_t)nc * bins + d] = base;
 }
 
 // H[b][d] becomes block b's global start of digit d
-__global__ void __launch_bounds__(kRadixBins) radix_coldown_kernel(
-    uint32_t* __restrict__ hist, unsigned nb, unsigned rows, const uint32_t* __restrict__ csum,
-    unsigned nc) {
+__global__ void __launch_bounds__(kMaxBins) radix_coldown_kernel(
+    uint32_t* __restrict__ hist, unsigned nb, unsigned rows, int bins,
+    const uint32_t* __restrict__ csum, unsigned nc) {
   const unsigned d = threadIdx.x;
+  if ((int)d >= bins) return;
   const unsigned b0 = blockIdx.x * rows, b1 = min(nb, b0 + rows);
-  uint32_t run = csum[(uint64_t)blockIdx.x * kRadixBins + d] + csum[(uint64_t)nc * kRadixBins + d];
+  uint32_t run = csum[(uint64_t)blockIdx.x * bins + d] + csum[(uint64_t)nc * bins + d];
   for (unsigned b = b0; b < b1; b += kColBatch) {
     uint32_t v[kColBatch];
 #pragma unroll
     for (int j = 0; j < kColBatch; ++j)
-      v[j] = b + j < b1 ? hist[(uint64_t)(b + j) * kRadixBins + d] : 0u;
+      v[j] = b + j < b1 ? hist[(uint64_t)(b + j) * bins + d] : 0u;
 #pragma unroll
     for (int j = 0; j < kColBatch; ++j)
       if (b + j < b1) {
-        hist[(uint64_t)(b + j) * kRadixBins + d] = run;
+        hist[(uint64_t)(b + j) * bins + d] = run;
         run += v[j];
       }
   }
 }
 
-__global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
-    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
-    const uint64_t* n_dev, uint64_t n_host, int shift,
-    const uint32_t* __restrict__ offsets /* scanned [nblocks][256] */,
-    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
-  __shared__ uint32_t wcnt[kSortWaves][kRadixBins];  // counts, then wave bases in digit
-  __shared__ uint32_t dstart[kRadixBins];            // block-local start of each digit
-  __shared__ uint32_t gbase[kRadixBins];             // global start of digit for the block
-  __shared__ uint32_t scan_sh[kSortThreads];
-  __shared__ uint32_t sk[kSortTile], sv[kSortTile];  // block keys in local digit order
-  const uint64_t n = n_dev ? min(*n_dev, n_host) : n_host;
+template <int BINS, int WAVES>
+struct ScatterLds {
+  uint32_t wcnt[WAVES][BINS];  // counts, then wave bases in digit
+  uint32_t dstart[BINS];       // block-local start of each digit
+  uint32_t gbase[BINS];        // global start of digit for the block
+  uint32_t wsum[WAVES];
+  uint32_t sk[RadixShape<WAVES>::kTile], sv[RadixShape<WAVES>::kTile];
+};
+
+// Ranks the block's keys (lane's round-k key is block-local index
+// w 1024 + 64 k + lane; L.wcnt zeroed and the zeroing visible to all waves),
+// moves them into digit order through L.sk / L.sv and writes them to
+// gbase[d] + (position inside the block's run of digit d).
+template <int BINS, int WAVES>
+__device__ __forceinline__ void rank_and_scatter(ScatterLds<BINS, WAVES>& L,
+                                                 const uint32_t (&key)[kSortRounds],
+                                                 const uint32_t (&val)[kSortRounds],
+                                                 uint32_t nkeys, int shift, int width,
+                                                 const uint32_t* __restrict__ offs_row,
+                                                 uint32_t* __restrict__ keys_out,
+                                                 uint32_t* __restrict__ vals_out) {
+  constexpr int kThreads = RadixShape<WAVES>::kThreads;
+  constexpr int DPT = (BINS + kThreads - 1) / kThreads;  // digits per thread in the combine
+  const int bins = 1 << width;
+  const uint32_t mask = (uint32_t)bins - 1u;
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
-  for (int i = threadIdx.x; i < kSortWaves * kRadixBins; i += kSortThreads)
-    (&wcnt[0][0])[i] = 0;
-  __syncthreads();
-  const uint64_t bbase = (uint64_t)blockIdx.x * kSortTile;
-  const uint64_t wbase = bbase + (uint64_t)w * (kWave * kSortRounds);
+  const uint32_t wbase = (uint32_t)w * (kWave * kSortRounds);
   const uint64_t lt = lanemask_lt();
-  uint32_t key[kSortRounds], val[kSortRounds], rank[kSortRounds];
+  uint32_t rank[kSortRounds];
+#pragma unroll
   for (int k = 0; k < kSortRounds; ++k) {
-    const uint64_t i = wbase + (uint64_t)k * kWave + lane;
-    const bool valid = i < n;
-    key[k] = valid ? keys_in[i] : 0u;
-    val[k] = valid ? vals_in[i] : 0u;
-    const uint32_t d = (key[k] >> shift) & 0xffu;
-    const uint64_t m = digit_peers(d, valid);
+    const uint32_t i = wbase + (uint32_t)k * kWave + lane;
+    const bool valid = i < nkeys;
+    const uint32_t d = (key[k] >> shift) & mask;
+    const uint64_t m = digit_peers(d, valid, width);
     // LDS ops of one wave complete in issue order: the read precedes the
     // leader's write of the same counter
-    const uint32_t before = wcnt[w][d];
+    const uint32_t before = L.wcnt[w][d];
     rank[k] = before + (uint32_t)__popcll(m & lt);
-    if (valid && (m & lt) == 0) wcnt[w][d] = before + (uint32_t)__popcll(m);
+    if (valid && (m & lt) == 0) L.wcnt[w][d] = before + (uint32_t)__popcll(m);
   }
   __syncthreads();
   {
-    const int d = threadIdx.x;
-    uint32_t run = 0;
-    for (int ww = 0; ww < kSortWaves; ++ww) {
-      const uint32_t c = wcnt[ww][d];
-      wcnt[ww][d] = run;
-      run += c;
+    // thread t owns digits [t DPT, t DPT + DPT): wave bases per digit, then
+    // the block-local digit starts by a scan over the threads
+    uint32_t tot[DPT];
+    uint32_t mine = 0;
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+      const int d = threadIdx.x * DPT + j;
+      uint32_t run = 0;
+      if (d < bins) {
+        for (int ww = 0; ww < WAVES; ++ww) {
+          const uint32_t c = L.wcnt[ww][d];
+          L.wcnt[ww][d] = run;
+          run += c;
+        }
+      }
+      tot[j] = run;
+      mine += run;
     }
     uint32_t total;
-    dstart[d] = block_exclusive_scan<uint32_t>(run, scan_sh, total);
-    gbase[d] = offsets[(uint64_t)blockIdx.x * kRadixBins + d];
+    uint32_t base = block_scan_excl<uint32_t>(mine, L.wsum, total);
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+      const int d = threadIdx.x * DPT + j;
+      if (d < bins) {
+        L.dstart[d] = base;
+        L.gbase[d] = offs_row[d];
+      }
+      base += tot[j];
+    }
   }
-  __syncthreads();
+  __syncthreads();  // (also: every wave is done with whatever L.sk held)
+#pragma unroll
   for (int k = 0; k < kSortRounds; ++k) {
-    const uint64_t i = wbase + (uint64_t)k * kWave + lane;
-    if (i < n) {
-      const uint32_t d = (key[k] >> shift) & 0xffu;
-      const uint32_t lp = dstart[d] + wcnt[w][d] + rank[k];
-      sk[lp] = key[k];
-      sv[lp] = val[k];
+    const uint32_t i = wbase + (uint32_t)k * kWave + lane;
+    if (i < nkeys) {
+      const uint32_t d = (key[k] >> shift) & mask;
+      const uint32_t lp = L.dstart[d] + L.wcnt[w][d] + rank[k];
+      L.sk[lp] = key[k];
+      L.sv[lp] = val[k];
     }
   }
   __syncthreads();
-  const uint32_t nb = (uint32_t)(n > bbase ? min((uint64_t)kSortTile, n - bbase) : 0);
-  for (uint32_t idx = threadIdx.x; idx < nb; idx += kSortThreads) {
-    const uint32_t kk = sk[idx];
-    const uint32_t d = (kk >> shift) & 0xffu;
-    const uint32_t dst = gbase[d] + (idx - dstart[d]);
+  for (uint32_t idx = threadIdx.x; idx < nkeys; idx += kThreads) {
+    const uint32_t kk = L.sk[idx];
+    const uint32_t d = (kk >> shift) & mask;
+    const uint32_t dst = L.gbase[d] + (idx - L.dstart[d]);
     keys_out[dst] = kk;
-    vals_out[dst] = sv[idx];
+    vals_out[dst] = L.sv[idx];
   }
 }
 
+template <int BINS, int WAVES>
+__global__ void __launch_bounds__(WAVES * kWave) radix_scatter_kernel(
+    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
+    const uint64_t* n_dev, uint64_t n_host, int shift, int width, unsigned nb, unsigned per,
+    const uint32_t* __restrict__ offsets /* scanned [nblocks][2^width] */,
+    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
+  constexpr int kThreads = RadixShape<WAVES>::kThreads;
+  constexpr int kTile = RadixShape<WAVES>::kTile;
+  __shared__ ScatterLds<BINS, WAVES> L;
+  const unsigned b = xcd_block(blockIdx.x, per);
+  if (b >= nb) return;  // padding workgroup: before any barrier
+  const uint64_t n = n_dev ? min(*n_dev, n_host) : n_host;
+  const uint64_t bbase = (uint64_t)b * kTile;
+  const uint32_t nkeys = (uint32_t)(n > bbase ? min((uint64_t)kTile, n - bbase) : 0);
+  for (int i = threadIdx.x; i < WAVES * BINS; i += kThreads) (&L.wcnt[0][0])[i] = 0;
+  const int lane = threadIdx.x & (kWave - 1);
+  const uint32_t wbase = (uint32_t)(threadIdx.x / kWave) * (kWave * kSortRounds);
+  uint32_t key[kSortRounds], val[kSortRounds];
+#pragma unroll
+  for (int k = 0; k < kSortRounds; ++k) {
+    const uint32_t i = wbase + (uint32_t)k * kWave + lane;
+    key[k] = i < nkeys ? keys_in[bbase + i] : 0u;
+    val[k] = i < nkeys ? vals_in[bbase + i] : 0u;
+  }
+  __syncthreads();
+  rank_and_scatter<BINS, WAVES>(L, key, val, nkeys, shift, width,
+                                offsets + (uint64_t)b * (1u << width), keys_out, vals_out);
+}
+
+// q = floor(a / b), r = a - q b for b >= 1: a float estimate corrected by
+// one step each way (exact while a < 2^21, where the estimate is off by at
+// most one), else the integer division.
+__device__ __forceinline__ uint32_t div_rem(uint32_t a, uint32_t b, uint32_t& r) {
+  if (a >= (1u << 21)) {
+    const uint32_t q = a / b;
+    r = a - q * b;
+    return q;
+  }
+  uint32_t q = (uint32_t)((float)a * __builtin_amdgcn_rcpf((float)b));
+  int32_t rr = (int32_t)(a - q * b);
+  if (rr < 0) {
+    --q;
+    rr += (int32_t)b;
+  } else if (rr >= (int32_t)b) {
+    ++q;
+    rr -= (int32_t)b;
+  }
+  r = (uint32_t)rr;
+  return q;
+}
+
 // ---------------------------------------------------------------------------
-// keygen: a wave owns 64 consecutive depth-sorted records; their key slots
-// form one contiguous range, which the lanes write cooperatively (slot o by
-// lane o % 64) after locating the owning record with a 6-step search in LDS,
-// so every store instruction writes 64 consecutive keys.
+// keygen: key slot o (0 <= o < K) belongs to the depth-ordered record i with
+// offsets[i] <= o < offsets[i] + cnt[i]; its key is the global id of the
+// (o - offsets[i])-th tile of the record's tile rect, row by row, and its
+// value the record id perm[i].  A wave owns 64 consecutive depth-ordered
+// records; their slots form one contiguous range, which the lanes write
+// cooperatively (slot o by lane o % 64, every store instruction 64
+// consecutive keys) after locating the owning record with a 6-step search in
+// LDS.  A record whose slots pass the key capacity gets the all-ones
+// sentinel key (past every tile) on its slots below the capacity.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) keygen_kernel(
     uint64_t m, uint64_t n, const uint32_t* __restrict__ perm,
     const uint32_t* __restrict__ cnt_sorted, const uint64_t* __restrict__ offsets,
     uint32_t* __restrict__ keyoff, const uint2* __restrict__ trect,
-    const FrameDesc* __restrict__ frames, uint64_t capacity,
-    uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, uint32_t* __restrict__ overflow) {
-  __shared__ uint64_t s_off[4][kWave];
-  __shared__ uint32_t s_r[4][kWave], s_w[4][kWave], s_gx[4][kWave], s_base[4][kWave];
-  __shared__ uint8_t s_ovf[4][kWave];
+    const FrameDesc* __restrict__ frames, uint64_t capacity, uint32_t* __restrict__ keys,
+    uint32_t* __restrict__ vals, uint32_t* __restrict__ overflow) {
+  // per record: first slot relative to the wave's first (all-ones for a
+  // record without slots in the range), and (first tile id or sentinel, rect
+  // width | grid width << 16, value)
+  __shared__ uint32_t s_rel[4][kWave];
+  __shared__ uint4 s_rec[4][kWave];
   const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const uint64_t i0 = ((uint64_t)blockIdx.x * 4 + w) * kWave;
   const uint64_t i = i0 + lane;
   uint32_t cnt = 0;
   uint64_t off = 0;
   if (i < m) {
-    const uint32_t r = perm[i];
     cnt = cnt_sorted[i];
     off = offsets[i];
-    s_r[w][lane] = r;
     if (cnt) {
+      const uint32_t r = perm[i];
       const FrameDesc fr = frames[r / n];
       const uint2 tr = trect[r];
-      const int tx0 = tr.x & 0xffff, tx1 = tr.x >> 16;
-      const int ty0 = tr.y & 0xffff;
-      s_w[w][lane] = (uint32_t)(tx1 - tx0 + 1);
-      s_gx[w][lane] = (uint32_t)fr.grid_x;
-      s_base[w][lane] = (uint32_t)(fr.tile_offset + ty0 * fr.grid_x + tx0);
+      const uint32_t tx0 = tr.x & 0xffffu, tx1 = tr.x >> 16, ty0 = tr.y & 0xffffu;
       const bool ovf = off + cnt > capacity;
-      s_ovf[w][lane] = ovf ? 1 : 0;
       keyoff[r] = ovf ? 0xffffffffu : (uint32_t)off;
       if (ovf) atomicOr(overflow, 1u);
+      s_rec[w][lane] =
+          make_uint4(ovf ? 0xffffffffu : (uint32_t)fr.tile_offset + ty0 * (uint32_t)fr.grid_x + tx0,
+                     (tx1 - tx0 + 1u) | ((uint32_t)fr.grid_x << 16), ovf ? 0u : r, 0u);
     }
   }
-  s_off[w][lane] = i < m ? off : ~0ull;
-  __syncthreads();  // every wave reaches the barrier; empty waves leave after it
-  if (i0 >= m) return;
-  // contiguous slot range of the wave's records
-  const uint64_t lo = s_off[w][0];
-  uint64_t hi = off + cnt;
+  // contiguous slot range [lo, hi) of the wave's records
+  const uint64_t lo = __shfl(off, 0, kWave);
+  uint64_t hi = i < m ? off + cnt : 0;
   for (int o = 32; o > 0; o >>= 1) {
-    const uint64_t h2 = __shfl_xor(hi, o, 64);
+    const uint64_t h2 = __shfl_xor(hi, o, kWave);
     hi = h2 > hi ? h2 : hi;
   }
   if (hi > capacity) hi = capacity;
-  for (uint64_t o = lo + lane; o < hi; o += kWave) {
-    // owner: the last record with s_off <= o
+  // records with a slot in the range have first slots below hi; the others
+  // (culled, or past the capacity) never own a slot
+  s_rel[w][lane] = (i < m && cnt && off < hi) ? (uint32_t)(off - lo) : 0xffffffffu;
+  __syncthreads();  // every wave reaches the barrier; empty waves leave after it
+  if (i0 >= m || hi <= lo) return;
+  const uint32_t span = (uint32_t)(hi - lo);  // < 2^32: slots are 32-bit
+  for (uint32_t o = lane; o < span; o += kWave) {
+    // owner: the last record whose first slot is <= o
     int j = 0;
 #pragma unroll
     for (int step = 32; step > 0; step >>= 1)
-      if (s_off[w][j + step] <= o) j += step;
-    uint32_t key, val;
-    if (s_ovf[w][j]) {
-      key = 0xffffffffu;  // sentinel past every real tile
-      val = 0u;
-    } else {
-      const uint32_t local = (uint32_t)(o - s_off[w][j]);
-      const uint32_t wdt = s_w[w][j];
-      const uint32_t row = local / wdt;
-      key = s_base[w][j] + row * s_gx[w][j] + (local - row * wdt);
-      val = s_r[w][j];
+      if (s_rel[w][j + step] <= o) j += step;
+    const uint4 R = s_rec[w][j];
+    uint32_t key = 0xffffffffu;
+    if (R.x != 0xffffffffu) {
+      uint32_t col;
+      const uint32_t row = div_rem(o - s_rel[w][j], R.y & 0xffffu, col);
+      key = R.x + row * (R.y >> 16) + col;
     }
-    keys[o] = key;
-    vals[o] = val;
+    keys[lo + o] = key;
+    vals[lo + o] = R.z;
   }
 }
 
@@ -477,42 +620,123 @@ void launch_fill_u32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t v) {
   hipLaunchKernelGGL(fill_u32_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n, v);
 }
 
-size_t radix_hist_elems(uint64_t n_max) { return (size_t)kRadixBins * blocks_for(n_max, kSortTile); }
+// Digit widths of the tile passes: ceil(bits / kMaxDigitBits) passes of
+// near-equal width, the narrower ones first (fewer digits make longer runs
+// per block).
+static int tile_pass_widths(int bits, int* widths) {
+  const int passes = std::max(1, (bits + kMaxDigitBits - 1) / kMaxDigitBits);
+  const int base = bits / passes, extra = bits % passes;
+  for (int p = 0; p < passes; ++p) widths[p] = base + (p >= passes - extra ? 1 : 0);
+  return passes;
+}
+
+static int max_digit_width(int bits) {
+  int w[8];
+  const int passes = tile_pass_widths(bits, w);
+  int mx = 1;
+  for (int p = 0; p < passes; ++p) mx = std::max(mx, w[p]);
+  return mx;
+}
+
+// Workspace bounds use the smallest block (4 waves, 4096 keys).
+size_t radix_hist_elems(uint64_t n_max, int bits) {
+  const int wmax = bits > 0 ? max_digit_width(bits) : 8;
+  return ((size_t)1 << std::max(wmax, 8)) * blocks_for(n_max, RadixShape<4>::kTile);
+}
 size_t scan_block_elems(uint64_t n_max) { return blocks_for(n_max, kScanTile) + 1; }
 // u32 elements of the column scan's chunk sums for up to n_max keys (an upper
 // bound for every smaller count as well)
-size_t radix_scan_elems(uint64_t n_max) {
-  const uint64_t nb = blocks_for(n_max, kSortTile);
+size_t radix_scan_elems(uint64_t n_max, int bits) {
+  const int wmax = bits > 0 ? max_digit_width(bits) : 8;
+  const uint64_t nb = blocks_for(n_max, RadixShape<4>::kTile);
   const uint64_t nc = std::min<uint64_t>(isqrt_ceil(nb), kColMaxChunks);
-  return (size_t)(nc + 1) * kRadixBins;
+  return (size_t)(nc + 1) << std::max(wmax, 8);
 }
 
-// Stable sort of (keys, vals) by the key bits [0, bits).  The element count
-// is *n_dev (<= n_max).  Result ends in (keys_a, vals_a) if the number of
-// passes is even, else in (keys_b, vals_b); returns true if in b.
+// Column scan of the block-major digit counts into per-block digit starts.
+static void radix_offsets(hipStream_t st, uint32_t* hist, unsigned nb, int width,
+                          uint32_t* scan_tmp) {
+  const int bins = 1 << width;
+  const unsigned rows = col_rows(nb);
+  const unsigned nc = (nb + rows - 1) / rows;
+  const unsigned thr = (unsigned)std::max(bins, kWave);
+  hipLaunchKernelGGL(radix_colsum_kernel, dim3(nc), dim3(thr), 0, st, hist, nb, rows, bins,
+                     scan_tmp);
+  hipLaunchKernelGGL(radix_colspine_kernel, dim3(1), dim3(thr), 0, st, scan_tmp, nc, bins);
+  hipLaunchKernelGGL(radix_coldown_kernel, dim3(nc), dim3(thr), 0, st, hist, nb, rows, bins,
+                     scan_tmp, nc);
+}
+
+template <int BINS, int WAVES>
+static void radix_pass(hipStream_t st, const uint32_t* ki, const uint32_t* vi, uint32_t* ko,
+                       uint32_t* vo, const uint64_t* n_dev, uint64_t n_max, int shift, int width,
+                       uint32_t* hist, uint32_t* scan_tmp) {
+  const unsigned nb = blocks_for(n_max, RadixShape<WAVES>::kTile);
+  const unsigned per = (nb + kXcds - 1) / kXcds;
+  hipLaunchKernelGGL((radix_hist_kernel<BINS, WAVES>), dim3(nb), dim3(256), 0, st, ki, n_dev,
+                     n_max, shift, width, hist);
+  radix_offsets(st, hist, nb, width, scan_tmp);
+  hipLaunchKernelGGL((radix_scatter_kernel<BINS, WAVES>), dim3(per * kXcds),
+                     dim3(RadixShape<WAVES>::kThreads), 0, st, ki, vi, n_dev, n_max, shift,
+                     width, nb, per, hist, ko, vo);
+}
+
+// Large passes take 8-wave blocks (longer digit runs per block); small ones
+// and 10-bit digits (LDS) take 4-wave blocks.
+constexpr uint64_t kBigPass = 1ull << 24;
+
+static void radix_pass_any(hipStream_t st, const uint32_t* ki, const uint32_t* vi, uint32_t* ko,
+                           uint32_t* vo, const uint64_t* n_dev, uint64_t n_max, int shift,
+                           int width, uint32_t* hist, uint32_t* scan_tmp) {
+  if (width > 8)
+    radix_pass<kMaxBins, 4>(st, ki, vi, ko, vo, n_dev, n_max, shift, width, hist, scan_tmp);
+  else if (n_max >= kBigPass)
+    radix_pass<256, 8>(st, ki, vi, ko, vo, n_dev, n_max, shift, width, hist, scan_tmp);
+  else
+    radix_pass<256, 4>(st, ki, vi, ko, vo, n_dev, n_max, shift, width, hist, scan_tmp);
+}
+
+// Stable sort of (keys, vals) by the key bits [0, bits), 8-bit digits.  The
+// element count is *n_dev (<= n_max).  Result ends in (keys_a, vals_a) if the
+// number of passes is even, else in (keys_b, vals_b); returns true if in b.
 bool launch_radix_sort(hipStream_t st, uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b,
                        uint32_t* vals_b, const uint64_t* n_dev, uint64_t n_max, int bits,
                        uint32_t* hist, uint32_t* scan_tmp) {
   if (n_max == 0) return false;
-  const unsigned nb = blocks_for(n_max, kSortTile);
-  const unsigned rows = col_rows(nb);
-  const unsigned nc = (nb + rows - 1) / rows;
   bool in_b = false;
   for (int shift = 0; shift < bits; shift += 8) {
-    uint32_t* ki = in_b ? keys_b : keys_a;
-    uint32_t* vi = in_b ? vals_b : vals_a;
-    uint32_t* ko = in_b ? keys_a : keys_b;
-    uint32_t* vo = in_b ? vals_a : vals_b;
-    hipLaunchKernelGGL(radix_hist_kernel, dim3(nb), dim3(kSortThreads), 0, st, ki, n_dev, n_max,
-                       shift, hist);
-    hipLaunchKernelGGL(radix_colsum_kernel, dim3(nc), dim3(kRadixBins), 0, st, hist, nb, rows,
-                       scan_tmp);
-    hipLaunchKernelGGL(radix_colspine_kernel, dim3(1), dim3(kRadixBins), 0, st, scan_tmp, nc);
-    hipLaunchKernelGGL(radix_coldown_kernel, dim3(nc), dim3(kRadixBins), 0, st, hist, nb, rows,
-                       scan_tmp, nc);
-    hipLaunchKernelGGL(radix_scatter_kernel, dim3(nb), dim3(kSortThreads), 0, st, ki, vi, n_dev,
-                       n_max, shift, hist, ko, vo);
+    const int width = std::min(8, bits - shift);
+    radix_pass_any(st, in_b ? keys_b : keys_a, in_b ? vals_b : vals_a, in_b ? keys_a : keys_b,
+                   in_b ? vals_a : vals_b, n_dev, n_max, shift, width, hist, scan_tmp);
     in_b = !in_b;
+  }
+  return in_b;
+}
+
+void launch_keygen(hipStream_t st, uint64_t m, uint64_t n, const uint32_t* perm,
+                   const uint32_t* cnt_sorted, const uint64_t* offsets, uint32_t* keyoff,
+                   const uint2* trect, const FrameDesc* frames, uint64_t capacity,
+                   uint32_t* keys, uint32_t* vals, uint32_t* overflow) {
+  if (m == 0) return;
+  hipLaunchKernelGGL(keygen_kernel, dim3(blocks_for(m, 256)), dim3(256), 0, st, m, n, perm,
+                     cnt_sorted, offsets, keyoff, trect, frames, capacity, keys, vals, overflow);
+}
+
+// Stable sort of the tile keys by the tile-id bits [0, bits) in passes of
+// near-equal width; returns true if the result is in (keys_b, vals_b).
+bool launch_tile_sort(hipStream_t st, uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b,
+                      uint32_t* vals_b, const uint64_t* k_dev, uint64_t k_max, int bits,
+                      uint32_t* hist, uint32_t* scan_tmp) {
+  if (k_max == 0) return false;
+  int widths[8];
+  const int passes = tile_pass_widths(bits, widths);
+  bool in_b = false;
+  int shift = 0;
+  for (int p = 0; p < passes; ++p) {
+    radix_pass_any(st, in_b ? keys_b : keys_a, in_b ? vals_b : vals_a, in_b ? keys_a : keys_b,
+                   in_b ? vals_a : vals_b, k_dev, k_max, shift, widths[p], hist, scan_tmp);
+    in_b = !in_b;
+    shift += widths[p];
   }
   return in_b;
 }
@@ -548,15 +772,6 @@ void launch_offsets_scan(hipStream_t st, const uint32_t* ntiles, const uint32_t*
                      ld, (const uint64_t*)nullptr, m, block_tmp, offsets);
 }
 
-void launch_keygen(hipStream_t st, uint64_t m, uint64_t n, const uint32_t* perm,
-                   const uint32_t* cnt_sorted, const uint64_t* offsets, uint32_t* keyoff,
-                   const uint2* trect, const FrameDesc* frames, uint64_t capacity,
-                   uint32_t* keys, uint32_t* vals, uint32_t* overflow) {
-  if (m == 0) return;
-  hipLaunchKernelGGL(keygen_kernel, dim3(blocks_for(m, 256)), dim3(256), 0, st, m, n, perm,
-                     cnt_sorted, offsets, keyoff, trect, frames, capacity, keys, vals, overflow);
-}
-
 void launch_ranges(hipStream_t st, const uint32_t* keys, const uint64_t* k_dev, uint64_t k_max,
                    uint64_t capacity, uint2* ranges, uint64_t n_tiles) {
   launch_fill_u32(st, (uint32_t*)ranges, 2 * n_tiles, 0u);
@@ -566,3 +781,4 @@ void launch_ranges(hipStream_t st, const uint32_t* keys, const uint64_t* k_dev, 
 }
 
 }  // namespace gsr
+

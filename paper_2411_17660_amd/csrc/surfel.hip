@@ -74,11 +74,13 @@ __global__ void __launch_bounds__(256) surfel_preprocess_kernel(
   const double mu[3] = {means[3 * g], means[3 * g + 1], means[3 * g + 2]};
   constexpr int nb = (DEG + 1) * (DEG + 1);
   const double amin = (double)kAlphaMin;
-  // a surfel with a non-finite parameter is culled in every frame
+  // a surfel with a non-finite parameter is culled in every frame: the 9
+  // geometric values here, the SH coefficients through the FP64 colour sum of
+  // a kept record (finite exactly when every coefficient is, as for the 3D
+  // Gaussians)
   bool finite = isfinite(opac[g]) && isfinite(log_scales[2 * g]) && isfinite(log_scales[2 * g + 1]);
   for (int a = 0; a < 3; ++a) finite = finite && isfinite(means[3 * g + a]);
   for (int a = 0; a < 4; ++a) finite = finite && isfinite(quats[4 * g + a]);
-  for (int i = 0; i < nb * 3; ++i) finite = finite && isfinite(sh[g * nb * 3 + i]);
   for (int f = (int)blockIdx.y; f < n_frames; f += (int)gridDim.y) {
     const int64_t r = (int64_t)f * n + g;
     const FrameDesc fr = frames[f];
@@ -132,13 +134,6 @@ __global__ void __launch_bounds__(256) surfel_preprocess_kernel(
     const int x_hi = xh < (double)(fr.width - 1) ? (int)xh : fr.width - 1;
     const int y_hi = yh < (double)(fr.height - 1) ? (int)yh : fr.height - 1;
     if (!(x_lo <= x_hi && y_lo <= y_hi)) continue;
-    const int tx0 = x_lo / tile_w, tx1 = x_hi / tile_w;
-    const int ty0 = y_lo / tile_h, ty1 = y_hi / tile_h;
-    ntiles[r] = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
-    trect[r] = make_uint2((uint32_t)tx0 | ((uint32_t)tx1 << 16),
-                          (uint32_t)ty0 | ((uint32_t)ty1 << 16));
-    const float zf = (float)mc[2];
-    depth_key[r] = __float_as_uint(zf);
     double dir[3];
     view_dir(W, tf, mu, dir);
     double Y[16];
@@ -147,6 +142,14 @@ __global__ void __launch_bounds__(256) surfel_preprocess_kernel(
     const float* shg = sh + g * nb * 3;
     for (int k = 0; k < nb; ++k)
       for (int c = 0; c < 3; ++c) raw[c] += (double)shg[k * 3 + c] * Y[k];
+    if (!isfinite(raw[0] + raw[1] + raw[2])) continue;
+    const int tx0 = x_lo / tile_w, tx1 = x_hi / tile_w;
+    const int ty0 = y_lo / tile_h, ty1 = y_hi / tile_h;
+    ntiles[r] = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+    trect[r] = make_uint2((uint32_t)tx0 | ((uint32_t)tx1 << 16),
+                          (uint32_t)ty0 | ((uint32_t)ty1 << 16));
+    const float zf = (float)mc[2];
+    depth_key[r] = __float_as_uint(zf);
     // normal turned to face the camera
     const double tw[3] = {T[2], T[5], T[8]};
     const double sgn = (tw[0] * mc[0] + tw[1] * mc[1] + tw[2] * mc[2]) < 0.0 ? 1.0 : -1.0;
@@ -601,7 +604,7 @@ __global__ void __launch_bounds__(256) surfel_slot_reduce_kernel(
   const uint64_t r = active ? order[k] : 0;
   uint32_t cnt = active ? ntiles[r] : 0u;
   const uint32_t off = cnt ? keyoff[r] : 0u;
-  if (cnt && (uint64_t)off + cnt > key_capacity) cnt = 0;  // overflowed in keygen
+  if (cnt && (uint64_t)off + cnt > key_capacity) cnt = 0;  // overflowed the key capacity
   double acc[kSG];
 #pragma unroll
   for (int j = 0; j < kSG; ++j) acc[j] = 0.0;
@@ -673,7 +676,7 @@ __global__ void __launch_bounds__(256) surfel_preprocess_bwd_kernel(
     uint32_t cnt = active ? ntiles[r] : 0u;
     kept = kept || cnt > 0;
     const uint32_t off = cnt ? keyoff[r] : 0u;
-    if (cnt && (uint64_t)off + cnt > key_capacity) cnt = 0;  // overflowed in keygen
+    if (cnt && (uint64_t)off + cnt > key_capacity) cnt = 0;  // overflowed the key capacity
     if (cnt > 0) {
       double K[kSG];
       for (int i = 0; i < kSG; ++i) K[i] = sgrad[r * kSG + i];

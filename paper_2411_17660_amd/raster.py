@@ -83,6 +83,8 @@ class Rasterizer:
                                          _ptr(alpha), _stream()))
         self.n, self.F, self.sh_degree = n, F, sh_degree
         self.sizes = [(int(c[0]), int(c[1])) for c in cams]
+        # gsr_loss_l1 reads these buffers by pointer: keep them alive
+        self._fwd_out = (rgb, depth, alpha)
         return rgb, depth, alpha
 
     def forward_surfel(self, means, log_scales, quats, opacity, sh, poses, cams, sh_degree,
@@ -108,6 +110,7 @@ class Rasterizer:
             _ptr(alpha), _ptr(normal), _ptr(dist), _stream()))
         self.n, self.F, self.sh_degree = n, len(cams), sh_degree
         self.sizes = [(int(c[0]), int(c[1])) for c in cams]
+        self._fwd_out = out
         return rgb, depth, alpha, normal, dist
 
     def normal_consistency(self, cams, depth, alpha, normal, weight, g_depth, g_alpha,
@@ -204,6 +207,7 @@ class Rasterizer:
             _ptr(b["sh"]), _ptr(b["twist"]), _stream()))
         self.n, self.F, self.sh_degree = n, len(cams), sh_degree
         self.sizes = [(int(c[0]), int(c[1])) for c in cams]
+        self._fwd_out = (b["rgb"], b["depth"], b["alpha"])
 
     def densify_stats(self, grad_accum, count):
         """Adds the last backward's |dL/d(u, v)| per kept (Gaussian, frame)
@@ -243,6 +247,7 @@ class Rasterizer:
             _ptr(b["quats"]), _ptr(b["opacity"]), _ptr(b["sh"]), _ptr(b["twist"]), _stream()))
         self.n, self.F, self.sh_degree = n, len(cams), sh_degree
         self.sizes = [(int(c[0]), int(c[1])) for c in cams]
+        self._fwd_out = (b["rgb"], b["depth"], b["alpha"])
 
     def autotune(self, means, log_scales, quats, opacity, sh, poses, cams, sh_degree,
                  target_rgb, target_depth, depth_weight, background=(0.0, 0.0, 0.0), reps=3,

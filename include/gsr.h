@@ -227,6 +227,21 @@ gsr_status gsr_loss_l1(gsr_context* ctx, const float* target_rgb, const float* t
                        float depth_weight, float* loss, float* g_rgb, float* g_depth,
                        float* g_alpha, void* stream);
 
+/* gsr_loss_l1 for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, results and error behaviour, but it allocates nothing.
+ * Its per-block partial sums and per-frame scale factors live in a static
+ * device array of 1 MiB (one copy per GPU, resolved by gsr_create and held
+ * until the process ends), which limits it to F * ceil(max W*H / 2048) * 24
+ * + 8 F <= 1 MiB bytes (e.g. 43 frames of 1920x1080); a larger last forward
+ * returns GSR_ERR_UNSUPPORTED without launching anything.  All calls on one
+ * GPU share that array: calls that overlap on one GPU (any streams or
+ * contexts) race; run them in sequence.  Every scratch value a call reads is
+ * written by that call first. */
+gsr_status gsr_loss_l1_noalloc(gsr_context* ctx, const float* target_rgb,
+                               const float* target_depth, float depth_weight, float* loss,
+                               float* g_rgb, float* g_depth, float* g_alpha, void* stream);
+
 /* One mapping step: gsr_forward, gsr_loss_l1 and gsr_backward in sequence,
  * with the upstream gradients held in the context. */
 gsr_status gsr_step_l1(gsr_context* ctx, const gsr_settings* settings, int64_t n,

@@ -90,6 +90,10 @@ void launch_composite_bwd(hipStream_t st, int tw, int th, int n_tiles, int F,
 
 // loss.hip
 int loss_blocks_x(int64_t max_hw);
+// The static scratch of the allocation-free L1 loss: its device address on
+// `device` (the current device; resolved once, then cached) and its size.
+hipError_t loss_scratch_init(int device, void** out);
+size_t loss_scratch_bytes();
 void launch_loss_l1(hipStream_t st, int F, int blocks_x, const FrameDesc* frames,
                     const float* rgb, const float* depth, const float* t_rgb,
                     const float* t_depth, float depth_weight, double* part, float* scale,

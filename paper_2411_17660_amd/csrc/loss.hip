@@ -12,7 +12,40 @@
 // images then writes the gradients and the loss partials together.
 #include "launch.h"
 
+#include <mutex>
+
 namespace gsr {
+
+// Fixed scratch of the allocation-free L1 loss (gsr_loss_l1_noalloc): the
+// per-block partial sums and the per-frame scale factors of launch_loss_l1,
+// in a static device array (one copy per GPU, held until the process ends)
+// instead of context workspace.  Every byte a call reads was written by that
+// call's own kernels first, so nothing needs clearing between calls; calls
+// that overlap on one GPU share the array and race.
+constexpr size_t kLossScratchBytes = size_t(1) << 20;
+static __device__ __align__(256) unsigned char scratch[kLossScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];
+
+// Resolves the device address of `scratch` on `device` (which must be the
+// current device) once and caches it; later calls return the cached address.
+hipError_t loss_scratch_init(int device, void** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
+
+size_t loss_scratch_bytes() { return kLossScratchBytes; }
 
 constexpr int kLossThreads = 256;
 constexpr int kLossItems = 8;

@@ -74,6 +74,7 @@ struct gsr_context {
   int h_frames_cap = 0;
   uint64_t* h_count = nullptr;
   hipEvent_t frames_ev = nullptr;
+  void* loss_scratch = nullptr;     // this device's static scratch of gsr_loss_l1_noalloc
   std::vector<FrameDesc> last_frames;
   uint32_t epoch = 0;
   Saved s;
@@ -260,7 +261,8 @@ gsr_status gsr_create(gsr_context** out, int32_t device) {
   gsr_context* ctx = new (std::nothrow) gsr_context();
   if (!ctx) return GSR_ERR_OUT_OF_MEMORY;
   ctx->device = device;
-  if (hipEventCreateWithFlags(&ctx->frames_ev, hipEventDisableTiming) != hipSuccess ||
+  if (loss_scratch_init(device, &ctx->loss_scratch) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->frames_ev, hipEventDisableTiming) != hipSuccess ||
       hipHostMalloc((void**)&ctx->h_count, sizeof(uint64_t) * 8, hipHostMallocDefault) !=
           hipSuccess) {
     if (ctx->frames_ev) (void)hipEventDestroy(ctx->frames_ev);
@@ -796,6 +798,34 @@ gsr_status gsr_loss_l1(gsr_context* ctx, const float* target_rgb, const float* t
                    target_depth, depth_weight, P<double>(ctx->loss_part),
                    P<float>(ctx->loss_scale), loss, g_rgb, g_depth, g_alpha);
   }
+  GSR_HIP(hipGetLastError());
+  return GSR_OK;
+}
+
+gsr_status gsr_loss_l1_noalloc(gsr_context* ctx, const float* target_rgb,
+                               const float* target_depth, float depth_weight, float* loss,
+                               float* g_rgb, float* g_depth, float* g_alpha, void* stream) {
+  if (!ctx) return GSR_ERR_INVALID_ARGUMENT;
+  Saved& sv = ctx->s;
+  if (!sv.valid) return fail(ctx, GSR_ERR_STATE, "loss without a preceding forward");
+  if (!target_rgb || !target_depth || !loss || !g_rgb || !g_depth || !g_alpha)
+    return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "pointer is NULL");
+  if (!ctx->loss_scratch) return fail(ctx, GSR_ERR_STATE, "static scratch not resolved");
+  const int bx = loss_blocks_x(sv.max_hw);
+  // [F][bx][3] doubles, then [F][2] floats
+  const size_t part_bytes = (size_t)bx * sv.F * 3 * 8;
+  const size_t need = part_bytes + (size_t)sv.F * 2 * 4;
+  if (need > loss_scratch_bytes())
+    return fail(ctx, GSR_ERR_UNSUPPORTED,
+                "%d frames of up to %lld pixels need %zu bytes of loss scratch; the static "
+                "buffer holds %zu (use gsr_loss_l1)",
+                sv.F, (long long)sv.max_hw, need, loss_scratch_bytes());
+  hipStream_t st = (hipStream_t)stream;
+  GSR_HIP(hipSetDevice(ctx->device));
+  unsigned char* base = static_cast<unsigned char*>(ctx->loss_scratch);
+  launch_loss_l1(st, sv.F, bx, P<FrameDesc>(ctx->frames), sv.rgb, sv.depth, target_rgb,
+                 target_depth, depth_weight, reinterpret_cast<double*>(base),
+                 reinterpret_cast<float*>(base + part_bytes), loss, g_rgb, g_depth, g_alpha);
   GSR_HIP(hipGetLastError());
   return GSR_OK;
 }

@@ -23,7 +23,7 @@ STAGES = ["preprocess", "depth_sort", "offsets", "keygen", "tile_sort", "ranges"
 
 EXPORTS = ["gsr_create", "gsr_destroy", "gsr_last_error", "gsr_forward", "gsr_forward_surfel",
            "gsr_backward", "gsr_backward_surfel", "gsr_normal_consistency",
-           "gsr_loss_l1", "gsr_step_l1", "gsr_loss_render", "gsr_step_render",
+           "gsr_loss_l1", "gsr_loss_l1_noalloc", "gsr_step_l1", "gsr_loss_render", "gsr_step_render",
            "gsr_densify_stats", "gsr_mcmc_noise", "gsr_mcmc_relocate", "gsr_check_overflow", "gsr_debug_stats",
            "gsr_debug_timings", "gsr_debug_lists", "gsr_debug_grad2d", "gsr_autotune",
            "gsr_adam_step"]
@@ -87,6 +87,7 @@ def load(path=LIB_PATH):
     lib.gsr_normal_consistency.argtypes = [V, I32, C.POINTER(Camera), V, V, V, F32, V, V, V, V,
                                            V]
     lib.gsr_loss_l1.argtypes = [V, V, V, F32, V, V, V, V, V]
+    lib.gsr_loss_l1_noalloc.argtypes = [V, V, V, F32, V, V, V, V, V]
     lib.gsr_step_l1.argtypes = [V, C.POINTER(Settings), I64, V, V, V, V, V, I32,
                                 C.POINTER(Camera), V, V, V, F32, V, V, V, V, V, V, V, V, V, V,
                                 V]

@@ -169,6 +169,15 @@ class Rasterizer:
                                          _ptr(out["g_alpha"]), _stream()))
         return out
 
+    def loss_l1_noalloc(self, target_rgb, target_depth, depth_weight, out):
+        """loss_l1 into preallocated `out` (dict loss, g_rgb, g_depth,
+        g_alpha) through the entry point that allocates no device memory."""
+        self._check(self.lib.gsr_loss_l1_noalloc(self.h, _ptr(target_rgb), _ptr(target_depth),
+                                                 float(depth_weight), _ptr(out["loss"]),
+                                                 _ptr(out["g_rgb"]), _ptr(out["g_depth"]),
+                                                 _ptr(out["g_alpha"]), _stream()))
+        return out
+
     def loss_render(self, rgb, depth, target_rgb, target_depth, lambda1=0.9, lambda2=0.2,
                     out=None):
         """Full rendering loss (L1 + SSIM colour term, L1 depth term) of

@@ -23,6 +23,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -49,12 +51,14 @@ def log(msg):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--tile", default="auto", help="WxH or 'auto' (autotuner's choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-frame", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-c4", action="store_true")
+    ap.add_argument("--no-c5", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--n", type=int, default=500_000)
     ap.add_argument("--copy-kernel", type=int, default=0, metavar="BYTES",
@@ -135,43 +139,35 @@ def main():
     for _ in range(args.warmup):
         step(rast, sc.cams, dev["poses"], t_rgb, t_dep, bb, cap)
     torch.cuda.synchronize()
+    # eager steps with the library's per-stage HIP events (stage times, the
+    # roofline's kernel duration)
     rast.timings()  # drop anything recorded so far
-    log(f"[bench] timed batched steps: {args.steps}")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(rast, sc.cams, dev["poses"], t_rgb, t_dep, bb, cap, timing=True)
-    torch.cuda.synchronize()
-    t_batched = (time.perf_counter() - t0) / args.steps
+    t_eager = median_event_ms(
+        lambda: step(rast, sc.cams, dev["poses"], t_rgb, t_dep, bb, cap, timing=True),
+        args.steps)
     rast.check_overflow()
     stages = rast.timings()
     loss = bb["loss"].item()
-    log(f"[bench] batched {t_batched * 1e3:.2f} ms/step, loss {loss:.5f}")
+    log(f"[bench] eager batched {t_eager:.3f} ms/step (median), loss {loss:.5f}")
 
-    # the same step captured as one HIP graph (no host work per step)
-    t_graph = None
+    # the headline: the same step captured as one HIP graph, warmed up, then
+    # exactly `steps` replays between two synchronisations, each bracketed by
+    # HIP events on the stream it runs on; the median replay is the step time
+    t_graph = t_wall = None
     try:
         if args.no_graph:
             raise RuntimeError("graph replay disabled by --no-graph")
-        side = torch.cuda.Stream()
-        side.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(side):
-            step(rast, sc.cams, dev["poses"], t_rgb, t_dep, bb, cap)
-        torch.cuda.current_stream().wait_stream(side)
-        torch.cuda.synchronize()
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            step(rast, sc.cams, dev["poses"], t_rgb, t_dep, bb, cap)
-        torch.cuda.synchronize()
-        graph.replay()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
+        graph = capture(lambda: step(rast, sc.cams, dev["poses"], t_rgb, t_dep, bb, cap))
+        for _ in range(args.warmup):
             graph.replay()
         torch.cuda.synchronize()
-        t_graph = (time.perf_counter() - t0) / args.steps
+        t0 = time.perf_counter()
+        t_graph = median_event_ms(graph.replay, args.steps, sync=False)
+        torch.cuda.synchronize()
+        t_wall = (time.perf_counter() - t0) * 1e3 / args.steps
         rast.check_overflow()
-        log(f"[bench] graph-replayed batched {t_graph * 1e3:.2f} ms/step")
+        log(f"[bench] graph-replayed batched {t_graph:.3f} ms/step (median of {args.steps}; "
+            f"wall mean {t_wall:.3f})")
         del graph
     except Exception as e:  # reported, never silently substituted
         log(f"[bench] graph capture failed: {e!r}")
@@ -183,32 +179,11 @@ def main():
     log(f"[bench] evaluated pairs per forward {pairs}")
 
     # ---------------- per-frame: the same work, one launch sequence per frame
-    t_per_frame = None
+    per_frame = None
     if not args.no_per_frame:
-        rf = Rasterizer(0)
-        per = []
-        for f in range(F):
-            cams_f = [sc.cams[f]]
-            poses_f = dev["poses"][f:f + 1].contiguous()
-            tr = t_rgb[3 * f * W * H:3 * (f + 1) * W * H]
-            td = t_dep[f * W * H:(f + 1) * W * H]
-            bf = buffers(W * H, 1)
-            step(rf, cams_f, poses_f, tr, td, bf, 0)
-            torch.cuda.synchronize()
-            kf = rf.stats()["n_keys"]
-            per.append((cams_f, poses_f, tr, td, bf, int(kf * 1.05) + 1024))
-        for _ in range(args.warmup):
-            for (c, p, tr, td, bf, kc) in per:
-                step(rf, c, p, tr, td, bf, kc)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            for (c, p, tr, td, bf, kc) in per:
-                step(rf, c, p, tr, td, bf, kc)
-        torch.cuda.synchronize()
-        t_per_frame = (time.perf_counter() - t0) / args.steps
-        rf.check_overflow()
-        log(f"[bench] per-frame {t_per_frame * 1e3:.2f} ms/step")
+        per_frame = measure_per_frame(sc, dev, t_rgb, t_dep, tile, depth_weight, args.steps,
+                                      args.warmup)
+        log(f"[bench] per-frame {per_frame}")
 
     # ---------------- the paper's full rendering loss (L1 + SSIM colour term)
     render = measure_render_loss(rast, sc, dev, bb, t_rgb, t_dep, tile, cap, args.steps)
@@ -218,9 +193,9 @@ def main():
     surfel = measure_surfel(rast, sc, dev, tile, args.steps)
 
     mpix = P / 1e6
-    t_best = min(t_batched, t_graph) if t_graph else t_batched
-    value = mpix / t_best
-    per_stage = {k: round(v[0] / max(args.steps, 1), 4) for k, v in stages.items() if v[1]}
+    t_best = t_graph if t_graph is not None else t_eager
+    value = mpix / (t_best * 1e-3)
+    per_stage = {k: round(v[0] / max(v[1], 1), 4) for k, v in stages.items() if v[1]}
     # roofline of the dominant compositing kernel
     dom = max(("composite_fwd", "composite_bwd"), key=lambda k: stages[k][0])
     dur_ms = stages[dom][0] / max(stages[dom][1], 1)
@@ -231,30 +206,49 @@ def main():
                 "traffic": measured_traffic(dom, tile),
                 "avg_launch_ms": round(dur_ms, 4), "pairs_per_launch": pairs,
                 "flops_per_pair": FLOPS_PER_PAIR[dom]}
+    achievable = measure_copy(rast)
+    sort = sort_roofline(stages, int(K), achievable)
+    log(f"[bench] achievable HBM {achievable}; sort {sort}")
+    del bb
+
+    c4 = None if args.no_c4 else measure_c4(args.steps, args.warmup)
+    c5 = None if args.no_c5 else measure_c5(args.steps)
 
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(sc, args.cpu_threads)
 
+    speedup = speedup_eager = None
+    if per_frame is not None:
+        pf = per_frame["graph_ms"] if per_frame["graph_ms"] is not None else per_frame["eager_ms"]
+        speedup = round(pf / t_best, 4)
+        speedup_eager = round(per_frame["eager_ms"] / t_eager, 4)
     out = {
         "metric": "fwd+bwd Mpixels/s at 500k Gaussians; batched vs per-frame speedup",
         "value": round(value, 3), "unit": "Mpixels/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(t_best * 1e3, 4),
+        "warmup": args.warmup, "ms_per_step": round(t_best, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded piecewise-planar scenes shaped like the paper's maps)",
         "config": {"workload": "c3: 500k Gaussians SH3, 8 keyframes 1200x680 f=600, "
                                "fwd + L1 rgb + L1 depth + bwd incl. pose twists",
                    "n_gaussians": sc.n, "frames": F, "resolution": [W, H],
                    "tile": list(tile), "keys_per_step": int(K)},
+        "timing": "median of the per-step HIP-event times of `steps` HIP-graph replays "
+                  "after `warmup` untimed ones",
         "autotune_ms_per_tile_shape": tune,
-        "eager_ms_per_step": round(t_batched * 1e3, 4),
-        "graph_ms_per_step": None if t_graph is None else round(t_graph * 1e3, 4),
-        "per_frame_ms_per_step": None if t_per_frame is None else round(t_per_frame * 1e3, 4),
-        "batched_vs_per_frame_speedup": None if t_per_frame is None else
-        round(t_per_frame / t_best, 4),
+        "eager_ms_per_step": round(t_eager, 4),
+        "graph_ms_per_step": None if t_graph is None else round(t_graph, 4),
+        "graph_wall_mean_ms_per_step": None if t_wall is None else round(t_wall, 4),
+        "per_frame": per_frame,
+        "batched_vs_per_frame_speedup": speedup,
+        "batched_vs_per_frame_speedup_eager": speedup_eager,
         "stage_ms_per_step": per_stage,
         "loss": loss,
         "roofline": roofline,
+        "sort": sort,
+        "achievable_hbm": achievable,
+        "c4": c4,
+        "c5": c5,
         "render_loss": render,
         "median_depth": median,
         "densify": densify,
@@ -262,6 +256,258 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def median_event_ms(fn, reps, sync=True):
+    """Median over `reps` calls of fn() of the HIP-event time around each call,
+    events recorded on the current stream (the one the library and graph
+    replays run on)."""
+    import torch
+    if sync:
+        torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+
+def capture(fn):
+    """fn() captured as one HIP graph (one eager call on a side stream first,
+    so that every workspace buffer exists before the capture)."""
+    import torch
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    torch.cuda.synchronize()
+    return g
+
+
+def step_buffers(n, K, F, P):
+    import torch
+    return dict(rgb=torch.empty(3 * P, device="cuda"), depth=torch.empty(P, device="cuda"),
+                alpha=torch.empty(P, device="cuda"), loss=torch.empty(1, device="cuda"),
+                means=torch.empty(n, 3, device="cuda"), log_scales=torch.empty(n, 3, device="cuda"),
+                quats=torch.empty(n, 4, device="cuda"), opacity=torch.empty(n, device="cuda"),
+                sh=torch.empty(n, K, 3, device="cuda"), twist=torch.empty(F, 6, device="cuda"))
+
+
+def per_frame_setup(sc, dev, t_rgb, t_dep, tile, depth_weight):
+    """The batch as F single-frame steps on one context (each frame runs its
+    own depth sort, scan and tile sort), each at its own fixed key capacity:
+    returns the function running all F in sequence."""
+    import torch
+    from paper_2411_17660_amd.raster import Rasterizer
+    rf = Rasterizer(0)
+    K = (sc.sh_degree + 1) ** 2
+    per, off = [], 0
+    for f, cam in enumerate(sc.cams):
+        w, h = int(cam[0]), int(cam[1])
+        poses_f = dev["poses"][f:f + 1].contiguous()
+        tr = t_rgb[3 * off:3 * (off + w * h)]
+        td = t_dep[off:off + w * h]
+        bf = step_buffers(sc.n, K, 1, w * h)
+        rf.step_l1(dev["means"], dev["log_scales"], dev["quats"], dev["opacity"], dev["sh"],
+                   poses_f, [cam], sc.sh_degree, tr, td, depth_weight, bf, tile=tile)
+        torch.cuda.synchronize()
+        kf = rf.stats()["n_keys"]
+        per.append(([cam], poses_f, tr, td, bf, int(kf * 1.05) + 1024))
+        off += w * h
+
+    def run():
+        for (c, p, tr, td, bf, kc) in per:
+            rf.step_l1(dev["means"], dev["log_scales"], dev["quats"], dev["opacity"], dev["sh"],
+                       p, c, sc.sh_degree, tr, td, depth_weight, bf, tile=tile, key_capacity=kc)
+    return rf, run
+
+
+def measure_per_frame(sc, dev, t_rgb, t_dep, tile, depth_weight, steps, warmup):
+    """Per-frame baseline: the same library called once per frame (F = 1),
+    eager and captured as one graph of F steps; median step times."""
+    import torch
+    rf, run = per_frame_setup(sc, dev, t_rgb, t_dep, tile, depth_weight)
+    for _ in range(warmup):
+        run()
+    eager = median_event_ms(run, steps)
+    rf.check_overflow()
+    graph_ms = None
+    try:
+        g = capture(run)
+        for _ in range(warmup):
+            g.replay()
+        graph_ms = median_event_ms(g.replay, steps)
+        rf.check_overflow()
+        del g
+    except Exception as e:
+        log(f"[bench] per-frame graph capture failed: {e!r}")
+    torch.cuda.synchronize()
+    return {"eager_ms": round(eager, 4),
+            "graph_ms": None if graph_ms is None else round(graph_ms, 4)}
+
+
+def measure_copy(rast, nbytes=2 << 30):
+    """Achievable HBM: the library's plain 16-byte copy kernel over 2 GiB
+    buffers (read 2 GiB + write 2 GiB), median of 10 launches."""
+    import torch
+    src = torch.ones(nbytes // 4, device="cuda")
+    dst = torch.empty_like(src)
+    rast.debug_copy(src, dst)
+    ms = median_event_ms(lambda: rast.debug_copy(src, dst), 10)
+    assert bool(torch.equal(dst[:1024], src[:1024]))
+    del src, dst
+    gbs = 2 * nbytes / (ms * 1e-3) / 1e9
+    return {"kernel": "copy16 (one 16-byte element per thread)", "buffer_bytes": nbytes,
+            "ms": round(ms, 4), "GBps": round(gbs, 1), "frac_of_peak": round(gbs / PEAK_HBM_GBS, 4)}
+
+
+# Algorithmic HBM bytes per key of the list stages: the sort moves each
+# (tile, Gaussian) pair once in and once out (12-byte pairs: 24 B); keygen
+# writes the pair (12 B); the ranges read each key once (8 B).
+SORT_BYTES_PER_KEY = 24
+KEYGEN_BYTES_PER_KEY = 12
+RANGES_BYTES_PER_KEY = 8
+
+
+def sort_roofline(stages, K, achievable):
+    def ms(k):
+        return stages[k][0] / max(stages[k][1], 1)
+    t_sort = ms("tile_sort")
+    gbs = SORT_BYTES_PER_KEY * K / (t_sort * 1e-3) / 1e9
+    t_all = ms("keygen") + t_sort + ms("ranges")
+    b_all = (KEYGEN_BYTES_PER_KEY + SORT_BYTES_PER_KEY + RANGES_BYTES_PER_KEY) * K
+    gbs_all = b_all / (t_all * 1e-3) / 1e9
+    return {"bound": "hbm", "stage": "tile_sort", "keys": K,
+            "algorithmic_bytes_per_key": SORT_BYTES_PER_KEY, "ms": round(t_sort, 4),
+            "achieved_GBps": round(gbs, 1), "peak_GBps": PEAK_HBM_GBS,
+            "frac": round(gbs / PEAK_HBM_GBS, 4),
+            "frac_of_achievable": round(gbs / achievable["GBps"], 4),
+            "lists": {"stages": ["keygen", "tile_sort", "ranges"],
+                      "algorithmic_bytes_per_key": KEYGEN_BYTES_PER_KEY + SORT_BYTES_PER_KEY +
+                      RANGES_BYTES_PER_KEY, "ms": round(t_all, 4),
+                      "achieved_GBps": round(gbs_all, 1),
+                      "frac": round(gbs_all / PEAK_HBM_GBS, 4),
+                      "frac_of_achievable": round(gbs_all / achievable["GBps"], 4)}}
+
+
+def measure_c4(steps, warmup):
+    """C4: 1M Gaussians with Student-t scales, 16 keyframes of mixed
+    resolution; the autotuner picks the tile; batched graph replays against
+    per-frame launches (eager and graph)."""
+    import torch
+    from paper_2411_17660_amd import scenes
+    from paper_2411_17660_amd.raster import Rasterizer
+    t0 = time.time()
+    sc = scenes.scene_c4()
+    log(f"[bench] c4 scene in {time.time() - t0:.1f}s")
+    dev = {k: torch.from_numpy(np.ascontiguousarray(getattr(sc, k), np.float32)).cuda()
+           for k in ("means", "log_scales", "quats", "opacity", "sh", "poses")}
+    gt = torch.from_numpy(sc.extra["gt_means"]).cuda()
+    r = Rasterizer(0)
+    t_rgb, t_dep, _ = r.forward(gt, dev["log_scales"], dev["quats"], dev["opacity"], dev["sh"],
+                                dev["poses"], sc.cams, 3)
+    t_rgb, t_dep = t_rgb.clone(), t_dep.clone()
+    tile, cap, times = r.autotune(dev["means"], dev["log_scales"], dev["quats"], dev["opacity"],
+                                  dev["sh"], dev["poses"], sc.cams, 3, t_rgb, t_dep, 1.0,
+                                  reps=2, force=True)
+    P = sc.n_pixels
+    b = step_buffers(sc.n, 16, sc.n_frames, P)
+
+    def st():
+        r.step_l1(dev["means"], dev["log_scales"], dev["quats"], dev["opacity"], dev["sh"],
+                  dev["poses"], sc.cams, 3, t_rgb, t_dep, 1.0, b, tile=tile, key_capacity=cap)
+    st()
+    torch.cuda.synchronize()
+    keys = int(r.stats()["n_keys"])
+    g = capture(st)
+    for _ in range(warmup):
+        g.replay()
+    t_b = median_event_ms(g.replay, steps)
+    r.check_overflow()
+    del g
+    rf, run = per_frame_setup(sc, dev, t_rgb, t_dep, tile, 1.0)
+    for _ in range(warmup):
+        run()
+    t_pf_eager = median_event_ms(run, max(3, steps // 2))
+    gp = capture(run)
+    for _ in range(warmup):
+        gp.replay()
+    t_pf = median_event_ms(gp.replay, max(3, steps // 2))
+    rf.check_overflow()
+    del gp
+    res = {"workload": "c4: 1M Gaussians SH3 (Student-t log-scales), 16 keyframes of mixed "
+                       "resolution, fwd + L1 rgb + L1 depth + bwd",
+           "resolutions": [[int(c[0]), int(c[1])] for c in sc.cams], "pixels": P,
+           "keys": keys, "tile": list(tile),
+           "autotune_ms_per_tile_shape": {f"{w}x{h}": round(v, 3) for (w, h), v in times.items()},
+           "ms_per_step": round(t_b, 4), "Mpix_per_s": round(P / 1e6 / (t_b * 1e-3), 3),
+           "per_frame_ms": round(t_pf, 4), "per_frame_eager_ms": round(t_pf_eager, 4),
+           "batched_vs_per_frame_speedup": round(t_pf / t_b, 4)}
+    log(f"[bench] c4 {res}")
+    del rf, r
+    torch.cuda.synchronize()
+    return res
+
+
+def measure_c5(steps):
+    """C5: one mapping iteration (forward + L1 rgb + 0.1 L1 depth + backward +
+    fused Adam on means, SH and poses with the pose fold) on 3M Gaussians and
+    12 x 1920x1080 keyframes, captured as one graph; median replay time."""
+    import torch
+    from paper_2411_17660_amd import scenes
+    from paper_2411_17660_amd.raster import Rasterizer
+    t0 = time.time()
+    sc = scenes.scene_c5()
+    log(f"[bench] c5 scene in {time.time() - t0:.1f}s")
+    dev = {k: torch.from_numpy(np.ascontiguousarray(getattr(sc, k), np.float32)).cuda()
+           for k in ("means", "log_scales", "quats", "opacity", "sh", "poses")}
+    gt = torch.from_numpy(sc.extra["gt_means"]).cuda()
+    r = Rasterizer(0)
+    t_rgb, t_dep, _ = r.forward(gt, dev["log_scales"], dev["quats"], dev["opacity"], dev["sh"],
+                                dev["poses"], sc.cams, 3)
+    t_rgb, t_dep = t_rgb.clone(), t_dep.clone()
+    n, F, P = sc.n, sc.n_frames, sc.n_pixels
+    b = step_buffers(n, 16, F, P)
+    state = dict(m_means=torch.zeros(n, 3, device="cuda"), v_means=torch.zeros(n, 3, device="cuda"),
+                 m_sh=torch.zeros(n, 16, 3, device="cuda"), v_sh=torch.zeros(n, 16, 3, device="cuda"),
+                 m_twist=torch.zeros(F, 6, device="cuda"), v_twist=torch.zeros(F, 6, device="cuda"),
+                 step=torch.zeros(1, dtype=torch.int32, device="cuda"))
+
+    def stp(cap):
+        r.step_l1(dev["means"], dev["log_scales"], dev["quats"], dev["opacity"], dev["sh"],
+                  dev["poses"], sc.cams, 3, t_rgb, t_dep, 0.1, b, key_capacity=cap)
+    stp(0)
+    torch.cuda.synchronize()
+    keys = int(r.stats()["n_keys"])
+    cap = int(keys * 1.1) + 4096
+
+    def iteration():
+        stp(cap)
+        r.adam_step(dict(means=dev["means"], sh=dev["sh"], poses=dev["poses"]),
+                    dict(means=b["means"], sh=b["sh"], twist=b["twist"]), state)
+    g = capture(iteration)
+    g.replay()
+    t_it = median_event_ms(g.replay, steps)
+    r.check_overflow()
+    loss = float(b["loss"].item())
+    del g
+    res = {"workload": "c5: 3M Gaussians SH3, 12 keyframes 1920x1080 f=1000, one mapping "
+                       "iteration (fwd + L1 rgb + 0.1 L1 depth + bwd + fused Adam, pose fold)",
+           "keys": keys, "iteration_ms": round(t_it, 4),
+           "Mpix_per_s": round(P / 1e6 / (t_it * 1e-3), 3), "iterations_timed": steps,
+           "adam_steps_taken": int(state["step"].item()), "loss_after": loss}
+    log(f"[bench] c5 {res}")
+    del r
+    torch.cuda.synchronize()
+    return res
 
 
 # Rendering loss with SSIM (11x11 window, FP64 arithmetic), per pixel of the
@@ -497,38 +743,56 @@ def measured_traffic(kernel, tile):
     return None
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(sc, threads, budget_s=25.0):
     """FP64 oracle, forward + backward of the keyframes one at a time (each
     with all Gaussians) on the host cores, until every frame is done or
     `budget_s` has passed; upstream gradients of the L1 loss's shape
-    (+-1/(3HW) per channel, +-1/HW per depth pixel)."""
-    import numpy as np
-
+    (+-1/(3HW) per channel, +-1/HW per depth pixel).  Then the first keyframe
+    again on one thread."""
     import oracle
     nthreads = threads or min(16, os.cpu_count() or 1)
     log(f"[bench] cpu baseline: oracle, keyframes one at a time, {nthreads} threads")
     rng = np.random.default_rng(0)
-    pixels, done, t0 = 0, 0, time.perf_counter()
-    for f in range(sc.n_frames):
+
+    def one(f, nt):
         sf = sc.subset_frames([f])
-        r = oracle.forward(sf, threads=nthreads)
+        r = oracle.forward(sf, threads=nt)
         P = r.P
         G = (rng.choice([-1.0, 1.0], 3 * P) / (3 * P), rng.choice([-1.0, 1.0], P) / P,
              np.zeros(P))
         r.backward(*G)
-        del r
-        pixels += P
+        return P
+    pixels, done, t0 = 0, 0, time.perf_counter()
+    for f in range(sc.n_frames):
+        pixels += one(f, nthreads)
         done += 1
         dt = time.perf_counter() - t0
         log(f"[bench] cpu baseline: frame {f} done, {dt:.1f}s")
         if dt >= budget_s:
             break
     dt = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    p1 = one(0, 1)
+    dt1 = time.perf_counter() - t1
+    log(f"[bench] cpu baseline: frame 0 on one thread {dt1:.1f}s")
     w, h = int(sc.cams[0][0]), int(sc.cams[0][1])
     return {"value": round(pixels / 1e6 / dt, 5), "unit": "Mpixels/s", "cores": nthreads,
             "kind": "oracle", "seconds": round(dt, 2),
             "sample": f"{done} of the {sc.n_frames} keyframes ({w}x{h}, all {sc.n} Gaussians "
-                      f"each), one at a time, fwd+bwd, FP64"}
+                      f"each), one at a time, fwd+bwd, FP64",
+            "one_thread": {"value": round(p1 / 1e6 / dt1, 5), "unit": "Mpixels/s",
+                           "seconds": round(dt1, 2), "sample": "keyframe 0, fwd+bwd, FP64"},
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
 
 
 if __name__ == "__main__":

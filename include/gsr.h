@@ -418,6 +418,13 @@ gsr_status gsr_debug_lists(gsr_context* ctx, uint32_t* ntiles, uint32_t* depth_k
  * GSR_ERR_STATE before the first backward. */
 gsr_status gsr_debug_grad2d(gsr_context* ctx, double* out, void* stream);
 
+/* Measurement aid: a plain device copy of `bytes` (a multiple of 16, both
+ * pointers 16-byte aligned, device memory, no overlap), one 16-byte element
+ * per thread, enqueued on `stream`.  Copies of >= 2 GB give the achievable
+ * HBM bandwidth that the sort's bandwidth fraction is reported against. */
+gsr_status gsr_debug_copy(gsr_context* ctx, const void* src, void* dst, uint64_t bytes,
+                          void* stream);
+
 #ifdef __cplusplus
 }
 #endif

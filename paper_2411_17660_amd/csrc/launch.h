@@ -39,6 +39,10 @@ void launch_size_class(hipStream_t st, uint64_t m, const uint32_t* ntiles, uint3
 // radix_hist_elems / radix_scan_elems: u32 workspace of a sort of up to
 // n_max keys whose widest digit serves `bits` key bits (0: 8-bit digits).
 void launch_fill_u32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t v);
+// dst[0..n) = host[0..n), the descriptors travelling as kernel arguments
+void launch_set_frames(hipStream_t st, const FrameDesc* host, int n, FrameDesc* dst);
+// dst[i] = src[i] for n16 16-byte elements (plain copy, bandwidth reference)
+void launch_copy16(hipStream_t st, const void* src, void* dst, uint64_t n16);
 size_t radix_hist_elems(uint64_t n_max, int bits);
 size_t scan_block_elems(uint64_t n_max);
 size_t radix_scan_elems(uint64_t n_max, int bits);

@@ -70,10 +70,7 @@ struct gsr_context {
   std::map<std::string, gsr_settings> tune_cache;
   uint64_t key_cap = 0;             // allocated key slots
   // pinned host staging
-  FrameDesc* h_frames = nullptr;
-  int h_frames_cap = 0;
   uint64_t* h_count = nullptr;
-  hipEvent_t frames_ev = nullptr;
   void* loss_scratch = nullptr;     // this device's static scratch of gsr_loss_l1_noalloc
   std::vector<FrameDesc> last_frames;
   uint32_t epoch = 0;
@@ -192,26 +189,14 @@ gsr_status validate(gsr_context* ctx, const gsr_settings* s, int64_t n, const fl
 }
 
 // Frame descriptors to the device (re-uploaded only when they change).
+// The frame table goes to the device as kernel arguments (by value), so
+// every forward writes its own table on its stream, also inside a captured
+// graph that holds several forwards with different tables; no host staging
+// buffer has to outlive the call.
 gsr_status upload_frames(gsr_context* ctx, const std::vector<FrameDesc>& fr, hipStream_t st) {
-  const size_t bytes = fr.size() * sizeof(FrameDesc);
-  if (ctx->last_frames.size() == fr.size() &&
-      std::memcmp(ctx->last_frames.data(), fr.data(), bytes) == 0)
-    return GSR_OK;
-  gsr_status rc = ensure(ctx, ctx->frames, bytes, st);
+  gsr_status rc = ensure(ctx, ctx->frames, fr.size() * sizeof(FrameDesc), st);
   if (rc) return rc;
-  if ((int)fr.size() > ctx->h_frames_cap) {
-    if (ctx->h_frames) {
-      GSR_HIP(hipEventSynchronize(ctx->frames_ev));
-      GSR_HIP(hipHostFree(ctx->h_frames));
-    }
-    GSR_HIP(hipHostMalloc((void**)&ctx->h_frames, bytes, hipHostMallocDefault));
-    ctx->h_frames_cap = (int)fr.size();
-  } else {
-    GSR_HIP(hipEventSynchronize(ctx->frames_ev));  // previous copy has read the staging
-  }
-  std::memcpy(ctx->h_frames, fr.data(), bytes);
-  GSR_HIP(hipMemcpyAsync(ctx->frames.p, ctx->h_frames, bytes, hipMemcpyHostToDevice, st));
-  GSR_HIP(hipEventRecord(ctx->frames_ev, st));
+  launch_set_frames(st, fr.data(), (int)fr.size(), P<FrameDesc>(ctx->frames));
   ctx->last_frames = fr;
   return GSR_OK;
 }
@@ -262,10 +247,8 @@ gsr_status gsr_create(gsr_context** out, int32_t device) {
   if (!ctx) return GSR_ERR_OUT_OF_MEMORY;
   ctx->device = device;
   if (loss_scratch_init(device, &ctx->loss_scratch) != hipSuccess ||
-      hipEventCreateWithFlags(&ctx->frames_ev, hipEventDisableTiming) != hipSuccess ||
       hipHostMalloc((void**)&ctx->h_count, sizeof(uint64_t) * 8, hipHostMallocDefault) !=
           hipSuccess) {
-    if (ctx->frames_ev) (void)hipEventDestroy(ctx->frames_ev);
     delete ctx;
     return GSR_ERR_HIP;
   }
@@ -291,9 +274,7 @@ gsr_status gsr_destroy(gsr_context* ctx) {
                   &ctx->clsv_b, &ctx->dist_aux, &ctx->spart, &ctx->sgrad, &ctx->nc_part};
   for (DBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
-  if (ctx->h_frames) (void)hipHostFree(ctx->h_frames);
   if (ctx->h_count) (void)hipHostFree(ctx->h_count);
-  if (ctx->frames_ev) (void)hipEventDestroy(ctx->frames_ev);
   for (auto& t : ctx->timed) {
     (void)hipEventDestroy(t.a);
     (void)hipEventDestroy(t.b);
@@ -1133,6 +1114,19 @@ gsr_status gsr_debug_lists(gsr_context* ctx, uint32_t* ntiles, uint32_t* depth_k
   if (ranges && sv.T) GSR_HIP(hipMemcpy(ranges, ctx->ranges.p, sv.T * 8, hipMemcpyDeviceToHost));
   if (n_last && sv.P) GSR_HIP(hipMemcpy(n_last, ctx->n_last.p, sv.P * 4, hipMemcpyDeviceToHost));
   if (t_final && sv.P) GSR_HIP(hipMemcpy(t_final, ctx->t_final.p, sv.P * 4, hipMemcpyDeviceToHost));
+  return GSR_OK;
+}
+
+gsr_status gsr_debug_copy(gsr_context* ctx, const void* src, void* dst, uint64_t bytes,
+                          void* stream) {
+  if (!ctx) return GSR_ERR_INVALID_ARGUMENT;
+  if (bytes == 0) return GSR_OK;
+  if (!src || !dst) return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "pointer is NULL");
+  if ((((uintptr_t)src) | ((uintptr_t)dst) | bytes) & 15u)
+    return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "pointers and size must be 16-byte multiples");
+  GSR_HIP(hipSetDevice(ctx->device));
+  launch_copy16((hipStream_t)stream, src, dst, bytes / 16);
+  GSR_HIP(hipGetLastError());
   return GSR_OK;
 }
 

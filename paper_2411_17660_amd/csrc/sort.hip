@@ -603,6 +603,33 @@ __global__ void __launch_bounds__(256) ranges_kernel(const uint32_t* __restrict_
   if (last == K - 1 && prev < n_tiles) ranges[prev].y = (uint32_t)K;
 }
 
+// Plain copy, one 16-byte element per thread: the reference for the
+// achievable HBM bandwidth that the sort's fraction is taken against.
+__global__ void __launch_bounds__(256) copy16_kernel(const uint4* __restrict__ a,
+                                                     uint4* __restrict__ b, uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+void launch_copy16(hipStream_t st, const void* src, void* dst, uint64_t n16) {
+  if (n16 == 0) return;
+  hipLaunchKernelGGL(copy16_kernel, dim3((unsigned)((n16 + 255) / 256)), dim3(256), 0, st,
+                     static_cast<const uint4*>(src), static_cast<uint4*>(dst), n16);
+}
+
+// Frame descriptors passed by value as kernel arguments (at most 64 per
+// launch: 3 KB of the 4 KB argument space), so that a captured graph keeps
+// each forward's own table.
+constexpr int kFramesPerLaunch = 64;
+struct FrameBatch {
+  FrameDesc f[kFramesPerLaunch];
+};
+
+__global__ void set_frames_kernel(FrameBatch b, int count, FrameDesc* __restrict__ dst) {
+  const int i = threadIdx.x;
+  if (i < count) dst[i] = b.f[i];
+}
+
 __global__ void fill_u32_kernel(uint32_t* __restrict__ p, uint64_t n, uint32_t v) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -613,6 +640,16 @@ __global__ void fill_u32_kernel(uint32_t* __restrict__ p, uint64_t n, uint32_t v
 // ---------------------------------------------------------------------------
 static inline unsigned blocks_for(uint64_t n, uint64_t per) {
   return (unsigned)((n + per - 1) / per);
+}
+
+void launch_set_frames(hipStream_t st, const FrameDesc* host, int n, FrameDesc* dst) {
+  for (int i0 = 0; i0 < n; i0 += kFramesPerLaunch) {
+    FrameBatch b{};
+    const int c = std::min(kFramesPerLaunch, n - i0);
+    std::copy(host + i0, host + i0 + c, b.f);
+    hipLaunchKernelGGL(set_frames_kernel, dim3(1), dim3(kFramesPerLaunch), 0, st, b, c,
+                       dst + i0);
+  }
 }
 
 void launch_fill_u32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t v) {

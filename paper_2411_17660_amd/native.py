@@ -25,7 +25,8 @@ EXPORTS = ["gsr_create", "gsr_destroy", "gsr_last_error", "gsr_forward", "gsr_fo
            "gsr_backward", "gsr_backward_surfel", "gsr_normal_consistency",
            "gsr_loss_l1", "gsr_loss_l1_noalloc", "gsr_step_l1", "gsr_loss_render", "gsr_step_render",
            "gsr_densify_stats", "gsr_mcmc_noise", "gsr_mcmc_relocate", "gsr_check_overflow", "gsr_debug_stats",
-           "gsr_debug_timings", "gsr_debug_lists", "gsr_debug_grad2d", "gsr_autotune",
+           "gsr_debug_timings", "gsr_debug_lists", "gsr_debug_grad2d", "gsr_debug_copy",
+           "gsr_autotune",
            "gsr_adam_step"]
 TILE_SHAPES = [(16, 16), (8, 8), (32, 8), (16, 8), (32, 16)]
 
@@ -102,6 +103,7 @@ def load(path=LIB_PATH):
     lib.gsr_debug_stats.argtypes = [V, C.POINTER(Stats), V]
     lib.gsr_debug_lists.argtypes = [V] + [V] * 8 + [V]
     lib.gsr_debug_grad2d.argtypes = [V, V, V]
+    lib.gsr_debug_copy.argtypes = [V, V, V, C.c_uint64, V]
     lib.gsr_debug_timings.argtypes = [V, V, V]
     lib.gsr_adam_step.argtypes = [V, I64, I32, V, V, V, V, V, V, V, V, I32, V, V, V, V, F32, F32,
                                   F32, F32, F32, F32, V, V]

@@ -299,6 +299,15 @@ class Rasterizer:
         self._check(self.lib.gsr_debug_timings(self.h, ms, calls))
         return {name: (ms[i], calls[i]) for i, name in enumerate(native.STAGES)}
 
+    def debug_copy(self, src, dst):
+        """dst <- src by the library's plain 16-byte copy kernel (bandwidth
+        reference); both contiguous device tensors of the same byte size."""
+        nbytes = src.numel() * src.element_size()
+        assert src.is_cuda and dst.is_cuda and src.is_contiguous() and dst.is_contiguous()
+        assert dst.numel() * dst.element_size() == nbytes
+        self._check(self.lib.gsr_debug_copy(self.h, C.c_void_p(src.data_ptr()),
+                                            C.c_void_p(dst.data_ptr()), nbytes, _stream()))
+
     def check_overflow(self):
         self._check(self.lib.gsr_check_overflow(self.h, _stream()))
 

@@ -187,3 +187,66 @@ def test_benchmarked_step_c3():
     _bitwise(replays[1], sep, "c3")
     print("[step] c3: replayed step bitwise equal to forward + loss + backward", flush=True)
     _check_against_oracle(rast, sc, d, sep, lo, t_rgb, t_dep, wd, tile, "c3")
+
+
+def test_graph_of_steps_with_different_frame_tables():
+    """Two steps of one context with different frame tables (sizes and
+    intrinsics) captured in one HIP graph: every replay, with eager work of the
+    same context between replays, gives each step's eager outputs bitwise.
+    The frame table travels as kernel arguments, so each captured forward
+    writes its own."""
+    import torch
+    from paper_2411_17660_amd.raster import Rasterizer
+    rast = Rasterizer(0)
+    sa = scenes.tiny_scene(seed=31, n=1500, W=96, H=72, f=80.0, n_frames=2)
+    sb = scenes.tiny_scene(seed=32, n=1500, W=150, H=100, f=120.0, n_frames=1)
+    runs = []
+    for sc, seed in ((sa, 1), (sb, 2)):
+        d = to_dev(sc)
+        t_rgb, t_dep = _targets(sc, 50 + seed)
+        trgb, tdep = torch.from_numpy(t_rgb).cuda(), torch.from_numpy(t_dep).cuda()
+        runs.append((sc, d, trgb, tdep, _bufs(sc)))
+
+    def step(i, cap):
+        sc, d, trgb, tdep, b = runs[i]
+        rast.step_l1(d["means"], d["log_scales"], d["quats"], d["opacity"], d["sh"], d["poses"],
+                     sc.cams, sc.sh_degree, trgb, tdep, 0.5, b, background=sc.background,
+                     key_capacity=cap)
+    caps = []
+    eager = []
+    for i in range(2):
+        step(i, 0)
+        torch.cuda.synchronize()
+        caps.append(int(rast.stats()["n_keys"]) + 256)
+    for i in range(2):
+        step(i, caps[i])
+        torch.cuda.synchronize()
+        eager.append({k: v.clone() for k, v in runs[i][4].items()})
+
+    def both():
+        step(0, caps[0])
+        step(1, caps[1])
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        both()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        both()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for r in runs:
+            for v in r[4].values():
+                v.fill_(float("nan"))
+        g.replay()
+        torch.cuda.synchronize()
+        for i in range(2):
+            _bitwise(runs[i][4], eager[i], f"replay {rep} step {i}")
+        # eager work of the same context between replays (the other table last)
+        step(1, caps[1])
+        step(0, caps[0])
+        torch.cuda.synchronize()
+    rast.check_overflow()
+    del g

@@ -53,7 +53,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--tile", default="auto", help="WxH or 'auto' (autotuner's choice)")
+    ap.add_argument("--tile", default="auto", help="WxH or 'auto' (autotuner's choice of tile "
+                    "shape and LDS batch)")
+    ap.add_argument("--lds-batch", type=int, default=64, help="with --tile WxH: 32, 64 or 128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-frame", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
@@ -105,13 +107,14 @@ def main():
     torch.cuda.synchronize()
     tune = None
     if args.tile == "auto":
-        tile, _, times = rast.autotune(dev["means"], dev["log_scales"], dev["quats"],
-                                       dev["opacity"], dev["sh"], dev["poses"], sc.cams, 3,
-                                       t_rgb, t_dep, depth_weight, reps=3, force=True)
-        tune = {f"{w}x{h}": round(ms, 3) for (w, h), ms in times.items()}
-        log(f"[bench] autotune: {tune} -> {tile}")
+        tile, batch, _, times = rast.autotune(dev["means"], dev["log_scales"], dev["quats"],
+                                              dev["opacity"], dev["sh"], dev["poses"], sc.cams,
+                                              3, t_rgb, t_dep, depth_weight, reps=3, force=True)
+        tune = {f"{w}x{h}/{b}": round(ms, 3) for ((w, h), b), ms in times.items()}
+        log(f"[bench] autotune: {tune} -> {tile} x {batch}")
     else:
         tile = tuple(int(v) for v in args.tile.split("x"))
+        batch = args.lds_batch
 
     def buffers(n_frames_px, nF):
         K = (sc.sh_degree + 1) ** 2
@@ -127,7 +130,7 @@ def main():
     def step(r, cams, poses, trgb, tdep, bufs, cap, timing=False):
         r.step_l1(dev["means"], dev["log_scales"], dev["quats"], dev["opacity"], dev["sh"],
                   poses, cams, 3, trgb, tdep, depth_weight, bufs, tile=tile, key_capacity=cap,
-                  timing=timing)
+                  timing=timing, lds_batch=batch)
 
     # ---------------- batched: one launch sequence for all 8 frames
     bb = buffers(P, F)
@@ -174,15 +177,16 @@ def main():
 
     # evaluated (pixel, entry) pairs of one forward (separate counting pass)
     rast.forward(dev["means"], dev["log_scales"], dev["quats"], dev["opacity"], dev["sh"],
-                 dev["poses"], sc.cams, 3, tile=tile, key_capacity=cap, count_pairs=True)
+                 dev["poses"], sc.cams, 3, tile=tile, key_capacity=cap, count_pairs=True,
+                 lds_batch=batch)
     pairs = rast.stats()["n_pairs"]
     log(f"[bench] evaluated pairs per forward {pairs}")
 
     # ---------------- per-frame: the same work, one launch sequence per frame
     per_frame = None
     if not args.no_per_frame:
-        per_frame = measure_per_frame(sc, dev, t_rgb, t_dep, tile, depth_weight, args.steps,
-                                      args.warmup)
+        per_frame = measure_per_frame(sc, dev, t_rgb, t_dep, tile, batch, depth_weight,
+                                      args.steps, args.warmup)
         log(f"[bench] per-frame {per_frame}")
 
     # ---------------- the paper's full rendering loss (L1 + SSIM colour term)
@@ -232,10 +236,10 @@ def main():
         "config": {"workload": "c3: 500k Gaussians SH3, 8 keyframes 1200x680 f=600, "
                                "fwd + L1 rgb + L1 depth + bwd incl. pose twists",
                    "n_gaussians": sc.n, "frames": F, "resolution": [W, H],
-                   "tile": list(tile), "keys_per_step": int(K)},
+                   "tile": list(tile), "lds_batch": batch, "keys_per_step": int(K)},
         "timing": "median of the per-step HIP-event times of `steps` HIP-graph replays "
                   "after `warmup` untimed ones",
-        "autotune_ms_per_tile_shape": tune,
+        "autotune_ms_per_tile_and_batch": tune,
         "eager_ms_per_step": round(t_eager, 4),
         "graph_ms_per_step": None if t_graph is None else round(t_graph, 4),
         "graph_wall_mean_ms_per_step": None if t_wall is None else round(t_wall, 4),
@@ -301,7 +305,7 @@ def step_buffers(n, K, F, P):
                 sh=torch.empty(n, K, 3, device="cuda"), twist=torch.empty(F, 6, device="cuda"))
 
 
-def per_frame_setup(sc, dev, t_rgb, t_dep, tile, depth_weight):
+def per_frame_setup(sc, dev, t_rgb, t_dep, tile, batch, depth_weight):
     """The batch as F single-frame steps on one context (each frame runs its
     own depth sort, scan and tile sort), each at its own fixed key capacity:
     returns the function running all F in sequence."""
@@ -317,7 +321,8 @@ def per_frame_setup(sc, dev, t_rgb, t_dep, tile, depth_weight):
         td = t_dep[off:off + w * h]
         bf = step_buffers(sc.n, K, 1, w * h)
         rf.step_l1(dev["means"], dev["log_scales"], dev["quats"], dev["opacity"], dev["sh"],
-                   poses_f, [cam], sc.sh_degree, tr, td, depth_weight, bf, tile=tile)
+                   poses_f, [cam], sc.sh_degree, tr, td, depth_weight, bf, tile=tile,
+                   lds_batch=batch)
         torch.cuda.synchronize()
         kf = rf.stats()["n_keys"]
         per.append(([cam], poses_f, tr, td, bf, int(kf * 1.05) + 1024))
@@ -326,15 +331,16 @@ def per_frame_setup(sc, dev, t_rgb, t_dep, tile, depth_weight):
     def run():
         for (c, p, tr, td, bf, kc) in per:
             rf.step_l1(dev["means"], dev["log_scales"], dev["quats"], dev["opacity"], dev["sh"],
-                       p, c, sc.sh_degree, tr, td, depth_weight, bf, tile=tile, key_capacity=kc)
+                       p, c, sc.sh_degree, tr, td, depth_weight, bf, tile=tile, key_capacity=kc,
+                       lds_batch=batch)
     return rf, run
 
 
-def measure_per_frame(sc, dev, t_rgb, t_dep, tile, depth_weight, steps, warmup):
+def measure_per_frame(sc, dev, t_rgb, t_dep, tile, batch, depth_weight, steps, warmup):
     """Per-frame baseline: the same library called once per frame (F = 1),
     eager and captured as one graph of F steps; median step times."""
     import torch
-    rf, run = per_frame_setup(sc, dev, t_rgb, t_dep, tile, depth_weight)
+    rf, run = per_frame_setup(sc, dev, t_rgb, t_dep, tile, batch, depth_weight)
     for _ in range(warmup):
         run()
     eager = median_event_ms(run, steps)
@@ -415,15 +421,16 @@ def measure_c4(steps, warmup):
     t_rgb, t_dep, _ = r.forward(gt, dev["log_scales"], dev["quats"], dev["opacity"], dev["sh"],
                                 dev["poses"], sc.cams, 3)
     t_rgb, t_dep = t_rgb.clone(), t_dep.clone()
-    tile, cap, times = r.autotune(dev["means"], dev["log_scales"], dev["quats"], dev["opacity"],
-                                  dev["sh"], dev["poses"], sc.cams, 3, t_rgb, t_dep, 1.0,
-                                  reps=2, force=True)
+    tile, batch, cap, times = r.autotune(dev["means"], dev["log_scales"], dev["quats"],
+                                         dev["opacity"], dev["sh"], dev["poses"], sc.cams, 3,
+                                         t_rgb, t_dep, 1.0, reps=2, force=True)
     P = sc.n_pixels
     b = step_buffers(sc.n, 16, sc.n_frames, P)
 
     def st():
         r.step_l1(dev["means"], dev["log_scales"], dev["quats"], dev["opacity"], dev["sh"],
-                  dev["poses"], sc.cams, 3, t_rgb, t_dep, 1.0, b, tile=tile, key_capacity=cap)
+                  dev["poses"], sc.cams, 3, t_rgb, t_dep, 1.0, b, tile=tile, key_capacity=cap,
+                  lds_batch=batch)
     st()
     torch.cuda.synchronize()
     keys = int(r.stats()["n_keys"])
@@ -433,7 +440,7 @@ def measure_c4(steps, warmup):
     t_b = median_event_ms(g.replay, steps)
     r.check_overflow()
     del g
-    rf, run = per_frame_setup(sc, dev, t_rgb, t_dep, tile, 1.0)
+    rf, run = per_frame_setup(sc, dev, t_rgb, t_dep, tile, batch, 1.0)
     for _ in range(warmup):
         run()
     t_pf_eager = median_event_ms(run, max(3, steps // 2))
@@ -446,8 +453,9 @@ def measure_c4(steps, warmup):
     res = {"workload": "c4: 1M Gaussians SH3 (Student-t log-scales), 16 keyframes of mixed "
                        "resolution, fwd + L1 rgb + L1 depth + bwd",
            "resolutions": [[int(c[0]), int(c[1])] for c in sc.cams], "pixels": P,
-           "keys": keys, "tile": list(tile),
-           "autotune_ms_per_tile_shape": {f"{w}x{h}": round(v, 3) for (w, h), v in times.items()},
+           "keys": keys, "tile": list(tile), "lds_batch": batch,
+           "autotune_ms_per_tile_and_batch": {f"{w}x{h}/{b}": round(v, 3)
+                                              for ((w, h), b), v in times.items()},
            "ms_per_step": round(t_b, 4), "Mpix_per_s": round(P / 1e6 / (t_b * 1e-3), 3),
            "per_frame_ms": round(t_pf, 4), "per_frame_eager_ms": round(t_pf_eager, 4),
            "batched_vs_per_frame_speedup": round(t_pf / t_b, 4)}

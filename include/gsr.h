@@ -82,7 +82,8 @@ typedef struct {
   int32_t sh_degree;      /* 0..3 */
   float background[3];
   int32_t tile_w, tile_h; /* 16x16, 8x8, 32x8, 16x8 or 32x16 */
-  int32_t lds_batch;      /* entries staged per LDS round; 0 or 64 */
+  int32_t lds_batch;      /* Gaussians staged per LDS round by the 3D compositing kernels:
+                             32, 64, 128; 0 = 64 (the surfel kernels always stage 64) */
   int64_t key_capacity;   /* 0: the library sizes the key buffers from the
                              exact count (one 8-byte device->host read per
                              forward); > 0: fixed capacity, no host read, and
@@ -328,14 +329,20 @@ gsr_status gsr_mcmc_relocate(gsr_context* ctx, int64_t n, int32_t sh_degree, flo
                              const int32_t* src, void* stream);
 
 /* Autotuner: runs gsr_step_l1 with every supported tile shape (16x16, 8x8,
- * 32x8, 16x8, 32x16) on the given inputs, `reps` timed runs each with HIP
- * events on `stream` after one untimed sizing run, and writes the fastest
- * settings to *chosen (base settings with tile_w/tile_h replaced and a fixed
- * key_capacity 5% above the measured count).  ms[i] receives the median step
- * time of shape i in the order above (array of 5; NULL allowed).  The choice
- * is cached in the context per (frame sizes, n rounded to a power of two, SH
- * degree); a cached choice is returned without measuring unless `force`.
+ * 32x8, 16x8, 32x16) and every LDS batch (32, 64, 128 Gaussians staged per
+ * round) on the given inputs: one untimed sizing run per tile shape, then
+ * `reps` runs per (shape, batch) timed with HIP events on `stream`.  Writes
+ * the fastest settings to *chosen (base settings with tile_w, tile_h and
+ * lds_batch replaced and a fixed key_capacity 5% above the measured count).
+ * ms[GSR_TUNE_BATCHES * i + j] receives the median step time of shape i with
+ * batch j in the orders above (array of GSR_TUNE_TILES * GSR_TUNE_BATCHES;
+ * NULL allowed).  Results do not depend on the choice: images are bitwise
+ * the same for every shape and batch.  The choice is cached in the context
+ * per (multiset of frame sizes, n rounded up to a power of two, SH degree);
+ * a cached choice is returned without measuring (ms all -1) unless `force`.
  * The library owns the scratch outputs it renders into. */
+#define GSR_TUNE_TILES 5
+#define GSR_TUNE_BATCHES 3
 gsr_status gsr_autotune(gsr_context* ctx, const gsr_settings* base, int64_t n, const float* means,
                         const float* log_scales, const float* quats,
                         const float* opacity_logits, const float* sh, int32_t n_frames,

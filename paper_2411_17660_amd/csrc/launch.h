@@ -69,6 +69,8 @@ void launch_ranges(hipStream_t st, const uint32_t* keys, const uint64_t* k_dev, 
 
 // raster.hip: compositing forward and backward
 bool tile_shape_supported(int tw, int th);
+// Gaussians staged per LDS round in the compositing kernels: 32, 64 or 128
+bool lds_batch_supported(int batch);
 // med_pos (NULL: alpha-blended depth) selects the median depth: the forward
 // writes, per pixel, the list position of the entry after which T first
 // falls below 1/2 (-1: none) and outputs that entry's z as the depth; the
@@ -77,13 +79,13 @@ bool tile_shape_supported(int tw, int th);
 // (`xcd_groups`, else one group), longest expected work first by
 // `prev_nproc` (processed entries of a previous forward over the same
 // tiles) when given, else in spatial order.  order [n_tiles] is scratch.
-void launch_composite_fwd(hipStream_t st, int tw, int th, int n_tiles, int F,
+void launch_composite_fwd(hipStream_t st, int tw, int th, int batch, int n_tiles, int F,
                           const FrameDesc* frames, const uint2* ranges, const uint32_t* vals,
                           const Record* rec, const float* bg, float* rgb, float* depth,
                           float* alpha, float* t_final, int32_t* n_last, uint32_t* nproc,
                           const uint32_t* prev_nproc, uint32_t* order, bool xcd_groups,
                           unsigned long long* pairs, int32_t* med_pos);
-void launch_composite_bwd(hipStream_t st, int tw, int th, int n_tiles, int F,
+void launch_composite_bwd(hipStream_t st, int tw, int th, int batch, int n_tiles, int F,
                           const FrameDesc* frames, const uint2* ranges, const uint32_t* vals,
                           const Record* rec, const uint2* trect, const uint32_t* keyoff,
                           const uint32_t* nproc, const float* bg, const float* g_rgb,

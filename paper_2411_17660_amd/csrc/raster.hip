@@ -99,7 +99,7 @@ __global__ void __launch_bounds__(1024) tile_order_kernel(int n_tiles, int group
 
 // The tile of workgroup `bid`, or -1 past the end of its group.
 
-template <int TW, int TH, bool COUNT, bool MEDIAN>
+template <int TW, int TH, bool COUNT, bool MEDIAN, int BATCH>
 __device__ __forceinline__ void composite_fwd_tile(
     int tile, Record* sm, int n_frames, const FrameDesc* __restrict__ frames,
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals,
@@ -130,15 +130,18 @@ __device__ __forceinline__ void composite_fwd_tile(
     const int py = y0 + k * RPP + ly;
     done[k] = !(px < fr.width && py < fr.height);
   }
-  for (uint32_t b = rg.x; b < rg.y; b += kWave) {
+  for (uint32_t b = rg.x; b < rg.y; b += BATCH) {
     bool live = false;
 #pragma unroll
     for (int k = 0; k < PIX; ++k) live |= !done[k];
     if (__ballot(live) == 0) break;
-    const uint32_t e = b + lane;
-    if (e < rg.y) sm[lane] = rec[vals[e]];
+#pragma unroll
+    for (int i = lane; i < BATCH; i += kWave) {
+      const uint32_t e = b + (uint32_t)i;
+      if (e < rg.y) sm[i] = rec[vals[e]];
+    }
     __syncthreads();
-    const int cnt = (int)min((uint32_t)kWave, rg.y - b);
+    const int cnt = (int)min((uint32_t)BATCH, rg.y - b);
     for (int j = 0; j < cnt; ++j) {
       const Record& R = sm[j];
       const int xlo = R.sqx & 0xffff, xhi = R.sqx >> 16;
@@ -206,7 +209,7 @@ __device__ __forceinline__ void composite_fwd_tile(
 }
 
 
-template <int TW, int TH, bool COUNT, bool MEDIAN>
+template <int TW, int TH, bool COUNT, bool MEDIAN, int BATCH>
 __global__ void __launch_bounds__(64) composite_fwd_kernel(
     int n_tiles, int groups, const uint32_t* __restrict__ order, int n_frames,
     const FrameDesc* __restrict__ frames, const uint2* __restrict__ ranges,
@@ -214,10 +217,10 @@ __global__ void __launch_bounds__(64) composite_fwd_kernel(
     float bg2, float* __restrict__ rgb, float* __restrict__ depth, float* __restrict__ alpha,
     float* __restrict__ t_final, int32_t* __restrict__ n_last, uint32_t* __restrict__ tile_nproc,
     unsigned long long* __restrict__ pair_count, int32_t* __restrict__ med_pos) {
-  __shared__ Record sm[kWave];
+  __shared__ Record sm[BATCH];
   const int tile = tile_of_block(blockIdx.x, n_tiles, groups, order);
   if (tile < 0) return;
-  composite_fwd_tile<TW, TH, COUNT, MEDIAN>(tile, sm, n_frames, frames, ranges, vals, rec, bg0,
+  composite_fwd_tile<TW, TH, COUNT, MEDIAN, BATCH>(tile, sm, n_frames, frames, ranges, vals, rec, bg0,
                                              bg1, bg2, rgb, depth, alpha, t_final, n_last,
                                              tile_nproc, pair_count, med_pos);
 }
@@ -267,7 +270,7 @@ __device__ __forceinline__ double wave_transpose_sum10(const double v[10], int l
   return r;
 }
 
-template <int TW, int TH, bool MEDIAN>
+template <int TW, int TH, bool MEDIAN, int BATCH>
 __device__ __forceinline__ void composite_bwd_tile(
     int tile, Record* sm, uint32_t* slot, uint32_t epoch, int n_frames,
     const FrameDesc* __restrict__ frames,
@@ -321,15 +324,18 @@ __device__ __forceinline__ void composite_bwd_tile(
     GD[k] = valid ? g_depth[fr.pixel_offset + p] : 0.0f;
     GA[k] = valid ? g_alpha[fr.pixel_offset + p] : 0.0f;
   }
-  for (int hi = (int)nproc; hi > 0; hi -= kWave) {
-    const int lo = max(0, hi - kWave);
-    if (lo + lane < hi) {
-      const uint32_t r = vals[rg.x + lo + lane];
-      const Record R = rec[r];
-      sm[lane] = R;
-      const uint2 tr = trect[r];
-      const int rx0 = tr.x & 0xffff, rx1 = tr.x >> 16, ry0 = tr.y & 0xffff;
-      slot[lane] = keyoff[r] + (uint32_t)((ty - ry0) * (rx1 - rx0 + 1) + (tx - rx0));
+  for (int hi = (int)nproc; hi > 0; hi -= BATCH) {
+    const int lo = max(0, hi - BATCH);
+#pragma unroll
+    for (int i = lane; i < BATCH; i += kWave) {
+      if (lo + i < hi) {
+        const uint32_t r = vals[rg.x + lo + i];
+        const Record R = rec[r];
+        sm[i] = R;
+        const uint2 tr = trect[r];
+        const int rx0 = tr.x & 0xffff, rx1 = tr.x >> 16, ry0 = tr.y & 0xffff;
+        slot[i] = keyoff[r] + (uint32_t)((ty - ry0) * (rx1 - rx0 + 1) + (tx - rx0));
+      }
     }
     __syncthreads();
     for (int j = hi - lo - 1; j >= 0; --j) {
@@ -426,7 +432,7 @@ __device__ __forceinline__ void composite_bwd_tile(
   }
 }
 
-template <int TW, int TH, bool MEDIAN>
+template <int TW, int TH, bool MEDIAN, int BATCH>
 __global__ void __launch_bounds__(64) composite_bwd_kernel(
     int n_tiles, int groups, const uint32_t* __restrict__ order, int n_frames,
     const FrameDesc* __restrict__ frames, const uint2* __restrict__ ranges,
@@ -438,12 +444,12 @@ __global__ void __launch_bounds__(64) composite_bwd_kernel(
     const int32_t* __restrict__ n_last, float* __restrict__ partial,
     uint32_t* __restrict__ stamp, const uint32_t* __restrict__ epoch_dev,
     const int32_t* __restrict__ med_pos) {
-  __shared__ Record sm[kWave];
-  __shared__ uint32_t slot[kWave];
+  __shared__ Record sm[BATCH];
+  __shared__ uint32_t slot[BATCH];
   const int tile = tile_of_block(blockIdx.x, n_tiles, groups, order);
   if (tile < 0) return;
   const uint32_t epoch = *epoch_dev;
-  composite_bwd_tile<TW, TH, MEDIAN>(tile, sm, slot, epoch, n_frames, frames, ranges, vals, rec,
+  composite_bwd_tile<TW, TH, MEDIAN, BATCH>(tile, sm, slot, epoch, n_frames, frames, ranges, vals, rec,
                                      trect, keyoff, tile_nproc, bg0, bg1, bg2, g_rgb, g_depth,
                                      g_alpha, t_final, n_last, partial, stamp, med_pos);
 }
@@ -466,27 +472,28 @@ void launch_tile_order(hipStream_t st, int n_tiles, int groups, const uint32_t* 
 unsigned tile_schedule_grid(int n_tiles, int groups) { return grid_of(n_tiles, groups); }
 int tile_schedule_groups(bool xcd_groups) { return xcd_groups ? kQueues : 1; }
 
-template <int TW, int TH, bool COUNT, bool MEDIAN>
+template <int TW, int TH, bool COUNT, bool MEDIAN, int BATCH>
 static void launch_fwd_v(hipStream_t st, int n_tiles, int groups, const uint32_t* order, int F,
                          const FrameDesc* frames, const uint2* ranges, const uint32_t* vals,
                          const Record* rec, const float* bg, float* rgb, float* depth,
                          float* alpha, float* t_final, int32_t* n_last, uint32_t* nproc,
                          unsigned long long* pairs, int32_t* med_pos) {
-  auto k = composite_fwd_kernel<TW, TH, COUNT, MEDIAN>;
+  auto k = composite_fwd_kernel<TW, TH, COUNT, MEDIAN, BATCH>;
   hipLaunchKernelGGL(k, dim3(grid_of(n_tiles, groups)), dim3(kWave), 0, st, n_tiles, groups,
                      order, F, frames, ranges, vals, rec, bg[0], bg[1], bg[2], rgb, depth, alpha,
                      t_final, n_last, nproc, pairs, med_pos);
 }
 
-template <int TW, int TH>
-static void launch_fwd_t(hipStream_t st, int n_tiles, int groups, const uint32_t* order, int F,
+template <int TW, int TH, int BATCH>
+static void launch_fwd_b(hipStream_t st, int n_tiles, int groups, const uint32_t* order, int F,
                          const FrameDesc* frames, const uint2* ranges, const uint32_t* vals,
                          const Record* rec, const float* bg, float* rgb, float* depth,
                          float* alpha, float* t_final, int32_t* n_last, uint32_t* nproc,
                          unsigned long long* pairs, int32_t* med_pos) {
-#define GSR_FWD_V(C, M)                                                                        \
-  launch_fwd_v<TW, TH, C, M>(st, n_tiles, groups, order, F, frames, ranges, vals, rec, bg, rgb, \
-                             depth, alpha, t_final, n_last, nproc, pairs, med_pos)
+#define GSR_FWD_V(C, M)                                                                         \
+  launch_fwd_v<TW, TH, C, M, BATCH>(st, n_tiles, groups, order, F, frames, ranges, vals, rec,    \
+                                    bg, rgb, depth, alpha, t_final, n_last, nproc, pairs,        \
+                                    med_pos)
   if (pairs) {
     if (med_pos) GSR_FWD_V(true, true); else GSR_FWD_V(true, false);
   } else {
@@ -496,20 +503,37 @@ static void launch_fwd_t(hipStream_t st, int n_tiles, int groups, const uint32_t
 }
 
 template <int TW, int TH>
-static void launch_bwd_t(hipStream_t st, int n_tiles, int groups, const uint32_t* order, int F, const FrameDesc* frames, const uint2* ranges,
-                         const uint32_t* vals, const Record* rec, const uint2* trect,
-                         const uint32_t* keyoff, const uint32_t* nproc, const float* bg,
-                         const float* g_rgb, const float* g_depth, const float* g_alpha,
-                         const float* t_final, const int32_t* n_last, float* partial,
-                         uint32_t* stamp, const uint32_t* epoch, const int32_t* med_pos) {
+static void launch_fwd_t(hipStream_t st, int batch, int n_tiles, int groups,
+                         const uint32_t* order, int F, const FrameDesc* frames,
+                         const uint2* ranges, const uint32_t* vals, const Record* rec,
+                         const float* bg, float* rgb, float* depth, float* alpha, float* t_final,
+                         int32_t* n_last, uint32_t* nproc, unsigned long long* pairs,
+                         int32_t* med_pos) {
+#define GSR_FWD_B(B)                                                                           \
+  launch_fwd_b<TW, TH, B>(st, n_tiles, groups, order, F, frames, ranges, vals, rec, bg, rgb,     \
+                          depth, alpha, t_final, n_last, nproc, pairs, med_pos)
+  if (batch == 32) GSR_FWD_B(32);
+  else if (batch == 128) GSR_FWD_B(128);
+  else GSR_FWD_B(64);
+#undef GSR_FWD_B
+}
+
+template <int TW, int TH, int BATCH>
+static void launch_bwd_b(hipStream_t st, int n_tiles, int groups, const uint32_t* order, int F,
+                         const FrameDesc* frames, const uint2* ranges, const uint32_t* vals,
+                         const Record* rec, const uint2* trect, const uint32_t* keyoff,
+                         const uint32_t* nproc, const float* bg, const float* g_rgb,
+                         const float* g_depth, const float* g_alpha, const float* t_final,
+                         const int32_t* n_last, float* partial, uint32_t* stamp,
+                         const uint32_t* epoch, const int32_t* med_pos) {
   if (med_pos) {
-    auto k = composite_bwd_kernel<TW, TH, true>;
+    auto k = composite_bwd_kernel<TW, TH, true, BATCH>;
     hipLaunchKernelGGL(k, dim3(grid_of(n_tiles, groups)), dim3(kWave), 0, st, n_tiles,
                        groups, order, F, frames, ranges, vals, rec, trect, keyoff, nproc,
                        bg[0], bg[1], bg[2], g_rgb, g_depth, g_alpha, t_final, n_last, partial,
                        stamp, epoch, med_pos);
   } else {
-    auto k = composite_bwd_kernel<TW, TH, false>;
+    auto k = composite_bwd_kernel<TW, TH, false, BATCH>;
     hipLaunchKernelGGL(k, dim3(grid_of(n_tiles, groups)), dim3(kWave), 0, st, n_tiles,
                        groups, order, F, frames, ranges, vals, rec, trect, keyoff, nproc,
                        bg[0], bg[1], bg[2], g_rgb, g_depth, g_alpha, t_final, n_last, partial,
@@ -517,12 +541,33 @@ static void launch_bwd_t(hipStream_t st, int n_tiles, int groups, const uint32_t
   }
 }
 
+template <int TW, int TH>
+static void launch_bwd_t(hipStream_t st, int batch, int n_tiles, int groups,
+                         const uint32_t* order, int F, const FrameDesc* frames,
+                         const uint2* ranges, const uint32_t* vals, const Record* rec,
+                         const uint2* trect, const uint32_t* keyoff, const uint32_t* nproc,
+                         const float* bg, const float* g_rgb, const float* g_depth,
+                         const float* g_alpha, const float* t_final, const int32_t* n_last,
+                         float* partial, uint32_t* stamp, const uint32_t* epoch,
+                         const int32_t* med_pos) {
+#define GSR_BWD_B(B)                                                                           \
+  launch_bwd_b<TW, TH, B>(st, n_tiles, groups, order, F, frames, ranges, vals, rec, trect,     \
+                          keyoff, nproc, bg, g_rgb, g_depth, g_alpha, t_final, n_last,         \
+                          partial, stamp, epoch, med_pos)
+  if (batch == 32) GSR_BWD_B(32);
+  else if (batch == 128) GSR_BWD_B(128);
+  else GSR_BWD_B(64);
+#undef GSR_BWD_B
+}
+
 bool tile_shape_supported(int tw, int th) {
   return (tw == 16 && th == 16) || (tw == 8 && th == 8) || (tw == 32 && th == 8) ||
          (tw == 16 && th == 8) || (tw == 32 && th == 16);
 }
 
-void launch_composite_fwd(hipStream_t st, int tw, int th, int n_tiles, int F,
+bool lds_batch_supported(int batch) { return batch == 32 || batch == 64 || batch == 128; }
+
+void launch_composite_fwd(hipStream_t st, int tw, int th, int batch, int n_tiles, int F,
                           const FrameDesc* frames, const uint2* ranges, const uint32_t* vals,
                           const Record* rec, const float* bg, float* rgb, float* depth,
                           float* alpha, float* t_final, int32_t* n_last, uint32_t* nproc,
@@ -532,7 +577,7 @@ void launch_composite_fwd(hipStream_t st, int tw, int th, int n_tiles, int F,
   const int groups = xcd_groups ? kQueues : 1;
   launch_order(st, n_tiles, groups, prev_nproc, order);
 #define GSR_FWD(W, H)                                                                         \
-  launch_fwd_t<W, H>(st, n_tiles, groups, order, F, frames, ranges, vals, rec, bg, rgb,         \
+  launch_fwd_t<W, H>(st, batch, n_tiles, groups, order, F, frames, ranges, vals, rec, bg, rgb,  \
                      depth, alpha, t_final, n_last, nproc, pairs, med_pos)
   if (tw == 16 && th == 16) GSR_FWD(16, 16);
   else if (tw == 8 && th == 8) GSR_FWD(8, 8);
@@ -542,7 +587,7 @@ void launch_composite_fwd(hipStream_t st, int tw, int th, int n_tiles, int F,
 #undef GSR_FWD
 }
 
-void launch_composite_bwd(hipStream_t st, int tw, int th, int n_tiles, int F,
+void launch_composite_bwd(hipStream_t st, int tw, int th, int batch, int n_tiles, int F,
                           const FrameDesc* frames, const uint2* ranges, const uint32_t* vals,
                           const Record* rec, const uint2* trect, const uint32_t* keyoff,
                           const uint32_t* nproc, const float* bg, const float* g_rgb,
@@ -554,7 +599,7 @@ void launch_composite_bwd(hipStream_t st, int tw, int th, int n_tiles, int F,
   const int groups = xcd_groups ? kQueues : 1;
   launch_order(st, n_tiles, groups, nproc, order);
 #define GSR_BWD(W, H)                                                                          \
-  launch_bwd_t<W, H>(st, n_tiles, groups, order, F, frames, ranges, vals, rec, trect,          \
+  launch_bwd_t<W, H>(st, batch, n_tiles, groups, order, F, frames, ranges, vals, rec, trect,   \
                      keyoff, nproc, bg, g_rgb, g_depth, g_alpha, t_final, n_last, partial,     \
                      stamp, epoch, med_pos)
   if (tw == 16 && th == 16) GSR_BWD(16, 16);

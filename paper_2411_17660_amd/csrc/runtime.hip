@@ -163,8 +163,9 @@ gsr_status validate(gsr_context* ctx, const gsr_settings* s, int64_t n, const fl
   if (!tile_shape_supported(s->tile_w, s->tile_h))
     return fail(ctx, GSR_ERR_UNSUPPORTED, "tile shape %dx%d not supported", s->tile_w,
                 s->tile_h);
-  if (s->lds_batch != 0 && s->lds_batch != kWave)
-    return fail(ctx, GSR_ERR_UNSUPPORTED, "lds_batch %d not supported", s->lds_batch);
+  if (s->lds_batch != 0 && !lds_batch_supported(s->lds_batch))
+    return fail(ctx, GSR_ERR_UNSUPPORTED, "lds_batch %d not supported (0, 32, 64 or 128)",
+                s->lds_batch);
   if (s->key_capacity < 0 || s->key_capacity >= ((int64_t)1 << 32))
     return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "key_capacity out of range");
   if (!cams || !poses) return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "cams/poses is NULL");
@@ -472,7 +473,8 @@ gsr_status forward_impl(gsr_context* ctx, const gsr_settings* s, int64_t n, cons
                         P<uint32_t>(ctx->nproc), have_prev ? P<uint32_t>(ctx->nproc) : nullptr,
                         P<uint32_t>(ctx->order_f), remap, count ? d_pairs : nullptr);
     else
-      launch_composite_fwd(st, tw, th, (int)T, F, P<FrameDesc>(ctx->frames),
+      launch_composite_fwd(st, tw, th, s->lds_batch ? s->lds_batch : kWave, (int)T, F,
+                           P<FrameDesc>(ctx->frames),
                            P<uint2>(ctx->ranges), svals, P<Record>(ctx->rec), s->background,
                            rgb, depth, alpha, P<float>(ctx->t_final), P<int32_t>(ctx->n_last),
                            P<uint32_t>(ctx->nproc),
@@ -660,7 +662,8 @@ gsr_status gsr_backward(gsr_context* ctx, const float* g_rgb, const float* g_dep
   // A8 reverse compositing -> per-key partials
   {
     StageTimer t(ctx, st, timing, GSR_STAGE_COMPOSITE_BWD);
-    launch_composite_bwd(st, s.tile_w, s.tile_h, (int)sv.T, sv.F, P<FrameDesc>(ctx->frames),
+    launch_composite_bwd(st, s.tile_w, s.tile_h, s.lds_batch ? s.lds_batch : kWave, (int)sv.T,
+                         sv.F, P<FrameDesc>(ctx->frames),
                          P<uint2>(ctx->ranges), svals, P<Record>(ctx->rec),
                          P<uint2>(ctx->trect), P<uint32_t>(ctx->keyoff),
                          P<uint32_t>(ctx->nproc), s.background, g_rgb,
@@ -902,24 +905,29 @@ gsr_status gsr_autotune(gsr_context* ctx, const gsr_settings* base, int64_t n, c
                         const float* target_rgb, const float* target_depth, float depth_weight,
                         int32_t reps, int32_t force, gsr_settings* chosen, float* ms_out,
                         void* stream) {
-  static const int kShapes[5][2] = {{16, 16}, {8, 8}, {32, 8}, {16, 8}, {32, 16}};
+  static const int kShapes[GSR_TUNE_TILES][2] = {{16, 16}, {8, 8}, {32, 8}, {16, 8}, {32, 16}};
+  static const int kBatches[GSR_TUNE_BATCHES] = {32, 64, 128};
+  constexpr int kConfigs = GSR_TUNE_TILES * GSR_TUNE_BATCHES;
   if (!ctx || !base || !chosen || !cams || F < 1) return GSR_ERR_INVALID_ARGUMENT;
   if (reps < 1) reps = 1;
   hipStream_t st = (hipStream_t)stream;
   GSR_HIP(hipSetDevice(ctx->device));
-  // cache key: frame sizes, n rounded up to a power of two, SH degree
+  // cache key: the multiset of frame sizes, n rounded up to a power of two,
+  // SH degree
+  std::vector<std::pair<int, int>> sizes;
+  for (int f = 0; f < F; ++f) sizes.push_back({cams[f].width, cams[f].height});
+  std::sort(sizes.begin(), sizes.end());
   std::string key = "d" + std::to_string(base->sh_degree) + ":n";
   int64_t nb = 1;
   while (nb < n) nb <<= 1;
   key += std::to_string(nb);
-  for (int f = 0; f < F; ++f)
-    key += ":" + std::to_string(cams[f].width) + "x" + std::to_string(cams[f].height);
+  for (const auto& wh : sizes) key += ":" + std::to_string(wh.first) + "x" + std::to_string(wh.second);
   if (!force) {
     auto it = ctx->tune_cache.find(key);
     if (it != ctx->tune_cache.end()) {
       *chosen = it->second;
       if (ms_out)
-        for (int i = 0; i < 5; ++i) ms_out[i] = -1.0f;
+        for (int i = 0; i < kConfigs; ++i) ms_out[i] = -1.0f;
       return GSR_OK;
     }
   }
@@ -939,35 +947,40 @@ gsr_status gsr_autotune(gsr_context* ctx, const gsr_settings* base, int64_t n, c
   GSR_HIP(hipEventCreate(&e1));
   float best = 1e30f;
   gsr_settings best_s = *base;
-  for (int i = 0; i < 5; ++i) {
+  for (int i = 0; i < GSR_TUNE_TILES && !rc; ++i) {
     gsr_settings s = *base;
     s.tile_w = kShapes[i][0];
     s.tile_h = kShapes[i][1];
+    s.lds_batch = kWave;
     s.key_capacity = 0;
     s.flags &= ~(uint32_t)(GSR_FLAG_TIMING | GSR_FLAG_COUNT_PAIRS);
+    // one sizing run per tile shape (the keys do not depend on the batch)
     rc = gsr_step_l1(ctx, &s, n, means, log_scales, quats, opac, sh, F, cams, poses, target_rgb,
                      target_depth, depth_weight, rgb, depth, alpha, loss, gm, gl, gq, go, gsh, gt,
                      stream);
     if (rc) break;
     s.key_capacity = (int64_t)(ctx->s.K + ctx->s.K / 20 + 1024);
-    std::vector<float> t(reps);
-    for (int r = 0; r < reps && !rc; ++r) {
-      GSR_HIP(hipEventRecord(e0, st));
-      rc = gsr_step_l1(ctx, &s, n, means, log_scales, quats, opac, sh, F, cams, poses,
-                       target_rgb, target_depth, depth_weight, rgb, depth, alpha, loss, gm, gl,
-                       gq, go, gsh, gt, stream);
-      GSR_HIP(hipEventRecord(e1, st));
-      GSR_HIP(hipEventSynchronize(e1));
-      GSR_HIP(hipEventElapsedTime(&t[r], e0, e1));
-    }
-    if (rc) break;
-    if ((rc = gsr_check_overflow(ctx, stream))) break;
-    std::sort(t.begin(), t.end());
-    const float med = t[reps / 2];
-    if (ms_out) ms_out[i] = med;
-    if (med < best) {
-      best = med;
-      best_s = s;
+    for (int j = 0; j < GSR_TUNE_BATCHES && !rc; ++j) {
+      s.lds_batch = kBatches[j];
+      std::vector<float> t(reps);
+      for (int r = 0; r < reps && !rc; ++r) {
+        GSR_HIP(hipEventRecord(e0, st));
+        rc = gsr_step_l1(ctx, &s, n, means, log_scales, quats, opac, sh, F, cams, poses,
+                         target_rgb, target_depth, depth_weight, rgb, depth, alpha, loss, gm, gl,
+                         gq, go, gsh, gt, stream);
+        GSR_HIP(hipEventRecord(e1, st));
+        GSR_HIP(hipEventSynchronize(e1));
+        GSR_HIP(hipEventElapsedTime(&t[r], e0, e1));
+      }
+      if (rc) break;
+      if ((rc = gsr_check_overflow(ctx, stream))) break;
+      std::sort(t.begin(), t.end());
+      const float med = t[reps / 2];
+      if (ms_out) ms_out[i * GSR_TUNE_BATCHES + j] = med;
+      if (med < best) {
+        best = med;
+        best_s = s;
+      }
     }
   }
   (void)hipEventDestroy(e0);

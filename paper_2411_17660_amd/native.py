@@ -29,6 +29,7 @@ EXPORTS = ["gsr_create", "gsr_destroy", "gsr_last_error", "gsr_forward", "gsr_fo
            "gsr_autotune",
            "gsr_adam_step"]
 TILE_SHAPES = [(16, 16), (8, 8), (32, 8), (16, 8), (32, 16)]
+LDS_BATCHES = [32, 64, 128]
 
 
 class Camera(C.Structure):

@@ -59,7 +59,7 @@ class Rasterizer:
 
     def forward(self, means, log_scales, quats, opacity, sh, poses, cams, sh_degree,
                 background=(0.0, 0.0, 0.0), tile=(16, 16), key_capacity=0, xcd_remap=True,
-                out=None, timing=False, count_pairs=False, median=False):
+                out=None, timing=False, count_pairs=False, median=False, lds_batch=0):
         """Renders F frames; returns packed (rgb [sum 3HW], depth [sum HW],
         alpha [sum HW]) float32 device tensors."""
         F = len(cams)
@@ -72,8 +72,8 @@ class Rasterizer:
         else:
             rgb, depth, alpha = out
         self.settings = native.make_settings(sh_degree, background, tile, key_capacity,
-                                             xcd_remap, timing=timing, count_pairs=count_pairs,
-                                             median=median)
+                                             xcd_remap, lds_batch=lds_batch, timing=timing,
+                                             count_pairs=count_pairs, median=median)
         self.cams = native.make_cameras(cams)
         n = int(means.shape[0])
         self.generation += 1
@@ -198,11 +198,12 @@ class Rasterizer:
     def step_render(self, means, log_scales, quats, opacity, sh, poses, cams, sh_degree,
                     target_rgb, target_depth, bufs, lambda1=0.9, lambda2=0.2,
                     background=(0.0, 0.0, 0.0), tile=(16, 16), key_capacity=0, xcd_remap=True,
-                    timing=False, median=False):
+                    timing=False, median=False, lds_batch=0):
         """Forward + full rendering loss + backward in one call into
         preallocated `bufs` (as for step_l1, plus an optional `ssim` [F])."""
         self.settings = native.make_settings(sh_degree, background, tile, key_capacity,
-                                             xcd_remap, timing=timing, median=median)
+                                             xcd_remap, lds_batch=lds_batch, timing=timing,
+                                             median=median)
         self.cams = native.make_cameras(cams)
         n = int(means.shape[0])
         b = bufs
@@ -239,11 +240,13 @@ class Rasterizer:
 
     def step_l1(self, means, log_scales, quats, opacity, sh, poses, cams, sh_degree,
                 target_rgb, target_depth, depth_weight, bufs, background=(0.0, 0.0, 0.0),
-                tile=(16, 16), key_capacity=0, xcd_remap=True, timing=False, median=False):
+                tile=(16, 16), key_capacity=0, xcd_remap=True, timing=False, median=False,
+                lds_batch=0):
         """Forward + L1 loss + backward in one call into preallocated `bufs`
         (dict with rgb, depth, alpha, loss and the gradient tensors)."""
         self.settings = native.make_settings(sh_degree, background, tile, key_capacity,
-                                             xcd_remap, timing=timing, median=median)
+                                             xcd_remap, lds_batch=lds_batch, timing=timing,
+                                             median=median)
         self.cams = native.make_cameras(cams)
         n = int(means.shape[0])
         b = bufs
@@ -261,11 +264,12 @@ class Rasterizer:
     def autotune(self, means, log_scales, quats, opacity, sh, poses, cams, sh_degree,
                  target_rgb, target_depth, depth_weight, background=(0.0, 0.0, 0.0), reps=3,
                  force=False):
-        """Measure every tile shape on these inputs; returns (tile, key_capacity,
-        {tile: median ms})."""
+        """Measure every tile shape with every LDS batch on these inputs;
+        returns (tile, lds_batch, key_capacity, {(tile, batch): median ms})."""
         base = native.make_settings(sh_degree, background)
         chosen = native.Settings()
-        ms = (C.c_float * len(native.TILE_SHAPES))()
+        nt, nbt = len(native.TILE_SHAPES), len(native.LDS_BATCHES)
+        ms = (C.c_float * (nt * nbt))()
         cams_c = native.make_cameras(cams)
         self.generation += 1
         self._check(self.lib.gsr_autotune(
@@ -273,8 +277,9 @@ class Rasterizer:
             _ptr(quats), _ptr(opacity), _ptr(sh), len(cams), cams_c, _ptr(poses),
             _ptr(target_rgb), _ptr(target_depth), float(depth_weight), int(reps), int(force),
             C.byref(chosen), ms, _stream()))
-        times = {t: ms[i] for i, t in enumerate(native.TILE_SHAPES)}
-        return (chosen.tile_w, chosen.tile_h), chosen.key_capacity, times
+        times = {(t, b): ms[i * nbt + j] for i, t in enumerate(native.TILE_SHAPES)
+                 for j, b in enumerate(native.LDS_BATCHES)}
+        return (chosen.tile_w, chosen.tile_h), chosen.lds_batch, chosen.key_capacity, times
 
     def adam_step(self, params, grads, state, lr_means=1.6e-4, lr_sh=5e-3, lr_pose=1e-3,
                   beta1=0.9, beta2=0.999, eps=1e-15):

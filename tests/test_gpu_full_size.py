@@ -34,12 +34,13 @@ def test_c4_uneven_autotuned_batch_sampled_frames(rast):
     P = sc.n_pixels
     d = to_dev(sc)
     zeros3, zeros1 = torch.zeros(3 * P, device="cuda"), torch.zeros(P, device="cuda")
-    tile, cap, times = rast.autotune(d["means"], d["log_scales"], d["quats"], d["opacity"],
-                                     d["sh"], d["poses"], sc.cams, sc.sh_degree, zeros3, zeros1,
-                                     1.0, background=sc.background, reps=2, force=True)
-    print(f"[c4] autotune {times} -> {tile}, capacity {cap}", flush=True)
+    tile, batch, cap, times = rast.autotune(d["means"], d["log_scales"], d["quats"],
+                                            d["opacity"], d["sh"], d["poses"], sc.cams,
+                                            sc.sh_degree, zeros3, zeros1, 1.0,
+                                            background=sc.background, reps=2, force=True)
+    print(f"[c4] autotune {times} -> {tile} x {batch}, capacity {cap}", flush=True)
     G = scenes.upstream(4, sc)
-    _, rgb, dep, alp = gpu_forward(rast, sc, tile, key_capacity=cap)
+    _, rgb, dep, alp = gpu_forward(rast, sc, tile, key_capacity=cap, lds_batch=batch)
     rast.check_overflow()
     K = rast.stats()["n_keys"]
     print(f"[c4] K = {K} keys over {sc.n_frames} frames", flush=True)

@@ -113,6 +113,31 @@ def test_tile_shapes_lists_and_bitwise_images(rast, tile):
     check_backward(rast, sc, ref, flags, 7, label=f"tile{tile}")
 
 
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 16)])
+def test_lds_batch_bitwise_invariance(rast, tile):
+    """Every LDS batch (Gaussians staged per round: 32, 64, 128) gives the
+    same images, per-pixel stop positions and gradients bit for bit: the
+    batch only changes how entries are staged, never the order in which a
+    pixel composites them.  The 64-batch result is itself checked against the
+    oracle by the other tests."""
+    import torch
+    sc = scenes.tiny_scene(seed=17, n=3000, W=150, H=110, f=110.0, n_frames=2, ls_mean=-2.2)
+    G = scenes.upstream(17, sc)
+    ref = None
+    for batch in (64, 32, 128):
+        _, rgb, dep, alp = gpu_forward(rast, sc, tile, lds_batch=batch)
+        lists = rast.debug_lists()
+        g = gpu_backward(rast, G)
+        cur = dict(rgb=rgb.cpu().numpy(), depth=dep.cpu().numpy(), alpha=alp.cpu().numpy(),
+                   n_last=lists["n_last"], t_final=lists["t_final"], **g)
+        if ref is None:
+            ref = cur
+            continue
+        for k, v in ref.items():
+            assert np.array_equal(v, cur[k]), (tile, batch, k)
+    torch.cuda.synchronize()
+
+
 def test_c1_full(rast):
     sc = scenes.scene_c1()
     ref, _, flags = check_forward(rast, sc, label="c1")
@@ -384,18 +409,21 @@ def test_autotuner_picks_a_measured_shape_with_identical_images(rast):
     rng = np.random.default_rng(13)
     t_rgb = torch.from_numpy(rng.uniform(0, 1, 3 * P).astype(np.float32)).cuda()
     t_dep = torch.from_numpy(rng.uniform(0.5, 4, P).astype(np.float32)).cuda()
-    tile, cap, times = rast.autotune(d["means"], d["log_scales"], d["quats"], d["opacity"],
-                                     d["sh"], d["poses"], sc.cams, sc.sh_degree, t_rgb, t_dep,
-                                     0.5, background=sc.background, reps=2, force=True)
-    assert tile in native.TILE_SHAPES and cap > 0
+    tile, batch, cap, times = rast.autotune(d["means"], d["log_scales"], d["quats"],
+                                            d["opacity"], d["sh"], d["poses"], sc.cams,
+                                            sc.sh_degree, t_rgb, t_dep, 0.5,
+                                            background=sc.background, reps=2, force=True)
+    assert tile in native.TILE_SHAPES and batch in native.LDS_BATCHES and cap > 0
+    assert len(times) == len(native.TILE_SHAPES) * len(native.LDS_BATCHES)
     assert all(t > 0 for t in times.values())
-    assert times[tile] == min(times.values())
-    tile2, _, times2 = rast.autotune(d["means"], d["log_scales"], d["quats"], d["opacity"],
-                                     d["sh"], d["poses"], sc.cams, sc.sh_degree, t_rgb, t_dep,
-                                     0.5, background=sc.background)
-    assert tile2 == tile and all(t < 0 for t in times2.values())  # cached
+    assert times[(tile, batch)] == min(times.values())
+    tile2, batch2, _, times2 = rast.autotune(d["means"], d["log_scales"], d["quats"],
+                                             d["opacity"], d["sh"], d["poses"], sc.cams,
+                                             sc.sh_degree, t_rgb, t_dep, 0.5,
+                                             background=sc.background)
+    assert (tile2, batch2) == (tile, batch) and all(t < 0 for t in times2.values())  # cached
     _, a16, _, _ = gpu_forward(rast, sc, (16, 16))
-    _, at, _, _ = gpu_forward(rast, sc, tile, key_capacity=cap)
+    _, at, _, _ = gpu_forward(rast, sc, tile, key_capacity=cap, lds_batch=batch)
     rast.check_overflow()
     assert np.array_equal(a16.cpu().numpy(), at.cpu().numpy())
 

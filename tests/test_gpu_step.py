@@ -49,11 +49,12 @@ def _sizes(sc):
     return [(int(c[0]), int(c[1])) for c in sc.cams]
 
 
-def _separate(rast, d, sc, trgb, tdep, wd, tile):
+def _separate(rast, d, sc, trgb, tdep, wd, tile, batch=0):
     """gsr_forward (grown key buffers) + gsr_loss_l1 + gsr_backward."""
     import torch
     rgb, dep, alp = rast.forward(d["means"], d["log_scales"], d["quats"], d["opacity"], d["sh"],
-                                 d["poses"], sc.cams, sc.sh_degree, sc.background, tile=tile)
+                                 d["poses"], sc.cams, sc.sh_degree, sc.background, tile=tile,
+                                 lds_batch=batch)
     lo = rast.loss_l1(trgb, tdep, wd)
     g = rast.backward(lo["g_rgb"], lo["g_depth"], lo["g_alpha"])
     torch.cuda.synchronize()
@@ -150,16 +151,17 @@ def test_benchmarked_step_c3():
     trgb, tdep = torch.from_numpy(t_rgb).cuda(), torch.from_numpy(t_dep).cuda()
     wd = 1.0
     print("[step] c3: autotune", flush=True)
-    tile, cap, times = rast.autotune(d["means"], d["log_scales"], d["quats"], d["opacity"],
-                                     d["sh"], d["poses"], sc.cams, 3, trgb, tdep, wd,
-                                     background=sc.background, reps=1, force=True)
-    print(f"[step] c3: tile {tile} capacity {cap} times {times}", flush=True)
+    tile, batch, cap, times = rast.autotune(d["means"], d["log_scales"], d["quats"],
+                                            d["opacity"], d["sh"], d["poses"], sc.cams, 3, trgb,
+                                            tdep, wd, background=sc.background, reps=1,
+                                            force=True)
+    print(f"[step] c3: tile {tile} batch {batch} capacity {cap} times {times}", flush=True)
     b = _bufs(sc)
 
     def step():
         rast.step_l1(d["means"], d["log_scales"], d["quats"], d["opacity"], d["sh"], d["poses"],
                      sc.cams, 3, trgb, tdep, wd, b, background=sc.background, tile=tile,
-                     key_capacity=cap)
+                     key_capacity=cap, lds_batch=batch)
     step()
     torch.cuda.synchronize()
     side = torch.cuda.Stream()
@@ -183,7 +185,7 @@ def test_benchmarked_step_c3():
     del g
     _bitwise(replays[0], replays[1], "c3 replays")
     print("[step] c3: separate calls with grown key buffers", flush=True)
-    sep, lo = _separate(rast, d, sc, trgb, tdep, wd, tile)
+    sep, lo = _separate(rast, d, sc, trgb, tdep, wd, tile, batch)
     _bitwise(replays[1], sep, "c3")
     print("[step] c3: replayed step bitwise equal to forward + loss + backward", flush=True)
     _check_against_oracle(rast, sc, d, sep, lo, t_rgb, t_dep, wd, tile, "c3")

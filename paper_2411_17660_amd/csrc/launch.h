@@ -17,8 +17,8 @@ int64_t preprocess_bwd_waves(int64_t n);
 void launch_preprocess_bwd(hipStream_t st, int64_t n, int F, const FrameDesc* frames,
                            const float* poses, const float* means, const float* log_scales,
                            const float* quats, const float* opac, const float* sh, int deg,
-                           const uint32_t* order, const uint32_t* keyoff,
-                           const uint32_t* ntiles, const float* partial,
+                           const uint32_t* order, const uint32_t* first_wide,
+                           const uint32_t* keyoff, const uint32_t* ntiles, const float* partial,
                            const uint32_t* stamp, const uint32_t* epoch, uint64_t key_capacity,
                            double* grad2d, float* g_means, float* g_log_scales, float* g_quats,
                            float* g_opac, float* g_sh, double* twist_partial, float* g_twist);
@@ -34,6 +34,11 @@ void launch_cull_stats(hipStream_t st, uint64_t m, const uint32_t* ntiles, int64
                        unsigned long long* out);
 void launch_size_class(hipStream_t st, uint64_t m, const uint32_t* ntiles, uint32_t* cls,
                        uint32_t* idx);
+// *first_wide = the first position of the ascending sorted classes whose
+// record has 128 or more slots (m if none); the 3D backward reduces those
+// records a wave each
+void launch_wide_boundary(hipStream_t st, uint64_t m, const uint32_t* sorted_cls,
+                          uint32_t* first_wide);
 
 // sort.hip: depth sort, offsets, tile keys and their sort, ranges.
 // radix_hist_elems / radix_scan_elems: u32 workspace of a sort of up to

@@ -255,16 +255,39 @@ __global__ void __launch_bounds__(256) preprocess_fwd_kernel(
 }
 
 // --------------------------------------------------------------------------
-// A9: per-record reduction of the key partials.  A group of 8 lanes owns one
+// A9: per-record reduction of the key partials.  A group of 4 lanes owns one
 // record and strides over its contiguous key slots (coalesced stamp and
-// partial reads); slots not stamped with this backward's epoch belong to
+// partial reads), 16 slots per round with all of a lane's loads of a round in
+// flight together; slots not stamped with this backward's epoch belong to
 // keys behind every pixel's stop and are skipped.  Lane sums are FP64 and the
 // group combines them with a fixed butterfly, so the result is deterministic.
 // The records are visited in order of their key count (a one-pass radix sort
-// by floor(log2(count)), `order`): a wave's eight records then have similar
-// counts, instead of waiting on the one Gaussian in eight that covers
-// hundreds of tiles.
+// by floor(log2(count)), `order`), largest first: a wave's records then
+// have similar counts, instead of waiting on the one Gaussian among them that
+// covers hundreds of tiles, and the longest waves start first instead of
+// running alone at the end; records with kWideSlots or more slots get a whole
+// wave each.
 // --------------------------------------------------------------------------
+// Records with at least kWideSlots key slots are reduced by a whole wave each
+// (slot_reduce_wide_kernel), the others by groups of kSlotGroup lanes.
+constexpr uint32_t kWideSlots = 128;
+constexpr uint64_t kWideWaves = 8192;  // the wide pass's grid (32 waves per CU)
+
+// The class of kWideSlots slots: records of this class or above are wide.
+constexpr uint32_t kWideClass = 8;  // 1 + log2(kWideSlots)
+static_assert((1u << (kWideClass - 1)) == kWideSlots, "wide class");
+
+// *first_wide (pre-filled with m) = the first position of the ascending
+// class keys with class >= kWideClass: the one position where the class
+// crosses it is written by its own thread.
+__global__ void __launch_bounds__(256) wide_boundary_kernel(uint64_t m,
+                                                            const uint32_t* __restrict__ cls,
+                                                            uint32_t* __restrict__ first_wide) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  if (cls[i] >= kWideClass && (i == 0 || cls[i - 1] < kWideClass)) *first_wide = (uint32_t)i;
+}
+
 __global__ void __launch_bounds__(256) size_class_kernel(uint64_t m,
                                                          const uint32_t* __restrict__ ntiles,
                                                          uint32_t* __restrict__ cls,
@@ -276,31 +299,125 @@ __global__ void __launch_bounds__(256) size_class_kernel(uint64_t m,
   idx[r] = (uint32_t)r;
 }
 
-constexpr int kSlotGroup = 8;
+constexpr int kSlotGroup = 4;
+constexpr int kSlotUnroll = 4;
+static_assert(kNG % 2 == 0, "partials are read as float pairs");
 
+// The wide pass takes the w-th largest records, w < n_wide = m - *first_wide
+// (capped at wide_max), a wave each in turn (grid stride); 64 lanes stride
+// over a record's slots, kSlotUnroll per lane per round.
+__global__ void __launch_bounds__(256) slot_reduce_wide_kernel(
+    uint64_t m, const uint32_t* __restrict__ order, const uint32_t* __restrict__ keyoff,
+    const uint32_t* __restrict__ ntiles, const float* __restrict__ partial,
+    const uint32_t* __restrict__ stamp, const uint32_t* __restrict__ epoch_dev,
+    uint64_t key_capacity, const uint32_t* __restrict__ first_wide, uint64_t wide_max,
+    double* __restrict__ grad2d) {
+  const uint64_t n_wide = min(m - *first_wide, wide_max);
+  const uint64_t stride = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+  const uint32_t epoch = *epoch_dev;
+  const int lane = threadIdx.x & (kWave - 1);
+  for (uint64_t w = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; w < n_wide;
+       w += stride) {  // uniform per wave
+  const uint64_t r = order[m - 1 - w];
+  uint32_t cnt = ntiles[r];
+  const uint32_t off = keyoff[r];
+  if ((uint64_t)off + cnt > key_capacity) cnt = 0;  // overflowed the key capacity
+  double acc[kNG];
+#pragma unroll
+  for (int j = 0; j < kNG; ++j) acc[j] = 0.0;
+  for (uint32_t s0 = 0; s0 < cnt; s0 += kWave * kSlotUnroll) {
+    uint32_t st[kSlotUnroll];
+#pragma unroll
+    for (int u = 0; u < kSlotUnroll; ++u) {
+      const uint32_t s = s0 + lane + u * kWave;
+      st[u] = s < cnt ? stamp[off + s] : 0u;
+    }
+    float2 v[kSlotUnroll][kNG / 2];
+#pragma unroll
+    for (int u = 0; u < kSlotUnroll; ++u) {
+#pragma unroll
+      for (int j = 0; j < kNG / 2; ++j) v[u][j] = make_float2(0.0f, 0.0f);
+      const uint32_t s = s0 + lane + u * kWave;
+      if (s < cnt && st[u] == epoch) {
+        const float2* pp = reinterpret_cast<const float2*>(partial + (size_t)(off + s) * kNG);
+#pragma unroll
+        for (int j = 0; j < kNG / 2; ++j) v[u][j] = pp[j];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kSlotUnroll; ++u)
+#pragma unroll
+      for (int j = 0; j < kNG / 2; ++j) {
+        acc[2 * j] += v[u][j].x;
+        acc[2 * j + 1] += v[u][j].y;
+      }
+  }
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1)
+#pragma unroll
+    for (int j = 0; j < kNG; ++j) acc[j] += __shfl_xor(acc[j], o, kWave);
+  double v = acc[0];
+#pragma unroll
+  for (int j = 1; j < kNG; ++j) v = lane == j ? acc[j] : v;
+  if (lane < kNG) grad2d[r * kNG + lane] = v;
+  }
+}
+
+// Group k (4 lanes) takes the k-th largest record after the ones the wide
+// pass took.
 __global__ void __launch_bounds__(256) slot_reduce_kernel(
     uint64_t m, const uint32_t* __restrict__ order, const uint32_t* __restrict__ keyoff,
     const uint32_t* __restrict__ ntiles,
     const float* __restrict__ partial, const uint32_t* __restrict__ stamp,
     const uint32_t* __restrict__ epoch_dev, uint64_t key_capacity,
+    const uint32_t* __restrict__ first_wide, uint64_t wide_max,
     double* __restrict__ grad2d /* [m][kNG] */) {
   const uint32_t epoch = *epoch_dev;
   const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t k = gid / kSlotGroup;
+  const uint64_t k = gid / kSlotGroup + min(m - *first_wide, wide_max);
   const int sub = threadIdx.x & (kSlotGroup - 1);
+  // `order` ascends in key count: walk it from the end, so that the records
+  // with the most slots (a wave of them runs longest) start first and the
+  // small ones fill in around them
   const bool active = k < m;
-  const uint64_t r = active ? order[k] : 0;
+  const uint64_t r = active ? order[m - 1 - k] : 0;
   uint32_t cnt = active ? ntiles[r] : 0u;
   const uint32_t off = cnt ? keyoff[r] : 0u;
   if (cnt && (uint64_t)off + cnt > key_capacity) cnt = 0;  // overflowed the key capacity
   double acc[kNG];
 #pragma unroll
   for (int j = 0; j < kNG; ++j) acc[j] = 0.0;
-  for (uint32_t s = sub; s < cnt; s += kSlotGroup) {
-    if (stamp[off + s] != epoch) continue;
-    const float* pp = partial + (size_t)(off + s) * kNG;
+  // kSlotUnroll slots per lane per round: all their stamps are loaded at
+  // once, then the partials of the stamped ones (independent loads, all in
+  // flight), then they are added in slot order
+  for (uint32_t s0 = 0; s0 < cnt; s0 += kSlotGroup * kSlotUnroll) {
+    uint32_t st[kSlotUnroll];
 #pragma unroll
-    for (int j = 0; j < kNG; ++j) acc[j] += pp[j];
+    for (int u = 0; u < kSlotUnroll; ++u) {
+      const uint32_t s = s0 + sub + u * kSlotGroup;
+      st[u] = s < cnt ? stamp[off + s] : 0u;
+    }
+    float2 v[kSlotUnroll][kNG / 2];
+#pragma unroll
+    for (int u = 0; u < kSlotUnroll; ++u) {
+#pragma unroll
+      for (int j = 0; j < kNG / 2; ++j) v[u][j] = make_float2(0.0f, 0.0f);
+      const uint32_t s = s0 + sub + u * kSlotGroup;
+      // 40-byte partials are 8-byte aligned: five 8-byte loads, issued only
+      // by the lanes whose slot is stamped
+      if (s < cnt && st[u] == epoch) {
+        const float2* pp = reinterpret_cast<const float2*>(partial + (size_t)(off + s) * kNG);
+#pragma unroll
+        for (int j = 0; j < kNG / 2; ++j) v[u][j] = pp[j];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kSlotUnroll; ++u)
+#pragma unroll
+      for (int j = 0; j < kNG / 2; ++j) {
+        acc[2 * j] += v[u][j].x;
+        acc[2 * j + 1] += v[u][j].y;
+      }
   }
 #pragma unroll
   for (int o = kSlotGroup / 2; o > 0; o >>= 1)
@@ -311,17 +428,17 @@ __global__ void __launch_bounds__(256) slot_reduce_kernel(
     for (int j = sub; j < kNG; j += kSlotGroup) grad2d[r * kNG + j] = 0.0;
     return;
   }
-  double v = acc[0];
+  // lane sub writes values sub, sub + kSlotGroup, ...
 #pragma unroll
-  for (int j = 1; j < kNG; ++j) v = sub == j ? acc[j] : v;
-  if (sub < kNG) grad2d[r * kNG + sub] = v;
-  if (sub + kSlotGroup < kNG) {  // values 8, 9
-    double v2 = acc[kSlotGroup];
+  for (int j0 = 0; j0 < kNG; j0 += kSlotGroup) {
+    double v = acc[j0];
 #pragma unroll
-    for (int j = kSlotGroup + 1; j < kNG; ++j) v2 = sub + kSlotGroup == j ? acc[j] : v2;
-    grad2d[r * kNG + sub + kSlotGroup] = v2;
+    for (int t = 1; t < kSlotGroup; ++t)
+      if (j0 + t < kNG) v = sub == t ? acc[j0 + t] : v;
+    if (j0 + sub < kNG) grad2d[r * kNG + j0 + sub] = v;
   }
 }
+
 
 // --------------------------------------------------------------------------
 // A10: chain rule to the parameters; per (Gaussian, frame) twist partials
@@ -570,6 +687,14 @@ void launch_size_class(hipStream_t st, uint64_t m, const uint32_t* ntiles, uint3
                      ntiles, cls, idx);
 }
 
+void launch_wide_boundary(hipStream_t st, uint64_t m, const uint32_t* sorted_cls,
+                          uint32_t* first_wide) {
+  launch_fill_u32(st, first_wide, 1, (uint32_t)m);
+  if (m == 0) return;
+  hipLaunchKernelGGL(wide_boundary_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st,
+                     m, sorted_cls, first_wide);
+}
+
 void launch_bump_epoch(hipStream_t st, uint32_t* epoch) {
   hipLaunchKernelGGL(bump_epoch_kernel, dim3(1), dim3(1), 0, st, epoch);
 }
@@ -629,8 +754,8 @@ int64_t preprocess_bwd_waves(int64_t n) { return ((n + 255) / 256) * 4; }
 void launch_preprocess_bwd(hipStream_t st, int64_t n, int F, const FrameDesc* frames,
                            const float* poses, const float* means, const float* log_scales,
                            const float* quats, const float* opac, const float* sh, int deg,
-                           const uint32_t* order, const uint32_t* keyoff,
-                           const uint32_t* ntiles, const float* partial,
+                           const uint32_t* order, const uint32_t* first_wide,
+                           const uint32_t* keyoff, const uint32_t* ntiles, const float* partial,
                            const uint32_t* stamp, const uint32_t* epoch, uint64_t key_capacity,
                            double* grad2d, float* g_means, float* g_log_scales, float* g_quats,
                            float* g_opac, float* g_sh, double* twist_partial, float* g_twist) {
@@ -641,9 +766,20 @@ void launch_preprocess_bwd(hipStream_t st, int64_t n, int F, const FrameDesc* fr
                      g_log_scales, g_quats, g_opac, g_sh, twist_partial)
   if (n > 0) {
     const uint64_t m = (uint64_t)n * F;
+    // wide records come first in the largest-first order and there are at
+    // most K / kWideSlots of them; the wide grid covers the first
+    // min(m, capacity / kWideSlots + 1) (all of them unless the keys
+    // overflow the capacity), the group pass every record after those
+    const uint64_t wide_max = std::min<uint64_t>(m, key_capacity / kWideSlots + 1);
+    // a fixed grid of kWideWaves waves strides over the wide records
+    const uint64_t wide_waves = std::min<uint64_t>(wide_max, kWideWaves);
+    hipLaunchKernelGGL(slot_reduce_wide_kernel, dim3((unsigned)((wide_waves + 3) / 4)),
+                       dim3(256), 0, st, m, order, keyoff, ntiles, partial, stamp, epoch,
+                       key_capacity, first_wide, wide_max, grad2d);
     const uint64_t threads = m * kSlotGroup;
     hipLaunchKernelGGL(slot_reduce_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0,
-                       st, m, order, keyoff, ntiles, partial, stamp, epoch, key_capacity, grad2d);
+                       st, m, order, keyoff, ntiles, partial, stamp, epoch, key_capacity,
+                       first_wide, wide_max, grad2d);
     switch (deg) {
       case 0: GSR_PRE_BWD(0); break;
       case 1: GSR_PRE_BWD(1); break;

@@ -686,6 +686,7 @@ gsr_status gsr_backward(gsr_context* ctx, const float* g_rgb, const float* g_dep
   {
     StageTimer t(ctx, st, timing, GSR_STAGE_PREPROCESS_BWD);
     bool cls_in_b = false;
+    uint32_t* first_wide = (uint32_t*)(P<uint64_t>(ctx->counters) + 6);
     if (M > 0) {
       launch_size_class(st, M, P<uint32_t>(ctx->ntiles), P<uint32_t>(ctx->cls_a),
                         P<uint32_t>(ctx->clsv_a));
@@ -693,9 +694,10 @@ gsr_status gsr_backward(gsr_context* ctx, const float* g_rgb, const float* g_dep
                                    P<uint32_t>(ctx->cls_b), P<uint32_t>(ctx->clsv_b), nullptr, M,
                                    8, P<uint32_t>(ctx->hist), P<uint32_t>(ctx->scan_tmp));
     }
+    launch_wide_boundary(st, M, P<uint32_t>(cls_in_b ? ctx->cls_b : ctx->cls_a), first_wide);
     launch_preprocess_bwd(st, sv.n, sv.F, P<FrameDesc>(ctx->frames), sv.poses, sv.means,
                           sv.log_scales, sv.quats, sv.opac, sv.sh, s.sh_degree,
-                          P<uint32_t>(cls_in_b ? ctx->clsv_b : ctx->clsv_a),
+                          P<uint32_t>(cls_in_b ? ctx->clsv_b : ctx->clsv_a), first_wide,
                           P<uint32_t>(ctx->keyoff), P<uint32_t>(ctx->ntiles), P<float>(ctx->partial),
                           P<uint32_t>(ctx->stamp), d_epoch, ctx->key_cap,
                           P<double>(ctx->grad2d), g_means, g_log_scales, g_quats, g_opac, g_sh,

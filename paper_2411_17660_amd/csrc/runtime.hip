@@ -38,6 +38,7 @@ struct Saved {
   uint64_t K = 0;          // exact count (grow mode) or capacity bound (fixed mode)
   bool k_known = false;
   bool sorted_in_b = false;   // tile sort result buffer
+  bool keys16 = false;        // tile keys stored as 16 bits
   bool recs_in_b = false;     // depth sort result buffer
   bool surfel = false;        // the forward rendered 2D surfels
   bool has_backward = false;  // a backward of this forward has filled grad2d
@@ -439,7 +440,7 @@ gsr_status forward_impl(gsr_context* ctx, const gsr_settings* s, int64_t n, cons
     StageTimer t(ctx, st, timing, GSR_STAGE_KEYGEN);
     launch_keygen(st, M, (uint64_t)n, perm, P<uint32_t>(ctx->cnt_sorted),
                   P<uint64_t>(ctx->offsets), P<uint32_t>(ctx->keyoff), P<uint2>(ctx->trect),
-                  P<FrameDesc>(ctx->frames), use_cap, P<uint32_t>(ctx->keys_a),
+                  P<FrameDesc>(ctx->frames), use_cap, tile_bits, ctx->keys_a.p,
                   P<uint32_t>(ctx->vals_a), d_overflow);
   }
   // A4 stable sort by tile id
@@ -447,17 +448,17 @@ gsr_status forward_impl(gsr_context* ctx, const gsr_settings* s, int64_t n, cons
   bool keys_in_b = false;
   {
     StageTimer t(ctx, st, timing, GSR_STAGE_TILE_SORT);
-    keys_in_b = launch_tile_sort(st, P<uint32_t>(ctx->keys_a), P<uint32_t>(ctx->vals_a),
-                                 P<uint32_t>(ctx->keys_b), P<uint32_t>(ctx->vals_b),
-                                 k_known ? nullptr : d_count, sort_n, tile_bits,
-                                 P<uint32_t>(ctx->hist), P<uint32_t>(ctx->scan_tmp));
+    keys_in_b = launch_tile_sort(st, ctx->keys_a.p, P<uint32_t>(ctx->vals_a), ctx->keys_b.p,
+                                 P<uint32_t>(ctx->vals_b), k_known ? nullptr : d_count, sort_n,
+                                 tile_bits, P<uint32_t>(ctx->hist), P<uint32_t>(ctx->scan_tmp));
   }
-  const uint32_t* skeys = P<uint32_t>(keys_in_b ? ctx->keys_b : ctx->keys_a);
+  const void* skeys = (keys_in_b ? ctx->keys_b : ctx->keys_a).p;
   const uint32_t* svals = P<uint32_t>(keys_in_b ? ctx->vals_b : ctx->vals_a);
   // A5 ranges
   {
     StageTimer t(ctx, st, timing, GSR_STAGE_RANGES);
-    launch_ranges(st, skeys, d_count, sort_n, use_cap, P<uint2>(ctx->ranges), (uint64_t)T);
+    launch_ranges(st, skeys, tile_bits, d_count, sort_n, use_cap, P<uint2>(ctx->ranges),
+                  (uint64_t)T);
   }
   // A6 compositing
   const bool remap = !(s->flags & GSR_FLAG_NO_XCD_REMAP);
@@ -501,6 +502,7 @@ gsr_status forward_impl(gsr_context* ctx, const gsr_settings* s, int64_t n, cons
   sv.K = sort_n;
   sv.k_known = k_known;
   sv.sorted_in_b = keys_in_b;
+  sv.keys16 = tile_keys_16bit(tile_bits);
   sv.recs_in_b = recs_in_b;
   sv.surfel = surfel;
   return GSR_OK;
@@ -1124,7 +1126,16 @@ gsr_status gsr_debug_lists(gsr_context* ctx, uint32_t* ntiles, uint32_t* depth_k
   }
   const DBuf& kb = sv.sorted_in_b ? ctx->keys_b : ctx->keys_a;
   const DBuf& vb = sv.sorted_in_b ? ctx->vals_b : ctx->vals_a;
-  if (tile_keys && K) GSR_HIP(hipMemcpy(tile_keys, kb.p, K * 4, hipMemcpyDeviceToHost));
+  if (tile_keys && K) {
+    if (sv.keys16) {  // widened, the 16-bit sentinel to the 32-bit one
+      std::vector<uint16_t> k16(K);
+      GSR_HIP(hipMemcpy(k16.data(), kb.p, K * 2, hipMemcpyDeviceToHost));
+      for (uint64_t i = 0; i < K; ++i)
+        tile_keys[i] = k16[i] == 0xffffu ? 0xffffffffu : (uint32_t)k16[i];
+    } else {
+      GSR_HIP(hipMemcpy(tile_keys, kb.p, K * 4, hipMemcpyDeviceToHost));
+    }
+  }
   if (tile_vals && K) GSR_HIP(hipMemcpy(tile_vals, vb.p, K * 4, hipMemcpyDeviceToHost));
   if (ranges && sv.T) GSR_HIP(hipMemcpy(ranges, ctx->ranges.p, sv.T * 8, hipMemcpyDeviceToHost));
   if (n_last && sv.P) GSR_HIP(hipMemcpy(n_last, ctx->n_last.p, sv.P * 4, hipMemcpyDeviceToHost));

@@ -7,12 +7,13 @@
 //   1. the N*F records by depth bits (stable LSD radix, 4 x 8-bit passes over
 //      N*F elements), which puts each frame's Gaussians front to back with
 //      ties broken by index;
-//   2. keygen walks the records in that order and writes one 32-bit tile id
-//      per covered tile (the "slot" order); a stable LSD radix over only the
+//   2. keygen walks the records in that order and writes one tile id per
+//      covered tile (the "slot" order), 16 bits wide while the tile ids fit
+//      (up to 65,535 tiles), else 32; a stable LSD radix over only the
 //      tile-id bits (two passes of <= 10 bits up to 2^20 tiles) then groups
 //      the keys by tile while keeping the depth order inside each tile.
-// This moves about 40 bytes per key instead of 6-7 passes over 12-byte
-// (tile | depth, value) pairs.
+// With 16-bit keys, keygen, the two passes and the ranges move 36 bytes per
+// key, instead of 6-7 passes over 12-byte (tile | depth, value) pairs.
 //
 // The radix passes use a hand-written LDS multi-split: each wave ranks its
 // 64 keys per round with one ballot per digit bit (lanes with equal digits
@@ -213,14 +214,16 @@ struct RadixShape {
 };
 
 // Digit counts of one block's keys.  A count does not depend on the order,
-// so each thread loads four keys with one 16-byte load and bumps its wave's
-// LDS counters with atomics; the wave histograms are summed.
-template <int BINS, int WAVES>
+// so each thread loads 16 bytes of keys at once and bumps its wave's LDS
+// counters with atomics; the wave histograms are summed.  KeyT is uint32_t
+// or uint16_t (tile ids below 2^16).
+template <int BINS, int WAVES, typename KeyT>
 __global__ void __launch_bounds__(256) radix_hist_kernel(
-    const uint32_t* __restrict__ keys, const uint64_t* n_dev, uint64_t n_host, int shift,
+    const KeyT* __restrict__ keys, const uint64_t* n_dev, uint64_t n_host, int shift,
     int width, uint32_t* __restrict__ hist /* [nblocks][2^width] */) {
   constexpr int kTile = RadixShape<WAVES>::kTile;
-  constexpr int kHW = 256 / kWave;  // waves of this kernel
+  constexpr int kHW = 256 / kWave;             // waves of this kernel
+  constexpr int kPer = 16 / (int)sizeof(KeyT);  // keys per 16-byte load
   __shared__ uint32_t wcnt[kHW][BINS];
   const uint64_t n = n_dev ? min(*n_dev, n_host) : n_host;
   const int bins = 1 << width;
@@ -231,16 +234,19 @@ __global__ void __launch_bounds__(256) radix_hist_kernel(
   const uint64_t bbase = (uint64_t)blockIdx.x * kTile;
   uint32_t* cw = wcnt[w];
 #pragma unroll
-  for (int j = 0; j < kTile / (4 * 256); ++j) {
-    const uint64_t i = bbase + 4 * ((uint64_t)threadIdx.x + (uint64_t)j * 256);
-    if (i + 4 <= n) {
-      const uint4 k = *reinterpret_cast<const uint4*>(keys + i);  // i % 4 == 0
-      atomicAdd(&cw[(k.x >> shift) & mask], 1u);
-      atomicAdd(&cw[(k.y >> shift) & mask], 1u);
-      atomicAdd(&cw[(k.z >> shift) & mask], 1u);
-      atomicAdd(&cw[(k.w >> shift) & mask], 1u);
+  for (int j = 0; j < kTile / (kPer * 256); ++j) {
+    const uint64_t i = bbase + kPer * ((uint64_t)threadIdx.x + (uint64_t)j * 256);
+    if (i + kPer <= n) {
+      union {
+        uint4 v;
+        KeyT k[kPer];
+      } u;
+      u.v = *reinterpret_cast<const uint4*>(keys + i);  // i % kPer == 0
+#pragma unroll
+      for (int t = 0; t < kPer; ++t) atomicAdd(&cw[((uint32_t)u.k[t] >> shift) & mask], 1u);
     } else {
-      for (uint64_t t = i; t < n && t < i + 4; ++t) atomicAdd(&cw[(keys[t] >> shift) & mask], 1u);
+      for (uint64_t t = i; t < n && t < i + kPer; ++t)
+        atomicAdd(&cw[((uint32_t)keys[t] >> shift) & mask], 1u);
     }
   }
   __syncthreads();
@@ -356,13 +362,13 @@ struct ScatterLds {
 // w 1024 + 64 k + lane; L.wcnt zeroed and the zeroing visible to all waves),
 // moves them into digit order through L.sk / L.sv and writes them to
 // gbase[d] + (position inside the block's run of digit d).
-template <int BINS, int WAVES>
+template <int BINS, int WAVES, typename KeyT>
 __device__ __forceinline__ void rank_and_scatter(ScatterLds<BINS, WAVES>& L,
                                                  const uint32_t (&key)[kSortRounds],
                                                  const uint32_t (&val)[kSortRounds],
                                                  uint32_t nkeys, int shift, int width,
                                                  const uint32_t* __restrict__ offs_row,
-                                                 uint32_t* __restrict__ keys_out,
+                                                 KeyT* __restrict__ keys_out,
                                                  uint32_t* __restrict__ vals_out) {
   constexpr int kThreads = RadixShape<WAVES>::kThreads;
   constexpr int DPT = (BINS + kThreads - 1) / kThreads;  // digits per thread in the combine
@@ -433,17 +439,17 @@ __device__ __forceinline__ void rank_and_scatter(ScatterLds<BINS, WAVES>& L,
     const uint32_t kk = L.sk[idx];
     const uint32_t d = (kk >> shift) & mask;
     const uint32_t dst = L.gbase[d] + (idx - L.dstart[d]);
-    keys_out[dst] = kk;
+    keys_out[dst] = (KeyT)kk;
     vals_out[dst] = L.sv[idx];
   }
 }
 
-template <int BINS, int WAVES>
+template <int BINS, int WAVES, typename KeyT>
 __global__ void __launch_bounds__(WAVES * kWave) radix_scatter_kernel(
-    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
+    const KeyT* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     const uint64_t* n_dev, uint64_t n_host, int shift, int width, unsigned nb, unsigned per,
     const uint32_t* __restrict__ offsets /* scanned [nblocks][2^width] */,
-    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
+    KeyT* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
   constexpr int kThreads = RadixShape<WAVES>::kThreads;
   constexpr int kTile = RadixShape<WAVES>::kTile;
   __shared__ ScatterLds<BINS, WAVES> L;
@@ -459,11 +465,11 @@ __global__ void __launch_bounds__(WAVES * kWave) radix_scatter_kernel(
 #pragma unroll
   for (int k = 0; k < kSortRounds; ++k) {
     const uint32_t i = wbase + (uint32_t)k * kWave + lane;
-    key[k] = i < nkeys ? keys_in[bbase + i] : 0u;
+    key[k] = i < nkeys ? (uint32_t)keys_in[bbase + i] : 0u;
     val[k] = i < nkeys ? vals_in[bbase + i] : 0u;
   }
   __syncthreads();
-  rank_and_scatter<BINS, WAVES>(L, key, val, nkeys, shift, width,
+  rank_and_scatter<BINS, WAVES, KeyT>(L, key, val, nkeys, shift, width,
                                 offsets + (uint64_t)b * (1u << width), keys_out, vals_out);
 }
 
@@ -500,11 +506,12 @@ __device__ __forceinline__ uint32_t div_rem(uint32_t a, uint32_t b, uint32_t& r)
 // LDS.  A record whose slots pass the key capacity gets the all-ones
 // sentinel key (past every tile) on its slots below the capacity.
 // ---------------------------------------------------------------------------
+template <typename KeyT>
 __global__ void __launch_bounds__(256) keygen_kernel(
     uint64_t m, uint64_t n, const uint32_t* __restrict__ perm,
     const uint32_t* __restrict__ cnt_sorted, const uint64_t* __restrict__ offsets,
     uint32_t* __restrict__ keyoff, const uint2* __restrict__ trect,
-    const FrameDesc* __restrict__ frames, uint64_t capacity, uint32_t* __restrict__ keys,
+    const FrameDesc* __restrict__ frames, uint64_t capacity, KeyT* __restrict__ keys,
     uint32_t* __restrict__ vals, uint32_t* __restrict__ overflow) {
   // per record: first slot relative to the wave's first (all-ones for a
   // record without slots in the range), and (first tile id or sentinel, rect
@@ -559,7 +566,7 @@ __global__ void __launch_bounds__(256) keygen_kernel(
       const uint32_t row = div_rem(o - s_rel[w][j], R.y & 0xffffu, col);
       key = R.x + row * (R.y >> 16) + col;
     }
-    keys[lo + o] = key;
+    keys[lo + o] = (KeyT)key;  // the sentinel stays all ones
     vals[lo + o] = R.z;
   }
 }
@@ -570,24 +577,33 @@ __global__ void __launch_bounds__(256) keygen_kernel(
 // of the previous one.
 constexpr int kRangeItems = 8;
 
-__global__ void __launch_bounds__(256) ranges_kernel(const uint32_t* __restrict__ keys,
+template <typename KeyT>
+__global__ void __launch_bounds__(256) ranges_kernel(const KeyT* __restrict__ keys,
                                                      const uint64_t* k_dev, uint64_t capacity,
                                                      uint2* __restrict__ ranges,
                                                      uint32_t n_tiles) {
+  constexpr int kPer = 16 / (int)sizeof(KeyT);  // keys per 16-byte load
+  static_assert(kRangeItems % kPer == 0, "whole 16-byte loads");
   const uint64_t K = *k_dev < capacity ? *k_dev : capacity;
   const uint64_t i0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRangeItems;
   if (i0 >= K) return;
   uint32_t k[kRangeItems];
   if (i0 + kRangeItems <= K) {
-    const uint4 a = *reinterpret_cast<const uint4*>(keys + i0);
-    const uint4 b = *reinterpret_cast<const uint4*>(keys + i0 + 4);
-    k[0] = a.x; k[1] = a.y; k[2] = a.z; k[3] = a.w;
-    k[4] = b.x; k[5] = b.y; k[6] = b.z; k[7] = b.w;
+#pragma unroll
+    for (int q = 0; q < kRangeItems / kPer; ++q) {
+      union {
+        uint4 v;
+        KeyT k[kPer];
+      } u;
+      u.v = *reinterpret_cast<const uint4*>(keys + i0 + q * kPer);
+#pragma unroll
+      for (int t = 0; t < kPer; ++t) k[q * kPer + t] = u.k[t];
+    }
   } else {
 #pragma unroll
-    for (int j = 0; j < kRangeItems; ++j) k[j] = i0 + j < K ? keys[i0 + j] : 0xffffffffu;
+    for (int j = 0; j < kRangeItems; ++j) k[j] = i0 + j < K ? (uint32_t)keys[i0 + j] : 0xffffffffu;
   }
-  uint32_t prev = i0 == 0 ? 0xffffffffu : keys[i0 - 1];
+  uint32_t prev = i0 == 0 ? 0xffffffffu : (uint32_t)keys[i0 - 1];
 #pragma unroll
   for (int j = 0; j < kRangeItems; ++j) {
     const uint64_t i = i0 + j;
@@ -704,16 +720,16 @@ static void radix_offsets(hipStream_t st, uint32_t* hist, unsigned nb, int width
                      scan_tmp, nc);
 }
 
-template <int BINS, int WAVES>
-static void radix_pass(hipStream_t st, const uint32_t* ki, const uint32_t* vi, uint32_t* ko,
+template <int BINS, int WAVES, typename KeyT>
+static void radix_pass(hipStream_t st, const KeyT* ki, const uint32_t* vi, KeyT* ko,
                        uint32_t* vo, const uint64_t* n_dev, uint64_t n_max, int shift, int width,
                        uint32_t* hist, uint32_t* scan_tmp) {
   const unsigned nb = blocks_for(n_max, RadixShape<WAVES>::kTile);
   const unsigned per = (nb + kXcds - 1) / kXcds;
-  hipLaunchKernelGGL((radix_hist_kernel<BINS, WAVES>), dim3(nb), dim3(256), 0, st, ki, n_dev,
-                     n_max, shift, width, hist);
+  hipLaunchKernelGGL((radix_hist_kernel<BINS, WAVES, KeyT>), dim3(nb), dim3(256), 0, st, ki,
+                     n_dev, n_max, shift, width, hist);
   radix_offsets(st, hist, nb, width, scan_tmp);
-  hipLaunchKernelGGL((radix_scatter_kernel<BINS, WAVES>), dim3(per * kXcds),
+  hipLaunchKernelGGL((radix_scatter_kernel<BINS, WAVES, KeyT>), dim3(per * kXcds),
                      dim3(RadixShape<WAVES>::kThreads), 0, st, ki, vi, n_dev, n_max, shift,
                      width, nb, per, hist, ko, vo);
 }
@@ -722,7 +738,8 @@ static void radix_pass(hipStream_t st, const uint32_t* ki, const uint32_t* vi, u
 // and 10-bit digits (LDS) take 4-wave blocks.
 constexpr uint64_t kBigPass = 1ull << 24;
 
-static void radix_pass_any(hipStream_t st, const uint32_t* ki, const uint32_t* vi, uint32_t* ko,
+template <typename KeyT>
+static void radix_pass_any(hipStream_t st, const KeyT* ki, const uint32_t* vi, KeyT* ko,
                            uint32_t* vo, const uint64_t* n_dev, uint64_t n_max, int shift,
                            int width, uint32_t* hist, uint32_t* scan_tmp) {
   if (width > 8)
@@ -743,39 +760,63 @@ bool launch_radix_sort(hipStream_t st, uint32_t* keys_a, uint32_t* vals_a, uint3
   bool in_b = false;
   for (int shift = 0; shift < bits; shift += 8) {
     const int width = std::min(8, bits - shift);
-    radix_pass_any(st, in_b ? keys_b : keys_a, in_b ? vals_b : vals_a, in_b ? keys_a : keys_b,
-                   in_b ? vals_a : vals_b, n_dev, n_max, shift, width, hist, scan_tmp);
+    radix_pass_any<uint32_t>(st, in_b ? keys_b : keys_a, in_b ? vals_b : vals_a,
+                             in_b ? keys_a : keys_b, in_b ? vals_a : vals_b, n_dev, n_max, shift,
+                             width, hist, scan_tmp);
     in_b = !in_b;
   }
   return in_b;
 }
 
+bool tile_keys_16bit(int bits) { return bits <= 16; }
+
 void launch_keygen(hipStream_t st, uint64_t m, uint64_t n, const uint32_t* perm,
                    const uint32_t* cnt_sorted, const uint64_t* offsets, uint32_t* keyoff,
-                   const uint2* trect, const FrameDesc* frames, uint64_t capacity,
-                   uint32_t* keys, uint32_t* vals, uint32_t* overflow) {
+                   const uint2* trect, const FrameDesc* frames, uint64_t capacity, int bits,
+                   void* keys, uint32_t* vals, uint32_t* overflow) {
   if (m == 0) return;
-  hipLaunchKernelGGL(keygen_kernel, dim3(blocks_for(m, 256)), dim3(256), 0, st, m, n, perm,
-                     cnt_sorted, offsets, keyoff, trect, frames, capacity, keys, vals, overflow);
+  if (tile_keys_16bit(bits))
+    hipLaunchKernelGGL(keygen_kernel<uint16_t>, dim3(blocks_for(m, 256)), dim3(256), 0, st, m,
+                       n, perm, cnt_sorted, offsets, keyoff, trect, frames, capacity,
+                       static_cast<uint16_t*>(keys), vals, overflow);
+  else
+    hipLaunchKernelGGL(keygen_kernel<uint32_t>, dim3(blocks_for(m, 256)), dim3(256), 0, st, m,
+                       n, perm, cnt_sorted, offsets, keyoff, trect, frames, capacity,
+                       static_cast<uint32_t*>(keys), vals, overflow);
 }
 
-// Stable sort of the tile keys by the tile-id bits [0, bits) in passes of
-// near-equal width; returns true if the result is in (keys_b, vals_b).
-bool launch_tile_sort(hipStream_t st, uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b,
-                      uint32_t* vals_b, const uint64_t* k_dev, uint64_t k_max, int bits,
-                      uint32_t* hist, uint32_t* scan_tmp) {
-  if (k_max == 0) return false;
+template <typename KeyT>
+static bool tile_sort_t(hipStream_t st, KeyT* keys_a, uint32_t* vals_a, KeyT* keys_b,
+                        uint32_t* vals_b, const uint64_t* k_dev, uint64_t k_max, int bits,
+                        uint32_t* hist, uint32_t* scan_tmp) {
   int widths[8];
   const int passes = tile_pass_widths(bits, widths);
   bool in_b = false;
   int shift = 0;
   for (int p = 0; p < passes; ++p) {
-    radix_pass_any(st, in_b ? keys_b : keys_a, in_b ? vals_b : vals_a, in_b ? keys_a : keys_b,
-                   in_b ? vals_a : vals_b, k_dev, k_max, shift, widths[p], hist, scan_tmp);
+    radix_pass_any<KeyT>(st, in_b ? keys_b : keys_a, in_b ? vals_b : vals_a,
+                         in_b ? keys_a : keys_b, in_b ? vals_a : vals_b, k_dev, k_max, shift,
+                         widths[p], hist, scan_tmp);
     in_b = !in_b;
     shift += widths[p];
   }
   return in_b;
+}
+
+// Stable sort of the tile keys by the tile-id bits [0, bits) in passes of
+// near-equal width; 16-bit keys when bits <= 16.  Returns true if the result
+// is in (keys_b, vals_b).
+bool launch_tile_sort(hipStream_t st, void* keys_a, uint32_t* vals_a, void* keys_b,
+                      uint32_t* vals_b, const uint64_t* k_dev, uint64_t k_max, int bits,
+                      uint32_t* hist, uint32_t* scan_tmp) {
+  if (k_max == 0) return false;
+  if (tile_keys_16bit(bits))
+    return tile_sort_t<uint16_t>(st, static_cast<uint16_t*>(keys_a), vals_a,
+                                 static_cast<uint16_t*>(keys_b), vals_b, k_dev, k_max, bits,
+                                 hist, scan_tmp);
+  return tile_sort_t<uint32_t>(st, static_cast<uint32_t*>(keys_a), vals_a,
+                               static_cast<uint32_t*>(keys_b), vals_b, k_dev, k_max, bits, hist,
+                               scan_tmp);
 }
 
 // The tile counts in depth order, cnt_sorted[i] = ntiles[perm[i]], gathered
@@ -809,12 +850,19 @@ void launch_offsets_scan(hipStream_t st, const uint32_t* ntiles, const uint32_t*
                      ld, (const uint64_t*)nullptr, m, block_tmp, offsets);
 }
 
-void launch_ranges(hipStream_t st, const uint32_t* keys, const uint64_t* k_dev, uint64_t k_max,
-                   uint64_t capacity, uint2* ranges, uint64_t n_tiles) {
+void launch_ranges(hipStream_t st, const void* keys, int bits, const uint64_t* k_dev,
+                   uint64_t k_max, uint64_t capacity, uint2* ranges, uint64_t n_tiles) {
   launch_fill_u32(st, (uint32_t*)ranges, 2 * n_tiles, 0u);
   if (k_max == 0) return;
-  hipLaunchKernelGGL(ranges_kernel, dim3(blocks_for(k_max, 256 * kRangeItems)), dim3(256), 0, st,
-                     keys, k_dev, capacity, ranges, (uint32_t)n_tiles);
+  const dim3 grid(blocks_for(k_max, 256 * kRangeItems));
+  if (tile_keys_16bit(bits))
+    hipLaunchKernelGGL(ranges_kernel<uint16_t>, grid, dim3(256), 0, st,
+                       static_cast<const uint16_t*>(keys), k_dev, capacity, ranges,
+                       (uint32_t)n_tiles);
+  else
+    hipLaunchKernelGGL(ranges_kernel<uint32_t>, grid, dim3(256), 0, st,
+                       static_cast<const uint32_t*>(keys), k_dev, capacity, ranges,
+                       (uint32_t)n_tiles);
 }
 
 }  // namespace gsr

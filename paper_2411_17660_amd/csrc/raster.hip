@@ -296,13 +296,17 @@ __device__ __forceinline__ void composite_bwd_tile(
   const uint2 rg = ranges[tile];
   const int64_t plane = (int64_t)fr.width * fr.height;
 
-  // per pixel: T_{i+1}; colour, depth and transmittance seen behind the
-  // current entry (normalised by T_{i+1}); upstream gradients.  The colour
-  // and depth behind are FP64: dL/da_i uses c_i - B_i, which cancels on
-  // surfaces of uniform colour, and the gradient of a large Gaussian sums
-  // that difference over up to 10^5 pixels.
+  // per pixel: T_{i+1}; the transmittance seen behind the current entry
+  // (normalised by T_{i+1}); upstream gradients.  dL/da_i needs the upstream-
+  // weighted difference G . (c_i - B_i) between the entry's colour (and
+  // depth) and what is seen behind it, B_i.  That difference cancels on
+  // surfaces of uniform colour, and the gradient of a large Gaussian sums it
+  // over up to 10^5 pixels, so it is formed in FP64.  G is fixed per pixel,
+  // so the recursion B_i = B_{i+1} + a_i (c_i - B_{i+1}) carries over to the
+  // scalar E = G . B, which is what the pixel keeps (in FP64), together with
+  // G itself in FP64.
   float T[PIX], BT[PIX];
-  double B0[PIX], B1[PIX], B2[PIX], BZ[PIX];
+  double E[PIX], H0[PIX], H1[PIX], H2[PIX], HZ[PIX];
   float G0[PIX], G1[PIX], G2[PIX], GD[PIX], GA[PIX];
   int last[PIX];
   // MEDIAN: the depth is the z of the entry at list position mp, so G_D
@@ -316,13 +320,17 @@ __device__ __forceinline__ void composite_bwd_tile(
     last[k] = valid ? n_last[fr.pixel_offset + p] : 0;
     mp[k] = (MEDIAN && valid) ? med_pos[fr.pixel_offset + p] : -1;
     T[k] = valid ? t_final[fr.pixel_offset + p] : 1.0f;
-    B0[k] = bg0; B1[k] = bg1; B2[k] = bg2; BZ[k] = 0.0; BT[k] = 1.0f;
+    BT[k] = 1.0f;
     const float* gi = g_rgb + 3 * fr.pixel_offset;
     G0[k] = valid ? gi[p] : 0.0f;
     G1[k] = valid ? gi[plane + p] : 0.0f;
     G2[k] = valid ? gi[2 * plane + p] : 0.0f;
     GD[k] = valid ? g_depth[fr.pixel_offset + p] : 0.0f;
     GA[k] = valid ? g_alpha[fr.pixel_offset + p] : 0.0f;
+    H0[k] = G0[k]; H1[k] = G1[k]; H2[k] = G2[k];
+    HZ[k] = MEDIAN ? 0.0 : (double)GD[k];
+    // behind the last entry: the background colour at depth 0
+    E[k] = __builtin_fma(H2[k], (double)bg2, __builtin_fma(H1[k], (double)bg1, H0[k] * (double)bg0));
   }
   for (int hi = (int)nproc; hi > 0; hi -= BATCH) {
     const int lo = max(0, hi - BATCH);
@@ -347,6 +355,10 @@ __device__ __forceinline__ void composite_bwd_tile(
       const float dx = dx_of(R.u_hi, R.u_lo, px);
       const float a1dx = R.a1 * dx;
       const double c0 = R.c0, c1 = R.c1, c2 = R.c2, cz = R.z;
+      // With p = a dL/da, dL/dq = -p/2: gu, gv carry sum(-p Q d), the
+      // gradient of the centre, and gS* carry sum(p (Q d)(Q d)^T), twice the
+      // gradient of the 2D covariance; the 1/2 is applied once per key (a
+      // power of two: exact)
       float gu = 0.f, gv = 0.f, gs = 0.f;
       double gSxx = 0.0, gSxy = 0.0, gSyy = 0.0;
       float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f, gz = 0.f;
@@ -374,11 +386,12 @@ __device__ __forceinline__ void composite_bwd_tile(
         float Ti = T[k] * inv;
         Ti = __builtin_fmaf(__builtin_fmaf(-Ti, om, T[k]), inv, Ti);  // Newton step
         const float w = a * Ti;
-        const double ad = a;
-        const double d0 = c0 - B0[k], d1 = c1 - B1[k], d2 = c2 - B2[k], dz = cz - BZ[k];
-        // dL/da_i = T_i [G . (c_i - B_i) + G_D (z_i - BZ_i) + G_A BT_i]
-        const float dLda = Ti * (G0[k] * (float)d0 + G1[k] * (float)d1 + G2[k] * (float)d2 +
-                                 (MEDIAN ? 0.0f : GD[k] * (float)dz) + GA[k] * BT[k]);
+        // G . (c_i - B_i) = G . c_i - E
+        double gc = __builtin_fma(H2[k], c2, __builtin_fma(H1[k], c1, H0[k] * c0));
+        if (!MEDIAN) gc = __builtin_fma(HZ[k], cz, gc);
+        const double diff = gc - E[k];
+        // dL/da_i = T_i [G . (c_i - B_i) + G_A BT_i]
+        const float dLda = Ti * __builtin_fmaf(GA[k], BT[k], (float)diff);
         gc0 += G0[k] * w;
         gc1 += G1[k] * w;
         gc2 += G2[k] * w;
@@ -387,40 +400,38 @@ __device__ __forceinline__ void composite_bwd_tile(
         else
           gz += GD[k] * w;
         // step the 'behind' state in front of entry i
-        B0[k] = __builtin_fma(ad, d0, B0[k]);
-        B1[k] = __builtin_fma(ad, d1, B1[k]);
-        B2[k] = __builtin_fma(ad, d2, B2[k]);
-        if (!MEDIAN) BZ[k] = __builtin_fma(ad, dz, BZ[k]);
+        E[k] = __builtin_fma((double)a, diff, E[k]);
         BT[k] = BT[k] * om;
         T[k] = Ti;
         any = true;
         if (sg > kAlphaMax) continue;  // clamped: alpha does not move
         gs += dLda * g;
-        const float dq = -0.5f * a * dLda;
+        const float pa = a * dLda;
         // Q d = L (L^T d), L^T d = (a1 dx + a2 dy, a3 dy)
         const float m = __builtin_fmaf(R.a2, dy, a1dx);
         const float b = R.a3 * dy;
         const float qx = R.a1 * m;
         const float qy = __builtin_fmaf(R.a2, m, R.a3 * b);
-        gu += 2.0f * dq * qx;
-        gv += 2.0f * dq * qy;
-        // Each pixel adds the rank-1 matrix -dq (Q d)(Q d)^T.  Formed in FP64
+        gu = __builtin_fmaf(-pa, qx, gu);
+        gv = __builtin_fmaf(-pa, qy, gv);
+        // Each pixel adds the rank-1 matrix p (Q d)(Q d)^T.  Formed in FP64
         // its three entries stay exactly rank-1; rounded one by one in FP32
         // they would not, and a Gaussian at the near plane has scale
         // gradients that read the near-null direction of the summed matrix.
         {
-          const double dqd = dq, qxd = qx, qyd = qy;
-          const double t = dqd * qxd;
-          gSxx -= t * qxd;
-          gSxy -= t * qyd;
-          gSyy -= dqd * qyd * qyd;
+          const double pd = pa, qxd = qx, qyd = qy;
+          const double t = pd * qxd;
+          gSxx = __builtin_fma(t, qxd, gSxx);
+          gSxy = __builtin_fma(t, qyd, gSxy);
+          gSyy = __builtin_fma(pd * qyd, qyd, gSyy);
         }
       }
       if (__ballot(any) == 0) continue;
       // The lanes' values of one key cancel against each other: sum them in
       // FP64; the key's total is stored as FP32 and the per-record sum over
       // its keys is FP64 again
-      const double vals10[kNG] = {gu, gv, gSxx, gSxy, gSyy, gs, gc0, gc1, gc2, gz};
+      const double vals10[kNG] = {gu, gv, 0.5 * gSxx, 0.5 * gSxy, 0.5 * gSyy,
+                                   gs, gc0, gc1, gc2, gz};
       int idx;
       bool writer;
       const double tot = wave_transpose_sum10(vals10, lane, idx, writer);

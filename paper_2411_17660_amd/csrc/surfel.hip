@@ -405,12 +405,16 @@ __global__ void __launch_bounds__(64) surfel_bwd_kernel(
   const int ly = lane / TW;
   const uint2 rg = ranges[tile];
   const int64_t plane = (int64_t)fr.width * fr.height;
-  // per pixel: T_{i+1}, the totals of the distortion sums, and the values
-  // seen behind the current entry (colour, depth, normal, distortion weight
-  // e, transmittance), normalised by T_{i+1}; FP64 because dL/da_i takes
-  // their differences with the entry's own values
+  // per pixel: T_{i+1}, the totals of the distortion sums, and the
+  // transmittance seen behind the current entry (normalised by T_{i+1}).
+  // dL/da_i takes the upstream-weighted difference G . (v_i - B_i) between
+  // the entry's values (colour, depth, normal, distortion weight e) and
+  // those seen behind it; it cancels where neighbouring surfels agree, so it
+  // is formed in FP64.  G is fixed per pixel, so the recursion
+  // B_i = B_{i+1} + a_i (v_i - B_{i+1}) carries over to the scalar E = G . B,
+  // which the pixel keeps (FP64) together with G in FP64.
   float T[PIX], BT[PIX], AT[PIX], ZR[PIX], S1[PIX], S2[PIX];
-  double BC0[PIX], BC1[PIX], BC2[PIX], BD[PIX], BN0[PIX], BN1[PIX], BN2[PIX], BE[PIX];
+  double E[PIX], H0[PIX], H1[PIX], H2[PIX], HD[PIX], HN0[PIX], HN1[PIX], HN2[PIX], HE[PIX];
   float G0[PIX], G1[PIX], G2[PIX], GD[PIX], GA[PIX], GN0[PIX], GN1[PIX], GN2[PIX], GE[PIX];
   int last[PIX];
 #pragma unroll
@@ -427,8 +431,6 @@ __global__ void __launch_bounds__(64) surfel_bwd_kernel(
     AT[k] = ax.y;
     S1[k] = ax.z;
     S2[k] = ax.w;
-    BC0[k] = bg0; BC1[k] = bg1; BC2[k] = bg2;
-    BD[k] = BN0[k] = BN1[k] = BN2[k] = BE[k] = 0.0;
     BT[k] = 1.0f;
     const float* gi = g_rgb + 3 * fr.pixel_offset;
     const float* gn = g_normal + 3 * fr.pixel_offset;
@@ -441,6 +443,10 @@ __global__ void __launch_bounds__(64) surfel_bwd_kernel(
     GD[k] = valid ? g_depth[q] : 0.0f;
     GA[k] = valid ? g_alpha[q] : 0.0f;
     GE[k] = valid ? g_dist[q] : 0.0f;
+    H0[k] = G0[k]; H1[k] = G1[k]; H2[k] = G2[k]; HD[k] = GD[k];
+    HN0[k] = GN0[k]; HN1[k] = GN1[k]; HN2[k] = GN2[k]; HE[k] = GE[k];
+    // behind the last entry: the background colour, zero depth, normal and e
+    E[k] = __builtin_fma(H2[k], (double)bg2, __builtin_fma(H1[k], (double)bg1, H0[k] * (double)bg0));
   }
   for (int hi = most; hi > 0; hi -= kWave) {
     const int lo = hi > kWave ? hi - kWave : 0;
@@ -485,14 +491,17 @@ __global__ void __launch_bounds__(64) surfel_bwd_kernel(
         const double zp = h.z - ZR[k];
         // dDist/dw_i: sum over the other entries m of w_m (z_i - z_m)^2
         const double e = AT[k] * zp * zp - 2.0 * zp * S1[k] + S2[k];
-        const double ad = a;
-        const double d0 = S.c0 - BC0[k], d1 = S.c1 - BC1[k], d2 = S.c2 - BC2[k];
-        const double dz = h.z - BD[k], de = e - BE[k];
-        const double dn0 = S.n0 - BN0[k], dn1 = S.n1 - BN1[k], dn2 = S.n2 - BN2[k];
-        const float dLda =
-            Ti * (G0[k] * (float)d0 + G1[k] * (float)d1 + G2[k] * (float)d2 +
-                  GD[k] * (float)dz + GN0[k] * (float)dn0 + GN1[k] * (float)dn1 +
-                  GN2[k] * (float)dn2 + GE[k] * (float)de + GA[k] * BT[k]);
+        // G . (v_i - B_i) = G . v_i - E
+        double gv = H0[k] * (double)S.c0;
+        gv = __builtin_fma(H1[k], (double)S.c1, gv);
+        gv = __builtin_fma(H2[k], (double)S.c2, gv);
+        gv = __builtin_fma(HD[k], (double)h.z, gv);
+        gv = __builtin_fma(HN0[k], (double)S.n0, gv);
+        gv = __builtin_fma(HN1[k], (double)S.n1, gv);
+        gv = __builtin_fma(HN2[k], (double)S.n2, gv);
+        gv = __builtin_fma(HE[k], e, gv);
+        const double diff = gv - E[k];
+        const float dLda = Ti * __builtin_fmaf(GA[k], BT[k], (float)diff);
         acc[10] += G0[k] * w;
         acc[11] += G1[k] * w;
         acc[12] += G2[k] * w;
@@ -501,14 +510,7 @@ __global__ void __launch_bounds__(64) surfel_bwd_kernel(
         acc[15] += GN2[k] * w;
         // dL/dz_i: the depth map and the distortion, 2 w_i sum_m w_m (z_i - z_m)
         const float dzv = w * (GD[k] + (float)(2.0 * GE[k] * (zp * AT[k] - S1[k])));
-        BC0[k] = __builtin_fma(ad, d0, BC0[k]);
-        BC1[k] = __builtin_fma(ad, d1, BC1[k]);
-        BC2[k] = __builtin_fma(ad, d2, BC2[k]);
-        BD[k] = __builtin_fma(ad, dz, BD[k]);
-        BN0[k] = __builtin_fma(ad, dn0, BN0[k]);
-        BN1[k] = __builtin_fma(ad, dn1, BN1[k]);
-        BN2[k] = __builtin_fma(ad, dn2, BN2[k]);
-        BE[k] = __builtin_fma(ad, de, BE[k]);
+        E[k] = __builtin_fma((double)a, diff, E[k]);
         BT[k] = BT[k] * om;
         T[k] = Ti;
         any = true;

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libgsr.so")
-SOURCES = ["runtime.hip", "preprocess.hip", "sort.hip", "raster.hip", "loss.hip", "ssim.hip", "densify.hip", "surfel.hip", "normals.hip", "adam.hip"]
+SOURCES = ["runtime.hip", "preprocess.hip", "sort.hip", "raster.hip", "loss.hip", "ssim.hip", "densify.hip", "surfel.hip", "normals.hip", "adam.hip", "host_check.cpp"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

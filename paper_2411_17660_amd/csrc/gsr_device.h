@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "host_check.h"  // FrameDesc
+
 namespace gsr {
 
 // Per-pair thresholds of the compositing loop (FP32 compares).
@@ -19,15 +21,6 @@ constexpr double kExtent = 3.0;
 constexpr float kNegHalfLog2e = -0.72134752044448170368f;
 
 constexpr int kWave = 64;
-
-// One frame of a batch (A0 batch descriptor).
-struct FrameDesc {
-  int32_t width, height;
-  float fx, fy, cx, cy, near_z;
-  int32_t grid_x, grid_y;
-  int32_t tile_offset;   // first global tile id of the frame
-  int64_t pixel_offset;  // first packed pixel of the frame
-};
 
 // Per (Gaussian, frame) record written by the preprocess and staged through
 // LDS by the compositing kernels: 64 bytes, read with 4 x 16-byte loads.

@@ -76,9 +76,6 @@ void launch_ranges(hipStream_t st, const void* keys, int bits, const uint64_t* k
                    uint64_t k_max, uint64_t capacity, uint2* ranges, uint64_t n_tiles);
 
 // raster.hip: compositing forward and backward
-bool tile_shape_supported(int tw, int th);
-// Gaussians staged per LDS round in the compositing kernels: 32, 64 or 128
-bool lds_batch_supported(int batch);
 // med_pos (NULL: alpha-blended depth) selects the median depth: the forward
 // writes, per pixel, the list position of the entry after which T first
 // falls below 1/2 (-1: none) and outputs that entry's z as the depth; the

@@ -571,13 +571,6 @@ static void launch_bwd_t(hipStream_t st, int batch, int n_tiles, int groups,
 #undef GSR_BWD_B
 }
 
-bool tile_shape_supported(int tw, int th) {
-  return (tw == 16 && th == 16) || (tw == 8 && th == 8) || (tw == 32 && th == 8) ||
-         (tw == 16 && th == 8) || (tw == 32 && th == 16);
-}
-
-bool lds_batch_supported(int batch) { return batch == 32 || batch == 64 || batch == 128; }
-
 void launch_composite_fwd(hipStream_t st, int tw, int th, int batch, int n_tiles, int F,
                           const FrameDesc* frames, const uint2* ranges, const uint32_t* vals,
                           const Record* rec, const float* bg, float* rgb, float* depth,

@@ -140,53 +140,15 @@ gsr_status ensure(gsr_context* ctx, DBuf& b, size_t bytes, hipStream_t st, bool 
 template <typename T>
 T* P(const DBuf& b) { return static_cast<T*>(b.p); }
 
-// Bits needed for values < v.  The tile sort uses bits_for(T + 1) so that the
-// all-ones sentinel of an overflowed record never aliases a real tile id.
-int bits_for(uint64_t v) {
-  int b = 1;
-  while (b < 32 && (1ull << b) < v) ++b;
-  return b;
-}
-
 gsr_status validate(gsr_context* ctx, const gsr_settings* s, int64_t n, const float* means,
                     const float* log_scales, const float* quats, const float* opac,
                     const float* sh, int32_t F, const gsr_camera* cams, const float* poses,
                     const float* rgb, const float* depth, const float* alpha) {
   if (!ctx) return GSR_ERR_INVALID_ARGUMENT;
-  if (!s) return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "settings is NULL");
-  if (n < 0) return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "n < 0");
-  if (n >= (int64_t)1 << 31) return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "n >= 2^31");
-  if (F < 1) return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "n_frames < 1");
-  if ((int64_t)F * n >= (int64_t)1 << 32)
-    return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "n * n_frames >= 2^32");
-  if (s->sh_degree < 0 || s->sh_degree > 3)
-    return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "sh_degree %d not in [0,3]", s->sh_degree);
-  if (!tile_shape_supported(s->tile_w, s->tile_h))
-    return fail(ctx, GSR_ERR_UNSUPPORTED, "tile shape %dx%d not supported", s->tile_w,
-                s->tile_h);
-  if (s->lds_batch != 0 && !lds_batch_supported(s->lds_batch))
-    return fail(ctx, GSR_ERR_UNSUPPORTED, "lds_batch %d not supported (0, 32, 64 or 128)",
-                s->lds_batch);
-  if (s->key_capacity < 0 || s->key_capacity >= ((int64_t)1 << 32))
-    return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "key_capacity out of range");
-  if (!cams || !poses) return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "cams/poses is NULL");
-  if (!rgb || !depth || !alpha) return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "output is NULL");
-  if (n > 0 && (!means || !log_scales || !quats || !opac || !sh))
-    return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "parameter pointer is NULL");
-  const void* ptrs[] = {means, log_scales, quats, opac, sh, poses, rgb, depth, alpha};
-  for (const void* p : ptrs)
-    if (((uintptr_t)p) & 3u) return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "pointer not 4-aligned");
-  for (int f = 0; f < F; ++f) {
-    const gsr_camera& c = cams[f];
-    if (c.width < 1 || c.height < 1 || c.width > 65535 || c.height > 65535)
-      return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "frame %d: size %dx%d", f, c.width, c.height);
-    if (!(c.fx > 0.0f) || !(c.fy > 0.0f) || !std::isfinite(c.fx) || !std::isfinite(c.fy))
-      return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "frame %d: focal length not finite and > 0", f);
-    if (!std::isfinite(c.cx) || !std::isfinite(c.cy))
-      return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "frame %d: principal point not finite", f);
-    if (!(c.near_z > 0.0f) || !std::isfinite(c.near_z))
-      return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "frame %d: near_z not finite and > 0", f);
-  }
+  char msg[256];
+  const gsr_status rc = check_forward(s, n, means, log_scales, quats, opac, sh, F, cams, poses,
+                                      rgb, depth, alpha, msg, sizeof msg);
+  if (rc) return fail(ctx, rc, "%s", msg);
   return GSR_OK;
 }
 
@@ -315,22 +277,13 @@ gsr_status forward_impl(gsr_context* ctx, const gsr_settings* s, int64_t n, cons
   GSR_HIP(hipSetDevice(ctx->device));
   const int tw = s->tile_w, th = s->tile_h;
   // A0: frame descriptors
-  std::vector<FrameDesc> fr(F);
+  std::vector<FrameDesc> fr;
   int64_t T = 0, Px = 0, max_hw = 0;
-  for (int f = 0; f < F; ++f) {
-    const gsr_camera& c = cams[f];
-    FrameDesc& d = fr[f];
-    d.width = c.width; d.height = c.height;
-    d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy; d.near_z = c.near_z;
-    d.grid_x = (c.width + tw - 1) / tw;
-    d.grid_y = (c.height + th - 1) / th;
-    d.tile_offset = (int32_t)T;
-    d.pixel_offset = Px;
-    T += (int64_t)d.grid_x * d.grid_y;
-    Px += (int64_t)c.width * c.height;
-    max_hw = std::max<int64_t>(max_hw, (int64_t)c.width * c.height);
+  {
+    char msg[256];
+    if ((rc = build_frames(F, cams, tw, th, fr, &T, &Px, &max_hw, msg, sizeof msg)))
+      return fail(ctx, rc, "%s", msg);
   }
-  if (T >= ((int64_t)1 << 31)) return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "too many tiles");
   if ((rc = upload_frames(ctx, fr, st))) return rc;
   const uint64_t M = (uint64_t)n * F;
   // workspace sized by M, T, P
@@ -535,20 +488,18 @@ gsr_status gsr_normal_consistency(gsr_context* ctx, int32_t F, const gsr_camera*
                                   float weight, float* loss, float* g_depth, float* g_alpha,
                                   float* g_normal, void* stream) {
   if (!ctx) return GSR_ERR_INVALID_ARGUMENT;
-  if (F <= 0 || !cams) return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "no frames");
+  {
+    char msg[256];
+    gsr_status rc0 = check_image_cameras(F, cams, msg, sizeof msg);
+    if (rc0) return fail(ctx, rc0, "%s", msg);
+  }
   if (!depth || !alpha || !normal || !loss || !g_depth || !g_alpha || !g_normal)
     return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "pointer is NULL");
   const void* ptrs[] = {depth, alpha, normal, loss, g_depth, g_alpha, g_normal};
   for (const void* p : ptrs)
     if (((uintptr_t)p) & 3u) return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "pointer not 4-aligned");
   int64_t blocks = 0;
-  for (int f = 0; f < F; ++f) {
-    const gsr_camera& c = cams[f];
-    if (c.width <= 0 || c.height <= 0 || c.width > 65535 || c.height > 65535 ||
-        !(c.fx > 0.0f) || !(c.fy > 0.0f))
-      return fail(ctx, GSR_ERR_INVALID_ARGUMENT, "camera %d invalid", f);
-    blocks += normal_consistency_blocks(c.width, c.height);
-  }
+  for (int f = 0; f < F; ++f) blocks += normal_consistency_blocks(cams[f].width, cams[f].height);
   ctx->err.clear();
   hipStream_t st = (hipStream_t)stream;
   GSR_HIP(hipSetDevice(ctx->device));

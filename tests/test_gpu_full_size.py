@@ -6,7 +6,7 @@ properties that hold at any size."""
 import numpy as np
 import pytest
 
-from gpu_util import check_sampled_frames, gpu_backward, gpu_forward, to_dev
+from gpu_util import assert_grad_close, check_sampled_frames, gpu_backward, gpu_forward, to_dev
 from paper_2411_17660_amd import scenes
 
 pytestmark = pytest.mark.gpu
@@ -233,3 +233,121 @@ def test_c3_surfels_full_size_sampled_windows(rast):
         if k != "twist":
             assert np.all(v[culled] == 0), k
     print(f"[c3-surfel] backward finite; {int(culled.sum())} surfels culled everywhere", flush=True)
+
+
+def _c3_facing_surfels():
+    """The C3 surfel scene (500k surfels, 8 x 1200x680) with round disks
+    (equal scales) rotated within ~20 degrees of the first camera's image
+    plane.  A tilted or elongated disk makes the ray-disk intersection
+    ill-conditioned; at C3 density every pixel of the plain C3 surfel scene
+    blends such a disk, so its gradients cannot be held to the 1e-3 bar.
+    Here frames 0 to ~4 see most disks nearly face-on."""
+    sc = scenes.scene_c3(seed=0)
+    ls = np.array(sc.log_scales[:, :2])
+    ls[:, 1] = ls[:, 0]
+    sc.log_scales = np.ascontiguousarray(ls)
+    rng = np.random.default_rng(5)
+    sc.quats = np.concatenate([np.ones((sc.n, 1)), 0.1 * rng.normal(size=(sc.n, 3))],
+                              1).astype(np.float32)
+    return sc
+
+
+def test_c3_surfels_facing_full_size_gradients_on_windows(rast):
+    """Surfel backward parity at the benchmark's size and launch (500k
+    surfels, one batched forward and backward over 8 x 1200x680, tile 16x16):
+    upstream gradients of all five images are random on windows of frames 0
+    and 3 and zero elsewhere and on the pixels the oracle flags; the oracle
+    renders those windows alone and differentiates them.  Every surfel a
+    window touches is held to the bar of the 3D backward (1e-3 relative,
+    1 % group floor, 3x the oracle's noise), not the 5 % group floor the
+    tilted small scenes need; every other surfel, and the twists of the
+    frames without a window, get exactly zero."""
+    import torch
+    from oracle import surfel as S
+    from gpu_util import GRAD_REL, perturbed, NOISE_MULT
+    sc = _c3_facing_surfels()
+    W, H = sc.cams[0][0], sc.cams[0][1]
+    P = W * H
+    F = sc.n_frames
+    t = S.to64
+    wins = [(0, (588, 619, 331, 354)), (0, (1168, 1199, 656, 679)), (3, (100, 131, 100, 123))]
+    names = ("means", "log_scales", "quats", "opacity", "sh")
+    g_ref = [np.zeros(x.shape) for x in (sc.means, sc.log_scales, sc.quats, sc.opacity, sc.sh)]
+    noise = [np.zeros_like(x) for x in g_ref]
+    tw_ref = np.zeros((F, 6))
+    tw_noise = np.zeros((F, 6))
+    ups = [np.zeros(3 * F * P, np.float32), np.zeros(F * P, np.float32),
+           np.zeros(F * P, np.float32), np.zeros(3 * F * P, np.float32),
+           np.zeros(F * P, np.float32)]
+    rng = np.random.default_rng(31)
+
+    def window_grads(sf, win, G, jitter=None):
+        params = [t(sf.means, True), t(sf.log_scales, True), t(sf.quats, True),
+                  t(sf.opacity, True), t(sf.sh, True), t(np.zeros((1, 6)), True)]
+        gen = None if jitter is None else torch.Generator().manual_seed(jitter)
+        fr = S.render(*params[:5], sf.sh_degree, sf.cams, t(sf.poses), sf.background,
+                      twist=params[5], window=win, jitter=gen)[0]
+        maps = [fr["rgb"].reshape(-1), fr["depth"].reshape(-1), fr["alpha"].reshape(-1),
+                fr["normal"].reshape(-1), fr["dist"].reshape(-1)]
+
+        def grads(Gs, retain):
+            loss = sum((m * torch.from_numpy(np.asarray(g, np.float64))).sum()
+                       for m, g in zip(maps, Gs))
+            return [x.numpy() for x in torch.autograd.grad(loss, params, retain_graph=retain)]
+        return fr["flags"], grads
+
+    for f, (x0, x1, y0, y1) in wins:
+        sf = sc.subset_frames([f])
+        print(f"[c3-facing] frame {f} window {(x0, x1, y0, y1)}: oracle", flush=True)
+        flags, grads = window_grads(sf, (x0, x1, y0, y1), None)
+        keep = (flags == 0).ravel().astype(np.float64)
+        n_px = keep.size
+        print(f"[c3-facing]   flagged {int(n_px - keep.sum())} of {n_px}", flush=True)
+        assert keep.sum() > 0.9 * n_px
+        G = [rng.normal(size=3 * n_px) * np.tile(keep, 3), rng.normal(size=n_px) * keep,
+             rng.normal(size=n_px) * keep, rng.normal(size=3 * n_px) * np.tile(keep, 3),
+             5.0 * rng.normal(size=n_px) * keep]
+        G = [x.astype(np.float32) for x in G]
+        gw = grads(G, True)
+        dG = [p - np.asarray(g, np.float64) for p, g in zip(perturbed(G), G)]
+        nw = [np.abs(x) for x in grads(dG, False)]
+        _, grads_j = window_grads(sf, (x0, x1, y0, y1), G, jitter=17 + f)
+        nw = [np.maximum(a, np.abs(b - r)) for a, b, r in zip(nw, grads_j(G, False), gw)]
+        for i in range(5):
+            g_ref[i] += gw[i]
+            noise[i] += nw[i]
+        tw_ref[f] += gw[5][0]
+        tw_noise[f] += nw[5][0]
+        # scatter the window's upstream into the batch's image layout
+        ys, xs = np.mgrid[y0:y1 + 1, x0:x1 + 1]
+        pix = (ys * W + xs).ravel()
+        for c, nch in enumerate((3, 1, 1, 3, 1)):
+            Gc = G[c].reshape(nch, n_px)
+            for ch in range(nch):
+                ups[c][nch * f * P + ch * P + pix] = Gc[ch]
+    d = to_dev(sc)
+    rast.forward_surfel(d["means"], d["log_scales"], d["quats"], d["opacity"], d["sh"],
+                        d["poses"], sc.cams, sc.sh_degree, sc.background, tile=(16, 16))
+    g = rast.backward_surfel(*[torch.from_numpy(x).cuda() for x in ups])
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy().astype(np.float64) for k, v in g.items()}
+    touched = np.zeros(sc.n, bool)
+    for r in g_ref:
+        touched |= np.abs(r.reshape(sc.n, -1)).sum(1) > 0
+    print(f"[c3-facing] {int(touched.sum())} surfels touched by the windows", flush=True)
+    assert touched.sum() > 100
+    for k, r, nz in zip(names, g_ref, noise):
+        v = got[k].reshape(sc.n, -1)
+        assert np.all(v[~touched] == 0), k
+        rt, vt, nt = r.reshape(sc.n, -1)[touched], v[touched], nz.reshape(sc.n, -1)[touched]
+        assert_grad_close(f"c3-facing:{k}", vt, rt, noise=nt, block=1e-2)
+    for f in range(F):
+        if not tw_ref[f].any():
+            assert np.all(got["twist"][f] == 0), f
+            continue
+        bound = np.maximum(GRAD_REL * np.maximum(np.abs(tw_ref[f]), 1e-2 * np.abs(tw_ref[f]).max()),
+                           NOISE_MULT * tw_noise[f])
+        err = np.abs(got["twist"][f] - tw_ref[f])
+        print(f"[c3-facing]   twist frame {f} max err/bound {float((err / bound).max()):.3g}",
+              flush=True)
+        assert np.all(err <= bound)

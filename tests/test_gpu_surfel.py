@@ -257,6 +257,28 @@ def test_surfel_backward_matches_oracle_autograd(rast, seed, n, frames, deg, W, 
     _check_backward(rast, sc, tile, seed, f"surfels{seed}")
 
 
+def _large_facing_scene(seed, n=30, W=320, H=240, frames=2):
+    """Round disks, nearly face-on, large enough that each covers most of the
+    image: records with hundreds of keys."""
+    sc = _surfel_scene(seed, n, W, H, 0.8 * W, frames, 1, ls_mean=-0.8)
+    sc.log_scales = np.ascontiguousarray(np.repeat(sc.log_scales[:, :1], 2, 1))
+    rng = np.random.default_rng(seed + 1000)
+    sc.quats = np.concatenate([np.ones((n, 1)), 0.1 * rng.normal(size=(n, 3))],
+                              1).astype(np.float32)
+    return sc
+
+
+def test_surfel_backward_large_disks_many_tiles(rast):
+    """Backward parity where every record spans hundreds of tiles, so that
+    the per-record reduction walks its longest lists."""
+    sc = _large_facing_scene(26)
+    _check_backward(rast, sc, (16, 16), 26, "large-disks")
+    nt = rast.debug_lists()["ntiles"]
+    print(f"[surfel] large-disks: tiles per record max {int(nt.max())}, "
+          f"mean {float(nt[nt > 0].mean()):.1f}", flush=True)
+    assert int(nt.max()) >= 200
+
+
 def test_surfel_objective_chain_matches_oracle(rast):
     """The surfel objective end to end: rendering loss with SSIM (lambda1 0.8,
     lambda2 0.2) + 0.05 x normal consistency + 100 x the mean depth

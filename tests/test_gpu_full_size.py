@@ -183,8 +183,9 @@ def test_c3_surfels_full_size_sampled_windows(rast):
     a backward of random upstream gradients over all pixels is finite, and
     the surfels culled in every frame get exactly zero.  (At this density
     every pixel holds a blended surfel whose intersection is too
-    ill-conditioned for the 1e-3 gradient bar, kappa (1 + q) > 32, so the
-    gradient parity runs on the smaller scenes.)"""
+    ill-conditioned for the 1e-3 gradient bar, kappa (1 + q) > 32; the
+    full-size gradient parity runs on the same scene with round, nearly
+    face-on disks, in the next test.)"""
     import torch
     from oracle import surfel as S
     from gpu_util import IMG_TOL

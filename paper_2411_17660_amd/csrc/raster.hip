@@ -144,6 +144,11 @@ __device__ __forceinline__ void composite_fwd_tile(
     const int cnt = (int)min((uint32_t)BATCH, rg.y - b);
     for (int j = 0; j < cnt; ++j) {
       const Record& R = sm[j];
+      // The fields every pixel strip reads up to the alpha test, loaded from
+      // LDS once per entry (read in each strip, they would be reloaded there
+      // with the address rebuilt each time).
+      float e_vhi = R.v_hi, e_vlo = R.v_lo, e_a1 = R.a1, e_a2 = R.a2, e_a3 = R.a3, e_op = R.opacity;
+      asm volatile("" : "+v"(e_vhi), "+v"(e_vlo), "+v"(e_a1), "+v"(e_a2), "+v"(e_a3), "+v"(e_op));
       const int xlo = R.sqx & 0xffff, xhi = R.sqx >> 16;
       const int ylo = R.sqy & 0xffff, yhi = R.sqy >> 16;
       const bool xin = (unsigned)(px - xlo) <= (unsigned)(xhi - xlo);
@@ -155,10 +160,10 @@ __device__ __forceinline__ void composite_fwd_tile(
         const int py = row0 + ly;
         if (done[k] || !xin || (unsigned)(py - ylo) > (unsigned)(yhi - ylo)) continue;
         if (COUNT) ++hits;
-        const float dy = dx_of(R.v_hi, R.v_lo, py);
-        const float q = q_of(R.a1, R.a2, R.a3, dx, dy);
+        const float dy = dx_of(e_vhi, e_vlo, py);
+        const float q = q_of(e_a1, e_a2, e_a3, dx, dy);
         const float g = gauss_of(q);
-        const float a = fminf(kAlphaMax, R.opacity * g);
+        const float a = fminf(kAlphaMax, e_op * g);
         if (a < kAlphaMin) continue;
         const float Tn = T[k] * (1.0f - a);
         if (Tn < kTMin) { done[k] = true; continue; }
@@ -349,11 +354,16 @@ __device__ __forceinline__ void composite_bwd_tile(
     for (int j = hi - lo - 1; j >= 0; --j) {
       const int pos = lo + j;
       const Record& R = sm[j];
+      // The fields every pixel strip reads, loaded from LDS once per entry
+      // (read in each strip, they would be reloaded there with the address
+      // rebuilt each time).
+      float e_vhi = R.v_hi, e_vlo = R.v_lo, e_a1 = R.a1, e_a2 = R.a2, e_a3 = R.a3, e_op = R.opacity;
+      asm volatile("" : "+v"(e_vhi), "+v"(e_vlo), "+v"(e_a1), "+v"(e_a2), "+v"(e_a3), "+v"(e_op));
       const int xlo = R.sqx & 0xffff, xhi = R.sqx >> 16;
       const int ylo = R.sqy & 0xffff, yhi = R.sqy >> 16;
       const bool xin = (unsigned)(px - xlo) <= (unsigned)(xhi - xlo);
       const float dx = dx_of(R.u_hi, R.u_lo, px);
-      const float a1dx = R.a1 * dx;
+      const float a1dx = e_a1 * dx;
       const double c0 = R.c0, c1 = R.c1, c2 = R.c2, cz = R.z;
       // With p = a dL/da, dL/dq = -p/2: gu, gv carry sum(-p Q d), the
       // gradient of the centre, and gS* carry sum(p (Q d)(Q d)^T), twice the
@@ -375,10 +385,10 @@ __device__ __forceinline__ void composite_bwd_tile(
         if (ylo > row0 + RPP - 1 || yhi < row0) continue;
         const int py = row0 + ly;
         if (pos >= last[k] || !xin || (unsigned)(py - ylo) > (unsigned)(yhi - ylo)) continue;
-        const float dy = dx_of(R.v_hi, R.v_lo, py);
-        const float q = q_of(R.a1, R.a2, R.a3, dx, dy);
+        const float dy = dx_of(e_vhi, e_vlo, py);
+        const float q = q_of(e_a1, e_a2, e_a3, dx, dy);
         const float g = gauss_of(q);
-        const float sg = R.opacity * g;
+        const float sg = e_op * g;
         const float a = fminf(kAlphaMax, sg);
         if (a < kAlphaMin) continue;
         const float om = 1.0f - a;
@@ -408,10 +418,10 @@ __device__ __forceinline__ void composite_bwd_tile(
         gs += dLda * g;
         const float pa = a * dLda;
         // Q d = L (L^T d), L^T d = (a1 dx + a2 dy, a3 dy)
-        const float m = __builtin_fmaf(R.a2, dy, a1dx);
-        const float b = R.a3 * dy;
-        const float qx = R.a1 * m;
-        const float qy = __builtin_fmaf(R.a2, m, R.a3 * b);
+        const float m = __builtin_fmaf(e_a2, dy, a1dx);
+        const float b = e_a3 * dy;
+        const float qx = e_a1 * m;
+        const float qy = __builtin_fmaf(e_a2, m, e_a3 * b);
         gu = __builtin_fmaf(-pa, qx, gu);
         gv = __builtin_fmaf(-pa, qy, gv);
         // Each pixel adds the rank-1 matrix p (Q d)(Q d)^T.  Formed in FP64
@@ -444,7 +454,7 @@ __device__ __forceinline__ void composite_bwd_tile(
 }
 
 template <int TW, int TH, bool MEDIAN, int BATCH>
-__global__ void __launch_bounds__(64) composite_bwd_kernel(
+__global__ void __launch_bounds__(64, (TW * TH <= 256) ? 4 : 1) composite_bwd_kernel(
     int n_tiles, int groups, const uint32_t* __restrict__ order, int n_frames,
     const FrameDesc* __restrict__ frames, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ vals, const Record* __restrict__ rec,

@@ -194,17 +194,40 @@ struct SurfelHit {
 // alpha < 1/255 either way).
 constexpr float kLowpassReach = 5.6f;
 
-__device__ __forceinline__ SurfelHit surfel_eval(const Surfel& S, int px, int py) {
+// The fields of an entry that every pixel strip reads, and the part of the
+// intersection fixed by the lane's pixel column (h_u = (x - c_x) M2 + k_u
+// does not depend on the row): formed once per entry, in registers, instead
+// of once per strip from LDS.
+struct SurfelEntry {
+  float cyh, cyl, m2x, m2y, kvx, kvy, zc, opacity;  // the record's row fields
+  float ex, hux, huy, huz;                          // the column's part
+};
+
+__device__ __forceinline__ SurfelEntry surfel_entry(const Surfel& S, int px) {
+#pragma clang fp contract(off)
+  SurfelEntry e;
+  e.cyh = S.cyh; e.cyl = S.cyl; e.m2x = S.m2x; e.m2y = S.m2y;
+  e.kvx = S.kvx; e.kvy = S.kvy; e.zc = S.zc; e.opacity = S.opacity;
+  asm volatile("" : "+v"(e.cyh), "+v"(e.cyl), "+v"(e.m2x), "+v"(e.m2y), "+v"(e.kvx),
+               "+v"(e.kvy), "+v"(e.zc), "+v"(e.opacity));
+  e.ex = -dx_of(S.cxh, S.cxl, px);  // x - c_x
+  e.hux = e.ex * e.m2x + S.kux;
+  e.huy = e.ex * e.m2y + S.kuy;
+  e.huz = e.ex * e.zc;
+  return e;
+}
+
+__device__ __forceinline__ SurfelHit surfel_eval(const SurfelEntry& e, int py) {
 #pragma clang fp contract(off)
   SurfelHit h;
-  h.ex = -dx_of(S.cxh, S.cxl, px);  // x - c_x
-  h.ey = -dx_of(S.cyh, S.cyl, py);
-  h.hux = h.ex * S.m2x + S.kux;
-  h.huy = h.ex * S.m2y + S.kuy;
-  h.huz = h.ex * S.zc;
-  h.hvx = h.ey * S.m2x + S.kvx;
-  h.hvy = h.ey * S.m2y + S.kvy;
-  h.hvz = h.ey * S.zc;
+  h.ex = e.ex;
+  h.ey = -dx_of(e.cyh, e.cyl, py);
+  h.hux = e.hux;
+  h.huy = e.huy;
+  h.huz = e.huz;
+  h.hvx = h.ey * e.m2x + e.kvx;
+  h.hvy = h.ey * e.m2y + e.kvy;
+  h.hvz = h.ey * e.zc;
   const float p0 = h.huy * h.hvz - h.huz * h.hvy;
   const float p1 = h.huz * h.hvx - h.hux * h.hvz;
   const float p2 = h.hux * h.hvy - h.huy * h.hvx;
@@ -224,7 +247,7 @@ __device__ __forceinline__ SurfelHit surfel_eval(const Surfel& S, int px, int py
   const float Glp = d2 < kLowpassReach ? gauss_of(2.0f * d2) : 0.0f;
   h.obj = G >= Glp;
   h.Gh = h.obj ? G : Glp;
-  h.z = h.obj ? (S.m2x * h.u + S.m2y * h.v + S.zc) : S.zc;
+  h.z = h.obj ? (e.m2x * h.u + e.m2y * h.v + e.zc) : e.zc;
   return h;
 }
 
@@ -285,6 +308,7 @@ __global__ void __launch_bounds__(64) surfel_fwd_kernel(
       const int xlo = S.sqx & 0xffff, xhi = S.sqx >> 16;
       const int ylo = S.sqy & 0xffff, yhi = S.sqy >> 16;
       const bool xin = (unsigned)(px - xlo) <= (unsigned)(xhi - xlo);
+      const SurfelEntry en = surfel_entry(S, px);
 #pragma unroll
       for (int k = 0; k < PIX; ++k) {
         const int row0 = y0 + k * RPP;
@@ -292,8 +316,8 @@ __global__ void __launch_bounds__(64) surfel_fwd_kernel(
         const int py = row0 + ly;
         if (done[k] || !xin || (unsigned)(py - ylo) > (unsigned)(yhi - ylo)) continue;
         if (COUNT) ++hits;
-        const SurfelHit h = surfel_eval(S, px, py);
-        const float a = fminf(kAlphaMax, S.opacity * h.Gh);
+        const SurfelHit h = surfel_eval(en, py);
+        const float a = fminf(kAlphaMax, en.opacity * h.Gh);
         if (a < kAlphaMin) continue;
         const float Tn = T[k] * (1.0f - a);
         if (Tn < kTMin) {
@@ -464,6 +488,7 @@ __global__ void __launch_bounds__(64) surfel_bwd_kernel(
       const int xlo = S.sqx & 0xffff, xhi = S.sqx >> 16;
       const int ylo = S.sqy & 0xffff, yhi = S.sqy >> 16;
       const bool xin = (unsigned)(px - xlo) <= (unsigned)(xhi - xlo);
+      const SurfelEntry en = surfel_entry(S, px);
       // the lane's own pixels sum in FP32; the lanes' sums, which cancel
       // against each other, in FP64
       float acc[kSG];
@@ -479,8 +504,8 @@ __global__ void __launch_bounds__(64) surfel_bwd_kernel(
         if (ylo > row0 + RPP - 1 || yhi < row0) continue;
         const int py = row0 + ly;
         if (pos >= last[k] || !xin || (unsigned)(py - ylo) > (unsigned)(yhi - ylo)) continue;
-        const SurfelHit h = surfel_eval(S, px, py);
-        const float sg = S.opacity * h.Gh;
+        const SurfelHit h = surfel_eval(en, py);
+        const float sg = en.opacity * h.Gh;
         const float a = fminf(kAlphaMax, sg);
         if (a < kAlphaMin) continue;
         const float om = 1.0f - a;
@@ -515,7 +540,7 @@ __global__ void __launch_bounds__(64) surfel_bwd_kernel(
         T[k] = Ti;
         any = true;
         const bool clamped = sg > kAlphaMax;  // clamped: alpha does not move
-        const float dGh = clamped ? 0.0f : dLda * S.opacity;
+        const float dGh = clamped ? 0.0f : dLda * en.opacity;
         if (!clamped) acc[9] += dLda * h.Gh;
         if (h.obj) {
           // z = M2 . (u, v, 1), G = exp(-(u^2 + v^2)/2), (u, v) = (p0, p1) / p2.
@@ -526,8 +551,8 @@ __global__ void __launch_bounds__(64) surfel_bwd_kernel(
           // rebuilt from the stored FP32 values (the products are exact in
           // FP64); G and the decisions are the forward's.
           const double ex = h.ex, ey = h.ey;
-          const double hux = ex * S.m2x + S.kux, huy = ex * S.m2y + S.kuy, huz = ex * S.zc;
-          const double hvx = ey * S.m2x + S.kvx, hvy = ey * S.m2y + S.kvy, hvz = ey * S.zc;
+          const double hux = ex * en.m2x + S.kux, huy = ex * en.m2y + S.kuy, huz = ex * en.zc;
+          const double hvx = ey * en.m2x + en.kvx, hvy = ey * en.m2y + en.kvy, hvz = ey * en.zc;
           const double p0 = huy * hvz - huz * hvy, p1 = huz * hvx - hux * hvz;
           // 1/p2: hardware reciprocal and two Newton steps (FP64 accuracy;
           // p2 != 0 where the disk term was blended)
@@ -537,8 +562,8 @@ __global__ void __launch_bounds__(64) surfel_bwd_kernel(
           ip = __builtin_fma(__builtin_fma(-p2, ip, 1.0), ip, ip);
           const double u = p0 * ip, v = p1 * ip;
           const double gGd = (double)h.Gh * dGh, dzd = dzv;
-          const double gu = -u * gGd + dzd * S.m2x;
-          const double gv = -v * gGd + dzd * S.m2y;
+          const double gu = -u * gGd + dzd * en.m2x;
+          const double gv = -v * gGd + dzd * en.m2y;
           const double ox = (double)px - fr.cx, oy = (double)py - fr.cy;
           const double dp0 = gu * ip, dp1 = gv * ip, dp2 = -(gu * u + gv * v) * ip;
           // p = h_u x h_v: dL/dh_u = h_v x dL/dp, dL/dh_v = dL/dp x h_u
@@ -559,7 +584,7 @@ __global__ void __launch_bounds__(64) surfel_bwd_kernel(
           // the low-pass: z = z_c, G_lp = exp(-|(x, y) - c|^2); its gradient
           // of c reaches M0_z, M1_z (S_u[2], S_v[2]) and, with the principal
           // point's share, R[2]
-          const float t = 2.0f * h.Gh * dGh / S.zc;
+          const float t = 2.0f * h.Gh * dGh / en.zc;
           const float gx = t * h.ex, gy = t * h.ey;
           acc[2] -= gx;
           acc[5] -= gy;

@@ -21,6 +21,7 @@
 // in frame order.
 #include "launch.h"
 #include "sh_device.h"
+#include "wave_util.h"
 
 #include <algorithm>
 
@@ -444,10 +445,6 @@ __global__ void __launch_bounds__(256) slot_reduce_kernel(
 // A10: chain rule to the parameters; per (Gaussian, frame) twist partials
 // reduced per wave in FP64.
 // --------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum_f64(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
 
 template <int DEG>
 __global__ void __launch_bounds__(256) preprocess_bwd_kernel(
@@ -598,10 +595,13 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(
         }
       }
     }
-    for (int j = 0; j < 6; ++j) {
-      const double s = wave_sum_f64(tw[j]);
-      if ((threadIdx.x & (kWave - 1)) == 0)
-        twist_partial[((int64_t)f * n_waves + wave_id) * 6 + j] = s;
+    {
+      // the wave's six twist sums by a transposing VALU reduction (DPP and
+      // permlane moves: no LDS round trips), total j on one lane each
+      int idx;
+      bool writer;
+      const double s = wave_transpose_sum<6>(tw, threadIdx.x & (kWave - 1), idx, writer);
+      if (writer) twist_partial[((int64_t)f * n_waves + wave_id) * 6 + idx] = s;
     }
   }
   if (!active) return;

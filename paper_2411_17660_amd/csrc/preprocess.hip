@@ -353,14 +353,12 @@ __global__ void __launch_bounds__(256) slot_reduce_wide_kernel(
         acc[2 * j + 1] += v[u][j].y;
       }
   }
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1)
-#pragma unroll
-    for (int j = 0; j < kNG; ++j) acc[j] += __shfl_xor(acc[j], o, kWave);
-  double v = acc[0];
-#pragma unroll
-  for (int j = 1; j < kNG; ++j) v = lane == j ? acc[j] : v;
-  if (lane < kNG) grad2d[r * kNG + lane] = v;
+  // the record's ten totals by the transposing VALU reduction (no LDS
+  // round trips), total idx on lane `writer`
+  int idx;
+  bool writer;
+  const double v = wave_transpose_sum<kNG>(acc, lane, idx, writer);
+  if (writer) grad2d[r * kNG + idx] = v;
   }
 }
 
@@ -420,10 +418,13 @@ __global__ void __launch_bounds__(256) slot_reduce_kernel(
         acc[2 * j + 1] += v[u][j].y;
       }
   }
+  // sum over the group's 4 lanes: quad DPP moves (partners l ^ 2, l ^ 1),
+  // the butterfly order of a shuffle reduction without its LDS round trips
 #pragma unroll
-  for (int o = kSlotGroup / 2; o > 0; o >>= 1)
+  for (int j = 0; j < kNG; ++j) acc[j] += dpp<kDppQuadXor2>(acc[j]);
 #pragma unroll
-    for (int j = 0; j < kNG; ++j) acc[j] += __shfl_xor(acc[j], o, kSlotGroup);
+  for (int j = 0; j < kNG; ++j) acc[j] += dpp<kDppQuadXor1>(acc[j]);
+  static_assert(kSlotGroup == 4, "the group reduction is a quad permute");
   if (!active) return;
   if (cnt == 0) {
     for (int j = sub; j < kNG; j += kSlotGroup) grad2d[r * kNG + j] = 0.0;
@@ -439,7 +440,6 @@ __global__ void __launch_bounds__(256) slot_reduce_kernel(
     if (j0 + sub < kNG) grad2d[r * kNG + j0 + sub] = v;
   }
 }
-
 
 // --------------------------------------------------------------------------
 // A10: chain rule to the parameters; per (Gaussian, frame) twist partials

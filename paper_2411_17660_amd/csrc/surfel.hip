@@ -607,11 +607,6 @@ __global__ void __launch_bounds__(64) surfel_bwd_kernel(
   }
 }
 
-__device__ __forceinline__ double wave_sum_d(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
-}
-
 // Per record (surfel, frame): the sum of its keys' partials that this
 // backward stamped, FP64.  A group of kSlotGroup lanes shares a record; the
 // records come in order of tile count, so the groups of one wave walk lists
@@ -641,10 +636,17 @@ __global__ void __launch_bounds__(256) surfel_slot_reduce_kernel(
 #pragma unroll
     for (int j = 0; j < kSG; ++j) acc[j] += pp[j];
   }
+  // sum over the group's 8 lanes by DPP moves (no LDS round trips): the
+  // half-row mirror (partner 7 - l) leaves the group symmetric, then the
+  // quad permutes l ^ 2 and l ^ 1 finish; all 8 lanes end with the same
+  // total (each add is commutative, so mirrored lanes agree bitwise)
+  static_assert(kSlotGroup == 8, "the group reduction is a half-row of DPP lanes");
 #pragma unroll
-  for (int o = kSlotGroup / 2; o > 0; o >>= 1)
+  for (int j = 0; j < kSG; ++j) acc[j] += dpp<kDppHalfMirror>(acc[j]);
 #pragma unroll
-    for (int j = 0; j < kSG; ++j) acc[j] += __shfl_xor(acc[j], o, kSlotGroup);
+  for (int j = 0; j < kSG; ++j) acc[j] += dpp<kDppQuadXor2>(acc[j]);
+#pragma unroll
+  for (int j = 0; j < kSG; ++j) acc[j] += dpp<kDppQuadXor1>(acc[j]);
   if (!active || !ntiles[r]) return;
 #pragma unroll
   for (int j0 = 0; j0 < kSG; j0 += kSlotGroup) {
@@ -783,10 +785,12 @@ __global__ void __launch_bounds__(256) surfel_preprocess_bwd_kernel(
         tw[5] += Yv[0] * Gv[1] - Yv[1] * Gv[0];
       }
     }
-    for (int j = 0; j < 6; ++j) {
-      const double s = wave_sum_d(tw[j]);
-      if ((threadIdx.x & (kWave - 1)) == 0)
-        twist_partial[((int64_t)f * n_waves + wave_id) * 6 + j] = s;
+    {
+      // the wave's six twist sums by the transposing VALU reduction
+      int idx;
+      bool writer;
+      const double s = wave_transpose_sum<6>(tw, threadIdx.x & (kWave - 1), idx, writer);
+      if (writer) twist_partial[((int64_t)f * n_waves + wave_id) * 6 + idx] = s;
     }
   }
   if (!active) return;

@@ -162,15 +162,20 @@ __global__ void __launch_bounds__(kScanThreads) scan_down_kernel(Load ld, const 
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid, int width) {
   uint64_t m = __ballot(valid);
+  uint32_t m_lo = (uint32_t)m, m_hi = (uint32_t)(m >> 32);
 #pragma unroll
   for (int b = 0; b < kMaxDigitBits; ++b) {
     if (b < width) {  // wave-uniform
-      const bool bit = (d >> b) & 1u;
-      const uint64_t bb = __ballot(bit);
-      m &= bit ? bb : ~bb;
+      // x: all ones where the lane's bit b is set; the lanes that agree
+      // with it on bit b are ~(ballot ^ x), which gfx950 forms with the
+      // mask update in one three-input bit operation per half
+      const uint32_t x = (uint32_t)((int32_t)(d << (31 - b)) >> 31);
+      const uint64_t bb = __ballot((int32_t)x < 0);
+      m_lo &= ~((uint32_t)bb ^ x);
+      m_hi &= ~((uint32_t)(bb >> 32) ^ x);
     }
   }
-  return m;
+  return ((uint64_t)m_hi << 32) | m_lo;
 }
 
 // The logical block of workgroup `bid` when the grid (kXcds * per

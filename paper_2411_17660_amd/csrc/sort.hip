@@ -382,7 +382,6 @@ __device__ __forceinline__ void rank_and_scatter(ScatterLds<BINS, WAVES>& L,
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
   const uint32_t wbase = (uint32_t)w * (kWave * kSortRounds);
-  const uint64_t lt = lanemask_lt();
   uint32_t rank[kSortRounds];
 #pragma unroll
   for (int k = 0; k < kSortRounds; ++k) {
@@ -393,8 +392,11 @@ __device__ __forceinline__ void rank_and_scatter(ScatterLds<BINS, WAVES>& L,
     // LDS ops of one wave complete in issue order: the read precedes the
     // leader's write of the same counter
     const uint32_t before = L.wcnt[w][d];
-    rank[k] = before + (uint32_t)__popcll(m & lt);
-    if (valid && (m & lt) == 0) L.wcnt[w][d] = before + (uint32_t)__popcll(m);
+    // peers below this lane: mbcnt counts the mask's bits under the lane
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+        (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    rank[k] = before + below;
+    if (valid && below == 0) L.wcnt[w][d] = before + (uint32_t)__popcll(m);
   }
   __syncthreads();
   {
@@ -440,12 +442,18 @@ __device__ __forceinline__ void rank_and_scatter(ScatterLds<BINS, WAVES>& L,
     }
   }
   __syncthreads();
-  for (uint32_t idx = threadIdx.x; idx < nkeys; idx += kThreads) {
-    const uint32_t kk = L.sk[idx];
-    const uint32_t d = (kk >> shift) & mask;
-    const uint32_t dst = L.gbase[d] + (idx - L.dstart[d]);
-    keys_out[dst] = (KeyT)kk;
-    vals_out[dst] = L.sv[idx];
+  // kSortRounds slots per thread, unrolled so that their LDS reads are all
+  // in flight before the dependent ones and the stores
+#pragma unroll
+  for (int k = 0; k < kSortRounds; ++k) {
+    const uint32_t idx = threadIdx.x + (uint32_t)k * kThreads;
+    if (idx < nkeys) {
+      const uint32_t kk = L.sk[idx];
+      const uint32_t d = (kk >> shift) & mask;
+      const uint32_t dst = L.gbase[d] + (idx - L.dstart[d]);
+      keys_out[dst] = (KeyT)kk;
+      vals_out[dst] = L.sv[idx];
+    }
   }
 }
 

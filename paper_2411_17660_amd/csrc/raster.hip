@@ -230,54 +230,15 @@ __global__ void __launch_bounds__(64) composite_fwd_kernel(
                                              tile_nproc, pair_count, med_pos);
 }
 
-// Sums v[0..9] over the 64 lanes of the wave in FP64.  Each butterfly round
-// halves the set of values a lane carries (10 -> 5 -> 3|2 -> 2|1 -> 1) before
-// the plain rounds over lane bits 1 and 0.  On return lane l holds the total
-// of value index
-//   idx(l) = 5 b5 + (b4 ? 3 + b3 : (b3 ? 2 : b2)),   b_k = bit k of l,
-// and `writer` is set on exactly one lane per index.
-__device__ __forceinline__ double wave_transpose_sum10(const double v[10], int lane, int& idx,
-                                                       bool& writer) {
-  const bool b4 = (lane >> 4) & 1, b3 = (lane >> 3) & 1, b2 = (lane >> 2) & 1;
-  // bit 5: the lower half keeps v[0..4], the upper half v[5..9]
-  double r1[5];
-#pragma unroll
-  for (int j = 0; j < 5; ++j) r1[j] = swap_sum<32>(v[j], v[5 + j]);
-  // bit 4: b4 = 0 keeps r1[0..2], b4 = 1 keeps r1[3..4]
-  double r2[3];
-  r2[0] = swap_sum<16>(r1[0], r1[3]);
-  r2[1] = swap_sum<16>(r1[1], r1[4]);
-  r2[2] = swap_sum<16>(r1[2], 0.0);
-  // bit 3.  b4 = 0: b3 = 0 keeps {r2[0], r2[1]}, b3 = 1 keeps {r2[2]}
-  //         b4 = 1: b3 = 0 keeps {r2[0]},        b3 = 1 keeps {r2[1]}
-  double r3[2];
-  {
-    double s0, k0, s1, k1;
-    if (!b4) {
-      s0 = b3 ? r2[0] : r2[2]; k0 = b3 ? r2[2] : r2[0];
-      s1 = b3 ? r2[1] : 0.0;   k1 = b3 ? 0.0 : r2[1];
-    } else {
-      s0 = b3 ? r2[0] : r2[1]; k0 = b3 ? r2[1] : r2[0];
-      s1 = 0.0; k1 = 0.0;
-    }
-    r3[0] = k0 + dpp<kDppRowMirror>(s0);
-    r3[1] = k1 + dpp<kDppRowMirror>(s1);
-  }
-  // bit 2: lanes still carrying two values (b4 = 0, b3 = 0) split on b2
-  const bool two = !b4 && !b3;
-  const double s4 = two ? (b2 ? r3[0] : r3[1]) : r3[0];
-  const double k4 = two ? (b2 ? r3[1] : r3[0]) : r3[0];
-  double r = k4 + dpp<kDppHalfMirror>(s4);
-  r += dpp<kDppQuadXor2>(r);
-  r += dpp<kDppQuadXor1>(r);
-  idx = 5 * ((lane >> 5) & 1) + (b4 ? 3 + (int)b3 : (b3 ? 2 : (int)b2));
-  writer = (lane & 3) == 0 && (two || !b2);
-  return r;
-}
+// LDS layout of the backward's per-key reduction: value v, part p (lanes
+// 16 p .. 16 p + 15), term t at v kRedValue + p kRedPart + t.  The padding
+// (17 and 68 doubles instead of 16 and 64) spreads the 40 summing lanes'
+// reads over the banks: at most 3 lanes share one (40 without it).
+constexpr int kRedPart = 17, kRedValue = 4 * kRedPart;
 
 template <int TW, int TH, bool MEDIAN, int BATCH>
 __device__ __forceinline__ void composite_bwd_tile(
-    int tile, Record* sm, uint32_t* slot, uint32_t epoch, int n_frames,
+    int tile, Record* sm, uint32_t* slot, double* red, uint32_t epoch, int n_frames,
     const FrameDesc* __restrict__ frames,
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals,
     const Record* __restrict__ rec, const uint2* __restrict__ trect,
@@ -298,6 +259,13 @@ __device__ __forceinline__ void composite_bwd_tile(
   const int lane = threadIdx.x;
   const int px = x0 + lane % TW;
   const int ly = lane / TW;
+  // the key reduction's lane roles: lane 4 v + p sums part p of value v
+  // (lanes 40..63 repeat value 9 and write nothing); the covariance sums
+  // carry twice the gradient (the 1/2 is a power of two: exact)
+  const int red_v = min(lane >> 2, kNG - 1), red_p = lane & 3;
+  const int red_w = (lane >> 4) * kRedPart + (lane & 15);  // this lane's slot of a value
+  const bool red_writer = red_p == 0 && (lane >> 2) < kNG;
+  const double red_scale = (red_v >= 2 && red_v <= 4) ? 0.5 : 1.0;
   const uint2 rg = ranges[tile];
   const int64_t plane = (int64_t)fr.width * fr.height;
 
@@ -438,15 +406,32 @@ __device__ __forceinline__ void composite_bwd_tile(
       }
       if (__ballot(any) == 0) continue;
       // The lanes' values of one key cancel against each other: sum them in
-      // FP64; the key's total is stored as FP32 and the per-record sum over
-      // its keys is FP64 again
-      const double vals10[kNG] = {gu, gv, 0.5 * gSxx, 0.5 * gSxy, 0.5 * gSyy,
-                                   gs, gc0, gc1, gc2, gz};
-      int idx;
-      bool writer;
-      const double tot = wave_transpose_sum10(vals10, lane, idx, writer);
+      // FP64 (the key's total is stored as FP32; the per-record sum over its
+      // keys is FP64 again).  Each lane writes its ten values to LDS; lane
+      // 4 v + p adds lanes 16 p .. 16 p + 15 of value v, and the quad adds
+      // its four parts.  The wave's LDS operations run in issue order, so
+      // the next key's writes cannot pass these reads.
+      double* dst = red + red_w;
+      dst[0 * kRedValue] = gu;
+      dst[1 * kRedValue] = gv;
+      dst[2 * kRedValue] = gSxx;
+      dst[3 * kRedValue] = gSxy;
+      dst[4 * kRedValue] = gSyy;
+      dst[5 * kRedValue] = gs;
+      dst[6 * kRedValue] = gc0;
+      dst[7 * kRedValue] = gc1;
+      dst[8 * kRedValue] = gc2;
+      dst[9 * kRedValue] = gz;
+      const double* src = red + red_v * kRedValue + red_p * kRedPart;
+      double s4[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        s4[t] = (src[4 * t] + src[4 * t + 1]) + (src[4 * t + 2] + src[4 * t + 3]);
+      double tot = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+      tot += dpp<kDppQuadXor2>(tot);
+      tot += dpp<kDppQuadXor1>(tot);
       const uint32_t sl = slot[j];
-      if (writer) partial[(size_t)sl * kNG + idx] = (float)tot;
+      if (red_writer) partial[(size_t)sl * kNG + red_v] = (float)(tot * red_scale);
       if (lane == 1) stamp[sl] = epoch;
     }
     __syncthreads();
@@ -467,10 +452,11 @@ __global__ void __launch_bounds__(64, (TW * TH <= 256) ? 4 : 1) composite_bwd_ke
     const int32_t* __restrict__ med_pos) {
   __shared__ Record sm[BATCH];
   __shared__ uint32_t slot[BATCH];
+  __shared__ double red[kNG * kRedValue];
   const int tile = tile_of_block(blockIdx.x, n_tiles, groups, order);
   if (tile < 0) return;
   const uint32_t epoch = *epoch_dev;
-  composite_bwd_tile<TW, TH, MEDIAN, BATCH>(tile, sm, slot, epoch, n_frames, frames, ranges, vals, rec,
+  composite_bwd_tile<TW, TH, MEDIAN, BATCH>(tile, sm, slot, red, epoch, n_frames, frames, ranges, vals, rec,
                                      trect, keyoff, tile_nproc, bg0, bg1, bg2, g_rgb, g_depth,
                                      g_alpha, t_final, n_last, partial, stamp, med_pos);
 }

@@ -55,9 +55,11 @@ __device__ __forceinline__ double swap_sum(double a, double b) {
 template <int CTRL>
 __device__ __forceinline__ double dpp(double v) {
   const uint64_t u = (uint64_t)__double_as_longlong(v);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, false);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf,
-                                                            0xf, false);
+  // every lane's partner lies in its own row, so no lane reads out of
+  // bounds and no old value is needed (bound_ctrl)
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xf, 0xf, true);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf,
+                                                         true);
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 constexpr int kDppRowMirror = 0x140, kDppHalfMirror = 0x141, kDppQuadXor2 = 0x4e,

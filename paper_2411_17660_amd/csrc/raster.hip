@@ -230,12 +230,6 @@ __global__ void __launch_bounds__(64) composite_fwd_kernel(
                                              tile_nproc, pair_count, med_pos);
 }
 
-// LDS layout of the backward's per-key reduction: value v, part p (lanes
-// 16 p .. 16 p + 15), term t at v kRedValue + p kRedPart + t.  The padding
-// (17 and 68 doubles instead of 16 and 64) spreads the 40 summing lanes'
-// reads over the banks: at most 3 lanes share one (40 without it).
-constexpr int kRedPart = 17, kRedValue = 4 * kRedPart;
-
 template <int TW, int TH, bool MEDIAN, int BATCH>
 __device__ __forceinline__ void composite_bwd_tile(
     int tile, Record* sm, uint32_t* slot, double* red, uint32_t epoch, int n_frames,
@@ -259,12 +253,11 @@ __device__ __forceinline__ void composite_bwd_tile(
   const int lane = threadIdx.x;
   const int px = x0 + lane % TW;
   const int ly = lane / TW;
-  // the key reduction's lane roles: lane 4 v + p sums part p of value v
-  // (lanes 40..63 repeat value 9 and write nothing); the covariance sums
-  // carry twice the gradient (the 1/2 is a power of two: exact)
-  const int red_v = min(lane >> 2, kNG - 1), red_p = lane & 3;
-  const int red_w = (lane >> 4) * kRedPart + (lane & 15);  // this lane's slot of a value
-  const bool red_writer = red_p == 0 && (lane >> 2) < kNG;
+  // the key reduction leaves value min(lane >> 2, 9) on each quad (lanes
+  // 40..63 repeat value 9 and write nothing); the covariance sums carry
+  // twice the gradient (the 1/2 is a power of two: exact)
+  const int red_v = min(lane >> 2, kNG - 1);
+  const bool red_writer = (lane & 3) == 0 && (lane >> 2) < kNG;
   const double red_scale = (red_v >= 2 && red_v <= 4) ? 0.5 : 1.0;
   const uint2 rg = ranges[tile];
   const int64_t plane = (int64_t)fr.width * fr.height;
@@ -407,29 +400,9 @@ __device__ __forceinline__ void composite_bwd_tile(
       if (__ballot(any) == 0) continue;
       // The lanes' values of one key cancel against each other: sum them in
       // FP64 (the key's total is stored as FP32; the per-record sum over its
-      // keys is FP64 again).  Each lane writes its ten values to LDS; lane
-      // 4 v + p adds lanes 16 p .. 16 p + 15 of value v, and the quad adds
-      // its four parts.  The wave's LDS operations run in issue order, so
-      // the next key's writes cannot pass these reads.
-      double* dst = red + red_w;
-      dst[0 * kRedValue] = gu;
-      dst[1 * kRedValue] = gv;
-      dst[2 * kRedValue] = gSxx;
-      dst[3 * kRedValue] = gSxy;
-      dst[4 * kRedValue] = gSyy;
-      dst[5 * kRedValue] = gs;
-      dst[6 * kRedValue] = gc0;
-      dst[7 * kRedValue] = gc1;
-      dst[8 * kRedValue] = gc2;
-      dst[9 * kRedValue] = gz;
-      const double* src = red + red_v * kRedValue + red_p * kRedPart;
-      double s4[4];
-#pragma unroll
-      for (int t = 0; t < 4; ++t)
-        s4[t] = (src[4 * t] + src[4 * t + 1]) + (src[4 * t + 2] + src[4 * t + 3]);
-      double tot = (s4[0] + s4[1]) + (s4[2] + s4[3]);
-      tot += dpp<kDppQuadXor2>(tot);
-      tot += dpp<kDppQuadXor1>(tot);
+      // keys is FP64 again)
+      const double vals10[kNG] = {gu, gv, gSxx, gSxy, gSyy, gs, gc0, gc1, gc2, gz};
+      const double tot = lds_wave_sum<kNG>(red, vals10, lane);
       const uint32_t sl = slot[j];
       if (red_writer) partial[(size_t)sl * kNG + red_v] = (float)(tot * red_scale);
       if (lane == 1) stamp[sl] = epoch;

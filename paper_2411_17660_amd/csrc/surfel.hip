@@ -414,6 +414,7 @@ __global__ void __launch_bounds__(64) surfel_bwd_kernel(
   constexpr int RPP = kWave / TW;
   __shared__ Surfel sm[kWave];
   __shared__ uint32_t slot[kWave];
+  __shared__ double red[kSG * kRedValue];  // the per-key reduction
   const int tile = tile_of_block(blockIdx.x, n_tiles, groups, order);
   if (tile < 0) return;
   const int most = (int)tile_nproc[tile];
@@ -596,11 +597,10 @@ __global__ void __launch_bounds__(64) surfel_bwd_kernel(
       double accd[kSG];
 #pragma unroll
       for (int i = 0; i < kSG; ++i) accd[i] = acc[i];
-      int idx;
-      bool writer;
-      const double tot = wave_transpose_sum<kSG>(accd, lane, idx, writer);
+      // value lane >> 2 on every lane of its quad
+      const double tot = lds_wave_sum<kSG>(red, accd, lane);
       const uint32_t sl = slot[j];
-      if (writer) partial[(size_t)sl * kSG + idx] = (float)tot;
+      if ((lane & 3) == 0) partial[(size_t)sl * kSG + (lane >> 2)] = (float)tot;
       if (lane == 0) stamp[sl] = epoch;
     }
     __syncthreads();

@@ -65,6 +65,36 @@ __device__ __forceinline__ double dpp(double v) {
 constexpr int kDppRowMirror = 0x140, kDppHalfMirror = 0x141, kDppQuadXor2 = 0x4e,
               kDppQuadXor1 = 0xb1;
 
+// Sum over the wave of N <= 16 FP64 values per lane through LDS: every
+// lane stores its values, lane 4 v + p (v < N) adds the 16 lanes
+// 16 p .. 16 p + 15 of value v in a fixed pairwise order, and the quad adds
+// its four parts by DPP moves.  Returns the total of value
+// min(lane >> 2, N - 1) on every lane of the quad.  `red` holds
+// N * kRedValue doubles used by this wave only; a wave's LDS operations
+// complete in issue order, so calls may follow each other on one buffer.
+// Value v, part p, term t live at v kRedValue + p kRedPart + t: the padding
+// (17 and 68 doubles instead of 16 and 64) spreads the summing lanes' reads
+// over the LDS banks (at most 4 lanes share one; 64 without it).
+constexpr int kRedPart = 17, kRedValue = 4 * kRedPart;
+
+template <int N>
+__device__ __forceinline__ double lds_wave_sum(double* red, const double (&v)[N], int lane) {
+  static_assert(N >= 1 && N <= 16, "four lanes per value");
+  double* dst = red + (lane >> 4) * kRedPart + (lane & 15);
+#pragma unroll
+  for (int i = 0; i < N; ++i) dst[i * kRedValue] = v[i];
+  const int rv = lane >> 2 < N ? lane >> 2 : N - 1, rp = lane & 3;
+  const double* src = red + rv * kRedValue + rp * kRedPart;
+  double s4[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+    s4[t] = (src[4 * t] + src[4 * t + 1]) + (src[4 * t + 2] + src[4 * t + 3]);
+  double tot = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+  tot += dpp<kDppQuadXor2>(tot);
+  tot += dpp<kDppQuadXor1>(tot);
+  return tot;
+}
+
 // Sum over the wave of N FP64 values per lane by recursive halving: at lane
 // bit b a lane keeps the lower or the upper half of its values (by that bit)
 // and adds its partner's copy of the same half.  The partners are those of

@@ -298,6 +298,19 @@ __device__ __forceinline__ void composite_bwd_tile(
     // behind the last entry: the background colour at depth 0
     E[k] = __builtin_fma(H2[k], (double)bg2, __builtin_fma(H1[k], (double)bg1, H0[k] * (double)bg0));
   }
+  // Per-entry sums.  With p = a dL/da, dL/dq = -p/2: gu, gv carry
+  // sum(-p Q d), the gradient of the centre, and gS* carry
+  // sum(p (Q d)(Q d)^T), twice the gradient of the 2D covariance; the 1/2 is
+  // applied once per key (a power of two: exact).  A lane adds to them only
+  // past the alpha test, so they are still zero after an entry no lane
+  // blended, and are reset only after an entry that was reduced.  The empty
+  // asm hides the zeros from constant folding, so that they are set in place
+  // rather than rewritten on every branch of the first strip.
+  float gu = 0.f, gv = 0.f, gs = 0.f;
+  double gSxx = 0.0, gSxy = 0.0, gSyy = 0.0;
+  float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f, gz = 0.f;
+  asm volatile("" : "+v"(gu), "+v"(gv), "+v"(gs), "+v"(gSxx), "+v"(gSxy), "+v"(gSyy),
+               "+v"(gc0), "+v"(gc1), "+v"(gc2), "+v"(gz));
   for (int hi = (int)nproc; hi > 0; hi -= BATCH) {
     const int lo = max(0, hi - BATCH);
 #pragma unroll
@@ -326,19 +339,6 @@ __device__ __forceinline__ void composite_bwd_tile(
       const float dx = dx_of(R.u_hi, R.u_lo, px);
       const float a1dx = e_a1 * dx;
       const double c0 = R.c0, c1 = R.c1, c2 = R.c2, cz = R.z;
-      // With p = a dL/da, dL/dq = -p/2: gu, gv carry sum(-p Q d), the
-      // gradient of the centre, and gS* carry sum(p (Q d)(Q d)^T), twice the
-      // gradient of the 2D covariance; the 1/2 is applied once per key (a
-      // power of two: exact)
-      float gu = 0.f, gv = 0.f, gs = 0.f;
-      double gSxx = 0.0, gSxy = 0.0, gSyy = 0.0;
-      float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f, gz = 0.f;
-      // Hide the zeros from constant folding (no instruction is emitted):
-      // the sums are then set to zero once per entry and updated in place
-      // under the lane mask, instead of each branch of the first strip
-      // writing its own zeros.
-      asm volatile("" : "+v"(gu), "+v"(gv), "+v"(gs), "+v"(gSxx), "+v"(gSxy), "+v"(gSyy),
-                   "+v"(gc0), "+v"(gc1), "+v"(gc2), "+v"(gz));
       bool any = false;
 #pragma unroll
       for (int k = 0; k < PIX; ++k) {
@@ -403,6 +403,10 @@ __device__ __forceinline__ void composite_bwd_tile(
       // keys is FP64 again)
       const double vals10[kNG] = {gu, gv, gSxx, gSxy, gSyy, gs, gc0, gc1, gc2, gz};
       const double tot = lds_wave_sum<kNG>(red, vals10, lane);
+      gu = gv = gs = gc0 = gc1 = gc2 = gz = 0.f;
+      gSxx = gSxy = gSyy = 0.0;
+      asm volatile("" : "+v"(gu), "+v"(gv), "+v"(gs), "+v"(gSxx), "+v"(gSxy), "+v"(gSyy),
+                   "+v"(gc0), "+v"(gc1), "+v"(gc2), "+v"(gz));
       const uint32_t sl = slot[j];
       if (red_writer) partial[(size_t)sl * kNG + red_v] = (float)(tot * red_scale);
       if (lane == 1) stamp[sl] = epoch;

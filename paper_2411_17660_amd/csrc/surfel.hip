@@ -473,6 +473,17 @@ __global__ void __launch_bounds__(64) surfel_bwd_kernel(
     // behind the last entry: the background colour, zero depth, normal and e
     E[k] = __builtin_fma(H2[k], (double)bg2, __builtin_fma(H1[k], (double)bg1, H0[k] * (double)bg0));
   }
+  // Per-entry sums: the lane's own pixels sum in FP32; the lanes' sums,
+  // which cancel against each other, in FP64.  A lane adds to them only past
+  // the alpha test, so they are still zero after an entry no lane blended
+  // and are reset only after an entry that was reduced (the empty asm keeps
+  // the zeros from being rewritten on every branch of the first strip).
+  float acc[kSG];
+#pragma unroll
+  for (int i = 0; i < kSG; ++i) {
+    acc[i] = 0.0f;
+    asm volatile("" : "+v"(acc[i]));
+  }
   for (int hi = most; hi > 0; hi -= kWave) {
     const int lo = hi > kWave ? hi - kWave : 0;
     if (lo + lane < hi) {
@@ -490,14 +501,6 @@ __global__ void __launch_bounds__(64) surfel_bwd_kernel(
       const int ylo = S.sqy & 0xffff, yhi = S.sqy >> 16;
       const bool xin = (unsigned)(px - xlo) <= (unsigned)(xhi - xlo);
       const SurfelEntry en = surfel_entry(S, px);
-      // the lane's own pixels sum in FP32; the lanes' sums, which cancel
-      // against each other, in FP64
-      float acc[kSG];
-#pragma unroll
-      for (int i = 0; i < kSG; ++i) {
-        acc[i] = 0.0f;
-        asm volatile("" : "+v"(acc[i]));  // zeroed once per entry, not per branch
-      }
       bool any = false;
 #pragma unroll
       for (int k = 0; k < PIX; ++k) {
@@ -599,6 +602,11 @@ __global__ void __launch_bounds__(64) surfel_bwd_kernel(
       for (int i = 0; i < kSG; ++i) accd[i] = acc[i];
       // value lane >> 2 on every lane of its quad
       const double tot = lds_wave_sum<kSG>(red, accd, lane);
+#pragma unroll
+      for (int i = 0; i < kSG; ++i) {
+        acc[i] = 0.0f;
+        asm volatile("" : "+v"(acc[i]));
+      }
       const uint32_t sl = slot[j];
       if ((lane & 3) == 0) partial[(size_t)sl * kSG + (lane >> 2)] = (float)tot;
       if (lane == 0) stamp[sl] = epoch;

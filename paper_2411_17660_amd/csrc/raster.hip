@@ -17,20 +17,21 @@
 // Backward: the wave walks the tile's processed prefix from the back.  Each
 // lane recomputes alpha bit-identically (same helpers, explicit fma),
 // rebuilds T_i = T_{i+1} / (1 - a_i) (reciprocal plus one Newton step) and
-// carries the normalised colour seen behind each entry,
-// B_{i-1} = a_i c_i + (1 - a_i) B_i from B = background (likewise depth from 0
-// and the transmittance behind from 1), so that dC/da_i = T_i (c_i - B_i):
-// T_i only scales the result and the convex recurrence damps rounding
-// instead of accumulating it.  The screen-space gradient of an
-// entry is taken with respect to (u, v, Sigma'): with Q = Sigma'^-1 = L L^T
-// (L the factor the forward already uses) and d the offset, dq/dd = 2 Q d and
-// dq/dSigma' = -(Q d)(Q d)^T, Q d = L (L^T d); this avoids the ill-conditioned
-// -Q dQ Q step from conic gradients for elongated Gaussians.  The 10 per-entry
-// values are summed over the lane's pixels and then across the wave by a
-// transpose-reduce (13 shuffles instead of 60, fixed order); the result for
-// this (tile, entry) key goes to its own slot (no atomics), stamped with the
-// backward's epoch so the per-record reduction can skip slots of keys that
-// no pixel reached.
+// carries what is seen behind each entry through the convex recurrence
+// B_{i-1} = a_i c_i + (1 - a_i) B_i from B = background (depth from 0, the
+// transmittance behind from 1), so that dC/da_i = T_i (c_i - B_i): T_i only
+// scales the result and the recurrence damps rounding instead of
+// accumulating it.  Colour and depth enter only through G . B (G the pixel's
+// upstream gradient), which is what the lane keeps, in FP64.  The
+// screen-space gradient of an entry is taken with respect to (u, v, Sigma'):
+// with Q = Sigma'^-1 = L L^T (L the factor the forward already uses) and d
+// the offset, dq/dd = 2 Q d and dq/dSigma' = -(Q d)(Q d)^T,
+// Q d = L (L^T d); this avoids the ill-conditioned -Q dQ Q step from conic
+// gradients for elongated Gaussians.  The 10 per-entry values are summed
+// over the lane's pixels and then across the wave in FP64 through LDS
+// (fixed order); the result for this (tile, entry) key goes to its own slot
+// (no atomics), stamped with the backward's epoch so the per-record
+// reduction can skip slots of keys that no pixel reached.
 #include "launch.h"
 #include "wave_util.h"
 

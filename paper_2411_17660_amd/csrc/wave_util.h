@@ -1,6 +1,7 @@
-// wave_util.h -- wave-level helpers shared by the compositing kernels of the
-// 3D Gaussian and 2D surfel paths: the FP64 cross-lane swaps and DPP moves of
-// the transposing reductions, and the XCD-grouped tile schedule.
+// wave_util.h -- wave-level helpers shared by the kernels of the 3D Gaussian
+// and 2D surfel paths: the FP64 cross-lane swaps and DPP moves, the
+// transposing and LDS wave sums built on them, and the XCD-grouped tile
+// schedule.
 #pragma once
 #include "gsr_device.h"
 

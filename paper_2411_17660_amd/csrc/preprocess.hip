@@ -307,17 +307,16 @@ static_assert(kNG % 2 == 0, "partials are read as float pairs");
 // The wide pass takes the w-th largest records, w < n_wide = m - *first_wide
 // (capped at wide_max), a wave each in turn (grid stride); 64 lanes stride
 // over a record's slots, kSlotUnroll per lane per round.
-__global__ void __launch_bounds__(256) slot_reduce_wide_kernel(
-    uint64_t m, const uint32_t* __restrict__ order, const uint32_t* __restrict__ keyoff,
-    const uint32_t* __restrict__ ntiles, const float* __restrict__ partial,
-    const uint32_t* __restrict__ stamp, const uint32_t* __restrict__ epoch_dev,
+__device__ __forceinline__ void slot_reduce_wide(
+    unsigned block, unsigned n_blocks, uint64_t m, const uint32_t* __restrict__ order,
+    const uint32_t* __restrict__ keyoff, const uint32_t* __restrict__ ntiles,
+    const float* __restrict__ partial, const uint32_t* __restrict__ stamp, uint32_t epoch,
     uint64_t key_capacity, const uint32_t* __restrict__ first_wide, uint64_t wide_max,
     double* __restrict__ grad2d) {
   const uint64_t n_wide = min(m - *first_wide, wide_max);
-  const uint64_t stride = ((uint64_t)gridDim.x * blockDim.x) / kWave;
-  const uint32_t epoch = *epoch_dev;
+  const uint64_t stride = ((uint64_t)n_blocks * blockDim.x) / kWave;
   const int lane = threadIdx.x & (kWave - 1);
-  for (uint64_t w = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; w < n_wide;
+  for (uint64_t w = ((uint64_t)block * blockDim.x + threadIdx.x) / kWave; w < n_wide;
        w += stride) {  // uniform per wave
   const uint64_t r = order[m - 1 - w];
   uint32_t cnt = ntiles[r];
@@ -364,15 +363,13 @@ __global__ void __launch_bounds__(256) slot_reduce_wide_kernel(
 
 // Group k (4 lanes) takes the k-th largest record after the ones the wide
 // pass took.
-__global__ void __launch_bounds__(256) slot_reduce_kernel(
-    uint64_t m, const uint32_t* __restrict__ order, const uint32_t* __restrict__ keyoff,
-    const uint32_t* __restrict__ ntiles,
-    const float* __restrict__ partial, const uint32_t* __restrict__ stamp,
-    const uint32_t* __restrict__ epoch_dev, uint64_t key_capacity,
-    const uint32_t* __restrict__ first_wide, uint64_t wide_max,
+__device__ __forceinline__ void slot_reduce_groups(
+    unsigned block, uint64_t m, const uint32_t* __restrict__ order,
+    const uint32_t* __restrict__ keyoff, const uint32_t* __restrict__ ntiles,
+    const float* __restrict__ partial, const uint32_t* __restrict__ stamp, uint32_t epoch,
+    uint64_t key_capacity, const uint32_t* __restrict__ first_wide, uint64_t wide_max,
     double* __restrict__ grad2d /* [m][kNG] */) {
-  const uint32_t epoch = *epoch_dev;
-  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t gid = (uint64_t)block * blockDim.x + threadIdx.x;
   const uint64_t k = gid / kSlotGroup + min(m - *first_wide, wide_max);
   const int sub = threadIdx.x & (kSlotGroup - 1);
   // `order` ascends in key count: walk it from the end, so that the records
@@ -439,6 +436,25 @@ __global__ void __launch_bounds__(256) slot_reduce_kernel(
       if (j0 + t < kNG) v = sub == t ? acc[j0 + t] : v;
     if (j0 + sub < kNG) grad2d[r * kNG + j0 + sub] = v;
   }
+}
+
+// One launch for both passes: the first `wide_blocks` workgroups take the
+// wide records (a wave each, grid stride), the rest the groups.  Workgroups
+// start in order, so the long wide records start first and the group work
+// fills the machine around them instead of waiting for them to finish.
+__global__ void __launch_bounds__(256) slot_reduce_kernel(
+    uint64_t m, const uint32_t* __restrict__ order, const uint32_t* __restrict__ keyoff,
+    const uint32_t* __restrict__ ntiles, const float* __restrict__ partial,
+    const uint32_t* __restrict__ stamp, const uint32_t* __restrict__ epoch_dev,
+    uint64_t key_capacity, const uint32_t* __restrict__ first_wide, uint64_t wide_max,
+    unsigned wide_blocks, double* __restrict__ grad2d) {
+  const uint32_t epoch = *epoch_dev;
+  if (blockIdx.x < wide_blocks)
+    slot_reduce_wide(blockIdx.x, wide_blocks, m, order, keyoff, ntiles, partial, stamp, epoch,
+                     key_capacity, first_wide, wide_max, grad2d);
+  else
+    slot_reduce_groups(blockIdx.x - wide_blocks, m, order, keyoff, ntiles, partial, stamp,
+                       epoch, key_capacity, first_wide, wide_max, grad2d);
 }
 
 // --------------------------------------------------------------------------
@@ -773,13 +789,11 @@ void launch_preprocess_bwd(hipStream_t st, int64_t n, int F, const FrameDesc* fr
     const uint64_t wide_max = std::min<uint64_t>(m, key_capacity / kWideSlots + 1);
     // a fixed grid of kWideWaves waves strides over the wide records
     const uint64_t wide_waves = std::min<uint64_t>(wide_max, kWideWaves);
-    hipLaunchKernelGGL(slot_reduce_wide_kernel, dim3((unsigned)((wide_waves + 3) / 4)),
-                       dim3(256), 0, st, m, order, keyoff, ntiles, partial, stamp, epoch,
-                       key_capacity, first_wide, wide_max, grad2d);
+    const unsigned wide_blocks = (unsigned)((wide_waves + 3) / 4);
     const uint64_t threads = m * kSlotGroup;
-    hipLaunchKernelGGL(slot_reduce_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0,
-                       st, m, order, keyoff, ntiles, partial, stamp, epoch, key_capacity,
-                       first_wide, wide_max, grad2d);
+    hipLaunchKernelGGL(slot_reduce_kernel, dim3(wide_blocks + (unsigned)((threads + 255) / 256)),
+                       dim3(256), 0, st, m, order, keyoff, ntiles, partial, stamp, epoch,
+                       key_capacity, first_wide, wide_max, wide_blocks, grad2d);
     switch (deg) {
       case 0: GSR_PRE_BWD(0); break;
       case 1: GSR_PRE_BWD(1); break;

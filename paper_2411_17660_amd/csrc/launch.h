@@ -54,9 +54,12 @@ size_t radix_scan_elems(uint64_t n_max, int bits);
 bool launch_radix_sort(hipStream_t st, uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b,
                        uint32_t* vals_b, const uint64_t* n_dev, uint64_t n_max, int bits,
                        uint32_t* hist, uint32_t* scan_tmp);
-void launch_offsets_scan(hipStream_t st, const uint32_t* ntiles, const uint32_t* perm,
-                         uint64_t m, uint32_t* cnt_sorted, uint64_t* offsets,
-                         uint64_t* block_tmp, uint64_t* total);
+// skey: the sorted depth keys (all ones: culled); trect_sorted[i] and
+// cnt_sorted[i]: the tile rect and tile count of record perm[i].
+void launch_offsets_scan(hipStream_t st, const uint32_t* skey, const uint32_t* perm,
+                         const uint2* trect, uint64_t m, uint32_t* cnt_sorted,
+                         uint2* trect_sorted, uint64_t* offsets, uint64_t* block_tmp,
+                         uint64_t* total);
 // Tile keys are 16-bit when the tile ids and the all-ones sentinel fit
 // (bits <= 16), else 32-bit; `keys` buffers hold that type.
 bool tile_keys_16bit(int bits);
@@ -65,8 +68,8 @@ bool tile_keys_16bit(int bits);
 // record with a tile (all-ones past the capacity, raising *overflow).
 void launch_keygen(hipStream_t st, uint64_t m, uint64_t n, const uint32_t* perm,
                    const uint32_t* cnt_sorted, const uint64_t* offsets, uint32_t* keyoff,
-                   const uint2* trect, const FrameDesc* frames, uint64_t capacity, int bits,
-                   void* keys, uint32_t* vals, uint32_t* overflow);
+                   const uint2* trect_sorted, const FrameDesc* frames, uint64_t capacity,
+                   int bits, void* keys, uint32_t* vals, uint32_t* overflow);
 // Stable sort of min(*k_dev, k_max) tile keys (k_dev NULL: k_max) by the
 // tile-id bits [0, bits); returns true if the result is in (keys_b, vals_b).
 bool launch_tile_sort(hipStream_t st, void* keys_a, uint32_t* vals_a, void* keys_b,

@@ -50,7 +50,7 @@ struct gsr_context {
   int device = 0;
   std::string err;
   // workspace
-  DBuf rec, trect, keyoff, dkey_a, dval_a, dkey_b, dval_b, ntiles, cnt_sorted, offsets, scan_tmp, hist,
+  DBuf rec, trect, trect_s, keyoff, dkey_a, dval_a, dkey_b, dval_b, ntiles, cnt_sorted, offsets, scan_tmp, hist,
       counters;
   DBuf keys_a, vals_a, keys_b, vals_b, partial, stamp, grad2d;
   DBuf ranges, nproc, t_final, n_last, frames, twist_part, loss_part, loss_scale;
@@ -224,7 +224,7 @@ gsr_status gsr_destroy(gsr_context* ctx) {
   if (!ctx) return GSR_ERR_INVALID_ARGUMENT;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
-  DBuf* bufs[] = {&ctx->rec, &ctx->trect, &ctx->keyoff, &ctx->dkey_a, &ctx->dval_a, &ctx->dkey_b, &ctx->dval_b,
+  DBuf* bufs[] = {&ctx->rec, &ctx->trect, &ctx->trect_s, &ctx->keyoff, &ctx->dkey_a, &ctx->dval_a, &ctx->dkey_b, &ctx->dval_b,
                   &ctx->ntiles, &ctx->cnt_sorted, &ctx->offsets, &ctx->scan_tmp, &ctx->hist,
                   &ctx->counters,
                   &ctx->keys_a, &ctx->vals_a, &ctx->keys_b, &ctx->vals_b, &ctx->partial,
@@ -290,6 +290,7 @@ gsr_status forward_impl(gsr_context* ctx, const gsr_settings* s, int64_t n, cons
   const size_t rec_bytes = surfel ? surfel_record_bytes() : sizeof(Record);
   if ((rc = ensure(ctx, ctx->rec, M * rec_bytes, st))) return rc;
   if ((rc = ensure(ctx, ctx->trect, M * sizeof(uint2), st))) return rc;
+  if ((rc = ensure(ctx, ctx->trect_s, M * sizeof(uint2), st))) return rc;
   if ((rc = ensure(ctx, ctx->keyoff, M * 4, st))) return rc;
   if ((rc = ensure(ctx, ctx->dkey_a, M * 4, st))) return rc;
   if ((rc = ensure(ctx, ctx->dval_a, M * 4, st))) return rc;
@@ -354,8 +355,10 @@ gsr_status forward_impl(gsr_context* ctx, const gsr_settings* s, int64_t n, cons
   // A2 offsets over the depth-ordered records, K on the device
   {
     StageTimer t(ctx, st, timing, GSR_STAGE_OFFSETS);
-    launch_offsets_scan(st, P<uint32_t>(ctx->ntiles), perm, M, P<uint32_t>(ctx->cnt_sorted),
-                        P<uint64_t>(ctx->offsets), P<uint64_t>(ctx->scan_tmp), d_count);
+    launch_offsets_scan(st, P<uint32_t>(recs_in_b ? ctx->dkey_b : ctx->dkey_a), perm,
+                        P<uint2>(ctx->trect), M, P<uint32_t>(ctx->cnt_sorted),
+                        P<uint2>(ctx->trect_s), P<uint64_t>(ctx->offsets),
+                        P<uint64_t>(ctx->scan_tmp), d_count);
   }
   // key capacity
   uint64_t K = 0, cap = 0;
@@ -392,7 +395,7 @@ gsr_status forward_impl(gsr_context* ctx, const gsr_settings* s, int64_t n, cons
   {
     StageTimer t(ctx, st, timing, GSR_STAGE_KEYGEN);
     launch_keygen(st, M, (uint64_t)n, perm, P<uint32_t>(ctx->cnt_sorted),
-                  P<uint64_t>(ctx->offsets), P<uint32_t>(ctx->keyoff), P<uint2>(ctx->trect),
+                  P<uint64_t>(ctx->offsets), P<uint32_t>(ctx->keyoff), P<uint2>(ctx->trect_s),
                   P<FrameDesc>(ctx->frames), use_cap, tile_bits, ctx->keys_a.p,
                   P<uint32_t>(ctx->vals_a), d_overflow);
   }

@@ -523,7 +523,7 @@ template <typename KeyT>
 __global__ void __launch_bounds__(256) keygen_kernel(
     uint64_t m, uint64_t n, const uint32_t* __restrict__ perm,
     const uint32_t* __restrict__ cnt_sorted, const uint64_t* __restrict__ offsets,
-    uint32_t* __restrict__ keyoff, const uint2* __restrict__ trect,
+    uint32_t* __restrict__ keyoff, const uint2* __restrict__ trect_sorted,
     const FrameDesc* __restrict__ frames, uint64_t capacity, KeyT* __restrict__ keys,
     uint32_t* __restrict__ vals, uint32_t* __restrict__ overflow) {
   // per record: first slot relative to the wave's first (all-ones for a
@@ -541,8 +541,8 @@ __global__ void __launch_bounds__(256) keygen_kernel(
     off = offsets[i];
     if (cnt) {
       const uint32_t r = perm[i];
-      const FrameDesc fr = frames[r / n];
-      const uint2 tr = trect[r];
+      const uint2 tr = trect_sorted[i];
+      const FrameDesc fr = frames[r / (uint32_t)n];
       const uint32_t tx0 = tr.x & 0xffffu, tx1 = tr.x >> 16, ty0 = tr.y & 0xffffu;
       const bool ovf = off + cnt > capacity;
       keyoff[r] = ovf ? 0xffffffffu : (uint32_t)off;
@@ -785,16 +785,16 @@ bool tile_keys_16bit(int bits) { return bits <= 16; }
 
 void launch_keygen(hipStream_t st, uint64_t m, uint64_t n, const uint32_t* perm,
                    const uint32_t* cnt_sorted, const uint64_t* offsets, uint32_t* keyoff,
-                   const uint2* trect, const FrameDesc* frames, uint64_t capacity, int bits,
-                   void* keys, uint32_t* vals, uint32_t* overflow) {
+                   const uint2* trect_sorted, const FrameDesc* frames, uint64_t capacity,
+                   int bits, void* keys, uint32_t* vals, uint32_t* overflow) {
   if (m == 0) return;
   if (tile_keys_16bit(bits))
     hipLaunchKernelGGL(keygen_kernel<uint16_t>, dim3(blocks_for(m, 256)), dim3(256), 0, st, m,
-                       n, perm, cnt_sorted, offsets, keyoff, trect, frames, capacity,
+                       n, perm, cnt_sorted, offsets, keyoff, trect_sorted, frames, capacity,
                        static_cast<uint16_t*>(keys), vals, overflow);
   else
     hipLaunchKernelGGL(keygen_kernel<uint32_t>, dim3(blocks_for(m, 256)), dim3(256), 0, st, m,
-                       n, perm, cnt_sorted, offsets, keyoff, trect, frames, capacity,
+                       n, perm, cnt_sorted, offsets, keyoff, trect_sorted, frames, capacity,
                        static_cast<uint32_t*>(keys), vals, overflow);
 }
 
@@ -833,26 +833,43 @@ bool launch_tile_sort(hipStream_t st, void* keys_a, uint32_t* vals_a, void* keys
 }
 
 // The tile counts in depth order, cnt_sorted[i] = ntiles[perm[i]], gathered
-// once so that the offsets scan and keygen read them in order.
+// once so that the offsets scan and keygen read them in order, together
+// with the tile rects (keygen's one random read per record happens here, as
+// part of the gather that has to be random anyway).  A record is kept iff its
+// sorted depth key is not the all-ones of a culled record, and a kept
+// record's tile count is the area of its rect (the preprocess writes the two
+// together; a culled record has neither).
 __global__ void __launch_bounds__(256) gather_counts_kernel(uint64_t m,
-                                                            const uint32_t* __restrict__ ntiles,
+                                                            const uint32_t* __restrict__ skey,
                                                             const uint32_t* __restrict__ perm,
-                                                            uint32_t* __restrict__ cnt_sorted) {
+                                                            const uint2* __restrict__ trect,
+                                                            uint32_t* __restrict__ cnt_sorted,
+                                                            uint2* __restrict__ trect_sorted) {
   const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < m) cnt_sorted[i] = ntiles[perm[i]];
+  if (i >= m) return;
+  uint2 tr = make_uint2(0u, 0u);
+  uint32_t c = 0;
+  if (skey[i] != 0xffffffffu) {
+    tr = trect[perm[i]];
+    c = ((tr.x >> 16) - (tr.x & 0xffffu) + 1u) * ((tr.y >> 16) - (tr.y & 0xffffu) + 1u);
+  }
+  cnt_sorted[i] = c;
+  trect_sorted[i] = tr;
 }
 
-// Exclusive scan of ntiles[perm[i]] over the m records into offsets (u64),
-// total into *total; cnt_sorted[i] receives ntiles[perm[i]].
-void launch_offsets_scan(hipStream_t st, const uint32_t* ntiles, const uint32_t* perm,
-                         uint64_t m, uint32_t* cnt_sorted, uint64_t* offsets,
-                         uint64_t* block_tmp, uint64_t* total) {
+// Exclusive scan of the depth-ordered records' tile counts into offsets
+// (u64), total into *total; cnt_sorted[i] and trect_sorted[i] receive the
+// count and the tile rect of record perm[i] (zero for a culled record).
+void launch_offsets_scan(hipStream_t st, const uint32_t* skey, const uint32_t* perm,
+                         const uint2* trect, uint64_t m, uint32_t* cnt_sorted,
+                         uint2* trect_sorted, uint64_t* offsets, uint64_t* block_tmp,
+                         uint64_t* total) {
   if (m == 0) {
     launch_fill_u32(st, (uint32_t*)total, 2, 0u);
     return;
   }
-  hipLaunchKernelGGL(gather_counts_kernel, dim3(blocks_for(m, 256)), dim3(256), 0, st, m, ntiles,
-                     perm, cnt_sorted);
+  hipLaunchKernelGGL(gather_counts_kernel, dim3(blocks_for(m, 256)), dim3(256), 0, st, m, skey,
+                     perm, trect, cnt_sorted, trect_sorted);
   const unsigned sb = blocks_for(m, kScanTile);
   LoadU32 ld{cnt_sorted};
   hipLaunchKernelGGL((scan_reduce_kernel<uint64_t, LoadU32>), dim3(sb), dim3(kScanThreads), 0,

@@ -49,10 +49,17 @@ static_assert(sizeof(Record) == 64, "record layout");
 // (symmetric-matrix gradient), dopacity, dc0..2, dz
 constexpr int kNG = 10;
 
+// The frame of a global tile id: the last frame whose first tile is <= tile
+// (every frame has at least one tile, so the first tiles increase), by
+// binary search over the frame table.
 __device__ __forceinline__ int frame_of_tile(const FrameDesc* fr, int n_frames, int tile) {
-  int f = 0;
-  while (f + 1 < n_frames && tile >= fr[f + 1].tile_offset) ++f;
-  return f;
+  int lo = 0, hi = n_frames - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (fr[mid].tile_offset <= tile) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
 }
 
 __device__ __forceinline__ uint64_t lanemask_lt() {

@@ -153,27 +153,33 @@ __global__ void __launch_bounds__(kScanThreads) scan_down_kernel(Load ld, const 
 // contiguous 1024 keys from w * 1024 as 16 rounds of 64.  Each lane loads
 // its 16 keys and values straight into registers (fully unrolled, so all the
 // loads are in flight at once).  Per round a wave ranks its 64 keys by digit
-// with `width` ballots (lanes with equal digits form one mask); the lowest
-// lane of each group bumps the wave's LDS counter.  No atomics there, so the
+// with one ballot per digit bit, 8 or 10 whatever the width (lanes with
+// equal digits form one mask); the lowest lane of each group bumps the
+// wave's LDS counter.  No atomics there, so the
 // ranks are deterministic and the scatter is stable.  The keys then pass
 // through LDS in digit order so that each digit's run leaves the block as
 // consecutive stores.  BINS (256 or 1024) sizes the LDS counters; the pass
 // uses 2^width of them.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid, int width) {
-  uint64_t m = __ballot(valid);
-  uint32_t m_lo = (uint32_t)m, m_hi = (uint32_t)(m >> 32);
+
+// The lanes whose digits d agree with this lane's on the bits [0, NBITS).
+// A digit narrower than NBITS has zeros above its width, where every lane
+// agrees, so those steps leave the mask as it is: the loop runs a fixed
+// NBITS steps with no per-bit width test.
+template <int NBITS>
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d) {
+  uint32_t m_lo = 0xffffffffu, m_hi = 0xffffffffu;
 #pragma unroll
-  for (int b = 0; b < kMaxDigitBits; ++b) {
-    if (b < width) {  // wave-uniform
-      // x: all ones where the lane's bit b is set; the lanes that agree
-      // with it on bit b are ~(ballot ^ x), which gfx950 forms with the
-      // mask update in one three-input bit operation per half
-      const uint32_t x = (uint32_t)((int32_t)(d << (31 - b)) >> 31);
-      const uint64_t bb = __ballot((int32_t)x < 0);
-      m_lo &= ~((uint32_t)bb ^ x);
-      m_hi &= ~((uint32_t)(bb >> 32) ^ x);
-    }
+  for (int b = 0; b < NBITS; ++b) {
+    // x: all ones where the lane's bit b is set; the lanes that agree with
+    // it on bit b are ~(ballot ^ x), which gfx950 forms with the mask update
+    // in one three-input bit operation per half (the empty asm keeps the
+    // steps from being refolded into a longer xor / or chain)
+    const uint32_t x = (uint32_t)__builtin_amdgcn_sbfe((int32_t)d, (uint32_t)b, 1u);
+    const uint64_t bb = __ballot((int32_t)x < 0);
+    asm volatile("" : "+v"(m_lo), "+v"(m_hi));
+    m_lo &= ~((uint32_t)bb ^ x);
+    m_hi &= ~((uint32_t)(bb >> 32) ^ x);
   }
   return ((uint64_t)m_hi << 32) | m_lo;
 }
@@ -377,18 +383,22 @@ __device__ __forceinline__ void rank_and_scatter(ScatterLds<BINS, WAVES>& L,
                                                  uint32_t* __restrict__ vals_out) {
   constexpr int kThreads = RadixShape<WAVES>::kThreads;
   constexpr int DPT = (BINS + kThreads - 1) / kThreads;  // digits per thread in the combine
+  static_assert(BINS == 256 || BINS == kMaxBins, "8- or 10-bit digit counters");
+  constexpr int kBinBits = BINS == 256 ? 8 : kMaxDigitBits;
   const int bins = 1 << width;
   const uint32_t mask = (uint32_t)bins - 1u;
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
   const uint32_t wbase = (uint32_t)w * (kWave * kSortRounds);
+  const uint32_t wbase_s = __builtin_amdgcn_readfirstlane(wbase);  // wave-uniform
   uint32_t rank[kSortRounds];
 #pragma unroll
   for (int k = 0; k < kSortRounds; ++k) {
     const uint32_t i = wbase + (uint32_t)k * kWave + lane;
     const bool valid = i < nkeys;
     const uint32_t d = (key[k] >> shift) & mask;
-    const uint64_t m = digit_peers(d, valid, width);
+    uint64_t m = digit_peers<kBinBits>(d);
+    if (wbase_s + (uint32_t)k * kWave + kWave > nkeys) m &= __ballot(valid);  // partial round
     // LDS ops of one wave complete in issue order: the read precedes the
     // leader's write of the same counter
     const uint32_t before = L.wcnt[w][d];

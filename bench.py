@@ -732,20 +732,38 @@ def measure_surfel(rast, sc, dev, tile, steps):
     return res
 
 
+# The compositing kernels' source: raster.hip and every header it includes.
+COMPOSITING_SOURCES = ("paper_2411_17660_amd/csrc/raster.hip",
+                       "paper_2411_17660_amd/csrc/wave_util.h",
+                       "paper_2411_17660_amd/csrc/launch.h",
+                       "paper_2411_17660_amd/csrc/gsr_device.h",
+                       "paper_2411_17660_amd/csrc/host_check.h",
+                       "include/gsr.h")
+
+
+def compositing_sources_sha256(root=ROOT):
+    """SHA-256 over the compositing kernels' source files, in the order above."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in COMPOSITING_SOURCES:
+        h.update(open(os.path.join(root, rel), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(kernel, tile):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary (scaled by the copy-kernel calibration), or None when
     the summary covers another kernel or tile shape or the compositing source
-    has changed since the counters were taken."""
-    import hashlib
+    (raster.hip or a header it includes) has changed since the counters were
+    taken."""
     import re
     path = os.path.join(ROOT, "profiles", "c3_hbm_traffic_pmc.md")
-    src = os.path.join(ROOT, "paper_2411_17660_amd", "csrc", "raster.hip")
     if not os.path.exists(path) or tuple(tile) != (16, 16):
         return None
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    sha = compositing_sources_sha256()
     for line in open(path):
-        m = re.search(r"traffic (\w+)<16, 16> bytes_per_launch=(\d+) raster_hip_sha256=(\w+)", line)
+        m = re.search(r"traffic (\w+)<16, 16> bytes_per_launch=(\d+) "
+                      r"compositing_sources_sha256=(\w+)", line)
         if m and m.group(1) == kernel + "_kernel" and m.group(3) == sha:
             return int(m.group(2))
     return None

@@ -525,9 +525,14 @@ __device__ __forceinline__ uint32_t div_rem(uint32_t a, uint32_t b, uint32_t& r)
 // value the record id perm[i].  A wave owns 64 consecutive depth-ordered
 // records; their slots form one contiguous range, which the lanes write
 // cooperatively (slot o by lane o % 64, every store instruction 64
-// consecutive keys) after locating the owning record with a 6-step search in
-// LDS.  A record whose slots pass the key capacity gets the all-ones
-// sentinel key (past every tile) on its slots below the capacity.
+// consecutive keys).  The owner of each slot of a 64-slot round comes from
+// the record starts that fall in the round: those records mark their slot in
+// LDS, and a slot's owner is the number of records started at or before it,
+// less one (one LDS write, one read and a ballot per round; a binary search
+// over the 64 starts took six dependent LDS reads and twice the VALU work,
+// and this kernel is bound by VALU issue).  A record whose slots pass the key
+// capacity gets the all-ones sentinel key (past every tile) on its slots
+// below the capacity.
 // ---------------------------------------------------------------------------
 template <typename KeyT>
 __global__ void __launch_bounds__(256) keygen_kernel(
@@ -536,11 +541,12 @@ __global__ void __launch_bounds__(256) keygen_kernel(
     uint32_t* __restrict__ keyoff, const uint2* __restrict__ trect_sorted,
     const FrameDesc* __restrict__ frames, uint64_t capacity, KeyT* __restrict__ keys,
     uint32_t* __restrict__ vals, uint32_t* __restrict__ overflow) {
-  // per record: first slot relative to the wave's first (all-ones for a
-  // record without slots in the range), and (first tile id or sentinel, rect
-  // width | grid width << 16, value)
-  __shared__ uint32_t s_rel[4][kWave];
+  // per record: (first tile id or sentinel, rect width | grid width << 16,
+  // value, first slot relative to the wave's first); per slot of a round:
+  // the round's number where a record starts there.  Each wave uses its own
+  // rows.
   __shared__ uint4 s_rec[4][kWave];
+  __shared__ uint32_t s_mark[4][kWave];
   const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const uint64_t i0 = ((uint64_t)blockIdx.x * 4 + w) * kWave;
   const uint64_t i = i0 + lane;
@@ -570,27 +576,48 @@ __global__ void __launch_bounds__(256) keygen_kernel(
     hi = h2 > hi ? h2 : hi;
   }
   if (hi > capacity) hi = capacity;
+  if (i0 >= m || hi <= lo) return;  // wave-uniform
   // records with a slot in the range have first slots below hi; the others
-  // (culled, or past the capacity) never own a slot
-  s_rel[w][lane] = (i < m && cnt && off < hi) ? (uint32_t)(off - lo) : 0xffffffffu;
-  __syncthreads();  // every wave reaches the barrier; empty waves leave after it
-  if (i0 >= m || hi <= lo) return;
+  // (culled, or past the capacity) never own a slot.  The starts of the
+  // records with slots increase strictly along the lanes from 0.
+  const uint32_t start = (i < m && cnt && off < hi) ? (uint32_t)(off - lo) : 0xffffffffu;
+  s_rec[w][lane].w = start;
+  s_mark[w][lane] = 0u;
   const uint32_t span = (uint32_t)(hi - lo);  // < 2^32: slots are 32-bit
-  for (uint32_t o = lane; o < span; o += kWave) {
-    // owner: the last record whose first slot is <= o
-    int j = 0;
-#pragma unroll
-    for (int step = 32; step > 0; step >>= 1)
-      if (s_rel[w][j + step] <= o) j += step;
-    const uint4 R = s_rec[w][j];
-    uint32_t key = 0xffffffffu;
-    if (R.x != 0xffffffffu) {
-      uint32_t col;
-      const uint32_t row = div_rem(o - s_rel[w][j], R.y & 0xffffu, col);
-      key = R.x + row * (R.y >> 16) + col;
+  // the wave's output runs, from wave-uniform bases
+  const uint64_t lo_s = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(lo >> 32)) << 32) |
+                        __builtin_amdgcn_readfirstlane((uint32_t)lo);
+  KeyT* __restrict__ kout = keys + lo_s;
+  uint32_t* __restrict__ vout = vals + lo_s;
+  uint32_t before = 0;  // records starting before the round
+  uint32_t round = 0;
+  for (uint32_t base = 0; base < span; base += kWave) {
+    // owner of slot base + lane: the last record starting at or before it.
+    // Records starting inside the window mark their slot with the round's
+    // number (distinct slots, so no two lanes write one word); LDS ops of
+    // one wave complete in issue order, so the marks are in place when the
+    // lanes read them.
+    ++round;
+    if (start != 0xffffffffu && start - base < (uint32_t)kWave) s_mark[w][start - base] = round;
+    __builtin_amdgcn_wave_barrier();
+    const uint64_t sm = __ballot(s_mark[w][lane] == round);
+    const uint32_t upto =
+        __builtin_amdgcn_mbcnt_hi((uint32_t)(sm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)sm, 0u)) +
+        (uint32_t)((sm >> lane) & 1ull);
+    const uint32_t owner = (before + upto - 1u) & (kWave - 1);
+    before += (uint32_t)__popcll(sm);
+    const uint32_t o = base + (uint32_t)lane;
+    const uint4 R = s_rec[w][owner];
+    if (o < span) {
+      uint32_t key = 0xffffffffu;
+      if (R.x != 0xffffffffu) {
+        uint32_t col;
+        const uint32_t row = div_rem(o - R.w, R.y & 0xffffu, col);
+        key = R.x + row * (R.y >> 16) + col;
+      }
+      kout[o] = (KeyT)key;  // the sentinel stays all ones
+      vout[o] = R.z;
     }
-    keys[lo + o] = (KeyT)key;  // the sentinel stays all ones
-    vals[lo + o] = R.z;
   }
 }
 

@@ -362,9 +362,8 @@ __global__ void __launch_bounds__(kMaxBins) radix_coldown_kernel(
 
 template <int BINS, int WAVES>
 struct ScatterLds {
-  uint32_t wcnt[WAVES][BINS];  // counts, then wave bases in digit
-  uint32_t dstart[BINS];       // block-local start of each digit
-  uint32_t gbase[BINS];        // global start of digit for the block
+  uint32_t wcnt[WAVES][BINS];  // counts, then each wave's block-local start in digit
+  uint32_t gofs[BINS];         // global start of digit d minus its block-local start
   uint32_t wsum[WAVES];
   uint32_t sk[RadixShape<WAVES>::kTile], sv[RadixShape<WAVES>::kTile];
 };
@@ -372,7 +371,10 @@ struct ScatterLds {
 // Ranks the block's keys (lane's round-k key is block-local index
 // w 1024 + 64 k + lane; L.wcnt zeroed and the zeroing visible to all waves),
 // moves them into digit order through L.sk / L.sv and writes them to
-// gbase[d] + (position inside the block's run of digit d).
+// (global start of digit d) + (position inside the block's run of digit d).
+// The combine folds the block-local digit starts into the waves' bases and
+// the global offsets, so that each key reads one LDS word on its way into
+// the staging rows and one on its way out.
 template <int BINS, int WAVES, typename KeyT>
 __device__ __forceinline__ void rank_and_scatter(ScatterLds<BINS, WAVES>& L,
                                                  const uint32_t (&key)[kSortRounds],
@@ -434,35 +436,63 @@ __device__ __forceinline__ void rank_and_scatter(ScatterLds<BINS, WAVES>& L,
     for (int j = 0; j < DPT; ++j) {
       const int d = threadIdx.x * DPT + j;
       if (d < bins) {
-        L.dstart[d] = base;
-        L.gbase[d] = offs_row[d];
+        for (int ww = 0; ww < WAVES; ++ww) L.wcnt[ww][d] += base;
+        L.gofs[d] = offs_row[d] - base;  // mod 2^32: the output index adds base back
       }
       base += tot[j];
     }
   }
   __syncthreads();  // (also: every wave is done with whatever L.sk held)
+  // A full block (all but the last) takes the loops without a per-key test,
+  // so that the unrolled rounds' LDS reads are all in flight before the
+  // dependent writes and stores; the test made each round wait for its own.
+  const bool full = nkeys == (uint32_t)RadixShape<WAVES>::kTile;  // block-uniform
+  if (full) {
 #pragma unroll
-  for (int k = 0; k < kSortRounds; ++k) {
-    const uint32_t i = wbase + (uint32_t)k * kWave + lane;
-    if (i < nkeys) {
-      const uint32_t d = (key[k] >> shift) & mask;
-      const uint32_t lp = L.dstart[d] + L.wcnt[w][d] + rank[k];
+    for (int k = 0; k < kSortRounds; ++k) {
+      const uint32_t lp = L.wcnt[w][__builtin_amdgcn_ubfe(key[k], shift, width)] + rank[k];
       L.sk[lp] = key[k];
       L.sv[lp] = val[k];
     }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kSortRounds; ++k) {
+      const uint32_t i = wbase + (uint32_t)k * kWave + lane;
+      if (i < nkeys) {
+        const uint32_t lp = L.wcnt[w][__builtin_amdgcn_ubfe(key[k], shift, width)] + rank[k];
+        L.sk[lp] = key[k];
+        L.sv[lp] = val[k];
+      }
+    }
   }
   __syncthreads();
-  // kSortRounds slots per thread, unrolled so that their LDS reads are all
-  // in flight before the dependent ones and the stores
+  // kSortRounds slots per thread: consecutive threads take consecutive
+  // slots, so each digit's run leaves as consecutive stores
+  if (full) {
+    uint32_t kk[kSortRounds], vv[kSortRounds];
 #pragma unroll
-  for (int k = 0; k < kSortRounds; ++k) {
-    const uint32_t idx = threadIdx.x + (uint32_t)k * kThreads;
-    if (idx < nkeys) {
-      const uint32_t kk = L.sk[idx];
-      const uint32_t d = (kk >> shift) & mask;
-      const uint32_t dst = L.gbase[d] + (idx - L.dstart[d]);
-      keys_out[dst] = (KeyT)kk;
-      vals_out[dst] = L.sv[idx];
+    for (int k = 0; k < kSortRounds; ++k) {
+      const uint32_t idx = threadIdx.x + (uint32_t)k * kThreads;
+      kk[k] = L.sk[idx];
+      vv[k] = L.sv[idx];
+    }
+#pragma unroll
+    for (int k = 0; k < kSortRounds; ++k) {
+      const uint32_t idx = threadIdx.x + (uint32_t)k * kThreads;
+      const uint32_t dst = L.gofs[__builtin_amdgcn_ubfe(kk[k], shift, width)] + idx;
+      keys_out[dst] = (KeyT)kk[k];
+      vals_out[dst] = vv[k];
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kSortRounds; ++k) {
+      const uint32_t idx = threadIdx.x + (uint32_t)k * kThreads;
+      if (idx < nkeys) {
+        const uint32_t kk = L.sk[idx];
+        const uint32_t dst = L.gofs[__builtin_amdgcn_ubfe(kk, shift, width)] + idx;
+        keys_out[dst] = (KeyT)kk;
+        vals_out[dst] = L.sv[idx];
+      }
     }
   }
 }

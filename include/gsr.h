@@ -333,7 +333,10 @@ gsr_status gsr_mcmc_relocate(gsr_context* ctx, int64_t n, int32_t sh_degree, flo
  * round) on the given inputs: one untimed sizing run per tile shape, then
  * `reps` runs per (shape, batch) timed with HIP events on `stream`.  Writes
  * the fastest settings to *chosen (base settings with tile_w, tile_h and
- * lds_batch replaced and a fixed key_capacity 5% above the measured count).
+ * lds_batch replaced and a fixed key_capacity 5% above the measured count);
+ * on the fastest shape the default batch of 64 is kept when its time is
+ * within 1% of the fastest batch's, so that run-to-run noise does not flip
+ * between batches that differ by less than it.
  * ms[GSR_TUNE_BATCHES * i + j] receives the median step time of shape i with
  * batch j in the orders above (array of GSR_TUNE_TILES * GSR_TUNE_BATCHES;
  * NULL allowed).  Results do not depend on the choice: images are bitwise

@@ -416,7 +416,11 @@ def test_autotuner_picks_a_measured_shape_with_identical_images(rast):
     assert tile in native.TILE_SHAPES and batch in native.LDS_BATCHES and cap > 0
     assert len(times) == len(native.TILE_SHAPES) * len(native.LDS_BATCHES)
     assert all(t > 0 for t in times.values())
-    assert times[(tile, batch)] == min(times.values())
+    # the fastest shape; on it the fastest batch, or the default batch of 64
+    # when that is within 1% of it
+    best = min(times, key=times.get)
+    assert tile == best[0]
+    assert batch == best[1] or (batch == 64 and times[(tile, 64)] <= 1.01 * times[best])
     tile2, batch2, _, times2 = rast.autotune(d["means"], d["log_scales"], d["quats"],
                                              d["opacity"], d["sh"], d["poses"], sc.cams,
                                              sc.sh_degree, t_rgb, t_dep, 0.5,

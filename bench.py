@@ -741,9 +741,11 @@ COMPOSITING_SOURCES = ("paper_2411_17660_amd/csrc/raster.hip",
                        "include/gsr.h")
 
 
-def compositing_sources_sha256(root=ROOT):
-    """SHA-256 over the compositing kernels' source files, in the order above."""
+def compositing_sources_sha256(root=None):
+    """SHA-256 over the compositing kernels' source files under `root` (the
+    repository by default), in the order above."""
     import hashlib
+    root = ROOT if root is None else root
     h = hashlib.sha256()
     for rel in COMPOSITING_SOURCES:
         h.update(open(os.path.join(root, rel), "rb").read())
@@ -760,7 +762,7 @@ def measured_traffic(kernel, tile):
     path = os.path.join(ROOT, "profiles", "c3_hbm_traffic_pmc.md")
     if not os.path.exists(path) or tuple(tile) != (16, 16):
         return None
-    sha = compositing_sources_sha256()
+    sha = compositing_sources_sha256(ROOT)
     for line in open(path):
         m = re.search(r"traffic (\w+)<16, 16> bytes_per_launch=(\d+) "
                       r"compositing_sources_sha256=(\w+)", line)

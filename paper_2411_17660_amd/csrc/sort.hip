@@ -653,9 +653,8 @@ __global__ void __launch_bounds__(256) keygen_kernel(
 
 // [start, end) of every tile's run in the sorted keys (ranges pre-zeroed).
 // Each thread scans 32 consecutive keys (four 16-byte loads of 16-bit keys,
-// eight of 32-bit ones) plus the key just
-// before them; a run boundary writes the start of the new tile and the end
-// of the previous one.
+// eight of 32-bit ones) plus the key just before them; a run boundary writes
+// the start of the new tile and the end of the previous one.
 constexpr int kRangeItems = 32;
 
 template <typename KeyT>
